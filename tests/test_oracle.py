@@ -1,0 +1,401 @@
+"""Pins of the oracle against what the paper and the mathematics fix
+(CPU only).  Each test would fail on a plausible slip in the oracle: a wrong
+weight coefficient, a transposed offset, a dropped sigma^2, a wrong sign or
+index in the factorized recurrences."""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def keys_kernel(s):
+    """Textbook Keys kernel (a = -1/2), independent of the oracle's
+    polynomial-in-t form."""
+    s = np.abs(s)
+    return np.where(s <= 1, 1.5 * s ** 3 - 2.5 * s ** 2 + 1,
+                    np.where(s < 2, -0.5 * s ** 3 + 2.5 * s ** 2 - 4 * s + 2, 0.0))
+
+
+def dense_w_textbook(grid, X):
+    """W[i, j] = prod_k keys(u_ik - j_k) over all grid nodes (brute force)."""
+    d = grid["d"]
+    m = grid["m"]
+    n = X.shape[1]
+    M = int(np.prod(m))
+    coords = np.array(np.unravel_index(np.arange(M), m))  # [d, M]
+    W = np.ones((n, M))
+    for k in range(d):
+        u = (X[k] - grid["origin"][k]) / grid["spacing"][k]
+        W *= keys_kernel(u[:, None] - coords[k][None, :])
+    return W
+
+
+def rand_points(rng, grid, n):
+    X = []
+    for k in range(grid["d"]):
+        lo = grid["origin"][k] + grid["spacing"][k]
+        hi = grid["origin"][k] + (grid["m"][k] - 2) * grid["spacing"][k]
+        X.append(rng.uniform(lo, hi, n))
+    return np.array(X)
+
+
+# --------------------------------------------------------------------------
+# Interpolation weights (Keys cubic convolution, Sec. 3 / Fig. 1 basis).
+# --------------------------------------------------------------------------
+def test_keys_weights_golden():
+    rows = np.loadtxt(os.path.join(GOLD, "keys_weights.txt"))
+    grid = oracle.make_grid([10], origin=[0.0], spacing=[1.0])
+    for t, *w in rows:
+        _, wts, _ = oracle.stencils(grid, np.array([4.0 + t]))
+        # t = 1 is assigned to cell 4 with t = 0 (floor); compare by node
+        nodes, _, _ = oracle.stencils(grid, np.array([4.0 + t]))
+        full = np.zeros(10)
+        full[nodes[0]] = wts[0]
+        ref = np.zeros(10)
+        ref[3:7] = w
+        np.testing.assert_allclose(full, ref, atol=1e-15)
+
+
+def test_keys_weights_polynomial_reproduction():
+    grid = oracle.make_grid([20], origin=[0.0], spacing=[1.0])
+    u = np.linspace(1.0, 18.0, 997)
+    nodes, w, _ = oracle.stencils(grid, u)
+    np.testing.assert_allclose(w.sum(1), 1.0, atol=1e-14)
+    np.testing.assert_allclose((w * nodes).sum(1), u, atol=1e-12)
+    np.testing.assert_allclose((w * nodes ** 2).sum(1), u ** 2, atol=1e-10)
+    # cubic is not reproduced (third-order kernel)
+    assert np.max(np.abs((w * nodes ** 3).sum(1) - u ** 3)) > 1e-3
+
+
+def test_keys_weights_match_textbook_kernel_and_continuity():
+    rng = np.random.default_rng(0)
+    grid = oracle.make_grid([12, 9], origin=[-0.3, 1.0], spacing=[0.1, 0.25])
+    X = rand_points(rng, grid, 300)
+    # include exact node positions and the upper boundary u = m - 2
+    X[:, 0] = [grid["origin"][0] + 5 * grid["spacing"][0], grid["origin"][1] + 7 * grid["spacing"][1]]
+    X[:, 1] = [grid["origin"][0] + 10 * grid["spacing"][0], grid["origin"][1] + 1 * grid["spacing"][1]]
+    W = oracle.dense_w(grid, X)
+    Wt = dense_w_textbook(grid, X)
+    np.testing.assert_allclose(W, Wt, atol=1e-14)
+
+
+def test_out_of_grid_rejected():
+    grid = oracle.make_grid([10], origin=[0.0], spacing=[1.0])
+    for bad in (0.999, 8.0001, np.nan):
+        with pytest.raises(ValueError):
+            oracle.precompute(grid, np.array([3.0, bad]), np.array([1.0, 1.0]))
+    oracle.precompute(grid, np.array([1.0, 8.0]), np.array([1.0, 1.0]))
+
+
+# --------------------------------------------------------------------------
+# Sufficient statistics (Sec. 3.1; Claim 2).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [[11], [7, 9], [6, 5, 7]])
+def test_wtw_bruteforce_dense(m):
+    rng = np.random.default_rng(len(m))
+    grid = oracle.make_grid(m, origin=[0.5] * len(m), spacing=[0.3] * len(m))
+    n = 400
+    X = rand_points(rng, grid, n)
+    y = rng.standard_normal(n)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    W = dense_w_textbook(grid, X)
+    A = oracle.wtw_dense_from_dia(grid, wtw)
+    np.testing.assert_allclose(A, W.T @ W, atol=1e-12 * n)
+    np.testing.assert_allclose(wty, W.T @ y, atol=1e-12 * n)
+    assert abs(yty - y @ y) <= 1e-12 * n
+    # the DIA layout holds every nonzero: at most 7^d per row (Claim 2)
+    assert np.count_nonzero(np.abs(W.T @ W) > 1e-14, axis=1).max() <= 7 ** len(m)
+
+
+def test_wtw_invariants():
+    rng = np.random.default_rng(5)
+    grid = oracle.make_grid([8, 10], origin=[0.0, 0.0], spacing=[1.0, 0.5])
+    n = 2000
+    X = rand_points(rng, grid, n)
+    y = rng.standard_normal(n)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    A = oracle.wtw_dense_from_dia(grid, wtw)
+    M = A.shape[0]
+    np.testing.assert_allclose(A, A.T, atol=1e-12)
+    assert np.linalg.eigvalsh(A).min() >= -1e-12 * np.abs(A).max()
+    ones = np.ones(M)
+    _, w1, _ = oracle.precompute(grid, X, np.ones(n))
+    np.testing.assert_allclose(A @ ones, w1, atol=1e-10)
+    assert abs(ones @ A @ ones - n) < 1e-8
+    assert abs(wty.sum() - y.sum()) < 1e-9
+    _, wts, _ = oracle.stencils(grid, X)
+    assert abs(np.trace(A) - (wts ** 2).sum()) < 1e-9
+    np.testing.assert_allclose(oracle.wtw_matvec(grid, wtw, ones), A @ ones, atol=1e-12)
+
+
+def test_points_on_nodes_give_diagonal_histogram():
+    grid = oracle.make_grid([9, 6], origin=[0.0, 0.0], spacing=[1.0, 1.0])
+    rng = np.random.default_rng(1)
+    i0 = rng.integers(1, 8, 500)
+    i1 = rng.integers(1, 5, 500)
+    X = np.array([i0, i1], float)
+    wtw, wty, _ = oracle.precompute(grid, X, np.ones(500))
+    A = oracle.wtw_dense_from_dia(grid, wtw)
+    hist = np.zeros((9, 6))
+    np.add.at(hist, (i0, i1), 1.0)
+    np.testing.assert_allclose(A, np.diag(hist.ravel()), atol=1e-13)
+
+
+def test_probe_generator_published_vectors():
+    rows = [l.split() for l in open(os.path.join(GOLD, "splitmix64_seed0.txt"))
+            if not l.startswith("#")]
+    for c, out in rows:
+        assert oracle.splitmix64(int(c, 16)) == int(out, 16)
+    z = oracle.probe_values(4, 3, 1000)
+    assert set(np.unique(z)) == {-1.0, 1.0}
+    assert abs(z.mean()) < 0.15
+
+
+def test_probe_sketches_match_dense():
+    rng = np.random.default_rng(2)
+    grid = oracle.make_grid([7, 8], origin=[0.0, 0.0], spacing=[1.0, 1.0])
+    X = rand_points(rng, grid, 300)
+    S = oracle.probe_sketches(grid, X, 7, 3)
+    W = dense_w_textbook(grid, X)
+    for j in range(3):
+        z = oracle.probe_values(7, j, 300)
+        np.testing.assert_allclose(S[j], W.T @ z, atol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# K_G (Sec. 2.3: multilevel Toeplitz for a stationary kernel on a grid).
+# --------------------------------------------------------------------------
+def test_kg_matvec_vs_kernel_on_grid_points():
+    grid = oracle.make_grid([9, 6, 5], origin=[0.1, -0.2, 0.0], spacing=[0.07, 0.11, 0.05])
+    hyp = {"lengthscale": [0.13, 0.2, 0.09], "outputscale": 1.7, "noise": 0.1}
+    coords = np.array(np.meshgrid(*[grid["origin"][k] + grid["spacing"][k] * np.arange(grid["m"][k])
+                                    for k in range(3)], indexing="ij")).reshape(3, -1).T
+    K = oracle.se_kernel(coords, coords, hyp["lengthscale"], hyp["outputscale"])
+    np.testing.assert_allclose(oracle.kg_dense(grid, hyp), K, atol=1e-13)
+    v = np.random.default_rng(0).standard_normal(K.shape[0])
+    np.testing.assert_allclose(oracle.kg_matvec(grid, hyp, v), K @ v, atol=1e-12)
+
+
+def test_dkg_matvec_vs_finite_difference():
+    grid = oracle.make_grid([8, 7], origin=[0.0, 0.0], spacing=[0.1, 0.1])
+    hyp = {"lengthscale": [0.2, 0.3], "outputscale": 1.3, "noise": 0.1}
+    v = np.random.default_rng(1).standard_normal(56)
+    for which in range(3):
+        h = 1e-6
+        hp = {k: (list(v_) if isinstance(v_, list) else v_) for k, v_ in hyp.items()}
+        hm = {k: (list(v_) if isinstance(v_, list) else v_) for k, v_ in hyp.items()}
+        if which < 2:
+            hp["lengthscale"][which] *= np.exp(h)
+            hm["lengthscale"][which] *= np.exp(-h)
+        else:
+            hp["outputscale"] *= np.exp(h)
+            hm["outputscale"] *= np.exp(-h)
+        fd = (oracle.kg_matvec(grid, hp, v) - oracle.kg_matvec(grid, hm, v)) / (2 * h)
+        np.testing.assert_allclose(oracle.dkg_matvec(grid, hyp, v, which), fd, rtol=1e-6, atol=1e-8)
+
+
+# --------------------------------------------------------------------------
+# Solves: Theorem 1 / Claim 5 (m-space mean == SKI mean), Prop. 1.
+# --------------------------------------------------------------------------
+def small_problem(seed=0, m=(14, 12), n=600):
+    rng = np.random.default_rng(seed)
+    grid = oracle.make_grid(list(m), lo=0.0, hi=1.0)
+    X = rng.uniform(0, 1, (len(m), n))
+    y = np.sin(4 * X[0]) + (np.cos(3 * X[1]) if len(m) > 1 else 0) + 0.1 * rng.standard_normal(n)
+    hyp = {"lengthscale": [0.2] * len(m), "outputscale": 1.2, "noise": 0.3}
+    return grid, X, y, hyp
+
+
+@pytest.mark.parametrize("m", [(30,), (14, 12), (6, 7, 5)])
+def test_m_space_mean_equals_dense_ski(m):
+    grid, X, y, hyp = small_problem(1, m, 500)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    mu, wtz, info = oracle.solve_mean(grid, hyp, wtw, wty, yty, tol=1e-13)
+    mu_d, z_d, W = oracle.ski_dense_mean(grid, hyp, X, y)
+    np.testing.assert_allclose(mu, mu_d, rtol=0, atol=1e-10 * np.abs(mu_d).max())
+    np.testing.assert_allclose(wtz, W.T @ z_d, atol=1e-9 * np.abs(W.T @ z_d).max())
+    xq = np.random.default_rng(9).uniform(0.1, 0.9, (len(m), 50))
+    np.testing.assert_allclose(oracle.interpolate(grid, mu, xq),
+                               oracle.dense_w(grid, xq) @ mu_d, atol=1e-9)
+
+
+def test_factorized_cg_iterates_equal_plain_cg():
+    """Prop. 1: Alg. 1 on the n x n SKI system, from x_0 = y / sigma^2, has
+    the same iterates as the factorized algorithm (compared through W^T x_k)."""
+    grid, X, y, hyp = small_problem(2, (10, 9), 300)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    _, _, info = oracle.solve_mean(grid, hyp, wtw, wty, yty, tol=1e-10, history=True)
+    W = oracle.dense_w(grid, X)
+    A = W @ oracle.kg_dense(grid, hyp) @ W.T + hyp["noise"] ** 2 * np.eye(300)
+    x = y / hyp["noise"] ** 2
+    r = y - A @ x
+    p = r.copy()
+    hist = [W.T @ x]
+    rr = r @ r
+    for k in range(1000):
+        Ap = A @ p
+        a = rr / (p @ Ap)
+        x = x + a * p
+        r = r - a * Ap
+        hist.append(W.T @ x)
+        rn = r @ r
+        if rn <= 1e-20 * (y @ y):
+            break
+        p = r + (rn / rr) * p
+        rr = rn
+    # exact agreement while rounding has not yet been amplified by the loss of
+    # orthogonality of finite-precision CG
+    for k in range(8):
+        np.testing.assert_allclose(info["wtx_history"][k], hist[k],
+                                   atol=1e-10 * np.abs(hist[-1]).max())
+    # both reach the same solution; iteration counts differ only through
+    # rounding (the paper reports near-identical counts)
+    np.testing.assert_allclose(info["wtx_history"][-1], hist[-1],
+                               atol=1e-6 * np.abs(hist[-1]).max())
+    n_plain = len(hist) - 1
+    assert info["iterations"] <= 1.5 * n_plain + 2
+
+
+def test_grid_rhs_solve():
+    grid, X, y, hyp = small_problem(3, (9, 8), 250)
+    wtw, _, _ = oracle.precompute(grid, X, y)
+    yhat = np.random.default_rng(0).standard_normal(72)
+    xd, _ = oracle.solve_grid_rhs(grid, hyp, wtw, yhat, tol=1e-13)
+    W = oracle.dense_w(grid, X)
+    A = W @ oracle.kg_dense(grid, hyp) @ W.T + hyp["noise"] ** 2 * np.eye(250)
+    ref = W.T @ np.linalg.solve(A, W @ yhat)
+    np.testing.assert_allclose(xd, ref, atol=1e-9 * np.abs(ref).max())
+
+
+def test_ski_mean_converges_to_exact_gp():
+    """(iii) The SKI mean approaches the exact GP mean (Fact 1) as the grid is
+    refined; Keys' kernel is third order, so halving h cuts the error >= 4x
+    until it levels off."""
+    rng = np.random.default_rng(0)
+    n = 400
+    x = rng.uniform(0, 1, n)
+    y = np.sin(6 * np.pi * x) + 0.5 * np.sin(20 * np.pi * x) + 0.1 * rng.standard_normal(n)
+    ell, s, sig = 0.05, 1.0, 0.1
+    xq = np.linspace(0.05, 0.95, 200)
+    exact = oracle.exact_gp_mean(x[:, None], y, xq[:, None], [ell], s, sig)
+    errs = []
+    for m in (40, 80, 160):
+        grid = oracle.make_grid([m], lo=0.0, hi=1.0)
+        wtw, wty, yty = oracle.precompute(grid, x, y)
+        mu, _, _ = oracle.solve_mean(grid, {"lengthscale": [ell], "outputscale": s, "noise": sig},
+                                     wtw, wty, yty, tol=1e-12)
+        errs.append(np.abs(oracle.interpolate(grid, mu, xq) - exact).max())
+    assert errs[1] < errs[0] / 4 and errs[2] < errs[1] / 4, errs
+
+
+# --------------------------------------------------------------------------
+# Log likelihood: Claim 6, Fact 2 == Def. 2, gradient, SLQ.
+# --------------------------------------------------------------------------
+def test_claim6_logdet_shift_and_fact2_equals_def2():
+    grid, X, y, hyp = small_problem(4, (8, 7), 200)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    W = oracle.dense_w(grid, X)
+    KG = oracle.kg_dense(grid, hyp)
+    s2 = hyp["noise"] ** 2
+    n, M = W.shape
+    ld_n = np.linalg.slogdet(W @ KG @ W.T + s2 * np.eye(n))[1]
+    ld_m = np.linalg.slogdet(KG @ (W.T @ W) + s2 * np.eye(M))[1]
+    assert abs(ld_n - (ld_m + (n - M) * np.log(s2))) < 1e-8 * abs(ld_n)
+    a = oracle.gsgp_mll_fact2(grid, hyp, wtw, wty, yty, n)
+    b = oracle.ski_dense_mll(grid, hyp, X, y)
+    assert abs(a - b) < 1e-8 * abs(b)
+
+
+def _fd_grad(f, hyp, d, h=1e-5):
+    g = np.zeros(d + 2)
+    for th in range(d + 2):
+        def shifted(e):
+            hp = {"lengthscale": list(hyp["lengthscale"]), "outputscale": hyp["outputscale"],
+                  "noise": hyp["noise"]}
+            if th < d:
+                hp["lengthscale"][th] *= np.exp(e)
+            elif th == d:
+                hp["outputscale"] *= np.exp(e)
+            else:
+                hp["noise"] *= np.exp(e)
+            return f(hp)
+        g[th] = (shifted(h) - shifted(-h)) / (2 * h)
+    return g
+
+
+def test_dense_gradient_vs_finite_differences():
+    grid, X, y, hyp = small_problem(5, (7, 6), 120)
+    g = oracle.ski_dense_grad(grid, hyp, X, y)
+    fd = _fd_grad(lambda hp: oracle.ski_dense_mll(grid, hp, X, y), hyp, 2)
+    np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-6)
+
+
+def test_mll_exact_trace_gradient_and_quadratic_term():
+    grid, X, y, hyp = small_problem(6, (7, 6), 150)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    sk = oracle.probe_sketches(grid, X, 11, 4)
+    mll, g, info = oracle.mll_and_grad(grid, hyp, wtw, wty, yty, 150, sk,
+                                       exact_trace=True, tol=1e-13)
+    np.testing.assert_allclose(g, oracle.ski_dense_grad(grid, hyp, X, y), rtol=1e-7, atol=1e-8)
+    W = oracle.dense_w(grid, X)
+    A = W @ oracle.kg_dense(grid, hyp) @ W.T + hyp["noise"] ** 2 * np.eye(150)
+    assert abs(info["q"] - y @ np.linalg.solve(A, y)) < 1e-8 * abs(info["q"])
+
+
+def test_lanczos_from_cg_matches_dense_lanczos():
+    grid, X, y, hyp = small_problem(7, (6, 7), 160)
+    wtw, _, _ = oracle.precompute(grid, X, y)
+    z = oracle.probe_values(3, 0, 160)
+    bhat = oracle.probe_sketches(grid, X, 3, 1)[0]
+    _, info = oracle.fcg_probe(grid, hyp, wtw, bhat, 160.0, tol=1e-14, maxiter=12)
+    T_cg = oracle.lanczos_from_cg(info["alpha"], info["beta"], 10)
+    W = oracle.dense_w(grid, X)
+    A = W @ oracle.kg_dense(grid, hyp) @ W.T + hyp["noise"] ** 2 * np.eye(160)
+    T_l, _ = oracle.lanczos_dense(A, z, 10)
+    np.testing.assert_allclose(T_cg, T_l, atol=1e-8 * np.abs(T_l).max())
+
+
+def test_fcg_probe_iterates_equal_dense_cg():
+    grid, X, y, hyp = small_problem(8, (7, 7), 180)
+    wtw, _, _ = oracle.precompute(grid, X, y)
+    z = oracle.probe_values(5, 1, 180)
+    bhat = oracle.probe_sketches(grid, X, 5, 2)[1]
+    wx, info = oracle.fcg_probe(grid, hyp, wtw, bhat, 180.0, tol=1e-12, history=True)
+    W = oracle.dense_w(grid, X)
+    A = W @ oracle.kg_dense(grid, hyp) @ W.T + hyp["noise"] ** 2 * np.eye(180)
+    x = np.zeros(180); r = z.copy(); p = r.copy(); rr = r @ r
+    for k in range(10):
+        Ap = A @ p
+        a = rr / (p @ Ap)
+        x += a * p; r -= a * Ap
+        np.testing.assert_allclose(info["wtx_history"][k], W.T @ x, atol=1e-9 * np.abs(W.T @ x).max())
+        rn = r @ r; p = r + rn / rr * p; rr = rn
+    np.testing.assert_allclose(wx, W.T @ np.linalg.solve(A, z), atol=1e-8 * np.abs(wx).max())
+
+
+def test_slq_logdet_unbiased():
+    grid, X, y, hyp = small_problem(9, (6, 6), 120)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    W = oracle.dense_w(grid, X)
+    A = W @ oracle.kg_dense(grid, hyp) @ W.T + hyp["noise"] ** 2 * np.eye(120)
+    exact = np.linalg.slogdet(A)[1]
+    sk = oracle.probe_sketches(grid, X, 21, 200)
+    _, _, info = oracle.mll_and_grad(grid, hyp, wtw, wty, yty, 120, sk, lanczos_steps=30)
+    samples = info["logdet_samples"]
+    se = samples.std(ddof=1) / np.sqrt(len(samples))
+    assert abs(samples.mean() - exact) < 4 * se + 1e-6 * abs(exact), (samples.mean(), exact, se)
+
+
+def test_hutchinson_gradient_close_to_exact():
+    grid, X, y, hyp = small_problem(10, (6, 6), 140)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    sk = oracle.probe_sketches(grid, X, 31, 64)
+    _, g_h, _ = oracle.mll_and_grad(grid, hyp, wtw, wty, yty, 140, sk)
+    g_e = oracle.ski_dense_grad(grid, hyp, X, y)
+    # loose statistical agreement (64 probes)
+    assert np.all(np.abs(g_h - g_e) < 0.25 * np.abs(g_e) + 2.0), (g_h, g_e)
