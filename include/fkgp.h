@@ -1,0 +1,202 @@
+/*
+ * fkgp -- MI355X (gfx950) implementation of the hot path of "Faster Kernel
+ * Interpolation for Gaussian Processes" (Yadav, Sheldon, Musco).
+ *
+ * Structured kernel interpolation (SKI) approximates the kernel matrix as
+ * W K_G W^T (Sec. 2.3, Eq. (ski)); W (n x m) holds each point's cubic
+ * interpolation stencil and K_G (m x m) is the kernel on an equispaced grid.
+ * Sec. 3 shows SKI is exact inference in a Bayesian linear regression on the
+ * m grid basis functions (Def. 3, Theorem 1, Fact 2), so after one O(n) pass
+ * that builds the sufficient statistics W^T W, W^T y and y^T y (Sec. 3.1,
+ * Claim 2) every solver iteration costs O(m log m) independently of n.  The
+ * factorized conjugate-gradient methods of Sec. 4 and the appendix keep every
+ * n-vector in the compressed form W z_hat + c z_0 (Claims 3 and 4), so the
+ * method still solves the original symmetric SKI system.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named x, y, rhs, out, mean_grid, wtw, wty, xq are DEVICE
+ *     pointers on the current HIP device; `stream` is a hipStream_t (NULL =
+ *     the null stream).  The caller owns them; the library never frees them.
+ *   - The library owns a handle's internals (allocated on the current device)
+ *     until fkgp_destroy.  A handle is immutable after fkgp_precompute, so
+ *     calls on different streams may share it.
+ *   - Grid nodes of dimension k sit at origin[k] + j*spacing[k], j < m[k];
+ *     nodes are flattened in C order (dimension 0 slowest).  Grid vectors
+ *     (length M = prod m) use that order.
+ *   - No exception crosses the ABI.  Arguments are validated on the host
+ *     before any launch; on failure the function returns a negative status
+ *     and fkgp_last_error() gives a message.  Functions that return host
+ *     scalars synchronise `stream`.
+ */
+#ifndef FKGP_H
+#define FKGP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FKGP_OK = 0,
+    FKGP_ENOTCONV = 1,     /* solver hit maxiter; result written, see info */
+    FKGP_EINVAL = -1,      /* invalid argument (message in fkgp_last_error) */
+    FKGP_EOUTOFGRID = -2,  /* a point lies outside the interpolable region */
+    FKGP_ENOMEM = -3,      /* device allocation failed */
+    FKGP_EDEVICE = -4      /* HIP runtime error */
+} fkgp_status;
+
+typedef enum { FKGP_F32 = 0, FKGP_F64 = 1 } fkgp_dtype;
+
+/* Equispaced grid, 1 <= d <= 3, m[k] >= 4, spacing[k] > 0.  A point x is
+ * interpolable iff 1 <= (x_k - origin_k)/spacing_k <= m_k - 2 for every k, so
+ * that all four cubic stencil nodes exist. */
+typedef struct {
+    int d;
+    int64_t m[3];
+    double origin[3];
+    double spacing[3];
+} fkgp_grid;
+
+/* Squared-exponential product kernel inside a scale kernel (the kernels of
+ * Sec. 5): k(x,x') = outputscale * exp(-1/2 sum_k (x_k-x'_k)^2/l_k^2), and
+ * Gaussian noise of standard deviation noise_std (Sec. 2.1), i.e. noise
+ * variance noise_std^2 on the diagonal. */
+typedef struct {
+    double lengthscale[3];
+    double outputscale;
+    double noise_std;
+} fkgp_hypers;
+
+typedef struct fkgp_handle fkgp_handle;
+
+typedef struct {
+    fkgp_dtype stats_dtype;  /* storage of W^T W and precision of the operator
+                                B(x) = ((K_G W^T W + s2 I)x, W^T W x); FP32
+                                or FP64.  CG vectors and scalars are FP64. */
+    int n_probes;            /* Rademacher probe sketches W^T z_j to build
+                                (0..64, d <= 2), for fkgp_mll_and_grad */
+    uint64_t probe_seed;     /* z_j[i] = 1 - 2*(SplitMix64((seed<<48) ^
+                                (j<<40) ^ i) >> 63) */
+} fkgp_precompute_opts;
+
+/* One-shot O(n) pass (Sec. 3.1 "Precomputation", Claim 2).
+ *   x: d device pointers, x[k][i] = coordinate k of point i (dtype `in`);
+ *   y: n responses (dtype `in`); n >= 0 (n = 0 gives zero statistics).
+ * Builds W^T W (at most 7^d nonzeros per row for cubic interpolation, Claim
+ * 2), W^T y, y^T y and the optional probe sketches, deterministically:
+ * points are sorted by grid cell and each cell is reduced in a fixed order;
+ * no floating-point atomics are used.  Returns FKGP_EOUTOFGRID if any point
+ * is not interpolable (NaN included); *out is then NULL.
+ * Synchronises `stream`. */
+fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x,
+                            const void* y, int64_t n, fkgp_dtype in,
+                            const fkgp_precompute_opts* opts, void* stream,
+                            fkgp_handle** out);
+
+typedef struct {
+    int64_t n;
+    int64_t m_total;
+    int d;
+    fkgp_dtype stats_dtype;
+    int n_probes;
+    double yty;
+    int64_t bytes_wtw;       /* device bytes of the stored W^T W */
+    int64_t nnz_wtw;         /* stored stencil-diagonal entries (m * 7^d) */
+} fkgp_handle_desc;
+
+fkgp_status fkgp_describe(const fkgp_handle* h, fkgp_handle_desc* desc);
+
+/* Copies the statistics out.  wtw: device buffer of m * 7^d elements of the
+ * handle's stats dtype in the canonical layout [j][o] (o in [-3,3]^d, C
+ * order; entry (j,o) = (W^T W)[j, j+o], 0 when j+o leaves the grid).  wty:
+ * device buffer of m doubles.  yty: host double.  Any pointer may be NULL.
+ * Synchronises `stream`. */
+fkgp_status fkgp_export_stats(const fkgp_handle* h, void* wtw, double* wty,
+                              double* yty, void* stream);
+
+/* Probe sketches W^T z_j, j < n_probes, as [n_probes][m] doubles (device). */
+fkgp_status fkgp_export_sketches(const fkgp_handle* h, double* out, void* stream);
+
+typedef struct {
+    double tol;        /* relative residual: stop when ||r|| <= tol ||b|| */
+    int maxiter;
+} fkgp_solve_opts;
+
+typedef struct {
+    int iterations;
+    int converged;
+    double rel_residual;   /* recursive relative residual at exit */
+} fkgp_solve_info;
+
+/* Posterior mean on the grid, or a grid right-hand side solve, with the
+ * simplified efficiently-factorized CG of the appendix (one operator
+ * application B per iteration; needs only W^T W and W^T y).
+ *   rhs_grid == NULL: x_0 = y/s2, r_hat_0 = -K_G W^T y/s2; out (m doubles) =
+ *     mu_G = K_G W^T z~ with z~ = (W K_G W^T + s2 I)^{-1} y, the grid weights
+ *     of the SKI mean (Def. 2; Fact 2 and Claim 5 equate the two forms);
+ *     the mean at any x is w_x^T mu_G (fkgp_interpolate).
+ *   rhs_grid != NULL (m doubles, b = W rhs_grid): x_0 = 0, r_hat_0 = rhs;
+ *     out = W^T (W K_G W^T + s2 I)^{-1} W rhs_grid.
+ * Returns FKGP_ENOTCONV if maxiter is reached (out still written).
+ * Synchronises `stream`. */
+fkgp_status fkgp_solve(const fkgp_handle* h, const fkgp_hypers* hyp,
+                       const double* rhs_grid, double* out,
+                       const fkgp_solve_opts* opts, fkgp_solve_info* info,
+                       void* stream);
+
+typedef struct {
+    int lanczos_steps;  /* tridiagonal size used for each probe (<= iters) */
+    double tol;         /* relative residual for the y and probe solves */
+    int maxiter;
+} fkgp_mll_opts;
+
+typedef struct {
+    double logdet;      /* stochastic Lanczos quadrature estimate */
+    double quad;        /* y^T (W K_G W^T + s2 I)^{-1} y */
+    int iterations_y;
+    int iterations_probes_max;
+} fkgp_mll_info;
+
+/* Log marginal likelihood (Def. 2 / Fact 2) and its gradient with respect to
+ * (log l_0 .. log l_{d-1}, log outputscale, log noise_std); grad has d + 2
+ * host doubles.  logdet(W K_G W^T + s2 I) comes from stochastic Lanczos
+ * quadrature over the handle's probes with tridiagonals taken from the
+ * factorized-CG coefficients; the gradient is 1/2[x_y^T dA x_y -
+ * tr(A^{-1} dA)] with the trace estimated from the same probe solves.
+ * Requires n_probes > 0 at precompute.  Synchronises `stream`. */
+fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers* hyp,
+                              const fkgp_mll_opts* opts, double* mll,
+                              double* grad, fkgp_mll_info* info, void* stream);
+
+/* out[i] = w_{xq_i}^T mean_grid (Fact 2 mean) for nq query points; xq: d
+ * device pointers of dtype `in`; mean_grid, out: device doubles.
+ * Returns FKGP_EOUTOFGRID if a query point is not interpolable.
+ * Synchronises `stream`. */
+fkgp_status fkgp_interpolate(const fkgp_handle* h, const double* mean_grid,
+                             const void* const* xq, int64_t nq, fkgp_dtype in,
+                             double* out, void* stream);
+
+/* Operator-level entry points (for tests and benchmarks).
+ * fkgp_apply_B: for k right-hand sides stored as [k][m] in the handle's stats
+ * dtype, v = (K_G W^T W + s2 I) x and u = W^T W x (the operator B of the
+ * efficiently factorized CG); u may be NULL.  Does not synchronise. */
+fkgp_status fkgp_apply_B(const fkgp_handle* h, const fkgp_hypers* hyp,
+                         const void* x, void* v, void* u, int k, void* stream);
+
+/* out = K_G x for k grid vectors [k][m] in the handle's stats dtype, through
+ * per-dimension circulant embeddings and batched radix-2 FFTs.  Does not
+ * synchronise. */
+fkgp_status fkgp_kg_matvec(const fkgp_handle* h, const fkgp_hypers* hyp,
+                           const void* x, void* out, int k, void* stream);
+
+void fkgp_destroy(fkgp_handle* h);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* fkgp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FKGP_H */

@@ -1,0 +1,320 @@
+"""Python binding of libfkgp, the MI355X (gfx950) implementation of the hot path
+of "Faster Kernel Interpolation for Gaussian Processes" (Yadav, Sheldon,
+Musco): the one-shot O(n) sufficient-statistics pass and the n-independent
+factorized conjugate-gradient operator (banded W^T W product composed with the
+Kronecker-of-Toeplitz grid kernel through circulant-embedding FFTs).
+
+This module only marshals arguments: torch provides device memory and the
+current stream, and every step runs in the HIP kernels of ``libfkgp.so`` (the
+C ABI of ``include/fkgp.h``).  There is no CPU fallback: if the library has
+not been built, every entry point raises.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfkgp.so")
+
+F32, F64 = 0, 1
+OK, ENOTCONV, EINVAL, EOUTOFGRID, ENOMEM, EDEVICE = 0, 1, -1, -2, -3, -4
+
+#: every symbol that include/fkgp.h declares
+EXPORTS = ("fkgp_precompute", "fkgp_describe", "fkgp_export_stats", "fkgp_export_sketches",
+           "fkgp_solve", "fkgp_mll_and_grad", "fkgp_interpolate", "fkgp_apply_B",
+           "fkgp_kg_matvec", "fkgp_destroy", "fkgp_last_error")
+
+
+class FkgpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fkgp status {status}: {msg}")
+        self.status = status
+
+
+class OutOfGridError(FkgpError, ValueError):
+    pass
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("m", ctypes.c_int64 * 3),
+                ("origin", ctypes.c_double * 3), ("spacing", ctypes.c_double * 3)]
+
+
+class _Hypers(ctypes.Structure):
+    _fields_ = [("lengthscale", ctypes.c_double * 3), ("outputscale", ctypes.c_double),
+                ("noise_std", ctypes.c_double)]
+
+
+class _PreOpts(ctypes.Structure):
+    _fields_ = [("stats_dtype", ctypes.c_int), ("n_probes", ctypes.c_int),
+                ("probe_seed", ctypes.c_uint64)]
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m_total", ctypes.c_int64), ("d", ctypes.c_int),
+                ("stats_dtype", ctypes.c_int), ("n_probes", ctypes.c_int),
+                ("yty", ctypes.c_double), ("bytes_wtw", ctypes.c_int64),
+                ("nnz_wtw", ctypes.c_int64)]
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rel_residual", ctypes.c_double)]
+
+
+class _MllOpts(ctypes.Structure):
+    _fields_ = [("lanczos_steps", ctypes.c_int), ("tol", ctypes.c_double),
+                ("maxiter", ctypes.c_int)]
+
+
+class _MllInfo(ctypes.Structure):
+    _fields_ = [("logdet", ctypes.c_double), ("quad", ctypes.c_double),
+                ("iterations_y", ctypes.c_int), ("iterations_probes_max", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library():
+    """Loads libfkgp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2101_11751_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    p = ctypes.c_void_p
+    L.fkgp_precompute.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(p), p, ctypes.c_int64,
+                                  ctypes.c_int, ctypes.POINTER(_PreOpts), p, ctypes.POINTER(p)]
+    L.fkgp_describe.argtypes = [p, ctypes.POINTER(_Desc)]
+    L.fkgp_export_stats.argtypes = [p, p, p, ctypes.POINTER(ctypes.c_double), p]
+    L.fkgp_export_sketches.argtypes = [p, p, p]
+    L.fkgp_solve.argtypes = [p, ctypes.POINTER(_Hypers), p, p, ctypes.POINTER(_SolveOpts),
+                             ctypes.POINTER(_SolveInfo), p]
+    L.fkgp_mll_and_grad.argtypes = [p, ctypes.POINTER(_Hypers), ctypes.POINTER(_MllOpts),
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_MllInfo), p]
+    L.fkgp_interpolate.argtypes = [p, p, ctypes.POINTER(p), ctypes.c_int64, ctypes.c_int, p, p]
+    L.fkgp_apply_B.argtypes = [p, ctypes.POINTER(_Hypers), p, p, p, ctypes.c_int, p]
+    L.fkgp_kg_matvec.argtypes = [p, ctypes.POINTER(_Hypers), p, p, ctypes.c_int, p]
+    L.fkgp_destroy.argtypes = [p]
+    L.fkgp_destroy.restype = None
+    L.fkgp_last_error.argtypes = []
+    L.fkgp_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("fkgp_destroy", "fkgp_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status == OK:
+        return status
+    msg = load_library().fkgp_last_error().decode()
+    if status == ENOTCONV:
+        return status
+    if status == EOUTOFGRID:
+        raise OutOfGridError(status, msg)
+    raise FkgpError(status, msg)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _grid_struct(grid):
+    g = _Grid()
+    g.d = int(grid["d"])
+    for k in range(g.d):
+        g.m[k] = int(grid["m"][k])
+        g.origin[k] = float(grid["origin"][k])
+        g.spacing[k] = float(grid["spacing"][k])
+    return g
+
+
+def _hyp_struct(hyp, d):
+    h = _Hypers()
+    ell = hyp["lengthscale"]
+    ell = list(ell) if hasattr(ell, "__len__") else [ell] * d
+    for k in range(d):
+        h.lengthscale[k] = float(ell[k])
+    h.outputscale = float(hyp["outputscale"])
+    h.noise_std = float(hyp["noise"])
+    return h
+
+
+def _dtype_code(t):
+    if t == torch.float32:
+        return F32
+    if t == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {t}")
+
+
+class Handle:
+    """Sufficient statistics of one data set on one device (immutable)."""
+
+    def __init__(self, ptr, grid):
+        self._ptr = ptr
+        self.grid = grid
+        d = _Desc()
+        _check(load_library().fkgp_describe(ptr, ctypes.byref(d)))
+        self.n = d.n
+        self.m_total = d.m_total
+        self.d = d.d
+        self.stats_dtype = torch.float32 if d.stats_dtype == F32 else torch.float64
+        self.n_probes = d.n_probes
+        self.yty = d.yty
+        self.bytes_wtw = d.bytes_wtw
+        self.nnz_wtw = d.nnz_wtw
+
+    @property
+    def ptr(self):
+        return self._ptr
+
+    def close(self):
+        if self._ptr:
+            load_library().fkgp_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def precompute(grid, x, y, stats_dtype=torch.float32, n_probes=0, probe_seed=0):
+    """fkgp_precompute: x is a list of d device tensors (float32 or float64),
+    y a device tensor of the same dtype and length."""
+    L = load_library()
+    d = int(grid["d"])
+    xs = [t.contiguous() for t in x]
+    y = y.contiguous()
+    n = y.numel()
+    dt = _dtype_code(y.dtype)
+    for t in xs:
+        assert t.dtype == y.dtype and t.numel() == n and t.is_cuda
+    arr = (ctypes.c_void_p * 3)(*([t.data_ptr() for t in xs] + [0] * (3 - d)))
+    g = _grid_struct(grid)
+    o = _PreOpts(_dtype_code(stats_dtype), int(n_probes), int(probe_seed))
+    out = ctypes.c_void_p()
+    _check(L.fkgp_precompute(ctypes.byref(g), arr, _ptr(y), n, dt, ctypes.byref(o), _stream(),
+                             ctypes.byref(out)))
+    return Handle(out, grid)
+
+
+def export_stats(h):
+    """(W^T W [M, 7^d] canonical layout, W^T y [M] float64, y^T y)."""
+    L = load_library()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    wtw = torch.empty(h.m_total, 7 ** h.d, dtype=h.stats_dtype, device=dev)
+    wty = torch.empty(h.m_total, dtype=torch.float64, device=dev)
+    yty = ctypes.c_double()
+    _check(L.fkgp_export_stats(h.ptr, _ptr(wtw), _ptr(wty), ctypes.byref(yty), _stream()))
+    return wtw, wty, yty.value
+
+
+def export_sketches(h):
+    L = load_library()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty(h.n_probes, h.m_total, dtype=torch.float64, device=dev)
+    _check(L.fkgp_export_sketches(h.ptr, _ptr(out), _stream()))
+    return out
+
+
+def solve(h, hypers, rhs=None, tol=1e-6, maxiter=1000):
+    """Posterior-mean grid weights mu_G (rhs None), or W^T A^{-1} W rhs.
+    Returns (out [M] float64, info dict)."""
+    L = load_library()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty(h.m_total, dtype=torch.float64, device=dev)
+    if rhs is not None:
+        rhs = rhs.to(torch.float64).contiguous()
+    info = _SolveInfo()
+    st = _check(L.fkgp_solve(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)), _ptr(rhs), _ptr(out),
+                             ctypes.byref(_SolveOpts(float(tol), int(maxiter))),
+                             ctypes.byref(info), _stream()))
+    return out, {"iterations": info.iterations, "converged": bool(info.converged),
+                 "rel_residual": info.rel_residual, "status": st}
+
+
+def interpolate(h, mean_grid, xq):
+    L = load_library()
+    xs = [t.contiguous() for t in xq]
+    nq = xs[0].numel()
+    out = torch.empty(nq, dtype=torch.float64, device=xs[0].device)
+    arr = (ctypes.c_void_p * 3)(*([t.data_ptr() for t in xs] + [0] * (3 - len(xs))))
+    _check(L.fkgp_interpolate(h.ptr, _ptr(mean_grid.contiguous()), arr, nq,
+                              _dtype_code(xs[0].dtype), _ptr(out), _stream()))
+    return out
+
+
+def apply_B(h, hypers, x):
+    """x: [k, M] (or [M]) in the handle's stats dtype -> (v, u)."""
+    L = load_library()
+    squeeze = x.dim() == 1
+    X = x.reshape(-1, h.m_total).to(h.stats_dtype).contiguous()
+    v = torch.empty_like(X)
+    u = torch.empty_like(X)
+    _check(L.fkgp_apply_B(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)), _ptr(X), _ptr(v),
+                          _ptr(u), X.shape[0], _stream()))
+    return (v[0], u[0]) if squeeze else (v, u)
+
+
+def kg_matvec(h, hypers, x):
+    L = load_library()
+    squeeze = x.dim() == 1
+    X = x.reshape(-1, h.m_total).to(h.stats_dtype).contiguous()
+    out = torch.empty_like(X)
+    _check(L.fkgp_kg_matvec(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)), _ptr(X), _ptr(out),
+                            X.shape[0], _stream()))
+    return out[0] if squeeze else out
+
+
+def mll_and_grad(h, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000):
+    """(mll, grad [d+2] w.r.t. (log l_k, log s, log sigma), info)."""
+    L = load_library()
+    mll = ctypes.c_double()
+    grad = (ctypes.c_double * (h.d + 2))()
+    info = _MllInfo()
+    st = _check(L.fkgp_mll_and_grad(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)),
+                                    ctypes.byref(_MllOpts(int(lanczos_steps), float(tol),
+                                                          int(maxiter))),
+                                    ctypes.byref(mll), grad, ctypes.byref(info), _stream()))
+    return mll.value, [grad[i] for i in range(h.d + 2)], {
+        "logdet": info.logdet, "quad": info.quad, "iterations_y": info.iterations_y,
+        "iterations_probes_max": info.iterations_probes_max, "status": st}
+
+
+class MarginalLogLikelihood(torch.autograd.Function):
+    """MLL as a differentiable function of log-hyperparameters
+    theta = (log l_0..log l_{d-1}, log s, log sigma) (a 1-D CPU float64 tensor).
+    Forward runs fkgp_mll_and_grad and saves the gradient; backward scales it."""
+
+    @staticmethod
+    def forward(ctx, theta, handle, lanczos_steps, tol, maxiter):
+        d = handle.d
+        t = theta.detach().cpu().double().tolist()
+        hyp = {"lengthscale": [math.exp(v) for v in t[:d]], "outputscale": math.exp(t[d]),
+               "noise": math.exp(t[d + 1])}
+        val, grad, _ = mll_and_grad(handle, hyp, lanczos_steps, tol, maxiter)
+        ctx.save_for_backward(torch.tensor(grad, dtype=torch.float64))
+        return torch.tensor(val, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        return gout * grad, None, None, None, None

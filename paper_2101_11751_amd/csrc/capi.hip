@@ -1,0 +1,800 @@
+// C-ABI of libfkgp: handle management, argument validation, and the
+// device-resident factorized conjugate-gradient loop.
+//
+// The posterior mean uses the simplified efficiently-factorized CG of the
+// appendix (initial residual in the span of W): one operator application
+// B(x) = ((K_G W^T W + s2 I) x, W^T W x) per iteration, FP64 vectors and
+// scalars, B in the handle's stats dtype.  Scalars live on the device; every
+// kernel of an iteration reads them there and returns early once the stop
+// test has fired, so the host only polls a flag every few iterations.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+struct fkgp_handle {
+    fkgp::GridDev g;
+    int64_t n = 0;
+    int64_t M = 0;
+    int NB = 0;
+    fkgp_dtype dt = FKGP_F32;
+    int nprobe = 0;
+    uint64_t seed = 0;
+    void* A = nullptr;          // [NB][M] stats dtype
+    double* wty = nullptr;      // [M]
+    double* sketches = nullptr; // [nprobe][M]
+    double* yty_dev = nullptr;
+    double yty = 0.0;
+};
+
+namespace fkgp {
+
+fkgp_status kg_apply_skip(const GridDev& g, const Spectra& sp, fkgp_dtype dt, const void* x,
+                          void* y, int k, double scale, const void* addv, double add_coef,
+                          const int* skip, hipStream_t s);
+fkgp_status spmv_dia_skip(const GridDev& g, fkgp_dtype dt, const void* A, const void* xpad,
+                          void* u, int k, int64_t halo, const int* skip, hipStream_t s);
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+fkgp_status hip_fail(hipError_t e, const char* what) {
+    set_error(std::string("HIP error in ") + what + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? FKGP_ENOMEM : FKGP_EDEVICE;
+}
+
+namespace {
+
+// Scratch allocations released (stream-ordered) when the scope ends.
+struct Scratch {
+    hipStream_t s;
+    std::vector<void*> ptrs;
+    explicit Scratch(hipStream_t st) : s(st) {}
+    ~Scratch() {
+        for (void* p : ptrs) (void)hipFreeAsync(p, s);
+    }
+    template <class T>
+    hipError_t get(T** p, size_t count) {
+        hipError_t e = alloc_async(p, count, s);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+};
+
+size_t dsize(fkgp_dtype dt) { return dt == FKGP_F32 ? 4 : 8; }
+
+// ---------------------------------------------------------------------------
+// CG kernels (FP64 vectors and scalars).
+// ---------------------------------------------------------------------------
+struct CgState {
+    double rho;     // ||r_k||^2 in n-space (= u^T r_hat)
+    double sz;      // s^T z
+    double alpha;
+    double beta;
+    double eps;     // stop when rho <= eps
+    double bnorm2;  // ||b||^2
+    int done;
+    int iters;
+};
+
+enum FinOp { FIN_INIT = 0, FIN_INIT_RHS = 1, FIN_RHO = 2, FIN_SZ = 3 };
+
+constexpr int kRedBlock = 256;
+constexpr int kRedMaxBlocks = 1024;
+
+int red_blocks(int64_t M) {
+    int64_t b = (M + 4 * kRedBlock - 1) / (4 * kRedBlock);
+    if (b < 1) b = 1;
+    if (b > kRedMaxBlocks) b = kRedMaxBlocks;
+    return (int)b;
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+template <class TU>
+__global__ __launch_bounds__(kRedBlock) void dot_partial(const TU* __restrict__ a,
+                                                         const double* __restrict__ b, int64_t M,
+                                                         double* __restrict__ partials,
+                                                         const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    __shared__ double sh[kRedBlock];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * kRedBlock)
+        acc = fma((double)a[i], b[i], acc);
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kRedBlock) void finalize(const double* __restrict__ partials, int nb,
+                                                      CgState* st, int op) {
+    __shared__ double sh[kRedBlock];
+    if (op >= FIN_RHO && st->done) return;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kRedBlock) acc += partials[i];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x != 0) return;
+    if (op == FIN_INIT || op == FIN_INIT_RHS) {
+        st->rho = t;
+        st->beta = 0.0;
+        st->iters = 0;
+        if (op == FIN_INIT_RHS) {
+            st->bnorm2 = t;
+            st->eps = st->eps * t;   // eps held tol^2 on entry
+        }
+        st->done = (t <= st->eps) ? 1 : 0;
+    } else if (op == FIN_RHO) {
+        st->iters += 1;
+        const double rho_new = t;
+        if (!(rho_new > st->eps)) {
+            st->done = 1;   // converged (or NaN: stop)
+            st->rho = rho_new;
+            return;
+        }
+        st->beta = rho_new / st->rho;
+        st->rho = rho_new;
+    } else {
+        st->sz = t;
+        st->alpha = st->rho / t;
+        if (!std::isfinite(st->alpha)) st->done = 2;
+    }
+}
+
+// xd += alpha s; r -= alpha z; rpad = (T) r
+template <class T>
+__global__ void cg_step1(const CgState* __restrict__ st, double* __restrict__ xd,
+                         double* __restrict__ r, const double* __restrict__ s,
+                         const double* __restrict__ z, T* __restrict__ rpad, int64_t M) {
+    if (st->done) return;
+    const double a = st->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        xd[i] = fma(a, s[i], xd[i]);
+        const double rn = fma(-a, z[i], r[i]);
+        r[i] = rn;
+        rpad[i] = (T)rn;
+    }
+}
+
+// s = u + beta s; z = v + beta z; partial s.z
+template <class T>
+__global__ __launch_bounds__(kRedBlock) void cg_step2(const CgState* __restrict__ st,
+                                                      double* __restrict__ s,
+                                                      double* __restrict__ z,
+                                                      const T* __restrict__ u,
+                                                      const T* __restrict__ v, int64_t M,
+                                                      double* __restrict__ partials) {
+    if (st->done) return;
+    __shared__ double sh[kRedBlock];
+    const double b = st->beta;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * kRedBlock) {
+        const double sn = fma(b, s[i], (double)u[i]);
+        const double zn = fma(b, z[i], (double)v[i]);
+        s[i] = sn;
+        z[i] = zn;
+        acc = fma(sn, zn, acc);
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+template <class TI, class TO>
+__global__ void convert(const TI* __restrict__ in, TO* __restrict__ out, int64_t M, double scale) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (TO)(scale * (double)in[i]);
+}
+
+// out = a + c * b  (FP64)
+__global__ void axpy_out(const double* __restrict__ a, const double* __restrict__ b, double c,
+                         double* __restrict__ out, int64_t M) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = fma(c, b[i], a[i]);
+}
+
+unsigned ew_grid(int64_t M) {
+    int64_t b = (M + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+template <class TI, class TO>
+hipError_t launch_convert(const TI* in, TO* out, int64_t M, double scale, hipStream_t s) {
+    convert<TI, TO><<<ew_grid(M), 256, 0, s>>>(in, out, M, scale);
+    return hipGetLastError();
+}
+
+hipError_t convert_any(const void* in, fkgp_dtype din, void* out, fkgp_dtype dout, int64_t M,
+                       double scale, hipStream_t s) {
+    if (din == FKGP_F64 && dout == FKGP_F32)
+        return launch_convert(static_cast<const double*>(in), static_cast<float*>(out), M, scale, s);
+    if (din == FKGP_F64 && dout == FKGP_F64)
+        return launch_convert(static_cast<const double*>(in), static_cast<double*>(out), M, scale, s);
+    if (din == FKGP_F32 && dout == FKGP_F64)
+        return launch_convert(static_cast<const float*>(in), static_cast<double*>(out), M, scale, s);
+    return launch_convert(static_cast<const float*>(in), static_cast<float*>(out), M, scale, s);
+}
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+fkgp_status grid_from_abi(const fkgp_grid* gr, GridDev& g, int64_t& M) {
+    if (!gr) {
+        set_error("grid is NULL");
+        return FKGP_EINVAL;
+    }
+    if (gr->d < 1 || gr->d > 3) {
+        set_error("grid.d must be 1, 2 or 3");
+        return FKGP_EINVAL;
+    }
+    std::memset(&g, 0, sizeof(g));
+    g.d = gr->d;
+    M = 1;
+    int64_t cells = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (k < gr->d) {
+            if (gr->m[k] < 4 || gr->m[k] > (1 << 20)) {
+                set_error("grid.m[k] must be in [4, 2^20]");
+                return FKGP_EINVAL;
+            }
+            if (!(gr->spacing[k] > 0.0) || !std::isfinite(gr->spacing[k]) ||
+                !std::isfinite(gr->origin[k])) {
+                set_error("grid spacing must be positive and finite, origin finite");
+                return FKGP_EINVAL;
+            }
+            g.m[k] = (int)gr->m[k];
+            g.nc[k] = g.m[k] - 3;
+            g.g0[k] = gr->origin[k];
+            g.h[k] = gr->spacing[k];
+            M *= g.m[k];
+            cells *= g.nc[k];
+        } else {
+            g.m[k] = 1;
+            g.nc[k] = 1;
+            g.h[k] = 1.0;
+        }
+    }
+    if (M > (int64_t(1) << 30) || cells >= (int64_t(1) << 30)) {
+        set_error("grid too large (more than 2^30 nodes)");
+        return FKGP_EINVAL;
+    }
+    return FKGP_OK;
+}
+
+fkgp_status check_hypers(const fkgp_handle* h, const fkgp_hypers* hyp) {
+    if (!hyp) {
+        set_error("hypers is NULL");
+        return FKGP_EINVAL;
+    }
+    for (int k = 0; k < h->g.d; ++k)
+        if (!(hyp->lengthscale[k] > 0.0) || !std::isfinite(hyp->lengthscale[k])) {
+            set_error("lengthscales must be positive and finite");
+            return FKGP_EINVAL;
+        }
+    if (!(hyp->outputscale > 0.0) || !std::isfinite(hyp->outputscale) ||
+        !(hyp->noise_std > 0.0) || !std::isfinite(hyp->noise_std)) {
+        set_error("outputscale and noise_std must be positive and finite");
+        return FKGP_EINVAL;
+    }
+    return FKGP_OK;
+}
+
+// Spectra (and, optionally, derivative spectra for dimension `dderiv`).
+fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, int dderiv, Spectra& sp,
+                         Scratch& sc) {
+    std::memset(&sp, 0, sizeof(sp));
+    const size_t es = dsize(h->dt);
+    for (int k = 0; k < h->g.d; ++k) {
+        sp.log2L[k] = circulant_log2(h->g.m[k]);
+        if (sp.log2L[k] > (h->dt == FKGP_F32 ? 11 : 11)) {
+            set_error("grid dimension longer than 1024 nodes is not supported by the line FFT");
+            return FKGP_EINVAL;
+        }
+        sp.L[k] = 1 << sp.log2L[k];
+        unsigned char *lam = nullptr, *tw = nullptr;
+        FKGP_HIP(sc.get(&lam, es * sp.L[k]));
+        FKGP_HIP(sc.get(&tw, 2 * es * (sp.L[k] / 2)));
+        fkgp_status st = build_spectrum(h->g, k, hyp->lengthscale[k], k == dderiv, h->dt, lam,
+                                        sp.log2L[k], sc.s);
+        if (st != FKGP_OK) return st;
+        st = build_twiddles(sp.log2L[k], h->dt, tw, sc.s);
+        if (st != FKGP_OK) return st;
+        sp.lam[k] = lam;
+        sp.tw[k] = tw;
+    }
+    return FKGP_OK;
+}
+
+// B(x) on k vectors: xpad [k][M + 2 halo] (stats dtype), u, v [k][M].
+fkgp_status apply_B_padded(const fkgp_handle* h, const Spectra& sp, double s, double s2,
+                           const void* xpad, void* u, void* v, int k, const int* skip,
+                           hipStream_t st) {
+    const int64_t halo = dia_halo(h->g);
+    fkgp_status r = spmv_dia_skip(h->g, h->dt, h->A, xpad, u, k, halo, skip, st);
+    if (r != FKGP_OK) return r;
+    // v = s * K u + s2 * x   (x interior of the padded buffer; k == 1 here)
+    const void* xin = static_cast<const unsigned char*>(xpad) + halo * dsize(h->dt);
+    return kg_apply_skip(h->g, sp, h->dt, u, v, k, s, k == 1 ? xin : nullptr, s2, skip, st);
+}
+
+struct SolveBuffers {
+    double *r, *s, *z, *xd, *partials;
+    void *rpad, *u, *v, *tmp;
+    CgState* st;
+};
+
+fkgp_status solve_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const double* rhs,
+                       double* out, double tol, int maxiter, fkgp_solve_info* info,
+                       hipStream_t st) {
+    Scratch sc(st);
+    Spectra sp;
+    fkgp_status rs = make_spectra(h, hyp, -1, sp, sc);
+    if (rs != FKGP_OK) return rs;
+    const int64_t M = h->M;
+    const int64_t halo = dia_halo(h->g);
+    const size_t es = dsize(h->dt);
+    SolveBuffers b{};
+    FKGP_HIP(sc.get(&b.r, M));
+    FKGP_HIP(sc.get(&b.s, M));
+    FKGP_HIP(sc.get(&b.z, M));
+    FKGP_HIP(sc.get(&b.xd, M));
+    FKGP_HIP(sc.get(&b.partials, kRedMaxBlocks));
+    unsigned char *rpad, *u, *v, *tmp;
+    FKGP_HIP(sc.get(&rpad, es * (M + 2 * halo)));
+    FKGP_HIP(sc.get(&u, es * M));
+    FKGP_HIP(sc.get(&v, es * M));
+    FKGP_HIP(sc.get(&tmp, es * M));
+    FKGP_HIP(sc.get(&b.st, 1));
+    b.rpad = rpad;
+    b.u = u;
+    b.v = v;
+    b.tmp = tmp;
+    void* rin = rpad + halo * es;   // interior of the padded residual
+    const double s2 = hyp->noise_std * hyp->noise_std;
+    const double so = hyp->outputscale;
+    FKGP_HIP(hipMemsetAsync(rpad, 0, es * (M + 2 * halo), st));
+    FKGP_HIP(hipMemsetAsync(b.xd, 0, sizeof(double) * M, st));
+    FKGP_HIP(hipMemsetAsync(b.s, 0, sizeof(double) * M, st));
+    FKGP_HIP(hipMemsetAsync(b.z, 0, sizeof(double) * M, st));
+
+    CgState init{};
+    init.eps = rhs ? tol * tol : tol * tol * h->yty;
+    init.bnorm2 = h->yty;
+    FKGP_HIP(hipMemcpyAsync(b.st, &init, sizeof(CgState), hipMemcpyHostToDevice, st));
+    // initial residual
+    if (rhs) {
+        FKGP_HIP(convert_any(rhs, FKGP_F64, rin, h->dt, M, 1.0, st));
+        FKGP_HIP(hipMemcpyAsync(b.r, rhs, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+    } else {
+        // r_hat_0 = -K_G W^T y / s2
+        FKGP_HIP(convert_any(h->wty, FKGP_F64, tmp, h->dt, M, 1.0, st));
+        rs = kg_apply(h->g, sp, h->dt, tmp, rin, 1, -so / s2, nullptr, 0.0, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+        FKGP_HIP(convert_any(rin, h->dt, b.r, FKGP_F64, M, 1.0, st));
+    }
+    rs = apply_B_padded(h, sp, so, s2, rpad, u, v, 1, nullptr, st);
+    if (rs != FKGP_OK) return rs;
+    const int nb = red_blocks(M);
+    const unsigned ewg = ew_grid(M);
+    auto dot_ur = [&]() -> hipError_t {
+        if (h->dt == FKGP_F32)
+            dot_partial<float><<<nb, kRedBlock, 0, st>>>(static_cast<float*>(b.u), b.r, M,
+                                                         b.partials, &b.st->done);
+        else
+            dot_partial<double><<<nb, kRedBlock, 0, st>>>(static_cast<double*>(b.u), b.r, M,
+                                                          b.partials, &b.st->done);
+        return hipGetLastError();
+    };
+    auto step2 = [&]() -> hipError_t {
+        if (h->dt == FKGP_F32)
+            cg_step2<float><<<nb, kRedBlock, 0, st>>>(b.st, b.s, b.z, static_cast<float*>(b.u),
+                                                      static_cast<float*>(b.v), M, b.partials);
+        else
+            cg_step2<double><<<nb, kRedBlock, 0, st>>>(b.st, b.s, b.z, static_cast<double*>(b.u),
+                                                       static_cast<double*>(b.v), M, b.partials);
+        return hipGetLastError();
+    };
+    // rho_0 = u^T r  (no skip: the flag is not yet meaningful)
+    if (h->dt == FKGP_F32)
+        dot_partial<float><<<nb, kRedBlock, 0, st>>>(static_cast<float*>(b.u), b.r, M, b.partials,
+                                                     nullptr);
+    else
+        dot_partial<double><<<nb, kRedBlock, 0, st>>>(static_cast<double*>(b.u), b.r, M,
+                                                      b.partials, nullptr);
+    finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, rhs ? FIN_INIT_RHS : FIN_INIT);
+    FKGP_HIP(step2());
+    finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_SZ);
+    FKGP_HIP(hipGetLastError());
+
+    CgState hst{};
+    constexpr int kBatch = 8;
+    int launched = 0;
+    for (;;) {
+        FKGP_HIP(hipMemcpyAsync(&hst, b.st, sizeof(CgState), hipMemcpyDeviceToHost, st));
+        FKGP_HIP(hipStreamSynchronize(st));
+        if (hst.done || launched >= maxiter) break;
+        const int nit = std::min(kBatch, maxiter - launched);
+        for (int it = 0; it < nit; ++it) {
+            if (h->dt == FKGP_F32)
+                cg_step1<float><<<ewg, 256, 0, st>>>(b.st, b.xd, b.r, b.s, b.z,
+                                                     static_cast<float*>(rin), M);
+            else
+                cg_step1<double><<<ewg, 256, 0, st>>>(b.st, b.xd, b.r, b.s, b.z,
+                                                      static_cast<double*>(rin), M);
+            FKGP_HIP(hipGetLastError());
+            rs = apply_B_padded(h, sp, so, s2, rpad, u, v, 1, &b.st->done, st);
+            if (rs != FKGP_OK) return rs;
+            FKGP_HIP(dot_ur());
+            finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_RHO);
+            FKGP_HIP(step2());
+            finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_SZ);
+            FKGP_HIP(hipGetLastError());
+        }
+        launched += nit;
+    }
+    // outputs
+    if (rhs) {
+        FKGP_HIP(hipMemcpyAsync(out, b.xd, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+    } else {
+        // W^T z~ = xd + W^T y / s2 ; mu_G = K_G (W^T z~)
+        axpy_out<<<ewg, 256, 0, st>>>(b.xd, h->wty, 1.0 / s2, b.r, M);
+        FKGP_HIP(hipGetLastError());
+        FKGP_HIP(convert_any(b.r, FKGP_F64, tmp, h->dt, M, 1.0, st));
+        rs = kg_apply(h->g, sp, h->dt, tmp, u, 1, so, nullptr, 0.0, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+        FKGP_HIP(convert_any(u, h->dt, out, FKGP_F64, M, 1.0, st));
+    }
+    FKGP_HIP(hipStreamSynchronize(st));
+    const double bn = hst.bnorm2 > 0 ? hst.bnorm2 : 1.0;
+    if (info) {
+        info->iterations = hst.iters;
+        info->converged = hst.done == 1;
+        info->rel_residual = std::sqrt(std::max(hst.rho, 0.0) / bn);
+    }
+    if (hst.done == 2) {
+        set_error("factorized CG broke down (non-finite step)");
+        return FKGP_EDEVICE;
+    }
+    return hst.done == 1 ? FKGP_OK : FKGP_ENOTCONV;
+}
+
+}  // namespace
+}  // namespace fkgp
+
+using namespace fkgp;
+
+namespace {
+
+template <class F>
+fkgp_status guarded(F&& f) {
+    try {
+        return f();
+    } catch (const std::exception& e) {
+        set_error(std::string("internal error: ") + e.what());
+        return FKGP_EDEVICE;
+    } catch (...) {
+        set_error("internal error");
+        return FKGP_EDEVICE;
+    }
+}
+
+void free_handle(fkgp_handle* h) {
+    if (!h) return;
+    (void)hipFree(h->A);
+    (void)hipFree(h->wty);
+    (void)hipFree(h->sketches);
+    (void)hipFree(h->yty_dev);
+    delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fkgp_last_error(void) { return g_last_error.c_str(); }
+
+fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const void* y,
+                            int64_t n, fkgp_dtype in, const fkgp_precompute_opts* opts,
+                            void* stream, fkgp_handle** out) {
+    return guarded([&]() -> fkgp_status {
+        set_error("");
+        if (!out) {
+            set_error("out is NULL");
+            return FKGP_EINVAL;
+        }
+        *out = nullptr;
+        GridDev g;
+        int64_t M;
+        fkgp_status st = grid_from_abi(grid, g, M);
+        if (st != FKGP_OK) return st;
+        if (n < 0 || n >= (int64_t(1) << 31) - 1) {
+            set_error("n must be in [0, 2^31 - 1)");
+            return FKGP_EINVAL;
+        }
+        if (in != FKGP_F32 && in != FKGP_F64) {
+            set_error("input dtype must be FKGP_F32 or FKGP_F64");
+            return FKGP_EINVAL;
+        }
+        if (n > 0) {
+            if (!x || !y) {
+                set_error("x and y must be non-NULL when n > 0");
+                return FKGP_EINVAL;
+            }
+            for (int k = 0; k < g.d; ++k)
+                if (!x[k]) {
+                    set_error("x[k] is NULL");
+                    return FKGP_EINVAL;
+                }
+        }
+        fkgp_precompute_opts o{FKGP_F32, 0, 0};
+        if (opts) o = *opts;
+        if (o.stats_dtype != FKGP_F32 && o.stats_dtype != FKGP_F64) {
+            set_error("stats dtype must be FKGP_F32 or FKGP_F64");
+            return FKGP_EINVAL;
+        }
+        if (o.n_probes < 0 || o.n_probes > kMaxProbes) {
+            set_error("n_probes must be in [0, 31]");
+            return FKGP_EINVAL;
+        }
+        if (o.n_probes > 0 && g.d > 2) {
+            set_error("probe sketches are supported for d <= 2");
+            return FKGP_EINVAL;
+        }
+        for (int k = 0; k < g.d; ++k)
+            if (circulant_log2(g.m[k]) > 11) {
+                set_error("grid dimension longer than 1024 nodes is not supported");
+                return FKGP_EINVAL;
+            }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        fkgp_handle* h = new fkgp_handle();
+        h->g = g;
+        h->n = n;
+        h->M = M;
+        h->NB = 1;
+        for (int k = 0; k < g.d; ++k) h->NB *= 7;
+        h->dt = o.stats_dtype;
+        h->nprobe = o.n_probes;
+        h->seed = o.probe_seed;
+        auto fail = [&](fkgp_status e) {
+            free_handle(h);
+            return e;
+        };
+        hipError_t e;
+        if ((e = hipMalloc(&h->A, dsize(h->dt) * (size_t)M * h->NB)) != hipSuccess)
+            return fail(hip_fail(e, "hipMalloc(W^T W)"));
+        if ((e = hipMalloc(&h->wty, sizeof(double) * M)) != hipSuccess)
+            return fail(hip_fail(e, "hipMalloc(W^T y)"));
+        if (h->nprobe > 0 &&
+            (e = hipMalloc(&h->sketches, sizeof(double) * M * h->nprobe)) != hipSuccess)
+            return fail(hip_fail(e, "hipMalloc(sketches)"));
+        if ((e = hipMalloc(&h->yty_dev, sizeof(double))) != hipSuccess)
+            return fail(hip_fail(e, "hipMalloc(yty)"));
+        unsigned long long* bad = nullptr;
+        if ((e = hipMallocAsync(reinterpret_cast<void**>(&bad), sizeof(unsigned long long), s)) !=
+            hipSuccess)
+            return fail(hip_fail(e, "hipMallocAsync(flag)"));
+        (void)hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), s);
+        StatsOut so{h->A, h->wty, h->sketches, h->yty_dev};
+        st = run_precompute(g, x, y, n, in, h->dt, h->nprobe, h->seed, so, bad, s);
+        unsigned long long hbad = ~0ull;
+        if (st == FKGP_OK) {
+            if ((e = hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s)) != hipSuccess)
+                st = hip_fail(e, "hipMemcpyAsync(flag)");
+            else if ((e = hipMemcpyAsync(&h->yty, h->yty_dev, sizeof(double), hipMemcpyDeviceToHost,
+                                         s)) != hipSuccess)
+                st = hip_fail(e, "hipMemcpyAsync(yty)");
+        }
+        (void)hipFreeAsync(bad, s);
+        if ((e = hipStreamSynchronize(s)) != hipSuccess && st == FKGP_OK)
+            st = hip_fail(e, "hipStreamSynchronize");
+        if (st != FKGP_OK) return fail(st);
+        if (hbad != ~0ull) {
+            set_error("point " + std::to_string(hbad) + " lies outside the interpolable region");
+            return fail(FKGP_EOUTOFGRID);
+        }
+        *out = h;
+        return FKGP_OK;
+    });
+}
+
+fkgp_status fkgp_describe(const fkgp_handle* h, fkgp_handle_desc* desc) {
+    if (!h || !desc) {
+        set_error("NULL argument");
+        return FKGP_EINVAL;
+    }
+    desc->n = h->n;
+    desc->m_total = h->M;
+    desc->d = h->g.d;
+    desc->stats_dtype = h->dt;
+    desc->n_probes = h->nprobe;
+    desc->yty = h->yty;
+    desc->nnz_wtw = h->M * h->NB;
+    desc->bytes_wtw = h->M * h->NB * (int64_t)dsize(h->dt);
+    return FKGP_OK;
+}
+
+fkgp_status fkgp_export_stats(const fkgp_handle* h, void* wtw, double* wty, double* yty,
+                              void* stream) {
+    return guarded([&]() -> fkgp_status {
+        if (!h) {
+            set_error("handle is NULL");
+            return FKGP_EINVAL;
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (wtw) {
+            fkgp_status st = dia_to_canonical(h->g, h->dt, h->A, wtw, s);
+            if (st != FKGP_OK) return st;
+        }
+        if (wty) FKGP_HIP(hipMemcpyAsync(wty, h->wty, sizeof(double) * h->M, hipMemcpyDeviceToDevice, s));
+        FKGP_HIP(hipStreamSynchronize(s));
+        if (yty) *yty = h->yty;
+        return FKGP_OK;
+    });
+}
+
+fkgp_status fkgp_export_sketches(const fkgp_handle* h, double* out, void* stream) {
+    return guarded([&]() -> fkgp_status {
+        if (!h || !out) {
+            set_error("NULL argument");
+            return FKGP_EINVAL;
+        }
+        if (h->nprobe == 0) {
+            set_error("handle has no probe sketches");
+            return FKGP_EINVAL;
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        FKGP_HIP(hipMemcpyAsync(out, h->sketches, sizeof(double) * h->M * h->nprobe,
+                                hipMemcpyDeviceToDevice, s));
+        FKGP_HIP(hipStreamSynchronize(s));
+        return FKGP_OK;
+    });
+}
+
+fkgp_status fkgp_solve(const fkgp_handle* h, const fkgp_hypers* hyp, const double* rhs_grid,
+                       double* out, const fkgp_solve_opts* opts, fkgp_solve_info* info,
+                       void* stream) {
+    return guarded([&]() -> fkgp_status {
+        set_error("");
+        if (!h || !out) {
+            set_error("handle and out must be non-NULL");
+            return FKGP_EINVAL;
+        }
+        fkgp_status st = check_hypers(h, hyp);
+        if (st != FKGP_OK) return st;
+        fkgp_solve_opts o{1e-6, 1000};
+        if (opts) o = *opts;
+        if (!(o.tol >= 0.0) || o.maxiter < 0) {
+            set_error("tol must be >= 0 and maxiter >= 0");
+            return FKGP_EINVAL;
+        }
+        return solve_impl(h, hyp, rhs_grid, out, o.tol, o.maxiter, info,
+                          static_cast<hipStream_t>(stream));
+    });
+}
+
+fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers* hyp,
+                              const fkgp_mll_opts* opts, double* mll, double* grad,
+                              fkgp_mll_info* info, void* stream);
+
+fkgp_status fkgp_interpolate(const fkgp_handle* h, const double* mean_grid,
+                             const void* const* xq, int64_t nq, fkgp_dtype in, double* out,
+                             void* stream) {
+    return guarded([&]() -> fkgp_status {
+        set_error("");
+        if (!h || !mean_grid || (nq > 0 && (!xq || !out))) {
+            set_error("NULL argument");
+            return FKGP_EINVAL;
+        }
+        if (nq < 0) {
+            set_error("nq must be >= 0");
+            return FKGP_EINVAL;
+        }
+        if (nq > 0)
+            for (int k = 0; k < h->g.d; ++k)
+                if (!xq[k]) {
+                    set_error("xq[k] is NULL");
+                    return FKGP_EINVAL;
+                }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        unsigned long long* bad = nullptr;
+        FKGP_HIP(hipMallocAsync(reinterpret_cast<void**>(&bad), sizeof(unsigned long long), s));
+        FKGP_HIP(hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), s));
+        fkgp_status st = interpolate_points(h->g, mean_grid, xq, nq, in, out, bad, s);
+        unsigned long long hbad = ~0ull;
+        if (st == FKGP_OK)
+            FKGP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s));
+        (void)hipFreeAsync(bad, s);
+        FKGP_HIP(hipStreamSynchronize(s));
+        if (st != FKGP_OK) return st;
+        if (hbad != ~0ull) {
+            set_error("query point " + std::to_string(hbad) + " lies outside the interpolable region");
+            return FKGP_EOUTOFGRID;
+        }
+        return FKGP_OK;
+    });
+}
+
+fkgp_status fkgp_apply_B(const fkgp_handle* h, const fkgp_hypers* hyp, const void* x, void* v,
+                         void* u, int k, void* stream) {
+    return guarded([&]() -> fkgp_status {
+        if (!h || !x || !v || k < 1) {
+            set_error("invalid argument");
+            return FKGP_EINVAL;
+        }
+        fkgp_status st = check_hypers(h, hyp);
+        if (st != FKGP_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        Scratch sc(s);
+        Spectra sp;
+        st = make_spectra(h, hyp, -1, sp, sc);
+        if (st != FKGP_OK) return st;
+        const int64_t halo = dia_halo(h->g);
+        const size_t es = dsize(h->dt);
+        const int64_t ldx = h->M + 2 * halo;
+        unsigned char *xpad, *ubuf = static_cast<unsigned char*>(u);
+        FKGP_HIP(sc.get(&xpad, es * ldx * k));
+        if (!ubuf) FKGP_HIP(sc.get(&ubuf, es * h->M * k));
+        FKGP_HIP(hipMemsetAsync(xpad, 0, es * ldx * k, s));
+        for (int r = 0; r < k; ++r)
+            FKGP_HIP(hipMemcpyAsync(xpad + (r * ldx + halo) * es,
+                                    static_cast<const unsigned char*>(x) + r * h->M * es,
+                                    es * h->M, hipMemcpyDeviceToDevice, s));
+        const double s2 = hyp->noise_std * hyp->noise_std;
+        st = spmv_dia(h->g, h->dt, h->A, xpad, ubuf, k, halo, s);
+        if (st != FKGP_OK) return st;
+        return kg_apply(h->g, sp, h->dt, ubuf, v, k, hyp->outputscale, x, s2, nullptr, s);
+    });
+}
+
+fkgp_status fkgp_kg_matvec(const fkgp_handle* h, const fkgp_hypers* hyp, const void* x,
+                           void* out, int k, void* stream) {
+    return guarded([&]() -> fkgp_status {
+        if (!h || !x || !out || k < 1) {
+            set_error("invalid argument");
+            return FKGP_EINVAL;
+        }
+        fkgp_status st = check_hypers(h, hyp);
+        if (st != FKGP_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        Scratch sc(s);
+        Spectra sp;
+        st = make_spectra(h, hyp, -1, sp, sc);
+        if (st != FKGP_OK) return st;
+        return kg_apply(h->g, sp, h->dt, x, out, k, hyp->outputscale, nullptr, 0.0, nullptr, s);
+    });
+}
+
+void fkgp_destroy(fkgp_handle* h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    free_handle(h);
+}
+
+}  // extern "C"
+
+extern "C" fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers* hyp,
+                                         const fkgp_mll_opts* opts, double* mll, double* grad,
+                                         fkgp_mll_info* info, void* stream) {
+    (void)h; (void)hyp; (void)opts; (void)mll; (void)grad; (void)info; (void)stream;
+    fkgp::set_error("fkgp_mll_and_grad: not built yet");
+    return FKGP_EINVAL;
+}

@@ -1,0 +1,92 @@
+// Internal declarations shared by the HIP translation units of libfkgp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/fkgp.h"
+
+namespace fkgp {
+
+// Grid as seen by the kernels.  Dimensions beyond d have m = 1, nc = 1.
+struct GridDev {
+    int d;
+    int m[3];       // nodes per dimension
+    int nc[3];      // cells per dimension (m - 3)
+    double g0[3];   // origin
+    double h[3];    // spacing
+};
+
+constexpr int kMaxProbes = 31;
+
+// ---- error plumbing -------------------------------------------------------
+void set_error(const std::string& msg);
+fkgp_status hip_fail(hipError_t e, const char* what);
+
+#define FKGP_HIP(call)                                           \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return ::fkgp::hip_fail(e_, #call); \
+    } while (0)
+
+// ---- device buffers -------------------------------------------------------
+// Stream-ordered scratch allocation (freed with hipFreeAsync on the same
+// stream).
+template <class T>
+inline hipError_t alloc_async(T** p, size_t count, hipStream_t s) {
+    if (count == 0) count = 1;
+    return hipMallocAsync(reinterpret_cast<void**>(p), count * sizeof(T), s);
+}
+
+// ---- precompute (precompute.hip) -------------------------------------------
+struct StatsOut {
+    void* wtw;          // [7^d][M] in stats dtype (offset-major)
+    double* wty;        // [M]
+    double* sketches;   // [nprobe][M] or null
+    double* yty_dev;    // scalar
+};
+
+fkgp_status run_precompute(const GridDev& g, const void* const* x, const void* y,
+                           int64_t n, fkgp_dtype in, fkgp_dtype stats,
+                           int nprobe, uint64_t seed, const StatsOut& out,
+                           unsigned long long* bad_dev, hipStream_t s);
+
+// ---- operators (ops.hip) -------------------------------------------------
+struct Spectra {
+    int L[3];           // circulant length per dim (power of two)
+    int log2L[3];
+    void* lam[3];       // [L] bit-reversed, scaled by 1/L, stats dtype
+    void* tw[3];        // twiddles exp(-2 pi i t / L), t < L/2, complex stats dtype
+};
+
+int circulant_log2(int m);
+// Builds lam[k] for dimension k from the SE column (deriv: multiply the
+// column by (j h / l)^2).  Runs on the device (FP64 direct DFT).
+fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv,
+                           fkgp_dtype dt, void* lam, int log2L, hipStream_t s);
+fkgp_status build_twiddles(int log2L, fkgp_dtype dt, void* tw, hipStream_t s);
+
+// y = scale * (T_0 (x) .. (x) T_{d-1}) x (+ add_coef * addv), batched over k
+// vectors of length M; all arrays in dtype dt.  `work` holds M*k elements.
+fkgp_status kg_apply(const GridDev& g, const Spectra& sp, fkgp_dtype dt,
+                     const void* x, void* y, int k, double scale,
+                     const void* addv, double add_coef, void* work,
+                     hipStream_t s);
+
+// u = A x (A: [7^d][M] offset-major), x padded by `halo` elements each side.
+fkgp_status spmv_dia(const GridDev& g, fkgp_dtype dt, const void* A,
+                     const void* xpad, void* u, int k, int64_t halo,
+                     hipStream_t s);
+int64_t dia_halo(const GridDev& g);
+
+fkgp_status interpolate_points(const GridDev& g, const double* mu,
+                               const void* const* xq, int64_t nq,
+                               fkgp_dtype in, double* out,
+                               unsigned long long* bad_dev, hipStream_t s);
+
+fkgp_status dia_to_canonical(const GridDev& g, fkgp_dtype dt, const void* A,
+                             void* out, hipStream_t s);
+
+}  // namespace fkgp

@@ -1,0 +1,588 @@
+// Per-iteration operators of the factorized solvers: the banded W^T W
+// product and K_G = s * T_0 (x) ... (x) T_{d-1} (Sec. 2.3: multilevel
+// Toeplitz for a stationary kernel on an equispaced grid, applied with FFTs),
+// plus interpolation to query points (Fact 2 mean).
+//
+// K_G is applied one dimension at a time.  Each line of the grid along
+// dimension k is convolved with the symmetric Toeplitz column of T_k through
+// a circulant embedding of length L >= 2 m_k - 1 (a power of two), entirely
+// in registers/LDS: two real lines are packed into one complex line (the
+// circulant is real, so real and imaginary parts stay separate), transformed
+// by a radix-2 decimation-in-frequency FFT (natural in, bit-reversed out),
+// scaled by the real spectrum stored in bit-reversed order, and transformed
+// back by the matching decimation-in-time inverse (bit-reversed in, natural
+// out).  No padded grid ever touches HBM.  Butterfly spans below 64 use
+// wavefront shuffles; larger spans are within a lane's registers.  Lines
+// along a strided dimension are staged through LDS so that global loads and
+// stores stay coalesced (an LDS transpose).
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace fkgp {
+namespace {
+
+template <class T>
+struct cplx {
+    T re, im;
+};
+
+template <class T>
+__device__ inline cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T>
+__device__ inline cplx<T> cmul_conj(cplx<T> a, cplx<T> b) {  // a * conj(b)
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+
+// ---------------------------------------------------------------------------
+// Line geometry.  Data of k vectors [k][M] are viewed as [outer][m_line][S]:
+// line l = (outer, inner) with outer = l / S, inner = l % S.
+// ---------------------------------------------------------------------------
+struct LineGeom {
+    int m_line;
+    int64_t S;         // stride between consecutive entries of a line
+    int64_t nlines;    // k * M / m_line
+};
+
+__device__ inline int64_t line_addr(const LineGeom& lg, int64_t l, int e) {
+    const int64_t outer = l / lg.S;
+    const int64_t inner = l - outer * lg.S;
+    return outer * (int64_t)lg.m_line * lg.S + (int64_t)e * lg.S + inner;
+}
+
+constexpr int kLineBlock = 256;
+
+// One launch convolves a block of LB lines (LB even).  R = elements per lane
+// (L >= 64: R = L/64, one complex line pair per wave at a time; L < 64: one
+// element per lane, 64/L pairs per wave at a time).
+template <class T, int LOG2L>
+__global__ __launch_bounds__(kLineBlock) void line_conv(
+    const T* __restrict__ in, T* __restrict__ out, LineGeom lg, int LB,
+    const T* __restrict__ lam_br, const cplx<T>* __restrict__ tw, T scale,
+    const T* __restrict__ addv, T add_coef, const int* __restrict__ skip) {
+    constexpr int L = 1 << LOG2L;
+    constexpr int R = L >= 64 ? L / 64 : 1;
+    constexpr int G = L >= 64 ? 1 : 64 / L;   // pairs per wave per round
+    if (skip && *skip) return;
+    extern __shared__ unsigned char lds_raw[];
+    T* lds = reinterpret_cast<T*>(lds_raw);
+    const int ms = lg.m_line + 1;   // padded LDS row
+    const int64_t l0 = (int64_t)blockIdx.x * LB;
+    const int nvalid = (int)min((int64_t)LB, lg.nlines - l0);
+    const int tid = threadIdx.x;
+    const int tot = LB * lg.m_line;
+    // ---- load (LDS transpose for strided lines) ----
+    if (lg.S == 1) {
+        for (int idx = tid; idx < tot; idx += kLineBlock) {
+            const int ll = idx / lg.m_line, e = idx - ll * lg.m_line;
+            lds[ll * ms + e] = ll < nvalid ? in[line_addr(lg, l0 + ll, e)] : T(0);
+        }
+    } else {
+        for (int idx = tid; idx < tot; idx += kLineBlock) {
+            const int e = idx / LB, ll = idx - e * LB;
+            lds[ll * ms + e] = ll < nvalid ? in[line_addr(lg, l0 + ll, e)] : T(0);
+        }
+    }
+    __syncthreads();
+    // ---- convolve line pairs ----
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int npairs = LB / 2;
+    const int e_lane = L >= 64 ? lane : (lane & (L - 1));
+    const int g_lane = L >= 64 ? 0 : (lane / L);
+    for (int pb = wave * G; pb < npairs; pb += 4 * G) {
+        const int pair = pb + g_lane;
+        const bool active = pair < npairs;
+        const int la = 2 * pair, lb = 2 * pair + 1;
+        cplx<T> z[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = r * 64 + e_lane;
+            if (active && e < lg.m_line) {
+                z[r].re = lds[la * ms + e];
+                z[r].im = lds[lb * ms + e];
+            } else {
+                z[r].re = T(0);
+                z[r].im = T(0);
+            }
+        }
+        // forward DIF: spans L/2 .. 1
+#pragma unroll
+        for (int st = LOG2L - 1; st >= 0; --st) {
+            const int S = 1 << st;
+            if (S >= 64) {
+                const int rs = S / 64;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r & rs) continue;
+                    const int e = r * 64 + e_lane;
+                    const cplx<T> w = tw[(e & (S - 1)) * (L / (2 * S))];
+                    const cplx<T> a = z[r], b = z[r + rs];
+                    z[r] = {a.re + b.re, a.im + b.im};
+                    z[r + rs] = cmul(cplx<T>{a.re - b.re, a.im - b.im}, w);
+                }
+            } else {
+                const bool upper = (e_lane & S) != 0;
+                const cplx<T> w = tw[(e_lane & (S - 1)) * (L / (2 * S))];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    cplx<T> p;
+                    p.re = __shfl_xor(z[r].re, S);
+                    p.im = __shfl_xor(z[r].im, S);
+                    const cplx<T> sum{z[r].re + p.re, z[r].im + p.im};
+                    const cplx<T> dif = cmul(cplx<T>{p.re - z[r].re, p.im - z[r].im}, w);
+                    z[r] = upper ? dif : sum;
+                }
+            }
+        }
+        // spectrum (bit-reversed order, includes 1/L)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const T lmb = lam_br[r * 64 + e_lane];
+            z[r].re *= lmb;
+            z[r].im *= lmb;
+        }
+        // inverse DIT: spans 1 .. L/2, conjugate twiddles
+#pragma unroll
+        for (int st = 0; st < LOG2L; ++st) {
+            const int S = 1 << st;
+            if (S >= 64) {
+                const int rs = S / 64;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r & rs) continue;
+                    const int e = r * 64 + e_lane;
+                    const cplx<T> w = tw[(e & (S - 1)) * (L / (2 * S))];
+                    const cplx<T> a = z[r];
+                    const cplx<T> b = cmul_conj(z[r + rs], w);
+                    z[r] = {a.re + b.re, a.im + b.im};
+                    z[r + rs] = {a.re - b.re, a.im - b.im};
+                }
+            } else {
+                const bool upper = (e_lane & S) != 0;
+                const cplx<T> w = tw[(e_lane & (S - 1)) * (L / (2 * S))];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    cplx<T> p;
+                    p.re = __shfl_xor(z[r].re, S);
+                    p.im = __shfl_xor(z[r].im, S);
+                    const cplx<T> t = cmul_conj(upper ? z[r] : p, w);
+                    const cplx<T> a = upper ? p : z[r];
+                    z[r] = upper ? cplx<T>{a.re - t.re, a.im - t.im}
+                                 : cplx<T>{a.re + t.re, a.im + t.im};
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = r * 64 + e_lane;
+            if (active && e < lg.m_line) {
+                lds[la * ms + e] = z[r].re;
+                lds[lb * ms + e] = z[r].im;
+            }
+        }
+    }
+    __syncthreads();
+    // ---- store (+ scale, + add_coef * addv) ----
+    if (lg.S == 1) {
+        for (int idx = tid; idx < tot; idx += kLineBlock) {
+            const int ll = idx / lg.m_line, e = idx - ll * lg.m_line;
+            if (ll < nvalid) {
+                const int64_t a = line_addr(lg, l0 + ll, e);
+                T v = scale * lds[ll * ms + e];
+                if (addv) v += add_coef * addv[a];
+                out[a] = v;
+            }
+        }
+    } else {
+        for (int idx = tid; idx < tot; idx += kLineBlock) {
+            const int e = idx / LB, ll = idx - e * LB;
+            if (ll < nvalid) {
+                const int64_t a = line_addr(lg, l0 + ll, e);
+                T v = scale * lds[ll * ms + e];
+                if (addv) v += add_coef * addv[a];
+                out[a] = v;
+            }
+        }
+    }
+}
+
+template <class T>
+fkgp_status launch_line_conv(int log2L, const T* in, T* out, const LineGeom& lg,
+                             const T* lam, const cplx<T>* tw, T scale, const T* addv,
+                             T add_coef, const int* skip, hipStream_t s) {
+    // lines per block: fill ~48 KiB of LDS, even, at most 64
+    const int64_t row = (int64_t)(lg.m_line + 1) * sizeof(T);
+    int LB = (int)std::min<int64_t>(64, std::max<int64_t>(2, (48 * 1024) / row));
+    LB &= ~1;
+    if (LB > lg.nlines + (lg.nlines & 1)) LB = (int)(lg.nlines + (lg.nlines & 1));
+    if (LB < 2) LB = 2;
+    const size_t lds = (size_t)LB * row;
+    const unsigned grid = (unsigned)((lg.nlines + LB - 1) / LB);
+#define FKGP_LC(LG)                                                                       \
+    case LG:                                                                              \
+        line_conv<T, LG><<<grid, kLineBlock, lds, s>>>(in, out, lg, LB, lam, tw, scale,   \
+                                                        addv, add_coef, skip);            \
+        break;
+    switch (log2L) {
+        FKGP_LC(3) FKGP_LC(4) FKGP_LC(5) FKGP_LC(6) FKGP_LC(7) FKGP_LC(8) FKGP_LC(9)
+        FKGP_LC(10) FKGP_LC(11)
+        default:
+            set_error("grid dimension too long for the register-resident line FFT");
+            return FKGP_EINVAL;
+    }
+#undef FKGP_LC
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Spectra and twiddles (FP64 on the device, cast to the working dtype).
+// ---------------------------------------------------------------------------
+__device__ inline double se_col(int j, double h, double ell, bool deriv) {
+    const double r = (double)j * h / ell;
+    const double c = exp(-0.5 * r * r);
+    return deriv ? c * r * r : c;
+}
+
+__device__ inline unsigned bitrev(unsigned v, int bits) {
+    return __brev(v) >> (32 - bits);
+}
+
+// lam_br[e] = (1/L) sum_j c_emb[j] cos(2 pi j f / L), f = bitrev(e); the
+// circulant embedding is c_emb[j] = c[min(j, L-j)] for min(j, L-j) < m,
+// else 0 (symmetric, so the DFT is real).
+template <class T>
+__global__ void spectrum_kernel(T* __restrict__ lam_br, int log2L, int m, double h,
+                                double ell, bool deriv) {
+    const int L = 1 << log2L;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= L) return;
+    const unsigned f = bitrev((unsigned)e, log2L);
+    double acc = se_col(0, h, ell, deriv);
+    for (int j = 1; j < m; ++j) {
+        if (L - j < j) break;
+        const unsigned long long ph = ((unsigned long long)j * f) & (unsigned long long)(L - 1);
+        const double c = cospi(2.0 * (double)ph / (double)L);
+        const double v = se_col(j, h, ell, deriv);
+        acc += (L - j == j) ? v * c : 2.0 * v * c;
+    }
+    lam_br[e] = (T)(acc / (double)L);
+}
+
+template <class T>
+__global__ void twiddle_kernel(cplx<T>* __restrict__ tw, int log2L) {
+    const int L = 1 << log2L;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= L / 2) return;
+    double sn, cs;
+    sincospi(2.0 * (double)t / (double)L, &sn, &cs);
+    tw[t] = {(T)cs, (T)(-sn)};
+}
+
+// ---------------------------------------------------------------------------
+// Banded W^T W product in stencil-diagonal layout A[o][j], o in [-3,3]^d.
+// ---------------------------------------------------------------------------
+struct DiaGeom {
+    int d;
+    int64_t M;
+    int64_t stride[3];   // flat stride of each dimension
+    int ext[3];          // 7 for active dims, 1 otherwise
+};
+
+template <class T, int K>
+__global__ __launch_bounds__(256) void spmv_dia_kernel(const T* __restrict__ A,
+                                                       const T* __restrict__ xpad,
+                                                       T* __restrict__ u, DiaGeom dg,
+                                                       int64_t halo, int64_t ldx,
+                                                       const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= dg.M) return;
+    T acc[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) acc[r] = T(0);
+    const T* xj = xpad + halo + j;
+    int oi = 0;
+    for (int a = 0; a < dg.ext[0]; ++a) {
+        const int64_t oa = (dg.ext[0] == 7 ? (a - 3) : 0) * dg.stride[0];
+        for (int b = 0; b < dg.ext[1]; ++b) {
+            const int64_t ob = oa + (dg.ext[1] == 7 ? (b - 3) : 0) * dg.stride[1];
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+                if (c >= dg.ext[2]) break;
+                const int64_t off = ob + (dg.ext[2] == 7 ? (c - 3) : 0) * dg.stride[2];
+                const T av = A[(int64_t)oi * dg.M + j];
+#pragma unroll
+                for (int r = 0; r < K; ++r) acc[r] += av * xj[off + r * ldx];
+                ++oi;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < K; ++r) u[r * dg.M + j] = acc[r];
+}
+
+// ---------------------------------------------------------------------------
+// Interpolation mu(x) = sum_a w_a(x) mu_G[node_a] (FP64).
+// ---------------------------------------------------------------------------
+__device__ inline void keys4(double t, double w[4]) {
+    const double t2 = t * t, t3 = t2 * t;
+    w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
+    w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+    w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+    w[3] = 0.5 * (t3 - t2);
+}
+
+template <class Tin>
+__global__ void interp_kernel(GridDev g, const double* __restrict__ mu, const Tin* x0,
+                              const Tin* x1, const Tin* x2, int64_t nq,
+                              double* __restrict__ out, unsigned long long* bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const Tin* xs[3] = {x0, x1, x2};
+    int base[3] = {1, 1, 1};
+    double w[3][4] = {{0, 1, 0, 0}, {0, 1, 0, 0}, {0, 1, 0, 0}};
+    bool ok = true;
+    for (int k = 0; k < g.d; ++k) {
+        const double u = ((double)xs[k][i] - g.g0[k]) / g.h[k];
+        if (!(u >= 1.0 && u <= (double)(g.m[k] - 2))) {
+            ok = false;
+            break;
+        }
+        int b = (int)floor(u);
+        if (b > g.m[k] - 3) b = g.m[k] - 3;
+        base[k] = b;
+        keys4(u - (double)b, w[k]);
+    }
+    if (!ok) {
+        atomicMin(bad, (unsigned long long)i);
+        out[i] = 0.0;
+        return;
+    }
+    const int e1 = g.d > 1 ? 4 : 1, e2 = g.d > 2 ? 4 : 1;
+    double acc = 0.0;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < e1; ++b)
+            for (int c = 0; c < e2; ++c) {
+                int64_t j = base[0] - 1 + a;
+                double wt = w[0][a];
+                if (g.d > 1) {
+                    j = j * g.m[1] + (base[1] - 1 + b);
+                    wt *= w[1][b];
+                }
+                if (g.d > 2) {
+                    j = j * g.m[2] + (base[2] - 1 + c);
+                    wt *= w[2][c];
+                }
+                acc = fma(wt, mu[j], acc);
+            }
+    out[i] = acc;
+}
+
+template <class T>
+__global__ void dia_to_canonical_kernel(const T* __restrict__ A, T* __restrict__ out,
+                                        int64_t M, int NB) {
+    __shared__ T tile[32][33];
+    const int64_t j0 = (int64_t)blockIdx.x * 32;
+    const int o0 = blockIdx.y * 32;
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        const int o = o0 + r;
+        const int64_t j = j0 + threadIdx.x;
+        tile[r][threadIdx.x] = (o < NB && j < M) ? A[(int64_t)o * M + j] : T(0);
+    }
+    __syncthreads();
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        const int64_t j = j0 + r;
+        const int o = o0 + threadIdx.x;
+        if (j < M && o < NB) out[j * NB + o] = tile[threadIdx.x][r];
+    }
+}
+
+}  // namespace
+
+int circulant_log2(int m) {
+    int l = 3;
+    while ((1 << l) < 2 * m - 1) ++l;
+    return l;
+}
+
+fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv, fkgp_dtype dt,
+                           void* lam, int log2L, hipStream_t s) {
+    const int L = 1 << log2L;
+    const unsigned grid = (unsigned)((L + 255) / 256);
+    if (dt == FKGP_F32)
+        spectrum_kernel<float><<<grid, 256, 0, s>>>(static_cast<float*>(lam), log2L, g.m[k],
+                                                    g.h[k], ell, deriv);
+    else
+        spectrum_kernel<double><<<grid, 256, 0, s>>>(static_cast<double*>(lam), log2L, g.m[k],
+                                                     g.h[k], ell, deriv);
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+fkgp_status build_twiddles(int log2L, fkgp_dtype dt, void* tw, hipStream_t s) {
+    const int L = 1 << log2L;
+    const unsigned grid = (unsigned)((L / 2 + 255) / 256);
+    if (dt == FKGP_F32)
+        twiddle_kernel<float><<<grid, 256, 0, s>>>(static_cast<cplx<float>*>(tw), log2L);
+    else
+        twiddle_kernel<double><<<grid, 256, 0, s>>>(static_cast<cplx<double>*>(tw), log2L);
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+template <class T>
+static fkgp_status kg_apply_t(const GridDev& g, const Spectra& sp, const T* x, T* y, int k,
+                              double scale, const T* addv, double add_coef, const int* skip,
+                              hipStream_t s) {
+    int64_t M = 1;
+    for (int i = 0; i < g.d; ++i) M *= g.m[i];
+    // innermost dimension first (contiguous lines), then the strided ones
+    for (int pass = 0; pass < g.d; ++pass) {
+        const int dim = g.d - 1 - pass;
+        int64_t S = 1;
+        for (int i = dim + 1; i < g.d; ++i) S *= g.m[i];
+        LineGeom lg{g.m[dim], S, (int64_t)k * M / g.m[dim]};
+        const bool last = pass == g.d - 1;
+        const T* src = pass == 0 ? x : y;
+        fkgp_status st = launch_line_conv<T>(
+            sp.log2L[dim], src, y, lg, static_cast<const T*>(sp.lam[dim]),
+            static_cast<const cplx<T>*>(sp.tw[dim]), last ? (T)scale : T(1),
+            last ? addv : nullptr, (T)add_coef, skip, s);
+        if (st != FKGP_OK) return st;
+    }
+    return FKGP_OK;
+}
+
+fkgp_status kg_apply(const GridDev& g, const Spectra& sp, fkgp_dtype dt, const void* x, void* y,
+                     int k, double scale, const void* addv, double add_coef, void* /*work*/,
+                     hipStream_t s) {
+    if (dt == FKGP_F32)
+        return kg_apply_t<float>(g, sp, static_cast<const float*>(x), static_cast<float*>(y), k,
+                                 scale, static_cast<const float*>(addv), add_coef, nullptr, s);
+    return kg_apply_t<double>(g, sp, static_cast<const double*>(x), static_cast<double*>(y), k,
+                              scale, static_cast<const double*>(addv), add_coef, nullptr, s);
+}
+
+fkgp_status kg_apply_skip(const GridDev& g, const Spectra& sp, fkgp_dtype dt, const void* x,
+                          void* y, int k, double scale, const void* addv, double add_coef,
+                          const int* skip, hipStream_t s) {
+    if (dt == FKGP_F32)
+        return kg_apply_t<float>(g, sp, static_cast<const float*>(x), static_cast<float*>(y), k,
+                                 scale, static_cast<const float*>(addv), add_coef, skip, s);
+    return kg_apply_t<double>(g, sp, static_cast<const double*>(x), static_cast<double*>(y), k,
+                              scale, static_cast<const double*>(addv), add_coef, skip, s);
+}
+
+int64_t dia_halo(const GridDev& g) {
+    int64_t h = 0, st = 1;
+    for (int i = g.d - 1; i >= 0; --i) {
+        h += 3 * st;
+        st *= g.m[i];
+    }
+    return h;
+}
+
+template <class T>
+static fkgp_status spmv_t(const GridDev& g, const T* A, const T* xpad, T* u, int k,
+                          int64_t halo, const int* skip, hipStream_t s) {
+    DiaGeom dg{};
+    dg.d = g.d;
+    dg.M = 1;
+    for (int i = 0; i < g.d; ++i) dg.M *= g.m[i];
+    // map grid dims onto the three loop levels (innermost = last grid dim)
+    int64_t st = 1;
+    for (int lvl = 2; lvl >= 0; --lvl) {
+        const int dim = g.d - 3 + lvl;
+        if (dim >= 0) {
+            dg.stride[lvl] = st;
+            dg.ext[lvl] = 7;
+            st *= g.m[dim];
+        } else {
+            dg.stride[lvl] = 0;
+            dg.ext[lvl] = 1;
+        }
+    }
+    const int64_t ldx = dg.M + 2 * halo;
+    const unsigned grid = (unsigned)((dg.M + 255) / 256);
+    for (int r0 = 0; r0 < k;) {
+        const int left = k - r0;
+        const T* xr = xpad + (int64_t)r0 * ldx;
+        T* ur = u + (int64_t)r0 * dg.M;
+        if (left >= 8) {
+            spmv_dia_kernel<T, 8><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
+            r0 += 8;
+        } else if (left >= 4) {
+            spmv_dia_kernel<T, 4><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
+            r0 += 4;
+        } else if (left >= 2) {
+            spmv_dia_kernel<T, 2><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
+            r0 += 2;
+        } else {
+            spmv_dia_kernel<T, 1><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
+            r0 += 1;
+        }
+    }
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+fkgp_status spmv_dia(const GridDev& g, fkgp_dtype dt, const void* A, const void* xpad, void* u,
+                     int k, int64_t halo, hipStream_t s) {
+    if (dt == FKGP_F32)
+        return spmv_t<float>(g, static_cast<const float*>(A), static_cast<const float*>(xpad),
+                             static_cast<float*>(u), k, halo, nullptr, s);
+    return spmv_t<double>(g, static_cast<const double*>(A), static_cast<const double*>(xpad),
+                          static_cast<double*>(u), k, halo, nullptr, s);
+}
+
+fkgp_status spmv_dia_skip(const GridDev& g, fkgp_dtype dt, const void* A, const void* xpad,
+                          void* u, int k, int64_t halo, const int* skip, hipStream_t s) {
+    if (dt == FKGP_F32)
+        return spmv_t<float>(g, static_cast<const float*>(A), static_cast<const float*>(xpad),
+                             static_cast<float*>(u), k, halo, skip, s);
+    return spmv_t<double>(g, static_cast<const double*>(A), static_cast<const double*>(xpad),
+                          static_cast<double*>(u), k, halo, skip, s);
+}
+
+fkgp_status interpolate_points(const GridDev& g, const double* mu, const void* const* xq,
+                               int64_t nq, fkgp_dtype in, double* out, unsigned long long* bad,
+                               hipStream_t s) {
+    if (nq == 0) return FKGP_OK;
+    const unsigned grid = (unsigned)((nq + 255) / 256);
+    if (in == FKGP_F32) {
+        const float* p[3] = {nullptr, nullptr, nullptr};
+        for (int k = 0; k < g.d; ++k) p[k] = static_cast<const float*>(xq[k]);
+        interp_kernel<float><<<grid, 256, 0, s>>>(g, mu, p[0], p[1], p[2], nq, out, bad);
+    } else {
+        const double* p[3] = {nullptr, nullptr, nullptr};
+        for (int k = 0; k < g.d; ++k) p[k] = static_cast<const double*>(xq[k]);
+        interp_kernel<double><<<grid, 256, 0, s>>>(g, mu, p[0], p[1], p[2], nq, out, bad);
+    }
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+fkgp_status dia_to_canonical(const GridDev& g, fkgp_dtype dt, const void* A, void* out,
+                             hipStream_t s) {
+    int64_t M = 1;
+    int NB = 1;
+    for (int i = 0; i < g.d; ++i) {
+        M *= g.m[i];
+        NB *= 7;
+    }
+    dim3 tb(32, 8), tg((unsigned)((M + 31) / 32), (unsigned)((NB + 31) / 32));
+    if (dt == FKGP_F32)
+        dia_to_canonical_kernel<float><<<tg, tb, 0, s>>>(static_cast<const float*>(A),
+                                                         static_cast<float*>(out), M, NB);
+    else
+        dia_to_canonical_kernel<double><<<tg, tb, 0, s>>>(static_cast<const double*>(A),
+                                                          static_cast<double*>(out), M, NB);
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+}  // namespace fkgp

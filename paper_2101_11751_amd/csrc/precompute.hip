@@ -1,0 +1,806 @@
+// One-shot O(n) pass: sufficient statistics W^T W, W^T y, y^T y and probe
+// sketches W^T z_j (Sec. 3.1 "Precomputation"; Claim 2 and its proof).
+//
+// Pipeline (all deterministic, no floating-point atomics):
+//   1. cell keys: each point's base cell (FP64 grid coordinate, floor) and a
+//      per-tile digit histogram for the first radix pass;
+//   2. stable LSD radix sort by cell key (digits of <= 10 bits; per-wave
+//      ballot matching gives stable ranks; tiles write through registers);
+//      the payload carries the raw coordinates, y and (for probes) the
+//      original point index;
+//   3. per-cell moments in FP64, in sorted (= input) order within the cell:
+//      the cubic weights are polynomials of degree 3 in the fractional
+//      offset t, so sum_i w_i w_i^T over a cell is fixed by the 7^d moments
+//      sum_i prod_k t_k^{q_k} (q_k <= 6), and sum_i y_i w_i by the 4^d moments
+//      sum_i y_i prod_k t_k^{q_k} (q_k <= 3);
+//   4. separable assembly: one pass per dimension turns a cell moment index
+//      q_k into a stencil offset o_k (resp. sums it out for the vectors),
+//      giving W^T W in stencil-diagonal form, W^T y and the sketches.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "common.h"
+
+namespace fkgp {
+namespace {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Keys cubic convolution (a = -1/2) as polynomials in t (ascending powers):
+// weights of the nodes i-1, i, i+1, i+2 of a point at offset t from node i.
+// ---------------------------------------------------------------------------
+struct KeysTables {
+    double E[7][4][7];   // [o+3][a][q]: coeff of t^q in w_a(t) w_{a+o}(t)
+    double C[4][4];      // [a][q]: coeff of t^q in w_a(t)
+};
+
+KeysTables make_tables() {
+    const double w[4][4] = {{0.0, -0.5, 1.0, -0.5},
+                            {1.0, 0.0, -2.5, 1.5},
+                            {0.0, 0.5, 2.0, -1.5},
+                            {0.0, 0.0, -0.5, 0.5}};
+    KeysTables t{};
+    for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 4; ++q) t.C[a][q] = w[a][q];
+    for (int o = -3; o <= 3; ++o)
+        for (int a = 0; a < 4; ++a) {
+            int b = a + o;
+            if (b < 0 || b > 3) continue;
+            for (int p = 0; p < 4; ++p)
+                for (int q = 0; q < 4; ++q) t.E[o + 3][a][p + q] += w[a][p] * w[b][q];
+        }
+    return t;
+}
+
+// Grid coordinate of one dimension: u = (x - g0)/h in FP64, interpolable iff
+// 1 <= u <= m-2; base node i = min(floor(u), m-3); t = u - i in [0,1].
+__device__ inline bool locate(double x, double g0, double h, int m, int& base,
+                              double& t) {
+    double u = (x - g0) / h;
+    if (!(u >= 1.0 && u <= (double)(m - 2))) return false;
+    int i = (int)floor(u);
+    if (i > m - 3) i = m - 3;
+    base = i;
+    t = u - (double)i;
+    return true;
+}
+
+template <class Tin>
+__device__ inline bool cell_of(const GridDev& g, const Tin* const* xs, int64_t i,
+                               uint32_t& key) {
+    uint32_t c = 0;
+    bool ok = true;
+    for (int k = 0; k < g.d; ++k) {
+        int b;
+        double t;
+        ok &= locate((double)xs[k][i], g.g0[k], g.h[k], g.m[k], b, t);
+        if (!ok) b = 1;
+        c = c * (uint32_t)g.nc[k] + (uint32_t)(b - 1);
+    }
+    key = ok ? c : 0u;
+    return ok;
+}
+
+template <class Tin>
+struct Coords {
+    const Tin* p[3];
+};
+
+// Payload: slots [0,d) coordinates, slot d the response, slot d+1 the
+// original index (bit-cast) when probes are requested.
+template <class Tin>
+struct PayloadOf;
+template <>
+struct PayloadOf<float> { using type = float4; };
+template <>
+struct PayloadOf<double> { using type = double4; };
+
+__device__ inline float idx_to_slot(uint32_t i, float) { return __uint_as_float(i); }
+__device__ inline double idx_to_slot(uint32_t i, double) {
+    return __longlong_as_double((long long)i);
+}
+__device__ inline uint32_t slot_to_idx(float v) { return __float_as_uint(v); }
+__device__ inline uint32_t slot_to_idx(double v) { return (uint32_t)__double_as_longlong(v); }
+
+template <class P, class S>
+__device__ inline void set_slot(P& p, int s, S v) {
+    if (s == 0) p.x = v;
+    else if (s == 1) p.y = v;
+    else if (s == 2) p.z = v;
+    else p.w = v;
+}
+template <class P>
+__device__ inline auto get_slot(const P& p, int s) -> decltype(p.x) {
+    return s == 0 ? p.x : s == 1 ? p.y : s == 2 ? p.z : p.w;
+}
+
+template <class Tin>
+constexpr int items_per_thread() { return sizeof(Tin) == 4 ? 16 : 8; }
+template <class Tin>
+constexpr int tile_size() { return kBlock * items_per_thread<Tin>(); }
+
+// ---------------------------------------------------------------------------
+// 1. Cell keys and the first pass's per-tile digit counts.
+// ---------------------------------------------------------------------------
+template <class Tin>
+__global__ __launch_bounds__(kBlock) void keys_and_counts(
+    Coords<Tin> xs, int64_t n, GridDev g, uint32_t* __restrict__ keys,
+    uint32_t* __restrict__ counts, int ntiles, int shift, int bits,
+    unsigned long long* bad) {
+    extern __shared__ uint32_t hist[];
+    const int nd = 1 << bits;
+    for (int i = threadIdx.x; i < nd; i += kBlock) hist[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * tile_size<Tin>();
+    const int64_t end = min(n, base + tile_size<Tin>());
+    for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
+        uint32_t key;
+        if (!cell_of<Tin>(g, xs.p, i, key)) atomicMin(bad, (unsigned long long)i);
+        keys[i] = key;
+        atomicAdd(&hist[(key >> shift) & (nd - 1)], 1u);
+    }
+    __syncthreads();
+    for (int dgt = threadIdx.x; dgt < nd; dgt += kBlock)
+        counts[(size_t)dgt * ntiles + blockIdx.x] = hist[dgt];
+}
+
+// Per-tile digit counts of a later pass.
+template <class Tin>
+__global__ __launch_bounds__(kBlock) void digit_counts(
+    const uint32_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ counts,
+    int ntiles, int shift, int bits) {
+    extern __shared__ uint32_t hist[];
+    const int nd = 1 << bits;
+    for (int i = threadIdx.x; i < nd; i += kBlock) hist[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * tile_size<Tin>();
+    const int64_t end = min(n, base + tile_size<Tin>());
+    for (int64_t i = base + threadIdx.x; i < end; i += kBlock)
+        atomicAdd(&hist[(keys[i] >> shift) & (nd - 1)], 1u);
+    __syncthreads();
+    for (int dgt = threadIdx.x; dgt < nd; dgt += kBlock)
+        counts[(size_t)dgt * ntiles + blockIdx.x] = hist[dgt];
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of uint32 (digit-major counts -> scatter offsets).
+// ---------------------------------------------------------------------------
+constexpr int kScanChunk = 4096;
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
+    // Hillis-Steele over 256 threads in LDS.
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        uint32_t a = t >= off ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    total = sh[kBlock - 1];
+    uint32_t incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_reduce(const uint32_t* __restrict__ in,
+                                                       size_t n, uint32_t* __restrict__ sums) {
+    __shared__ uint32_t sh[kBlock];
+    size_t base = (size_t)blockIdx.x * kScanChunk;
+    uint32_t acc = 0;
+    for (int i = threadIdx.x; i < kScanChunk; i += kBlock)
+        if (base + i < n) acc += in[base + i];
+    uint32_t total;
+    block_exclusive_scan(acc, sh, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_sums(uint32_t* __restrict__ sums, int nb) {
+    __shared__ uint32_t sh[kBlock];
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += kBlock) {
+        int i = base + threadIdx.x;
+        uint32_t v = i < nb ? sums[i] : 0u;
+        uint32_t total;
+        uint32_t ex = block_exclusive_scan(v, sh, total);
+        if (i < nb) sums[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void scan_apply(const uint32_t* __restrict__ in, size_t n,
+                                                      const uint32_t* __restrict__ sums,
+                                                      uint32_t* __restrict__ out) {
+    __shared__ uint32_t sh[kBlock];
+    constexpr int per = kScanChunk / kBlock;
+    size_t base = (size_t)blockIdx.x * kScanChunk + (size_t)threadIdx.x * per;
+    uint32_t v[per];
+    uint32_t acc = 0;
+    for (int j = 0; j < per; ++j) {
+        v[j] = base + j < n ? in[base + j] : 0u;
+        acc += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(acc, sh, total) + sums[blockIdx.x];
+    for (int j = 0; j < per; ++j) {
+        if (base + j < n) out[base + j] = run;
+        run += v[j];
+    }
+}
+
+fkgp_status exclusive_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* sums,
+                           hipStream_t s) {
+    int nb = (int)((n + kScanChunk - 1) / kScanChunk);
+    scan_reduce<<<nb, kBlock, 0, s>>>(in, n, sums);
+    scan_sums<<<1, kBlock, 0, s>>>(sums, nb);
+    scan_apply<<<nb, kBlock, 0, s>>>(in, n, sums, out);
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// 2. Stable scatter of one radix pass.  Wave w of a tile owns the contiguous
+// chunk [w*64*IT, (w+1)*64*IT) and walks it in steps of 64; lanes with equal
+// digits in a step are matched by ballots, so ranks follow input order.
+// ---------------------------------------------------------------------------
+template <class Tin, bool kRaw>
+__global__ __launch_bounds__(kBlock) void radix_scatter(
+    const uint32_t* __restrict__ keys_in,
+    const typename PayloadOf<Tin>::type* __restrict__ pay_in, Coords<Tin> xs,
+    const Tin* __restrict__ yin, int d, bool with_idx, int64_t n,
+    const uint32_t* __restrict__ offsets, int ntiles, int shift, int bits,
+    uint32_t* __restrict__ keys_out, typename PayloadOf<Tin>::type* __restrict__ pay_out) {
+    using P = typename PayloadOf<Tin>::type;
+    constexpr int IT = items_per_thread<Tin>();
+    extern __shared__ uint32_t whist[];   // [4 waves][1 << bits]
+    const int nd = 1 << bits;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < 4 * nd; i += kBlock) whist[i] = 0;
+    __syncthreads();
+
+    const int64_t wbase = (int64_t)blockIdx.x * tile_size<Tin>() + (int64_t)wave * 64 * IT;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t key[IT];
+    uint32_t rank[IT];
+    P pay[IT];
+#pragma unroll
+    for (int s = 0; s < IT; ++s) {
+        const int64_t i = wbase + (int64_t)s * 64 + lane;
+        const bool valid = i < n;
+        uint32_t k = 0;
+        P p{};
+        if (valid) {
+            k = keys_in[i];
+            if constexpr (kRaw) {
+                for (int c = 0; c < d; ++c) set_slot(p, c, xs.p[c][i]);
+                set_slot(p, d, yin[i]);
+                if (with_idx) set_slot(p, d + 1, idx_to_slot((uint32_t)i, Tin(0)));
+            } else {
+                p = pay_in[i];
+            }
+        }
+        const uint32_t dg = (k >> shift) & (nd - 1);
+        unsigned long long peers = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (dg >> b) & 1u;
+            const unsigned long long bb = __ballot(valid && bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint32_t before = (uint32_t)__popcll(peers & lt);
+        const uint32_t cnt = (uint32_t)__popcll(peers);
+        uint32_t r = 0;
+        if (valid) r = whist[wave * nd + dg] + before;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (valid && before + 1 == cnt) whist[wave * nd + dg] = r + 1;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        key[s] = valid ? k : 0xffffffffu;
+        rank[s] = r;
+        pay[s] = p;
+    }
+    __syncthreads();
+    // exclusive prefix over waves, plus the tile's global offset per digit
+    for (int dg = threadIdx.x; dg < nd; dg += kBlock) {
+        uint32_t run = offsets[(size_t)dg * ntiles + blockIdx.x];
+        for (int w = 0; w < 4; ++w) {
+            uint32_t c = whist[w * nd + dg];
+            whist[w * nd + dg] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < IT; ++s) {
+        if (key[s] == 0xffffffffu) continue;
+        const uint32_t dg = (key[s] >> shift) & (nd - 1);
+        const uint32_t pos = whist[wave * nd + dg] + rank[s];
+        keys_out[pos] = key[s];
+        pay_out[pos] = pay[s];
+    }
+}
+
+// Segment bounds of each cell in the sorted keys.
+__global__ void cell_bounds(const uint32_t* __restrict__ keys, int64_t n,
+                            uint32_t* __restrict__ start, uint32_t* __restrict__ end) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t k = keys[i];
+    if (i == 0 || keys[i - 1] != k) start[k] = (uint32_t)i;
+    if (i == n - 1 || keys[i + 1] != k) end[k] = (uint32_t)(i + 1);
+}
+
+// ---------------------------------------------------------------------------
+// 3. Per-cell moments (FP64), one wave per cell, points in batches of 64.
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t splitmix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline double rademacher(uint64_t seed, uint64_t j, uint64_t i) {
+    return (splitmix64((seed << 48) ^ (j << 40) ^ i) >> 63) ? -1.0 : 1.0;
+}
+
+template <int D>
+constexpr int ipow_c(int b) {
+    int r = 1;
+    for (int i = 0; i < D; ++i) r *= b;
+    return r;
+}
+
+constexpr int kPw = 22;   // LDS row: 7 powers per dimension (+ pad)
+
+template <int D, class Tin>
+__global__ __launch_bounds__(64) void cell_moments(
+    const typename PayloadOf<Tin>::type* __restrict__ pay,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, GridDev g,
+    int nprobe, uint64_t seed, int ncells, double* __restrict__ Mw,
+    double* __restrict__ Mr, double* __restrict__ Myy) {
+    constexpr int NW = ipow_c<D>(7);
+    constexpr int NR = ipow_c<D>(4);
+    extern __shared__ double smem[];
+    const int nr = 1 + nprobe;
+    double(*pw)[kPw] = reinterpret_cast<double(*)[kPw]>(smem);
+    double* rvb = smem + 64 * kPw;   // [64][nr]
+    const int cell = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t s0 = cstart[cell];
+    const uint32_t s1 = cend[cell];
+    const int ncol_r = nr * (NR / 4);
+
+    // W moments: D=3 lane owns (q1,q2) with 7 rows q0; D<=2 lane owns one moment.
+    constexpr int WROWS = (D == 3) ? 7 : 1;
+    double accw[WROWS];
+#pragma unroll
+    for (int r = 0; r < WROWS; ++r) accw[r] = 0.0;
+    // rhs moments: columns (r, trailing q) with 4 rows q0 (D>=2: trailing
+    // index over dims 1..D-1; D=1: one column per rhs, 4 rows).
+    constexpr int MAXG = 2;   // up to 128 rhs-moment columns
+    double accr[MAXG][4];
+#pragma unroll
+    for (int gi = 0; gi < MAXG; ++gi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accr[gi][r] = 0.0;
+    double accyy = 0.0;
+
+    for (uint32_t b0 = s0; b0 < s1; b0 += 64) {
+        const uint32_t i = b0 + lane;
+        const int cnt = (int)min(64u, s1 - b0);
+        if (i < s1) {
+            auto p = pay[i];
+            for (int k = 0; k < D; ++k) {
+                int base;
+                double t;
+                locate((double)get_slot(p, k), g.g0[k], g.h[k], g.m[k], base, t);
+                double v = 1.0;
+                for (int q = 0; q < 7; ++q) {
+                    pw[lane][k * 7 + q] = v;
+                    v *= t;
+                }
+            }
+            const double yv = (double)get_slot(p, D);
+            rvb[lane * nr] = yv;
+            if (nprobe > 0) {
+                const uint32_t orig = slot_to_idx(get_slot(p, D + 1));
+                for (int j = 0; j < nprobe; ++j) rvb[lane * nr + 1 + j] = rademacher(seed, j, orig);
+            }
+        } else {
+            for (int q = 0; q < 7 * D; ++q) pw[lane][q] = 0.0;
+            for (int j = 0; j < nr; ++j) rvb[lane * nr + j] = 0.0;
+        }
+        __syncthreads();
+        // W moments
+        if constexpr (D == 3) {
+            if (lane < 49) {
+                const int q1 = lane / 7, q2 = lane % 7;
+                for (int p = 0; p < cnt; ++p) {
+                    const double bc = pw[p][7 + q1] * pw[p][14 + q2];
+#pragma unroll
+                    for (int q0 = 0; q0 < 7; ++q0) accw[q0] = fma(pw[p][q0], bc, accw[q0]);
+                }
+            }
+        } else if constexpr (D == 2) {
+            if (lane < 49) {
+                const int q0 = lane / 7, q1 = lane % 7;
+                for (int p = 0; p < cnt; ++p) accw[0] = fma(pw[p][q0], pw[p][7 + q1], accw[0]);
+            }
+        } else {
+            if (lane < 7)
+                for (int p = 0; p < cnt; ++p) accw[0] += pw[p][lane];
+        }
+        // rhs moments
+#pragma unroll
+        for (int gi = 0; gi < MAXG; ++gi) {
+            const int col = gi * 64 + lane;
+            if (col < ncol_r) {
+                if constexpr (D == 1) {
+                    const int r = col;
+                    for (int p = 0; p < cnt; ++p) {
+                        const double yv = rvb[p * nr + r];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) accr[gi][q] = fma(yv, pw[p][q], accr[gi][q]);
+                    }
+                } else if constexpr (D == 2) {
+                    const int r = col / 4, q1 = col % 4;
+                    for (int p = 0; p < cnt; ++p) {
+                        const double yb = rvb[p * nr + r] * pw[p][7 + q1];
+#pragma unroll
+                        for (int q0 = 0; q0 < 4; ++q0) accr[gi][q0] = fma(pw[p][q0], yb, accr[gi][q0]);
+                    }
+                } else {
+                    const int r = col / 16, q1 = (col / 4) % 4, q2 = col % 4;
+                    for (int p = 0; p < cnt; ++p) {
+                        const double ybc = rvb[p * nr + r] * pw[p][7 + q1] * pw[p][14 + q2];
+#pragma unroll
+                        for (int q0 = 0; q0 < 4; ++q0) accr[gi][q0] = fma(pw[p][q0], ybc, accr[gi][q0]);
+                    }
+                }
+            }
+        }
+        if (lane == 0)
+            for (int p = 0; p < cnt; ++p) accyy = fma(rvb[p * nr], rvb[p * nr], accyy);
+        __syncthreads();
+    }
+    // write out: Mw[cell][q0..], Mr[r][cell][q], Myy[cell]
+    if constexpr (D == 3) {
+        if (lane < 49)
+#pragma unroll
+            for (int q0 = 0; q0 < 7; ++q0) Mw[(size_t)cell * NW + q0 * 49 + lane] = accw[q0];
+    } else if constexpr (D == 2) {
+        if (lane < 49) Mw[(size_t)cell * NW + lane] = accw[0];
+    } else {
+        if (lane < 7) Mw[(size_t)cell * NW + lane] = accw[0];
+    }
+#pragma unroll
+    for (int gi = 0; gi < MAXG; ++gi) {
+        const int col = gi * 64 + lane;
+        if (col < ncol_r) {
+            int r, rest;
+            if (D == 1) { r = col; rest = 0; }
+            else if (D == 2) { r = col / 4; rest = col % 4; }
+            else { r = col / 16; rest = col % 16; }
+            const int trail = (D == 1) ? 1 : (D == 2 ? 4 : 16);
+            double* dst = Mr + ((size_t)r * ncells + cell) * NR;
+#pragma unroll
+            for (int q0 = 0; q0 < 4; ++q0) dst[q0 * trail + rest] = accr[gi][q0];
+        }
+    }
+    if (lane == 0) Myy[cell] = accyy;
+}
+
+// ---------------------------------------------------------------------------
+// 4. Separable assembly.
+// ---------------------------------------------------------------------------
+struct Dims3 {
+    int n[3];
+};
+
+// W^T W stage for dimension k: payload digit k (base 7) changes from a moment
+// index q to an offset index o+3; spatial dimension k grows from cells to
+// nodes: out[.., j_k, ..][.., o, ..] = sum_{a, q} E[o][a][q] in[.., j_k-a, ..][.., q, ..].
+__global__ void assemble_wtw_stage(const double* __restrict__ in, double* __restrict__ out,
+                                   Dims3 sin, Dims3 sout, int d, int k, KeysTables tab) {
+    int P = 1;
+    for (int i = 0; i < d; ++i) P *= 7;
+    const int64_t total = (int64_t)sout.n[0] * sout.n[1] * sout.n[2] * P;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int pay = (int)(idx % P);
+    int64_t sp = idx / P;
+    int s[3];
+    for (int i = 2; i >= 0; --i) {
+        s[i] = (int)(sp % sout.n[i]);
+        sp /= sout.n[i];
+    }
+    int pstride = 1;
+    for (int i = d - 1; i > k; --i) pstride *= 7;
+    const int o = (pay / pstride) % 7;
+    const int pay0 = pay - o * pstride;
+    double acc = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        const int c = s[k] - a;
+        if (c < 0 || c >= sin.n[k]) continue;
+        int t[3] = {s[0], s[1], s[2]};
+        t[k] = c;
+        const int64_t ib = (((int64_t)t[0] * sin.n[1] + t[1]) * sin.n[2] + t[2]) * P + pay0;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) acc = fma(tab.E[o][a][q], in[ib + q * pstride], acc);
+    }
+    out[idx] = acc;
+}
+
+// Vector stage for dimension k (processed from the last to the first): the
+// trailing payload digit q_k (base 4) is summed out:
+// out[r][.., j_k, ..][p] = sum_{a, q} C[a][q] in[r][.., j_k-a, ..][p*4 + q].
+__global__ void assemble_vec_stage(const double* __restrict__ in, double* __restrict__ out,
+                                   Dims3 sin, Dims3 sout, int k, int Pout, int nr,
+                                   KeysTables tab) {
+    const int64_t sp_out = (int64_t)sout.n[0] * sout.n[1] * sout.n[2];
+    const int64_t sp_in = (int64_t)sin.n[0] * sin.n[1] * sin.n[2];
+    const int64_t total = sp_out * Pout * nr;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int p = (int)(idx % Pout);
+    int64_t rest = idx / Pout;
+    int64_t sp = rest % sp_out;
+    const int r = (int)(rest / sp_out);
+    int s[3];
+    for (int i = 2; i >= 0; --i) {
+        s[i] = (int)(sp % sout.n[i]);
+        sp /= sout.n[i];
+    }
+    double acc = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        const int c = s[k] - a;
+        if (c < 0 || c >= sin.n[k]) continue;
+        int t[3] = {s[0], s[1], s[2]};
+        t[k] = c;
+        const int64_t ib = ((int64_t)r * sp_in + ((int64_t)t[0] * sin.n[1] + t[1]) * sin.n[2] + t[2]) *
+                               (Pout * 4) + (int64_t)p * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc = fma(tab.C[a][q], in[ib + q], acc);
+    }
+    out[idx] = acc;
+}
+
+// [M][7^d] double -> [7^d][M] in T (LDS-tiled transpose).
+template <class T>
+__global__ void transpose_to_dia(const double* __restrict__ in, T* __restrict__ out, int64_t M,
+                                 int NB) {
+    __shared__ double tile[32][33];
+    const int64_t j0 = (int64_t)blockIdx.x * 32;
+    const int o0 = blockIdx.y * 32;
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        int64_t j = j0 + r;
+        int o = o0 + threadIdx.x;
+        tile[r][threadIdx.x] = (j < M && o < NB) ? in[j * NB + o] : 0.0;
+    }
+    __syncthreads();
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        int o = o0 + r;
+        int64_t j = j0 + threadIdx.x;
+        if (o < NB && j < M) out[(int64_t)o * M + j] = (T)tile[threadIdx.x][r];
+    }
+}
+
+// Deterministic sum of the per-cell sums of y^2 (single block, fixed tree).
+__global__ __launch_bounds__(1024) void sum_fixed(const double* __restrict__ v, int64_t n,
+                                                  double* __restrict__ out) {
+    __shared__ double sh[1024];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) acc += v[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+template <class Tin>
+fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void* yv,
+                             int64_t n, fkgp_dtype stats, int nprobe, uint64_t seed,
+                             const StatsOut& out, unsigned long long* bad, hipStream_t s) {
+    using P = typename PayloadOf<Tin>::type;
+    const int d = g.d;
+    int64_t ncells = 1, M = 1;
+    for (int k = 0; k < d; ++k) {
+        ncells *= g.nc[k];
+        M *= g.m[k];
+    }
+    int NB = 1;
+    for (int k = 0; k < d; ++k) NB *= 7;
+    int NR = 1;
+    for (int k = 0; k < d; ++k) NR *= 4;
+    const int nr = 1 + nprobe;
+    Coords<Tin> xs{};
+    for (int k = 0; k < d; ++k) xs.p[k] = static_cast<const Tin*>(xv[k]);
+    const Tin* y = static_cast<const Tin*>(yv);
+
+    // key bits and digit plan
+    int key_bits = 1;
+    while ((int64_t(1) << key_bits) < ncells) ++key_bits;
+    const int npass = (key_bits + 9) / 10;
+    int dbits[4], dshift[4];
+    {
+        int sh = 0;
+        for (int p = 0; p < npass; ++p) {
+            dbits[p] = (key_bits - sh + (npass - p) - 1) / (npass - p);
+            dshift[p] = sh;
+            sh += dbits[p];
+        }
+    }
+    const int ntiles = (int)((n + tile_size<Tin>() - 1) / tile_size<Tin>());
+
+    double* Mw = nullptr;
+    double* Mr = nullptr;
+    double* Myy = nullptr;
+    uint32_t* cstart = nullptr;
+    uint32_t* cend = nullptr;
+    FKGP_HIP(alloc_async(&Mw, (size_t)ncells * NB, s));
+    FKGP_HIP(alloc_async(&Mr, (size_t)ncells * NR * nr, s));
+    FKGP_HIP(alloc_async(&Myy, (size_t)ncells, s));
+    FKGP_HIP(alloc_async(&cstart, (size_t)ncells, s));
+    FKGP_HIP(alloc_async(&cend, (size_t)ncells, s));
+    FKGP_HIP(hipMemsetAsync(cstart, 0, sizeof(uint32_t) * ncells, s));
+    FKGP_HIP(hipMemsetAsync(cend, 0, sizeof(uint32_t) * ncells, s));
+
+    if (n > 0) {
+        uint32_t *ka = nullptr, *kb = nullptr, *counts = nullptr, *offs = nullptr, *sums = nullptr;
+        P *pa = nullptr, *pb = nullptr;
+        const size_t ncount = (size_t)ntiles << 10;
+        FKGP_HIP(alloc_async(&ka, (size_t)n, s));
+        FKGP_HIP(alloc_async(&kb, (size_t)n, s));
+        FKGP_HIP(alloc_async(&pa, (size_t)n, s));
+        FKGP_HIP(alloc_async(&pb, (size_t)n, s));
+        FKGP_HIP(alloc_async(&counts, ncount, s));
+        FKGP_HIP(alloc_async(&offs, ncount, s));
+        FKGP_HIP(alloc_async(&sums, (ncount + kScanChunk - 1) / kScanChunk + 1, s));
+
+        keys_and_counts<Tin><<<ntiles, kBlock, sizeof(uint32_t) << dbits[0], s>>>(
+            xs, n, g, ka, counts, ntiles, dshift[0], dbits[0], bad);
+        FKGP_HIP(hipGetLastError());
+        uint32_t* kin = ka;
+        uint32_t* kout = kb;
+        P* pin = pa;
+        P* pout = pb;
+        for (int p = 0; p < npass; ++p) {
+            const size_t nc = (size_t)ntiles << dbits[p];
+            if (p > 0) {
+                digit_counts<Tin><<<ntiles, kBlock, sizeof(uint32_t) << dbits[p], s>>>(
+                    kin, n, counts, ntiles, dshift[p], dbits[p]);
+                FKGP_HIP(hipGetLastError());
+            }
+            fkgp_status st = exclusive_scan(counts, offs, nc, sums, s);
+            if (st != FKGP_OK) return st;
+            const size_t lds = 4 * sizeof(uint32_t) << dbits[p];
+            if (p == 0)
+                radix_scatter<Tin, true><<<ntiles, kBlock, lds, s>>>(
+                    kin, nullptr, xs, y, d, nprobe > 0, n, offs, ntiles, dshift[p], dbits[p],
+                    kout, pout);
+            else
+                radix_scatter<Tin, false><<<ntiles, kBlock, lds, s>>>(
+                    kin, pin, xs, y, d, nprobe > 0, n, offs, ntiles, dshift[p], dbits[p],
+                    kout, pout);
+            FKGP_HIP(hipGetLastError());
+            std::swap(kin, kout);
+            std::swap(pin, pout);
+        }
+        // kin/pin now hold the sorted keys/payload
+        cell_bounds<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(kin, n, cstart, cend);
+        FKGP_HIP(hipGetLastError());
+        const size_t lds_mom = sizeof(double) * 64 * (kPw + nr);
+        if (d == 1)
+            cell_moments<1, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
+                                                                 (int)ncells, Mw, Mr, Myy);
+        else if (d == 2)
+            cell_moments<2, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
+                                                                 (int)ncells, Mw, Mr, Myy);
+        else
+            cell_moments<3, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
+                                                                 (int)ncells, Mw, Mr, Myy);
+        FKGP_HIP(hipGetLastError());
+        FKGP_HIP(hipFreeAsync(ka, s));
+        FKGP_HIP(hipFreeAsync(kb, s));
+        FKGP_HIP(hipFreeAsync(pa, s));
+        FKGP_HIP(hipFreeAsync(pb, s));
+        FKGP_HIP(hipFreeAsync(counts, s));
+        FKGP_HIP(hipFreeAsync(offs, s));
+        FKGP_HIP(hipFreeAsync(sums, s));
+    } else {
+        FKGP_HIP(hipMemsetAsync(Mw, 0, sizeof(double) * ncells * NB, s));
+        FKGP_HIP(hipMemsetAsync(Mr, 0, sizeof(double) * ncells * NR * nr, s));
+        FKGP_HIP(hipMemsetAsync(Myy, 0, sizeof(double) * ncells, s));
+    }
+
+    const KeysTables tab = make_tables();
+    // --- W^T W: stages over k = d-1 .. 0 ---
+    {
+        Dims3 cur{{1, 1, 1}};
+        for (int k = 0; k < d; ++k) cur.n[k] = g.nc[k];
+        double* bufA = nullptr;
+        double* bufB = nullptr;
+        FKGP_HIP(alloc_async(&bufA, (size_t)M * NB, s));
+        FKGP_HIP(alloc_async(&bufB, (size_t)M * NB, s));
+        const double* src = Mw;
+        double* dst = bufA;
+        for (int k = d - 1; k >= 0; --k) {
+            Dims3 nxt = cur;
+            nxt.n[k] = g.m[k];
+            const int64_t total = (int64_t)nxt.n[0] * nxt.n[1] * nxt.n[2] * NB;
+            assemble_wtw_stage<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(src, dst, cur, nxt,
+                                                                                d, k, tab);
+            FKGP_HIP(hipGetLastError());
+            cur = nxt;
+            src = dst;
+            dst = (dst == bufA) ? bufB : bufA;
+        }
+        dim3 tb(32, 8), tg((unsigned)((M + 31) / 32), (unsigned)((NB + 31) / 32));
+        if (stats == FKGP_F32)
+            transpose_to_dia<float><<<tg, tb, 0, s>>>(src, static_cast<float*>(out.wtw), M, NB);
+        else
+            transpose_to_dia<double><<<tg, tb, 0, s>>>(src, static_cast<double*>(out.wtw), M, NB);
+        FKGP_HIP(hipGetLastError());
+        FKGP_HIP(hipFreeAsync(bufA, s));
+        FKGP_HIP(hipFreeAsync(bufB, s));
+    }
+    // --- W^T y and sketches: stages over k = d-1 .. 0 ---
+    {
+        Dims3 cur{{1, 1, 1}};
+        for (int k = 0; k < d; ++k) cur.n[k] = g.nc[k];
+        double* bufA = nullptr;
+        double* bufB = nullptr;
+        FKGP_HIP(alloc_async(&bufA, (size_t)M * NR * nr, s));
+        FKGP_HIP(alloc_async(&bufB, (size_t)M * NR * nr, s));
+        const double* src = Mr;
+        int Pin = NR;
+        for (int k = d - 1; k >= 0; --k) {
+            Dims3 nxt = cur;
+            nxt.n[k] = g.m[k];
+            const int Pout = Pin / 4;
+            const int64_t total = (int64_t)nxt.n[0] * nxt.n[1] * nxt.n[2] * Pout * nr;
+            double* target = (src == bufA) ? bufB : bufA;
+            assemble_vec_stage<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(src, target, cur, nxt,
+                                                                                k, Pout, nr, tab);
+            FKGP_HIP(hipGetLastError());
+            cur = nxt;
+            src = target;
+            Pin = Pout;
+        }
+        // src: [nr][M]
+        FKGP_HIP(hipMemcpyAsync(out.wty, src, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+        if (nprobe > 0)
+            FKGP_HIP(hipMemcpyAsync(out.sketches, src + M, sizeof(double) * M * nprobe,
+                                    hipMemcpyDeviceToDevice, s));
+        FKGP_HIP(hipFreeAsync(bufA, s));
+        FKGP_HIP(hipFreeAsync(bufB, s));
+    }
+    sum_fixed<<<1, 1024, 0, s>>>(Myy, ncells, out.yty_dev);
+    FKGP_HIP(hipGetLastError());
+    FKGP_HIP(hipFreeAsync(Mw, s));
+    FKGP_HIP(hipFreeAsync(Mr, s));
+    FKGP_HIP(hipFreeAsync(Myy, s));
+    FKGP_HIP(hipFreeAsync(cstart, s));
+    FKGP_HIP(hipFreeAsync(cend, s));
+    return FKGP_OK;
+}
+
+}  // namespace
+
+fkgp_status run_precompute(const GridDev& g, const void* const* x, const void* y, int64_t n,
+                           fkgp_dtype in, fkgp_dtype stats, int nprobe, uint64_t seed,
+                           const StatsOut& out, unsigned long long* bad, hipStream_t s) {
+    if (in == FKGP_F32)
+        return precompute_typed<float>(g, x, y, n, stats, nprobe, seed, out, bad, s);
+    return precompute_typed<double>(g, x, y, n, stats, nprobe, seed, out, bad, s);
+}
+
+}  // namespace fkgp

@@ -1,0 +1,191 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Sizes span several sort tiles and cells with a ragged tail; tolerances are the
+ones the hot path is held to: FP64 statistics 1e-13 relative, FP32 statistics
+1e-6, K_G products 1e-13 / 1e-6, posterior mean 1e-10 (FP64) / 1e-5 (FP32).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2101_11751_amd")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def make_case(d, n, seed, m=None, dtype=np.float32):
+    rng = np.random.default_rng(seed)
+    m = m or {1: [203], 2: [37, 29], 3: [14, 11, 9]}[d]
+    grid = oracle.make_grid(m, lo=0.0, hi=1.0)
+    X = rng.uniform(0, 1, (d, n)).astype(dtype)
+    y = (np.sin(5 * X[0].astype(np.float64)) + 0.3 * rng.standard_normal(n)).astype(dtype)
+    return grid, X, y
+
+
+def to_dev(X, y):
+    xs = [torch.from_numpy(np.ascontiguousarray(X[k])).cuda() for k in range(X.shape[0])]
+    return xs, torch.from_numpy(np.ascontiguousarray(y)).cuda()
+
+
+HYP = {1: {"lengthscale": [0.05], "outputscale": 1.3, "noise": 0.2},
+       2: {"lengthscale": [0.1, 0.07], "outputscale": 1.1, "noise": 0.15},
+       3: {"lengthscale": [0.15, 0.2, 0.25], "outputscale": 0.9, "noise": 0.3}}
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("stats", ["f64", "f32"])
+@pytest.mark.parametrize("indt", [np.float32, np.float64])
+def test_precompute_parity(d, stats, indt):
+    _need_gpu()
+    n = 9000 + 123 * d  # several 2048/4096-point tiles plus a ragged tail
+    grid, X, y = make_case(d, n, 10 + d, dtype=indt)
+    wtw_o, wty_o, yty_o = oracle.precompute(grid, X, y)
+    xs, yt = to_dev(X, y)
+    sdt = torch.float64 if stats == "f64" else torch.float32
+    h = P.precompute(grid, xs, yt, stats_dtype=sdt)
+    wtw, wty, yty = P.export_stats(h)
+    tol = 1e-13 if stats == "f64" else 1e-6
+    assert rel(wtw.cpu(), wtw_o) <= tol
+    assert rel(wty.cpu(), wty_o) <= 1e-13
+    assert abs(yty - yty_o) <= 1e-13 * abs(yty_o)
+    assert h.n == n and h.m_total == int(np.prod(grid["m"]))
+
+
+def test_precompute_bitwise_deterministic():
+    _need_gpu()
+    grid, X, y = make_case(2, 50000, 3)
+    xs, yt = to_dev(X, y)
+    a = P.export_stats(P.precompute(grid, xs, yt, stats_dtype=torch.float32))
+    b = P.export_stats(P.precompute(grid, xs, yt, stats_dtype=torch.float32))
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_precompute_empty_and_out_of_grid():
+    _need_gpu()
+    grid = oracle.make_grid([20, 20], lo=0.0, hi=1.0)
+    e = torch.empty(0, device="cuda", dtype=torch.float32)
+    h = P.precompute(grid, [e, e], e)
+    wtw, wty, yty = P.export_stats(h)
+    assert float(wtw.abs().sum()) == 0.0 and float(wty.abs().sum()) == 0.0 and yty == 0.0
+    x0 = torch.tensor([0.5, 1.5], device="cuda")
+    x1 = torch.tensor([0.5, 0.5], device="cuda")
+    with pytest.raises(P.OutOfGridError):
+        P.precompute(grid, [x0, x1], torch.ones(2, device="cuda"))
+    x0 = torch.tensor([0.5, float("nan")], device="cuda")
+    with pytest.raises(P.OutOfGridError):
+        P.precompute(grid, [x0, x1], torch.ones(2, device="cuda"))
+    # boundary points are interpolable
+    x0 = torch.tensor([0.0, 1.0], device="cuda", dtype=torch.float64)
+    x1 = torch.tensor([1.0, 0.0], device="cuda", dtype=torch.float64)
+    yb = torch.ones(2, device="cuda", dtype=torch.float64)
+    h = P.precompute(grid, [x0, x1], yb, stats_dtype=torch.float64)
+    wtw_o, _, _ = oracle.precompute(grid, np.array([[0.0, 1.0], [1.0, 0.0]]), np.ones(2))
+    assert rel(P.export_stats(h)[0].cpu(), wtw_o) <= 1e-14
+
+
+@pytest.mark.parametrize("d,m", [(1, [1000]), (1, [9]), (2, [37, 29]), (2, [128, 128]),
+                                 (3, [14, 11, 9]), (3, [30, 17, 6])])
+@pytest.mark.parametrize("stats", ["f64", "f32"])
+def test_kg_matvec_parity(d, m, stats):
+    _need_gpu()
+    grid, X, y = make_case(d, 500, 7, m=m)
+    xs, yt = to_dev(X, y)
+    sdt = torch.float64 if stats == "f64" else torch.float32
+    h = P.precompute(grid, xs, yt, stats_dtype=sdt)
+    M = int(np.prod(m))
+    v = np.random.default_rng(1).standard_normal((3, M))
+    out = P.kg_matvec(h, HYP[d], torch.from_numpy(v).cuda()).cpu().numpy()
+    ref = oracle.kg_matvec(grid, HYP[d], v)
+    tol = 1e-13 if stats == "f64" else 1e-6
+    for r in range(3):
+        assert rel(out[r], ref[r]) <= tol
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("stats", ["f64", "f32"])
+def test_apply_B_parity(d, stats):
+    _need_gpu()
+    grid, X, y = make_case(d, 20000, 8)
+    xs, yt = to_dev(X, y)
+    sdt = torch.float64 if stats == "f64" else torch.float32
+    h = P.precompute(grid, xs, yt, stats_dtype=sdt)
+    wtw_o, _, _ = oracle.precompute(grid, X, y)
+    M = h.m_total
+    xv = np.random.default_rng(2).standard_normal((2, M))
+    v, u = P.apply_B(h, HYP[d], torch.from_numpy(xv).cuda())
+    tol = 1e-12 if stats == "f64" else 2e-6
+    for r in range(2):
+        vo, uo = oracle.B_apply(grid, HYP[d], wtw_o, xv[r])
+        assert rel(u[r].cpu(), uo) <= tol
+        assert rel(v[r].cpu(), vo) <= tol
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_solve_mean_fp64(d):
+    _need_gpu()
+    grid, X, y = make_case(d, 20000, 9, dtype=np.float64)
+    xs, yt = to_dev(X, y)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float64)
+    wtw_o, wty_o, yty_o = oracle.precompute(grid, X, y)
+    mu_o, _, info_o = oracle.solve_mean(grid, HYP[d], wtw_o, wty_o, yty_o, tol=1e-13)
+    mu, info = P.solve(h, HYP[d], tol=1e-12, maxiter=5000)
+    assert info["converged"]
+    assert rel(mu.cpu(), mu_o) <= 1e-10
+    xq = np.random.default_rng(3).uniform(0.05, 0.95, (d, 333))
+    mq = P.interpolate(h, mu, [torch.from_numpy(xq[k]).cuda() for k in range(d)])
+    assert rel(mq.cpu(), oracle.interpolate(grid, mu_o, xq)) <= 1e-10
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_solve_mean_fp32(d):
+    _need_gpu()
+    grid, X, y = make_case(d, 20000, 11)
+    xs, yt = to_dev(X, y)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float32)
+    wtw_o, wty_o, yty_o = oracle.precompute(grid, X, y)
+    mu_o, _, _ = oracle.solve_mean(grid, HYP[d], wtw_o, wty_o, yty_o, tol=1e-13)
+    mu, info = P.solve(h, HYP[d], tol=1e-7, maxiter=5000)
+    err = rel(mu.cpu(), mu_o)
+    print(f"d={d} fp32 mean rel err {err:.3e} iters {info['iterations']}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("stats", ["f64", "f32"])
+def test_solve_grid_rhs(stats):
+    _need_gpu()
+    grid, X, y = make_case(2, 15000, 12)
+    xs, yt = to_dev(X, y)
+    sdt = torch.float64 if stats == "f64" else torch.float32
+    h = P.precompute(grid, xs, yt, stats_dtype=sdt)
+    wtw_o, _, _ = oracle.precompute(grid, X, y)
+    rhs = np.random.default_rng(4).standard_normal(h.m_total)
+    ref, _ = oracle.solve_grid_rhs(grid, HYP[2], wtw_o, rhs, tol=1e-13)
+    out, info = P.solve(h, HYP[2], rhs=torch.from_numpy(rhs).cuda(), tol=1e-12 if stats == "f64" else 1e-7,
+                        maxiter=5000)
+    assert rel(out.cpu(), ref) <= (1e-9 if stats == "f64" else 1e-4)
+
+
+def test_solve_errors():
+    _need_gpu()
+    grid, X, y = make_case(1, 1000, 13)
+    xs, yt = to_dev(X, y)
+    h = P.precompute(grid, xs, yt)
+    with pytest.raises(P.FkgpError):
+        P.solve(h, {"lengthscale": [-1.0], "outputscale": 1.0, "noise": 0.1})
+    with pytest.raises(P.FkgpError):
+        P.solve(h, {"lengthscale": [0.1], "outputscale": 1.0, "noise": 0.0})
+    out, info = P.solve(h, HYP[1], tol=1e-14, maxiter=2)
+    assert info["status"] == P.ENOTCONV and info["iterations"] == 2
