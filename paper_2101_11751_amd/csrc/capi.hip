@@ -298,14 +298,14 @@ fkgp_status check_hypers(const fkgp_handle* h, const fkgp_hypers* hyp) {
     return FKGP_OK;
 }
 
-// Spectra (and, optionally, derivative spectra for dimension `dderiv`).
-fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, int dderiv, Spectra& sp,
-                         Scratch& sc) {
+// Spectra in dtype `dt` (derivative column for dimension `dderiv`, or none).
+fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtype dt, int dderiv,
+                         Spectra& sp, Scratch& sc) {
     std::memset(&sp, 0, sizeof(sp));
-    const size_t es = dsize(h->dt);
+    const size_t es = dsize(dt);
     for (int k = 0; k < h->g.d; ++k) {
         sp.log2L[k] = circulant_log2(h->g.m[k]);
-        if (sp.log2L[k] > (h->dt == FKGP_F32 ? 11 : 11)) {
+        if (sp.log2L[k] > 11) {
             set_error("grid dimension longer than 1024 nodes is not supported by the line FFT");
             return FKGP_EINVAL;
         }
@@ -313,10 +313,10 @@ fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, int dderi
         unsigned char *lam = nullptr, *tw = nullptr;
         FKGP_HIP(sc.get(&lam, es * sp.L[k]));
         FKGP_HIP(sc.get(&tw, 2 * es * (sp.L[k] / 2)));
-        fkgp_status st = build_spectrum(h->g, k, hyp->lengthscale[k], k == dderiv, h->dt, lam,
-                                        sp.log2L[k], sc.s);
+        fkgp_status st =
+            build_spectrum(h->g, k, hyp->lengthscale[k], k == dderiv, dt, lam, sp.log2L[k], sc.s);
         if (st != FKGP_OK) return st;
-        st = build_twiddles(sp.log2L[k], h->dt, tw, sc.s);
+        st = build_twiddles(sp.log2L[k], dt, tw, sc.s);
         if (st != FKGP_OK) return st;
         sp.lam[k] = lam;
         sp.tw[k] = tw;
@@ -324,126 +324,186 @@ fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, int dderi
     return FKGP_OK;
 }
 
-// B(x) on k vectors: xpad [k][M + 2 halo] (stats dtype), u, v [k][M].
-fkgp_status apply_B_padded(const fkgp_handle* h, const Spectra& sp, double s, double s2,
-                           const void* xpad, void* u, void* v, int k, const int* skip,
-                           hipStream_t st) {
-    const int64_t halo = dia_halo(h->g);
-    fkgp_status r = spmv_dia_skip(h->g, h->dt, h->A, xpad, u, k, halo, skip, st);
-    if (r != FKGP_OK) return r;
-    // v = s * K u + s2 * x   (x interior of the padded buffer; k == 1 here)
-    const void* xin = static_cast<const unsigned char*>(xpad) + halo * dsize(h->dt);
-    return kg_apply_skip(h->g, sp, h->dt, u, v, k, s, k == 1 ? xin : nullptr, s2, skip, st);
+// Everything needed to apply B in the working dtype and, for FP32 handles,
+// in FP64 (FP32-stored W^T W upcast exactly, FP64 K_G).
+struct OpCtx {
+    const fkgp_handle* h;
+    double so, s2;
+    int64_t M, halo;
+    Spectra sp;     // working dtype
+    Spectra sp64;   // FP64 (same as sp for FP64 handles)
+};
+
+fkgp_status make_ctx(const fkgp_handle* h, const fkgp_hypers* hyp, OpCtx& c, Scratch& sc) {
+    c.h = h;
+    c.so = hyp->outputscale;
+    c.s2 = hyp->noise_std * hyp->noise_std;
+    c.M = h->M;
+    c.halo = dia_halo(h->g);
+    fkgp_status st = make_spectra(h, hyp, h->dt, -1, c.sp, sc);
+    if (st != FKGP_OK) return st;
+    if (h->dt == FKGP_F64) {
+        c.sp64 = c.sp;
+        return FKGP_OK;
+    }
+    return make_spectra(h, hyp, FKGP_F64, -1, c.sp64, sc);
 }
 
-struct SolveBuffers {
-    double *r, *s, *z, *xd, *partials;
-    void *rpad, *u, *v, *tmp;
+// B in the working dtype on one padded vector: u = A x, v = so K u + s2 x.
+fkgp_status apply_B_padded(const OpCtx& c, const void* xpad, void* u, void* v, const int* skip,
+                           hipStream_t st) {
+    const fkgp_handle* h = c.h;
+    fkgp_status r = spmv_dia_skip(h->g, h->dt, h->A, xpad, u, 1, c.halo, skip, st);
+    if (r != FKGP_OK) return r;
+    const void* xin = static_cast<const unsigned char*>(xpad) + c.halo * dsize(h->dt);
+    return kg_apply_skip(h->g, c.sp, h->dt, u, v, 1, c.so, xin, c.s2, skip, st);
+}
+
+// B in FP64 on one padded FP64 vector (v may be NULL: u only).
+fkgp_status apply_B64(const OpCtx& c, const double* xpad, double* u, double* v, hipStream_t st) {
+    const fkgp_handle* h = c.h;
+    fkgp_status r = h->dt == FKGP_F32
+                        ? spmv_dia_f32a_f64x(h->g, h->A, xpad, u, 1, c.halo, st)
+                        : spmv_dia(h->g, FKGP_F64, h->A, xpad, u, 1, c.halo, st);
+    if (r != FKGP_OK || !v) return r;
+    return kg_apply(h->g, c.sp64, FKGP_F64, u, v, 1, c.so, xpad + c.halo, c.s2, nullptr, st);
+}
+
+struct CgBufs {
+    double *r, *s, *z, *p, *x, *xd, *partials;
+    unsigned char *rpad, *u, *v;
     CgState* st;
 };
 
-fkgp_status solve_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const double* rhs,
-                       double* out, double tol, int maxiter, fkgp_solve_info* info,
-                       hipStream_t st) {
-    Scratch sc(st);
-    Spectra sp;
-    fkgp_status rs = make_spectra(h, hyp, -1, sp, sc);
-    if (rs != FKGP_OK) return rs;
-    const int64_t M = h->M;
-    const int64_t halo = dia_halo(h->g);
-    const size_t es = dsize(h->dt);
-    SolveBuffers b{};
+fkgp_status alloc_cg(const OpCtx& c, CgBufs& b, Scratch& sc) {
+    const int64_t M = c.M;
+    const size_t es = dsize(c.h->dt);
     FKGP_HIP(sc.get(&b.r, M));
     FKGP_HIP(sc.get(&b.s, M));
     FKGP_HIP(sc.get(&b.z, M));
+    FKGP_HIP(sc.get(&b.p, M));
+    FKGP_HIP(sc.get(&b.x, M));
     FKGP_HIP(sc.get(&b.xd, M));
     FKGP_HIP(sc.get(&b.partials, kRedMaxBlocks));
-    unsigned char *rpad, *u, *v, *tmp;
-    FKGP_HIP(sc.get(&rpad, es * (M + 2 * halo)));
-    FKGP_HIP(sc.get(&u, es * M));
-    FKGP_HIP(sc.get(&v, es * M));
-    FKGP_HIP(sc.get(&tmp, es * M));
+    FKGP_HIP(sc.get(&b.rpad, es * (M + 2 * c.halo)));
+    FKGP_HIP(sc.get(&b.u, es * M));
+    FKGP_HIP(sc.get(&b.v, es * M));
     FKGP_HIP(sc.get(&b.st, 1));
-    b.rpad = rpad;
-    b.u = u;
-    b.v = v;
-    b.tmp = tmp;
-    void* rin = rpad + halo * es;   // interior of the padded residual
-    const double s2 = hyp->noise_std * hyp->noise_std;
-    const double so = hyp->outputscale;
-    FKGP_HIP(hipMemsetAsync(rpad, 0, es * (M + 2 * halo), st));
-    FKGP_HIP(hipMemsetAsync(b.xd, 0, sizeof(double) * M, st));
+    FKGP_HIP(hipMemsetAsync(b.rpad, 0, es * (M + 2 * c.halo), sc.s));
+    return FKGP_OK;
+}
+
+template <class T>
+__global__ void cg_step1x(const CgState* __restrict__ st, double* __restrict__ xd,
+                          double* __restrict__ x, double* __restrict__ r,
+                          const double* __restrict__ s, const double* __restrict__ z,
+                          const double* __restrict__ p, T* __restrict__ rpad, int64_t M) {
+    if (st->done) return;
+    const double a = st->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        xd[i] = fma(a, s[i], xd[i]);
+        x[i] = fma(a, p[i], x[i]);
+        const double rn = fma(-a, z[i], r[i]);
+        r[i] = rn;
+        rpad[i] = (T)rn;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(kRedBlock) void cg_step2x(const CgState* __restrict__ st,
+                                                       double* __restrict__ s,
+                                                       double* __restrict__ z,
+                                                       double* __restrict__ p,
+                                                       const double* __restrict__ r,
+                                                       const T* __restrict__ u,
+                                                       const T* __restrict__ v, int64_t M,
+                                                       double* __restrict__ partials) {
+    if (st->done) return;
+    __shared__ double sh[kRedBlock];
+    const double b = st->beta;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * kRedBlock) {
+        const double sn = fma(b, s[i], (double)u[i]);
+        const double zn = fma(b, z[i], (double)v[i]);
+        s[i] = sn;
+        z[i] = zn;
+        p[i] = fma(b, p[i], r[i]);
+        acc = fma(sn, zn, acc);
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// Simplified efficiently-factorized CG (appendix): the residual stays in the
+// span of W, r = W r_hat, and each iteration applies B once.  On entry b.r
+// holds r_hat_0; on exit b.xd += sum_k alpha_k s_k (= W^T W x_hat) and
+// b.x += sum_k alpha_k p_hat_k (= x_hat, the compressed solution update).
+// Stop when u^T r_hat <= eps, with eps = eps_abs, or eps_rel * (u^T r_hat)_0.
+fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, int maxiter,
+                   CgState& out, hipStream_t st) {
+    const fkgp_handle* h = c.h;
+    const int64_t M = c.M;
+    const size_t es = dsize(h->dt);
+    unsigned char* rin = b.rpad + c.halo * es;
+    CgState init{};
+    const bool rel = eps_rel >= 0.0;
+    init.eps = rel ? eps_rel : eps_abs;
+    FKGP_HIP(hipMemcpyAsync(b.st, &init, sizeof(CgState), hipMemcpyHostToDevice, st));
     FKGP_HIP(hipMemsetAsync(b.s, 0, sizeof(double) * M, st));
     FKGP_HIP(hipMemsetAsync(b.z, 0, sizeof(double) * M, st));
-
-    CgState init{};
-    init.eps = rhs ? tol * tol : tol * tol * h->yty;
-    init.bnorm2 = h->yty;
-    FKGP_HIP(hipMemcpyAsync(b.st, &init, sizeof(CgState), hipMemcpyHostToDevice, st));
-    // initial residual
-    if (rhs) {
-        FKGP_HIP(convert_any(rhs, FKGP_F64, rin, h->dt, M, 1.0, st));
-        FKGP_HIP(hipMemcpyAsync(b.r, rhs, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
-    } else {
-        // r_hat_0 = -K_G W^T y / s2
-        FKGP_HIP(convert_any(h->wty, FKGP_F64, tmp, h->dt, M, 1.0, st));
-        rs = kg_apply(h->g, sp, h->dt, tmp, rin, 1, -so / s2, nullptr, 0.0, nullptr, st);
-        if (rs != FKGP_OK) return rs;
-        FKGP_HIP(convert_any(rin, h->dt, b.r, FKGP_F64, M, 1.0, st));
-    }
-    rs = apply_B_padded(h, sp, so, s2, rpad, u, v, 1, nullptr, st);
+    FKGP_HIP(hipMemsetAsync(b.p, 0, sizeof(double) * M, st));
+    FKGP_HIP(convert_any(b.r, FKGP_F64, rin, h->dt, M, 1.0, st));
+    fkgp_status rs = apply_B_padded(c, b.rpad, b.u, b.v, nullptr, st);
     if (rs != FKGP_OK) return rs;
     const int nb = red_blocks(M);
     const unsigned ewg = ew_grid(M);
-    auto dot_ur = [&]() -> hipError_t {
+    auto dot_ur = [&](const int* skip) -> hipError_t {
         if (h->dt == FKGP_F32)
-            dot_partial<float><<<nb, kRedBlock, 0, st>>>(static_cast<float*>(b.u), b.r, M,
-                                                         b.partials, &b.st->done);
+            dot_partial<float><<<nb, kRedBlock, 0, st>>>(reinterpret_cast<float*>(b.u), b.r, M,
+                                                         b.partials, skip);
         else
-            dot_partial<double><<<nb, kRedBlock, 0, st>>>(static_cast<double*>(b.u), b.r, M,
-                                                          b.partials, &b.st->done);
+            dot_partial<double><<<nb, kRedBlock, 0, st>>>(reinterpret_cast<double*>(b.u), b.r, M,
+                                                          b.partials, skip);
         return hipGetLastError();
     };
     auto step2 = [&]() -> hipError_t {
         if (h->dt == FKGP_F32)
-            cg_step2<float><<<nb, kRedBlock, 0, st>>>(b.st, b.s, b.z, static_cast<float*>(b.u),
-                                                      static_cast<float*>(b.v), M, b.partials);
+            cg_step2x<float><<<nb, kRedBlock, 0, st>>>(b.st, b.s, b.z, b.p, b.r,
+                                                       reinterpret_cast<float*>(b.u),
+                                                       reinterpret_cast<float*>(b.v), M,
+                                                       b.partials);
         else
-            cg_step2<double><<<nb, kRedBlock, 0, st>>>(b.st, b.s, b.z, static_cast<double*>(b.u),
-                                                       static_cast<double*>(b.v), M, b.partials);
+            cg_step2x<double><<<nb, kRedBlock, 0, st>>>(b.st, b.s, b.z, b.p, b.r,
+                                                        reinterpret_cast<double*>(b.u),
+                                                        reinterpret_cast<double*>(b.v), M,
+                                                        b.partials);
         return hipGetLastError();
     };
-    // rho_0 = u^T r  (no skip: the flag is not yet meaningful)
-    if (h->dt == FKGP_F32)
-        dot_partial<float><<<nb, kRedBlock, 0, st>>>(static_cast<float*>(b.u), b.r, M, b.partials,
-                                                     nullptr);
-    else
-        dot_partial<double><<<nb, kRedBlock, 0, st>>>(static_cast<double*>(b.u), b.r, M,
-                                                      b.partials, nullptr);
-    finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, rhs ? FIN_INIT_RHS : FIN_INIT);
+    FKGP_HIP(dot_ur(nullptr));
+    finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, rel ? FIN_INIT_RHS : FIN_INIT);
     FKGP_HIP(step2());
     finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_SZ);
     FKGP_HIP(hipGetLastError());
-
-    CgState hst{};
     constexpr int kBatch = 8;
     int launched = 0;
     for (;;) {
-        FKGP_HIP(hipMemcpyAsync(&hst, b.st, sizeof(CgState), hipMemcpyDeviceToHost, st));
+        FKGP_HIP(hipMemcpyAsync(&out, b.st, sizeof(CgState), hipMemcpyDeviceToHost, st));
         FKGP_HIP(hipStreamSynchronize(st));
-        if (hst.done || launched >= maxiter) break;
+        if (out.done || launched >= maxiter) break;
         const int nit = std::min(kBatch, maxiter - launched);
         for (int it = 0; it < nit; ++it) {
             if (h->dt == FKGP_F32)
-                cg_step1<float><<<ewg, 256, 0, st>>>(b.st, b.xd, b.r, b.s, b.z,
-                                                     static_cast<float*>(rin), M);
+                cg_step1x<float><<<ewg, 256, 0, st>>>(b.st, b.xd, b.x, b.r, b.s, b.z, b.p,
+                                                      reinterpret_cast<float*>(rin), M);
             else
-                cg_step1<double><<<ewg, 256, 0, st>>>(b.st, b.xd, b.r, b.s, b.z,
-                                                      static_cast<double*>(rin), M);
+                cg_step1x<double><<<ewg, 256, 0, st>>>(b.st, b.xd, b.x, b.r, b.s, b.z, b.p,
+                                                       reinterpret_cast<double*>(rin), M);
             FKGP_HIP(hipGetLastError());
-            rs = apply_B_padded(h, sp, so, s2, rpad, u, v, 1, &b.st->done, st);
+            rs = apply_B_padded(c, b.rpad, b.u, b.v, &b.st->done, st);
             if (rs != FKGP_OK) return rs;
-            FKGP_HIP(dot_ur());
+            FKGP_HIP(dot_ur(&b.st->done));
             finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_RHO);
             FKGP_HIP(step2());
             finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_SZ);
@@ -451,30 +511,177 @@ fkgp_status solve_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const doubl
         }
         launched += nit;
     }
-    // outputs
-    if (rhs) {
-        FKGP_HIP(hipMemcpyAsync(out, b.xd, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
-    } else {
-        // W^T z~ = xd + W^T y / s2 ; mu_G = K_G (W^T z~)
-        axpy_out<<<ewg, 256, 0, st>>>(b.xd, h->wty, 1.0 / s2, b.r, M);
-        FKGP_HIP(hipGetLastError());
-        FKGP_HIP(convert_any(b.r, FKGP_F64, tmp, h->dt, M, 1.0, st));
-        rs = kg_apply(h->g, sp, h->dt, tmp, u, 1, so, nullptr, 0.0, nullptr, st);
-        if (rs != FKGP_OK) return rs;
-        FKGP_HIP(convert_any(u, h->dt, out, FKGP_F64, M, 1.0, st));
-    }
-    FKGP_HIP(hipStreamSynchronize(st));
-    const double bn = hst.bnorm2 > 0 ? hst.bnorm2 : 1.0;
-    if (info) {
-        info->iterations = hst.iters;
-        info->converged = hst.done == 1;
-        info->rel_residual = std::sqrt(std::max(hst.rho, 0.0) / bn);
-    }
-    if (hst.done == 2) {
+    if (out.done == 2) {
         set_error("factorized CG broke down (non-finite step)");
         return FKGP_EDEVICE;
     }
-    return hst.done == 1 ? FKGP_OK : FKGP_ENOTCONV;
+    return FKGP_OK;
+}
+
+__global__ void sub_out(const double* __restrict__ a, const double* __restrict__ b,
+                        double* __restrict__ out, int64_t M) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = a[i] - b[i];
+}
+
+__global__ void add_inplace(double* __restrict__ a, const double* __restrict__ b, int64_t M) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] += b[i];
+}
+
+fkgp_status dot64(const double* a, const double* b, int64_t M, double* partials, CgState* tmp,
+                  double& out, hipStream_t st) {
+    const int nb = red_blocks(M);
+    dot_partial<double><<<nb, kRedBlock, 0, st>>>(a, b, M, partials, nullptr);
+    CgState init{};
+    init.eps = -1.0;
+    FKGP_HIP(hipMemcpyAsync(tmp, &init, sizeof(CgState), hipMemcpyHostToDevice, st));
+    finalize<<<1, kRedBlock, 0, st>>>(partials, nb, tmp, FIN_INIT);
+    FKGP_HIP(hipGetLastError());
+    CgState h{};
+    FKGP_HIP(hipMemcpyAsync(&h, tmp, sizeof(CgState), hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipStreamSynchronize(st));
+    out = h.rho;
+    return FKGP_OK;
+}
+
+// Solve (W K_G W^T + s2 I) z = b for b = y (rhs == NULL; x_0 = y/s2) or
+// b = W rhs (x_0 = 0) and return W^T z in `wtz`.
+//  * FP64 handles: the simplified factorized CG as printed, output
+//    W^T z = x_hat^d (+ W^T y / s2).
+//  * FP32 handles: the same CG with B in FP32 as the inner solver of an FP64
+//    iterative refinement: the compressed iterate z = x_0 + W x_hat is kept
+//    in FP64, its residual W r_hat with r_hat = r_hat_0 - B_64(x_hat) is
+//    recomputed in FP64 after every inner solve, and the inner solve returns
+//    the correction of x_hat.
+fkgp_status solve_core(const OpCtx& c, const double* rhs, double tol, int maxiter, double* wtz,
+                       fkgp_solve_info* info, Scratch& sc, hipStream_t st) {
+    const fkgp_handle* h = c.h;
+    const int64_t M = c.M;
+    const unsigned ewg = ew_grid(M);
+    CgBufs b{};
+    fkgp_status rs = alloc_cg(c, b, sc);
+    if (rs != FKGP_OK) return rs;
+    double* r0 = nullptr;
+    FKGP_HIP(sc.get(&r0, M));
+    // r_hat_0 in FP64
+    if (rhs) {
+        FKGP_HIP(hipMemcpyAsync(r0, rhs, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+    } else {
+        rs = kg_apply(h->g, c.sp64, FKGP_F64, h->wty, r0, 1, -c.so / c.s2, nullptr, 0.0, nullptr,
+                      st);
+        if (rs != FKGP_OK) return rs;
+    }
+    int total_iters = 0;
+    bool converged = false;
+    double rho_final = 0.0, bnorm2 = rhs ? 0.0 : h->yty;
+    if (h->dt == FKGP_F64) {
+        FKGP_HIP(hipMemcpyAsync(b.r, r0, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+        FKGP_HIP(hipMemsetAsync(b.xd, 0, sizeof(double) * M, st));
+        FKGP_HIP(hipMemsetAsync(b.x, 0, sizeof(double) * M, st));
+        CgState out{};
+        rs = run_cg(c, b, tol * tol * h->yty, rhs ? tol * tol : -1.0, maxiter, out, st);
+        if (rs != FKGP_OK) return rs;
+        total_iters = out.iters;
+        converged = out.done == 1;
+        rho_final = out.rho;
+        if (rhs) bnorm2 = out.bnorm2;
+        if (rhs)
+            FKGP_HIP(hipMemcpyAsync(wtz, b.xd, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+        else
+            axpy_out<<<ewg, 256, 0, st>>>(b.xd, h->wty, 1.0 / c.s2, wtz, M);
+    } else {
+        double *xt = nullptr, *xpad64 = nullptr, *u64 = nullptr, *v64 = nullptr;
+        FKGP_HIP(sc.get(&xt, M));
+        FKGP_HIP(sc.get(&xpad64, M + 2 * c.halo));
+        FKGP_HIP(sc.get(&u64, M));
+        FKGP_HIP(sc.get(&v64, M));
+        FKGP_HIP(hipMemsetAsync(xt, 0, sizeof(double) * M, st));
+        FKGP_HIP(hipMemsetAsync(xpad64, 0, sizeof(double) * (M + 2 * c.halo), st));
+        FKGP_HIP(hipMemcpyAsync(b.r, r0, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+        double* xin64 = xpad64 + c.halo;
+        if (rhs) {
+            // ||b||^2 = rhs^T W^T W rhs
+            FKGP_HIP(hipMemcpyAsync(xin64, rhs, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+            rs = apply_B64(c, xpad64, u64, nullptr, st);
+            if (rs != FKGP_OK) return rs;
+            rs = dot64(u64, rhs, M, b.partials, b.st, bnorm2, st);
+            if (rs != FKGP_OK) return rs;
+        }
+        const double target = tol * tol * bnorm2;
+        constexpr int kMaxOuter = 12;
+        for (int outer = 0; outer <= kMaxOuter; ++outer) {
+            // true residual norm ||W r_hat||^2 = r_hat^T W^T W r_hat (FP64)
+            FKGP_HIP(hipMemcpyAsync(xin64, b.r, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+            rs = apply_B64(c, xpad64, u64, nullptr, st);
+            if (rs != FKGP_OK) return rs;
+            double rho_true = 0.0;
+            rs = dot64(u64, b.r, M, b.partials, b.st, rho_true, st);
+            if (rs != FKGP_OK) return rs;
+            rho_final = rho_true;
+            if (rho_true <= target) {
+                converged = true;
+                break;
+            }
+            if (outer == kMaxOuter || total_iters >= maxiter) break;
+            // inner FP32 solve to a modest relative accuracy
+            double tin = 0.5 * std::sqrt(target / std::max(rho_true, 1e-300));
+            tin = std::min(std::max(tin, 1e-4), 0.5);
+            FKGP_HIP(hipMemsetAsync(b.xd, 0, sizeof(double) * M, st));
+            FKGP_HIP(hipMemsetAsync(b.x, 0, sizeof(double) * M, st));
+            CgState out{};
+            rs = run_cg(c, b, 0.0, tin * tin, maxiter - total_iters, out, st);
+            if (rs != FKGP_OK) return rs;
+            total_iters += out.iters;
+            add_inplace<<<ewg, 256, 0, st>>>(xt, b.x, M);
+            // r_hat = r_hat_0 - B_64(x_hat).v
+            FKGP_HIP(hipMemcpyAsync(xin64, xt, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+            rs = apply_B64(c, xpad64, u64, v64, st);
+            if (rs != FKGP_OK) return rs;
+            sub_out<<<ewg, 256, 0, st>>>(r0, v64, b.r, M);
+            FKGP_HIP(hipGetLastError());
+            if (out.iters == 0) break;   // no progress possible
+        }
+        // W^T z = W^T W x_hat (+ W^T y / s2)
+        FKGP_HIP(hipMemcpyAsync(xin64, xt, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+        rs = apply_B64(c, xpad64, u64, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+        if (rhs)
+            FKGP_HIP(hipMemcpyAsync(wtz, u64, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+        else
+            axpy_out<<<ewg, 256, 0, st>>>(u64, h->wty, 1.0 / c.s2, wtz, M);
+    }
+    FKGP_HIP(hipGetLastError());
+    if (info) {
+        info->iterations = total_iters;
+        info->converged = converged ? 1 : 0;
+        info->rel_residual = std::sqrt(std::max(rho_final, 0.0) / (bnorm2 > 0 ? bnorm2 : 1.0));
+    }
+    return converged ? FKGP_OK : FKGP_ENOTCONV;
+}
+
+fkgp_status solve_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const double* rhs,
+                       double* out, double tol, int maxiter, fkgp_solve_info* info,
+                       hipStream_t st) {
+    Scratch sc(st);
+    OpCtx c;
+    fkgp_status rs = make_ctx(h, hyp, c, sc);
+    if (rs != FKGP_OK) return rs;
+    double* wtz = nullptr;
+    FKGP_HIP(sc.get(&wtz, h->M));
+    fkgp_status res = solve_core(c, rhs, tol, maxiter, wtz, info, sc, st);
+    if (res != FKGP_OK && res != FKGP_ENOTCONV) return res;
+    if (rhs) {
+        FKGP_HIP(hipMemcpyAsync(out, wtz, sizeof(double) * h->M, hipMemcpyDeviceToDevice, st));
+    } else {
+        // mu_G = K_G W^T z~ (FP64)
+        rs = kg_apply(h->g, c.sp64, FKGP_F64, wtz, out, 1, c.so, nullptr, 0.0, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+    }
+    FKGP_HIP(hipStreamSynchronize(st));
+    return res;
 }
 
 }  // namespace
@@ -745,7 +952,7 @@ fkgp_status fkgp_apply_B(const fkgp_handle* h, const fkgp_hypers* hyp, const voi
         hipStream_t s = static_cast<hipStream_t>(stream);
         Scratch sc(s);
         Spectra sp;
-        st = make_spectra(h, hyp, -1, sp, sc);
+        st = make_spectra(h, hyp, h->dt, -1, sp, sc);
         if (st != FKGP_OK) return st;
         const int64_t halo = dia_halo(h->g);
         const size_t es = dsize(h->dt);
@@ -777,7 +984,7 @@ fkgp_status fkgp_kg_matvec(const fkgp_handle* h, const fkgp_hypers* hyp, const v
         hipStream_t s = static_cast<hipStream_t>(stream);
         Scratch sc(s);
         Spectra sp;
-        st = make_spectra(h, hyp, -1, sp, sc);
+        st = make_spectra(h, hyp, h->dt, -1, sp, sc);
         if (st != FKGP_OK) return st;
         return kg_apply(h->g, sp, h->dt, x, out, k, hyp->outputscale, nullptr, 0.0, nullptr, s);
     });

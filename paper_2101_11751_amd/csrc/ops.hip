@@ -59,7 +59,7 @@ constexpr int kLineBlock = 256;
 // element per lane, 64/L pairs per wave at a time).
 template <class T, int LOG2L>
 __global__ __launch_bounds__(kLineBlock) void line_conv(
-    const T* __restrict__ in, T* __restrict__ out, LineGeom lg, int LB,
+    const T* in, T* out, LineGeom lg, int LB,   // in == out allowed (in place)
     const T* __restrict__ lam_br, const cplx<T>* __restrict__ tw, T scale,
     const T* __restrict__ addv, T add_coef, const int* __restrict__ skip) {
     constexpr int L = 1 << LOG2L;
@@ -292,8 +292,8 @@ struct DiaGeom {
     int ext[3];          // 7 for active dims, 1 otherwise
 };
 
-template <class T, int K>
-__global__ __launch_bounds__(256) void spmv_dia_kernel(const T* __restrict__ A,
+template <class TA, class T, int K>
+__global__ __launch_bounds__(256) void spmv_dia_kernel(const TA* __restrict__ A,
                                                        const T* __restrict__ xpad,
                                                        T* __restrict__ u, DiaGeom dg,
                                                        int64_t halo, int64_t ldx,
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void spmv_dia_kernel(const T* __restrict__ A,
             for (int c = 0; c < 7; ++c) {
                 if (c >= dg.ext[2]) break;
                 const int64_t off = ob + (dg.ext[2] == 7 ? (c - 3) : 0) * dg.stride[2];
-                const T av = A[(int64_t)oi * dg.M + j];
+                const T av = (T)A[(int64_t)oi * dg.M + j];
 #pragma unroll
                 for (int r = 0; r < K; ++r) acc[r] += av * xj[off + r * ldx];
                 ++oi;
@@ -486,8 +486,8 @@ int64_t dia_halo(const GridDev& g) {
     return h;
 }
 
-template <class T>
-static fkgp_status spmv_t(const GridDev& g, const T* A, const T* xpad, T* u, int k,
+template <class TA, class T>
+static fkgp_status spmv_t(const GridDev& g, const TA* A, const T* xpad, T* u, int k,
                           int64_t halo, const int* skip, hipStream_t s) {
     DiaGeom dg{};
     dg.d = g.d;
@@ -513,16 +513,16 @@ static fkgp_status spmv_t(const GridDev& g, const T* A, const T* xpad, T* u, int
         const T* xr = xpad + (int64_t)r0 * ldx;
         T* ur = u + (int64_t)r0 * dg.M;
         if (left >= 8) {
-            spmv_dia_kernel<T, 8><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
+            spmv_dia_kernel<TA, T, 8><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
             r0 += 8;
         } else if (left >= 4) {
-            spmv_dia_kernel<T, 4><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
+            spmv_dia_kernel<TA, T, 4><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
             r0 += 4;
         } else if (left >= 2) {
-            spmv_dia_kernel<T, 2><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
+            spmv_dia_kernel<TA, T, 2><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
             r0 += 2;
         } else {
-            spmv_dia_kernel<T, 1><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
+            spmv_dia_kernel<TA, T, 1><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
             r0 += 1;
         }
     }
@@ -532,20 +532,24 @@ static fkgp_status spmv_t(const GridDev& g, const T* A, const T* xpad, T* u, int
 
 fkgp_status spmv_dia(const GridDev& g, fkgp_dtype dt, const void* A, const void* xpad, void* u,
                      int k, int64_t halo, hipStream_t s) {
-    if (dt == FKGP_F32)
-        return spmv_t<float>(g, static_cast<const float*>(A), static_cast<const float*>(xpad),
-                             static_cast<float*>(u), k, halo, nullptr, s);
-    return spmv_t<double>(g, static_cast<const double*>(A), static_cast<const double*>(xpad),
-                          static_cast<double*>(u), k, halo, nullptr, s);
+    return spmv_dia_skip(g, dt, A, xpad, u, k, halo, nullptr, s);
 }
 
 fkgp_status spmv_dia_skip(const GridDev& g, fkgp_dtype dt, const void* A, const void* xpad,
                           void* u, int k, int64_t halo, const int* skip, hipStream_t s) {
     if (dt == FKGP_F32)
-        return spmv_t<float>(g, static_cast<const float*>(A), static_cast<const float*>(xpad),
-                             static_cast<float*>(u), k, halo, skip, s);
-    return spmv_t<double>(g, static_cast<const double*>(A), static_cast<const double*>(xpad),
-                          static_cast<double*>(u), k, halo, skip, s);
+        return spmv_t<float, float>(g, static_cast<const float*>(A),
+                                    static_cast<const float*>(xpad), static_cast<float*>(u), k,
+                                    halo, skip, s);
+    return spmv_t<double, double>(g, static_cast<const double*>(A),
+                                  static_cast<const double*>(xpad), static_cast<double*>(u), k,
+                                  halo, skip, s);
+}
+
+// FP64 product with an FP32-stored matrix (entries upcast exactly).
+fkgp_status spmv_dia_f32a_f64x(const GridDev& g, const void* A, const double* xpad, double* u,
+                               int k, int64_t halo, hipStream_t s) {
+    return spmv_t<float, double>(g, static_cast<const float*>(A), xpad, u, k, halo, nullptr, s);
 }
 
 fkgp_status interpolate_points(const GridDev& g, const double* mu, const void* const* xq,
