@@ -1,0 +1,192 @@
+#!/usr/bin/env python
+"""Benchmark of the fkgp hot path on one MI355X; prints ONE JSON line.
+
+A step is one pass of the hot path over the 3-D sweep-shaped workload
+(n = 1e8 points in a cylinder, m = 100 x 100 x 30 = 300,000 grid nodes, FP32
+inputs and statistics, FP64 CG scalars): the one-shot O(n) precompute of
+W^T W, W^T y, y^T y followed by the posterior-mean solve (spectra, factorized
+CG with FP32 operator and FP64 refinement, final K_G product).  Inputs are
+generated on the device before timing.
+
+value            = n * steps / timed seconds  (Mpts/s through the whole step)
+precompute_*     = n / precompute time
+cg_mvms_per_s    = CG iterations (one operator B each) per second of solve
+roofline         = banded W^T W product (the dominant kernel of the solve),
+                   algorithmic bytes / average launch duration (HIP events)
+cpu_baseline     = the FP64 CPU oracle on a bounded sample, scaled to the
+                   same per-step work (see "sample")
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=100_000_000)
+    ap.add_argument("--tol", type=float, default=1e-2)
+    ap.add_argument("--maxiter", type=int, default=20000)
+    ap.add_argument("--mvm-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, n_total, iters, budget_s):
+    """Times the oracle (plain serial FP64 C precompute + NumPy/SciPy operator)
+    on a bounded sample and scales it to one step of the full workload."""
+    import numpy as np
+    import oracle
+    grid = wl["grid"]
+    # precompute: calibrate on 20k points, then size the sample to the budget
+    n_cal = 20_000
+    xs = [c[:n_cal].cpu().numpy() for c in wl["x"]]
+    ys = wl["y"][:n_cal].cpu().numpy()
+    t0 = time.perf_counter()
+    oracle.precompute(grid, xs, ys)
+    per_pt = (time.perf_counter() - t0) / n_cal
+    n_s = int(min(n_total, max(n_cal, 0.6 * budget_s / per_pt)))
+    xs = [c[:n_s].cpu().numpy() for c in wl["x"]]
+    ys = wl["y"][:n_s].cpu().numpy()
+    t0 = time.perf_counter()
+    wtw, wty, yty = oracle.precompute(grid, xs, ys)
+    t_pre = time.perf_counter() - t0
+    # operator B at the full grid size (the oracle's MVM), 2 reps
+    v = np.random.default_rng(0).standard_normal(wty.shape[0])
+    reps = 2
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.B_apply(grid, wl["hypers"], wtw, v)
+    t_mvm = (time.perf_counter() - t0) / reps
+    t_step = t_pre * (n_total / n_s) + iters * t_mvm
+    return {"value": n_total / t_step / 1e6, "unit": "Mpts/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle precompute on the first {n_s} points ({t_pre:.1f} s, "
+                       f"{n_s / t_pre / 1e6:.4f} Mpts/s) scaled to n={n_total}, plus "
+                       f"{iters} oracle operator applications at m={wty.shape[0]} "
+                       f"({t_mvm:.3f} s each, {reps} timed)"),
+            "precompute_mpts_per_s": n_s / t_pre / 1e6, "mvm_per_s": 1.0 / t_mvm}
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2101_11751_amd as P
+    from paper_2101_11751_amd import workloads
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    P.load_library()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"generating radar3d workload n={args.n} on {torch.cuda.get_device_name(0)}")
+    wl = workloads.radar3d(n=args.n, device=dev)
+    torch.cuda.synchronize()
+    grid, hyp = wl["grid"], wl["hypers"]
+    n = args.n
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        h = P.precompute(grid, wl["x"], wl["y"], stats_dtype=torch.float32)
+        if ev is not None:
+            ev[1].record()
+        mu, info = P.solve(h, hyp, tol=args.tol, maxiter=args.maxiter)
+        if ev is not None:
+            ev[2].record()
+        return h, mu, info
+
+    for w in range(args.warmup):
+        h, mu, info = step()
+        log(f"warmup {w}: iterations={info['iterations']} converged={info['converged']} "
+            f"rel_res={info['rel_residual']:.2e}")
+        h.close()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    iters = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        h, mu, info = step(evs[k])
+        iters.append(info["iterations"])
+        if k < args.steps - 1:
+            h.close()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    t_pre = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps / 1e3
+    t_sol = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps / 1e3
+    log(f"timed {args.steps} steps: {elapsed:.3f} s; precompute {t_pre*1e3:.2f} ms, "
+        f"solve {t_sol*1e3:.2f} ms, iterations {iters}")
+
+    # dominant kernel: the banded W^T W product (one per CG iteration)
+    M = h.m_total
+    x = torch.randn(M, device=dev, dtype=torch.float32)
+    xp = P.padded(h, x)
+    u = torch.empty(1, M, device=dev, dtype=torch.float32)
+    for _ in range(3):
+        P.wtw_matvec_padded(h, xp, u)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.mvm_reps):
+        P.wtw_matvec_padded(h, xp, u)
+    e1.record()
+    torch.cuda.synchronize()
+    t_spmv = e0.elapsed_time(e1) / args.mvm_reps / 1e3
+    nb = 7 ** h.d
+    alg_bytes = 4 * (M * nb + 2 * M)
+    achieved = alg_bytes / t_spmv / 1e9
+    log(f"spmv avg {t_spmv*1e6:.1f} us, {achieved:.0f} GB/s algorithmic")
+
+    iters_mean = sum(iters) / len(iters)
+    result = {
+        "metric": "precompute Mpts/s; CG MVMs/s at m=300k; MLL+grad s/eval vs plain FP64",
+        "value": n * args.steps / elapsed / 1e6,
+        "unit": "Mpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "radar3d: n=1e8 cylinder r<=1, 0<=z<0.3, areal density ~1/(r+0.05), "
+                               "50 anisotropic blobs + N(0,0.1^2); grid 100x100x30 (m=300000); "
+                               "SE l=(0.05,0.05,0.02) s=1 sigma=0.1; FP32 stats/operator, FP64 CG",
+                   "n": n, "m": M, "tol": args.tol, "step": "precompute + posterior-mean solve"},
+        "precompute_mpts_per_s": n / t_pre / 1e6,
+        "precompute_ms": t_pre * 1e3,
+        "solve_ms": t_sol * 1e3,
+        "cg_iterations": iters_mean,
+        "cg_mvms_per_s": iters_mean / t_sol,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "spmv_dia_kernel<float,float,1> (banded W^T W product)",
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_us": t_spmv * 1e6},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cb = cpu_baseline(wl, n, iters_mean, args.cpu_seconds)
+        result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -103,6 +103,8 @@ typedef struct {
     double yty;
     int64_t bytes_wtw;       /* device bytes of the stored W^T W */
     int64_t nnz_wtw;         /* stored stencil-diagonal entries (m * 7^d) */
+    int64_t halo;            /* zero padding on each side of a vector passed
+                                to fkgp_wtw_matvec: 3 * sum_k stride_k */
 } fkgp_handle_desc;
 
 fkgp_status fkgp_describe(const fkgp_handle* h, fkgp_handle_desc* desc);
@@ -118,15 +120,27 @@ fkgp_status fkgp_export_stats(const fkgp_handle* h, void* wtw, double* wty,
 /* Probe sketches W^T z_j, j < n_probes, as [n_probes][m] doubles (device). */
 fkgp_status fkgp_export_sketches(const fkgp_handle* h, double* out, void* stream);
 
+/* Arithmetic of the operator B inside the CG loop.  The stored W^T W keeps
+ * the handle's stats dtype either way (it is what HBM traffic is made of).
+ *   FKGP_OP_F64:   vectors, FFTs and accumulation in FP64 (FP32-stored
+ *                  entries are upcast exactly); the solver is the printed
+ *                  simplified factorized CG.
+ *   FKGP_OP_STATS: arithmetic in the stats dtype; for FP32 handles the FP32
+ *                  CG is the inner solver of an FP64 iterative refinement
+ *                  (residual recomputed in FP64 after every inner solve). */
+typedef enum { FKGP_OP_F64 = 0, FKGP_OP_STATS = 1 } fkgp_op_precision;
+
 typedef struct {
     double tol;        /* relative residual: stop when ||r|| <= tol ||b|| */
     int maxiter;
+    fkgp_op_precision op_precision;
 } fkgp_solve_opts;
 
 typedef struct {
     int iterations;
     int converged;
-    double rel_residual;   /* recursive relative residual at exit */
+    double rel_residual;   /* relative residual at exit (recursive for
+                              FKGP_OP_F64, recomputed in FP64 otherwise) */
 } fkgp_solve_info;
 
 /* Posterior mean on the grid, or a grid right-hand side solve, with the
@@ -189,6 +203,14 @@ fkgp_status fkgp_apply_B(const fkgp_handle* h, const fkgp_hypers* hyp,
  * synchronise. */
 fkgp_status fkgp_kg_matvec(const fkgp_handle* h, const fkgp_hypers* hyp,
                            const void* x, void* out, int k, void* stream);
+
+/* u = (W^T W) x for k vectors (Claim 2: at most 7^d nonzeros per row, so
+ * one product costs O(m 7^d)).  x: [k][m + 2*halo] in the handle's stats
+ * dtype, each vector stored at offset halo with halo zeros on both sides
+ * (halo from fkgp_describe); u: [k][m].  The single kernel launch reads the
+ * stored W^T W once for all k vectors.  Does not synchronise. */
+fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int k,
+                            void* stream);
 
 void fkgp_destroy(fkgp_handle* h);
 

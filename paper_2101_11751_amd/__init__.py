@@ -24,7 +24,7 @@ OK, ENOTCONV, EINVAL, EOUTOFGRID, ENOMEM, EDEVICE = 0, 1, -1, -2, -3, -4
 #: every symbol that include/fkgp.h declares
 EXPORTS = ("fkgp_precompute", "fkgp_describe", "fkgp_export_stats", "fkgp_export_sketches",
            "fkgp_solve", "fkgp_mll_and_grad", "fkgp_interpolate", "fkgp_apply_B",
-           "fkgp_kg_matvec", "fkgp_destroy", "fkgp_last_error")
+           "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_destroy", "fkgp_last_error")
 
 
 class FkgpError(RuntimeError):
@@ -56,11 +56,15 @@ class _Desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m_total", ctypes.c_int64), ("d", ctypes.c_int),
                 ("stats_dtype", ctypes.c_int), ("n_probes", ctypes.c_int),
                 ("yty", ctypes.c_double), ("bytes_wtw", ctypes.c_int64),
-                ("nnz_wtw", ctypes.c_int64)]
+                ("nnz_wtw", ctypes.c_int64), ("halo", ctypes.c_int64)]
+
+
+OP_F64, OP_STATS = 0, 1
 
 
 class _SolveOpts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int)]
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int),
+                ("op_precision", ctypes.c_int)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -104,6 +108,7 @@ def load_library():
     L.fkgp_interpolate.argtypes = [p, p, ctypes.POINTER(p), ctypes.c_int64, ctypes.c_int, p, p]
     L.fkgp_apply_B.argtypes = [p, ctypes.POINTER(_Hypers), p, p, p, ctypes.c_int, p]
     L.fkgp_kg_matvec.argtypes = [p, ctypes.POINTER(_Hypers), p, p, ctypes.c_int, p]
+    L.fkgp_wtw_matvec.argtypes = [p, p, p, ctypes.c_int, p]
     L.fkgp_destroy.argtypes = [p]
     L.fkgp_destroy.restype = None
     L.fkgp_last_error.argtypes = []
@@ -179,6 +184,7 @@ class Handle:
         self.yty = d.yty
         self.bytes_wtw = d.bytes_wtw
         self.nnz_wtw = d.nnz_wtw
+        self.halo = d.halo
 
     @property
     def ptr(self):
@@ -235,9 +241,11 @@ def export_sketches(h):
     return out
 
 
-def solve(h, hypers, rhs=None, tol=1e-6, maxiter=1000):
+def solve(h, hypers, rhs=None, tol=1e-6, maxiter=1000, op_precision="f64"):
     """Posterior-mean grid weights mu_G (rhs None), or W^T A^{-1} W rhs.
-    Returns (out [M] float64, info dict)."""
+    op_precision "f64": operator arithmetic in FP64 on the stored W^T W;
+    "stats": arithmetic in the stats dtype (FP32 handles: FP32 inner CG with
+    FP64 iterative refinement).  Returns (out [M] float64, info dict)."""
     L = load_library()
     dev = torch.device("cuda", torch.cuda.current_device())
     out = torch.empty(h.m_total, dtype=torch.float64, device=dev)
@@ -245,7 +253,9 @@ def solve(h, hypers, rhs=None, tol=1e-6, maxiter=1000):
         rhs = rhs.to(torch.float64).contiguous()
     info = _SolveInfo()
     st = _check(L.fkgp_solve(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)), _ptr(rhs), _ptr(out),
-                             ctypes.byref(_SolveOpts(float(tol), int(maxiter))),
+                             ctypes.byref(_SolveOpts(float(tol), int(maxiter),
+                                                     OP_STATS if op_precision == "stats"
+                                                     else OP_F64)),
                              ctypes.byref(info), _stream()))
     return out, {"iterations": info.iterations, "converged": bool(info.converged),
                  "rel_residual": info.rel_residual, "status": st}
@@ -282,6 +292,28 @@ def kg_matvec(h, hypers, x):
     _check(L.fkgp_kg_matvec(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)), _ptr(X), _ptr(out),
                             X.shape[0], _stream()))
     return out[0] if squeeze else out
+
+
+def padded(h, x):
+    """[k, M] (or [M]) -> zero-padded [k, M + 2 halo] buffer in the stats dtype."""
+    X = x.reshape(-1, h.m_total)
+    out = torch.zeros(X.shape[0], h.m_total + 2 * h.halo, dtype=h.stats_dtype, device=X.device)
+    out[:, h.halo:h.halo + h.m_total] = X
+    return out
+
+
+def wtw_matvec_padded(h, xpad, u):
+    """u[k, M] = W^T W xpad (xpad from `padded`); launches one kernel, no sync."""
+    _check(load_library().fkgp_wtw_matvec(h.ptr, _ptr(xpad), _ptr(u), xpad.shape[0], _stream()))
+    return u
+
+
+def wtw_matvec(h, x):
+    squeeze = x.dim() == 1
+    xp = padded(h, x)
+    u = torch.empty(xp.shape[0], h.m_total, dtype=h.stats_dtype, device=x.device)
+    wtw_matvec_padded(h, xp, u)
+    return u[0] if squeeze else u
 
 
 def mll_and_grad(h, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000):

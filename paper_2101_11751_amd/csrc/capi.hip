@@ -328,35 +328,39 @@ fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtyp
 // in FP64 (FP32-stored W^T W upcast exactly, FP64 K_G).
 struct OpCtx {
     const fkgp_handle* h;
+    fkgp_dtype op;  // arithmetic dtype of B inside the CG loop
     double so, s2;
     int64_t M, halo;
-    Spectra sp;     // working dtype
-    Spectra sp64;   // FP64 (same as sp for FP64 handles)
+    Spectra sp;     // spectra in dtype `op`
+    Spectra sp64;   // FP64 spectra (same as sp when op is FP64)
 };
 
-fkgp_status make_ctx(const fkgp_handle* h, const fkgp_hypers* hyp, OpCtx& c, Scratch& sc) {
+fkgp_status make_ctx(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtype op, OpCtx& c,
+                     Scratch& sc) {
     c.h = h;
+    c.op = op;
     c.so = hyp->outputscale;
     c.s2 = hyp->noise_std * hyp->noise_std;
     c.M = h->M;
     c.halo = dia_halo(h->g);
-    fkgp_status st = make_spectra(h, hyp, h->dt, -1, c.sp, sc);
+    fkgp_status st = make_spectra(h, hyp, op, -1, c.sp, sc);
     if (st != FKGP_OK) return st;
-    if (h->dt == FKGP_F64) {
+    if (op == FKGP_F64) {
         c.sp64 = c.sp;
         return FKGP_OK;
     }
     return make_spectra(h, hyp, FKGP_F64, -1, c.sp64, sc);
 }
 
-// B in the working dtype on one padded vector: u = A x, v = so K u + s2 x.
+// B in dtype c.op on one padded vector: u = A x, v = so K u + s2 x (the
+// stored W^T W may be FP32 while c.op is FP64: entries are upcast exactly).
 fkgp_status apply_B_padded(const OpCtx& c, const void* xpad, void* u, void* v, const int* skip,
                            hipStream_t st) {
     const fkgp_handle* h = c.h;
-    fkgp_status r = spmv_dia_skip(h->g, h->dt, h->A, xpad, u, 1, c.halo, skip, st);
+    fkgp_status r = spmv_dia_any(h->g, h->dt, c.op, h->A, xpad, u, 1, c.halo, skip, st);
     if (r != FKGP_OK) return r;
-    const void* xin = static_cast<const unsigned char*>(xpad) + c.halo * dsize(h->dt);
-    return kg_apply_skip(h->g, c.sp, h->dt, u, v, 1, c.so, xin, c.s2, skip, st);
+    const void* xin = static_cast<const unsigned char*>(xpad) + c.halo * dsize(c.op);
+    return kg_apply_skip(h->g, c.sp, c.op, u, v, 1, c.so, xin, c.s2, skip, st);
 }
 
 // B in FP64 on one padded FP64 vector (v may be NULL: u only).
@@ -377,7 +381,7 @@ struct CgBufs {
 
 fkgp_status alloc_cg(const OpCtx& c, CgBufs& b, Scratch& sc) {
     const int64_t M = c.M;
-    const size_t es = dsize(c.h->dt);
+    const size_t es = dsize(c.op);
     FKGP_HIP(sc.get(&b.r, M));
     FKGP_HIP(sc.get(&b.s, M));
     FKGP_HIP(sc.get(&b.z, M));
@@ -445,7 +449,7 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
                    CgState& out, hipStream_t st) {
     const fkgp_handle* h = c.h;
     const int64_t M = c.M;
-    const size_t es = dsize(h->dt);
+    const size_t es = dsize(c.op);
     unsigned char* rin = b.rpad + c.halo * es;
     CgState init{};
     const bool rel = eps_rel >= 0.0;
@@ -454,13 +458,13 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
     FKGP_HIP(hipMemsetAsync(b.s, 0, sizeof(double) * M, st));
     FKGP_HIP(hipMemsetAsync(b.z, 0, sizeof(double) * M, st));
     FKGP_HIP(hipMemsetAsync(b.p, 0, sizeof(double) * M, st));
-    FKGP_HIP(convert_any(b.r, FKGP_F64, rin, h->dt, M, 1.0, st));
+    FKGP_HIP(convert_any(b.r, FKGP_F64, rin, c.op, M, 1.0, st));
     fkgp_status rs = apply_B_padded(c, b.rpad, b.u, b.v, nullptr, st);
     if (rs != FKGP_OK) return rs;
     const int nb = red_blocks(M);
     const unsigned ewg = ew_grid(M);
     auto dot_ur = [&](const int* skip) -> hipError_t {
-        if (h->dt == FKGP_F32)
+        if (c.op == FKGP_F32)
             dot_partial<float><<<nb, kRedBlock, 0, st>>>(reinterpret_cast<float*>(b.u), b.r, M,
                                                          b.partials, skip);
         else
@@ -469,7 +473,7 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
         return hipGetLastError();
     };
     auto step2 = [&]() -> hipError_t {
-        if (h->dt == FKGP_F32)
+        if (c.op == FKGP_F32)
             cg_step2x<float><<<nb, kRedBlock, 0, st>>>(b.st, b.s, b.z, b.p, b.r,
                                                        reinterpret_cast<float*>(b.u),
                                                        reinterpret_cast<float*>(b.v), M,
@@ -494,7 +498,7 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
         if (out.done || launched >= maxiter) break;
         const int nit = std::min(kBatch, maxiter - launched);
         for (int it = 0; it < nit; ++it) {
-            if (h->dt == FKGP_F32)
+            if (c.op == FKGP_F32)
                 cg_step1x<float><<<ewg, 256, 0, st>>>(b.st, b.xd, b.x, b.r, b.s, b.z, b.p,
                                                       reinterpret_cast<float*>(rin), M);
             else
@@ -577,7 +581,7 @@ fkgp_status solve_core(const OpCtx& c, const double* rhs, double tol, int maxite
     int total_iters = 0;
     bool converged = false;
     double rho_final = 0.0, bnorm2 = rhs ? 0.0 : h->yty;
-    if (h->dt == FKGP_F64) {
+    if (c.op == FKGP_F64) {
         FKGP_HIP(hipMemcpyAsync(b.r, r0, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
         FKGP_HIP(hipMemsetAsync(b.xd, 0, sizeof(double) * M, st));
         FKGP_HIP(hipMemsetAsync(b.x, 0, sizeof(double) * M, st));
@@ -663,11 +667,11 @@ fkgp_status solve_core(const OpCtx& c, const double* rhs, double tol, int maxite
 }
 
 fkgp_status solve_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const double* rhs,
-                       double* out, double tol, int maxiter, fkgp_solve_info* info,
-                       hipStream_t st) {
+                       double* out, double tol, int maxiter, fkgp_dtype op,
+                       fkgp_solve_info* info, hipStream_t st) {
     Scratch sc(st);
     OpCtx c;
-    fkgp_status rs = make_ctx(h, hyp, c, sc);
+    fkgp_status rs = make_ctx(h, hyp, op, c, sc);
     if (rs != FKGP_OK) return rs;
     double* wtz = nullptr;
     FKGP_HIP(sc.get(&wtz, h->M));
@@ -836,6 +840,7 @@ fkgp_status fkgp_describe(const fkgp_handle* h, fkgp_handle_desc* desc) {
     desc->yty = h->yty;
     desc->nnz_wtw = h->M * h->NB;
     desc->bytes_wtw = h->M * h->NB * (int64_t)dsize(h->dt);
+    desc->halo = dia_halo(h->g);
     return FKGP_OK;
 }
 
@@ -887,13 +892,18 @@ fkgp_status fkgp_solve(const fkgp_handle* h, const fkgp_hypers* hyp, const doubl
         }
         fkgp_status st = check_hypers(h, hyp);
         if (st != FKGP_OK) return st;
-        fkgp_solve_opts o{1e-6, 1000};
+        fkgp_solve_opts o{1e-6, 1000, FKGP_OP_F64};
         if (opts) o = *opts;
         if (!(o.tol >= 0.0) || o.maxiter < 0) {
             set_error("tol must be >= 0 and maxiter >= 0");
             return FKGP_EINVAL;
         }
-        return solve_impl(h, hyp, rhs_grid, out, o.tol, o.maxiter, info,
+        if (o.op_precision != FKGP_OP_F64 && o.op_precision != FKGP_OP_STATS) {
+            set_error("op_precision must be FKGP_OP_F64 or FKGP_OP_STATS");
+            return FKGP_EINVAL;
+        }
+        const fkgp_dtype op = o.op_precision == FKGP_OP_STATS ? h->dt : FKGP_F64;
+        return solve_impl(h, hyp, rhs_grid, out, o.tol, o.maxiter, op, info,
                           static_cast<hipStream_t>(stream));
     });
 }
@@ -987,6 +997,18 @@ fkgp_status fkgp_kg_matvec(const fkgp_handle* h, const fkgp_hypers* hyp, const v
         st = make_spectra(h, hyp, h->dt, -1, sp, sc);
         if (st != FKGP_OK) return st;
         return kg_apply(h->g, sp, h->dt, x, out, k, hyp->outputscale, nullptr, 0.0, nullptr, s);
+    });
+}
+
+fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int k,
+                            void* stream) {
+    return guarded([&]() -> fkgp_status {
+        if (!h || !xpad || !u || k < 1) {
+            set_error("invalid argument");
+            return FKGP_EINVAL;
+        }
+        return spmv_dia(h->g, h->dt, h->A, xpad, u, k, dia_halo(h->g),
+                        static_cast<hipStream_t>(stream));
     });
 }
 

@@ -86,6 +86,9 @@ fkgp_status spmv_dia_f32a_f64x(const GridDev& g, const void* A, const double* xp
 fkgp_status kg_apply_skip(const GridDev& g, const Spectra& sp, fkgp_dtype dt, const void* x,
                           void* y, int k, double scale, const void* addv, double add_coef,
                           const int* skip, hipStream_t s);
+fkgp_status spmv_dia_any(const GridDev& g, fkgp_dtype dta, fkgp_dtype dtx, const void* A,
+                         const void* xpad, void* u, int k, int64_t halo, const int* skip,
+                         hipStream_t s);
 int64_t dia_halo(const GridDev& g);
 
 fkgp_status interpolate_points(const GridDev& g, const double* mu,

@@ -546,6 +546,20 @@ fkgp_status spmv_dia_skip(const GridDev& g, fkgp_dtype dt, const void* A, const 
                                   halo, skip, s);
 }
 
+// Product with matrix dtype dta and vector dtype dtx (FP32 matrix entries are
+// upcast exactly when the vectors are FP64).
+fkgp_status spmv_dia_any(const GridDev& g, fkgp_dtype dta, fkgp_dtype dtx, const void* A,
+                         const void* xpad, void* u, int k, int64_t halo, const int* skip,
+                         hipStream_t s) {
+    if (dta == dtx) return spmv_dia_skip(g, dta, A, xpad, u, k, halo, skip, s);
+    if (dta == FKGP_F32 && dtx == FKGP_F64)
+        return spmv_t<float, double>(g, static_cast<const float*>(A),
+                                     static_cast<const double*>(xpad), static_cast<double*>(u), k,
+                                     halo, skip, s);
+    set_error("unsupported matrix/vector dtype combination");
+    return FKGP_EINVAL;
+}
+
 // FP64 product with an FP32-stored matrix (entries upcast exactly).
 fkgp_status spmv_dia_f32a_f64x(const GridDev& g, const void* A, const double* xpad, double* u,
                                int k, int64_t halo, hipStream_t s) {

@@ -150,16 +150,20 @@ def test_solve_mean_fp64(d):
 
 
 @pytest.mark.parametrize("d", [1, 2, 3])
-def test_solve_mean_fp32(d):
+@pytest.mark.parametrize("op", ["f64", "stats"])
+def test_solve_mean_fp32(d, op):
+    """FP32 statistics; operator arithmetic FP64 (on the FP32-stored W^T W) or
+    FP32 with FP64 iterative refinement: mean within 1e-5 of the oracle."""
     _need_gpu()
     grid, X, y = make_case(d, 20000, 11)
     xs, yt = to_dev(X, y)
     h = P.precompute(grid, xs, yt, stats_dtype=torch.float32)
     wtw_o, wty_o, yty_o = oracle.precompute(grid, X, y)
     mu_o, _, _ = oracle.solve_mean(grid, HYP[d], wtw_o, wty_o, yty_o, tol=1e-13)
-    mu, info = P.solve(h, HYP[d], tol=1e-7, maxiter=5000)
+    mu, info = P.solve(h, HYP[d], tol=1e-7, maxiter=5000, op_precision=op)
     err = rel(mu.cpu(), mu_o)
-    print(f"d={d} fp32 mean rel err {err:.3e} iters {info['iterations']}")
+    print(f"d={d} op={op} fp32-stats mean rel err {err:.3e} iters {info['iterations']}")
+    assert info["converged"]
     assert err <= 1e-5
 
 
@@ -174,7 +178,7 @@ def test_solve_grid_rhs(stats):
     rhs = np.random.default_rng(4).standard_normal(h.m_total)
     ref, _ = oracle.solve_grid_rhs(grid, HYP[2], wtw_o, rhs, tol=1e-13)
     out, info = P.solve(h, HYP[2], rhs=torch.from_numpy(rhs).cuda(), tol=1e-12 if stats == "f64" else 1e-7,
-                        maxiter=5000)
+                        maxiter=5000, op_precision="stats")
     assert rel(out.cpu(), ref) <= (1e-9 if stats == "f64" else 1e-4)
 
 
