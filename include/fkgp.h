@@ -205,12 +205,14 @@ fkgp_status fkgp_kg_matvec(const fkgp_handle* h, const fkgp_hypers* hyp,
                            const void* x, void* out, int k, void* stream);
 
 /* u = (W^T W) x for k vectors (Claim 2: at most 7^d nonzeros per row, so
- * one product costs O(m 7^d)).  x: [k][m + 2*halo] in the handle's stats
- * dtype, each vector stored at offset halo with halo zeros on both sides
- * (halo from fkgp_describe); u: [k][m].  The single kernel launch reads the
- * stored W^T W once for all k vectors.  Does not synchronise. */
+ * one product costs O(m 7^d)).  x: [k][m + 2*halo] of dtype `xdt` (the
+ * handle's stats dtype, or FKGP_F64 for FP64 vectors against FP32-stored
+ * entries, the product inside the FP64-arithmetic CG), each vector stored at
+ * offset halo with halo zeros on both sides (halo from fkgp_describe);
+ * u: [k][m] of dtype `xdt`.  One kernel launch reads the stored W^T W once
+ * for all k vectors.  Does not synchronise. */
 fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int k,
-                            void* stream);
+                            fkgp_dtype xdt, void* stream);
 
 void fkgp_destroy(fkgp_handle* h);
 

@@ -108,7 +108,7 @@ def load_library():
     L.fkgp_interpolate.argtypes = [p, p, ctypes.POINTER(p), ctypes.c_int64, ctypes.c_int, p, p]
     L.fkgp_apply_B.argtypes = [p, ctypes.POINTER(_Hypers), p, p, p, ctypes.c_int, p]
     L.fkgp_kg_matvec.argtypes = [p, ctypes.POINTER(_Hypers), p, p, ctypes.c_int, p]
-    L.fkgp_wtw_matvec.argtypes = [p, p, p, ctypes.c_int, p]
+    L.fkgp_wtw_matvec.argtypes = [p, p, p, ctypes.c_int, ctypes.c_int, p]
     L.fkgp_destroy.argtypes = [p]
     L.fkgp_destroy.restype = None
     L.fkgp_last_error.argtypes = []
@@ -294,24 +294,27 @@ def kg_matvec(h, hypers, x):
     return out[0] if squeeze else out
 
 
-def padded(h, x):
-    """[k, M] (or [M]) -> zero-padded [k, M + 2 halo] buffer in the stats dtype."""
+def padded(h, x, dtype=None):
+    """[k, M] (or [M]) -> zero-padded [k, M + 2 halo] buffer (stats dtype by
+    default, or float64 for FP64 vectors against FP32-stored entries)."""
     X = x.reshape(-1, h.m_total)
-    out = torch.zeros(X.shape[0], h.m_total + 2 * h.halo, dtype=h.stats_dtype, device=X.device)
+    dt = dtype or h.stats_dtype
+    out = torch.zeros(X.shape[0], h.m_total + 2 * h.halo, dtype=dt, device=X.device)
     out[:, h.halo:h.halo + h.m_total] = X
     return out
 
 
 def wtw_matvec_padded(h, xpad, u):
     """u[k, M] = W^T W xpad (xpad from `padded`); launches one kernel, no sync."""
-    _check(load_library().fkgp_wtw_matvec(h.ptr, _ptr(xpad), _ptr(u), xpad.shape[0], _stream()))
+    _check(load_library().fkgp_wtw_matvec(h.ptr, _ptr(xpad), _ptr(u), xpad.shape[0],
+                                          _dtype_code(xpad.dtype), _stream()))
     return u
 
 
-def wtw_matvec(h, x):
+def wtw_matvec(h, x, dtype=None):
     squeeze = x.dim() == 1
-    xp = padded(h, x)
-    u = torch.empty(xp.shape[0], h.m_total, dtype=h.stats_dtype, device=x.device)
+    xp = padded(h, x, dtype)
+    u = torch.empty(xp.shape[0], h.m_total, dtype=xp.dtype, device=x.device)
     wtw_matvec_padded(h, xp, u)
     return u[0] if squeeze else u
 

@@ -355,9 +355,10 @@ fkgp_status make_ctx(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtype op
 // B in dtype c.op on one padded vector: u = A x, v = so K u + s2 x (the
 // stored W^T W may be FP32 while c.op is FP64: entries are upcast exactly).
 fkgp_status apply_B_padded(const OpCtx& c, const void* xpad, void* u, void* v, const int* skip,
-                           hipStream_t st) {
+                           hipStream_t st, double* dotp = nullptr, int* nparts = nullptr) {
     const fkgp_handle* h = c.h;
-    fkgp_status r = spmv_dia_any(h->g, h->dt, c.op, h->A, xpad, u, 1, c.halo, skip, st);
+    fkgp_status r =
+        spmv_dia_any(h->g, h->dt, c.op, h->A, xpad, u, 1, c.halo, skip, st, dotp, nparts);
     if (r != FKGP_OK) return r;
     const void* xin = static_cast<const unsigned char*>(xpad) + c.halo * dsize(c.op);
     return kg_apply_skip(h->g, c.sp, c.op, u, v, 1, c.so, xin, c.s2, skip, st);
@@ -388,7 +389,7 @@ fkgp_status alloc_cg(const OpCtx& c, CgBufs& b, Scratch& sc) {
     FKGP_HIP(sc.get(&b.p, M));
     FKGP_HIP(sc.get(&b.x, M));
     FKGP_HIP(sc.get(&b.xd, M));
-    FKGP_HIP(sc.get(&b.partials, kRedMaxBlocks));
+    FKGP_HIP(sc.get(&b.partials, std::max<int64_t>(kRedMaxBlocks, spmv_dot_parts(c.h->g))));
     FKGP_HIP(sc.get(&b.rpad, es * (M + 2 * c.halo)));
     FKGP_HIP(sc.get(&b.u, es * M));
     FKGP_HIP(sc.get(&b.v, es * M));
@@ -407,7 +408,7 @@ __global__ void cg_step1x(const CgState* __restrict__ st, double* __restrict__ x
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
          i += (int64_t)gridDim.x * blockDim.x) {
         xd[i] = fma(a, s[i], xd[i]);
-        x[i] = fma(a, p[i], x[i]);
+        if (x) x[i] = fma(a, p[i], x[i]);
         const double rn = fma(-a, z[i], r[i]);
         r[i] = rn;
         rpad[i] = (T)rn;
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(kRedBlock) void cg_step2x(const CgState* __restrict
         const double zn = fma(b, z[i], (double)v[i]);
         s[i] = sn;
         z[i] = zn;
-        p[i] = fma(b, p[i], r[i]);
+        if (p) p[i] = fma(b, p[i], r[i]);
         acc = fma(sn, zn, acc);
     }
     const double t = block_sum(acc, sh);
@@ -446,7 +447,9 @@ __global__ __launch_bounds__(kRedBlock) void cg_step2x(const CgState* __restrict
 // b.x += sum_k alpha_k p_hat_k (= x_hat, the compressed solution update).
 // Stop when u^T r_hat <= eps, with eps = eps_abs, or eps_rel * (u^T r_hat)_0.
 fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, int maxiter,
-                   CgState& out, hipStream_t st) {
+                   CgState& out, hipStream_t st, bool track_x = true) {
+    double* px = track_x ? b.x : nullptr;
+    double* pp = track_x ? b.p : nullptr;
     const fkgp_handle* h = c.h;
     const int64_t M = c.M;
     const size_t es = dsize(c.op);
@@ -474,12 +477,12 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
     };
     auto step2 = [&]() -> hipError_t {
         if (c.op == FKGP_F32)
-            cg_step2x<float><<<nb, kRedBlock, 0, st>>>(b.st, b.s, b.z, b.p, b.r,
+            cg_step2x<float><<<nb, kRedBlock, 0, st>>>(b.st, b.s, b.z, pp, b.r,
                                                        reinterpret_cast<float*>(b.u),
                                                        reinterpret_cast<float*>(b.v), M,
                                                        b.partials);
         else
-            cg_step2x<double><<<nb, kRedBlock, 0, st>>>(b.st, b.s, b.z, b.p, b.r,
+            cg_step2x<double><<<nb, kRedBlock, 0, st>>>(b.st, b.s, b.z, pp, b.r,
                                                         reinterpret_cast<double*>(b.u),
                                                         reinterpret_cast<double*>(b.v), M,
                                                         b.partials);
@@ -499,16 +502,17 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
         const int nit = std::min(kBatch, maxiter - launched);
         for (int it = 0; it < nit; ++it) {
             if (c.op == FKGP_F32)
-                cg_step1x<float><<<ewg, 256, 0, st>>>(b.st, b.xd, b.x, b.r, b.s, b.z, b.p,
+                cg_step1x<float><<<ewg, 256, 0, st>>>(b.st, b.xd, px, b.r, b.s, b.z, pp,
                                                       reinterpret_cast<float*>(rin), M);
             else
-                cg_step1x<double><<<ewg, 256, 0, st>>>(b.st, b.xd, b.x, b.r, b.s, b.z, b.p,
+                cg_step1x<double><<<ewg, 256, 0, st>>>(b.st, b.xd, px, b.r, b.s, b.z, pp,
                                                        reinterpret_cast<double*>(rin), M);
             FKGP_HIP(hipGetLastError());
-            rs = apply_B_padded(c, b.rpad, b.u, b.v, &b.st->done, st);
+            int np = 0;
+            rs = apply_B_padded(c, b.rpad, b.u, b.v, &b.st->done, st, b.partials, &np);
             if (rs != FKGP_OK) return rs;
-            FKGP_HIP(dot_ur(&b.st->done));
-            finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_RHO);
+            if (np == 0) FKGP_HIP(dot_ur(&b.st->done));
+            finalize<<<1, kRedBlock, 0, st>>>(b.partials, np ? np : nb, b.st, FIN_RHO);
             FKGP_HIP(step2());
             finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_SZ);
             FKGP_HIP(hipGetLastError());
@@ -586,7 +590,8 @@ fkgp_status solve_core(const OpCtx& c, const double* rhs, double tol, int maxite
         FKGP_HIP(hipMemsetAsync(b.xd, 0, sizeof(double) * M, st));
         FKGP_HIP(hipMemsetAsync(b.x, 0, sizeof(double) * M, st));
         CgState out{};
-        rs = run_cg(c, b, tol * tol * h->yty, rhs ? tol * tol : -1.0, maxiter, out, st);
+        rs = run_cg(c, b, tol * tol * h->yty, rhs ? tol * tol : -1.0, maxiter, out, st,
+                    /*track_x=*/false);
         if (rs != FKGP_OK) return rs;
         total_iters = out.iters;
         converged = out.done == 1;
@@ -790,7 +795,7 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
             return e;
         };
         hipError_t e;
-        if ((e = hipMalloc(&h->A, dsize(h->dt) * (size_t)M * h->NB)) != hipSuccess)
+        if ((e = hipMalloc(&h->A, dsize(h->dt) * (size_t)dia_elems(M, h->NB))) != hipSuccess)
             return fail(hip_fail(e, "hipMalloc(W^T W)"));
         if ((e = hipMalloc(&h->wty, sizeof(double) * M)) != hipSuccess)
             return fail(hip_fail(e, "hipMalloc(W^T y)"));
@@ -839,7 +844,7 @@ fkgp_status fkgp_describe(const fkgp_handle* h, fkgp_handle_desc* desc) {
     desc->n_probes = h->nprobe;
     desc->yty = h->yty;
     desc->nnz_wtw = h->M * h->NB;
-    desc->bytes_wtw = h->M * h->NB * (int64_t)dsize(h->dt);
+    desc->bytes_wtw = dia_elems(h->M, h->NB) * (int64_t)dsize(h->dt);
     desc->halo = dia_halo(h->g);
     return FKGP_OK;
 }
@@ -1001,14 +1006,18 @@ fkgp_status fkgp_kg_matvec(const fkgp_handle* h, const fkgp_hypers* hyp, const v
 }
 
 fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int k,
-                            void* stream) {
+                            fkgp_dtype xdt, void* stream) {
     return guarded([&]() -> fkgp_status {
         if (!h || !xpad || !u || k < 1) {
             set_error("invalid argument");
             return FKGP_EINVAL;
         }
-        return spmv_dia(h->g, h->dt, h->A, xpad, u, k, dia_halo(h->g),
-                        static_cast<hipStream_t>(stream));
+        if (xdt != h->dt && !(h->dt == FKGP_F32 && xdt == FKGP_F64)) {
+            set_error("vector dtype must be the stats dtype or FKGP_F64");
+            return FKGP_EINVAL;
+        }
+        return spmv_dia_any(h->g, h->dt, xdt, h->A, xpad, u, k, dia_halo(h->g), nullptr,
+                            static_cast<hipStream_t>(stream));
     });
 }
 

@@ -21,6 +21,20 @@ struct GridDev {
 
 constexpr int kMaxProbes = 31;
 
+// Storage of W^T W: row-tiled stencil-diagonal layout [tile][o][kRowTile],
+// tile = j / kRowTile, so the entries one workgroup of the banded product
+// needs (kRowTile rows x 7^d offsets) are one contiguous block.  Rows past
+// the last grid node in the final tile are zero.
+constexpr int kRowTile = 256;
+
+__host__ __device__ inline int64_t dia_index(int64_t j, int o, int NB) {
+    return ((j / kRowTile) * NB + o) * kRowTile + (j % kRowTile);
+}
+
+inline int64_t dia_elems(int64_t M, int NB) {
+    return ((M + kRowTile - 1) / kRowTile) * NB * kRowTile;
+}
+
 // ---- error plumbing -------------------------------------------------------
 void set_error(const std::string& msg);
 fkgp_status hip_fail(hipError_t e, const char* what);
@@ -42,7 +56,7 @@ inline hipError_t alloc_async(T** p, size_t count, hipStream_t s) {
 
 // ---- precompute (precompute.hip) -------------------------------------------
 struct StatsOut {
-    void* wtw;          // [7^d][M] in stats dtype (offset-major)
+    void* wtw;          // row-tiled stencil-diagonal layout, stats dtype
     double* wty;        // [M]
     double* sketches;   // [nprobe][M] or null
     double* yty_dev;    // scalar
@@ -86,10 +100,14 @@ fkgp_status spmv_dia_f32a_f64x(const GridDev& g, const void* A, const double* xp
 fkgp_status kg_apply_skip(const GridDev& g, const Spectra& sp, fkgp_dtype dt, const void* x,
                           void* y, int k, double scale, const void* addv, double add_coef,
                           const int* skip, hipStream_t s);
+// dotp (optional, k == 1): per-block partials of sum_j u_j x_j; *nparts gets
+// their count (0 if the path used writes none).
 fkgp_status spmv_dia_any(const GridDev& g, fkgp_dtype dta, fkgp_dtype dtx, const void* A,
                          const void* xpad, void* u, int k, int64_t halo, const int* skip,
-                         hipStream_t s);
+                         hipStream_t s, double* dotp = nullptr, int* nparts = nullptr);
 int64_t dia_halo(const GridDev& g);
+// Upper bound on the dot partials spmv_dia_any writes (one per row tile).
+int64_t spmv_dot_parts(const GridDev& g);
 
 fkgp_status interpolate_points(const GridDev& g, const double* mu,
                                const void* const* xq, int64_t nq,

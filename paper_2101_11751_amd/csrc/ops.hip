@@ -67,12 +67,17 @@ __global__ __launch_bounds__(kLineBlock) void line_conv(
     constexpr int G = L >= 64 ? 1 : 64 / L;   // pairs per wave per round
     if (skip && *skip) return;
     extern __shared__ unsigned char lds_raw[];
-    T* lds = reinterpret_cast<T*>(lds_raw);
+    // LDS: twiddles (L/2 complex), spectrum (L), then the line block
+    cplx<T>* tws = reinterpret_cast<cplx<T>*>(lds_raw);
+    T* lams = reinterpret_cast<T*>(tws + L / 2);
+    T* lds = lams + L;
     const int ms = lg.m_line + 1;   // padded LDS row
     const int64_t l0 = (int64_t)blockIdx.x * LB;
     const int nvalid = (int)min((int64_t)LB, lg.nlines - l0);
     const int tid = threadIdx.x;
     const int tot = LB * lg.m_line;
+    for (int i = tid; i < L / 2; i += kLineBlock) tws[i] = tw[i];
+    for (int i = tid; i < L; i += kLineBlock) lams[i] = lam_br[i];
     // ---- load (LDS transpose for strided lines) ----
     if (lg.S == 1) {
         for (int idx = tid; idx < tot; idx += kLineBlock) {
@@ -118,14 +123,14 @@ __global__ __launch_bounds__(kLineBlock) void line_conv(
                 for (int r = 0; r < R; ++r) {
                     if (r & rs) continue;
                     const int e = r * 64 + e_lane;
-                    const cplx<T> w = tw[(e & (S - 1)) * (L / (2 * S))];
+                    const cplx<T> w = tws[(e & (S - 1)) * (L / (2 * S))];
                     const cplx<T> a = z[r], b = z[r + rs];
                     z[r] = {a.re + b.re, a.im + b.im};
                     z[r + rs] = cmul(cplx<T>{a.re - b.re, a.im - b.im}, w);
                 }
             } else {
                 const bool upper = (e_lane & S) != 0;
-                const cplx<T> w = tw[(e_lane & (S - 1)) * (L / (2 * S))];
+                const cplx<T> w = tws[(e_lane & (S - 1)) * (L / (2 * S))];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     cplx<T> p;
@@ -140,7 +145,7 @@ __global__ __launch_bounds__(kLineBlock) void line_conv(
         // spectrum (bit-reversed order, includes 1/L)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const T lmb = lam_br[r * 64 + e_lane];
+            const T lmb = lams[r * 64 + e_lane];
             z[r].re *= lmb;
             z[r].im *= lmb;
         }
@@ -154,7 +159,7 @@ __global__ __launch_bounds__(kLineBlock) void line_conv(
                 for (int r = 0; r < R; ++r) {
                     if (r & rs) continue;
                     const int e = r * 64 + e_lane;
-                    const cplx<T> w = tw[(e & (S - 1)) * (L / (2 * S))];
+                    const cplx<T> w = tws[(e & (S - 1)) * (L / (2 * S))];
                     const cplx<T> a = z[r];
                     const cplx<T> b = cmul_conj(z[r + rs], w);
                     z[r] = {a.re + b.re, a.im + b.im};
@@ -162,7 +167,7 @@ __global__ __launch_bounds__(kLineBlock) void line_conv(
                 }
             } else {
                 const bool upper = (e_lane & S) != 0;
-                const cplx<T> w = tw[(e_lane & (S - 1)) * (L / (2 * S))];
+                const cplx<T> w = tws[(e_lane & (S - 1)) * (L / (2 * S))];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     cplx<T> p;
@@ -213,13 +218,19 @@ template <class T>
 fkgp_status launch_line_conv(int log2L, const T* in, T* out, const LineGeom& lg,
                              const T* lam, const cplx<T>* tw, T scale, const T* addv,
                              T add_coef, const int* skip, hipStream_t s) {
-    // lines per block: fill ~48 KiB of LDS, even, at most 64
+    // lines per block: enough blocks to cover the chip (>= ~2 per CU), at
+    // least 8 lines for strided dimensions (64-byte coalesced rows), at most
+    // what fits in 48 KiB of LDS; even.
     const int64_t row = (int64_t)(lg.m_line + 1) * sizeof(T);
-    int LB = (int)std::min<int64_t>(64, std::max<int64_t>(2, (48 * 1024) / row));
-    LB &= ~1;
+    int64_t lb = lg.nlines / 512;
+    lb = std::max<int64_t>(lb, lg.S == 1 ? 2 : 8);
+    lb = std::min<int64_t>(lb, 64);
+    const int64_t budget = 60 * 1024 - (int64_t)(2 << log2L) * (int64_t)sizeof(T);
+    lb = std::min<int64_t>(lb, std::max<int64_t>(2, budget / row));
+    int LB = (int)lb & ~1;
     if (LB > lg.nlines + (lg.nlines & 1)) LB = (int)(lg.nlines + (lg.nlines & 1));
     if (LB < 2) LB = 2;
-    const size_t lds = (size_t)LB * row;
+    const size_t lds = (size_t)LB * row + (size_t)(2 << log2L) * sizeof(T);
     const unsigned grid = (unsigned)((lg.nlines + LB - 1) / LB);
 #define FKGP_LC(LG)                                                                       \
     case LG:                                                                              \
@@ -305,6 +316,7 @@ __global__ __launch_bounds__(256) void spmv_dia_kernel(const TA* __restrict__ A,
 #pragma unroll
     for (int r = 0; r < K; ++r) acc[r] = T(0);
     const T* xj = xpad + halo + j;
+    const int NB = dg.ext[0] * dg.ext[1] * dg.ext[2];
     int oi = 0;
     for (int a = 0; a < dg.ext[0]; ++a) {
         const int64_t oa = (dg.ext[0] == 7 ? (a - 3) : 0) * dg.stride[0];
@@ -314,7 +326,7 @@ __global__ __launch_bounds__(256) void spmv_dia_kernel(const TA* __restrict__ A,
             for (int c = 0; c < 7; ++c) {
                 if (c >= dg.ext[2]) break;
                 const int64_t off = ob + (dg.ext[2] == 7 ? (c - 3) : 0) * dg.stride[2];
-                const T av = (T)A[(int64_t)oi * dg.M + j];
+                const T av = (T)A[dia_index(j, oi, NB)];
 #pragma unroll
                 for (int r = 0; r < K; ++r) acc[r] += av * xj[off + r * ldx];
                 ++oi;
@@ -323,6 +335,99 @@ __global__ __launch_bounds__(256) void spmv_dia_kernel(const TA* __restrict__ A,
     }
 #pragma unroll
     for (int r = 0; r < K; ++r) u[r * dg.M + j] = acc[r];
+}
+
+// LDS-windowed banded product for one vector.  A block owns kTileRows
+// consecutive rows [j0, j0 + kTileRows); the x entries its 7^d offsets touch
+// lie in 7 windows (one per offset of the slowest dimension, 1 window in 1-D)
+// of kTileRows + 2*margin entries, staged once in LDS with coalesced loads.
+// Thread t handles row j0 + t, so every entry load of a wave is one
+// contiguous 64-element segment of a diagonal.  Optionally writes the block's
+// partial of sum_j u_j x_j (the CG inner product u^T r_hat) to dotp.
+constexpr int kTileRows = kRowTile;   // one row per thread
+
+struct TileGeom {
+    int64_t M, halo;
+    int64_t S0;       // stride of the slowest dimension (windows), d >= 2
+    int64_t S1;       // stride of the middle dimension (d == 3)
+    int margin;       // 3*S1 + 3 (d = 3), 3 (d <= 2)
+    int WL;           // window length kTileRows + 2*margin
+};
+
+// Accumulates one row of the product.  The stored tile is zero-padded past
+// the last grid node, so entry loads need no bounds; 49 independent loads
+// (one 7 x 7 slab of offsets) are in flight per step.
+template <class TA, class T, int D>
+__device__ __forceinline__ T tile_row(const TA* __restrict__ Ab, const T* __restrict__ win,
+                                      const TileGeom& tg, int t) {
+    T acc = T(0);
+    if constexpr (D == 1) {
+        TA av[7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) av[c] = Ab[c * kTileRows];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) acc += (T)av[c] * win[tg.margin + t + (c - 3)];
+    } else {
+        constexpr int NA = D == 3 ? 7 : 1;
+#pragma unroll 1
+        for (int a = 0; a < NA; ++a) {
+            TA av[49];
+            const TA* Aa = Ab + a * 49 * kTileRows;
+#pragma unroll
+            for (int q = 0; q < 49; ++q) av[q] = Aa[q * kTileRows];
+#pragma unroll
+            for (int q = 0; q < 49; ++q) {
+                // D = 3: q = (o1, o2) within slab a = o0; D = 2: q = (o0, o1)
+                const int p = q / 7, c = q % 7;
+                const T* w = D == 3 ? win + a * tg.WL + tg.margin + t + (p - 3) * (int)tg.S1
+                                    : win + p * tg.WL + tg.margin + t;
+                acc += (T)av[q] * w[c - 3];
+            }
+        }
+    }
+    return acc;
+}
+
+template <class TA, class T, int D>
+__global__ __launch_bounds__(256) void spmv_tiled_kernel(const TA* __restrict__ A,
+                                                         const T* __restrict__ xpad,
+                                                         T* __restrict__ u, TileGeom tg,
+                                                         double* __restrict__ dotp,
+                                                         const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    extern __shared__ unsigned char lds_raw[];
+    T* win = reinterpret_cast<T*>(lds_raw);
+    constexpr int NW = D >= 2 ? 7 : 1;
+    constexpr int kNB = D == 1 ? 7 : (D == 2 ? 49 : 343);
+    const int64_t j0 = (int64_t)blockIdx.x * kTileRows;
+    const int64_t ldx = tg.M + 2 * tg.halo;
+    // stage the windows
+    for (int w = 0; w < NW; ++w) {
+        const int64_t start = tg.halo + j0 + (D >= 2 ? (int64_t)(w - 3) * tg.S0 : 0) - tg.margin;
+        for (int i = threadIdx.x; i < tg.WL; i += 256) {
+            const int64_t idx = start + i;
+            win[w * tg.WL + i] = idx < ldx ? xpad[idx] : T(0);
+        }
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const T acc = tile_row<TA, T, D>(A + (int64_t)blockIdx.x * kNB * kTileRows + t, win, tg, t);
+    double part = 0.0;
+    const int xc = (D >= 2 ? 3 * tg.WL : 0) + tg.margin + t;
+    if (j0 + t < tg.M) {
+        u[j0 + t] = acc;
+        part = (double)acc * (double)win[xc];
+    }
+    if (dotp) {
+        __shared__ double red[256];
+        red[t] = part;
+        __syncthreads();
+        for (int s2 = 128; s2 > 0; s2 >>= 1) {
+            if (t < s2) red[t] += red[t + s2];
+            __syncthreads();
+        }
+        if (t == 0) dotp[blockIdx.x] = red[0];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -391,7 +496,7 @@ __global__ void dia_to_canonical_kernel(const T* __restrict__ A, T* __restrict__
     for (int r = threadIdx.y; r < 32; r += 8) {
         const int o = o0 + r;
         const int64_t j = j0 + threadIdx.x;
-        tile[r][threadIdx.x] = (o < NB && j < M) ? A[(int64_t)o * M + j] : T(0);
+        tile[r][threadIdx.x] = (o < NB && j < M) ? A[dia_index(j, o, NB)] : T(0);
     }
     __syncthreads();
     for (int r = threadIdx.y; r < 32; r += 8) {
@@ -486,9 +591,57 @@ int64_t dia_halo(const GridDev& g) {
     return h;
 }
 
+int64_t spmv_dot_parts(const GridDev& g) {
+    int64_t M = 1;
+    for (int i = 0; i < g.d; ++i) M *= g.m[i];
+    return (M + kTileRows - 1) / kTileRows;
+}
+
+// Geometry of the windowed kernel; false if its LDS would exceed 96 KiB.
+static bool tile_geom(const GridDev& g, size_t es, TileGeom& tg, size_t& lds) {
+    tg.M = 1;
+    for (int i = 0; i < g.d; ++i) tg.M *= g.m[i];
+    tg.halo = dia_halo(g);
+    tg.S0 = g.d >= 2 ? tg.M / g.m[0] : 0;
+    tg.S1 = g.d == 3 ? g.m[2] : 0;
+    tg.margin = g.d == 3 ? (int)(3 * tg.S1 + 3) : 3;
+    tg.WL = kTileRows + 2 * tg.margin;
+    lds = (size_t)(g.d >= 2 ? 7 : 1) * tg.WL * es;
+    return lds <= 96 * 1024;
+}
+
 template <class TA, class T>
 static fkgp_status spmv_t(const GridDev& g, const TA* A, const T* xpad, T* u, int k,
-                          int64_t halo, const int* skip, hipStream_t s) {
+                          int64_t halo, const int* skip, hipStream_t s, double* dotp = nullptr,
+                          int* nparts = nullptr) {
+    TileGeom tg;
+    size_t lds;
+    if (k == 1 && tile_geom(g, sizeof(T), tg, lds)) {
+        const unsigned grid = (unsigned)((tg.M + kTileRows - 1) / kTileRows);
+        if (g.d == 1) {
+            if (lds > 64 * 1024)
+                FKGP_HIP(hipFuncSetAttribute(
+                    reinterpret_cast<const void*>(&spmv_tiled_kernel<TA, T, 1>),
+                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            spmv_tiled_kernel<TA, T, 1><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip);
+        } else if (g.d == 2) {
+            if (lds > 64 * 1024)
+                FKGP_HIP(hipFuncSetAttribute(
+                    reinterpret_cast<const void*>(&spmv_tiled_kernel<TA, T, 2>),
+                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            spmv_tiled_kernel<TA, T, 2><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip);
+        } else {
+            if (lds > 64 * 1024)
+                FKGP_HIP(hipFuncSetAttribute(
+                    reinterpret_cast<const void*>(&spmv_tiled_kernel<TA, T, 3>),
+                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            spmv_tiled_kernel<TA, T, 3><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip);
+        }
+        if (nparts) *nparts = dotp ? (int)grid : 0;
+        FKGP_HIP(hipGetLastError());
+        return FKGP_OK;
+    }
+    if (nparts) *nparts = 0;
     DiaGeom dg{};
     dg.d = g.d;
     dg.M = 1;
@@ -550,12 +703,19 @@ fkgp_status spmv_dia_skip(const GridDev& g, fkgp_dtype dt, const void* A, const 
 // upcast exactly when the vectors are FP64).
 fkgp_status spmv_dia_any(const GridDev& g, fkgp_dtype dta, fkgp_dtype dtx, const void* A,
                          const void* xpad, void* u, int k, int64_t halo, const int* skip,
-                         hipStream_t s) {
-    if (dta == dtx) return spmv_dia_skip(g, dta, A, xpad, u, k, halo, skip, s);
+                         hipStream_t s, double* dotp, int* nparts) {
+    if (dta == FKGP_F32 && dtx == FKGP_F32)
+        return spmv_t<float, float>(g, static_cast<const float*>(A),
+                                    static_cast<const float*>(xpad), static_cast<float*>(u), k,
+                                    halo, skip, s, dotp, nparts);
+    if (dta == FKGP_F64 && dtx == FKGP_F64)
+        return spmv_t<double, double>(g, static_cast<const double*>(A),
+                                      static_cast<const double*>(xpad), static_cast<double*>(u), k,
+                                      halo, skip, s, dotp, nparts);
     if (dta == FKGP_F32 && dtx == FKGP_F64)
         return spmv_t<float, double>(g, static_cast<const float*>(A),
                                      static_cast<const double*>(xpad), static_cast<double*>(u), k,
-                                     halo, skip, s);
+                                     halo, skip, s, dotp, nparts);
     set_error("unsupported matrix/vector dtype combination");
     return FKGP_EINVAL;
 }

@@ -570,7 +570,8 @@ __global__ void assemble_vec_stage(const double* __restrict__ in, double* __rest
     out[idx] = acc;
 }
 
-// [M][7^d] double -> [7^d][M] in T (LDS-tiled transpose).
+// [M][7^d] double -> row-tiled diagonal layout in T (LDS-tiled transpose);
+// rows past M in the last tile are written as zeros.
 template <class T>
 __global__ void transpose_to_dia(const double* __restrict__ in, T* __restrict__ out, int64_t M,
                                  int NB) {
@@ -586,7 +587,7 @@ __global__ void transpose_to_dia(const double* __restrict__ in, T* __restrict__ 
     for (int r = threadIdx.y; r < 32; r += 8) {
         int o = o0 + r;
         int64_t j = j0 + threadIdx.x;
-        if (o < NB && j < M) out[(int64_t)o * M + j] = (T)tile[threadIdx.x][r];
+        if (o < NB) out[dia_index(j, o, NB)] = (T)tile[threadIdx.x][r];
     }
 }
 
@@ -743,7 +744,8 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
             src = dst;
             dst = (dst == bufA) ? bufB : bufA;
         }
-        dim3 tb(32, 8), tg((unsigned)((M + 31) / 32), (unsigned)((NB + 31) / 32));
+        const int64_t Mpad = (M + kRowTile - 1) / kRowTile * kRowTile;
+        dim3 tb(32, 8), tg((unsigned)(Mpad / 32), (unsigned)((NB + 31) / 32));
         if (stats == FKGP_F32)
             transpose_to_dia<float><<<tg, tb, 0, s>>>(src, static_cast<float*>(out.wtw), M, NB);
         else

@@ -193,3 +193,40 @@ def test_solve_errors():
         P.solve(h, {"lengthscale": [0.1], "outputscale": 1.0, "noise": 0.0})
     out, info = P.solve(h, HYP[1], tol=1e-14, maxiter=2)
     assert info["status"] == P.ENOTCONV and info["iterations"] == 2
+
+
+@pytest.mark.parametrize("d,m", [(1, [1000]), (2, [37, 29]), (2, [256, 250]), (3, [14, 11, 9]),
+                                 (3, [100, 20, 30])])
+@pytest.mark.parametrize("xdt", ["stats", "f64"])
+def test_wtw_matvec_tiled_parity(d, m, xdt):
+    """Banded product (tiled kernel for one vector; several tiles and a ragged
+    last tile), FP32-stored entries with FP32 or FP64 vectors."""
+    _need_gpu()
+    grid, X, y = make_case(d, 30000, 21, m=m)
+    xs, yt = to_dev(X, y)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float32)
+    wtw_o, _, _ = oracle.precompute(grid, X, y)
+    v = np.random.default_rng(5).standard_normal(h.m_total)
+    dt = torch.float64 if xdt == "f64" else None
+    u = P.wtw_matvec(h, torch.from_numpy(v).cuda(), dt).cpu().numpy()
+    # The rows are 7^d-term sums with cancellation, so the bound is the
+    # standard dot-product bound n_terms * eps * (|A| |x|) per row, plus one
+    # FP32 ulp of |A| |x|: the stored FP32 entries are rounded from the GPU's
+    # own FP64 moments and may sit one FP32 ulp from the rounded oracle values.
+    w32 = wtw_o.astype(np.float32).astype(np.float64)
+    eps = 2.0 ** -52 if xdt == "f64" else 2.0 ** -23
+    nt = 7 ** d
+
+    def check(uv, vv):
+        vr = vv if xdt == "f64" else vv.astype(np.float32).astype(np.float64)
+        ref = oracle.wtw_matvec(grid, w32, vr)
+        absax = oracle.wtw_matvec(grid, np.abs(w32), np.abs(vr))
+        bound = (2 * nt * eps + 2.0 ** -23) * absax + 1e-300
+        assert np.all(np.abs(uv - ref) <= bound), float(np.max(np.abs(uv - ref) / bound))
+
+    check(u, v)
+    # several vectors at once (untiled multi-vector kernel)
+    V = np.random.default_rng(6).standard_normal((3, h.m_total))
+    U = P.wtw_matvec(h, torch.from_numpy(V).cuda(), dt).cpu().numpy()
+    for r in range(3):
+        check(U[r], V[r])
