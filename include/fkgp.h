@@ -75,7 +75,7 @@ typedef struct {
                                 B(x) = ((K_G W^T W + s2 I)x, W^T W x); FP32
                                 or FP64.  CG vectors and scalars are FP64. */
     int n_probes;            /* Rademacher probe sketches W^T z_j to build
-                                (0..64, d <= 2), for fkgp_mll_and_grad */
+                                (0..31, d <= 2), for fkgp_mll_and_grad */
     uint64_t probe_seed;     /* z_j[i] = 1 - 2*(SplitMix64((seed<<48) ^
                                 (j<<40) ^ i) >> 63) */
 } fkgp_precompute_opts;
@@ -160,9 +160,14 @@ fkgp_status fkgp_solve(const fkgp_handle* h, const fkgp_hypers* hyp,
                        void* stream);
 
 typedef struct {
-    int lanczos_steps;  /* tridiagonal size used for each probe (<= iters) */
+    int lanczos_steps;  /* tridiagonal size used for each probe (<= iters,
+                           at most 64) */
     double tol;         /* relative residual for the y and probe solves */
     int maxiter;
+    int batched;        /* 1: all probes advance together (one W^T W read per
+                           iteration for every probe); 0: one probe at a time.
+                           Operator arithmetic is FP64 either way (on the
+                           stored W^T W, FP32 entries upcast exactly). */
 } fkgp_mll_opts;
 
 typedef struct {

@@ -74,7 +74,7 @@ class _SolveInfo(ctypes.Structure):
 
 class _MllOpts(ctypes.Structure):
     _fields_ = [("lanczos_steps", ctypes.c_int), ("tol", ctypes.c_double),
-                ("maxiter", ctypes.c_int)]
+                ("maxiter", ctypes.c_int), ("batched", ctypes.c_int)]
 
 
 class _MllInfo(ctypes.Structure):
@@ -319,15 +319,16 @@ def wtw_matvec(h, x, dtype=None):
     return u[0] if squeeze else u
 
 
-def mll_and_grad(h, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000):
-    """(mll, grad [d+2] w.r.t. (log l_k, log s, log sigma), info)."""
+def mll_and_grad(h, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000, batched=True):
+    """(mll, grad [d+2] w.r.t. (log l_k, log s, log sigma), info).  batched:
+    all probes advance together (one W^T W read per iteration)."""
     L = load_library()
     mll = ctypes.c_double()
     grad = (ctypes.c_double * (h.d + 2))()
     info = _MllInfo()
     st = _check(L.fkgp_mll_and_grad(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)),
                                     ctypes.byref(_MllOpts(int(lanczos_steps), float(tol),
-                                                          int(maxiter))),
+                                                          int(maxiter), int(bool(batched)))),
                                     ctypes.byref(mll), grad, ctypes.byref(info), _stream()))
     return mll.value, [grad[i] for i in range(h.d + 2)], {
         "logdet": info.logdet, "quad": info.quad, "iterations_y": info.iterations_y,

@@ -1029,10 +1029,533 @@ void fkgp_destroy(fkgp_handle* h) {
 
 }  // extern "C"
 
+// ===========================================================================
+// Log marginal likelihood and gradient.
+//
+// logdet(A), A = W K_G W^T + s2 I, by stochastic Lanczos quadrature: for each
+// Rademacher probe z_j the factorized CG from x_0 = 0 (Claims 3 and 4; the
+// iterates are r = W r_hat + c_r z_j, p = W p_hat + c_p z_j, x = W x_hat +
+// c_x z_j and only W^T z_j, ||z_j||^2 = n enter) gives CG coefficients whose
+// Lanczos tridiagonal T_j yields ||z_j||^2 e_1^T log(T_j) e_1.  The same probe
+// solves x_j = A^{-1} z_j give the Hutchinson trace of the gradient
+//   g_theta = 1/2 [ x_y^T dA x_y - (1/N) sum_j x_j^T dA z_j ],
+// where x^T (W dK W^T) z = (W^T x)^T dK (W^T z) and dA/dlog sigma = 2 s2 I.
+// ===========================================================================
+namespace fkgp {
+namespace {
+
+constexpr int kMaxLanczos = 64;
+
+struct PState {
+    double rho, cr, cp, cx, pb, alpha, beta, eps;
+    int done, iters;
+};
+
+__global__ void probe_init(PState* ps, int N, double n, double tol) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    PState s{};
+    s.rho = n;
+    s.cr = 1.0;
+    s.cp = 1.0;
+    s.eps = tol * tol * n;
+    s.done = n > 0 ? 0 : 1;
+    ps[j] = s;
+}
+
+// ap = z_p + c_p kappa_b (compressed A p); partials of s_p.ap and ap.b_hat
+__global__ __launch_bounds__(kRedBlock) void probe_ap(const PState* __restrict__ ps,
+                                                      const double* __restrict__ zp,
+                                                      const double* __restrict__ kb,
+                                                      const double* __restrict__ sp,
+                                                      const double* __restrict__ bh,
+                                                      double* __restrict__ ap, int64_t M,
+                                                      double* __restrict__ partials) {
+    const int j = blockIdx.y;
+    if (ps[j].done) return;
+    __shared__ double sh[kRedBlock];
+    const double cp = ps[j].cp;
+    const int64_t o = (int64_t)j * M;
+    double d1 = 0.0, d2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * kRedBlock) {
+        const double a = fma(cp, kb[o + i], zp[o + i]);
+        ap[o + i] = a;
+        d1 = fma(sp[o + i], a, d1);
+        d2 = fma(a, bh[o + i], d2);
+    }
+    const double t1 = block_sum(d1, sh);
+    const double t2 = block_sum(d2, sh);
+    if (threadIdx.x == 0) {
+        partials[((int64_t)j * gridDim.x + blockIdx.x) * 2] = t1;
+        partials[((int64_t)j * gridDim.x + blockIdx.x) * 2 + 1] = t2;
+    }
+}
+
+__device__ inline void sum_pairs(const double* partials, int j, int nbv, double* sh, double& a,
+                                 double& b) {
+    double x = 0.0, y = 0.0;
+    for (int i = threadIdx.x; i < nbv; i += kRedBlock) {
+        x += partials[((int64_t)j * nbv + i) * 2];
+        y += partials[((int64_t)j * nbv + i) * 2 + 1];
+    }
+    a = block_sum(x, sh);
+    b = block_sum(y, sh);
+}
+
+// alpha = rho / <p, A p> (Claim 4), scalar updates of x and r.
+__global__ __launch_bounds__(kRedBlock) void probe_fin_ap(PState* ps,
+                                                          const double* __restrict__ partials,
+                                                          int nbv, double s2, double n,
+                                                          double* __restrict__ alphas) {
+    const int j = blockIdx.x;
+    if (ps[j].done) return;
+    __shared__ double sh[kRedBlock];
+    double d1, d2;
+    sum_pairs(partials, j, nbv, sh, d1, d2);
+    if (threadIdx.x != 0) return;
+    PState s = ps[j];
+    const double apc = s2 * s.cp;
+    const double pap = d1 + apc * s.pb + s.cp * d2 + s.cp * apc * n;
+    const double alpha = s.rho / pap;
+    if (!isfinite(alpha)) {
+        ps[j].done = 2;
+        return;
+    }
+    if (s.iters < kMaxLanczos) alphas[j * kMaxLanczos + s.iters] = alpha;
+    s.alpha = alpha;
+    s.cx += alpha * s.cp;
+    s.cr -= alpha * apc;
+    ps[j] = s;
+}
+
+// u_x += alpha s_p; r_hat -= alpha ap; rpad = r_hat
+__global__ void probe_upd_r(const PState* __restrict__ ps, double* __restrict__ ux,
+                            const double* __restrict__ sp, double* __restrict__ rh,
+                            const double* __restrict__ ap, double* __restrict__ rpad, int64_t M,
+                            int64_t ldx, int64_t halo) {
+    const int j = blockIdx.y;
+    if (ps[j].done) return;
+    const double a = ps[j].alpha;
+    const int64_t o = (int64_t)j * M;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        ux[o + i] = fma(a, sp[o + i], ux[o + i]);
+        const double r = fma(-a, ap[o + i], rh[o + i]);
+        rh[o + i] = r;
+        rpad[(int64_t)j * ldx + halo + i] = r;
+    }
+}
+
+// partials of r_hat.u_r and r_hat.b_hat
+__global__ __launch_bounds__(kRedBlock) void probe_dot_r(const PState* __restrict__ ps,
+                                                         const double* __restrict__ rh,
+                                                         const double* __restrict__ ur,
+                                                         const double* __restrict__ bh,
+                                                         int64_t M,
+                                                         double* __restrict__ partials) {
+    const int j = blockIdx.y;
+    if (ps[j].done) return;
+    __shared__ double sh[kRedBlock];
+    const int64_t o = (int64_t)j * M;
+    double d1 = 0.0, d2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * kRedBlock) {
+        d1 = fma(rh[o + i], ur[o + i], d1);
+        d2 = fma(rh[o + i], bh[o + i], d2);
+    }
+    const double t1 = block_sum(d1, sh);
+    const double t2 = block_sum(d2, sh);
+    if (threadIdx.x == 0) {
+        partials[((int64_t)j * gridDim.x + blockIdx.x) * 2] = t1;
+        partials[((int64_t)j * gridDim.x + blockIdx.x) * 2 + 1] = t2;
+    }
+}
+
+// rho' = <r, r> (Claim 4); stop test; beta and the scalar parts of p.
+__global__ __launch_bounds__(kRedBlock) void probe_fin_r(PState* ps,
+                                                         const double* __restrict__ partials,
+                                                         int nbv, double n,
+                                                         double* __restrict__ betas) {
+    const int j = blockIdx.x;
+    if (ps[j].done) return;
+    __shared__ double sh[kRedBlock];
+    double d1, d2;
+    sum_pairs(partials, j, nbv, sh, d1, d2);
+    if (threadIdx.x != 0) return;
+    PState s = ps[j];
+    const double rho_new = d1 + 2.0 * s.cr * d2 + s.cr * s.cr * n;
+    s.iters += 1;
+    if (!(rho_new > s.eps)) {
+        s.done = 1;
+        s.rho = rho_new;
+        ps[j] = s;
+        return;
+    }
+    const double beta = rho_new / s.rho;
+    if (s.iters - 1 < kMaxLanczos) betas[j * kMaxLanczos + s.iters - 1] = beta;
+    s.beta = beta;
+    s.rho = rho_new;
+    s.pb = d2 + beta * s.pb;
+    s.cp = s.cr + beta * s.cp;
+    ps[j] = s;
+}
+
+// s_p = u_r + beta s_p; z_p = v_r + beta z_p
+__global__ void probe_upd_sz(const PState* __restrict__ ps, double* __restrict__ sp,
+                             double* __restrict__ zp, const double* __restrict__ ur,
+                             const double* __restrict__ vr, int64_t M) {
+    const int j = blockIdx.y;
+    if (ps[j].done) return;
+    const double b = ps[j].beta;
+    const int64_t o = (int64_t)j * M;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        sp[o + i] = fma(b, sp[o + i], ur[o + i]);
+        zp[o + i] = fma(b, zp[o + i], vr[o + i]);
+    }
+}
+
+// W^T x_j = u_x + c_x b_hat
+__global__ void probe_wtx(const PState* __restrict__ ps, const double* __restrict__ ux,
+                          const double* __restrict__ bh, double* __restrict__ out, int64_t M) {
+    const int j = blockIdx.y;
+    const double c = ps[j].cx;
+    const int64_t o = (int64_t)j * M;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[o + i] = fma(c, bh[o + i], ux[o + i]);
+}
+
+// e_1^T log(T) e_1 for the Lanczos tridiagonal of CG coefficients
+// (T_ii = 1/alpha_i + beta_{i-1}/alpha_{i-1}, T_{i,i+1} = sqrt(beta_i)/alpha_i)
+// by the implicit symmetric QL iteration with Wilkinson-type shifts, tracking
+// only the first row of the eigenvector matrix (Gauss quadrature weights).
+// One thread per probe, FP64.
+__global__ void lanczos_logdet(const PState* __restrict__ ps, const double* __restrict__ alphas,
+                               const double* __restrict__ betas, int N, int steps,
+                               double* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    int k = min(steps, min(ps[j].iters, kMaxLanczos));
+    double dg[kMaxLanczos], e[kMaxLanczos], q[kMaxLanczos];
+    const double* a = alphas + j * kMaxLanczos;
+    const double* b = betas + j * kMaxLanczos;
+    for (int i = 0; i < k; ++i) {
+        dg[i] = 1.0 / a[i] + (i > 0 ? b[i - 1] / a[i - 1] : 0.0);
+        e[i] = (i + 1 < k) ? sqrt(b[i]) / a[i] : 0.0;
+        q[i] = (i == 0) ? 1.0 : 0.0;
+    }
+    bool ok = k > 0;
+    for (int l = 0; l < k && ok; ++l) {
+        int iter = 0;
+        for (;;) {
+            int m = l;
+            for (; m < k - 1; ++m) {
+                const double dd = fabs(dg[m]) + fabs(dg[m + 1]);
+                if (fabs(e[m]) <= 8.9e-16 * dd) break;   // 4 ulp of 1.0
+            }
+            if (m == l) break;
+            if (++iter > 60) {
+                ok = false;
+                break;
+            }
+            double g = (dg[l + 1] - dg[l]) / (2.0 * e[l]);
+            double r = hypot(g, 1.0);
+            g = dg[m] - dg[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+            double s = 1.0, c = 1.0, p = 0.0;
+            int i = m - 1;
+            bool deflated = false;
+            for (; i >= l; --i) {
+                const double f = s * e[i];
+                const double bb = c * e[i];
+                r = hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {
+                    dg[i + 1] -= p;
+                    e[m] = 0.0;
+                    deflated = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = dg[i + 1] - p;
+                r = (dg[i] - g) * s + 2.0 * c * bb;
+                p = s * r;
+                dg[i + 1] = g + p;
+                g = c * r - bb;
+                const double fq = q[i + 1];
+                q[i + 1] = s * q[i] + c * fq;
+                q[i] = c * q[i] - s * fq;
+            }
+            if (deflated) continue;
+            dg[l] -= p;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+    double acc = 0.0;
+    for (int i = 0; i < k; ++i) acc += q[i] * q[i] * log(dg[i]);
+    out[j] = ok ? acc : NAN;
+}
+
+// dots[r] = A[r] . B[r] for k pairs of FP64 vectors of length M.
+__global__ __launch_bounds__(kRedBlock) void batched_dot(const double* __restrict__ A,
+                                                         const double* __restrict__ B,
+                                                         int64_t M, double* __restrict__ partials) {
+    __shared__ double sh[kRedBlock];
+    const int64_t o = (int64_t)blockIdx.y * M;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * kRedBlock)
+        acc = fma(A[o + i], B[o + i], acc);
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kRedBlock) void batched_dot_fin(const double* __restrict__ partials,
+                                                             int nbv, double* __restrict__ out) {
+    __shared__ double sh[kRedBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nbv; i += kRedBlock)
+        acc += partials[(int64_t)blockIdx.x * nbv + i];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+int vec_blocks(int64_t M) {
+    int64_t b = (M + 4 * kRedBlock - 1) / (4 * kRedBlock);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 256));
+}
+
+fkgp_status dots_dev(const double* A, const double* B, int64_t M, int k, double* partials,
+                     double* out, hipStream_t st) {
+    const int nbv = vec_blocks(M);
+    batched_dot<<<dim3(nbv, k), kRedBlock, 0, st>>>(A, B, M, partials);
+    batched_dot_fin<<<k, kRedBlock, 0, st>>>(partials, nbv, out);
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+// Factorized CG from x_0 = 0 for N probes at once (sketches bh [N][M]).
+// Outputs W^T x_j (wx [N][M]), the CG coefficients and the final states.
+fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double tol,
+                     int maxiter, double* wx, double* alphas, double* betas, PState* ps,
+                     Scratch& sc, hipStream_t st, int& iters_max) {
+    const fkgp_handle* h = c.h;
+    const int64_t M = c.M;
+    const int64_t ldx = M + 2 * c.halo;
+    double *kb, *ap, *sp, *zp, *ux, *rh, *rpad, *ur, *vr, *partials;
+    FKGP_HIP(sc.get(&kb, M * N));
+    FKGP_HIP(sc.get(&ap, M * N));
+    FKGP_HIP(sc.get(&sp, M * N));
+    FKGP_HIP(sc.get(&zp, M * N));
+    FKGP_HIP(sc.get(&ux, M * N));
+    FKGP_HIP(sc.get(&rh, M * N));
+    FKGP_HIP(sc.get(&ur, M * N));
+    FKGP_HIP(sc.get(&vr, M * N));
+    FKGP_HIP(sc.get(&rpad, ldx * N));
+    const int nbv = vec_blocks(M);
+    FKGP_HIP(sc.get(&partials, (size_t)2 * nbv * N));
+    for (double* v : {sp, zp, ux, rh})
+        FKGP_HIP(hipMemsetAsync(v, 0, sizeof(double) * M * N, st));
+    FKGP_HIP(hipMemsetAsync(rpad, 0, sizeof(double) * ldx * N, st));
+    // kappa_b = K_G W^T z_j (FP64)
+    fkgp_status rs = kg_apply(h->g, c.sp64, FKGP_F64, bh, kb, N, c.so, nullptr, 0.0, nullptr, st);
+    if (rs != FKGP_OK) return rs;
+    probe_init<<<(N + 63) / 64, 64, 0, st>>>(ps, N, n, tol);
+    FKGP_HIP(hipGetLastError());
+    const dim3 gv(nbv, N);
+    const dim3 ge((unsigned)std::min<int64_t>((M + 255) / 256, 1024), N);
+    std::vector<PState> hs(N);
+    int launched = 0;
+    constexpr int kBatch = 8;
+    for (;;) {
+        FKGP_HIP(hipMemcpyAsync(hs.data(), ps, sizeof(PState) * N, hipMemcpyDeviceToHost, st));
+        FKGP_HIP(hipStreamSynchronize(st));
+        bool all = true;
+        for (int j = 0; j < N; ++j) all &= hs[j].done != 0;
+        if (all || launched >= maxiter) break;
+        const int nit = std::min(kBatch, maxiter - launched);
+        for (int it = 0; it < nit; ++it) {
+            probe_ap<<<gv, kRedBlock, 0, st>>>(ps, zp, kb, sp, bh, ap, M, partials);
+            probe_fin_ap<<<N, kRedBlock, 0, st>>>(ps, partials, nbv, c.s2, n, alphas);
+            probe_upd_r<<<ge, 256, 0, st>>>(ps, ux, sp, rh, ap, rpad, M, ldx, c.halo);
+            FKGP_HIP(hipGetLastError());
+            rs = spmv_dia_any(h->g, h->dt, FKGP_F64, h->A, rpad, ur, N, c.halo, nullptr, st);
+            if (rs != FKGP_OK) return rs;
+            rs = kg_apply(h->g, c.sp64, FKGP_F64, ur, vr, N, c.so, rh, c.s2, nullptr, st);
+            if (rs != FKGP_OK) return rs;
+            probe_dot_r<<<gv, kRedBlock, 0, st>>>(ps, rh, ur, bh, M, partials);
+            probe_fin_r<<<N, kRedBlock, 0, st>>>(ps, partials, nbv, n, betas);
+            probe_upd_sz<<<ge, 256, 0, st>>>(ps, sp, zp, ur, vr, M);
+            FKGP_HIP(hipGetLastError());
+        }
+        launched += nit;
+    }
+    iters_max = 0;
+    for (int j = 0; j < N; ++j) {
+        iters_max = std::max(iters_max, hs[j].iters);
+        if (hs[j].done == 2) {
+            set_error("probe CG broke down (non-finite step)");
+            return FKGP_EDEVICE;
+        }
+    }
+    probe_wtx<<<ge, 256, 0, st>>>(ps, ux, bh, wx, M);
+    FKGP_HIP(hipGetLastError());
+    bool conv = true;
+    for (int j = 0; j < N; ++j) conv &= hs[j].done == 1;
+    return conv ? FKGP_OK : FKGP_ENOTCONV;
+}
+
+fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_mll_opts& o,
+                     double* mll, double* grad, fkgp_mll_info* info, hipStream_t st) {
+    Scratch sc(st);
+    OpCtx c;
+    fkgp_status rs = make_ctx(h, hyp, FKGP_F64, c, sc);
+    if (rs != FKGP_OK) return rs;
+    const int d = h->g.d;
+    const int N = h->nprobe;
+    const int64_t M = h->M;
+    const double n = (double)h->n;
+    // 1. mean solve: w_y = W^T z~, mu = K_G w_y
+    double *V, *DV, *wx, *mu, *Amu, *pad64, *dotp, *dots, *alphas, *betas, *ld;
+    PState* ps;
+    FKGP_HIP(sc.get(&V, M * (N + 1)));       // [w_y, b_hat_0 .. b_hat_{N-1}]
+    FKGP_HIP(sc.get(&DV, M * (N + 1)));
+    FKGP_HIP(sc.get(&wx, M * (N + 1)));      // [w_y, W^T x_0 .. W^T x_{N-1}]
+    FKGP_HIP(sc.get(&mu, M));
+    FKGP_HIP(sc.get(&Amu, M));
+    FKGP_HIP(sc.get(&pad64, M + 2 * c.halo));
+    FKGP_HIP(sc.get(&dotp, (size_t)vec_blocks(M) * (N + 1) * 2));
+    FKGP_HIP(sc.get(&dots, 4 * (N + 1)));
+    FKGP_HIP(sc.get(&alphas, (size_t)kMaxLanczos * N));
+    FKGP_HIP(sc.get(&betas, (size_t)kMaxLanczos * N));
+    FKGP_HIP(sc.get(&ld, N));
+    FKGP_HIP(sc.get(&ps, N));
+    fkgp_solve_info sinfo{};
+    fkgp_status sres = solve_core(c, nullptr, o.tol, o.maxiter, V, &sinfo, sc, st);
+    if (sres != FKGP_OK && sres != FKGP_ENOTCONV) return sres;
+    FKGP_HIP(hipMemcpyAsync(wx, V, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+    FKGP_HIP(hipMemcpyAsync(V + M, h->sketches, sizeof(double) * M * N, hipMemcpyDeviceToDevice, st));
+    rs = kg_apply(h->g, c.sp64, FKGP_F64, V, mu, 1, c.so, nullptr, 0.0, nullptr, st);
+    if (rs != FKGP_OK) return rs;
+    // 2. probe solves (batched, or one probe at a time)
+    int iters_max = 0;
+    fkgp_status pres = FKGP_OK;
+    if (o.batched) {
+        pres = probe_cg(c, V + M, N, n, o.tol, o.maxiter, wx + M, alphas, betas, ps, sc, st,
+                        iters_max);
+    } else {
+        for (int j = 0; j < N && (pres == FKGP_OK || pres == FKGP_ENOTCONV); ++j) {
+            int it = 0;
+            Scratch sj(st);
+            fkgp_status r1 = probe_cg(c, V + M * (1 + j), 1, n, o.tol, o.maxiter,
+                                      wx + M * (1 + j), alphas + kMaxLanczos * j,
+                                      betas + kMaxLanczos * j, ps + j, sj, st, it);
+            if (r1 != FKGP_OK) pres = r1;
+            iters_max = std::max(iters_max, it);
+        }
+    }
+    if (pres != FKGP_OK && pres != FKGP_ENOTCONV) return pres;
+    lanczos_logdet<<<(N + 63) / 64, 64, 0, st>>>(ps, alphas, betas, N, o.lanczos_steps, ld);
+    FKGP_HIP(hipGetLastError());
+    // 3. scalars: q, ||z~||^2 pieces
+    // dots: [0] wty.mu  [1] mu.(A mu)
+    FKGP_HIP(hipMemsetAsync(pad64, 0, sizeof(double) * (M + 2 * c.halo), st));
+    FKGP_HIP(hipMemcpyAsync(pad64 + c.halo, mu, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+    rs = apply_B64(c, pad64, Amu, nullptr, st);
+    if (rs != FKGP_OK) return rs;
+    rs = dots_dev(h->wty, mu, M, 1, dotp, dots, st);
+    if (rs != FKGP_OK) return rs;
+    rs = dots_dev(mu, Amu, M, 1, dotp, dots + 1, st);
+    if (rs != FKGP_OK) return rs;
+    std::vector<double> hv(2), hld(N);
+    FKGP_HIP(hipMemcpyAsync(hv.data(), dots, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipMemcpyAsync(hld.data(), ld, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    // 4. gradient terms: for theta = log l_k (k < d) and log s (k = d):
+    //    DV = dK_theta [w_y, b_hat_j]; quad = w_y.DV_0; tr_j = W^T x_j . DV_j
+    std::vector<double> quad(d + 1), tr(d + 1);
+    std::vector<double> hd(N + 1);
+    for (int th = 0; th <= d; ++th) {
+        Scratch sth(st);
+        Spectra dsp;
+        rs = make_spectra(h, hyp, FKGP_F64, th < d ? th : -1, dsp, sth);
+        if (rs != FKGP_OK) return rs;
+        rs = kg_apply(h->g, dsp, FKGP_F64, V, DV, N + 1, c.so, nullptr, 0.0, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+        rs = dots_dev(wx, DV, M, N + 1, dotp, dots + 2, st);
+        if (rs != FKGP_OK) return rs;
+        FKGP_HIP(hipMemcpyAsync(hd.data(), dots + 2, sizeof(double) * (N + 1),
+                                hipMemcpyDeviceToHost, st));
+        FKGP_HIP(hipStreamSynchronize(st));
+        quad[th] = hd[0];
+        double acc = 0.0;
+        for (int j = 0; j < N; ++j) acc += hd[1 + j];
+        tr[th] = acc / N;
+    }
+    // sigma: x_j^T z_j = (n - b_hat_j . K_G W^T x_j) / s2
+    rs = kg_apply(h->g, c.sp64, FKGP_F64, wx + M, DV + M, N, c.so, nullptr, 0.0, nullptr, st);
+    if (rs != FKGP_OK) return rs;
+    rs = dots_dev(V + M, DV + M, M, N, dotp, dots + 2, st);
+    if (rs != FKGP_OK) return rs;
+    FKGP_HIP(hipMemcpyAsync(hd.data(), dots + 2, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipStreamSynchronize(st));
+    const double s2 = c.s2;
+    const double yty = h->yty;
+    const double q = (yty - hv[0]) / s2;
+    const double zz = (yty - 2.0 * hv[0] + hv[1]) / (s2 * s2);
+    double logdet = 0.0;
+    for (int j = 0; j < N; ++j) logdet += n * hld[j];
+    logdet /= N;
+    double trs = 0.0;
+    for (int j = 0; j < N; ++j) trs += (n - hd[j]) / s2;
+    trs = 2.0 * s2 * trs / N;
+    *mll = -0.5 * (logdet + q + n * std::log(2.0 * M_PI));
+    for (int th = 0; th <= d; ++th) grad[th] = 0.5 * (quad[th] - tr[th]);
+    grad[d + 1] = 0.5 * (2.0 * s2 * zz - trs);
+    if (info) {
+        info->logdet = logdet;
+        info->quad = q;
+        info->iterations_y = sinfo.iterations;
+        info->iterations_probes_max = iters_max;
+    }
+    if (!std::isfinite(logdet)) {
+        set_error("Lanczos quadrature failed (non-finite log-determinant)");
+        return FKGP_EDEVICE;
+    }
+    return (sres == FKGP_ENOTCONV || pres == FKGP_ENOTCONV) ? FKGP_ENOTCONV : FKGP_OK;
+}
+
+}  // namespace
+}  // namespace fkgp
+
 extern "C" fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers* hyp,
                                          const fkgp_mll_opts* opts, double* mll, double* grad,
                                          fkgp_mll_info* info, void* stream) {
-    (void)h; (void)hyp; (void)opts; (void)mll; (void)grad; (void)info; (void)stream;
-    fkgp::set_error("fkgp_mll_and_grad: not built yet");
-    return FKGP_EINVAL;
+    return guarded([&]() -> fkgp_status {
+        fkgp::set_error("");
+        if (!h || !mll || !grad) {
+            fkgp::set_error("handle, mll and grad must be non-NULL");
+            return FKGP_EINVAL;
+        }
+        fkgp_status st = fkgp::check_hypers(h, hyp);
+        if (st != FKGP_OK) return st;
+        if (h->nprobe <= 0) {
+            fkgp::set_error("the handle has no probe sketches (n_probes = 0 at precompute)");
+            return FKGP_EINVAL;
+        }
+        if (h->n <= 0) {
+            fkgp::set_error("the marginal likelihood needs n > 0");
+            return FKGP_EINVAL;
+        }
+        fkgp_mll_opts o{30, 1e-6, 1000, 1};
+        if (opts) o = *opts;
+        if (o.lanczos_steps < 1 || o.lanczos_steps > fkgp::kMaxLanczos || !(o.tol >= 0.0) ||
+            o.maxiter < 1) {
+            fkgp::set_error("lanczos_steps must be in [1, 64], tol >= 0, maxiter >= 1");
+            return FKGP_EINVAL;
+        }
+        return fkgp::mll_impl(h, hyp, o, mll, grad, info, static_cast<hipStream_t>(stream));
+    });
 }
