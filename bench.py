@@ -25,6 +25,12 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the banded product on this workload, from the two
+# rocprofv3 --pmc runs (FETCH_SIZE x 1.9995, WRITE_SIZE x 1.0, calibrated on a
+# 256 MiB copy) recorded in profiles/radar3d_hbm_traffic_pmc.md.  Set to None
+# whenever spmv_tiled_kernel changes until the counters are taken again.
+SPMV_TRAFFIC_BYTES = 429.6e6
+
 
 def _parse():
     ap = argparse.ArgumentParser()
@@ -37,6 +43,10 @@ def _parse():
     ap.add_argument("--mvm-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-mll", action="store_true")
+    ap.add_argument("--mll-reps", type=int, default=2)
+    ap.add_argument("--mll-tol", type=float, default=1e-2)
+    ap.add_argument("--mll-maxiter", type=int, default=20000)
     return ap.parse_args()
 
 
@@ -79,6 +89,48 @@ def cpu_baseline(wl, n_total, iters, budget_s):
             "precompute_mpts_per_s": n_s / t_pre / 1e6, "mvm_per_s": 1.0 / t_mvm}
 
 
+def mll_compare(P, workloads, torch, dev, reps, tol, maxiter):
+    """MLL + gradient on the differentiation workload (n=4e6, 256x256 grid,
+    16 Rademacher probes, 30 Lanczos steps) at the offset hyperparameters:
+    batched probes on FP32-stored statistics vs one-probe-at-a-time on FP64
+    statistics (the plain FP64 path), both with FP64 CG scalars."""
+    wl = workloads.prior2d(device=dev)
+    torch.cuda.synchronize()
+    hyp = wl["hypers_offset"]
+    out = {}
+    for name, sdt, batched in (("batched_f32", torch.float32, True),
+                               ("plain_f64", torch.float64, False)):
+        h = P.precompute(wl["grid"], wl["x"], wl["y"], stats_dtype=sdt,
+                         n_probes=wl["nprobes"], probe_seed=wl["probe_seed"])
+        P.mll_and_grad(h, hyp, wl["lanczos_steps"], tol, maxiter, batched=batched)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            val, g, info = P.mll_and_grad(h, hyp, wl["lanczos_steps"], tol, maxiter,
+                                          batched=batched)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"s_per_eval": dt, "mll": val, "grad": g, "status": info["status"],
+                     "iterations_y": info["iterations_y"],
+                     "iterations_probes_max": info["iterations_probes_max"]}
+        log(f"mll {name}: {dt:.3f} s/eval, mll={val:.6f}, iters y={info['iterations_y']} "
+            f"probes={info['iterations_probes_max']}")
+        h.close()
+    a, b = out["batched_f32"], out["plain_f64"]
+    import numpy as np
+    gdiff = float(np.max(np.abs(np.array(a["grad"]) - np.array(b["grad"])))
+                  / np.max(np.abs(np.array(b["grad"]))))
+    return {"workload": "prior2d: n=4e6 x~U[0,1]^2, grid 256x256, GSGP-prior y (l=0.04, "
+                        "s=1.5, sigma=0.1), evaluated at l=0.05, s=1.0, sigma=0.15; 16 probes, "
+                        "30 Lanczos steps, tol %g" % tol,
+            "batched_f32_s_per_eval": a["s_per_eval"], "plain_f64_s_per_eval": b["s_per_eval"],
+            "speedup": b["s_per_eval"] / a["s_per_eval"],
+            "mll_rel_diff": abs(a["mll"] - b["mll"]) / abs(b["mll"]), "grad_rel_diff": gdiff,
+            "mll": b["mll"], "grad": b["grad"],
+            "converged": a["status"] == 0 and b["status"] == 0,
+            "iterations_y": b["iterations_y"], "iterations_probes_max": b["iterations_probes_max"]}
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -100,6 +152,13 @@ def main():
     torch.cuda.synchronize()
     grid, hyp = wl["grid"], wl["hypers"]
     n = args.n
+    # plain copy of a known size (256 MiB): the reference for scaling the
+    # FETCH_SIZE / WRITE_SIZE counters of a profiled run
+    calib = torch.empty(64 << 20, device=dev, dtype=torch.float32)
+    calib2 = torch.empty_like(calib)
+    calib2.copy_(calib)
+    torch.cuda.synchronize()
+    del calib, calib2
 
     def step(ev=None):
         if ev is not None:
@@ -178,10 +237,16 @@ def main():
         "cg_iterations": iters_mean,
         "cg_mvms_per_s": iters_mean / t_sol,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": SPMV_TRAFFIC_BYTES,
                      "kernel": "spmv_tiled_kernel<float,double,3> (banded W^T W product)",
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_us": t_spmv * 1e6},
     }
+    if not args.no_mll:
+        del h, mu
+        torch.cuda.empty_cache()
+        mc = mll_compare(P, workloads, torch, dev, args.mll_reps, args.mll_tol, args.mll_maxiter)
+        result["mll_grad_s_per_eval"] = mc["batched_f32_s_per_eval"]
+        result["mll_grad"] = mc
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cb = cpu_baseline(wl, n, iters_mean, args.cpu_seconds)

@@ -1,0 +1,74 @@
+"""CPU-only checks of the C ABI: every function include/fkgp.h declares is
+exported by the built library, host-side argument validation rejects bad
+input before touching a device, and the binding fails loudly without the
+library (no CPU fallback)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2101_11751_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "fkgp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fkgp_[A-Za-z_]+)\s*\(", src)))
+
+
+def test_header_declares_binding_exports():
+    assert set(declared_functions()) == set(P.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(P.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_host_validation_without_device():
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    L = P.load_library()
+    out = ctypes.c_void_p()
+    g = P._Grid()
+    g.d = 0
+    assert L.fkgp_precompute(ctypes.byref(g), None, None, 0, 0, None, None,
+                             ctypes.byref(out)) == P.EINVAL
+    assert b"grid.d" in L.fkgp_last_error()
+    g.d = 2
+    g.m[0], g.m[1] = 3, 10
+    g.spacing[0] = g.spacing[1] = 0.1
+    assert L.fkgp_precompute(ctypes.byref(g), None, None, 0, 0, None, None,
+                             ctypes.byref(out)) == P.EINVAL
+    g.m[0] = 10
+    assert L.fkgp_precompute(ctypes.byref(g), None, None, -5, 0, None, None,
+                             ctypes.byref(out)) == P.EINVAL
+    g.spacing[1] = -1.0
+    assert L.fkgp_precompute(ctypes.byref(g), None, None, 0, 0, None, None,
+                             ctypes.byref(out)) == P.EINVAL
+    g.spacing[1] = 0.1
+    # n > 0 requires pointers
+    assert L.fkgp_precompute(ctypes.byref(g), None, None, 10, 0, None, None,
+                             ctypes.byref(out)) == P.EINVAL
+    # grid lines longer than the line FFT supports
+    g.m[1] = 5000
+    assert L.fkgp_precompute(ctypes.byref(g), None, None, 0, 0, None, None,
+                             ctypes.byref(out)) == P.EINVAL
+    assert L.fkgp_precompute(ctypes.byref(g), None, None, 0, 0, None, None, None) == P.EINVAL
+    d = P._Desc()
+    assert L.fkgp_describe(None, ctypes.byref(d)) == P.EINVAL
+    assert L.fkgp_solve(None, None, None, None, None, None, None) == P.EINVAL
+    assert L.fkgp_mll_and_grad(None, None, None, None, None, None, None) == P.EINVAL
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(P, "_lib", None)
+    monkeypatch.setattr(P, "LIB_PATH", "/nonexistent/libfkgp.so")
+    with pytest.raises(ImportError):
+        P.load_library()
