@@ -188,6 +188,20 @@ fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers* hyp,
                               const fkgp_mll_opts* opts, double* mll,
                               double* grad, fkgp_mll_info* info, void* stream);
 
+/* The same quantities for nprob independent problems (handles with probe
+ * sketches, d <= 2, any mix of sizes) in one persistent launch: every
+ * right-hand side [y, z_0 .. z_{N-1}] of every problem is solved with the
+ * factorized CG from x_0 = 0 (Claims 3 and 4); a workgroup owns one problem
+ * and up to 8 of its right-hand sides and runs their CG to the end, so the
+ * stored W^T W is read once per iteration for all of them.
+ *   hyps: nprob hyperparameter sets; mll: nprob host doubles; grad: nprob x 5
+ *   host doubles (entries d+2 .. 4 of each row are 0); infos: nprob (or
+ *   NULL).  opts->batched is ignored.  Synchronises `stream`. */
+fkgp_status fkgp_batch_mll_and_grad(const fkgp_handle* const* hs, int nprob,
+                                    const fkgp_hypers* hyps, const fkgp_mll_opts* opts,
+                                    double* mll, double* grad, fkgp_mll_info* infos,
+                                    void* stream);
+
 /* out[i] = w_{xq_i}^T mean_grid (Fact 2 mean) for nq query points; xq: d
  * device pointers of dtype `in`; mean_grid, out: device doubles.
  * Returns FKGP_EOUTOFGRID if a query point is not interpolable.

@@ -23,7 +23,7 @@ OK, ENOTCONV, EINVAL, EOUTOFGRID, ENOMEM, EDEVICE = 0, 1, -1, -2, -3, -4
 
 #: every symbol that include/fkgp.h declares
 EXPORTS = ("fkgp_precompute", "fkgp_describe", "fkgp_export_stats", "fkgp_export_sketches",
-           "fkgp_solve", "fkgp_mll_and_grad", "fkgp_interpolate", "fkgp_apply_B",
+           "fkgp_solve", "fkgp_mll_and_grad", "fkgp_batch_mll_and_grad", "fkgp_interpolate", "fkgp_apply_B",
            "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_destroy", "fkgp_last_error")
 
 
@@ -105,6 +105,11 @@ def load_library():
     L.fkgp_mll_and_grad.argtypes = [p, ctypes.POINTER(_Hypers), ctypes.POINTER(_MllOpts),
                                     ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_MllInfo), p]
+    L.fkgp_batch_mll_and_grad.argtypes = [ctypes.POINTER(p), ctypes.c_int,
+                                          ctypes.POINTER(_Hypers), ctypes.POINTER(_MllOpts),
+                                          ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(_MllInfo), p]
     L.fkgp_interpolate.argtypes = [p, p, ctypes.POINTER(p), ctypes.c_int64, ctypes.c_int, p, p]
     L.fkgp_apply_B.argtypes = [p, ctypes.POINTER(_Hypers), p, p, p, ctypes.c_int, p]
     L.fkgp_kg_matvec.argtypes = [p, ctypes.POINTER(_Hypers), p, p, ctypes.c_int, p]
@@ -333,6 +338,28 @@ def mll_and_grad(h, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000, batched=Tr
     return mll.value, [grad[i] for i in range(h.d + 2)], {
         "logdet": info.logdet, "quad": info.quad, "iterations_y": info.iterations_y,
         "iterations_probes_max": info.iterations_probes_max, "status": st}
+
+
+def batch_mll_and_grad(handles, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000):
+    """Many problems in one persistent launch.  Returns (mll list, grad list
+    (d+2 entries each), info list)."""
+    L = load_library()
+    n = len(handles)
+    hs = (ctypes.c_void_p * n)(*[h.ptr for h in handles])
+    hy = (_Hypers * n)(*[_hyp_struct(hypers[i], handles[i].d) for i in range(n)])
+    mll = (ctypes.c_double * n)()
+    grad = (ctypes.c_double * (5 * n))()
+    infos = (_MllInfo * n)()
+    st = _check(L.fkgp_batch_mll_and_grad(hs, n, hy, ctypes.byref(_MllOpts(int(lanczos_steps),
+                                                                           float(tol),
+                                                                           int(maxiter), 1)),
+                                          mll, grad, infos, _stream()))
+    return ([mll[i] for i in range(n)],
+            [[grad[5 * i + k] for k in range(handles[i].d + 2)] for i in range(n)],
+            [{"logdet": infos[i].logdet, "quad": infos[i].quad,
+              "iterations_y": infos[i].iterations_y,
+              "iterations_probes_max": infos[i].iterations_probes_max, "status": st}
+             for i in range(n)])
 
 
 class MarginalLogLikelihood(torch.autograd.Function):

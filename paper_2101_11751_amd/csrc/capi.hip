@@ -1044,13 +1044,6 @@ void fkgp_destroy(fkgp_handle* h) {
 namespace fkgp {
 namespace {
 
-constexpr int kMaxLanczos = 64;
-
-struct PState {
-    double rho, cr, cp, cx, pb, alpha, beta, eps;
-    int done, iters;
-};
-
 __global__ void probe_init(PState* ps, int N, double n, double tol) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
@@ -1408,60 +1401,31 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
     return conv ? FKGP_OK : FKGP_ENOTCONV;
 }
 
-fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_mll_opts& o,
-                     double* mll, double* grad, fkgp_mll_info* info, hipStream_t st) {
-    Scratch sc(st);
-    OpCtx c;
-    fkgp_status rs = make_ctx(h, hyp, FKGP_F64, c, sc);
-    if (rs != FKGP_OK) return rs;
+// MLL and gradient from solved systems: V = [W^T z~, W^T z_0 .. W^T z_{N-1}],
+// wx = [W^T z~, W^T x_0 .. W^T x_{N-1}] (x_j = A^{-1} z_j), the probes' CG
+// coefficients and states.  V and wx are [N+1][M] device buffers.
+fkgp_status mll_post(const OpCtx& c, const fkgp_hypers* hyp, const fkgp_mll_opts& o,
+                     const double* V, const double* wx, const double* alphas,
+                     const double* betas, const PState* ps, double* mll, double* grad,
+                     Scratch& sc, hipStream_t st, double& logdet_out, double& q_out) {
+    const fkgp_handle* h = c.h;
     const int d = h->g.d;
     const int N = h->nprobe;
     const int64_t M = h->M;
     const double n = (double)h->n;
-    // 1. mean solve: w_y = W^T z~, mu = K_G w_y
-    double *V, *DV, *wx, *mu, *Amu, *pad64, *dotp, *dots, *alphas, *betas, *ld;
-    PState* ps;
-    FKGP_HIP(sc.get(&V, M * (N + 1)));       // [w_y, b_hat_0 .. b_hat_{N-1}]
+    double *DV, *mu, *Amu, *pad64, *dotp, *dots, *ld;
     FKGP_HIP(sc.get(&DV, M * (N + 1)));
-    FKGP_HIP(sc.get(&wx, M * (N + 1)));      // [w_y, W^T x_0 .. W^T x_{N-1}]
     FKGP_HIP(sc.get(&mu, M));
     FKGP_HIP(sc.get(&Amu, M));
     FKGP_HIP(sc.get(&pad64, M + 2 * c.halo));
     FKGP_HIP(sc.get(&dotp, (size_t)vec_blocks(M) * (N + 1) * 2));
     FKGP_HIP(sc.get(&dots, 4 * (N + 1)));
-    FKGP_HIP(sc.get(&alphas, (size_t)kMaxLanczos * N));
-    FKGP_HIP(sc.get(&betas, (size_t)kMaxLanczos * N));
     FKGP_HIP(sc.get(&ld, N));
-    FKGP_HIP(sc.get(&ps, N));
-    fkgp_solve_info sinfo{};
-    fkgp_status sres = solve_core(c, nullptr, o.tol, o.maxiter, V, &sinfo, sc, st);
-    if (sres != FKGP_OK && sres != FKGP_ENOTCONV) return sres;
-    FKGP_HIP(hipMemcpyAsync(wx, V, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
-    FKGP_HIP(hipMemcpyAsync(V + M, h->sketches, sizeof(double) * M * N, hipMemcpyDeviceToDevice, st));
-    rs = kg_apply(h->g, c.sp64, FKGP_F64, V, mu, 1, c.so, nullptr, 0.0, nullptr, st);
+    fkgp_status rs = kg_apply(h->g, c.sp64, FKGP_F64, V, mu, 1, c.so, nullptr, 0.0, nullptr, st);
     if (rs != FKGP_OK) return rs;
-    // 2. probe solves (batched, or one probe at a time)
-    int iters_max = 0;
-    fkgp_status pres = FKGP_OK;
-    if (o.batched) {
-        pres = probe_cg(c, V + M, N, n, o.tol, o.maxiter, wx + M, alphas, betas, ps, sc, st,
-                        iters_max);
-    } else {
-        for (int j = 0; j < N && (pres == FKGP_OK || pres == FKGP_ENOTCONV); ++j) {
-            int it = 0;
-            Scratch sj(st);
-            fkgp_status r1 = probe_cg(c, V + M * (1 + j), 1, n, o.tol, o.maxiter,
-                                      wx + M * (1 + j), alphas + kMaxLanczos * j,
-                                      betas + kMaxLanczos * j, ps + j, sj, st, it);
-            if (r1 != FKGP_OK) pres = r1;
-            iters_max = std::max(iters_max, it);
-        }
-    }
-    if (pres != FKGP_OK && pres != FKGP_ENOTCONV) return pres;
     lanczos_logdet<<<(N + 63) / 64, 64, 0, st>>>(ps, alphas, betas, N, o.lanczos_steps, ld);
     FKGP_HIP(hipGetLastError());
-    // 3. scalars: q, ||z~||^2 pieces
-    // dots: [0] wty.mu  [1] mu.(A mu)
+    // y^T A^{-1} y and ||z~||^2 need W^T y . mu and mu . (W^T W mu)
     FKGP_HIP(hipMemsetAsync(pad64, 0, sizeof(double) * (M + 2 * c.halo), st));
     FKGP_HIP(hipMemcpyAsync(pad64 + c.halo, mu, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
     rs = apply_B64(c, pad64, Amu, nullptr, st);
@@ -1473,8 +1437,7 @@ fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_ml
     std::vector<double> hv(2), hld(N);
     FKGP_HIP(hipMemcpyAsync(hv.data(), dots, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
     FKGP_HIP(hipMemcpyAsync(hld.data(), ld, sizeof(double) * N, hipMemcpyDeviceToHost, st));
-    // 4. gradient terms: for theta = log l_k (k < d) and log s (k = d):
-    //    DV = dK_theta [w_y, b_hat_j]; quad = w_y.DV_0; tr_j = W^T x_j . DV_j
+    // theta = log l_k (k < d), log s (k = d): DV = dK [w_y, b_hat_j]
     std::vector<double> quad(d + 1), tr(d + 1);
     std::vector<double> hd(N + 1);
     for (int th = 0; th <= d; ++th) {
@@ -1514,17 +1477,195 @@ fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_ml
     *mll = -0.5 * (logdet + q + n * std::log(2.0 * M_PI));
     for (int th = 0; th <= d; ++th) grad[th] = 0.5 * (quad[th] - tr[th]);
     grad[d + 1] = 0.5 * (2.0 * s2 * zz - trs);
+    logdet_out = logdet;
+    q_out = q;
+    if (!std::isfinite(logdet)) {
+        set_error("Lanczos quadrature failed (non-finite log-determinant)");
+        return FKGP_EDEVICE;
+    }
+    return FKGP_OK;
+}
+
+fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_mll_opts& o,
+                     double* mll, double* grad, fkgp_mll_info* info, hipStream_t st) {
+    Scratch sc(st);
+    OpCtx c;
+    fkgp_status rs = make_ctx(h, hyp, FKGP_F64, c, sc);
+    if (rs != FKGP_OK) return rs;
+    const int N = h->nprobe;
+    const int64_t M = h->M;
+    const double n = (double)h->n;
+    double *V, *wx, *alphas, *betas;
+    PState* ps;
+    FKGP_HIP(sc.get(&V, M * (N + 1)));       // [w_y, b_hat_0 .. b_hat_{N-1}]
+    FKGP_HIP(sc.get(&wx, M * (N + 1)));      // [w_y, W^T x_0 .. W^T x_{N-1}]
+    FKGP_HIP(sc.get(&alphas, (size_t)kMaxLanczos * N));
+    FKGP_HIP(sc.get(&betas, (size_t)kMaxLanczos * N));
+    FKGP_HIP(sc.get(&ps, N));
+    // mean solve: w_y = W^T z~
+    fkgp_solve_info sinfo{};
+    fkgp_status sres = solve_core(c, nullptr, o.tol, o.maxiter, V, &sinfo, sc, st);
+    if (sres != FKGP_OK && sres != FKGP_ENOTCONV) return sres;
+    FKGP_HIP(hipMemcpyAsync(wx, V, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+    FKGP_HIP(hipMemcpyAsync(V + M, h->sketches, sizeof(double) * M * N, hipMemcpyDeviceToDevice, st));
+    // probe solves (batched, or one probe at a time)
+    int iters_max = 0;
+    fkgp_status pres = FKGP_OK;
+    if (o.batched) {
+        pres = probe_cg(c, V + M, N, n, o.tol, o.maxiter, wx + M, alphas, betas, ps, sc, st,
+                        iters_max);
+    } else {
+        for (int j = 0; j < N && (pres == FKGP_OK || pres == FKGP_ENOTCONV); ++j) {
+            int it = 0;
+            Scratch sj(st);
+            fkgp_status r1 = probe_cg(c, V + M * (1 + j), 1, n, o.tol, o.maxiter,
+                                      wx + M * (1 + j), alphas + kMaxLanczos * j,
+                                      betas + kMaxLanczos * j, ps + j, sj, st, it);
+            if (r1 != FKGP_OK) pres = r1;
+            iters_max = std::max(iters_max, it);
+        }
+    }
+    if (pres != FKGP_OK && pres != FKGP_ENOTCONV) return pres;
+    double logdet = 0.0, q = 0.0;
+    rs = mll_post(c, hyp, o, V, wx, alphas, betas, ps, mll, grad, sc, st, logdet, q);
+    if (rs != FKGP_OK) return rs;
     if (info) {
         info->logdet = logdet;
         info->quad = q;
         info->iterations_y = sinfo.iterations;
         info->iterations_probes_max = iters_max;
     }
-    if (!std::isfinite(logdet)) {
-        set_error("Lanczos quadrature failed (non-finite log-determinant)");
-        return FKGP_EDEVICE;
-    }
     return (sres == FKGP_ENOTCONV || pres == FKGP_ENOTCONV) ? FKGP_ENOTCONV : FKGP_OK;
+}
+
+// Many problems in one persistent launch: for each problem the right-hand
+// sides [y, z_0 .. z_{N-1}] all use the factorized CG from x_0 = 0.
+fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hypers* hyps,
+                           const fkgp_mll_opts& o, double* mll, double* grad,
+                           fkgp_mll_info* infos, hipStream_t st) {
+    Scratch sc(st);
+    std::vector<OpCtx> ctx(np);
+    std::vector<BatchProb> probs(np);
+    std::vector<BatchItem> items;
+    std::vector<double*> Vs(np), wxs(np), alph(np), bet(np);
+    std::vector<PState*> pss(np);
+    size_t lds = 0;
+    for (int p = 0; p < np; ++p) {
+        const fkgp_handle* h = hs[p];
+        fkgp_status rs = make_ctx(h, &hyps[p], FKGP_F64, ctx[p], sc);
+        if (rs != FKGP_OK) return rs;
+        const OpCtx& c = ctx[p];
+        const int N = h->nprobe, nrhs = N + 1;
+        const int64_t M = h->M;
+        double *bh, *kb, *bn, *V, *wx, *al, *be;
+        PState* ps;
+        FKGP_HIP(sc.get(&bh, M * nrhs));
+        FKGP_HIP(sc.get(&kb, M * nrhs));
+        FKGP_HIP(sc.get(&bn, nrhs));
+        FKGP_HIP(sc.get(&V, M * nrhs));
+        FKGP_HIP(sc.get(&wx, M * nrhs));
+        FKGP_HIP(sc.get(&al, (size_t)kMaxLanczos * nrhs));
+        FKGP_HIP(sc.get(&be, (size_t)kMaxLanczos * nrhs));
+        FKGP_HIP(sc.get(&ps, nrhs));
+        FKGP_HIP(hipMemcpyAsync(bh, h->wty, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+        FKGP_HIP(hipMemcpyAsync(bh + M, h->sketches, sizeof(double) * M * N,
+                                hipMemcpyDeviceToDevice, st));
+        rs = kg_apply(h->g, c.sp64, FKGP_F64, bh, kb, nrhs, c.so, nullptr, 0.0, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+        std::vector<double> hb(nrhs, (double)h->n);
+        hb[0] = h->yty;
+        FKGP_HIP(hipMemcpyAsync(bn, hb.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+        FKGP_HIP(hipStreamSynchronize(st));   // hb leaves scope
+        BatchProb& P = probs[p];
+        P.d = h->g.d;
+        P.m[0] = h->g.m[0];
+        P.m[1] = h->g.d > 1 ? h->g.m[1] : 1;
+        P.M = M;
+        P.halo = c.halo;
+        P.NB = h->NB;
+        size_t l = 0;
+        for (int k = 0; k < 2; ++k) {
+            P.log2L[k] = k < h->g.d ? c.sp64.log2L[k] : 0;
+            P.tw[k] = k < h->g.d ? c.sp64.tw[k] : nullptr;
+            P.lam[k] = k < h->g.d ? static_cast<const double*>(c.sp64.lam[k]) : nullptr;
+            if (k < h->g.d) l += (size_t)16 * (1 << P.log2L[k]);
+        }
+        lds = std::max(lds, l);
+        P.a_f32 = h->dt == FKGP_F32 ? 1 : 0;
+        P.A = h->A;
+        P.so = c.so;
+        P.s2 = c.s2;
+        P.n = (double)h->n;
+        P.bh = bh;
+        P.kb = kb;
+        P.bnorm2 = bn;
+        P.alphas = al;
+        P.betas = be;
+        P.ps = ps;
+        P.wx = wx;
+        Vs[p] = V;
+        wxs[p] = wx;
+        alph[p] = al;
+        bet[p] = be;
+        pss[p] = ps;
+        const size_t wd = batch_work_doubles(M, c.halo);
+        for (int r0 = 0; r0 < nrhs; r0 += kBatchRhs) {
+            double* work = nullptr;
+            FKGP_HIP(sc.get(&work, wd));
+            items.push_back(BatchItem{p, r0, std::min(kBatchRhs, nrhs - r0), work});
+        }
+    }
+    BatchProb* probs_dev = nullptr;
+    BatchItem* items_dev = nullptr;
+    FKGP_HIP(sc.get(&probs_dev, np));
+    FKGP_HIP(sc.get(&items_dev, items.size()));
+    FKGP_HIP(hipMemcpyAsync(probs_dev, probs.data(), sizeof(BatchProb) * np,
+                            hipMemcpyHostToDevice, st));
+    FKGP_HIP(hipMemcpyAsync(items_dev, items.data(), sizeof(BatchItem) * items.size(),
+                            hipMemcpyHostToDevice, st));
+    fkgp_status rs = launch_batch_cg(probs_dev, items_dev, (int)items.size(), lds, o.tol,
+                                     o.maxiter, st);
+    if (rs != FKGP_OK) return rs;
+    FKGP_HIP(hipStreamSynchronize(st));
+    fkgp_status res = FKGP_OK;
+    for (int p = 0; p < np; ++p) {
+        const fkgp_handle* h = hs[p];
+        const int N = h->nprobe;
+        const int64_t M = h->M;
+        std::vector<PState> hsv(N + 1);
+        FKGP_HIP(hipMemcpyAsync(hsv.data(), pss[p], sizeof(PState) * (N + 1),
+                                hipMemcpyDeviceToHost, st));
+        // V = [W^T z~ (= wx_0), b_hat_j]
+        FKGP_HIP(hipMemcpyAsync(Vs[p], wxs[p], sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+        FKGP_HIP(hipMemcpyAsync(Vs[p] + M, h->sketches, sizeof(double) * M * N,
+                                hipMemcpyDeviceToDevice, st));
+        FKGP_HIP(hipStreamSynchronize(st));
+        int itmax = 0;
+        bool conv = true;
+        for (int j = 0; j <= N; ++j) {
+            if (hsv[j].done == 2) {
+                set_error("batched CG broke down (non-finite step) in problem " + std::to_string(p));
+                return FKGP_EDEVICE;
+            }
+            conv &= hsv[j].done == 1;
+            if (j > 0) itmax = std::max(itmax, hsv[j].iters);
+        }
+        double logdet = 0.0, q = 0.0;
+        Scratch sp_(st);
+        rs = mll_post(ctx[p], &hyps[p], o, Vs[p], wxs[p], alph[p] + kMaxLanczos,
+                      bet[p] + kMaxLanczos, pss[p] + 1, &mll[p], grad + 5 * p, sp_, st, logdet,
+                      q);
+        if (rs != FKGP_OK) return rs;
+        for (int k = h->g.d + 2; k < 5; ++k) grad[5 * p + k] = 0.0;
+        if (infos) {
+            infos[p].logdet = logdet;
+            infos[p].quad = q;
+            infos[p].iterations_y = hsv[0].iters;
+            infos[p].iterations_probes_max = itmax;
+        }
+        if (!conv) res = FKGP_ENOTCONV;
+    }
+    return res;
 }
 
 }  // namespace
@@ -1557,5 +1698,42 @@ extern "C" fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers
             return FKGP_EINVAL;
         }
         return fkgp::mll_impl(h, hyp, o, mll, grad, info, static_cast<hipStream_t>(stream));
+    });
+}
+
+extern "C" fkgp_status fkgp_batch_mll_and_grad(const fkgp_handle* const* hs, int nprob,
+                                               const fkgp_hypers* hyps,
+                                               const fkgp_mll_opts* opts, double* mll,
+                                               double* grad, fkgp_mll_info* infos,
+                                               void* stream) {
+    return guarded([&]() -> fkgp_status {
+        fkgp::set_error("");
+        if (!hs || !hyps || !mll || !grad || nprob < 0) {
+            fkgp::set_error("handles, hypers, mll and grad must be non-NULL, nprob >= 0");
+            return FKGP_EINVAL;
+        }
+        for (int p = 0; p < nprob; ++p) {
+            const fkgp_handle* h = hs[p];
+            if (!h) {
+                fkgp::set_error("handle " + std::to_string(p) + " is NULL");
+                return FKGP_EINVAL;
+            }
+            fkgp_status st = fkgp::check_hypers(h, &hyps[p]);
+            if (st != FKGP_OK) return st;
+            if (h->nprobe <= 0 || h->n <= 0 || h->g.d > 2) {
+                fkgp::set_error("problem " + std::to_string(p) +
+                                ": needs probe sketches, n > 0 and d <= 2");
+                return FKGP_EINVAL;
+            }
+        }
+        fkgp_mll_opts o{30, 1e-6, 1000, 1};
+        if (opts) o = *opts;
+        if (o.lanczos_steps < 1 || o.lanczos_steps > fkgp::kMaxLanczos || !(o.tol >= 0.0) ||
+            o.maxiter < 1) {
+            fkgp::set_error("lanczos_steps must be in [1, 64], tol >= 0, maxiter >= 1");
+            return FKGP_EINVAL;
+        }
+        return fkgp::batch_mll_impl(hs, nprob, hyps, o, mll, grad, infos,
+                                    static_cast<hipStream_t>(stream));
     });
 }

@@ -114,6 +114,45 @@ fkgp_status interpolate_points(const GridDev& g, const double* mu,
                                fkgp_dtype in, double* out,
                                unsigned long long* bad_dev, hipStream_t s);
 
+// ---- batched factorized CG over many problems (batch.hip) ---------------
+constexpr int kMaxLanczos = 64;   // CG coefficients kept per right-hand side
+constexpr int kBatchRhs = 8;      // right-hand sides per workgroup work item
+
+// State of one factorized CG from x_0 = 0 (r = W r_hat + c_r b, ...).
+struct PState {
+    double rho, cr, cp, cx, pb, alpha, beta, eps;
+    int done, iters;
+};
+
+struct BatchProb {
+    int d;
+    int m[2];
+    int64_t M, halo;
+    int NB;
+    int log2L[2];
+    int a_f32;                 // stored W^T W is FP32 (else FP64)
+    const void* A;             // row-tiled stencil-diagonal W^T W
+    double so, s2, n;
+    const double* bh;          // [nrhs][M] W^T b
+    const double* kb;          // [nrhs][M] K_G W^T b
+    const double* bnorm2;      // [nrhs] ||b||^2
+    const void* tw[2];         // FP64 twiddles per dimension
+    const double* lam[2];      // FP64 spectra per dimension
+    double* alphas;            // [nrhs][kMaxLanczos]
+    double* betas;             // [nrhs][kMaxLanczos]
+    PState* ps;                // [nrhs]
+    double* wx;                // [nrhs][M] W^T x on exit
+};
+
+struct BatchItem {
+    int prob, r0, nr;
+    double* work;              // batch_work_doubles(M, halo) doubles
+};
+
+size_t batch_work_doubles(int64_t M, int64_t halo);
+fkgp_status launch_batch_cg(const BatchProb* probs_dev, const BatchItem* items_dev, int nitems,
+                            size_t lds, double tol, int maxiter, hipStream_t s);
+
 fkgp_status dia_to_canonical(const GridDev& g, fkgp_dtype dt, const void* A,
                              void* out, hipStream_t s);
 

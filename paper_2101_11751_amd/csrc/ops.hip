@@ -18,23 +18,11 @@
 #include <hip/hip_runtime.h>
 
 #include "common.h"
+#include "line_fft.h"
 
 namespace fkgp {
 namespace {
 
-template <class T>
-struct cplx {
-    T re, im;
-};
-
-template <class T>
-__device__ inline cplx<T> cmul(cplx<T> a, cplx<T> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-template <class T>
-__device__ inline cplx<T> cmul_conj(cplx<T> a, cplx<T> b) {  // a * conj(b)
-    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
-}
 
 // ---------------------------------------------------------------------------
 // Line geometry.  Data of k vectors [k][M] are viewed as [outer][m_line][S]:
@@ -113,73 +101,7 @@ __global__ __launch_bounds__(kLineBlock) void line_conv(
                 z[r].im = T(0);
             }
         }
-        // forward DIF: spans L/2 .. 1
-#pragma unroll
-        for (int st = LOG2L - 1; st >= 0; --st) {
-            const int S = 1 << st;
-            if (S >= 64) {
-                const int rs = S / 64;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if (r & rs) continue;
-                    const int e = r * 64 + e_lane;
-                    const cplx<T> w = tws[(e & (S - 1)) * (L / (2 * S))];
-                    const cplx<T> a = z[r], b = z[r + rs];
-                    z[r] = {a.re + b.re, a.im + b.im};
-                    z[r + rs] = cmul(cplx<T>{a.re - b.re, a.im - b.im}, w);
-                }
-            } else {
-                const bool upper = (e_lane & S) != 0;
-                const cplx<T> w = tws[(e_lane & (S - 1)) * (L / (2 * S))];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    cplx<T> p;
-                    p.re = __shfl_xor(z[r].re, S);
-                    p.im = __shfl_xor(z[r].im, S);
-                    const cplx<T> sum{z[r].re + p.re, z[r].im + p.im};
-                    const cplx<T> dif = cmul(cplx<T>{p.re - z[r].re, p.im - z[r].im}, w);
-                    z[r] = upper ? dif : sum;
-                }
-            }
-        }
-        // spectrum (bit-reversed order, includes 1/L)
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const T lmb = lams[r * 64 + e_lane];
-            z[r].re *= lmb;
-            z[r].im *= lmb;
-        }
-        // inverse DIT: spans 1 .. L/2, conjugate twiddles
-#pragma unroll
-        for (int st = 0; st < LOG2L; ++st) {
-            const int S = 1 << st;
-            if (S >= 64) {
-                const int rs = S / 64;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if (r & rs) continue;
-                    const int e = r * 64 + e_lane;
-                    const cplx<T> w = tws[(e & (S - 1)) * (L / (2 * S))];
-                    const cplx<T> a = z[r];
-                    const cplx<T> b = cmul_conj(z[r + rs], w);
-                    z[r] = {a.re + b.re, a.im + b.im};
-                    z[r + rs] = {a.re - b.re, a.im - b.im};
-                }
-            } else {
-                const bool upper = (e_lane & S) != 0;
-                const cplx<T> w = tws[(e_lane & (S - 1)) * (L / (2 * S))];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    cplx<T> p;
-                    p.re = __shfl_xor(z[r].re, S);
-                    p.im = __shfl_xor(z[r].im, S);
-                    const cplx<T> t = cmul_conj(upper ? z[r] : p, w);
-                    const cplx<T> a = upper ? p : z[r];
-                    z[r] = upper ? cplx<T>{a.re - t.re, a.im - t.im}
-                                 : cplx<T>{a.re + t.re, a.im + t.im};
-                }
-            }
-        }
+        conv_line_regs<T, LOG2L>(z, e_lane, tws, lams);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int e = r * 64 + e_lane;
