@@ -106,11 +106,52 @@ __device__ void wg_line_pass(const double* src, double* dst, int nr, int64_t M, 
     }
 }
 
+// Long lines: the workgroup convolves one line pair at a time with the
+// four-step FFT (tw1/tw2 in LDS, half-circle twiddles twh and the four-step
+// spectrum in global memory, Y: L complex scratch of this work item).
+template <int LG1, int LG2>
+__device__ void wg_line_pass_long(const double* src, double* dst, int nr, int64_t M, int m_line,
+                                  int64_t S, const cplx<double>* tw1, const cplx<double>* tw2,
+                                  const cplx<double>* twh, const double* lamp, double scale,
+                                  const double* addv, int64_t ldx, int64_t halo, double add_coef,
+                                  cplx<double>* Y) {
+    const int64_t lines_per_vec = M / m_line;
+    const int64_t nlines = lines_per_vec * nr;
+    for (int64_t la = 0; la < nlines; la += 2) {
+        int64_t base[2] = {0, 0}, abase[2] = {0, 0};
+        const bool hb = la + 1 < nlines;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t l = (h == 0 || hb) ? la + h : la;
+            const int64_t r = l / lines_per_vec;
+            const int64_t li = l - r * lines_per_vec;
+            const int64_t outer = li / S, inner = li - outer * S;
+            const int64_t start = outer * m_line * S + inner;
+            base[h] = r * M + start;
+            abase[h] = r * ldx + halo + start;
+        }
+        wg_conv_long<double, LG1, LG2>(src + base[0], hb ? src + base[1] : nullptr, S, m_line,
+                                       dst + base[0], hb ? dst + base[1] : nullptr, scale,
+                                       addv ? addv + abase[0] : nullptr,
+                                       (addv && hb) ? addv + abase[1] : nullptr, add_coef, Y,
+                                       twh, lamp, tw1, tw2);
+    }
+}
+
 __device__ void wg_line_pass_any(int lg, const double* src, double* dst, int nr, int64_t M,
                                  int m_line, int64_t S, const cplx<double>* tws,
                                  const double* lams, double scale, const double* addv,
-                                 int64_t ldx, int64_t halo, double add_coef) {
+                                 int64_t ldx, int64_t halo, double add_coef,
+                                 const cplx<double>* tw2, const cplx<double>* twh,
+                                 cplx<double>* Y) {
     switch (lg) {
+#define FKGP_WLL(LG, A, B)                                                                  \
+    case LG:                                                                                \
+        wg_line_pass_long<A, B>(src, dst, nr, M, m_line, S, tws, tw2, twh, lams, scale,     \
+                                addv, ldx, halo, add_coef, Y);                              \
+        break;
+        FKGP_WLL(12, 6, 6) FKGP_WLL(13, 6, 7) FKGP_WLL(14, 7, 7)
+#undef FKGP_WLL
 #define FKGP_WLP(LG)                                                                     \
     case LG:                                                                             \
         wg_line_pass<LG>(src, dst, nr, M, m_line, S, tws, lams, scale, addv, ldx, halo, \
@@ -163,20 +204,38 @@ __global__ __launch_bounds__(kBatchBlock) void batch_cg_kernel(const BatchProb* 
     const int nr = it.nr;
     const int64_t M = P.M, halo = P.halo, ldx = M + 2 * halo;
     const int tid = threadIdx.x;
-    // spectra of both dimensions into LDS
-    cplx<double>* tws[2];
-    double* lams[2];
+    // spectra of both dimensions into LDS (long lines: only the twiddles of
+    // the two four-step sub-lengths; spectrum and w_L stay in global memory)
+    cplx<double>* tws[2] = {nullptr, nullptr};
+    cplx<double>* tw2s[2] = {nullptr, nullptr};
+    const cplx<double>* twhs[2] = {nullptr, nullptr};
+    const double* lams[2] = {nullptr, nullptr};
     {
         unsigned char* p = lds_raw;
         for (int k = 0; k < P.d; ++k) {
             const int L = 1 << P.log2L[k];
-            tws[k] = reinterpret_cast<cplx<double>*>(p);
-            p += sizeof(cplx<double>) * (L / 2);
-            lams[k] = reinterpret_cast<double*>(p);
-            p += sizeof(double) * L;
             const cplx<double>* twg = static_cast<const cplx<double>*>(P.tw[k]);
-            for (int i = tid; i < L / 2; i += kBatchBlock) tws[k][i] = twg[i];
-            for (int i = tid; i < L; i += kBatchBlock) lams[k][i] = P.lam[k][i];
+            if (P.log2L[k] > kMaxRegLog2) {
+                int lg1, lg2;
+                long_split(P.log2L[k], lg1, lg2);
+                const int L1 = 1 << lg1, L2 = 1 << lg2;
+                tws[k] = reinterpret_cast<cplx<double>*>(p);
+                p += sizeof(cplx<double>) * (L1 / 2);
+                tw2s[k] = reinterpret_cast<cplx<double>*>(p);
+                p += sizeof(cplx<double>) * (L2 / 2);
+                for (int i = tid; i < L1 / 2; i += kBatchBlock) tws[k][i] = twg[i * L2];
+                for (int i = tid; i < L2 / 2; i += kBatchBlock) tw2s[k][i] = twg[i * L1];
+                twhs[k] = twg;
+                lams[k] = P.lam[k];
+            } else {
+                tws[k] = reinterpret_cast<cplx<double>*>(p);
+                p += sizeof(cplx<double>) * (L / 2);
+                double* lm = reinterpret_cast<double*>(p);
+                p += sizeof(double) * L;
+                for (int i = tid; i < L / 2; i += kBatchBlock) tws[k][i] = twg[i];
+                for (int i = tid; i < L; i += kBatchBlock) lm[i] = P.lam[k][i];
+                lams[k] = lm;
+            }
         }
     }
     if (tid < P.NB) {
@@ -284,13 +343,13 @@ __global__ __launch_bounds__(kBatchBlock) void batch_cg_kernel(const BatchProb* 
         // v_r = s K u_r + s2 r_hat
         if (P.d == 1) {
             wg_line_pass_any(P.log2L[0], ur, vr, nr, M, P.m[0], 1, tws[0], lams[0], P.so, rp,
-                             ldx, halo, P.s2);
+                             ldx, halo, P.s2, tw2s[0], twhs[0], it.yscr);
         } else {
             wg_line_pass_any(P.log2L[1], ur, vr, nr, M, P.m[1], 1, tws[1], lams[1], 1.0,
-                             nullptr, ldx, halo, 0.0);
+                             nullptr, ldx, halo, 0.0, tw2s[1], twhs[1], it.yscr);
             __syncthreads();
             wg_line_pass_any(P.log2L[0], vr, vr, nr, M, P.m[0], P.m[1], tws[0], lams[0], P.so,
-                             rp, ldx, halo, P.s2);
+                             rp, ldx, halo, P.s2, tw2s[0], twhs[0], it.yscr);
         }
         __syncthreads();
         // rho' = <r, r>, beta

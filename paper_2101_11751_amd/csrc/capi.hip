@@ -305,14 +305,19 @@ fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtyp
     const size_t es = dsize(dt);
     for (int k = 0; k < h->g.d; ++k) {
         sp.log2L[k] = circulant_log2(h->g.m[k]);
-        if (sp.log2L[k] > 11) {
-            set_error("grid dimension longer than 1024 nodes is not supported by the line FFT");
+        if (sp.log2L[k] > kMaxLineLog2) {
+            set_error("grid dimension longer than 8192 nodes is not supported by the line FFT");
             return FKGP_EINVAL;
         }
         sp.L[k] = 1 << sp.log2L[k];
         unsigned char *lam = nullptr, *tw = nullptr;
         FKGP_HIP(sc.get(&lam, es * sp.L[k]));
         FKGP_HIP(sc.get(&tw, 2 * es * (sp.L[k] / 2)));
+        if (sp.log2L[k] > kMaxRegLog2) {
+            unsigned char* scr = nullptr;
+            FKGP_HIP(sc.get(&scr, 2 * es * (size_t)sp.L[k] * kLongWGs));
+            sp.scr[k] = scr;
+        }
         fkgp_status st =
             build_spectrum(h->g, k, hyp->lengthscale[k], k == dderiv, dt, lam, sp.log2L[k], sc.s);
         if (st != FKGP_OK) return st;
@@ -776,8 +781,8 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
             return FKGP_EINVAL;
         }
         for (int k = 0; k < g.d; ++k)
-            if (circulant_log2(g.m[k]) > 11) {
-                set_error("grid dimension longer than 1024 nodes is not supported");
+            if (circulant_log2(g.m[k]) > kMaxLineLog2) {
+                set_error("grid dimension longer than 8192 nodes is not supported");
                 return FKGP_EINVAL;
             }
         hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1584,11 +1589,20 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
         P.halo = c.halo;
         P.NB = h->NB;
         size_t l = 0;
+        int long_L = 0;   // longest circulant taking the four-step path
         for (int k = 0; k < 2; ++k) {
             P.log2L[k] = k < h->g.d ? c.sp64.log2L[k] : 0;
             P.tw[k] = k < h->g.d ? c.sp64.tw[k] : nullptr;
             P.lam[k] = k < h->g.d ? static_cast<const double*>(c.sp64.lam[k]) : nullptr;
-            if (k < h->g.d) l += (size_t)16 * (1 << P.log2L[k]);
+            if (k >= h->g.d) continue;
+            if (P.log2L[k] > kMaxRegLog2) {
+                int lg1, lg2;
+                long_split(P.log2L[k], lg1, lg2);
+                l += (size_t)8 * ((1 << lg1) + (1 << lg2));   // both sub-length twiddles
+                long_L = std::max(long_L, 1 << P.log2L[k]);
+            } else {
+                l += (size_t)16 * (1 << P.log2L[k]);          // twiddles + spectrum
+            }
         }
         lds = std::max(lds, l);
         P.a_f32 = h->dt == FKGP_F32 ? 1 : 0;
@@ -1612,7 +1626,10 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
         for (int r0 = 0; r0 < nrhs; r0 += kBatchRhs) {
             double* work = nullptr;
             FKGP_HIP(sc.get(&work, wd));
-            items.push_back(BatchItem{p, r0, std::min(kBatchRhs, nrhs - r0), work});
+            double* yscr = nullptr;
+            if (long_L > 0) FKGP_HIP(sc.get(&yscr, (size_t)2 * long_L));
+            items.push_back(BatchItem{p, r0, std::min(kBatchRhs, nrhs - r0), work,
+                                      reinterpret_cast<cplx<double>*>(yscr)});
         }
     }
     BatchProb* probs_dev = nullptr;

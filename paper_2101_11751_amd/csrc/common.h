@@ -68,11 +68,28 @@ fkgp_status run_precompute(const GridDev& g, const void* const* x, const void* y
                            unsigned long long* bad_dev, hipStream_t s);
 
 // ---- operators (ops.hip) -------------------------------------------------
+// Longest circulant handled by the register-resident line FFT, and by the
+// four-step path (grid dimensions up to 8192 nodes).
+constexpr int kMaxRegLog2 = 11;
+constexpr int kMaxLineLog2 = 14;
+// Workgroups (each with its own L-point complex scratch) of a four-step pass.
+constexpr int kLongWGs = 256;
+
+// Split of a long circulant length L = 2^lg1 * 2^lg2 for the four-step path.
+__host__ __device__ inline void long_split(int log2L, int& lg1, int& lg2) {
+    lg1 = log2L / 2;
+    lg2 = log2L - lg1;
+}
+
 struct Spectra {
     int L[3];           // circulant length per dim (power of two)
     int log2L[3];
-    void* lam[3];       // [L] bit-reversed, scaled by 1/L, stats dtype
+    // [L], scaled by 1/L, stats dtype: bit-reversed order for the register
+    // line FFT; for long lines (log2L > kMaxRegLog2) the four-step order
+    // lam[p1 * L2 + p2] = lambda[bitrev(p1) + L1 * bitrev(p2)] / L.
+    void* lam[3];
     void* tw[3];        // twiddles exp(-2 pi i t / L), t < L/2, complex stats dtype
+    void* scr[3];       // long lines: kLongWGs * L complex scratch, else null
 };
 
 int circulant_log2(int m);
@@ -124,6 +141,9 @@ struct PState {
     int done, iters;
 };
 
+template <class T>
+struct cplx;   // complex pair {re, im} (line FFTs)
+
 struct BatchProb {
     int d;
     int m[2];
@@ -147,6 +167,7 @@ struct BatchProb {
 struct BatchItem {
     int prob, r0, nr;
     double* work;              // batch_work_doubles(M, halo) doubles
+    cplx<double>* yscr;        // L complex (longest long line), or null
 };
 
 size_t batch_work_doubles(int64_t M, int64_t halo);

@@ -136,10 +136,65 @@ __global__ __launch_bounds__(kLineBlock) void line_conv(
     }
 }
 
+// Long lines: one workgroup per line pair at a time (grid-stride over the
+// pairs), four-step convolution through its own L-point scratch.
+template <class T, int LG1, int LG2>
+__global__ __launch_bounds__(kLineBlock) void line_conv_long(
+    const T* in, T* out, LineGeom lg, const T* __restrict__ lamp,
+    const cplx<T>* __restrict__ twh, T scale, const T* addv, T add_coef,
+    const int* __restrict__ skip, cplx<T>* __restrict__ scr) {
+    constexpr int L1 = 1 << LG1, L2 = 1 << LG2;
+    if (skip && *skip) return;
+    __shared__ cplx<T> tw1[L1 / 2], tw2[L2 / 2];
+    for (int t = threadIdx.x; t < L1 / 2; t += kLineBlock) tw1[t] = twh[t * L2];
+    for (int t = threadIdx.x; t < L2 / 2; t += kLineBlock) tw2[t] = twh[t * L1];
+    __syncthreads();
+    cplx<T>* Y = scr + (int64_t)blockIdx.x * (L1 * L2);
+    const int64_t npairs = (lg.nlines + 1) / 2;
+    for (int64_t pair = blockIdx.x; pair < npairs; pair += gridDim.x) {
+        const int64_t la = 2 * pair, lb = la + 1;
+        const bool hb = lb < lg.nlines;
+        const int64_t ba = line_addr(lg, la, 0);
+        const int64_t bb = hb ? line_addr(lg, lb, 0) : 0;
+        wg_conv_long<T, LG1, LG2>(in + ba, hb ? in + bb : nullptr, lg.S, lg.m_line, out + ba,
+                                  hb ? out + bb : nullptr, scale, addv ? addv + ba : nullptr,
+                                  (addv && hb) ? addv + bb : nullptr, add_coef, Y, twh, lamp,
+                                  tw1, tw2);
+    }
+}
+
 template <class T>
 fkgp_status launch_line_conv(int log2L, const T* in, T* out, const LineGeom& lg,
                              const T* lam, const cplx<T>* tw, T scale, const T* addv,
-                             T add_coef, const int* skip, hipStream_t s) {
+                             T add_coef, const int* skip, cplx<T>* scr, hipStream_t s) {
+    if (log2L > kMaxRegLog2) {
+        if (!scr) {
+            set_error("long grid line without four-step scratch");
+            return FKGP_EINVAL;
+        }
+        const int64_t npairs = (lg.nlines + 1) / 2;
+        const unsigned grid = (unsigned)std::min<int64_t>(npairs, kLongWGs);
+        if (grid == 0) return FKGP_OK;
+        switch (log2L) {
+            case 12:
+                line_conv_long<T, 6, 6><<<grid, kLineBlock, 0, s>>>(in, out, lg, lam, tw, scale,
+                                                                   addv, add_coef, skip, scr);
+                break;
+            case 13:
+                line_conv_long<T, 6, 7><<<grid, kLineBlock, 0, s>>>(in, out, lg, lam, tw, scale,
+                                                                   addv, add_coef, skip, scr);
+                break;
+            case 14:
+                line_conv_long<T, 7, 7><<<grid, kLineBlock, 0, s>>>(in, out, lg, lam, tw, scale,
+                                                                   addv, add_coef, skip, scr);
+                break;
+            default:
+                set_error("grid dimension too long for the line FFT (at most 8192 nodes)");
+                return FKGP_EINVAL;
+        }
+        FKGP_HIP(hipGetLastError());
+        return FKGP_OK;
+    }
     // lines per block: enough blocks to cover the chip (>= ~2 per CU), at
     // least 8 lines for strided dimensions (64-byte coalesced rows), at most
     // what fits in 48 KiB of LDS; even.
@@ -184,16 +239,24 @@ __device__ inline unsigned bitrev(unsigned v, int bits) {
     return __brev(v) >> (32 - bits);
 }
 
-// lam_br[e] = (1/L) sum_j c_emb[j] cos(2 pi j f / L), f = bitrev(e); the
+// lam_br[e] = (1/L) sum_j c_emb[j] cos(2 pi j f / L), f = bitrev(e) (or the
+// four-step order of long lines, lg1 > 0); the
 // circulant embedding is c_emb[j] = c[min(j, L-j)] for min(j, L-j) < m,
 // else 0 (symmetric, so the DFT is real).
 template <class T>
-__global__ void spectrum_kernel(T* __restrict__ lam_br, int log2L, int m, double h,
+__global__ void spectrum_kernel(T* __restrict__ lam_br, int log2L, int lg1, int m, double h,
                                 double ell, bool deriv) {
     const int L = 1 << log2L;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= L) return;
-    const unsigned f = bitrev((unsigned)e, log2L);
+    unsigned f;
+    if (lg1 > 0) {   // four-step order: e = p1 * L2 + p2
+        const int lg2 = log2L - lg1;
+        const unsigned p1 = (unsigned)e >> lg2, p2 = (unsigned)e & ((1u << lg2) - 1u);
+        f = bitrev(p1, lg1) + (bitrev(p2, lg2) << lg1);
+    } else {
+        f = bitrev((unsigned)e, log2L);
+    }
     double acc = se_col(0, h, ell, deriv);
     for (int j = 1; j < m; ++j) {
         if (L - j < j) break;
@@ -440,12 +503,14 @@ fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv, fkgp
                            void* lam, int log2L, hipStream_t s) {
     const int L = 1 << log2L;
     const unsigned grid = (unsigned)((L + 255) / 256);
+    int lg1 = 0, lg2 = 0;
+    if (log2L > kMaxRegLog2) long_split(log2L, lg1, lg2);
     if (dt == FKGP_F32)
-        spectrum_kernel<float><<<grid, 256, 0, s>>>(static_cast<float*>(lam), log2L, g.m[k],
-                                                    g.h[k], ell, deriv);
+        spectrum_kernel<float><<<grid, 256, 0, s>>>(static_cast<float*>(lam), log2L, lg1,
+                                                    g.m[k], g.h[k], ell, deriv);
     else
-        spectrum_kernel<double><<<grid, 256, 0, s>>>(static_cast<double*>(lam), log2L, g.m[k],
-                                                     g.h[k], ell, deriv);
+        spectrum_kernel<double><<<grid, 256, 0, s>>>(static_cast<double*>(lam), log2L, lg1,
+                                                     g.m[k], g.h[k], ell, deriv);
     FKGP_HIP(hipGetLastError());
     return FKGP_OK;
 }
@@ -478,7 +543,7 @@ static fkgp_status kg_apply_t(const GridDev& g, const Spectra& sp, const T* x, T
         fkgp_status st = launch_line_conv<T>(
             sp.log2L[dim], src, y, lg, static_cast<const T*>(sp.lam[dim]),
             static_cast<const cplx<T>*>(sp.tw[dim]), last ? (T)scale : T(1),
-            last ? addv : nullptr, (T)add_coef, skip, s);
+            last ? addv : nullptr, (T)add_coef, skip, static_cast<cplx<T>*>(sp.scr[dim]), s);
         if (st != FKGP_OK) return st;
     }
     return FKGP_OK;

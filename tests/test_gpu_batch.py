@@ -69,3 +69,32 @@ def test_batch_deterministic_and_errors():
     h3, hyp3, *_ = problem(7, 2, [20, 20], 1000, 0)
     with pytest.raises(P.FkgpError):
         P.batch_mll_and_grad(hs + [h3], hyps + [hyp3])
+
+
+def test_batch_long_lines():
+    """1-D problems with 1500 .. 8192 nodes (circulants of 4096 .. 16384
+    points, four-step line FFT inside the persistent kernel) beside short
+    ones; each matches the single-problem path, one matches the oracle."""
+    _need_gpu()
+    specs = [(8, 1, [1500], 20000, 5), (9, 1, [3000], 40000, 9), (10, 1, [8192], 60000, 4),
+             (11, 2, [2100, 12], 30000, 6), (12, 2, [30, 30], 8000, 3)]
+    probs = [problem(*s) for s in specs]
+    hs = [p[0] for p in probs]
+    hyps = [p[1] for p in probs]
+    for hyp in hyps[:4]:
+        hyp["lengthscale"][0] = 0.004
+    mll_b, g_b, inf_b = P.batch_mll_and_grad(hs, hyps, lanczos_steps=10, tol=1e-10,
+                                             maxiter=8000)
+    for k, (h, hyp, grid, X, y) in enumerate(probs):
+        mll_s, g_s, inf_s = P.mll_and_grad(h, hyp, lanczos_steps=10, tol=1e-10, maxiter=8000)
+        scale = abs(inf_s["logdet"]) + abs(inf_s["quad"]) + h.n * math.log(2 * math.pi)
+        assert abs(mll_b[k] - mll_s) <= 1e-7 * scale, (k, mll_b[k], mll_s)
+        np.testing.assert_allclose(g_b[k], g_s, rtol=0, atol=1e-5 * np.max(np.abs(g_s)))
+    h, hyp, grid, X, y = probs[1]
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    sk = oracle.probe_sketches(grid, X, 109, 9)
+    mll_o, g_o, inf_o = oracle.mll_and_grad(grid, hyp, wtw, wty, yty, X.shape[1], sk,
+                                            lanczos_steps=10, tol=1e-10)
+    scale = abs(inf_o["logdet"]) + abs(inf_o["q"]) + X.shape[1] * math.log(2 * math.pi)
+    assert abs(mll_b[1] - mll_o) <= 1e-6 * scale
+    np.testing.assert_allclose(g_b[1], g_o, rtol=0, atol=1e-4 * np.max(np.abs(g_o)))

@@ -97,7 +97,11 @@ def test_precompute_empty_and_out_of_grid():
 
 
 @pytest.mark.parametrize("d,m", [(1, [1000]), (1, [9]), (2, [37, 29]), (2, [128, 128]),
-                                 (3, [14, 11, 9]), (3, [30, 17, 6])])
+                                 (3, [14, 11, 9]), (3, [30, 17, 6]),
+                                 # four-step long lines: L = 4096, 8192, 16384; long
+                                 # contiguous and long strided dimensions
+                                 (1, [1500]), (1, [3000]), (1, [8192]), (2, [2100, 20]),
+                                 (2, [19, 2100]), (3, [4100, 4, 5])])
 @pytest.mark.parametrize("stats", ["f64", "f32"])
 def test_kg_matvec_parity(d, m, stats):
     _need_gpu()
@@ -112,6 +116,22 @@ def test_kg_matvec_parity(d, m, stats):
     tol = 1e-13 if stats == "f64" else 1e-6
     for r in range(3):
         assert rel(out[r], ref[r]) <= tol
+
+
+@pytest.mark.parametrize("m", [[5000], [2500, 6]])
+def test_solve_mean_long_lines(m):
+    """Posterior mean with a grid dimension on the four-step line FFT."""
+    _need_gpu()
+    d = len(m)
+    grid, X, y = make_case(d, 30000, 21, m=m, dtype=np.float64)
+    xs, yt = to_dev(X, y)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float64)
+    wtw_o, wty_o, yty_o = oracle.precompute(grid, X, y)
+    hyp = {"lengthscale": [0.002] + [0.3] * (d - 1), "outputscale": 1.0, "noise": 0.2}
+    mu_o, _, _ = oracle.solve_mean(grid, hyp, wtw_o, wty_o, yty_o, tol=1e-13)
+    mu, info = P.solve(h, hyp, tol=1e-12, maxiter=20000)
+    assert info["converged"]
+    assert rel(mu.cpu(), mu_o) <= 1e-10
 
 
 @pytest.mark.parametrize("d", [1, 2, 3])
