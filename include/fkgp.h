@@ -170,6 +170,12 @@ typedef struct {
                            iteration for every probe); 0: one probe at a time.
                            Operator arithmetic is FP64 either way (on the
                            stored W^T W, FP32 entries upcast exactly). */
+    int batch_rhs;      /* fkgp_batch_mll_and_grad only: right-hand sides per
+                           workgroup (2, 4 or 8); 0 = autotune */
+    int batch_block;    /* fkgp_batch_mll_and_grad only: threads per
+                           workgroup (256 or 512); 0 = autotune.  Autotuning
+                           times a short trial of each candidate and caches
+                           the fastest per batch shape for the process. */
 } fkgp_mll_opts;
 
 typedef struct {
@@ -177,6 +183,9 @@ typedef struct {
     double quad;        /* y^T (W K_G W^T + s2 I)^{-1} y */
     int iterations_y;
     int iterations_probes_max;
+    int batch_rhs;      /* fkgp_batch_mll_and_grad: right-hand sides per
+                           workgroup used (0 for fkgp_mll_and_grad) */
+    int batch_block;    /* fkgp_batch_mll_and_grad: threads per workgroup used */
 } fkgp_mll_info;
 
 /* Log marginal likelihood (Def. 2 / Fact 2) and its gradient with respect to
@@ -194,8 +203,9 @@ fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers* hyp,
  * sketches, d <= 2, any mix of sizes) in one persistent launch: every
  * right-hand side [y, z_0 .. z_{N-1}] of every problem is solved with the
  * factorized CG from x_0 = 0 (Claims 3 and 4); a workgroup owns one problem
- * and up to 8 of its right-hand sides and runs their CG to the end, so the
- * stored W^T W is read once per iteration for all of them.
+ * and up to opts->batch_rhs of its right-hand sides (autotuned when 0) and
+ * runs their CG to the end, so the stored W^T W is read once per iteration
+ * for all of them.
  *   hyps: nprob hyperparameter sets; mll: nprob host doubles; grad: nprob x 5
  *   host doubles (entries d+2 .. 4 of each row are 0); infos: nprob (or
  *   NULL).  opts->batched is ignored.  Synchronises `stream`. */

@@ -74,12 +74,14 @@ class _SolveInfo(ctypes.Structure):
 
 class _MllOpts(ctypes.Structure):
     _fields_ = [("lanczos_steps", ctypes.c_int), ("tol", ctypes.c_double),
-                ("maxiter", ctypes.c_int), ("batched", ctypes.c_int)]
+                ("maxiter", ctypes.c_int), ("batched", ctypes.c_int),
+                ("batch_rhs", ctypes.c_int), ("batch_block", ctypes.c_int)]
 
 
 class _MllInfo(ctypes.Structure):
     _fields_ = [("logdet", ctypes.c_double), ("quad", ctypes.c_double),
-                ("iterations_y", ctypes.c_int), ("iterations_probes_max", ctypes.c_int)]
+                ("iterations_y", ctypes.c_int), ("iterations_probes_max", ctypes.c_int),
+                ("batch_rhs", ctypes.c_int), ("batch_block", ctypes.c_int)]
 
 
 _lib = None
@@ -333,16 +335,19 @@ def mll_and_grad(h, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000, batched=Tr
     info = _MllInfo()
     st = _check(L.fkgp_mll_and_grad(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)),
                                     ctypes.byref(_MllOpts(int(lanczos_steps), float(tol),
-                                                          int(maxiter), int(bool(batched)))),
+                                                          int(maxiter), int(bool(batched)), 0, 0)),
                                     ctypes.byref(mll), grad, ctypes.byref(info), _stream()))
     return mll.value, [grad[i] for i in range(h.d + 2)], {
         "logdet": info.logdet, "quad": info.quad, "iterations_y": info.iterations_y,
         "iterations_probes_max": info.iterations_probes_max, "status": st}
 
 
-def batch_mll_and_grad(handles, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000):
-    """Many problems in one persistent launch.  Returns (mll list, grad list
-    (d+2 entries each), info list)."""
+def batch_mll_and_grad(handles, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000,
+                       batch_rhs=0, batch_block=0):
+    """Many problems in one persistent launch.  batch_rhs: right-hand sides
+    per workgroup (2, 4 or 8), batch_block: threads per workgroup (256 or
+    512); 0 = autotuned.  Returns (mll list, grad list (d+2 entries each),
+    info list)."""
     L = load_library()
     n = len(handles)
     hs = (ctypes.c_void_p * n)(*[h.ptr for h in handles])
@@ -352,13 +357,17 @@ def batch_mll_and_grad(handles, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000
     infos = (_MllInfo * n)()
     st = _check(L.fkgp_batch_mll_and_grad(hs, n, hy, ctypes.byref(_MllOpts(int(lanczos_steps),
                                                                            float(tol),
-                                                                           int(maxiter), 1)),
+                                                                           int(maxiter), 1,
+                                                                           int(batch_rhs),
+                                                                           int(batch_block))),
                                           mll, grad, infos, _stream()))
     return ([mll[i] for i in range(n)],
             [[grad[5 * i + k] for k in range(handles[i].d + 2)] for i in range(n)],
             [{"logdet": infos[i].logdet, "quad": infos[i].quad,
               "iterations_y": infos[i].iterations_y,
-              "iterations_probes_max": infos[i].iterations_probes_max, "status": st}
+              "iterations_probes_max": infos[i].iterations_probes_max,
+              "batch_rhs": infos[i].batch_rhs, "batch_block": infos[i].batch_block,
+              "status": st}
              for i in range(n)])
 
 

@@ -6,13 +6,23 @@
 // x = W x_hat + c_x b, which needs only b_hat = W^T b and ||b||^2 (the data
 // vector y: W^T y, y^T y; a Rademacher probe z_j: its sketch and n).  One
 // launch covers the whole batch: workgroup g owns one work item (a problem
-// and a group of at most kBatchRhs right-hand sides) and runs its CG to the
-// end with workgroup barriers only, so workgroups never wait on each other
-// and each one exits when all its right-hand sides have converged or the
+// and a group of at most NR right-hand sides) and runs its CG to the end
+// with workgroup barriers only, so workgroups never wait on each other and
+// each one exits when all its right-hand sides have converged or the
 // iteration cap is reached.  Inside an item the right-hand sides advance
-// together: one read of the stored W^T W per iteration serves all of them,
-// and the K_G product convolves their grid lines with the register-resident
-// line FFT (two real lines per complex line).
+// together: one read of the stored W^T W per iteration serves all of them.
+//
+// One iteration is four passes over the item's vectors:
+//   (A) s_p = u_r + beta s_p, z_p = v_r + beta z_p (the direction update of
+//       the previous iteration, fused here), and the dots s_p.ap, ap.b_hat
+//       with ap = z_p + c_p kappa_b (never stored);
+//   (B) u_x += alpha s_p, r_hat -= alpha ap;
+//   (C) u_r = W^T W r_hat with several consecutive rows per thread (the
+//       x values of a stencil row are shared by neighbouring rows) and the
+//       dots r_hat.u_r, r_hat.b_hat fused;
+//   (D) v_r = s K_G u_r + s2 r_hat: line convolutions per grid dimension,
+//       short lines by the register line FFT (strided lines staged through
+//       an LDS transpose), long lines by the four-step FFT.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -21,252 +31,379 @@
 namespace fkgp {
 namespace {
 
-constexpr int kBatchBlock = 256;
-constexpr int kBatchWaves = kBatchBlock / 64;
+constexpr int kMaxWaves = 8;        // waves per work item: 4 or 8 (256 or 512 threads)
+constexpr int kStrBlock = 32;       // strided lines per LDS transpose block
 
 // Sum of NV per-thread values over the workgroup, in a fixed order (wave
 // shuffles, then the waves in order).  Result in out[v] for all threads.
 template <int NV>
 __device__ inline void wg_sum(double (&v)[NV], double* red, double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double x = v[k];
 #pragma unroll
         for (int s = 32; s > 0; s >>= 1) x += __shfl_xor(x, s);
-        if (lane == 0) red[k * kBatchWaves + wave] = x;
+        if (lane == 0) red[k * kMaxWaves + wave] = x;
     }
     __syncthreads();
     if (threadIdx.x < NV) {
         double acc = 0.0;
-        for (int w = 0; w < kBatchWaves; ++w) acc += red[threadIdx.x * kBatchWaves + w];
+        for (int w = 0; w < nw; ++w) acc += red[threadIdx.x * kMaxWaves + w];
         out[threadIdx.x] = acc;
     }
     __syncthreads();
 }
 
-// One pass of line convolutions over all lines (of all nr vectors) along a
-// grid dimension: lines of length m_line with stride S inside [outer][m][S]
-// vectors of length M.  dst = scale * conv(src) (+ add_coef * addv, addv in
-// padded layout with leading dimension ldx and offset halo).
+// Geometry of the line passes of one item.
+struct PassGeom {
+    int m_line;         // line length
+    int64_t S;          // stride of a line's entries
+    int64_t per_vec;    // lines per vector (M / m_line)
+    int64_t M;          // vector length
+    int64_t ldr;        // stride between padded r_hat vectors
+    int64_t halo;
+};
+
+// Base offsets (vector layout and padded r_hat layout) of line li of vector r.
+__device__ inline void line_base(const PassGeom& pg, int r, int64_t li, int64_t& base,
+                                 int64_t& abase) {
+    const int64_t outer = li / pg.S, inner = li - outer * pg.S;
+    const int64_t start = outer * pg.m_line * pg.S + inner;
+    base = r * pg.M + start;
+    abase = r * pg.ldr + pg.halo + start;
+}
+
+// Lines read in place by the register line FFT (contiguous lines, and
+// strided lines shorter than 32 nodes): line pairs of the flattened (active
+// right-hand side, line) list, one pair per wave (64/L pairs when L < 64).
+// dst = scale * conv(src) (+ add_coef * addv).
 template <int LG>
-__device__ void wg_line_pass(const double* src, double* dst, int nr, int64_t M, int m_line,
-                             int64_t S, const cplx<double>* tws, const double* lams,
-                             double scale, const double* addv, int64_t ldx, int64_t halo,
-                             double add_coef) {
+__device__ void pass_reg_direct(const double* src, double* dst, const int* act, int na,
+                                const PassGeom& pg, const cplx<double>* tws, const double* lams,
+                                double scale, const double* addv, double add_coef) {
     constexpr int L = 1 << LG;
     constexpr int R = line_regs<LG>();
     constexpr int G = L >= 64 ? 1 : 64 / L;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int e_lane = L >= 64 ? lane : (lane & (L - 1));
     const int g_lane = L >= 64 ? 0 : lane / L;
-    const int64_t lines_per_vec = M / m_line;
-    const int64_t nlines = lines_per_vec * nr;
+    const int64_t nlines = pg.per_vec * na;
     const int64_t npairs = (nlines + 1) / 2;
-    for (int64_t pb = (int64_t)wave * G; pb < npairs; pb += (int64_t)kBatchWaves * G) {
+    const int nw = blockDim.x >> 6;
+    for (int64_t pb = (int64_t)wave * G; pb < npairs; pb += (int64_t)nw * G) {
         const int64_t pair = pb + g_lane;
-        int64_t base[2];
-        int64_t abase[2];
+        int64_t base[2] = {0, 0}, abase[2] = {0, 0};
         bool ok[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int64_t l = 2 * pair + h;
             ok[h] = pair < npairs && l < nlines;
-            const int64_t r = ok[h] ? l / lines_per_vec : 0;
-            const int64_t li = ok[h] ? l - r * lines_per_vec : 0;
-            const int64_t outer = li / S, inner = li - outer * S;
-            const int64_t start = outer * m_line * S + inner;
-            base[h] = r * M + start;
-            abase[h] = r * ldx + halo + start;
+            if (ok[h]) {
+                const int64_t ri = l / pg.per_vec;
+                line_base(pg, act[ri], l - ri * pg.per_vec, base[h], abase[h]);
+            }
         }
         cplx<double> z[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const int e = q * 64 + e_lane;
-            const bool in = e < m_line;
-            z[q].re = (in && ok[0]) ? src[base[0] + e * S] : 0.0;
-            z[q].im = (in && ok[1]) ? src[base[1] + e * S] : 0.0;
+            const bool in = e < pg.m_line;
+            z[q].re = (in && ok[0]) ? src[base[0] + e * pg.S] : 0.0;
+            z[q].im = (in && ok[1]) ? src[base[1] + e * pg.S] : 0.0;
         }
         conv_line_regs<double, LG>(z, e_lane, tws, lams);
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const int e = q * 64 + e_lane;
-            if (e >= m_line) continue;
+            if (e >= pg.m_line) continue;
             if (ok[0]) {
                 double v = scale * z[q].re;
-                if (addv) v += add_coef * addv[abase[0] + e * S];
-                dst[base[0] + e * S] = v;
+                if (addv) v += add_coef * addv[abase[0] + e * pg.S];
+                dst[base[0] + e * pg.S] = v;
             }
             if (ok[1]) {
                 double v = scale * z[q].im;
-                if (addv) v += add_coef * addv[abase[1] + e * S];
-                dst[base[1] + e * S] = v;
+                if (addv) v += add_coef * addv[abase[1] + e * pg.S];
+                dst[base[1] + e * pg.S] = v;
             }
         }
     }
 }
 
-// Long lines: the workgroup convolves one line pair at a time with the
-// four-step FFT (tw1/tw2 in LDS, half-circle twiddles twh and the four-step
-// spectrum in global memory, Y: L complex scratch of this work item).
+// Strided lines (2-D, dimension 0: stride m1, m1 lines per vector) by the
+// register line FFT through an LDS transpose: blocks of kStrBlock adjacent
+// lines are loaded and stored with coalesced rows.  T: kStrBlock x (m0 + 1).
+template <int LG>
+__device__ void pass_reg_strided(const double* src, double* dst, const int* act, int na,
+                                 const PassGeom& pg, const cplx<double>* tws,
+                                 const double* lams, double scale, const double* addv,
+                                 double add_coef, double* T) {
+    constexpr int R = line_regs<LG>();
+    static_assert((1 << LG) >= 64, "strided pass expects lines of at least 32 nodes");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6, nt = blockDim.x;
+    const int m = pg.m_line;
+    const int ms = m + 1;
+    const int S = (int)pg.S;
+    const int nblk = (S + kStrBlock - 1) / kStrBlock;
+    for (int bi = 0; bi < na * nblk; ++bi) {
+        const int r = act[bi / nblk];
+        const int i0 = (bi % nblk) * kStrBlock;
+        const int nv = min(kStrBlock, S - i0);
+        const double* s0 = src + (int64_t)r * pg.M + i0;
+        for (int idx = threadIdx.x; idx < kStrBlock * m; idx += nt) {
+            const int e = idx / kStrBlock, l = idx - e * kStrBlock;
+            T[l * ms + e] = l < nv ? s0[(int64_t)e * S + l] : 0.0;
+        }
+        __syncthreads();
+        for (int pr = wave; pr < kStrBlock / 2; pr += nw) {
+            cplx<double> z[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int e = q * 64 + lane;
+                z[q].re = e < m ? T[(2 * pr) * ms + e] : 0.0;
+                z[q].im = e < m ? T[(2 * pr + 1) * ms + e] : 0.0;
+            }
+            conv_line_regs<double, LG>(z, lane, tws, lams);
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int e = q * 64 + lane;
+                if (e < m) {
+                    T[(2 * pr) * ms + e] = z[q].re;
+                    T[(2 * pr + 1) * ms + e] = z[q].im;
+                }
+            }
+        }
+        __syncthreads();
+        double* d0 = dst + (int64_t)r * pg.M + i0;
+        const double* a0 = addv ? addv + (int64_t)r * pg.ldr + pg.halo + i0 : nullptr;
+        for (int idx = threadIdx.x; idx < kStrBlock * m; idx += nt) {
+            const int e = idx / kStrBlock, l = idx - e * kStrBlock;
+            if (l < nv) {
+                double v = scale * T[l * ms + e];
+                if (a0) v += add_coef * a0[(int64_t)e * S + l];
+                d0[(int64_t)e * S + l] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Long lines by the four-step FFT, one line pair at a time for the whole
+// workgroup (Y: L complex scratch of this item).
 template <int LG1, int LG2>
-__device__ void wg_line_pass_long(const double* src, double* dst, int nr, int64_t M, int m_line,
-                                  int64_t S, const cplx<double>* tw1, const cplx<double>* tw2,
-                                  const cplx<double>* twh, const double* lamp, double scale,
-                                  const double* addv, int64_t ldx, int64_t halo, double add_coef,
-                                  cplx<double>* Y) {
-    const int64_t lines_per_vec = M / m_line;
-    const int64_t nlines = lines_per_vec * nr;
+__device__ void pass_long(const double* src, double* dst, const int* act, int na,
+                          const PassGeom& pg, const cplx<double>* tw1, const cplx<double>* tw2,
+                          const cplx<double>* twh, const double* lamp, double scale,
+                          const double* addv, double add_coef, cplx<double>* Y) {
+    const int64_t nlines = pg.per_vec * na;
     for (int64_t la = 0; la < nlines; la += 2) {
         int64_t base[2] = {0, 0}, abase[2] = {0, 0};
         const bool hb = la + 1 < nlines;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int64_t l = (h == 0 || hb) ? la + h : la;
-            const int64_t r = l / lines_per_vec;
-            const int64_t li = l - r * lines_per_vec;
-            const int64_t outer = li / S, inner = li - outer * S;
-            const int64_t start = outer * m_line * S + inner;
-            base[h] = r * M + start;
-            abase[h] = r * ldx + halo + start;
+            const int64_t ri = l / pg.per_vec;
+            line_base(pg, act[ri], l - ri * pg.per_vec, base[h], abase[h]);
         }
-        wg_conv_long<double, LG1, LG2>(src + base[0], hb ? src + base[1] : nullptr, S, m_line,
-                                       dst + base[0], hb ? dst + base[1] : nullptr, scale,
-                                       addv ? addv + abase[0] : nullptr,
+        wg_conv_long<double, LG1, LG2>(src + base[0], hb ? src + base[1] : nullptr, pg.S,
+                                       pg.m_line, dst + base[0], hb ? dst + base[1] : nullptr,
+                                       scale, addv ? addv + abase[0] : nullptr,
                                        (addv && hb) ? addv + abase[1] : nullptr, add_coef, Y,
                                        twh, lamp, tw1, tw2);
     }
 }
 
-__device__ void wg_line_pass_any(int lg, const double* src, double* dst, int nr, int64_t M,
-                                 int m_line, int64_t S, const cplx<double>* tws,
-                                 const double* lams, double scale, const double* addv,
-                                 int64_t ldx, int64_t halo, double add_coef,
-                                 const cplx<double>* tw2, const cplx<double>* twh,
-                                 cplx<double>* Y) {
-    switch (lg) {
-#define FKGP_WLL(LG, A, B)                                                                  \
+// Spectrum data of one dimension as the kernel sees it.
+struct DimSpec {
+    int lg;                       // log2 of the circulant length
+    const cplx<double>* tw;       // register path: L/2 twiddles (LDS); long: w_L1 (LDS)
+    const cplx<double>* tw2;      // long: w_L2 (LDS)
+    const cplx<double>* twh;      // long: w_L, t < L/2 (global)
+    const double* lam;            // register path: bit-reversed (LDS); long: four-step order
+};
+
+__device__ void line_pass(const DimSpec& ds, bool strided, const double* src, double* dst,
+                          const int* act, int na, const PassGeom& pg, double scale,
+                          const double* addv, double add_coef, double* T, cplx<double>* Y) {
+    if (ds.lg > kBatchRegMaxLog2) {
+        switch (ds.lg) {
+#define FKGP_BL(LG, A, B)                                                                   \
     case LG:                                                                                \
-        wg_line_pass_long<A, B>(src, dst, nr, M, m_line, S, tws, tw2, twh, lams, scale,     \
-                                addv, ldx, halo, add_coef, Y);                              \
+        pass_long<A, B>(src, dst, act, na, pg, ds.tw, ds.tw2, ds.twh, ds.lam, scale, addv,  \
+                        add_coef, Y);                                                       \
         break;
-        FKGP_WLL(12, 6, 6) FKGP_WLL(13, 6, 7) FKGP_WLL(14, 7, 7)
-#undef FKGP_WLL
-#define FKGP_WLP(LG)                                                                     \
-    case LG:                                                                             \
-        wg_line_pass<LG>(src, dst, nr, M, m_line, S, tws, lams, scale, addv, ldx, halo, \
-                         add_coef);                                                      \
+            FKGP_BL(9, 4, 5) FKGP_BL(10, 5, 5) FKGP_BL(11, 5, 6) FKGP_BL(12, 6, 6)
+            FKGP_BL(13, 6, 7) FKGP_BL(14, 7, 7)
+#undef FKGP_BL
+            default:
+                break;
+        }
+        return;
+    }
+    if (strided && ds.lg >= 6) {
+        switch (ds.lg) {
+#define FKGP_BS(LG)                                                                          \
+    case LG:                                                                                 \
+        pass_reg_strided<LG>(src, dst, act, na, pg, ds.tw, ds.lam, scale, addv, add_coef, T); \
         break;
-        FKGP_WLP(3) FKGP_WLP(4) FKGP_WLP(5) FKGP_WLP(6) FKGP_WLP(7) FKGP_WLP(8)
-        FKGP_WLP(9) FKGP_WLP(10) FKGP_WLP(11)
-#undef FKGP_WLP
+            FKGP_BS(6) FKGP_BS(7) FKGP_BS(8)
+#undef FKGP_BS
+            default:
+                break;
+        }
+        return;
+    }
+    switch (ds.lg) {
+#define FKGP_BC(LG)                                                                          \
+    case LG:                                                                                 \
+        pass_reg_direct<LG>(src, dst, act, na, pg, ds.tw, ds.lam, scale, addv, add_coef);    \
+        break;
+        FKGP_BC(3) FKGP_BC(4) FKGP_BC(5) FKGP_BC(6) FKGP_BC(7) FKGP_BC(8)
+#undef FKGP_BC
         default:
             break;
     }
 }
 
-template <class TA>
-__device__ void wg_spmv(const TA* __restrict__ A, const double* __restrict__ rp,
-                        double* __restrict__ ur, int nr, const int* done, int64_t M,
-                        int64_t ldx, int64_t halo, int NB, const int* offs) {
-    for (int64_t j = threadIdx.x; j < M; j += kBatchBlock) {
-        double acc[kBatchRhs];
+// (C): u_r = W^T W r_hat for the active right-hand sides, RW = 2
+// consecutive rows per thread (eight x values per stencil row serve 2 x 7
+// products; wider blocks cost more registers than the saved loads are
+// worth); v[2r] += r_hat.u_r, v[2r+1] += r_hat.b_hat over those rows.
+template <int NR, class TA, int D>
+__device__ void spmv_rows(const TA* __restrict__ A, const double* rp, double* ur,
+                          const double* bh, const int* done, int nr, int64_t M, int64_t ldr,
+                          int64_t halo, int m1, double (&v)[2 * NR]) {
+    constexpr int RW = 2;
+    constexpr int NB = D == 1 ? 7 : 49;
+    constexpr int NA = D == 1 ? 1 : 7;
+    const int64_t nq = (M + RW - 1) / RW;
+#pragma unroll 1
+    for (int64_t qd = threadIdx.x; qd < nq; qd += blockDim.x) {
+        const int64_t j0 = RW * qd;
+        const TA* At = A + ((j0 / kRowTile) * NB) * kRowTile + (j0 % kRowTile);
+        double acc[NR][RW];
 #pragma unroll
-        for (int r = 0; r < kBatchRhs; ++r) acc[r] = 0.0;
-        const double* xj = rp + halo + j;
-        for (int o = 0; o < NB; ++o) {
-            const double a = (double)A[dia_index(j, o, NB)];
-            const int off = offs[o];
+        for (int r = 0; r < NR; ++r)
 #pragma unroll
-            for (int r = 0; r < kBatchRhs; ++r)
-                if (r < nr) acc[r] = fma(a, xj[r * ldx + off], acc[r]);
+            for (int q = 0; q < RW; ++q) acc[r][q] = 0.0;
+#pragma unroll 1
+        for (int a = 0; a < NA; ++a) {
+            double av[7][RW];
+#pragma unroll
+            for (int b = 0; b < 7; ++b) {
+                const TA* ap = At + (a * 7 + b) * kRowTile;
+#pragma unroll
+                for (int q = 0; q < RW; ++q) av[b][q] = (double)ap[q];
+            }
+            const int64_t off = (D == 1 ? 0 : (int64_t)(a - 3) * m1) - 3;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (r >= nr || done[r]) continue;
+                const double* xb = rp + r * ldr + halo + j0 + off;
+                double xv[RW + 6];
+#pragma unroll
+                for (int c = 0; c < RW + 6; ++c) xv[c] = xb[c];
+#pragma unroll
+                for (int b = 0; b < 7; ++b)
+#pragma unroll
+                    for (int q = 0; q < RW; ++q) acc[r][q] = fma(av[b][q], xv[q + b], acc[r][q]);
+            }
         }
 #pragma unroll
-        for (int r = 0; r < kBatchRhs; ++r)
-            if (r < nr && !done[r]) ur[r * M + j] = acc[r];
+        for (int r = 0; r < NR; ++r) {
+            if (r >= nr || done[r]) continue;
+            const double* xc = rp + r * ldr + halo + j0;
+#pragma unroll
+            for (int q = 0; q < RW; ++q) {
+                if (j0 + q < M) {
+                    ur[r * M + j0 + q] = acc[r][q];
+                    v[2 * r] = fma(xc[q], acc[r][q], v[2 * r]);
+                    v[2 * r + 1] = fma(xc[q], bh[r * M + j0 + q], v[2 * r + 1]);
+                }
+            }
+        }
     }
 }
 
-__global__ __launch_bounds__(kBatchBlock) void batch_cg_kernel(const BatchProb* __restrict__ probs,
-                                                               const BatchItem* __restrict__ items,
-                                                               double tol, int maxiter) {
-    extern __shared__ unsigned char lds_raw[];
-    __shared__ double red[2 * kBatchRhs * kBatchWaves];
-    __shared__ double sums[2 * kBatchRhs];
-    __shared__ double rho[kBatchRhs], cr[kBatchRhs], cp[kBatchRhs], cx[kBatchRhs],
-        pb[kBatchRhs], alpha[kBatchRhs], beta[kBatchRhs], eps[kBatchRhs];
-    __shared__ int done[kBatchRhs], iters[kBatchRhs];
-    __shared__ int offs[49];
-    __shared__ int all_done;
+// BB threads per work item (256 or 512); the register budget allows two
+// waves per SIMD (two 256-thread items or one 512-thread item per CU).
+template <int NR, int BB>
+__global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __restrict__ probs,
+                                                         const BatchItem* __restrict__ items,
+                                                         double tol, int maxiter) {
+    constexpr int kBB = BB;
+    extern __shared__ double lds_dyn[];
+    __shared__ double red[2 * NR * kMaxWaves];
+    __shared__ double sums[2 * NR];
+    __shared__ double rho[NR], cr[NR], cp[NR], cx[NR], pb[NR], alpha[NR], beta[NR], eps[NR];
+    __shared__ double bb[NR];   // ||b||^2 of each right-hand side (y^T y, or n for a probe)
+    __shared__ int done[NR], iters[NR];
 
     const BatchItem it = items[blockIdx.x];
     const BatchProb P = probs[it.prob];
     const int nr = it.nr;
-    const int64_t M = P.M, halo = P.halo, ldx = M + 2 * halo;
+    const int64_t M = P.M, halo = P.halo, ldr = batch_rhat_stride(M, halo);
     const int tid = threadIdx.x;
-    // spectra of both dimensions into LDS (long lines: only the twiddles of
-    // the two four-step sub-lengths; spectrum and w_L stay in global memory)
-    cplx<double>* tws[2] = {nullptr, nullptr};
-    cplx<double>* tw2s[2] = {nullptr, nullptr};
-    const cplx<double>* twhs[2] = {nullptr, nullptr};
-    const double* lams[2] = {nullptr, nullptr};
+    // spectra into LDS (long dimensions: only the sub-length twiddles)
+    DimSpec dsp[2] = {};
+    double* T = nullptr;
     {
-        unsigned char* p = lds_raw;
+        unsigned char* p = reinterpret_cast<unsigned char*>(lds_dyn);
         for (int k = 0; k < P.d; ++k) {
-            const int L = 1 << P.log2L[k];
+            const int lg = P.log2L[k], L = 1 << lg;
             const cplx<double>* twg = static_cast<const cplx<double>*>(P.tw[k]);
-            if (P.log2L[k] > kMaxRegLog2) {
+            DimSpec& ds = dsp[k];
+            ds.lg = lg;
+            if (lg > kBatchRegMaxLog2) {
                 int lg1, lg2;
-                long_split(P.log2L[k], lg1, lg2);
+                long_split(lg, lg1, lg2);
                 const int L1 = 1 << lg1, L2 = 1 << lg2;
-                tws[k] = reinterpret_cast<cplx<double>*>(p);
+                cplx<double>* t1 = reinterpret_cast<cplx<double>*>(p);
                 p += sizeof(cplx<double>) * (L1 / 2);
-                tw2s[k] = reinterpret_cast<cplx<double>*>(p);
+                cplx<double>* t2 = reinterpret_cast<cplx<double>*>(p);
                 p += sizeof(cplx<double>) * (L2 / 2);
-                for (int i = tid; i < L1 / 2; i += kBatchBlock) tws[k][i] = twg[i * L2];
-                for (int i = tid; i < L2 / 2; i += kBatchBlock) tw2s[k][i] = twg[i * L1];
-                twhs[k] = twg;
-                lams[k] = P.lam[k];
+                for (int i = tid; i < L1 / 2; i += kBB) t1[i] = twg[i * L2];
+                for (int i = tid; i < L2 / 2; i += kBB) t2[i] = twg[i * L1];
+                ds.tw = t1;
+                ds.tw2 = t2;
+                ds.twh = twg;
+                ds.lam = P.lam[k];
             } else {
-                tws[k] = reinterpret_cast<cplx<double>*>(p);
+                cplx<double>* t = reinterpret_cast<cplx<double>*>(p);
                 p += sizeof(cplx<double>) * (L / 2);
                 double* lm = reinterpret_cast<double*>(p);
                 p += sizeof(double) * L;
-                for (int i = tid; i < L / 2; i += kBatchBlock) tws[k][i] = twg[i];
-                for (int i = tid; i < L; i += kBatchBlock) lm[i] = P.lam[k][i];
-                lams[k] = lm;
+                for (int i = tid; i < L / 2; i += kBB) t[i] = twg[i];
+                for (int i = tid; i < L; i += kBB) lm[i] = P.lam[k][i];
+                ds.tw = t;
+                ds.tw2 = nullptr;
+                ds.twh = nullptr;
+                ds.lam = lm;
             }
         }
-    }
-    if (tid < P.NB) {
-        int o = tid, off = 0;
-        if (P.d == 1) {
-            off = o - 3;
-        } else {
-            off = (o / 7 - 3) * P.m[1] + (o % 7 - 3);
-        }
-        offs[tid] = off;
+        T = reinterpret_cast<double*>(p);   // strided-pass transpose block
     }
     // vectors of this item
-    double* rp = it.work;                  // [nr][ldx] padded r_hat
-    double* ap = rp + (int64_t)kBatchRhs * ldx;
-    double* sp = ap + kBatchRhs * M;
-    double* zp = sp + kBatchRhs * M;
-    double* ux = zp + kBatchRhs * M;
-    double* ur = ux + kBatchRhs * M;
-    double* vr = ur + kBatchRhs * M;
+    double* rp = it.work;                        // [NR][ldr] padded r_hat
+    double* sp = rp + (int64_t)NR * ldr;         // [NR][M] each
+    double* zp = sp + NR * M;
+    double* ux = zp + NR * M;
+    double* ur = ux + NR * M;
+    double* vr = ur + NR * M;
     const double* bh = P.bh + (int64_t)it.r0 * M;
     const double* kb = P.kb + (int64_t)it.r0 * M;
-    for (int64_t i = tid; i < (int64_t)kBatchRhs * ldx; i += kBatchBlock) rp[i] = 0.0;
-    for (int64_t i = tid; i < (int64_t)kBatchRhs * M; i += kBatchBlock) {
-        sp[i] = 0.0;
-        zp[i] = 0.0;
-        ux[i] = 0.0;
-    }
-    if (tid < kBatchRhs) {
+#pragma unroll 1
+    for (int64_t i = tid; i < (int64_t)NR * ldr; i += kBB) rp[i] = 0.0;
+#pragma unroll 1
+    for (int64_t i = tid; i < (int64_t)5 * NR * M; i += kBB) sp[i] = 0.0;
+    if (tid < NR) {
         const bool act = tid < nr;
         const double bn = act ? P.bnorm2[it.r0 + tid] : 0.0;
         rho[tid] = bn;
+        bb[tid] = bn;
         cr[tid] = 1.0;
         cp[tid] = 1.0;
         cx[tid] = 0.0;
@@ -279,37 +416,68 @@ __global__ __launch_bounds__(kBatchBlock) void batch_cg_kernel(const BatchProb* 
     }
     __syncthreads();
 
+    PassGeom pg1{}, pg0{};
+    if (P.d == 1) {
+        pg0 = PassGeom{P.m[0], 1, 1, M, ldr, halo};
+    } else {
+        pg1 = PassGeom{P.m[1], 1, P.m[0], M, ldr, halo};
+        pg0 = PassGeom{P.m[0], P.m[1], P.m[1], M, ldr, halo};
+    }
+
     for (int iter = 0; iter < maxiter; ++iter) {
-        if (tid == 0) {
-            int a = 1;
-            for (int r = 0; r < nr; ++r) a &= done[r];
-            all_done = a;
-        }
-        __syncthreads();
-        if (all_done) break;
-        // ap = z_p + c_p kappa_b; s_p.ap and ap.b_hat
+        int act[NR];
+        int na = 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if (r < nr && !done[r]) act[na++] = r;
+        if (na == 0) break;
+        // (A) direction update (beta = 0, u_r = v_r = 0 on the first pass)
         {
-            double v[2 * kBatchRhs];
+            double v[2 * NR];
 #pragma unroll
-            for (int k = 0; k < 2 * kBatchRhs; ++k) v[k] = 0.0;
+            for (int k = 0; k < 2 * NR; ++k) v[k] = 0.0;
 #pragma unroll
-            for (int r = 0; r < kBatchRhs; ++r) {
+            for (int r = 0; r < NR; ++r) {
                 if (r >= nr || done[r]) continue;
-                const double c = cp[r];
-                for (int64_t i = tid; i < M; i += kBatchBlock) {
-                    const double a = fma(c, kb[r * M + i], zp[r * M + i]);
-                    ap[r * M + i] = a;
-                    v[2 * r] = fma(sp[r * M + i], a, v[2 * r]);
-                    v[2 * r + 1] = fma(a, bh[r * M + i], v[2 * r + 1]);
+                const double b = beta[r], c = cp[r];
+                double* spr = sp + r * M;
+                double* zpr = zp + r * M;
+                const double* urr = ur + r * M;
+                const double* vrr = vr + r * M;
+                const double* kbr = kb + r * M;
+                const double* bhr = bh + r * M;
+#pragma unroll 1
+                for (int64_t i0 = tid; i0 < M; i0 += 4 * kBB) {
+                    double s[4], z[4], k4[4], b4[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t i = i0 + u * kBB;
+                        const bool in = i < M;
+                        s[u] = in ? fma(b, spr[i], urr[i]) : 0.0;
+                        z[u] = in ? fma(b, zpr[i], vrr[i]) : 0.0;
+                        k4[u] = in ? kbr[i] : 0.0;
+                        b4[u] = in ? bhr[i] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t i = i0 + u * kBB;
+                        if (i < M) {
+                            spr[i] = s[u];
+                            zpr[i] = z[u];
+                        }
+                        const double a = fma(c, k4[u], z[u]);
+                        v[2 * r] = fma(s[u], a, v[2 * r]);
+                        v[2 * r + 1] = fma(a, b4[u], v[2 * r + 1]);
+                    }
                 }
             }
-            wg_sum<2 * kBatchRhs>(v, red, sums);
+            wg_sum<2 * NR>(v, red, sums);
         }
         if (tid < nr && !done[tid]) {
             const int r = tid;
             const double apc = P.s2 * cp[r];
             const double pap = sums[2 * r] + apc * pb[r] + cp[r] * sums[2 * r + 1] +
-                               cp[r] * apc * P.n;
+                               cp[r] * apc * bb[r];
             const double a = rho[r] / pap;
             if (!isfinite(a)) {
                 done[r] = 2;
@@ -321,56 +489,63 @@ __global__ __launch_bounds__(kBatchBlock) void batch_cg_kernel(const BatchProb* 
             }
         }
         __syncthreads();
-        // u_x += alpha s_p; r_hat -= alpha ap
+        // (B) u_x += alpha s_p; r_hat -= alpha (z_p + c_p kappa_b)
 #pragma unroll
-        for (int r = 0; r < kBatchRhs; ++r) {
+        for (int r = 0; r < NR; ++r) {
             if (r >= nr || done[r]) continue;
-            const double a = alpha[r];
-            for (int64_t i = tid; i < M; i += kBatchBlock) {
-                ux[r * M + i] = fma(a, sp[r * M + i], ux[r * M + i]);
-                rp[r * ldx + halo + i] = fma(-a, ap[r * M + i], rp[r * ldx + halo + i]);
-            }
-        }
-        __syncthreads();
-        // u_r = W^T W r_hat
-        if (P.a_f32)
-            wg_spmv<float>(static_cast<const float*>(P.A), rp, ur, nr, done, M, ldx, halo, P.NB,
-                           offs);
-        else
-            wg_spmv<double>(static_cast<const double*>(P.A), rp, ur, nr, done, M, ldx, halo,
-                            P.NB, offs);
-        __syncthreads();
-        // v_r = s K u_r + s2 r_hat
-        if (P.d == 1) {
-            wg_line_pass_any(P.log2L[0], ur, vr, nr, M, P.m[0], 1, tws[0], lams[0], P.so, rp,
-                             ldx, halo, P.s2, tw2s[0], twhs[0], it.yscr);
-        } else {
-            wg_line_pass_any(P.log2L[1], ur, vr, nr, M, P.m[1], 1, tws[1], lams[1], 1.0,
-                             nullptr, ldx, halo, 0.0, tw2s[1], twhs[1], it.yscr);
-            __syncthreads();
-            wg_line_pass_any(P.log2L[0], vr, vr, nr, M, P.m[0], P.m[1], tws[0], lams[0], P.so,
-                             rp, ldx, halo, P.s2, tw2s[0], twhs[0], it.yscr);
-        }
-        __syncthreads();
-        // rho' = <r, r>, beta
-        {
-            double v[2 * kBatchRhs];
+            const double a = alpha[r], c = cp[r];
+            const double* spr = sp + r * M;
+            const double* zpr = zp + r * M;
+            const double* kbr = kb + r * M;
+            double* uxr = ux + r * M;
+            double* rpr = rp + r * ldr + halo;
+#pragma unroll 1
+            for (int64_t i0 = tid; i0 < M; i0 += 4 * kBB) {
+                double xs[4], xr[4];
 #pragma unroll
-            for (int k = 0; k < 2 * kBatchRhs; ++k) v[k] = 0.0;
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t i = i0 + u * kBB;
+                    const bool in = i < M;
+                    xs[u] = in ? fma(a, spr[i], uxr[i]) : 0.0;
+                    xr[u] = in ? fma(-a, fma(c, kbr[i], zpr[i]), rpr[i]) : 0.0;
+                }
 #pragma unroll
-            for (int r = 0; r < kBatchRhs; ++r) {
-                if (r >= nr || done[r]) continue;
-                for (int64_t i = tid; i < M; i += kBatchBlock) {
-                    const double x = rp[r * ldx + halo + i];
-                    v[2 * r] = fma(x, ur[r * M + i], v[2 * r]);
-                    v[2 * r + 1] = fma(x, bh[r * M + i], v[2 * r + 1]);
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t i = i0 + u * kBB;
+                    if (i < M) {
+                        uxr[i] = xs[u];
+                        rpr[i] = xr[u];
+                    }
                 }
             }
-            wg_sum<2 * kBatchRhs>(v, red, sums);
         }
+        __syncthreads();
+        // (C) u_r = W^T W r_hat with the dots r_hat.u_r and r_hat.b_hat
+        {
+            double v[2 * NR];
+#pragma unroll
+            for (int k = 0; k < 2 * NR; ++k) v[k] = 0.0;
+            if (P.d == 1) {
+                if (P.a_f32)
+                    spmv_rows<NR, float, 1>(static_cast<const float*>(P.A), rp, ur, bh, done,
+                                             nr, M, ldr, halo, 1, v);
+                else
+                    spmv_rows<NR, double, 1>(static_cast<const double*>(P.A), rp, ur, bh,
+                                              done, nr, M, ldr, halo, 1, v);
+            } else {
+                if (P.a_f32)
+                    spmv_rows<NR, float, 2>(static_cast<const float*>(P.A), rp, ur, bh, done,
+                                             nr, M, ldr, halo, P.m[1], v);
+                else
+                    spmv_rows<NR, double, 2>(static_cast<const double*>(P.A), rp, ur, bh,
+                                              done, nr, M, ldr, halo, P.m[1], v);
+            }
+            wg_sum<2 * NR>(v, red, sums);
+        }
+        // rho' = <r, r>, convergence, beta
         if (tid < nr && !done[tid]) {
             const int r = tid;
-            const double rn = sums[2 * r] + 2.0 * cr[r] * sums[2 * r + 1] + cr[r] * cr[r] * P.n;
+            const double rn = sums[2 * r] + 2.0 * cr[r] * sums[2 * r + 1] + cr[r] * cr[r] * bb[r];
             iters[r] += 1;
             if (!(rn > eps[r])) {
                 done[r] = 1;
@@ -386,25 +561,30 @@ __global__ __launch_bounds__(kBatchBlock) void batch_cg_kernel(const BatchProb* 
             }
         }
         __syncthreads();
-        // s_p = u_r + beta s_p; z_p = v_r + beta z_p
+        // (D) v_r = s K_G u_r + s2 r_hat for the right-hand sides still active
+        na = 0;
 #pragma unroll
-        for (int r = 0; r < kBatchRhs; ++r) {
-            if (r >= nr || done[r]) continue;
-            const double b = beta[r];
-            for (int64_t i = tid; i < M; i += kBatchBlock) {
-                sp[r * M + i] = fma(b, sp[r * M + i], ur[r * M + i]);
-                zp[r * M + i] = fma(b, zp[r * M + i], vr[r * M + i]);
+        for (int r = 0; r < NR; ++r)
+            if (r < nr && !done[r]) act[na++] = r;
+        if (na > 0) {
+            if (P.d == 1) {
+                line_pass(dsp[0], false, ur, vr, act, na, pg0, P.so, rp, P.s2, T, it.yscr);
+            } else {
+                line_pass(dsp[1], false, ur, vr, act, na, pg1, 1.0, nullptr, 0.0, T, it.yscr);
+                __syncthreads();
+                line_pass(dsp[0], true, vr, vr, act, na, pg0, P.so, rp, P.s2, T, it.yscr);
             }
         }
         __syncthreads();
     }
     // outputs: W^T x = u_x + c_x b_hat, and the final states
 #pragma unroll
-    for (int r = 0; r < kBatchRhs; ++r) {
+    for (int r = 0; r < NR; ++r) {
         if (r >= nr) continue;
         const double c = cx[r];
         double* out = P.wx + (int64_t)(it.r0 + r) * M;
-        for (int64_t i = tid; i < M; i += kBatchBlock) out[i] = fma(c, bh[r * M + i], ux[r * M + i]);
+#pragma unroll 1
+        for (int64_t i = tid; i < M; i += kBB) out[i] = fma(c, bh[r * M + i], ux[r * M + i]);
     }
     if (tid < nr) {
         PState s{};
@@ -422,21 +602,62 @@ __global__ __launch_bounds__(kBatchBlock) void batch_cg_kernel(const BatchProb* 
     }
 }
 
+template <int NR, int BB>
+fkgp_status launch_nr(const BatchProb* probs, const BatchItem* items, int nitems, size_t lds,
+                      double tol, int maxiter, hipStream_t s) {
+    if (lds > 64 * 1024)
+        FKGP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_cg_kernel<NR, BB>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    batch_cg_kernel<NR, BB><<<nitems, BB, lds, s>>>(probs, items, tol, maxiter);
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
 }  // namespace
 
-size_t batch_work_doubles(int64_t M, int64_t halo) {
-    return (size_t)kBatchRhs * (M + 2 * halo) + (size_t)6 * kBatchRhs * M;
+size_t batch_work_doubles(int64_t M, int64_t halo, int nr) {
+    return (size_t)nr * batch_rhat_stride(M, halo) + (size_t)5 * nr * M;
+}
+
+size_t batch_lds_bytes(int d, const int* m, const int* log2L) {
+    size_t l = 0;
+    for (int k = 0; k < d; ++k) {
+        if (log2L[k] > kBatchRegMaxLog2) {
+            int lg1, lg2;
+            long_split(log2L[k], lg1, lg2);
+            l += (size_t)8 * ((1 << lg1) + (1 << lg2));   // both sub-length twiddles
+        } else {
+            l += (size_t)16 * (1 << log2L[k]);            // twiddles + spectrum
+        }
+    }
+    if (d == 2 && log2L[0] <= kBatchRegMaxLog2)
+        l += (size_t)8 * kStrBlock * (m[0] + 1);          // strided-pass transpose
+    return l;
 }
 
 fkgp_status launch_batch_cg(const BatchProb* probs_dev, const BatchItem* items_dev, int nitems,
-                            size_t lds, double tol, int maxiter, hipStream_t s) {
+                            size_t lds, double tol, int maxiter, int nr, int block,
+                            hipStream_t s) {
     if (nitems == 0) return FKGP_OK;
-    if (lds > 64 * 1024)
-        FKGP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_cg_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    batch_cg_kernel<<<nitems, kBatchBlock, lds, s>>>(probs_dev, items_dev, tol, maxiter);
-    FKGP_HIP(hipGetLastError());
-    return FKGP_OK;
+    const int key = nr * 1000 + block;
+    switch (key) {
+        case 2256:
+            return launch_nr<2, 256>(probs_dev, items_dev, nitems, lds, tol, maxiter, s);
+        case 4256:
+            return launch_nr<4, 256>(probs_dev, items_dev, nitems, lds, tol, maxiter, s);
+        case 8256:
+            return launch_nr<8, 256>(probs_dev, items_dev, nitems, lds, tol, maxiter, s);
+        case 2512:
+            return launch_nr<2, 512>(probs_dev, items_dev, nitems, lds, tol, maxiter, s);
+        case 4512:
+            return launch_nr<4, 512>(probs_dev, items_dev, nitems, lds, tol, maxiter, s);
+        case 8512:
+            return launch_nr<8, 512>(probs_dev, items_dev, nitems, lds, tol, maxiter, s);
+        default:
+            set_error("batched solver: right-hand sides per item must be 2, 4 or 8 and the "
+                      "workgroup 256 or 512 threads");
+            return FKGP_EINVAL;
+    }
 }
 
 }  // namespace fkgp

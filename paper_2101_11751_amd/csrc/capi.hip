@@ -11,6 +11,8 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -299,8 +301,10 @@ fkgp_status check_hypers(const fkgp_handle* h, const fkgp_hypers* hyp) {
 }
 
 // Spectra in dtype `dt` (derivative column for dimension `dderiv`, or none).
+// Circulants longer than 2^reg_max take the four-step order; the standalone
+// passes (reg_max = kMaxRegLog2) also get their four-step scratch.
 fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtype dt, int dderiv,
-                         Spectra& sp, Scratch& sc) {
+                         Spectra& sp, Scratch& sc, int reg_max = kMaxRegLog2) {
     std::memset(&sp, 0, sizeof(sp));
     const size_t es = dsize(dt);
     for (int k = 0; k < h->g.d; ++k) {
@@ -313,13 +317,17 @@ fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtyp
         unsigned char *lam = nullptr, *tw = nullptr;
         FKGP_HIP(sc.get(&lam, es * sp.L[k]));
         FKGP_HIP(sc.get(&tw, 2 * es * (sp.L[k] / 2)));
-        if (sp.log2L[k] > kMaxRegLog2) {
-            unsigned char* scr = nullptr;
-            FKGP_HIP(sc.get(&scr, 2 * es * (size_t)sp.L[k] * kLongWGs));
-            sp.scr[k] = scr;
+        if (sp.log2L[k] > reg_max) {
+            int lg2;
+            long_split(sp.log2L[k], sp.lg1[k], lg2);
+            if (reg_max == kMaxRegLog2) {
+                unsigned char* scr = nullptr;
+                FKGP_HIP(sc.get(&scr, 2 * es * (size_t)sp.L[k] * kLongWGs));
+                sp.scr[k] = scr;
+            }
         }
-        fkgp_status st =
-            build_spectrum(h->g, k, hyp->lengthscale[k], k == dderiv, dt, lam, sp.log2L[k], sc.s);
+        fkgp_status st = build_spectrum(h->g, k, hyp->lengthscale[k], k == dderiv, dt, lam,
+                                        sp.log2L[k], sp.lg1[k], sc.s);
         if (st != FKGP_OK) return st;
         st = build_twiddles(sp.log2L[k], dt, tw, sc.s);
         if (st != FKGP_OK) return st;
@@ -1543,6 +1551,61 @@ fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_ml
     return (sres == FKGP_ENOTCONV || pres == FKGP_ENOTCONV) ? FKGP_ENOTCONV : FKGP_OK;
 }
 
+// Work items of a batch for NR right-hand sides per item (device arrays in
+// `sc`): each problem's right-hand sides in groups of NR, each group with its
+// own vectors and, for four-step lines, its own L-point scratch.
+fkgp_status build_batch_items(const std::vector<BatchProb>& probs, const std::vector<int>& nrhs,
+                              const std::vector<int>& long_L, int NR, Scratch& sc,
+                              BatchItem** items_dev, int& nitems) {
+    std::vector<BatchItem> items;
+    for (size_t p = 0; p < probs.size(); ++p) {
+        const size_t wd = batch_work_doubles(probs[p].M, probs[p].halo, NR);
+        for (int r0 = 0; r0 < nrhs[p]; r0 += NR) {
+            double* work = nullptr;
+            FKGP_HIP(sc.get(&work, wd));
+            double* yscr = nullptr;
+            if (long_L[p] > 0) FKGP_HIP(sc.get(&yscr, (size_t)2 * long_L[p]));
+            items.push_back(BatchItem{(int)p, r0, std::min(NR, nrhs[p] - r0), work,
+                                      reinterpret_cast<cplx<double>*>(yscr)});
+        }
+    }
+    nitems = (int)items.size();
+    FKGP_HIP(sc.get(items_dev, items.size()));
+    FKGP_HIP(hipMemcpyAsync(*items_dev, items.data(), sizeof(BatchItem) * items.size(),
+                            hipMemcpyHostToDevice, sc.s));
+    FKGP_HIP(hipStreamSynchronize(sc.s));   // `items` leaves scope
+    return FKGP_OK;
+}
+
+// Autotuner of the batched solver.  Two tile parameters: the number of
+// right-hand sides per work item (2, 4 or 8) trades per-item work and W^T W
+// re-reads against the number of co-resident workgroups and the load
+// balance at the tail; the workgroup size (256 or 512 threads) trades
+// latency hiding inside an item against items per CU.  Each candidate runs
+// a short trial (the first iterations of the real solve, whose state the
+// real launch re-initialises) timed with HIP events; the fastest per batch
+// shape (problem sizes, right-hand sides, stats dtype) is cached for the
+// life of the process.
+struct BatchTile {
+    int nr, block;
+};
+std::mutex g_tune_mu;
+std::map<std::string, BatchTile> g_tune_cache;
+constexpr BatchTile kTuneCandidates[6] = {{8, 256}, {4, 256}, {2, 256},
+                                          {8, 512}, {4, 512}, {2, 512}};
+constexpr int kTuneIters = 16;
+
+std::string batch_shape_key(const fkgp_handle* const* hs, int np) {
+    std::string key;
+    for (int p = 0; p < np; ++p) {
+        const fkgp_handle* h = hs[p];
+        key += std::to_string(h->g.d);
+        for (int k = 0; k < h->g.d; ++k) key += "x" + std::to_string(h->g.m[k]);
+        key += "r" + std::to_string(h->nprobe + 1) + (h->dt == FKGP_F32 ? "f;" : "d;");
+    }
+    return key;
+}
+
 // Many problems in one persistent launch: for each problem the right-hand
 // sides [y, z_0 .. z_{N-1}] all use the factorized CG from x_0 = 0.
 fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hypers* hyps,
@@ -1550,8 +1613,9 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
                            fkgp_mll_info* infos, hipStream_t st) {
     Scratch sc(st);
     std::vector<OpCtx> ctx(np);
+    std::vector<Spectra> bsp(np);
     std::vector<BatchProb> probs(np);
-    std::vector<BatchItem> items;
+    std::vector<int> nrhs_v(np), long_L(np, 0);
     std::vector<double*> Vs(np), wxs(np), alph(np), bet(np);
     std::vector<PState*> pss(np);
     size_t lds = 0;
@@ -1559,9 +1623,13 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
         const fkgp_handle* h = hs[p];
         fkgp_status rs = make_ctx(h, &hyps[p], FKGP_F64, ctx[p], sc);
         if (rs != FKGP_OK) return rs;
+        // the batched kernel's own spectra: register order up to 512 points
+        rs = make_spectra(h, &hyps[p], FKGP_F64, -1, bsp[p], sc, kBatchRegMaxLog2);
+        if (rs != FKGP_OK) return rs;
         const OpCtx& c = ctx[p];
         const int N = h->nprobe, nrhs = N + 1;
         const int64_t M = h->M;
+        nrhs_v[p] = nrhs;
         double *bh, *kb, *bn, *V, *wx, *al, *be;
         PState* ps;
         FKGP_HIP(sc.get(&bh, M * nrhs));
@@ -1588,28 +1656,18 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
         P.M = M;
         P.halo = c.halo;
         P.NB = h->NB;
-        size_t l = 0;
-        int long_L = 0;   // longest circulant taking the four-step path
         for (int k = 0; k < 2; ++k) {
-            P.log2L[k] = k < h->g.d ? c.sp64.log2L[k] : 0;
-            P.tw[k] = k < h->g.d ? c.sp64.tw[k] : nullptr;
-            P.lam[k] = k < h->g.d ? static_cast<const double*>(c.sp64.lam[k]) : nullptr;
-            if (k >= h->g.d) continue;
-            if (P.log2L[k] > kMaxRegLog2) {
-                int lg1, lg2;
-                long_split(P.log2L[k], lg1, lg2);
-                l += (size_t)8 * ((1 << lg1) + (1 << lg2));   // both sub-length twiddles
-                long_L = std::max(long_L, 1 << P.log2L[k]);
-            } else {
-                l += (size_t)16 * (1 << P.log2L[k]);          // twiddles + spectrum
-            }
+            P.log2L[k] = k < h->g.d ? bsp[p].log2L[k] : 0;
+            P.tw[k] = k < h->g.d ? bsp[p].tw[k] : nullptr;
+            P.lam[k] = k < h->g.d ? static_cast<const double*>(bsp[p].lam[k]) : nullptr;
+            if (k < h->g.d && P.log2L[k] > kBatchRegMaxLog2)
+                long_L[p] = std::max(long_L[p], 1 << P.log2L[k]);
         }
-        lds = std::max(lds, l);
+        lds = std::max(lds, batch_lds_bytes(P.d, P.m, P.log2L));
         P.a_f32 = h->dt == FKGP_F32 ? 1 : 0;
         P.A = h->A;
         P.so = c.so;
         P.s2 = c.s2;
-        P.n = (double)h->n;
         P.bh = bh;
         P.kb = kb;
         P.bnorm2 = bn;
@@ -1622,26 +1680,76 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
         alph[p] = al;
         bet[p] = be;
         pss[p] = ps;
-        const size_t wd = batch_work_doubles(M, c.halo);
-        for (int r0 = 0; r0 < nrhs; r0 += kBatchRhs) {
-            double* work = nullptr;
-            FKGP_HIP(sc.get(&work, wd));
-            double* yscr = nullptr;
-            if (long_L > 0) FKGP_HIP(sc.get(&yscr, (size_t)2 * long_L));
-            items.push_back(BatchItem{p, r0, std::min(kBatchRhs, nrhs - r0), work,
-                                      reinterpret_cast<cplx<double>*>(yscr)});
-        }
     }
     BatchProb* probs_dev = nullptr;
-    BatchItem* items_dev = nullptr;
     FKGP_HIP(sc.get(&probs_dev, np));
-    FKGP_HIP(sc.get(&items_dev, items.size()));
     FKGP_HIP(hipMemcpyAsync(probs_dev, probs.data(), sizeof(BatchProb) * np,
                             hipMemcpyHostToDevice, st));
-    FKGP_HIP(hipMemcpyAsync(items_dev, items.data(), sizeof(BatchItem) * items.size(),
-                            hipMemcpyHostToDevice, st));
-    fkgp_status rs = launch_batch_cg(probs_dev, items_dev, (int)items.size(), lds, o.tol,
-                                     o.maxiter, st);
+    // tile: forced, cached or tuned
+    BatchTile tile{o.batch_rhs, o.batch_block};
+    if (tile.nr == 0 || tile.block == 0) {
+        const std::string key = batch_shape_key(hs, np) + "/" + std::to_string(o.batch_rhs) +
+                                "/" + std::to_string(o.batch_block);
+        bool have = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto f = g_tune_cache.find(key);
+            if (f != g_tune_cache.end()) {
+                tile = f->second;
+                have = true;
+            }
+        }
+        if (!have) {
+            float best = 0.0f;
+            BatchTile chosen{0, 0};
+            hipEvent_t e0, e1;
+            FKGP_HIP(hipEventCreate(&e0));
+            FKGP_HIP(hipEventCreate(&e1));
+            for (const BatchTile& cand : kTuneCandidates) {
+                if ((o.batch_rhs && cand.nr != o.batch_rhs) ||
+                    (o.batch_block && cand.block != o.batch_block))
+                    continue;
+                Scratch tsc(st);
+                BatchItem* it_dev = nullptr;
+                int nit = 0;
+                fkgp_status rs =
+                    build_batch_items(probs, nrhs_v, long_L, cand.nr, tsc, &it_dev, nit);
+                if (rs == FKGP_OK)   // warm-up launch (code object load), then the trial
+                    rs = launch_batch_cg(probs_dev, it_dev, nit, lds, o.tol, 1, cand.nr,
+                                         cand.block, st);
+                if (rs == FKGP_OK) {
+                    FKGP_HIP(hipEventRecord(e0, st));
+                    rs = launch_batch_cg(probs_dev, it_dev, nit, lds, o.tol,
+                                         std::min(o.maxiter, kTuneIters), cand.nr, cand.block,
+                                         st);
+                    FKGP_HIP(hipEventRecord(e1, st));
+                }
+                if (rs != FKGP_OK) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return rs;
+                }
+                FKGP_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                FKGP_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (chosen.nr == 0 || ms < best) {
+                    best = ms;
+                    chosen = cand;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            tile = chosen;
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[key] = tile;
+        }
+    }
+    const int NR = tile.nr;
+    BatchItem* items_dev = nullptr;
+    int nitems = 0;
+    fkgp_status rs = build_batch_items(probs, nrhs_v, long_L, NR, sc, &items_dev, nitems);
+    if (rs != FKGP_OK) return rs;
+    rs = launch_batch_cg(probs_dev, items_dev, nitems, lds, o.tol, o.maxiter, NR, tile.block, st);
     if (rs != FKGP_OK) return rs;
     FKGP_HIP(hipStreamSynchronize(st));
     fkgp_status res = FKGP_OK;
@@ -1679,6 +1787,8 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
             infos[p].quad = q;
             infos[p].iterations_y = hsv[0].iters;
             infos[p].iterations_probes_max = itmax;
+            infos[p].batch_rhs = NR;
+            infos[p].batch_block = tile.block;
         }
         if (!conv) res = FKGP_ENOTCONV;
     }
@@ -1707,7 +1817,7 @@ extern "C" fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers
             fkgp::set_error("the marginal likelihood needs n > 0");
             return FKGP_EINVAL;
         }
-        fkgp_mll_opts o{30, 1e-6, 1000, 1};
+        fkgp_mll_opts o{30, 1e-6, 1000, 1, 0, 0};
         if (opts) o = *opts;
         if (o.lanczos_steps < 1 || o.lanczos_steps > fkgp::kMaxLanczos || !(o.tol >= 0.0) ||
             o.maxiter < 1) {
@@ -1743,11 +1853,17 @@ extern "C" fkgp_status fkgp_batch_mll_and_grad(const fkgp_handle* const* hs, int
                 return FKGP_EINVAL;
             }
         }
-        fkgp_mll_opts o{30, 1e-6, 1000, 1};
+        fkgp_mll_opts o{30, 1e-6, 1000, 1, 0, 0};
         if (opts) o = *opts;
         if (o.lanczos_steps < 1 || o.lanczos_steps > fkgp::kMaxLanczos || !(o.tol >= 0.0) ||
             o.maxiter < 1) {
             fkgp::set_error("lanczos_steps must be in [1, 64], tol >= 0, maxiter >= 1");
+            return FKGP_EINVAL;
+        }
+        if ((o.batch_rhs != 0 && o.batch_rhs != 2 && o.batch_rhs != 4 && o.batch_rhs != 8) ||
+            (o.batch_block != 0 && o.batch_block != 256 && o.batch_block != 512)) {
+            fkgp::set_error("batch_rhs must be 0 (autotune), 2, 4 or 8 and batch_block 0, 256 "
+                            "or 512");
             return FKGP_EINVAL;
         }
         return fkgp::batch_mll_impl(hs, nprob, hyps, o, mll, grad, infos,

@@ -90,13 +90,14 @@ struct Spectra {
     void* lam[3];
     void* tw[3];        // twiddles exp(-2 pi i t / L), t < L/2, complex stats dtype
     void* scr[3];       // long lines: kLongWGs * L complex scratch, else null
+    int lg1[3];         // four-step split of dim k (0: register order)
 };
 
 int circulant_log2(int m);
 // Builds lam[k] for dimension k from the SE column (deriv: multiply the
 // column by (j h / l)^2).  Runs on the device (FP64 direct DFT).
 fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv,
-                           fkgp_dtype dt, void* lam, int log2L, hipStream_t s);
+                           fkgp_dtype dt, void* lam, int log2L, int lg1, hipStream_t s);
 fkgp_status build_twiddles(int log2L, fkgp_dtype dt, void* tw, hipStream_t s);
 
 // y = scale * (T_0 (x) .. (x) T_{d-1}) x (+ add_coef * addv), batched over k
@@ -133,7 +134,10 @@ fkgp_status interpolate_points(const GridDev& g, const double* mu,
 
 // ---- batched factorized CG over many problems (batch.hip) ---------------
 constexpr int kMaxLanczos = 64;   // CG coefficients kept per right-hand side
-constexpr int kBatchRhs = 8;      // right-hand sides per workgroup work item
+constexpr int kBatchMaxRhs = 8;   // right-hand sides per work item: 2, 4 or 8
+// Longest circulant the batched solver convolves with the register line FFT
+// (longer ones take the four-step path, which keeps its registers low).
+constexpr int kBatchRegMaxLog2 = 8;
 
 // State of one factorized CG from x_0 = 0 (r = W r_hat + c_r b, ...).
 struct PState {
@@ -152,7 +156,7 @@ struct BatchProb {
     int log2L[2];
     int a_f32;                 // stored W^T W is FP32 (else FP64)
     const void* A;             // row-tiled stencil-diagonal W^T W
-    double so, s2, n;
+    double so, s2;
     const double* bh;          // [nrhs][M] W^T b
     const double* kb;          // [nrhs][M] K_G W^T b
     const double* bnorm2;      // [nrhs] ||b||^2
@@ -166,13 +170,21 @@ struct BatchProb {
 
 struct BatchItem {
     int prob, r0, nr;
-    double* work;              // batch_work_doubles(M, halo) doubles
-    cplx<double>* yscr;        // L complex (longest long line), or null
+    double* work;              // batch_work_doubles(M, halo, NR) doubles
+    cplx<double>* yscr;        // L complex (longest four-step line), or null
 };
 
-size_t batch_work_doubles(int64_t M, int64_t halo);
+// Stride between the padded r_hat vectors of a work item (8 spare zeros past
+// the halo: the four-row product reads up to 3 entries beyond the last row).
+__host__ __device__ inline int64_t batch_rhat_stride(int64_t M, int64_t halo) {
+    return M + 2 * halo + 8;
+}
+size_t batch_work_doubles(int64_t M, int64_t halo, int nr);
+// Dynamic LDS of the batched kernel for one problem (spectra, transpose).
+size_t batch_lds_bytes(int d, const int* m, const int* log2L);
 fkgp_status launch_batch_cg(const BatchProb* probs_dev, const BatchItem* items_dev, int nitems,
-                            size_t lds, double tol, int maxiter, hipStream_t s);
+                            size_t lds, double tol, int maxiter, int nr, int block,
+                            hipStream_t s);
 
 fkgp_status dia_to_canonical(const GridDev& g, fkgp_dtype dt, const void* A,
                              void* out, hipStream_t s);

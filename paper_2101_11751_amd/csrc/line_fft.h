@@ -128,17 +128,18 @@ __device__ inline unsigned bitrev_bits(unsigned v, int bits) {
     return bits ? (__brev(v) >> (32 - bits)) : 0u;
 }
 
-// Long lines (L = L1 * L2 > 2048): four-step convolution by one workgroup.
-// With n = L2 n1 + n2: (1) length-L1 DIF over n1 for every n2, times the
-// twiddle w_L^{n2 k1} (k1 = bit-reversed position p1); (2) per row p1:
-// length-L2 DIF over n2, spectrum in the resulting order
-// (lamp[p1][p2] = lambda[k1 + L1 k2] / L), length-L2 DIT, conjugate
-// twiddle; (3) length-L1 DIT over p1 for every n2 (bit-reversed in, natural
-// out).  Y: L complex scratch in global memory owned by this workgroup.
-// twh: w_L^t for t < L/2 (w_L^{t + L/2} = -w_L^t); tw1/tw2: w_L1^t (t <
-// L1/2) and w_L2^t (t < L2/2).  Lines a and b (b may be absent) of length m
-// with stride S; the result, times `scale` plus add_coef * add, is written
-// to dst (src == dst allowed: every read of a line precedes every write).
+// Long lines: four-step convolution by one workgroup, L = L1 * L2 with
+// L1, L2 >= 8 and L >= 64.  With n = L2 n1 + n2: (1) length-L1 DIF over n1
+// for every n2, times the twiddle w_L^{n2 k1} (k1 = bit-reversed position
+// p1); (2) per row p1: length-L2 DIF over n2, spectrum in the resulting order
+// (lamp[p1][p2] = lambda[k1 + L1 k2] / L), length-L2 DIT, conjugate twiddle;
+// (3) length-L1 DIT over p1 for every n2 (bit-reversed in, natural out).
+// Sub-lengths below 64 put 64/L1 columns (64/L2 rows) in one wave.
+// Y: L complex scratch in global memory owned by this workgroup.  twh: w_L^t
+// for t < L/2 (w_L^{t + L/2} = -w_L^t); tw1/tw2: w_L1^t (t < L1/2) and
+// w_L2^t (t < L2/2).  Lines a and b (b may be absent) of length m with
+// stride S; the result, times `scale` plus add_coef * add, is written to dst
+// (src == dst allowed: every read of a line precedes every write).
 template <class T, int LG1, int LG2>
 __device__ void wg_conv_long(const T* srcA, const T* srcB, int64_t S, int m, T* dstA, T* dstB,
                              T scale, const T* addA, const T* addB, T add_coef, cplx<T>* Y,
@@ -146,62 +147,68 @@ __device__ void wg_conv_long(const T* srcA, const T* srcB, int64_t S, int m, T* 
                              const cplx<T>* tw1, const cplx<T>* tw2) {
     constexpr int L1 = 1 << LG1, L2 = 1 << LG2, L = L1 * L2;
     constexpr int R1 = line_regs<LG1>(), R2 = line_regs<LG2>();
-    static_assert(L1 >= 64 && L2 >= 64, "four-step sub-lengths must be >= 64");
+    constexpr int G1 = L1 >= 64 ? 1 : 64 / L1, G2 = L2 >= 64 ? 1 : 64 / L2;
+    static_assert(LG1 >= 3 && LG2 >= 3 && L >= 64, "four-step sub-lengths too short");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
+    const int e1 = L1 >= 64 ? lane : (lane & (L1 - 1)), g1 = L1 >= 64 ? 0 : lane / L1;
+    const int e2 = L2 >= 64 ? lane : (lane & (L2 - 1)), g2 = L2 >= 64 ? 0 : lane / L2;
     auto cross = [&](unsigned t) -> cplx<T> {
         t &= (unsigned)(L - 1);
         if (t < (unsigned)(L / 2)) return twh[t];
         const cplx<T> w = twh[t - L / 2];
         return {-w.re, -w.im};
     };
-    // (1) columns
-    for (int n2 = wave; n2 < L2; n2 += nw) {
+    // (1) columns (G1 per wave; L2 is a multiple of G1 because L >= 64)
+    for (int c0 = wave * G1; c0 < L2; c0 += nw * G1) {
+        const int n2 = c0 + g1;
         cplx<T> z[R1];
 #pragma unroll
         for (int q = 0; q < R1; ++q) {
-            const int n = L2 * (q * 64 + lane) + n2;
+            const int n = L2 * (q * 64 + e1) + n2;
             z[q].re = (n < m) ? srcA[(int64_t)n * S] : T(0);
             z[q].im = (n < m && srcB) ? srcB[(int64_t)n * S] : T(0);
         }
-        dif_regs<T, LG1>(z, lane, tw1);
+        dif_regs<T, LG1>(z, e1, tw1);
 #pragma unroll
         for (int q = 0; q < R1; ++q) {
-            const int p1 = q * 64 + lane;
+            const int p1 = q * 64 + e1;
             Y[p1 * L2 + n2] = cmul(z[q], cross((unsigned)n2 * bitrev_bits(p1, LG1)));
         }
     }
     __syncthreads();
-    // (2) rows
-    for (int p1 = wave; p1 < L1; p1 += nw) {
+    // (2) rows (G2 per wave)
+    for (int r0 = wave * G2; r0 < L1; r0 += nw * G2) {
+        const int p1 = r0 + g2;
         cplx<T> z[R2];
 #pragma unroll
-        for (int q = 0; q < R2; ++q) z[q] = Y[p1 * L2 + q * 64 + lane];
-        dif_regs<T, LG2>(z, lane, tw2);
+        for (int q = 0; q < R2; ++q) z[q] = Y[p1 * L2 + q * 64 + e2];
+        dif_regs<T, LG2>(z, e2, tw2);
 #pragma unroll
         for (int q = 0; q < R2; ++q) {
-            const T lm = lamp[p1 * L2 + q * 64 + lane];
+            const T lm = lamp[p1 * L2 + q * 64 + e2];
             z[q].re *= lm;
             z[q].im *= lm;
         }
-        dit_regs<T, LG2>(z, lane, tw2);
+        dit_regs<T, LG2>(z, e2, tw2);
         const unsigned br = bitrev_bits(p1, LG1);
 #pragma unroll
         for (int q = 0; q < R2; ++q) {
-            const int n2 = q * 64 + lane;
+            const int n2 = q * 64 + e2;
             Y[p1 * L2 + n2] = cmul_conj(z[q], cross((unsigned)n2 * br));
         }
     }
     __syncthreads();
     // (3) columns back
-    for (int n2 = wave; n2 < L2; n2 += nw) {
+    for (int c0 = wave * G1; c0 < L2; c0 += nw * G1) {
+        const int n2 = c0 + g1;
         cplx<T> z[R1];
 #pragma unroll
-        for (int q = 0; q < R1; ++q) z[q] = Y[(q * 64 + lane) * L2 + n2];
-        dit_regs<T, LG1>(z, lane, tw1);
+        for (int q = 0; q < R1; ++q) z[q] = Y[(q * 64 + e1) * L2 + n2];
+        dit_regs<T, LG1>(z, e1, tw1);
 #pragma unroll
         for (int q = 0; q < R1; ++q) {
-            const int n = L2 * (q * 64 + lane) + n2;
+            const int n = L2 * (q * 64 + e1) + n2;
             if (n >= m) continue;
             T va = scale * z[q].re;
             if (addA) va += add_coef * addA[(int64_t)n * S];

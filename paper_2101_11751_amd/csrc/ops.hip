@@ -164,12 +164,14 @@ __global__ __launch_bounds__(kLineBlock) void line_conv_long(
 }
 
 template <class T>
-fkgp_status launch_line_conv(int log2L, const T* in, T* out, const LineGeom& lg,
+fkgp_status launch_line_conv(int log2L, int lg1, const T* in, T* out, const LineGeom& lg,
                              const T* lam, const cplx<T>* tw, T scale, const T* addv,
                              T add_coef, const int* skip, cplx<T>* scr, hipStream_t s) {
-    if (log2L > kMaxRegLog2) {
-        if (!scr) {
-            set_error("long grid line without four-step scratch");
+    if (lg1 > 0) {
+        int want1, want2;
+        long_split(log2L, want1, want2);
+        if (!scr || log2L <= kMaxRegLog2 || lg1 != want1) {
+            set_error("spectra not laid out for the standalone line FFT");
             return FKGP_EINVAL;
         }
         const int64_t npairs = (lg.nlines + 1) / 2;
@@ -198,6 +200,10 @@ fkgp_status launch_line_conv(int log2L, const T* in, T* out, const LineGeom& lg,
     // lines per block: enough blocks to cover the chip (>= ~2 per CU), at
     // least 8 lines for strided dimensions (64-byte coalesced rows), at most
     // what fits in 48 KiB of LDS; even.
+    if (log2L > kMaxRegLog2) {
+        set_error("spectra not laid out for the standalone line FFT");
+        return FKGP_EINVAL;
+    }
     const int64_t row = (int64_t)(lg.m_line + 1) * sizeof(T);
     int64_t lb = lg.nlines / 512;
     lb = std::max<int64_t>(lb, lg.S == 1 ? 2 : 8);
@@ -500,11 +506,9 @@ int circulant_log2(int m) {
 }
 
 fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv, fkgp_dtype dt,
-                           void* lam, int log2L, hipStream_t s) {
+                           void* lam, int log2L, int lg1, hipStream_t s) {
     const int L = 1 << log2L;
     const unsigned grid = (unsigned)((L + 255) / 256);
-    int lg1 = 0, lg2 = 0;
-    if (log2L > kMaxRegLog2) long_split(log2L, lg1, lg2);
     if (dt == FKGP_F32)
         spectrum_kernel<float><<<grid, 256, 0, s>>>(static_cast<float*>(lam), log2L, lg1,
                                                     g.m[k], g.h[k], ell, deriv);
@@ -541,7 +545,7 @@ static fkgp_status kg_apply_t(const GridDev& g, const Spectra& sp, const T* x, T
         const bool last = pass == g.d - 1;
         const T* src = pass == 0 ? x : y;
         fkgp_status st = launch_line_conv<T>(
-            sp.log2L[dim], src, y, lg, static_cast<const T*>(sp.lam[dim]),
+            sp.log2L[dim], sp.lg1[dim], src, y, lg, static_cast<const T*>(sp.lam[dim]),
             static_cast<const cplx<T>*>(sp.tw[dim]), last ? (T)scale : T(1),
             last ? addv : nullptr, (T)add_coef, skip, static_cast<cplx<T>*>(sp.scr[dim]), s);
         if (st != FKGP_OK) return st;

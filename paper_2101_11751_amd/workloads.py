@@ -26,13 +26,22 @@ Workloads (all kernels: squared exponential inside a scale kernel):
            circulant-embedding sampling on 512^2 (negative eigenvalues clipped)
            and a bilinear basis (the generator deliberately does not use the
            cubic basis of the method); 16 Rademacher probes, probe seed 4.
-The grid rule for the last three is h = (hi - lo)/(m - 3), origin = lo - h.
+  batch64  64 independent problems of uneven size: 32 1-D (seed 1000+i:
+           m = round(exp U[ln 512, ln 8192]), n = round(exp U[ln 1e4, ln 2e6]),
+           data as sine1d with sigma = 0.1) and 32 2-D (seed 1032+i: square
+           m x m grid, m ~ U{32..128}, n = round(exp U[ln 5e4, ln 1e6]), data as
+           bumps2d with sigma = 0.05); l ~ U[0.01, 0.1] per problem, s = 1;
+           31 Rademacher probes with probe seed 5000+i (32 right-hand sides
+           [y, z_1 .. z_31] per problem); FP32 inputs.  Sizes and
+           hyperparameters are drawn on the CPU (identical on every device),
+           the data on the requested device.
+The grid rule for the last four is h = (hi - lo)/(m - 3), origin = lo - h.
 """
 import math
 
 import torch
 
-WORKLOADS = ("sine1d", "bumps2d", "radar3d", "prior2d")
+WORKLOADS = ("sine1d", "bumps2d", "radar3d", "prior2d", "batch64")
 
 
 def padded_grid(m, lo, hi):
@@ -181,6 +190,52 @@ def prior2d(n=4_000_000, seed=3, device="cpu", m=(256, 256), probe_seed=4, nprob
             "lanczos_steps": 30, "clipped_spectrum_fraction": clipped, "tol": 1e-6}
 
 
+def _batch_problem(i, device, n_scale, nprobes):
+    """Problem i of batch64 (0 <= i < 32: 1-D, 32 <= i < 64: 2-D)."""
+    seed = 1000 + i
+    gc = _gen(seed, "cpu")
+    f64 = torch.float64
+    u = torch.rand(3, generator=gc, dtype=f64)
+    if i < 32:
+        m = [int(round(math.exp(math.log(512) + u[0].item() * math.log(8192 / 512))))]
+        n = int(round(math.exp(math.log(1e4) + u[1].item() * math.log(2e6 / 1e4))))
+        sigma = 0.1
+    else:
+        md = 32 + int(torch.randint(0, 97, (1,), generator=gc).item())
+        m = [md, md]
+        n = int(round(math.exp(math.log(5e4) + u[1].item() * math.log(1e6 / 5e4))))
+        sigma = 0.05
+    ell = 0.01 + 0.09 * u[2].item()
+    n = max(16, int(round(n * n_scale)))
+    g = _gen(seed, device)
+    d = len(m)
+    x = torch.rand(d, n, generator=g, device=device, dtype=f64)
+    if d == 1:
+        y = (torch.sin(6 * math.pi * x[0]) + 0.5 * torch.sin(20 * math.pi * x[0])
+             + sigma * torch.randn(n, generator=g, device=device, dtype=f64))
+    else:
+        nb = 20
+        c = torch.rand(nb, 2, generator=g, device=device, dtype=f64)
+        w = 0.02 + 0.18 * torch.rand(nb, generator=g, device=device, dtype=f64)
+        a = torch.randn(nb, generator=g, device=device, dtype=f64)
+        y = sigma * torch.randn(n, generator=g, device=device, dtype=f64)
+        for b in range(nb):
+            r2 = (x[0] - c[b, 0]) ** 2 + (x[1] - c[b, 1]) ** 2
+            y += a[b] * torch.exp(-r2 / (2 * w[b] ** 2))
+    return {"name": f"batch64[{i}]", "x": [x[k].float() for k in range(d)], "y": y.float(),
+            "grid": padded_grid(m, 0.0, 1.0),
+            "hypers": {"lengthscale": [ell] * d, "outputscale": 1.0, "noise": sigma},
+            "dtype": torch.float32, "probe_seed": 5000 + i, "nprobes": nprobes,
+            "lanczos_steps": 30, "n": n, "m": m}
+
+
+def batch64(device="cpu", n_scale=1.0, nprobes=31, which=None):
+    """List of the batch64 problems (all 64, or the indices in `which`);
+    n_scale shrinks every n (for tests)."""
+    idx = range(64) if which is None else which
+    return [_batch_problem(i, device, n_scale, nprobes) for i in idx]
+
+
 def get(name, **kw):
     return {"sine1d": sine1d, "bumps2d": bumps2d, "radar3d": radar3d,
-            "prior2d": prior2d}[name](**kw)
+            "prior2d": prior2d, "batch64": batch64}[name](**kw)

@@ -98,3 +98,83 @@ def test_batch_long_lines():
     scale = abs(inf_o["logdet"]) + abs(inf_o["q"]) + X.shape[1] * math.log(2 * math.pi)
     assert abs(mll_b[1] - mll_o) <= 1e-6 * scale
     np.testing.assert_allclose(g_b[1], g_o, rtol=0, atol=1e-4 * np.max(np.abs(g_o)))
+
+
+def test_batch_tiles_agree_and_autotune():
+    """Every (right-hand sides per workgroup, workgroup size) tile gives the
+    same result up to rounding (the workgroup size changes the reduction
+    order and the grouping changes which grid lines share a complex FFT, and
+    Lanczos coefficients taken from CG pass rounding on, so the comparison
+    uses the batch-vs-single tolerance); the autotuner reports the tile it
+    chose."""
+    _need_gpu()
+    probs = [problem(13, 2, [45, 37], 20000, 6), problem(14, 1, [700], 15000, 9),
+             problem(15, 2, [20, 70], 9000, 4)]
+    hs = [p[0] for p in probs]
+    hyps = [p[1] for p in probs]
+    for hyp in hyps:
+        hyp["lengthscale"] = [0.05] * len(hyp["lengthscale"])
+    ref = {}
+    for nr in (2, 4, 8):
+        for block in (256, 512):
+            m, g, inf = P.batch_mll_and_grad(hs, hyps, 10, 1e-9, 4000, batch_rhs=nr,
+                                             batch_block=block)
+            assert all(i["batch_rhs"] == nr and i["batch_block"] == block for i in inf)
+            if block not in ref:
+                ref[block] = (m, g, inf)
+                if block == 256:
+                    continue
+            r0 = ref[256]
+            for k in range(len(hs)):
+                scale = (abs(r0[2][k]["logdet"]) + abs(r0[2][k]["quad"])
+                         + hs[k].n * math.log(2 * math.pi))
+                assert abs(m[k] - r0[0][k]) <= 1e-7 * scale, (nr, block, k)
+                np.testing.assert_allclose(g[k], r0[1][k], rtol=0,
+                                           atol=1e-5 * np.max(np.abs(r0[1][k])))
+    m, g, inf = P.batch_mll_and_grad(hs, hyps, 10, 1e-9, 4000)
+    assert inf[0]["batch_rhs"] in (2, 4, 8) and inf[0]["batch_block"] in (256, 512)
+    with pytest.raises(P.FkgpError):
+        P.batch_mll_and_grad(hs, hyps, 10, 1e-9, 4000, batch_rhs=3)
+
+
+def test_batch64_workload_subset():
+    """Problems of the many-problem workload (1-D lines of 512 .. 8192 nodes,
+    2-D grids of 32^2 .. 128^2, 32 right-hand sides each) at reduced n: the
+    one-launch result matches the per-problem path."""
+    _need_gpu()
+    from paper_2101_11751_amd import workloads
+    wl = workloads.batch64(device=torch.device("cuda"), n_scale=0.02,
+                           which=[0, 4, 6, 30, 32, 36, 45, 59])
+    hs = [P.precompute(w["grid"], w["x"], w["y"], stats_dtype=torch.float32,
+                       n_probes=w["nprobes"], probe_seed=w["probe_seed"]) for w in wl]
+    hyps = [w["hypers"] for w in wl]
+    mb, gb, ib = P.batch_mll_and_grad(hs, hyps, 30, 1e-8, 20000)
+    for k, h in enumerate(hs):
+        ms, gs, inf = P.mll_and_grad(h, hyps[k], 30, 1e-8, 20000)
+        assert inf["status"] == 0 and ib[k]["status"] == 0
+        scale = abs(inf["logdet"]) + abs(inf["quad"]) + h.n * math.log(2 * math.pi)
+        assert abs(mb[k] - ms) <= 1e-6 * scale, (k, mb[k], ms)
+        np.testing.assert_allclose(gb[k], gs, rtol=0, atol=1e-4 * np.max(np.abs(gs)))
+
+
+def test_batch_response_norm_not_n():
+    """The data right-hand side enters the factorized inner products with
+    ||y||^2 = y^T y, the probes with n: a response scaled far from unit
+    variance (y^T y = 400 n here) must give the single-problem result."""
+    _need_gpu()
+    rng = np.random.default_rng(16)
+    n = 6000
+    grid = oracle.make_grid([50, 40], lo=0.0, hi=1.0)
+    X = rng.uniform(0, 1, (2, n)).astype(np.float32)
+    y = (20.0 * np.sign(np.sin(7 * X[0].astype(np.float64)))
+         + rng.standard_normal(n)).astype(np.float32)
+    xs = [torch.from_numpy(np.ascontiguousarray(X[k])).cuda() for k in range(2)]
+    h = P.precompute(grid, xs, torch.from_numpy(y).cuda(), stats_dtype=torch.float32,
+                     n_probes=5, probe_seed=7)
+    hyp = {"lengthscale": [0.06, 0.06], "outputscale": 50.0, "noise": 1.0}
+    mb, gb, ib = P.batch_mll_and_grad([h], [hyp], 10, 1e-10, 5000)
+    ms, gs, inf = P.mll_and_grad(h, hyp, 10, 1e-10, 5000)
+    assert ib[0]["iterations_y"] > 5
+    assert abs(ib[0]["quad"] - inf["quad"]) <= 1e-6 * inf["quad"]
+    scale = abs(inf["logdet"]) + abs(inf["quad"]) + n * math.log(2 * math.pi)
+    assert abs(mb[0] - ms) <= 1e-7 * scale
