@@ -9,6 +9,8 @@ CG with FP32 operator and FP64 refinement, final K_G product).  Inputs are
 generated on the device before timing.
 
 value            = n * steps / timed seconds  (Mpts/s through the whole step)
+mll_grad         = differentiation workload: batched FP32 vs plain FP64 path
+batch_mll_grad   = many-problem workload: one persistent launch vs a loop
 precompute_*     = n / precompute time
 cg_mvms_per_s    = CG iterations (one operator B each) per second of solve
 roofline         = banded W^T W product (the dominant kernel of the solve),
@@ -45,8 +47,11 @@ def _parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mll", action="store_true")
     ap.add_argument("--mll-reps", type=int, default=2)
-    ap.add_argument("--mll-tol", type=float, default=1e-2)
+    ap.add_argument("--mll-tol", type=float, default=1e-4)
     ap.add_argument("--mll-maxiter", type=int, default=20000)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-tol", type=float, default=1e-4)
+    ap.add_argument("--batch-maxiter", type=int, default=30000)
     return ap.parse_args()
 
 
@@ -129,6 +134,56 @@ def mll_compare(P, workloads, torch, dev, reps, tol, maxiter):
             "mll": b["mll"], "grad": b["grad"],
             "converged": a["status"] == 0 and b["status"] == 0,
             "iterations_y": b["iterations_y"], "iterations_probes_max": b["iterations_probes_max"]}
+
+
+def batch_compare(P, workloads, torch, dev, tol, maxiter):
+    """The many-problem workload (64 uneven problems, 32 right-hand sides
+    each): MLL + gradient of every problem in one persistent launch (tiles
+    autotuned; the tuning trial runs in an untimed first call) vs one
+    mll_and_grad call per problem (probes batched within each problem), both
+    on FP32-stored statistics with FP64 vectors and scalars."""
+    import numpy as np
+    probs = workloads.batch64(device=dev)
+    torch.cuda.synchronize()
+    n_total = sum(p["n"] for p in probs)
+    t0 = time.perf_counter()
+    hs = [P.precompute(p["grid"], p["x"], p["y"], stats_dtype=torch.float32,
+                       n_probes=p["nprobes"], probe_seed=p["probe_seed"]) for p in probs]
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t0
+    hyps = [p["hypers"] for p in probs]
+    steps = probs[0]["lanczos_steps"]
+    P.batch_mll_and_grad(hs, hyps, steps, tol, maxiter)   # tile autotuning + warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mb, gb, ib = P.batch_mll_and_grad(hs, hyps, steps, tol, maxiter)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batch64: one launch {t_batch:.3f} s (tile {ib[0]['batch_rhs']} rhs x "
+        f"{ib[0]['batch_block']} threads)")
+    t0 = time.perf_counter()
+    loop = [P.mll_and_grad(h, hyp, steps, tol, maxiter) for h, hyp in zip(hs, hyps)]
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    log(f"batch64: per-problem loop {t_loop:.3f} s")
+    rel_mll = max(abs(a - l[0]) / abs(l[0]) for a, l in zip(mb, loop))
+    rel_q = max(abs(i["quad"] - l[2]["quad"]) / abs(l[2]["quad"]) for i, l in zip(ib, loop))
+    rel_g = max(float(np.max(np.abs(np.array(g) - np.array(l[1]))) / np.max(np.abs(l[1])))
+                for g, l in zip(gb, loop))
+    conv = all(i["status"] == 0 for i in ib) and all(l[2]["status"] == 0 for l in loop)
+    for h in hs:
+        h.close()
+    return {"workload": "batch64: 32 1-D (m 512..8192, n 1e4..2e6, sine data) + 32 2-D "
+                        "(m 32^2..128^2, n 5e4..1e6, bump data) problems, l~U[0.01,0.1], "
+                        "31 probes + y per problem, %d Lanczos steps, tol %g" % (steps, tol),
+            "n_total": n_total, "precompute_s": t_pre,
+            "batched_s_per_eval": t_batch, "per_problem_loop_s_per_eval": t_loop,
+            "speedup": t_loop / t_batch,
+            "tile": {"rhs_per_workgroup": ib[0]["batch_rhs"],
+                     "threads_per_workgroup": ib[0]["batch_block"]},
+            "iterations_max": max(max(i["iterations_y"], i["iterations_probes_max"]) for i in ib),
+            "max_rel_diff_mll": rel_mll, "max_rel_diff_quad": rel_q, "max_rel_diff_grad": rel_g,
+            "converged": conv}
 
 
 def main():
@@ -247,6 +302,11 @@ def main():
         mc = mll_compare(P, workloads, torch, dev, args.mll_reps, args.mll_tol, args.mll_maxiter)
         result["mll_grad_s_per_eval"] = mc["batched_f32_s_per_eval"]
         result["mll_grad"] = mc
+    if not args.no_batch:
+        torch.cuda.empty_cache()
+        bc = batch_compare(P, workloads, torch, dev, args.batch_tol, args.batch_maxiter)
+        result["batch_mll_grad_s_per_eval"] = bc["batched_s_per_eval"]
+        result["batch_mll_grad"] = bc
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cb = cpu_baseline(wl, n, iters_mean, args.cpu_seconds)
