@@ -75,18 +75,7 @@ size_t dsize(fkgp_dtype dt) { return dt == FKGP_F32 ? 4 : 8; }
 // ---------------------------------------------------------------------------
 // CG kernels (FP64 vectors and scalars).
 // ---------------------------------------------------------------------------
-struct CgState {
-    double rho;     // ||r_k||^2 in n-space (= u^T r_hat)
-    double sz;      // s^T z
-    double alpha;
-    double beta;
-    double eps;     // stop when rho <= eps
-    double bnorm2;  // ||b||^2
-    int done;
-    int iters;
-};
 
-enum FinOp { FIN_INIT = 0, FIN_INIT_RHS = 1, FIN_RHO = 2, FIN_SZ = 3 };
 
 constexpr int kRedBlock = 256;
 constexpr int kRedMaxBlocks = 1024;
@@ -130,31 +119,7 @@ __global__ __launch_bounds__(kRedBlock) void finalize(const double* __restrict__
     double acc = 0.0;
     for (int i = threadIdx.x; i < nb; i += kRedBlock) acc += partials[i];
     const double t = block_sum(acc, sh);
-    if (threadIdx.x != 0) return;
-    if (op == FIN_INIT || op == FIN_INIT_RHS) {
-        st->rho = t;
-        st->beta = 0.0;
-        st->iters = 0;
-        if (op == FIN_INIT_RHS) {
-            st->bnorm2 = t;
-            st->eps = st->eps * t;   // eps held tol^2 on entry
-        }
-        st->done = (t <= st->eps) ? 1 : 0;
-    } else if (op == FIN_RHO) {
-        st->iters += 1;
-        const double rho_new = t;
-        if (!(rho_new > st->eps)) {
-            st->done = 1;   // converged (or NaN: stop)
-            st->rho = rho_new;
-            return;
-        }
-        st->beta = rho_new / st->rho;
-        st->rho = rho_new;
-    } else {
-        st->sz = t;
-        st->alpha = st->rho / t;
-        if (!std::isfinite(st->alpha)) st->done = 2;
-    }
+    if (threadIdx.x == 0) cg_state_update(st, t, op);
 }
 
 // xd += alpha s; r -= alpha z; rpad = (T) r
@@ -388,9 +353,10 @@ fkgp_status apply_B64(const OpCtx& c, const double* xpad, double* u, double* v, 
 }
 
 struct CgBufs {
-    double *r, *s, *z, *p, *x, *xd, *partials;
+    double *r, *s, *z, *p, *x, *xd, *partials, *partials2;
     unsigned char *rpad, *u, *v;
     CgState* st;
+    unsigned* tickets;   // [2], zero between launches (last-workgroup reductions)
 };
 
 fkgp_status alloc_cg(const OpCtx& c, CgBufs& b, Scratch& sc) {
@@ -407,6 +373,9 @@ fkgp_status alloc_cg(const OpCtx& c, CgBufs& b, Scratch& sc) {
     FKGP_HIP(sc.get(&b.u, es * M));
     FKGP_HIP(sc.get(&b.v, es * M));
     FKGP_HIP(sc.get(&b.st, 1));
+    FKGP_HIP(sc.get(&b.partials2, std::max<int64_t>(1, kg_last_pass_blocks(c.h->g))));
+    FKGP_HIP(sc.get(&b.tickets, 2));
+    FKGP_HIP(hipMemsetAsync(b.tickets, 0, 2 * sizeof(unsigned), sc.s));
     FKGP_HIP(hipMemsetAsync(b.rpad, 0, es * (M + 2 * c.halo), sc.s));
     return FKGP_OK;
 }
@@ -506,6 +475,9 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
     FKGP_HIP(step2());
     finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_SZ);
     FKGP_HIP(hipGetLastError());
+    const LastBlockRed rho_lb{b.partials, b.tickets, b.st, FIN_RHO};
+    const CgStep2 step2f{b.st, b.s, b.z, pp, b.r, b.u,
+                         LastBlockRed{b.partials2, b.tickets + 1, b.st, FIN_SZ}};
     constexpr int kBatch = 8;
     int launched = 0;
     for (;;) {
@@ -521,13 +493,25 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
                 cg_step1x<double><<<ewg, 256, 0, st>>>(b.st, b.xd, px, b.r, b.s, b.z, pp,
                                                        reinterpret_cast<double*>(rin), M);
             FKGP_HIP(hipGetLastError());
+            // u = W^T W r_hat; the product's last workgroup finishes u^T r_hat
+            // (rho, beta) when the tiled kernel runs
             int np = 0;
-            rs = apply_B_padded(c, b.rpad, b.u, b.v, &b.st->done, st, b.partials, &np);
+            rs = spmv_dia_any(h->g, h->dt, c.op, h->A, b.rpad, b.u, 1, c.halo, &b.st->done, st,
+                              b.partials, &np, &rho_lb);
             if (rs != FKGP_OK) return rs;
-            if (np == 0) FKGP_HIP(dot_ur(&b.st->done));
-            finalize<<<1, kRedBlock, 0, st>>>(b.partials, np ? np : nb, b.st, FIN_RHO);
-            FKGP_HIP(step2());
-            finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_SZ);
+            if (np == 0) {
+                FKGP_HIP(dot_ur(&b.st->done));
+                finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_RHO);
+            }
+            // v = s K_G u + s2 r_hat, consumed by the fused direction update
+            bool fused = false;
+            rs = kg_apply_fused(h->g, c.sp, c.op, b.u, b.v, c.so, rin, c.s2, &b.st->done, step2f,
+                                &fused, st);
+            if (rs != FKGP_OK) return rs;
+            if (!fused) {
+                FKGP_HIP(step2());
+                finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_SZ);
+            }
             FKGP_HIP(hipGetLastError());
         }
         launched += nit;

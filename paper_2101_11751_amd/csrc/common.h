@@ -35,6 +35,111 @@ inline int64_t dia_elems(int64_t M, int NB) {
     return ((M + kRowTile - 1) / kRowTile) * NB * kRowTile;
 }
 
+// ---- CG scalar state (capi.hip loops, fused epilogues in ops.hip) ----------
+struct CgState {
+    double rho;     // ||r_k||^2 in n-space (= u^T r_hat)
+    double sz;      // s^T z
+    double alpha;
+    double beta;
+    double eps;     // stop when rho <= eps
+    double bnorm2;  // ||b||^2
+    int done;
+    int iters;
+};
+
+enum FinOp { FIN_INIT = 0, FIN_INIT_RHS = 1, FIN_RHO = 2, FIN_SZ = 3 };
+
+// Scalar step of the CG loop once the dot product t of `op` is known.
+__device__ inline void cg_state_update(CgState* st, double t, int op) {
+    if (op == FIN_INIT || op == FIN_INIT_RHS) {
+        st->rho = t;
+        st->beta = 0.0;
+        st->iters = 0;
+        if (op == FIN_INIT_RHS) {
+            st->bnorm2 = t;
+            st->eps = st->eps * t;   // eps held tol^2 on entry
+        }
+        st->done = (t <= st->eps) ? 1 : 0;
+    } else if (op == FIN_RHO) {
+        st->iters += 1;
+        if (!(t > st->eps)) {
+            st->done = 1;   // converged (or NaN: stop)
+            st->rho = t;
+            return;
+        }
+        st->beta = t / st->rho;
+        st->rho = t;
+    } else {
+        st->sz = t;
+        st->alpha = st->rho / t;
+        if (!isfinite(st->alpha)) st->done = 2;
+    }
+}
+
+// Reduction finished by the last workgroup of a launch: every workgroup
+// publishes its partial, then takes a ticket; the one holding the last
+// ticket sums the partials in index order (the same order as a separate
+// one-block reduction, so the result is deterministic) and applies the CG
+// scalar step.  Partials and tickets use device-scope atomics, which are
+// coherent across the XCDs' L2 caches without the L2 write-back a
+// device-scope fence costs; the partial's exchange returns before the
+// ticket is taken, so a workgroup holding the last ticket sees every
+// partial.  `ticket` is zero between launches (the last workgroup resets it).
+struct LastBlockRed {
+    double* partials;
+    unsigned* ticket;
+    CgState* st;
+    int op;
+};
+
+// Called by all threads of a 256-thread workgroup; `part` is the
+// workgroup's partial (significant in thread 0).  sh: 256 doubles of LDS,
+// free for reuse.
+__device__ inline void last_block_finish(const LastBlockRed& lb, double part, double* sh) {
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+        const unsigned long long old = __hip_atomic_exchange(
+            reinterpret_cast<unsigned long long*>(lb.partials) + blockIdx.x,
+            (unsigned long long)__double_as_longlong(part), __ATOMIC_RELAXED,
+            __HIP_MEMORY_SCOPE_AGENT);
+        asm volatile("" : : "v"(old) : "memory");   // the exchange has returned
+        const unsigned t =
+            __hip_atomic_fetch_add(lb.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        is_last = t == gridDim.x - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    double acc = 0.0;
+    for (unsigned i = threadIdx.x; i < gridDim.x; i += 256)
+        acc += __longlong_as_double((long long)__hip_atomic_load(
+            reinterpret_cast<unsigned long long*>(lb.partials) + i, __ATOMIC_RELAXED,
+            __HIP_MEMORY_SCOPE_AGENT));
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cg_state_update(lb.st, sh[0], lb.op);
+        __hip_atomic_store(lb.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// CG direction update fused into the store of the last K_G line pass:
+// v = s K u + s2 x is consumed in place (never stored): s = u + beta s,
+// z = v + beta z, p = r + beta p (p optional), partial s.z, and the last
+// workgroup finishes s.z (FIN_SZ: alpha).  u has the operator dtype.
+struct CgStep2 {
+    const CgState* st;
+    double* s;
+    double* z;
+    double* p;
+    const double* r;
+    const void* u;
+    LastBlockRed lb;
+};
+
 // ---- error plumbing -------------------------------------------------------
 void set_error(const std::string& msg);
 fkgp_status hip_fail(hipError_t e, const char* what);
@@ -118,11 +223,23 @@ fkgp_status spmv_dia_f32a_f64x(const GridDev& g, const void* A, const double* xp
 fkgp_status kg_apply_skip(const GridDev& g, const Spectra& sp, fkgp_dtype dt, const void* x,
                           void* y, int k, double scale, const void* addv, double add_coef,
                           const int* skip, hipStream_t s);
+// As kg_apply_skip for one vector, with the CG direction update fused into
+// the last pass when that pass uses the register line FFT (*fused = true:
+// y holds intermediate values only).  Otherwise y is written and *fused is
+// false.  fuse->lb.partials needs kg_last_pass_blocks(g) entries.
+fkgp_status kg_apply_fused(const GridDev& g, const Spectra& sp, fkgp_dtype dt, const void* x,
+                           void* y, double scale, const void* addv, double add_coef,
+                           const int* skip, const CgStep2& fuse, bool* fused, hipStream_t s);
+int64_t kg_last_pass_blocks(const GridDev& g);
 // dotp (optional, k == 1): per-block partials of sum_j u_j x_j; *nparts gets
 // their count (0 if the path used writes none).
+// lb (optional, with dotp): the last workgroup also finishes the dot
+// product (partials = dotp) and applies the CG scalar step lb.op; *nparts
+// is then the number of partials and the reduction is done.
 fkgp_status spmv_dia_any(const GridDev& g, fkgp_dtype dta, fkgp_dtype dtx, const void* A,
                          const void* xpad, void* u, int k, int64_t halo, const int* skip,
-                         hipStream_t s, double* dotp = nullptr, int* nparts = nullptr);
+                         hipStream_t s, double* dotp = nullptr, int* nparts = nullptr,
+                         const LastBlockRed* lb = nullptr);
 int64_t dia_halo(const GridDev& g);
 // Upper bound on the dot partials spmv_dia_any writes (one per row tile).
 int64_t spmv_dot_parts(const GridDev& g);

@@ -6,15 +6,17 @@
 // K_G is applied one dimension at a time.  Each line of the grid along
 // dimension k is convolved with the symmetric Toeplitz column of T_k through
 // a circulant embedding of length L >= 2 m_k - 1 (a power of two), entirely
-// in registers/LDS: two real lines are packed into one complex line (the
+// in registers: two real lines are packed into one complex line (the
 // circulant is real, so real and imaginary parts stay separate), transformed
 // by a radix-2 decimation-in-frequency FFT (natural in, bit-reversed out),
 // scaled by the real spectrum stored in bit-reversed order, and transformed
 // back by the matching decimation-in-time inverse (bit-reversed in, natural
 // out).  No padded grid ever touches HBM.  Butterfly spans below 64 use
-// wavefront shuffles; larger spans are within a lane's registers.  Lines
-// along a strided dimension are staged through LDS so that global loads and
-// stores stay coalesced (an LDS transpose).
+// wavefront shuffles; larger spans are within a lane's registers.  Each wave
+// owns its line pair and reads it straight from global memory (strided
+// lines are gathered: the vectors are small and stay in L2), so thousands
+// of independent waves hide each other's latency; circulants longer than
+// 2048 points take a four-step FFT by one workgroup per line pair.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -42,96 +44,90 @@ __device__ inline int64_t line_addr(const LineGeom& lg, int64_t l, int e) {
 
 constexpr int kLineBlock = 256;
 
-// One launch convolves a block of LB lines (LB even).  R = elements per lane
-// (L >= 64: R = L/64, one complex line pair per wave at a time; L < 64: one
-// element per lane, 64/L pairs per wave at a time).
+// Barrier-free variant: each wave convolves its own line pair (64/L pairs
+// when L < 64), loading the lines straight from global memory (strided
+// lines are gathered; the vector is small enough to stay in L2) with
+// twiddles and spectrum read through the cache.  Many independent waves
+// hide each other's latency, where a block-wide LDS transpose leaves one
+// dependent load-FFT-store chain per CU.  Optionally fuses the CG direction
+// update into the store (see CgStep2).
 template <class T, int LOG2L>
-__global__ __launch_bounds__(kLineBlock) void line_conv(
-    const T* in, T* out, LineGeom lg, int LB,   // in == out allowed (in place)
-    const T* __restrict__ lam_br, const cplx<T>* __restrict__ tw, T scale,
-    const T* __restrict__ addv, T add_coef, const int* __restrict__ skip) {
+__global__ __launch_bounds__(kLineBlock) void line_conv_direct(
+    const T* in, T* out, LineGeom lg, const T* __restrict__ lam_br,
+    const cplx<T>* __restrict__ tw, T scale, const T* __restrict__ addv, T add_coef,
+    const int* __restrict__ skip, CgStep2 fz) {
     constexpr int L = 1 << LOG2L;
     constexpr int R = L >= 64 ? L / 64 : 1;
-    constexpr int G = L >= 64 ? 1 : 64 / L;   // pairs per wave per round
+    constexpr int G = L >= 64 ? 1 : 64 / L;
     if (skip && *skip) return;
-    extern __shared__ unsigned char lds_raw[];
-    // LDS: twiddles (L/2 complex), spectrum (L), then the line block
-    cplx<T>* tws = reinterpret_cast<cplx<T>*>(lds_raw);
-    T* lams = reinterpret_cast<T*>(tws + L / 2);
-    T* lds = lams + L;
-    const int ms = lg.m_line + 1;   // padded LDS row
-    const int64_t l0 = (int64_t)blockIdx.x * LB;
-    const int nvalid = (int)min((int64_t)LB, lg.nlines - l0);
     const int tid = threadIdx.x;
-    const int tot = LB * lg.m_line;
-    for (int i = tid; i < L / 2; i += kLineBlock) tws[i] = tw[i];
-    for (int i = tid; i < L; i += kLineBlock) lams[i] = lam_br[i];
-    // ---- load (LDS transpose for strided lines) ----
-    if (lg.S == 1) {
-        for (int idx = tid; idx < tot; idx += kLineBlock) {
-            const int ll = idx / lg.m_line, e = idx - ll * lg.m_line;
-            lds[ll * ms + e] = ll < nvalid ? in[line_addr(lg, l0 + ll, e)] : T(0);
-        }
-    } else {
-        for (int idx = tid; idx < tot; idx += kLineBlock) {
-            const int e = idx / LB, ll = idx - e * LB;
-            lds[ll * ms + e] = ll < nvalid ? in[line_addr(lg, l0 + ll, e)] : T(0);
-        }
-    }
-    __syncthreads();
-    // ---- convolve line pairs ----
     const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int npairs = LB / 2;
     const int e_lane = L >= 64 ? lane : (lane & (L - 1));
     const int g_lane = L >= 64 ? 0 : (lane / L);
-    for (int pb = wave * G; pb < npairs; pb += 4 * G) {
-        const int pair = pb + g_lane;
-        const bool active = pair < npairs;
-        const int la = 2 * pair, lb = 2 * pair + 1;
-        cplx<T> z[R];
+    const int64_t npairs = (lg.nlines + 1) / 2;
+    const int64_t pair = ((int64_t)blockIdx.x * (kLineBlock / 64) + (tid >> 6)) * G + g_lane;
+    const int m = lg.m_line;
+    const int S32 = (int)lg.S;
+    int64_t base[2] = {0, 0};
+    bool ok[2];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int e = r * 64 + e_lane;
-            if (active && e < lg.m_line) {
-                z[r].re = lds[la * ms + e];
-                z[r].im = lds[lb * ms + e];
-            } else {
-                z[r].re = T(0);
-                z[r].im = T(0);
-            }
-        }
-        conv_line_regs<T, LOG2L>(z, e_lane, tws, lams);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int e = r * 64 + e_lane;
-            if (active && e < lg.m_line) {
-                lds[la * ms + e] = z[r].re;
-                lds[lb * ms + e] = z[r].im;
-            }
-        }
+    for (int h = 0; h < 2; ++h) {
+        const int64_t l = 2 * pair + h;
+        ok[h] = pair < npairs && l < lg.nlines;
+        if (ok[h]) base[h] = line_addr(lg, l, 0);
     }
-    __syncthreads();
-    // ---- store (+ scale, + add_coef * addv) ----
-    if (lg.S == 1) {
-        for (int idx = tid; idx < tot; idx += kLineBlock) {
-            const int ll = idx / lg.m_line, e = idx - ll * lg.m_line;
-            if (ll < nvalid) {
-                const int64_t a = line_addr(lg, l0 + ll, e);
-                T v = scale * lds[ll * ms + e];
+    cplx<T> z[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = r * 64 + e_lane;
+        const bool in_line = e < m;
+        z[r].re = (in_line && ok[0]) ? in[base[0] + (int64_t)(e * S32)] : T(0);
+        z[r].im = (in_line && ok[1]) ? in[base[1] + (int64_t)(e * S32)] : T(0);
+    }
+    conv_line_regs<T, LOG2L>(z, e_lane, tw, lam_br);
+    if (fz.s) {
+        __shared__ double red[kLineBlock];
+        const double beta = fz.st->beta;
+        const T* uu = static_cast<const T*>(fz.u);
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = r * 64 + e_lane;
+            if (e >= m) continue;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (!ok[h]) continue;
+                const int64_t a = base[h] + (int64_t)(e * S32);
+                T v = scale * (h == 0 ? z[r].re : z[r].im);
                 if (addv) v += add_coef * addv[a];
-                out[a] = v;
+                const double sn = fma(beta, fz.s[a], (double)uu[a]);
+                const double zn = fma(beta, fz.z[a], (double)v);
+                fz.s[a] = sn;
+                fz.z[a] = zn;
+                if (fz.p) fz.p[a] = fma(beta, fz.p[a], fz.r[a]);
+                acc = fma(sn, zn, acc);
             }
         }
-    } else {
-        for (int idx = tid; idx < tot; idx += kLineBlock) {
-            const int e = idx / LB, ll = idx - e * LB;
-            if (ll < nvalid) {
-                const int64_t a = line_addr(lg, l0 + ll, e);
-                T v = scale * lds[ll * ms + e];
-                if (addv) v += add_coef * addv[a];
-                out[a] = v;
-            }
+        red[tid] = acc;
+        __syncthreads();
+        for (int s2 = kLineBlock / 2; s2 > 0; s2 >>= 1) {
+            if (tid < s2) red[tid] += red[tid + s2];
+            __syncthreads();
+        }
+        last_block_finish(fz.lb, red[0], red);
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = r * 64 + e_lane;
+        if (e >= m) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (!ok[h]) continue;
+            const int64_t a = base[h] + (int64_t)(e * S32);
+            T v = scale * (h == 0 ? z[r].re : z[r].im);
+            if (addv) v += add_coef * addv[a];
+            out[a] = v;
         }
     }
 }
@@ -163,10 +159,20 @@ __global__ __launch_bounds__(kLineBlock) void line_conv_long(
     }
 }
 
+// Blocks of a barrier-free pass: one line pair per wave (64/L per wave for
+// L < 64), four waves per block.
+static unsigned line_direct_blocks(int log2L, const LineGeom& lg) {
+    const int64_t G = log2L >= 6 ? 1 : (64 >> log2L);
+    const int64_t npairs = (lg.nlines + 1) / 2;
+    const int64_t waves = (npairs + G - 1) / G;
+    return (unsigned)std::max<int64_t>(1, (waves + kLineBlock / 64 - 1) / (kLineBlock / 64));
+}
+
 template <class T>
 fkgp_status launch_line_conv(int log2L, int lg1, const T* in, T* out, const LineGeom& lg,
                              const T* lam, const cplx<T>* tw, T scale, const T* addv,
-                             T add_coef, const int* skip, cplx<T>* scr, hipStream_t s) {
+                             T add_coef, const int* skip, cplx<T>* scr, hipStream_t s,
+                             const CgStep2* fuse = nullptr) {
     if (lg1 > 0) {
         int want1, want2;
         long_split(log2L, want1, want2);
@@ -204,21 +210,13 @@ fkgp_status launch_line_conv(int log2L, int lg1, const T* in, T* out, const Line
         set_error("spectra not laid out for the standalone line FFT");
         return FKGP_EINVAL;
     }
-    const int64_t row = (int64_t)(lg.m_line + 1) * sizeof(T);
-    int64_t lb = lg.nlines / 512;
-    lb = std::max<int64_t>(lb, lg.S == 1 ? 2 : 8);
-    lb = std::min<int64_t>(lb, 64);
-    const int64_t budget = 60 * 1024 - (int64_t)(2 << log2L) * (int64_t)sizeof(T);
-    lb = std::min<int64_t>(lb, std::max<int64_t>(2, budget / row));
-    int LB = (int)lb & ~1;
-    if (LB > lg.nlines + (lg.nlines & 1)) LB = (int)(lg.nlines + (lg.nlines & 1));
-    if (LB < 2) LB = 2;
-    const size_t lds = (size_t)LB * row + (size_t)(2 << log2L) * sizeof(T);
-    const unsigned grid = (unsigned)((lg.nlines + LB - 1) / LB);
-#define FKGP_LC(LG)                                                                       \
-    case LG:                                                                              \
-        line_conv<T, LG><<<grid, kLineBlock, lds, s>>>(in, out, lg, LB, lam, tw, scale,   \
-                                                        addv, add_coef, skip);            \
+    CgStep2 fz{};
+    if (fuse) fz = *fuse;
+    const unsigned grid = line_direct_blocks(log2L, lg);
+#define FKGP_LC(LG)                                                                          \
+    case LG:                                                                                 \
+        line_conv_direct<T, LG><<<grid, kLineBlock, 0, s>>>(in, out, lg, lam, tw, scale,      \
+                                                             addv, add_coef, skip, fz);      \
         break;
     switch (log2L) {
         FKGP_LC(3) FKGP_LC(4) FKGP_LC(5) FKGP_LC(6) FKGP_LC(7) FKGP_LC(8) FKGP_LC(9)
@@ -384,7 +382,8 @@ __global__ __launch_bounds__(256) void spmv_tiled_kernel(const TA* __restrict__ 
                                                          const T* __restrict__ xpad,
                                                          T* __restrict__ u, TileGeom tg,
                                                          double* __restrict__ dotp,
-                                                         const int* __restrict__ skip) {
+                                                         const int* __restrict__ skip,
+                                                         LastBlockRed lb) {
     if (skip && *skip) return;
     extern __shared__ unsigned char lds_raw[];
     T* win = reinterpret_cast<T*>(lds_raw);
@@ -417,7 +416,11 @@ __global__ __launch_bounds__(256) void spmv_tiled_kernel(const TA* __restrict__ 
             if (t < s2) red[t] += red[t + s2];
             __syncthreads();
         }
-        if (t == 0) dotp[blockIdx.x] = red[0];
+        if (lb.ticket) {
+            last_block_finish(lb, red[0], red);   // publishes dotp[blockIdx.x] itself
+        } else if (t == 0) {
+            dotp[blockIdx.x] = red[0];
+        }
     }
 }
 
@@ -553,6 +556,52 @@ static fkgp_status kg_apply_t(const GridDev& g, const Spectra& sp, const T* x, T
     return FKGP_OK;
 }
 
+template <class T>
+static fkgp_status kg_apply_fused_t(const GridDev& g, const Spectra& sp, const T* x, T* y,
+                                    double scale, const T* addv, double add_coef,
+                                    const int* skip, const CgStep2& fuse, bool* fused,
+                                    hipStream_t s) {
+    int64_t M = 1;
+    for (int i = 0; i < g.d; ++i) M *= g.m[i];
+    *fused = sp.lg1[0] == 0;   // the last pass (dimension 0) on the register path
+    for (int pass = 0; pass < g.d; ++pass) {
+        const int dim = g.d - 1 - pass;
+        int64_t S = 1;
+        for (int i = dim + 1; i < g.d; ++i) S *= g.m[i];
+        LineGeom lg{g.m[dim], S, M / g.m[dim]};
+        const bool last = pass == g.d - 1;
+        const T* src = pass == 0 ? x : y;
+        fkgp_status st = launch_line_conv<T>(
+            sp.log2L[dim], sp.lg1[dim], src, y, lg, static_cast<const T*>(sp.lam[dim]),
+            static_cast<const cplx<T>*>(sp.tw[dim]), last ? (T)scale : T(1),
+            last ? addv : nullptr, (T)add_coef, skip, static_cast<cplx<T>*>(sp.scr[dim]), s,
+            (last && *fused) ? &fuse : nullptr);
+        if (st != FKGP_OK) return st;
+    }
+    return FKGP_OK;
+}
+
+fkgp_status kg_apply_fused(const GridDev& g, const Spectra& sp, fkgp_dtype dt, const void* x,
+                           void* y, double scale, const void* addv, double add_coef,
+                           const int* skip, const CgStep2& fuse, bool* fused, hipStream_t s) {
+    if (dt == FKGP_F32)
+        return kg_apply_fused_t<float>(g, sp, static_cast<const float*>(x),
+                                       static_cast<float*>(y), scale,
+                                       static_cast<const float*>(addv), add_coef, skip, fuse,
+                                       fused, s);
+    return kg_apply_fused_t<double>(g, sp, static_cast<const double*>(x),
+                                    static_cast<double*>(y), scale,
+                                    static_cast<const double*>(addv), add_coef, skip, fuse,
+                                    fused, s);
+}
+
+int64_t kg_last_pass_blocks(const GridDev& g) {
+    int64_t M = 1;
+    for (int i = 0; i < g.d; ++i) M *= g.m[i];
+    LineGeom lg{g.m[0], M / g.m[0], M / g.m[0]};
+    return line_direct_blocks(circulant_log2(g.m[0]), lg);
+}
+
 fkgp_status kg_apply(const GridDev& g, const Spectra& sp, fkgp_dtype dt, const void* x, void* y,
                      int k, double scale, const void* addv, double add_coef, void* /*work*/,
                      hipStream_t s) {
@@ -604,29 +653,31 @@ static bool tile_geom(const GridDev& g, size_t es, TileGeom& tg, size_t& lds) {
 template <class TA, class T>
 static fkgp_status spmv_t(const GridDev& g, const TA* A, const T* xpad, T* u, int k,
                           int64_t halo, const int* skip, hipStream_t s, double* dotp = nullptr,
-                          int* nparts = nullptr) {
+                          int* nparts = nullptr, const LastBlockRed* lb = nullptr) {
     TileGeom tg;
     size_t lds;
     if (k == 1 && tile_geom(g, sizeof(T), tg, lds)) {
+        LastBlockRed lbv{};
+        if (lb && dotp) lbv = *lb;
         const unsigned grid = (unsigned)((tg.M + kTileRows - 1) / kTileRows);
         if (g.d == 1) {
             if (lds > 64 * 1024)
                 FKGP_HIP(hipFuncSetAttribute(
                     reinterpret_cast<const void*>(&spmv_tiled_kernel<TA, T, 1>),
                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            spmv_tiled_kernel<TA, T, 1><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip);
+            spmv_tiled_kernel<TA, T, 1><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip, lbv);
         } else if (g.d == 2) {
             if (lds > 64 * 1024)
                 FKGP_HIP(hipFuncSetAttribute(
                     reinterpret_cast<const void*>(&spmv_tiled_kernel<TA, T, 2>),
                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            spmv_tiled_kernel<TA, T, 2><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip);
+            spmv_tiled_kernel<TA, T, 2><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip, lbv);
         } else {
             if (lds > 64 * 1024)
                 FKGP_HIP(hipFuncSetAttribute(
                     reinterpret_cast<const void*>(&spmv_tiled_kernel<TA, T, 3>),
                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            spmv_tiled_kernel<TA, T, 3><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip);
+            spmv_tiled_kernel<TA, T, 3><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip, lbv);
         }
         if (nparts) *nparts = dotp ? (int)grid : 0;
         FKGP_HIP(hipGetLastError());
@@ -694,19 +745,19 @@ fkgp_status spmv_dia_skip(const GridDev& g, fkgp_dtype dt, const void* A, const 
 // upcast exactly when the vectors are FP64).
 fkgp_status spmv_dia_any(const GridDev& g, fkgp_dtype dta, fkgp_dtype dtx, const void* A,
                          const void* xpad, void* u, int k, int64_t halo, const int* skip,
-                         hipStream_t s, double* dotp, int* nparts) {
+                         hipStream_t s, double* dotp, int* nparts, const LastBlockRed* lb) {
     if (dta == FKGP_F32 && dtx == FKGP_F32)
         return spmv_t<float, float>(g, static_cast<const float*>(A),
                                     static_cast<const float*>(xpad), static_cast<float*>(u), k,
-                                    halo, skip, s, dotp, nparts);
+                                    halo, skip, s, dotp, nparts, lb);
     if (dta == FKGP_F64 && dtx == FKGP_F64)
         return spmv_t<double, double>(g, static_cast<const double*>(A),
                                       static_cast<const double*>(xpad), static_cast<double*>(u), k,
-                                      halo, skip, s, dotp, nparts);
+                                      halo, skip, s, dotp, nparts, lb);
     if (dta == FKGP_F32 && dtx == FKGP_F64)
         return spmv_t<float, double>(g, static_cast<const float*>(A),
                                      static_cast<const double*>(xpad), static_cast<double*>(u), k,
-                                     halo, skip, s, dotp, nparts);
+                                     halo, skip, s, dotp, nparts, lb);
     set_error("unsupported matrix/vector dtype combination");
     return FKGP_EINVAL;
 }

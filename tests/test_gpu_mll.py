@@ -63,11 +63,15 @@ def test_mll_and_grad_parity(stats, batched, steps):
         tol_m, tol_g = (1e-6, 1e-4) if steps == 10 else (1e-6, 1e-4)
     print(f"stats={stats} batched={batched} steps={steps}: mll {mll:.12g} vs {mll_o:.12g}; "
           f"grad {np.array(g)} vs {g_o}")
+    # q = y^T A^{-1} y from two solves stopped at relative residual 1e-10:
+    # |y^T A^{-1} r| <= ||y||^2 tol / sigma^2 each (lambda_min(A) >= sigma^2)
+    s2 = hyp["noise"] ** 2
+    q_bound = 2 * 1e-10 * float(np.dot(y.astype(np.float64), y)) / s2
     # the MLL is a small difference of large terms: scale by their magnitude
     scale = abs(inf_o["logdet"]) + abs(inf_o["q"]) + X.shape[1] * math.log(2 * math.pi)
-    assert abs(mll - mll_o) <= tol_m * scale, (mll, mll_o)
+    assert abs(mll - mll_o) <= tol_m * scale + 0.5 * q_bound, (mll, mll_o)
     assert abs(inf["logdet"] - inf_o["logdet"]) <= tol_m * abs(inf_o["logdet"])
-    assert abs(inf["quad"] - inf_o["q"]) <= tol_m * abs(inf_o["q"])
+    assert abs(inf["quad"] - inf_o["q"]) <= tol_m * abs(inf_o["q"]) + q_bound
     np.testing.assert_allclose(g, g_o, rtol=0, atol=tol_g * np.abs(g_o).max())
 
 
