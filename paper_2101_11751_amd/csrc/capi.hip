@@ -29,8 +29,9 @@ struct fkgp_handle {
     void* A = nullptr;          // [NB][M] stats dtype
     double* wty = nullptr;      // [M]
     double* sketches = nullptr; // [nprobe][M]
-    double* yty_dev = nullptr;
+    double* yty_dev = nullptr;  // [2]: y^T y, then the out-of-grid flag (bits)
     double yty = 0.0;
+    void* block = nullptr;      // one pool allocation holding the arrays above
 };
 
 namespace fkgp {
@@ -55,10 +56,29 @@ fkgp_status hip_fail(hipError_t e, const char* what) {
 namespace {
 
 // Scratch allocations released (stream-ordered) when the scope ends.
+// Memory freed to the device's default pool stays cached in it (release
+// threshold raised once per device), so repeated calls reuse mapped memory
+// instead of mapping fresh pages each time.
+std::mutex g_pool_mu;
+bool g_pool_ready[64] = {};
+
+void ensure_pool() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (g_pool_ready[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = ~0ull;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    g_pool_ready[dev] = true;
+}
+
 struct Scratch {
     hipStream_t s;
     std::vector<void*> ptrs;
-    explicit Scratch(hipStream_t st) : s(st) {}
+    explicit Scratch(hipStream_t st) : s(st) { ensure_pool(); }
     ~Scratch() {
         for (void* p : ptrs) (void)hipFreeAsync(p, s);
     }
@@ -710,14 +730,18 @@ fkgp_status guarded(F&& f) {
     }
 }
 
+// The handle's arrays come from the device's stream-ordered pool (as all
+// scratch does): freed on the default stream once pending work is done.
 void free_handle(fkgp_handle* h) {
     if (!h) return;
-    (void)hipFree(h->A);
-    (void)hipFree(h->wty);
-    (void)hipFree(h->sketches);
-    (void)hipFree(h->yty_dev);
+    if (h->block) {
+        (void)hipDeviceSynchronize();
+        (void)hipFreeAsync(h->block, nullptr);
+        (void)hipStreamSynchronize(nullptr);
+    }
     delete h;
 }
+
 
 }  // namespace
 
@@ -792,34 +816,36 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
             return e;
         };
         hipError_t e;
-        if ((e = hipMalloc(&h->A, dsize(h->dt) * (size_t)dia_elems(M, h->NB))) != hipSuccess)
-            return fail(hip_fail(e, "hipMalloc(W^T W)"));
-        if ((e = hipMalloc(&h->wty, sizeof(double) * M)) != hipSuccess)
-            return fail(hip_fail(e, "hipMalloc(W^T y)"));
-        if (h->nprobe > 0 &&
-            (e = hipMalloc(&h->sketches, sizeof(double) * M * h->nprobe)) != hipSuccess)
-            return fail(hip_fail(e, "hipMalloc(sketches)"));
-        if ((e = hipMalloc(&h->yty_dev, sizeof(double))) != hipSuccess)
-            return fail(hip_fail(e, "hipMalloc(yty)"));
-        unsigned long long* bad = nullptr;
-        if ((e = hipMallocAsync(reinterpret_cast<void**>(&bad), sizeof(unsigned long long), s)) !=
-            hipSuccess)
-            return fail(hip_fail(e, "hipMallocAsync(flag)"));
+        fkgp::ensure_pool();
+        // one allocation: W^T W, W^T y, sketches, then y^T y and the
+        // out-of-grid flag side by side (read back with one copy)
+        auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+        const size_t bA = up(dsize(h->dt) * (size_t)dia_elems(M, h->NB));
+        const size_t bW = up(sizeof(double) * M);
+        const size_t bS = up(sizeof(double) * M * h->nprobe);
+        if ((e = hipMallocAsync(&h->block, bA + bW + bS + 256, s)) != hipSuccess)
+            return fail(hip_fail(e, "hipMallocAsync(handle)"));
+        unsigned char* hb = static_cast<unsigned char*>(h->block);
+        h->A = hb;
+        h->wty = reinterpret_cast<double*>(hb + bA);
+        h->sketches = h->nprobe > 0 ? reinterpret_cast<double*>(hb + bA + bW) : nullptr;
+        h->yty_dev = reinterpret_cast<double*>(hb + bA + bW + bS);
+        unsigned long long* bad = reinterpret_cast<unsigned long long*>(h->yty_dev + 1);
         (void)hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), s);
         StatsOut so{h->A, h->wty, h->sketches, h->yty_dev};
         st = run_precompute(g, x, y, n, in, h->dt, h->nprobe, h->seed, so, bad, s);
         unsigned long long hbad = ~0ull;
+        double back[2] = {0.0, 0.0};
         if (st == FKGP_OK) {
-            if ((e = hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s)) != hipSuccess)
-                st = hip_fail(e, "hipMemcpyAsync(flag)");
-            else if ((e = hipMemcpyAsync(&h->yty, h->yty_dev, sizeof(double), hipMemcpyDeviceToHost,
-                                         s)) != hipSuccess)
-                st = hip_fail(e, "hipMemcpyAsync(yty)");
+            if ((e = hipMemcpyAsync(back, h->yty_dev, sizeof(back), hipMemcpyDeviceToHost, s)) !=
+                hipSuccess)
+                st = hip_fail(e, "hipMemcpyAsync(y^T y, flag)");
         }
-        (void)hipFreeAsync(bad, s);
         if ((e = hipStreamSynchronize(s)) != hipSuccess && st == FKGP_OK)
             st = hip_fail(e, "hipStreamSynchronize");
         if (st != FKGP_OK) return fail(st);
+        h->yty = back[0];
+        std::memcpy(&hbad, &back[1], sizeof(hbad));
         if (hbad != ~0ull) {
             set_error("point " + std::to_string(hbad) + " lies outside the interpolable region");
             return fail(FKGP_EOUTOFGRID);

@@ -18,6 +18,7 @@
 //      giving W^T W in stencil-diagonal form, W^T y and the sketches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "common.h"
@@ -495,6 +496,125 @@ __global__ __launch_bounds__(64) void cell_moments(
     if (lane == 0) Myy[cell] = accyy;
 }
 
+// 3-D moments (no probes), accumulated in registers.  Lane l < 63 of the
+// wave belongs to point group g = l / 7 (points g, g + 9, g + 18, ... of the
+// cell, in sorted order) and owns the moments with q2 = l % 7: 49 sums over
+// (q0, q1) of t0^q0 t1^q1 t2^q2, and for q2 <= 3 the 16 response moments
+// y t0^q0 t1^q1 t2^q2 (q0, q1 <= 3).  Points are located in batches of 64
+// (one per lane) into LDS; at the end the 9 groups are summed in group
+// order through LDS.  Deterministic: every sum has a fixed order.
+constexpr int kMomGroups = 9;
+
+template <class Tin>
+__global__ __launch_bounds__(64) void cell_moments3(
+    const typename PayloadOf<Tin>::type* __restrict__ pay,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, GridDev g,
+    double* __restrict__ Mw, double* __restrict__ Mr, double* __restrict__ Myy) {
+    __shared__ double pts[64][4];                     // t0, t1, t2, y
+    __shared__ double red[kMomGroups * 7][17];        // one chunk of 16 sums per lane
+    const int cell = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int grp = lane / 7, q2 = lane % 7;
+    const bool act = lane < kMomGroups * 7;
+    const uint32_t s0 = cstart[cell];
+    const uint32_t s1 = cend[cell];
+    double acc[7][7], accy[4][4];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+#pragma unroll
+        for (int j = 0; j < 7; ++j) acc[i][j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) accy[i][j] = 0.0;
+    double accyy = 0.0;
+    for (uint32_t b0 = s0; b0 < s1; b0 += 64) {
+        const int cnt = (int)min(64u, s1 - b0);
+        if (lane < cnt) {
+            const auto p = pay[b0 + lane];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                int base;
+                double t;
+                if (!locate((double)get_slot(p, k), g.g0[k], g.h[k], g.m[k], base, t)) t = 0.0;
+                pts[lane][k] = t;
+            }
+            pts[lane][3] = (double)get_slot(p, 3);
+        }
+        __syncthreads();
+        if (act) {
+            for (int p = grp; p < cnt; p += kMomGroups) {
+                const double t0 = pts[p][0], t1 = pts[p][1], t2 = pts[p][2], yv = pts[p][3];
+                double av[7], bv[7];
+                av[0] = 1.0;
+                bv[0] = 1.0;
+#pragma unroll
+                for (int q = 1; q < 7; ++q) {
+                    av[q] = av[q - 1] * t0;
+                    bv[q] = bv[q - 1] * t1;
+                }
+                const double t22 = t2 * t2;
+                double c = (q2 & 1) ? t2 : 1.0;
+                if (q2 & 2) c *= t22;
+                if (q2 & 4) c *= t22 * t22;
+#pragma unroll
+                for (int q0 = 0; q0 < 7; ++q0) {
+                    const double ac = av[q0] * c;
+#pragma unroll
+                    for (int q1 = 0; q1 < 7; ++q1) acc[q0][q1] = fma(ac, bv[q1], acc[q0][q1]);
+                }
+                if (q2 < 4) {
+                    const double yc = yv * c;
+#pragma unroll
+                    for (int q0 = 0; q0 < 4; ++q0) {
+                        const double ayc = av[q0] * yc;
+#pragma unroll
+                        for (int q1 = 0; q1 < 4; ++q1)
+                            accy[q0][q1] = fma(ayc, bv[q1], accy[q0][q1]);
+                    }
+                }
+                if (q2 == 0) accyy = fma(yv, yv, accyy);
+            }
+        }
+        __syncthreads();
+    }
+    // sum the 9 groups: 65 values per lane (49 W moments, 16 response
+    // moments), in chunks of 16 through LDS
+#pragma unroll
+    for (int ch = 0; ch < 5; ++ch) {
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int v = ch * 16 + j;
+                double x = 0.0;
+                if (v < 49) x = acc[v / 7][v % 7];
+                else if (v < 65) x = accy[(v - 49) / 4][(v - 49) % 4];
+                red[lane][j] = x;
+            }
+        }
+        __syncthreads();
+        for (int o = lane; o < 7 * 16; o += 64) {
+            const int oq2 = o / 16, j = o % 16;
+            const int v = ch * 16 + j;
+            double sum = 0.0;
+            for (int gg = 0; gg < kMomGroups; ++gg) sum += red[gg * 7 + oq2][j];
+            if (v < 49) {
+                Mw[(size_t)cell * 343 + v * 7 + oq2] = sum;   // q0*49 + q1*7 + q2
+            } else if (v < 65 && oq2 < 4) {
+                Mr[(size_t)cell * 64 + (v - 49) * 4 + oq2] = sum;   // q0*16 + q1*4 + q2
+            }
+        }
+        __syncthreads();
+    }
+    if (q2 == 0 && act) red[grp][0] = accyy;
+    __syncthreads();
+    if (lane == 0) {
+        double sum = 0.0;
+        for (int gg = 0; gg < kMomGroups; ++gg) sum += red[gg][0];
+        Myy[cell] = sum;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // 4. Separable assembly.
 // ---------------------------------------------------------------------------
@@ -505,35 +625,48 @@ struct Dims3 {
 // W^T W stage for dimension k: payload digit k (base 7) changes from a moment
 // index q to an offset index o+3; spatial dimension k grows from cells to
 // nodes: out[.., j_k, ..][.., o, ..] = sum_{a, q} E[o][a][q] in[.., j_k-a, ..][.., q, ..].
-__global__ void assemble_wtw_stage(const double* __restrict__ in, double* __restrict__ out,
-                                   Dims3 sin, Dims3 sout, int d, int k, KeysTables tab) {
-    int P = 1;
-    for (int i = 0; i < d; ++i) P *= 7;
-    const int64_t total = (int64_t)sout.n[0] * sout.n[1] * sout.n[2] * P;
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int pay = (int)(idx % P);
-    int64_t sp = idx / P;
-    int s[3];
-    for (int i = 2; i >= 0; --i) {
-        s[i] = (int)(sp % sout.n[i]);
-        sp /= sout.n[i];
-    }
+// One thread per (output position, payload with digit k removed): it reads
+// the 4 x 7 inputs once and produces all 7 offsets.  Positions (< 2^30) use
+// 32-bit arithmetic; the flat thread index is split by a compile-time 7^(d-1).
+template <int D>
+__global__ __launch_bounds__(256) void assemble_wtw_stage(const double* __restrict__ in,
+                                                          double* __restrict__ out, Dims3 sin,
+                                                          Dims3 sout, int k, KeysTables tab) {
+    constexpr int P = D == 1 ? 7 : (D == 2 ? 49 : 343);
+    constexpr int P0 = P / 7;
+    const int64_t tot_sp = (int64_t)sout.n[0] * sout.n[1] * sout.n[2];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tot_sp * P0) return;
+    const int p0i = (int)(idx % P0);
+    const int sp = (int)(idx / P0);
     int pstride = 1;
-    for (int i = d - 1; i > k; --i) pstride *= 7;
-    const int o = (pay / pstride) % 7;
-    const int pay0 = pay - o * pstride;
-    double acc = 0.0;
+    for (int i = D - 1; i > k; --i) pstride *= 7;
+    const int pay0 = (p0i / pstride) * pstride * 7 + p0i % pstride;
+    int s[3];
+    s[2] = sp % sout.n[2];
+    s[1] = (sp / sout.n[2]) % sout.n[1];
+    s[0] = sp / (sout.n[2] * sout.n[1]);
+    double acc[7];
+#pragma unroll
+    for (int o = 0; o < 7; ++o) acc[o] = 0.0;
+#pragma unroll
     for (int a = 0; a < 4; ++a) {
         const int c = s[k] - a;
         if (c < 0 || c >= sin.n[k]) continue;
         int t[3] = {s[0], s[1], s[2]};
         t[k] = c;
-        const int64_t ib = (((int64_t)t[0] * sin.n[1] + t[1]) * sin.n[2] + t[2]) * P + pay0;
+        const int64_t ib = (int64_t)((t[0] * sin.n[1] + t[1]) * sin.n[2] + t[2]) * P + pay0;
+        double v[7];
 #pragma unroll
-        for (int q = 0; q < 7; ++q) acc = fma(tab.E[o][a][q], in[ib + q * pstride], acc);
+        for (int q = 0; q < 7; ++q) v[q] = in[ib + q * pstride];
+#pragma unroll
+        for (int o = 0; o < 7; ++o)
+#pragma unroll
+            for (int q = 0; q < 7; ++q) acc[o] = fma(tab.E[o][a][q], v[q], acc[o]);
     }
-    out[idx] = acc;
+    const int64_t ob = (int64_t)sp * P + pay0;
+#pragma unroll
+    for (int o = 0; o < 7; ++o) out[ob + o * pstride] = acc[o];
 }
 
 // Vector stage for dimension k (processed from the last to the first): the
@@ -606,6 +739,24 @@ __global__ __launch_bounds__(1024) void sum_fixed(const double* __restrict__ v, 
     if (threadIdx.x == 0) *out = sh[0];
 }
 
+// Sub-allocation from one scratch block (256-byte aligned pieces): one
+// stream-ordered allocation and one free per precompute instead of a dozen
+// (each allocator call costs host time).
+struct Carver {
+    unsigned char* base = nullptr;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        T* p = reinterpret_cast<T*>(base + off);
+        off += (count * sizeof(T) + 255) & ~size_t(255);
+        return p;
+    }
+    template <class T>
+    void skip(size_t count) {
+        off += (count * sizeof(T) + 255) & ~size_t(255);
+    }
+};
+
 template <class Tin>
 fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void* yv,
                              int64_t n, fkgp_dtype stats, int nprobe, uint64_t seed,
@@ -641,30 +792,61 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
     }
     const int ntiles = (int)((n + tile_size<Tin>() - 1) / tile_size<Tin>());
 
-    double* Mw = nullptr;
-    double* Mr = nullptr;
-    double* Myy = nullptr;
-    uint32_t* cstart = nullptr;
-    uint32_t* cend = nullptr;
-    FKGP_HIP(alloc_async(&Mw, (size_t)ncells * NB, s));
-    FKGP_HIP(alloc_async(&Mr, (size_t)ncells * NR * nr, s));
-    FKGP_HIP(alloc_async(&Myy, (size_t)ncells, s));
-    FKGP_HIP(alloc_async(&cstart, (size_t)ncells, s));
-    FKGP_HIP(alloc_async(&cend, (size_t)ncells, s));
+    // scratch layout: the per-cell moments and cell bounds live throughout;
+    // the sort buffers and the assembly buffers share one region (the sort
+    // is finished before the assembly starts)
+    const size_t ncount = (size_t)ntiles << 10;
+    auto sort_bytes = [&](Carver c) {
+        c.skip<uint32_t>((size_t)n);
+        c.skip<uint32_t>((size_t)n);
+        c.skip<P>((size_t)n);
+        c.skip<P>((size_t)n);
+        c.skip<uint32_t>(ncount);
+        c.skip<uint32_t>(ncount);
+        c.skip<uint32_t>((ncount + kScanChunk - 1) / kScanChunk + 1);
+        return c.off;
+    };
+    auto asm_bytes = [&](Carver c) {
+        c.skip<double>((size_t)M * NB);
+        c.skip<double>((size_t)M * NB);
+        return c.off;
+    };
+    auto vec_bytes = [&](Carver c) {
+        c.skip<double>((size_t)M * NR * nr);
+        c.skip<double>((size_t)M * NR * nr);
+        return c.off;
+    };
+    Carver whole;
+    double* Mw = whole.take<double>((size_t)ncells * NB);
+    double* Mr = whole.take<double>((size_t)ncells * NR * nr);
+    double* Myy = whole.take<double>((size_t)ncells);
+    uint32_t* cstart = whole.take<uint32_t>((size_t)ncells);
+    uint32_t* cend = whole.take<uint32_t>((size_t)ncells);
+    const size_t shared_off = whole.off;
+    Carver z0;
+    const size_t region = std::max({sort_bytes(z0), asm_bytes(z0), vec_bytes(z0)});
+    unsigned char* block = nullptr;
+    FKGP_HIP(alloc_async(&block, shared_off + region, s));
+    auto rebase = [&](auto* p) {
+        return reinterpret_cast<decltype(p)>(block + reinterpret_cast<uintptr_t>(p));
+    };
+    Mw = rebase(Mw);
+    Mr = rebase(Mr);
+    Myy = rebase(Myy);
+    cstart = rebase(cstart);
+    cend = rebase(cend);
     FKGP_HIP(hipMemsetAsync(cstart, 0, sizeof(uint32_t) * ncells, s));
     FKGP_HIP(hipMemsetAsync(cend, 0, sizeof(uint32_t) * ncells, s));
 
     if (n > 0) {
-        uint32_t *ka = nullptr, *kb = nullptr, *counts = nullptr, *offs = nullptr, *sums = nullptr;
-        P *pa = nullptr, *pb = nullptr;
-        const size_t ncount = (size_t)ntiles << 10;
-        FKGP_HIP(alloc_async(&ka, (size_t)n, s));
-        FKGP_HIP(alloc_async(&kb, (size_t)n, s));
-        FKGP_HIP(alloc_async(&pa, (size_t)n, s));
-        FKGP_HIP(alloc_async(&pb, (size_t)n, s));
-        FKGP_HIP(alloc_async(&counts, ncount, s));
-        FKGP_HIP(alloc_async(&offs, ncount, s));
-        FKGP_HIP(alloc_async(&sums, (ncount + kScanChunk - 1) / kScanChunk + 1, s));
+        Carver c{block + shared_off, 0};
+        uint32_t* ka = c.take<uint32_t>((size_t)n);
+        uint32_t* kb = c.take<uint32_t>((size_t)n);
+        P* pa = c.take<P>((size_t)n);
+        P* pb = c.take<P>((size_t)n);
+        uint32_t* counts = c.take<uint32_t>(ncount);
+        uint32_t* offs = c.take<uint32_t>(ncount);
+        uint32_t* sums = c.take<uint32_t>((ncount + kScanChunk - 1) / kScanChunk + 1);
 
         keys_and_counts<Tin><<<ntiles, kBlock, sizeof(uint32_t) << dbits[0], s>>>(
             xs, n, g, ka, counts, ntiles, dshift[0], dbits[0], bad);
@@ -705,17 +887,12 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         else if (d == 2)
             cell_moments<2, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
                                                                  (int)ncells, Mw, Mr, Myy);
+        else if (nprobe == 0)
+            cell_moments3<Tin><<<(unsigned)ncells, 64, 0, s>>>(pin, cstart, cend, g, Mw, Mr, Myy);
         else
             cell_moments<3, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
                                                                  (int)ncells, Mw, Mr, Myy);
         FKGP_HIP(hipGetLastError());
-        FKGP_HIP(hipFreeAsync(ka, s));
-        FKGP_HIP(hipFreeAsync(kb, s));
-        FKGP_HIP(hipFreeAsync(pa, s));
-        FKGP_HIP(hipFreeAsync(pb, s));
-        FKGP_HIP(hipFreeAsync(counts, s));
-        FKGP_HIP(hipFreeAsync(offs, s));
-        FKGP_HIP(hipFreeAsync(sums, s));
     } else {
         FKGP_HIP(hipMemsetAsync(Mw, 0, sizeof(double) * ncells * NB, s));
         FKGP_HIP(hipMemsetAsync(Mr, 0, sizeof(double) * ncells * NR * nr, s));
@@ -727,18 +904,22 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
     {
         Dims3 cur{{1, 1, 1}};
         for (int k = 0; k < d; ++k) cur.n[k] = g.nc[k];
-        double* bufA = nullptr;
-        double* bufB = nullptr;
-        FKGP_HIP(alloc_async(&bufA, (size_t)M * NB, s));
-        FKGP_HIP(alloc_async(&bufB, (size_t)M * NB, s));
+        Carver c{block + shared_off, 0};
+        double* bufA = c.take<double>((size_t)M * NB);
+        double* bufB = c.take<double>((size_t)M * NB);
         const double* src = Mw;
         double* dst = bufA;
         for (int k = d - 1; k >= 0; --k) {
             Dims3 nxt = cur;
             nxt.n[k] = g.m[k];
-            const int64_t total = (int64_t)nxt.n[0] * nxt.n[1] * nxt.n[2] * NB;
-            assemble_wtw_stage<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(src, dst, cur, nxt,
-                                                                                d, k, tab);
+            const int64_t total = (int64_t)nxt.n[0] * nxt.n[1] * nxt.n[2] * (NB / 7);
+            const unsigned nbk = (unsigned)((total + 255) / 256);
+            if (d == 1)
+                assemble_wtw_stage<1><<<nbk, 256, 0, s>>>(src, dst, cur, nxt, k, tab);
+            else if (d == 2)
+                assemble_wtw_stage<2><<<nbk, 256, 0, s>>>(src, dst, cur, nxt, k, tab);
+            else
+                assemble_wtw_stage<3><<<nbk, 256, 0, s>>>(src, dst, cur, nxt, k, tab);
             FKGP_HIP(hipGetLastError());
             cur = nxt;
             src = dst;
@@ -751,17 +932,14 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         else
             transpose_to_dia<double><<<tg, tb, 0, s>>>(src, static_cast<double*>(out.wtw), M, NB);
         FKGP_HIP(hipGetLastError());
-        FKGP_HIP(hipFreeAsync(bufA, s));
-        FKGP_HIP(hipFreeAsync(bufB, s));
     }
     // --- W^T y and sketches: stages over k = d-1 .. 0 ---
     {
         Dims3 cur{{1, 1, 1}};
         for (int k = 0; k < d; ++k) cur.n[k] = g.nc[k];
-        double* bufA = nullptr;
-        double* bufB = nullptr;
-        FKGP_HIP(alloc_async(&bufA, (size_t)M * NR * nr, s));
-        FKGP_HIP(alloc_async(&bufB, (size_t)M * NR * nr, s));
+        Carver c{block + shared_off, 0};
+        double* bufA = c.take<double>((size_t)M * NR * nr);
+        double* bufB = c.take<double>((size_t)M * NR * nr);
         const double* src = Mr;
         int Pin = NR;
         for (int k = d - 1; k >= 0; --k) {
@@ -782,16 +960,10 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         if (nprobe > 0)
             FKGP_HIP(hipMemcpyAsync(out.sketches, src + M, sizeof(double) * M * nprobe,
                                     hipMemcpyDeviceToDevice, s));
-        FKGP_HIP(hipFreeAsync(bufA, s));
-        FKGP_HIP(hipFreeAsync(bufB, s));
     }
     sum_fixed<<<1, 1024, 0, s>>>(Myy, ncells, out.yty_dev);
     FKGP_HIP(hipGetLastError());
-    FKGP_HIP(hipFreeAsync(Mw, s));
-    FKGP_HIP(hipFreeAsync(Mr, s));
-    FKGP_HIP(hipFreeAsync(Myy, s));
-    FKGP_HIP(hipFreeAsync(cstart, s));
-    FKGP_HIP(hipFreeAsync(cend, s));
+    FKGP_HIP(hipFreeAsync(block, s));
     return FKGP_OK;
 }
 
