@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc runs (FETCH_SIZE x 1.9995, WRITE_SIZE x 1.0, calibrated on a
 # 256 MiB copy) recorded in profiles/radar3d_hbm_traffic_pmc.md.  Set to None
 # whenever spmv_tiled_kernel changes until the counters are taken again.
-SPMV_TRAFFIC_BYTES = None
+SPMV_TRAFFIC_BYTES = 429.7e6
 
 
 def _parse():

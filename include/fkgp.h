@@ -20,6 +20,10 @@
  *   - The library owns a handle's internals (allocated on the current device)
  *     until fkgp_destroy.  A handle is immutable after fkgp_precompute, so
  *     calls on different streams may share it.
+ *   - Device memory (handles and per-call scratch) comes from the device's
+ *     default stream-ordered pool, whose release threshold the library
+ *     raises on first use: freed memory stays cached in the process for
+ *     reuse by later calls (as a caching allocator does).
  *   - Grid nodes of dimension k sit at origin[k] + j*spacing[k], j < m[k];
  *     nodes are flattened in C order (dimension 0 slowest).  Grid vectors
  *     (length M = prod m) use that order.
