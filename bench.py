@@ -50,6 +50,7 @@ def _parse():
     ap.add_argument("--mll-tol", type=float, default=1e-4)
     ap.add_argument("--mll-maxiter", type=int, default=20000)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--batch-tol", type=float, default=1e-4)
     ap.add_argument("--batch-maxiter", type=int, default=30000)
     return ap.parse_args()
@@ -186,6 +187,32 @@ def batch_compare(P, workloads, torch, dev, tol, maxiter):
             "converged": conv}
 
 
+def precompute_extra(P, workloads, torch, dev, reps=3):
+    """Precompute throughput on the 2-D bump workload (128x128 grid) at
+    n = 1e6 (its own size) and n = 1e8 (large enough for a bandwidth
+    figure): Mpts/s of the best of `reps` timed calls after a warm-up."""
+    out = {}
+    for n in (1_000_000, 100_000_000):
+        wl = workloads.bumps2d(n=n, device=dev)
+        torch.cuda.synchronize()
+        best = None
+        for r in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            h = P.precompute(wl["grid"], wl["x"], wl["y"], stats_dtype=torch.float32)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 1e3
+            if r > 0:
+                best = t if best is None else min(best, t)
+            h.close()
+        out[f"bumps2d_n{n:.0e}".replace("+0", "")] = {"ms": best * 1e3, "mpts_per_s": n / best / 1e6}
+        log(f"precompute bumps2d n={n}: {best*1e3:.2f} ms, {n/best/1e6:.0f} Mpts/s")
+        del wl
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -297,11 +324,14 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_us": t_spmv * 1e6},
     }
     if not args.no_mll:
-        del h, mu
         torch.cuda.empty_cache()
         mc = mll_compare(P, workloads, torch, dev, args.mll_reps, args.mll_tol, args.mll_maxiter)
         result["mll_grad_s_per_eval"] = mc["batched_f32_s_per_eval"]
         result["mll_grad"] = mc
+    if not args.no_extra:
+        del h, mu
+        torch.cuda.empty_cache()
+        result["precompute_2d"] = precompute_extra(P, workloads, torch, dev)
     if not args.no_batch:
         torch.cuda.empty_cache()
         bc = batch_compare(P, workloads, torch, dev, args.batch_tol, args.batch_maxiter)

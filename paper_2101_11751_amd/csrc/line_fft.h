@@ -9,8 +9,8 @@
 // scaling by the real spectrum stored in bit-reversed order (and already
 // divided by L), then the matching decimation in time with conjugate
 // twiddles (bit-reversed in, natural out): no permutation pass is needed.
-// Spans below 64 are exchanged with wavefront shuffles, larger spans stay in
-// a lane's registers.  tws: exp(-2 pi i t / L), t < L/2; lams: spectrum.
+// Spans below 64 are exchanged across lanes (DPP moves for spans up to 8, a
+// swizzle for 16, a permute for 32), larger spans stay in a lane's registers.  tws: exp(-2 pi i t / L), t < L/2; lams: spectrum.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,6 +33,48 @@ __device__ inline cplx<T> cmul_conj(cplx<T> a, cplx<T> b) {  // a * conj(b)
 
 template <int LOG2L>
 constexpr int line_regs() { return (1 << LOG2L) >= 64 ? (1 << LOG2L) / 64 : 1; }
+
+// Value of lane (lane ^ S) for S < 64.  Spans 1 and 2 are quad permutes and
+// spans 4 and 8 a pair of row shifts and a select (DPP: VALU latency, no LDS
+// round trip); span 16 is a swizzle (xor within 32 lanes), span 32 a
+// permute through the LDS crossbar.
+__device__ __forceinline__ int lane_xor_b32(int v, int S) {
+    switch (S) {
+        case 1:
+            return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+        case 2:
+            return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+        case 4: {
+            const int from_up = __builtin_amdgcn_mov_dpp(v, 0x104, 0xF, 0xF, false);   // row_shl:4
+            const int from_dn = __builtin_amdgcn_mov_dpp(v, 0x114, 0xF, 0xF, false);   // row_shr:4
+            return (__lane_id() & 4) ? from_dn : from_up;
+        }
+        case 8: {
+            const int from_up = __builtin_amdgcn_mov_dpp(v, 0x108, 0xF, 0xF, false);   // row_shl:8
+            const int from_dn = __builtin_amdgcn_mov_dpp(v, 0x118, 0xF, 0xF, false);   // row_shr:8
+            return (__lane_id() & 8) ? from_dn : from_up;
+        }
+        case 16:
+            return __builtin_amdgcn_ds_swizzle(v, 0x401F);   // xor_mask 16, and_mask 31
+        default:
+            return __shfl_xor(v, S);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T lane_xor(T v, int S);
+
+template <>
+__device__ __forceinline__ float lane_xor<float>(float v, int S) {
+    return __int_as_float(lane_xor_b32(__float_as_int(v), S));
+}
+
+template <>
+__device__ __forceinline__ double lane_xor<double>(double v, int S) {
+    const int lo = lane_xor_b32(__double2loint(v), S);
+    const int hi = lane_xor_b32(__double2hiint(v), S);
+    return __hiloint2double(hi, lo);
+}
 
 template <class T, int LOG2L>
 __device__ __forceinline__ void dif_regs(cplx<T> (&z)[line_regs<LOG2L>()], int e_lane,
@@ -60,8 +102,8 @@ __device__ __forceinline__ void dif_regs(cplx<T> (&z)[line_regs<LOG2L>()], int e
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 cplx<T> p;
-                p.re = __shfl_xor(z[r].re, S);
-                p.im = __shfl_xor(z[r].im, S);
+                p.re = lane_xor<T>(z[r].re, S);
+                p.im = lane_xor<T>(z[r].im, S);
                 const cplx<T> sum{z[r].re + p.re, z[r].im + p.im};
                 const cplx<T> dif = cmul(cplx<T>{p.re - z[r].re, p.im - z[r].im}, w);
                 z[r] = upper ? dif : sum;
@@ -97,8 +139,8 @@ __device__ __forceinline__ void dit_regs(cplx<T> (&z)[line_regs<LOG2L>()], int e
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 cplx<T> p;
-                p.re = __shfl_xor(z[r].re, S);
-                p.im = __shfl_xor(z[r].im, S);
+                p.re = lane_xor<T>(z[r].re, S);
+                p.im = lane_xor<T>(z[r].im, S);
                 const cplx<T> t = cmul_conj(upper ? z[r] : p, w);
                 const cplx<T> a = upper ? p : z[r];
                 z[r] = upper ? cplx<T>{a.re - t.re, a.im - t.im}

@@ -615,6 +615,86 @@ __global__ __launch_bounds__(64) void cell_moments3(
     }
 }
 
+// 2-D moments (no probes): lane l accumulates, over the points l, l + 64,
+// ... of the cell (sorted order), all 49 moments t0^q0 t1^q1 (q <= 6) and the
+// 16 response moments y t0^q0 t1^q1 (q <= 3) in registers; the 64 lanes are
+// then summed in lane order through LDS.  Cells of the 2-D workloads hold
+// hundreds to thousands of points, so every lane stays busy.
+template <class Tin>
+__global__ __launch_bounds__(64) void cell_moments2(
+    const typename PayloadOf<Tin>::type* __restrict__ pay,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, GridDev g,
+    double* __restrict__ Mw, double* __restrict__ Mr, double* __restrict__ Myy) {
+    __shared__ double red[64][17];
+    const int cell = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t s0 = cstart[cell];
+    const uint32_t s1 = cend[cell];
+    double acc[7][7], accy[4][4];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+#pragma unroll
+        for (int j = 0; j < 7; ++j) acc[i][j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) accy[i][j] = 0.0;
+    double accyy = 0.0;
+    for (uint32_t i = s0 + lane; i < s1; i += 64) {
+        const auto p = pay[i];
+        double t[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            int base;
+            if (!locate((double)get_slot(p, k), g.g0[k], g.h[k], g.m[k], base, t[k])) t[k] = 0.0;
+        }
+        const double yv = (double)get_slot(p, 2);
+        double av[7], bv[7];
+        av[0] = 1.0;
+        bv[0] = 1.0;
+#pragma unroll
+        for (int q = 1; q < 7; ++q) {
+            av[q] = av[q - 1] * t[0];
+            bv[q] = bv[q - 1] * t[1];
+        }
+#pragma unroll
+        for (int q0 = 0; q0 < 7; ++q0)
+#pragma unroll
+            for (int q1 = 0; q1 < 7; ++q1) acc[q0][q1] = fma(av[q0], bv[q1], acc[q0][q1]);
+#pragma unroll
+        for (int q0 = 0; q0 < 4; ++q0) {
+            const double ay = av[q0] * yv;
+#pragma unroll
+            for (int q1 = 0; q1 < 4; ++q1) accy[q0][q1] = fma(ay, bv[q1], accy[q0][q1]);
+        }
+        accyy = fma(yv, yv, accyy);
+    }
+    // 66 values per lane (49 + 16 + 1), summed over the 64 lanes in lane order,
+    // in chunks of 17 through LDS
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+#pragma unroll
+        for (int j = 0; j < 17; ++j) {
+            const int v = ch * 17 + j;
+            double x = 0.0;
+            if (v < 49) x = acc[v / 7][v % 7];
+            else if (v < 65) x = accy[(v - 49) / 4][(v - 49) % 4];
+            else if (v == 65) x = accyy;
+            red[lane][j] = x;
+        }
+        __syncthreads();
+        if (lane < 17) {
+            const int v = ch * 17 + lane;
+            double sum = 0.0;
+            for (int l = 0; l < 64; ++l) sum += red[l][lane];
+            if (v < 49) Mw[(size_t)cell * 49 + v] = sum;                  // q0*7 + q1
+            else if (v < 65) Mr[(size_t)cell * 16 + (v - 49)] = sum;      // q0*4 + q1
+            else if (v == 65) Myy[cell] = sum;
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // 4. Separable assembly.
 // ---------------------------------------------------------------------------
@@ -781,7 +861,7 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
     int key_bits = 1;
     while ((int64_t(1) << key_bits) < ncells) ++key_bits;
     const int npass = (key_bits + 9) / 10;
-    int dbits[4], dshift[4];
+    int dbits[8], dshift[8];
     {
         int sh = 0;
         for (int p = 0; p < npass; ++p) {
@@ -884,6 +964,8 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         if (d == 1)
             cell_moments<1, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
                                                                  (int)ncells, Mw, Mr, Myy);
+        else if (d == 2 && nprobe == 0)
+            cell_moments2<Tin><<<(unsigned)ncells, 64, 0, s>>>(pin, cstart, cend, g, Mw, Mr, Myy);
         else if (d == 2)
             cell_moments<2, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
                                                                  (int)ncells, Mw, Mr, Myy);
