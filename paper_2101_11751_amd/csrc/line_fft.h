@@ -98,14 +98,20 @@ __device__ __forceinline__ void dif_regs(cplx<T> (&z)[line_regs<LOG2L>()], int e
             }
         } else {
             const bool upper = (e_lane & S) != 0;
-            const cplx<T> w = tws[(e_lane & (S - 1)) * (L / (2 * S))];
+            // spans 1 and 2 use the twiddles 1 and -i only: no multiplication
+            const cplx<T> w = S > 2 ? tws[(e_lane & (S - 1)) * (L / (2 * S))] : cplx<T>{T(1), T(0)};
+            const bool odd = (e_lane & 1) != 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 cplx<T> p;
                 p.re = lane_xor<T>(z[r].re, S);
                 p.im = lane_xor<T>(z[r].im, S);
                 const cplx<T> sum{z[r].re + p.re, z[r].im + p.im};
-                const cplx<T> dif = cmul(cplx<T>{p.re - z[r].re, p.im - z[r].im}, w);
+                const cplx<T> d{p.re - z[r].re, p.im - z[r].im};
+                cplx<T> dif;
+                if (S == 1) dif = d;
+                else if (S == 2) dif = odd ? cplx<T>{d.im, -d.re} : d;
+                else dif = cmul(d, w);
                 z[r] = upper ? dif : sum;
             }
         }
@@ -135,13 +141,18 @@ __device__ __forceinline__ void dit_regs(cplx<T> (&z)[line_regs<LOG2L>()], int e
             }
         } else {
             const bool upper = (e_lane & S) != 0;
-            const cplx<T> w = tws[(e_lane & (S - 1)) * (L / (2 * S))];
+            const cplx<T> w = S > 2 ? tws[(e_lane & (S - 1)) * (L / (2 * S))] : cplx<T>{T(1), T(0)};
+            const bool odd = (e_lane & 1) != 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 cplx<T> p;
                 p.re = lane_xor<T>(z[r].re, S);
                 p.im = lane_xor<T>(z[r].im, S);
-                const cplx<T> t = cmul_conj(upper ? z[r] : p, w);
+                const cplx<T> x = upper ? z[r] : p;
+                cplx<T> t;   // x * conj(w): w = 1 (span 1), 1 or -i (span 2)
+                if (S == 1) t = x;
+                else if (S == 2) t = odd ? cplx<T>{-x.im, x.re} : x;
+                else t = cmul_conj(x, w);
                 const cplx<T> a = upper ? p : z[r];
                 z[r] = upper ? cplx<T>{a.re - t.re, a.im - t.im}
                              : cplx<T>{a.re + t.re, a.im + t.im};
