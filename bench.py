@@ -14,7 +14,9 @@ batch_mll_grad   = many-problem workload: one persistent launch vs a loop
 precompute_*     = n / precompute time
 cg_mvms_per_s    = CG iterations (one operator B each) per second of solve
 roofline         = banded W^T W product (the dominant kernel of the solve),
-                   algorithmic bytes / average launch duration (HIP events)
+                   algorithmic bytes / average launch duration (HIP events);
+                   the algorithmic bytes are the nonzero 64-row blocks of the
+                   stored W^T W (the kernel reads only these) plus x and u
 cpu_baseline     = the FP64 CPU oracle on a bounded sample, scaled to the
                    same per-step work (see "sample")
 """
@@ -31,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc runs (FETCH_SIZE x 1.9995, WRITE_SIZE x 1.0, calibrated on a
 # 256 MiB copy) recorded in profiles/radar3d_hbm_traffic_pmc.md.  Set to None
 # whenever spmv_tiled_kernel changes until the counters are taken again.
-SPMV_TRAFFIC_BYTES = 429.7e6
+SPMV_TRAFFIC_BYTES = None
 
 
 def _parse():
@@ -290,8 +292,9 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     t_spmv = e0.elapsed_time(e1) / args.mvm_reps / 1e3
-    nb = 7 ** h.d
-    alg_bytes = 4 * M * nb + 8 * 2 * M   # FP32 entries, FP64 x read + u written
+    # FP32 entries of the nonzero blocks, FP64 x read + u written
+    alg_bytes = 4 * h.wtw_blocks_nonzero * h.wtw_block_entries + 8 * 2 * M
+    log(f"W^T W blocks: {h.wtw_blocks_nonzero} of {h.wtw_blocks} nonzero")
     achieved = alg_bytes / t_spmv / 1e9
     log(f"spmv avg {t_spmv*1e6:.1f} us, {achieved:.0f} GB/s algorithmic")
 

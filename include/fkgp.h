@@ -111,6 +111,13 @@ typedef struct {
     int64_t nnz_wtw;         /* stored stencil-diagonal entries (m * 7^d) */
     int64_t halo;            /* zero padding on each side of a vector passed
                                 to fkgp_wtw_matvec: 3 * sum_k stride_k */
+    int64_t wtw_blocks;      /* blocks of the stored W^T W: a 64-row chunk of
+                                rows times an offset slab (the 49 offsets
+                                sharing o_0 for d = 3; all 7^d for d <= 2) */
+    int64_t wtw_blocks_nonzero; /* blocks holding a nonzero entry; the banded
+                                product reads only these (points that do not
+                                fill the grid's box leave whole blocks zero) */
+    int64_t wtw_block_entries;  /* stored entries per block (64 * 49 or 64 * 7) */
 } fkgp_handle_desc;
 
 fkgp_status fkgp_describe(const fkgp_handle* h, fkgp_handle_desc* desc);

@@ -56,7 +56,9 @@ class _Desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m_total", ctypes.c_int64), ("d", ctypes.c_int),
                 ("stats_dtype", ctypes.c_int), ("n_probes", ctypes.c_int),
                 ("yty", ctypes.c_double), ("bytes_wtw", ctypes.c_int64),
-                ("nnz_wtw", ctypes.c_int64), ("halo", ctypes.c_int64)]
+                ("nnz_wtw", ctypes.c_int64), ("halo", ctypes.c_int64),
+                ("wtw_blocks", ctypes.c_int64), ("wtw_blocks_nonzero", ctypes.c_int64),
+                ("wtw_block_entries", ctypes.c_int64)]
 
 
 OP_F64, OP_STATS = 0, 1
@@ -192,6 +194,9 @@ class Handle:
         self.bytes_wtw = d.bytes_wtw
         self.nnz_wtw = d.nnz_wtw
         self.halo = d.halo
+        self.wtw_blocks = d.wtw_blocks
+        self.wtw_blocks_nonzero = d.wtw_blocks_nonzero
+        self.wtw_block_entries = d.wtw_block_entries
 
     @property
     def ptr(self):

@@ -29,8 +29,11 @@ struct fkgp_handle {
     void* A = nullptr;          // [NB][M] stats dtype
     double* wty = nullptr;      // [M]
     double* sketches = nullptr; // [nprobe][M]
-    double* yty_dev = nullptr;  // [2]: y^T y, then the out-of-grid flag (bits)
+    double* yty_dev = nullptr;  // [3]: y^T y, the out-of-grid flag, the
+                                // number of nonzero blocks of W^T W (bits)
+    uint32_t* bmask = nullptr;  // [mask_words(M)] block occupancy of W^T W
     double yty = 0.0;
+    int64_t nzblocks = 0;
     void* block = nullptr;      // one pool allocation holding the arrays above
 };
 
@@ -356,7 +359,7 @@ fkgp_status apply_B_padded(const OpCtx& c, const void* xpad, void* u, void* v, c
                            hipStream_t st, double* dotp = nullptr, int* nparts = nullptr) {
     const fkgp_handle* h = c.h;
     fkgp_status r =
-        spmv_dia_any(h->g, h->dt, c.op, h->A, xpad, u, 1, c.halo, skip, st, dotp, nparts);
+        spmv_dia_any(h->g, h->dt, c.op, h->A, h->bmask, xpad, u, 1, c.halo, skip, st, dotp, nparts);
     if (r != FKGP_OK) return r;
     const void* xin = static_cast<const unsigned char*>(xpad) + c.halo * dsize(c.op);
     return kg_apply_skip(h->g, c.sp, c.op, u, v, 1, c.so, xin, c.s2, skip, st);
@@ -516,7 +519,7 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
             // u = W^T W r_hat; the product's last workgroup finishes u^T r_hat
             // (rho, beta) when the tiled kernel runs
             int np = 0;
-            rs = spmv_dia_any(h->g, h->dt, c.op, h->A, b.rpad, b.u, 1, c.halo, &b.st->done, st,
+            rs = spmv_dia_any(h->g, h->dt, c.op, h->A, h->bmask, b.rpad, b.u, 1, c.halo, &b.st->done, st,
                               b.partials, &np, &rho_lb);
             if (rs != FKGP_OK) return rs;
             if (np == 0) {
@@ -823,19 +826,23 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
         const size_t bA = up(dsize(h->dt) * (size_t)dia_elems(M, h->NB));
         const size_t bW = up(sizeof(double) * M);
         const size_t bS = up(sizeof(double) * M * h->nprobe);
-        if ((e = hipMallocAsync(&h->block, bA + bW + bS + 256, s)) != hipSuccess)
+        const size_t bK = up(sizeof(uint32_t) * (size_t)mask_words(M));
+        if ((e = hipMallocAsync(&h->block, bA + bW + bS + bK + 256, s)) != hipSuccess)
             return fail(hip_fail(e, "hipMallocAsync(handle)"));
         unsigned char* hb = static_cast<unsigned char*>(h->block);
         h->A = hb;
         h->wty = reinterpret_cast<double*>(hb + bA);
         h->sketches = h->nprobe > 0 ? reinterpret_cast<double*>(hb + bA + bW) : nullptr;
-        h->yty_dev = reinterpret_cast<double*>(hb + bA + bW + bS);
+        h->bmask = reinterpret_cast<uint32_t*>(hb + bA + bW + bS);
+        h->yty_dev = reinterpret_cast<double*>(hb + bA + bW + bS + bK);
         unsigned long long* bad = reinterpret_cast<unsigned long long*>(h->yty_dev + 1);
         (void)hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), s);
-        StatsOut so{h->A, h->wty, h->sketches, h->yty_dev};
+        (void)hipMemsetAsync(h->bmask, 0, bK, s);
+        StatsOut so{h->A, h->wty, h->sketches, h->yty_dev, h->bmask,
+                    reinterpret_cast<unsigned long long*>(h->yty_dev + 2)};
         st = run_precompute(g, x, y, n, in, h->dt, h->nprobe, h->seed, so, bad, s);
         unsigned long long hbad = ~0ull;
-        double back[2] = {0.0, 0.0};
+        double back[3] = {0.0, 0.0, 0.0};
         if (st == FKGP_OK) {
             if ((e = hipMemcpyAsync(back, h->yty_dev, sizeof(back), hipMemcpyDeviceToHost, s)) !=
                 hipSuccess)
@@ -846,6 +853,9 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
         if (st != FKGP_OK) return fail(st);
         h->yty = back[0];
         std::memcpy(&hbad, &back[1], sizeof(hbad));
+        unsigned long long nzb = 0;
+        std::memcpy(&nzb, &back[2], sizeof(nzb));
+        h->nzblocks = (int64_t)nzb;
         if (hbad != ~0ull) {
             set_error("point " + std::to_string(hbad) + " lies outside the interpolable region");
             return fail(FKGP_EOUTOFGRID);
@@ -869,6 +879,10 @@ fkgp_status fkgp_describe(const fkgp_handle* h, fkgp_handle_desc* desc) {
     desc->nnz_wtw = h->M * h->NB;
     desc->bytes_wtw = dia_elems(h->M, h->NB) * (int64_t)dsize(h->dt);
     desc->halo = dia_halo(h->g);
+    const int slabs = h->g.d == 3 ? 7 : 1;
+    desc->wtw_blocks = mask_words(h->M) * (kRowTile / kWaveRows) * slabs;
+    desc->wtw_blocks_nonzero = h->nzblocks;
+    desc->wtw_block_entries = (int64_t)kWaveRows * mask_slab_width(h->g.d);
     return FKGP_OK;
 }
 
@@ -1039,7 +1053,7 @@ fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int
             set_error("vector dtype must be the stats dtype or FKGP_F64");
             return FKGP_EINVAL;
         }
-        return spmv_dia_any(h->g, h->dt, xdt, h->A, xpad, u, k, dia_halo(h->g), nullptr,
+        return spmv_dia_any(h->g, h->dt, xdt, h->A, h->bmask, xpad, u, k, dia_halo(h->g), nullptr,
                             static_cast<hipStream_t>(stream));
     });
 }
@@ -1398,7 +1412,7 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
             probe_fin_ap<<<N, kRedBlock, 0, st>>>(ps, partials, nbv, c.s2, n, alphas);
             probe_upd_r<<<ge, 256, 0, st>>>(ps, ux, sp, rh, ap, rpad, M, ldx, c.halo);
             FKGP_HIP(hipGetLastError());
-            rs = spmv_dia_any(h->g, h->dt, FKGP_F64, h->A, rpad, ur, N, c.halo, nullptr, st);
+            rs = spmv_dia_any(h->g, h->dt, FKGP_F64, h->A, h->bmask, rpad, ur, N, c.halo, nullptr, st);
             if (rs != FKGP_OK) return rs;
             rs = kg_apply(h->g, c.sp64, FKGP_F64, ur, vr, N, c.so, rh, c.s2, nullptr, st);
             if (rs != FKGP_OK) return rs;

@@ -35,6 +35,19 @@ inline int64_t dia_elems(int64_t M, int NB) {
     return ((M + kRowTile - 1) / kRowTile) * NB * kRowTile;
 }
 
+// Block occupancy of the stored W^T W.  A block is one 64-row wavefront
+// chunk w of a row tile times one offset slab a: the 49 offsets sharing o_0
+// for d = 3 (a = o / 49), all 7^d offsets for d <= 2 (a = 0).  Word `tile`
+// of the mask has bit w * kMaskSlabs + a set iff the block holds a nonzero
+// stored entry; the banded product skips the loads of the other blocks (the
+// points need not fill the grid's bounding box: a cylinder of points leaves
+// whole wavefront chunks of W^T W zero).
+constexpr int kWaveRows = 64;
+constexpr int kMaskSlabs = 7;
+inline int64_t mask_words(int64_t M) { return (M + kRowTile - 1) / kRowTile; }
+// entries per row of one slab: 49 for d >= 2, 7 for d = 1 (slab = o / 49)
+__host__ __device__ inline int mask_slab_width(int d) { return d == 1 ? 7 : 49; }
+
 // ---- CG scalar state (capi.hip loops, fused epilogues in ops.hip) ----------
 struct CgState {
     double rho;     // ||r_k||^2 in n-space (= u^T r_hat)
@@ -165,6 +178,8 @@ struct StatsOut {
     double* wty;        // [M]
     double* sketches;   // [nprobe][M] or null
     double* yty_dev;    // scalar
+    uint32_t* bmask;    // [mask_words(M)] block occupancy, zeroed by the caller
+    unsigned long long* nzblocks;   // number of set mask bits (written last)
 };
 
 fkgp_status run_precompute(const GridDev& g, const void* const* x, const void* y,
@@ -236,8 +251,11 @@ int64_t kg_last_pass_blocks(const GridDev& g);
 // lb (optional, with dotp): the last workgroup also finishes the dot
 // product (partials = dotp) and applies the CG scalar step lb.op; *nparts
 // is then the number of partials and the reduction is done.
+// bmask (optional): the block occupancy of A; blocks without a set bit are
+// not read (their entries are zero, so the result is the same).
 fkgp_status spmv_dia_any(const GridDev& g, fkgp_dtype dta, fkgp_dtype dtx, const void* A,
-                         const void* xpad, void* u, int k, int64_t halo, const int* skip,
+                         const uint32_t* bmask, const void* xpad, void* u, int k,
+                         int64_t halo, const int* skip,
                          hipStream_t s, double* dotp = nullptr, int* nparts = nullptr,
                          const LastBlockRed* lb = nullptr);
 int64_t dia_halo(const GridDev& g);

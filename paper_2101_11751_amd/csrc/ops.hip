@@ -297,10 +297,18 @@ __global__ __launch_bounds__(256) void spmv_dia_kernel(const TA* __restrict__ A,
                                                        const T* __restrict__ xpad,
                                                        T* __restrict__ u, DiaGeom dg,
                                                        int64_t halo, int64_t ldx,
-                                                       const int* __restrict__ skip) {
+                                                       const int* __restrict__ skip,
+                                                       const uint32_t* __restrict__ bmask) {
     if (skip && *skip) return;
+    // one block = one row tile of kRowTile rows
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= dg.M) return;
+    // slab bits of this wavefront (slab = the outermost offset level)
+    const uint32_t wb =
+        bmask ? __builtin_amdgcn_readfirstlane((bmask[blockIdx.x] >>
+                                                (kMaskSlabs * (threadIdx.x / kWaveRows))) &
+                                               ((1u << kMaskSlabs) - 1u))
+              : ~0u;
     T acc[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) acc[r] = T(0);
@@ -308,6 +316,10 @@ __global__ __launch_bounds__(256) void spmv_dia_kernel(const TA* __restrict__ A,
     const int NB = dg.ext[0] * dg.ext[1] * dg.ext[2];
     int oi = 0;
     for (int a = 0; a < dg.ext[0]; ++a) {
+        if (!((wb >> a) & 1u)) {   // zero slab
+            oi += dg.ext[1] * dg.ext[2];
+            continue;
+        }
         const int64_t oa = (dg.ext[0] == 7 ? (a - 3) : 0) * dg.stride[0];
         for (int b = 0; b < dg.ext[1]; ++b) {
             const int64_t ob = oa + (dg.ext[1] == 7 ? (b - 3) : 0) * dg.stride[1];
@@ -348,8 +360,9 @@ struct TileGeom {
 // (one 7 x 7 slab of offsets) are in flight per step.
 template <class TA, class T, int D>
 __device__ __forceinline__ T tile_row(const TA* __restrict__ Ab, const T* __restrict__ win,
-                                      const TileGeom& tg, int t) {
+                                      const TileGeom& tg, int t, uint32_t wb) {
     T acc = T(0);
+    if (wb == 0u) return acc;   // every block of this wavefront is zero
     if constexpr (D == 1) {
         TA av[7];
 #pragma unroll
@@ -360,6 +373,7 @@ __device__ __forceinline__ T tile_row(const TA* __restrict__ Ab, const T* __rest
         constexpr int NA = D == 3 ? 7 : 1;
 #pragma unroll 1
         for (int a = 0; a < NA; ++a) {
+            if (!((wb >> a) & 1u)) continue;   // zero slab: skip its loads
             TA av[49];
             const TA* Aa = Ab + a * 49 * kTileRows;
 #pragma unroll
@@ -383,6 +397,7 @@ __global__ __launch_bounds__(256) void spmv_tiled_kernel(const TA* __restrict__ 
                                                          T* __restrict__ u, TileGeom tg,
                                                          double* __restrict__ dotp,
                                                          const int* __restrict__ skip,
+                                                         const uint32_t* __restrict__ bmask,
                                                          LastBlockRed lb) {
     if (skip && *skip) return;
     extern __shared__ unsigned char lds_raw[];
@@ -391,22 +406,30 @@ __global__ __launch_bounds__(256) void spmv_tiled_kernel(const TA* __restrict__ 
     constexpr int kNB = D == 1 ? 7 : (D == 2 ? 49 : 343);
     const int64_t j0 = (int64_t)blockIdx.x * kTileRows;
     const int64_t ldx = tg.M + 2 * tg.halo;
-    // stage the windows
-    for (int w = 0; w < NW; ++w) {
-        const int64_t start = tg.halo + j0 + (D >= 2 ? (int64_t)(w - 3) * tg.S0 : 0) - tg.margin;
-        for (int i = threadIdx.x; i < tg.WL; i += 256) {
-            const int64_t idx = start + i;
-            win[w * tg.WL + i] = idx < ldx ? xpad[idx] : T(0);
+    const uint32_t mk = bmask ? bmask[blockIdx.x] : ~0u;
+    // stage the windows (not needed when the whole tile is zero)
+    if (mk != 0u) {
+        for (int w = 0; w < NW; ++w) {
+            const int64_t start =
+                tg.halo + j0 + (D >= 2 ? (int64_t)(w - 3) * tg.S0 : 0) - tg.margin;
+            for (int i = threadIdx.x; i < tg.WL; i += 256) {
+                const int64_t idx = start + i;
+                win[w * tg.WL + i] = idx < ldx ? xpad[idx] : T(0);
+            }
         }
     }
     __syncthreads();
     const int t = threadIdx.x;
-    const T acc = tile_row<TA, T, D>(A + (int64_t)blockIdx.x * kNB * kTileRows + t, win, tg, t);
+    // this wavefront's slab bits (uniform across the wavefront)
+    const uint32_t wb = __builtin_amdgcn_readfirstlane((mk >> (kMaskSlabs * (t / kWaveRows))) &
+                                                       ((1u << kMaskSlabs) - 1u));
+    const T acc =
+        tile_row<TA, T, D>(A + (int64_t)blockIdx.x * kNB * kTileRows + t, win, tg, t, wb);
     double part = 0.0;
     const int xc = (D >= 2 ? 3 * tg.WL : 0) + tg.margin + t;
     if (j0 + t < tg.M) {
         u[j0 + t] = acc;
-        part = (double)acc * (double)win[xc];
+        if (wb) part = (double)acc * (double)win[xc];
     }
     if (dotp) {
         __shared__ double red[256];
@@ -651,9 +674,10 @@ static bool tile_geom(const GridDev& g, size_t es, TileGeom& tg, size_t& lds) {
 }
 
 template <class TA, class T>
-static fkgp_status spmv_t(const GridDev& g, const TA* A, const T* xpad, T* u, int k,
-                          int64_t halo, const int* skip, hipStream_t s, double* dotp = nullptr,
-                          int* nparts = nullptr, const LastBlockRed* lb = nullptr) {
+static fkgp_status spmv_t(const GridDev& g, const TA* A, const uint32_t* bmask, const T* xpad,
+                          T* u, int k, int64_t halo, const int* skip, hipStream_t s,
+                          double* dotp = nullptr, int* nparts = nullptr,
+                          const LastBlockRed* lb = nullptr) {
     TileGeom tg;
     size_t lds;
     if (k == 1 && tile_geom(g, sizeof(T), tg, lds)) {
@@ -665,19 +689,22 @@ static fkgp_status spmv_t(const GridDev& g, const TA* A, const T* xpad, T* u, in
                 FKGP_HIP(hipFuncSetAttribute(
                     reinterpret_cast<const void*>(&spmv_tiled_kernel<TA, T, 1>),
                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            spmv_tiled_kernel<TA, T, 1><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip, lbv);
+            spmv_tiled_kernel<TA, T, 1><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip, bmask,
+                                                                   lbv);
         } else if (g.d == 2) {
             if (lds > 64 * 1024)
                 FKGP_HIP(hipFuncSetAttribute(
                     reinterpret_cast<const void*>(&spmv_tiled_kernel<TA, T, 2>),
                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            spmv_tiled_kernel<TA, T, 2><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip, lbv);
+            spmv_tiled_kernel<TA, T, 2><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip, bmask,
+                                                                   lbv);
         } else {
             if (lds > 64 * 1024)
                 FKGP_HIP(hipFuncSetAttribute(
                     reinterpret_cast<const void*>(&spmv_tiled_kernel<TA, T, 3>),
                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            spmv_tiled_kernel<TA, T, 3><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip, lbv);
+            spmv_tiled_kernel<TA, T, 3><<<grid, 256, lds, s>>>(A, xpad, u, tg, dotp, skip, bmask,
+                                                                   lbv);
         }
         if (nparts) *nparts = dotp ? (int)grid : 0;
         FKGP_HIP(hipGetLastError());
@@ -708,16 +735,16 @@ static fkgp_status spmv_t(const GridDev& g, const TA* A, const T* xpad, T* u, in
         const T* xr = xpad + (int64_t)r0 * ldx;
         T* ur = u + (int64_t)r0 * dg.M;
         if (left >= 8) {
-            spmv_dia_kernel<TA, T, 8><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
+            spmv_dia_kernel<TA, T, 8><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip, bmask);
             r0 += 8;
         } else if (left >= 4) {
-            spmv_dia_kernel<TA, T, 4><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
+            spmv_dia_kernel<TA, T, 4><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip, bmask);
             r0 += 4;
         } else if (left >= 2) {
-            spmv_dia_kernel<TA, T, 2><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
+            spmv_dia_kernel<TA, T, 2><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip, bmask);
             r0 += 2;
         } else {
-            spmv_dia_kernel<TA, T, 1><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
+            spmv_dia_kernel<TA, T, 1><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip, bmask);
             r0 += 1;
         }
     }
@@ -733,10 +760,10 @@ fkgp_status spmv_dia(const GridDev& g, fkgp_dtype dt, const void* A, const void*
 fkgp_status spmv_dia_skip(const GridDev& g, fkgp_dtype dt, const void* A, const void* xpad,
                           void* u, int k, int64_t halo, const int* skip, hipStream_t s) {
     if (dt == FKGP_F32)
-        return spmv_t<float, float>(g, static_cast<const float*>(A),
+        return spmv_t<float, float>(g, static_cast<const float*>(A), nullptr,
                                     static_cast<const float*>(xpad), static_cast<float*>(u), k,
                                     halo, skip, s);
-    return spmv_t<double, double>(g, static_cast<const double*>(A),
+    return spmv_t<double, double>(g, static_cast<const double*>(A), nullptr,
                                   static_cast<const double*>(xpad), static_cast<double*>(u), k,
                                   halo, skip, s);
 }
@@ -744,18 +771,19 @@ fkgp_status spmv_dia_skip(const GridDev& g, fkgp_dtype dt, const void* A, const 
 // Product with matrix dtype dta and vector dtype dtx (FP32 matrix entries are
 // upcast exactly when the vectors are FP64).
 fkgp_status spmv_dia_any(const GridDev& g, fkgp_dtype dta, fkgp_dtype dtx, const void* A,
-                         const void* xpad, void* u, int k, int64_t halo, const int* skip,
-                         hipStream_t s, double* dotp, int* nparts, const LastBlockRed* lb) {
+                         const uint32_t* bmask, const void* xpad, void* u, int k,
+                         int64_t halo, const int* skip, hipStream_t s, double* dotp,
+                         int* nparts, const LastBlockRed* lb) {
     if (dta == FKGP_F32 && dtx == FKGP_F32)
-        return spmv_t<float, float>(g, static_cast<const float*>(A),
+        return spmv_t<float, float>(g, static_cast<const float*>(A), bmask,
                                     static_cast<const float*>(xpad), static_cast<float*>(u), k,
                                     halo, skip, s, dotp, nparts, lb);
     if (dta == FKGP_F64 && dtx == FKGP_F64)
-        return spmv_t<double, double>(g, static_cast<const double*>(A),
+        return spmv_t<double, double>(g, static_cast<const double*>(A), bmask,
                                       static_cast<const double*>(xpad), static_cast<double*>(u), k,
                                       halo, skip, s, dotp, nparts, lb);
     if (dta == FKGP_F32 && dtx == FKGP_F64)
-        return spmv_t<float, double>(g, static_cast<const float*>(A),
+        return spmv_t<float, double>(g, static_cast<const float*>(A), bmask,
                                      static_cast<const double*>(xpad), static_cast<double*>(u), k,
                                      halo, skip, s, dotp, nparts, lb);
     set_error("unsupported matrix/vector dtype combination");
@@ -765,7 +793,8 @@ fkgp_status spmv_dia_any(const GridDev& g, fkgp_dtype dta, fkgp_dtype dtx, const
 // FP64 product with an FP32-stored matrix (entries upcast exactly).
 fkgp_status spmv_dia_f32a_f64x(const GridDev& g, const void* A, const double* xpad, double* u,
                                int k, int64_t halo, hipStream_t s) {
-    return spmv_t<float, double>(g, static_cast<const float*>(A), xpad, u, k, halo, nullptr, s);
+    return spmv_t<float, double>(g, static_cast<const float*>(A), nullptr, xpad, u, k, halo,
+                                 nullptr, s);
 }
 
 fkgp_status interpolate_points(const GridDev& g, const double* mu, const void* const* xq,

@@ -787,21 +787,49 @@ __global__ void assemble_vec_stage(const double* __restrict__ in, double* __rest
 // rows past M in the last tile are written as zeros.
 template <class T>
 __global__ void transpose_to_dia(const double* __restrict__ in, T* __restrict__ out, int64_t M,
-                                 int NB) {
+                                 int NB, uint32_t* __restrict__ bmask) {
     __shared__ double tile[32][33];
+    __shared__ uint32_t occ;
     const int64_t j0 = (int64_t)blockIdx.x * 32;
     const int o0 = blockIdx.y * 32;
+    if (threadIdx.x == 0 && threadIdx.y == 0) occ = 0u;
     for (int r = threadIdx.y; r < 32; r += 8) {
         int64_t j = j0 + r;
         int o = o0 + threadIdx.x;
         tile[r][threadIdx.x] = (j < M && o < NB) ? in[j * NB + o] : 0.0;
     }
     __syncthreads();
+    // the block's 32 rows lie in one wavefront chunk of one row tile
+    const int w = (int)((j0 % kRowTile) / kWaveRows);
+    uint32_t bits = 0u;
     for (int r = threadIdx.y; r < 32; r += 8) {
         int o = o0 + r;
         int64_t j = j0 + threadIdx.x;
-        if (o < NB) out[dia_index(j, o, NB)] = (T)tile[threadIdx.x][r];
+        if (o < NB) {
+            const T v = (T)tile[threadIdx.x][r];
+            out[dia_index(j, o, NB)] = v;
+            if (v != T(0)) bits |= 1u << (w * kMaskSlabs + o / 49);
+        }
     }
+    if (bits) atomicOr(&occ, bits);   // integer OR: order-independent
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0 && occ) atomicOr(&bmask[j0 / kRowTile], occ);
+}
+
+// Number of set bits of the block-occupancy mask (one workgroup).
+__global__ __launch_bounds__(256) void count_mask_bits(const uint32_t* __restrict__ bmask,
+                                                       int64_t nwords,
+                                                       unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long sh[256];
+    unsigned long long c = 0;
+    for (int64_t i = threadIdx.x; i < nwords; i += 256) c += (unsigned long long)__popc(bmask[i]);
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
 }
 
 // Deterministic sum of the per-cell sums of y^2 (single block, fixed tree).
@@ -1010,9 +1038,13 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         const int64_t Mpad = (M + kRowTile - 1) / kRowTile * kRowTile;
         dim3 tb(32, 8), tg((unsigned)(Mpad / 32), (unsigned)((NB + 31) / 32));
         if (stats == FKGP_F32)
-            transpose_to_dia<float><<<tg, tb, 0, s>>>(src, static_cast<float*>(out.wtw), M, NB);
+            transpose_to_dia<float><<<tg, tb, 0, s>>>(src, static_cast<float*>(out.wtw), M, NB,
+                                                      out.bmask);
         else
-            transpose_to_dia<double><<<tg, tb, 0, s>>>(src, static_cast<double*>(out.wtw), M, NB);
+            transpose_to_dia<double><<<tg, tb, 0, s>>>(src, static_cast<double*>(out.wtw), M, NB,
+                                                       out.bmask);
+        FKGP_HIP(hipGetLastError());
+        count_mask_bits<<<1, 256, 0, s>>>(out.bmask, mask_words(M), out.nzblocks);
         FKGP_HIP(hipGetLastError());
     }
     // --- W^T y and sketches: stages over k = d-1 .. 0 ---

@@ -250,3 +250,73 @@ def test_wtw_matvec_tiled_parity(d, m, xdt):
     U = P.wtw_matvec(h, torch.from_numpy(V).cuda(), dt).cpu().numpy()
     for r in range(3):
         check(U[r], V[r])
+
+
+def sparse_case(d, n, seed):
+    """Points filling only part of the grid's box (an interval, a disk, a
+    cylinder), so that whole 64-row blocks of W^T W are zero.  The region is
+    a union of whole grid cells, each filled uniformly, so no node is touched
+    only by a stray point in a nearly empty cell."""
+    rng = np.random.default_rng(seed)
+    m = {1: [1000], 2: [60, 50], 3: [30, 30, 12]}[d]
+    grid = oracle.make_grid(m, lo=0.0, hi=1.0)
+    nc = [mk - 3 for mk in m]                    # cells covering [0, 1]
+    idx = np.stack(np.meshgrid(*[np.arange(c) for c in nc], indexing="ij"), -1).reshape(-1, d)
+    ctr = (idx + 0.5) / np.asarray(nc)
+    if d == 1:
+        keep = ctr[:, 0] < 0.4
+    else:
+        keep = (ctr[:, 0] - 0.5) ** 2 + (ctr[:, 1] - 0.5) ** 2 < 0.35 ** 2
+    cells = idx[keep]
+    pick = cells[rng.integers(0, len(cells), n)]
+    X = ((pick + rng.uniform(0, 1, (n, d))) / np.asarray(nc)).T.astype(np.float32)
+    y = (np.sin(5 * X[0].astype(np.float64)) + 0.3 * rng.standard_normal(n)).astype(np.float32)
+    return grid, X, y
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_zero_block_skipping(d):
+    """The block-occupancy mask matches the stored W^T W exactly (counted on
+    the host from the exported entries); the products that skip the zero
+    blocks match the oracle's banded product row by row (exact zeros where
+    the row is zero), and so does the solve."""
+    _need_gpu()
+    grid, X, y = sparse_case(d, 40000, 31 + d)
+    xs, yt = to_dev(X, y)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float32)
+    wtw, _, _ = P.export_stats(h)
+    A = wtw.cpu().numpy()
+    M, NB = A.shape
+    slabs = 7 if d == 3 else 1
+    nt = (M + 255) // 256
+    Ap = np.zeros((nt * 256, NB), np.float32)
+    Ap[:M] = A
+    occ = (Ap.reshape(nt, 4, 64, slabs, NB // slabs) != 0).any(axis=(2, 4))
+    assert h.wtw_blocks == nt * 4 * slabs
+    assert h.wtw_block_entries == 64 * (NB // slabs)
+    assert h.wtw_blocks_nonzero == int(occ.sum())
+    assert 0 < h.wtw_blocks_nonzero < h.wtw_blocks
+    wtw_o, wty_o, yty_o = oracle.precompute(grid, X, y)
+    assert rel(A, wtw_o) <= 1e-6
+    w32 = wtw_o.astype(np.float32).astype(np.float64)
+    nterm = 7 ** d
+    rng = np.random.default_rng(8)
+    for dt, eps in ((torch.float64, 2.0 ** -52), (None, 2.0 ** -23)):
+        V = rng.standard_normal((3, h.m_total))
+        for k in (1, 3):   # one vector: tiled kernel; several: multi-vector kernel
+            U = P.wtw_matvec(h, torch.from_numpy(V[:k]).cuda(), dt).cpu().numpy().reshape(k, -1)
+            for r in range(k):
+                vr = V[r] if dt is not None else V[r].astype(np.float32).astype(np.float64)
+                ref = oracle.wtw_matvec(grid, w32, vr)
+                absax = oracle.wtw_matvec(grid, np.abs(w32), np.abs(vr))
+                # one FP32 ulp of |A||x| for the stored entries (rounded from
+                # the GPU's own FP64 moments) on top of the dot-product bound
+                bound = (2 * nterm * eps + 2.0 ** -23) * absax + 1e-300
+                err = np.abs(U[r] - ref)
+                i = int(np.argmax(err / bound))
+                assert err[i] <= bound[i], (dt, k, r, i, err[i], absax[i], U[r][i], ref[i])
+                assert np.all(U[r][absax == 0] == 0)
+    mu_o, _, _ = oracle.solve_mean(grid, HYP[d], wtw_o, wty_o, yty_o, tol=1e-13)
+    mu, info = P.solve(h, HYP[d], tol=1e-7, maxiter=5000)
+    assert info["converged"]
+    assert rel(mu.cpu(), mu_o) <= 1e-5
