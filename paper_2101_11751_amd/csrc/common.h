@@ -21,6 +21,18 @@ struct GridDev {
 
 constexpr int kMaxProbes = 31;
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b to XCD
+// b % 8), each with its own L2.  xcd_block() renumbers the blocks so that
+// every XCD runs one contiguous range of logical blocks: neighbouring blocks
+// that share cache lines (the interleaved lines of a strided pass) then share
+// an L2 instead of fetching the same lines on different dies.
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned xcd_block() {
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned q = nb / kXcds, r = nb % kXcds, x = b % kXcds, k = b / kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // Storage of W^T W: row-tiled stencil-diagonal layout [tile][o][kRowTile],
 // tile = j / kRowTile, so the entries one workgroup of the banded product
 // needs (kRowTile rows x 7^d offsets) are one contiguous block.  Rows past

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kLineBlock) void line_conv_direct(
     const int e_lane = L >= 64 ? lane : (lane & (L - 1));
     const int g_lane = L >= 64 ? 0 : (lane / L);
     const int64_t npairs = (lg.nlines + 1) / 2;
-    const int64_t pair = ((int64_t)blockIdx.x * (kLineBlock / 64) + (tid >> 6)) * G + g_lane;
+    const int64_t pair = ((int64_t)xcd_block() * (kLineBlock / 64) + (tid >> 6)) * G + g_lane;
     const int m = lg.m_line;
     const int S32 = (int)lg.S;
     int64_t base[2] = {0, 0};
@@ -297,18 +297,10 @@ __global__ __launch_bounds__(256) void spmv_dia_kernel(const TA* __restrict__ A,
                                                        const T* __restrict__ xpad,
                                                        T* __restrict__ u, DiaGeom dg,
                                                        int64_t halo, int64_t ldx,
-                                                       const int* __restrict__ skip,
-                                                       const uint32_t* __restrict__ bmask) {
+                                                       const int* __restrict__ skip) {
     if (skip && *skip) return;
-    // one block = one row tile of kRowTile rows
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= dg.M) return;
-    // slab bits of this wavefront (slab = the outermost offset level)
-    const uint32_t wb =
-        bmask ? __builtin_amdgcn_readfirstlane((bmask[blockIdx.x] >>
-                                                (kMaskSlabs * (threadIdx.x / kWaveRows))) &
-                                               ((1u << kMaskSlabs) - 1u))
-              : ~0u;
     T acc[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) acc[r] = T(0);
@@ -316,10 +308,6 @@ __global__ __launch_bounds__(256) void spmv_dia_kernel(const TA* __restrict__ A,
     const int NB = dg.ext[0] * dg.ext[1] * dg.ext[2];
     int oi = 0;
     for (int a = 0; a < dg.ext[0]; ++a) {
-        if (!((wb >> a) & 1u)) {   // zero slab
-            oi += dg.ext[1] * dg.ext[2];
-            continue;
-        }
         const int64_t oa = (dg.ext[0] == 7 ? (a - 3) : 0) * dg.stride[0];
         for (int b = 0; b < dg.ext[1]; ++b) {
             const int64_t ob = oa + (dg.ext[1] == 7 ? (b - 3) : 0) * dg.stride[1];
@@ -444,6 +432,80 @@ __global__ __launch_bounds__(256) void spmv_tiled_kernel(const TA* __restrict__ 
         } else if (t == 0) {
             dotp[blockIdx.x] = red[0];
         }
+    }
+}
+
+// LDS-windowed banded product for K vectors sharing one read of the stored
+// entries.  The offsets are taken slab by slab (slab a = offset a - 3 of the
+// slowest dimension: 49 entries per row for d = 3, 7 for d = 2, one slab of
+// 7 for d = 1); for each slab the block stages the K windows that slab
+// touches (kTileRows + 2*margin entries per vector) and every thread
+// multiplies its row's slab entries, held in registers, into K accumulators.
+// Entry loads of the next slab are issued before the barrier that precedes
+// its staging.  Zero (wavefront, slab) blocks are skipped as in the
+// one-vector kernel.
+template <class TA, class T, int D, int K>
+__global__ __launch_bounds__(256) void spmv_multi_kernel(const TA* __restrict__ A,
+                                                         const T* __restrict__ xpad,
+                                                         T* __restrict__ u, TileGeom tg,
+                                                         int64_t ldx,
+                                                         const int* __restrict__ skip,
+                                                         const uint32_t* __restrict__ bmask) {
+    if (skip && *skip) return;
+    extern __shared__ unsigned char lds_raw[];
+    T* win = reinterpret_cast<T*>(lds_raw);   // [K][WL]
+    constexpr int NS = D == 1 ? 1 : 7;        // slabs
+    constexpr int SW = D == 3 ? 49 : 7;       // entries per row and slab
+    constexpr int kNB = NS * SW;
+    const int t = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * kTileRows;
+    const uint32_t mk = bmask ? bmask[blockIdx.x] : ~0u;
+    const uint32_t wb = __builtin_amdgcn_readfirstlane((mk >> (kMaskSlabs * (t / kWaveRows))) &
+                                                       ((1u << kMaskSlabs) - 1u));
+    constexpr uint32_t kWaveBits = 0x204081u;   // bit 0 of each wavefront's group
+    const TA* Ab = A + (int64_t)blockIdx.x * kNB * kTileRows + t;
+    T acc[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) acc[r] = T(0);
+#pragma unroll 1
+    for (int a = 0; a < NS; ++a) {
+        const int bit = D == 3 ? a : 0;
+        const bool mine = (wb >> bit) & 1u;
+        const bool staged = ((mk >> bit) & kWaveBits) != 0u;   // uniform over the block
+        TA av[SW];
+        if (mine) {
+#pragma unroll
+            for (int q = 0; q < SW; ++q) av[q] = Ab[(a * SW + q) * kTileRows];
+        }
+        if (staged) {
+            // the K windows: all K loads of a position in flight together
+            const int64_t start =
+                tg.halo + j0 + (D >= 2 ? (int64_t)(a - 3) * tg.S0 : 0) - tg.margin;
+            for (int i = t; i < tg.WL; i += 256) {
+                const int64_t idx = start + i;
+                T v[K];
+#pragma unroll
+                for (int r = 0; r < K; ++r) v[r] = idx < ldx ? xpad[r * ldx + idx] : T(0);
+#pragma unroll
+                for (int r = 0; r < K; ++r) win[r * tg.WL + i] = v[r];
+            }
+        }
+        __syncthreads();
+        if (mine) {
+#pragma unroll
+            for (int q = 0; q < SW; ++q) {
+                const int p = D == 3 ? q / 7 : 0, c = D == 3 ? q % 7 : q;
+                const int off = tg.margin + t + (D == 3 ? (p - 3) * (int)tg.S1 : 0) + (c - 3);
+                const T e = (T)av[q];
+#pragma unroll
+                for (int r = 0; r < K; ++r) acc[r] += e * win[r * tg.WL + off];
+            }
+        }
+        __syncthreads();
+    }
+    if (j0 + t < tg.M) {
+#pragma unroll
+        for (int r = 0; r < K; ++r) u[(int64_t)r * tg.M + j0 + t] = acc[r];
     }
 }
 
@@ -673,6 +735,39 @@ static bool tile_geom(const GridDev& g, size_t es, TileGeom& tg, size_t& lds) {
     return lds <= 96 * 1024;
 }
 
+constexpr size_t kMultiLdsMax = 64 * 1024;
+
+template <class TA, class T, int D, int K>
+static fkgp_status launch_multi_k(unsigned grid, size_t lds, const TA* A, const T* x, T* u,
+                                  const TileGeom& tg, int64_t ldx, const int* skip,
+                                  const uint32_t* bmask, hipStream_t s) {
+    spmv_multi_kernel<TA, T, D, K><<<grid, 256, lds, s>>>(A, x, u, tg, ldx, skip, bmask);
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+template <class TA, class T, int D>
+static fkgp_status launch_multi_d(int K, unsigned grid, size_t lds, const TA* A, const T* x,
+                                  T* u, const TileGeom& tg, int64_t ldx, const int* skip,
+                                  const uint32_t* bmask, hipStream_t s) {
+    switch (K) {
+        case 16: return launch_multi_k<TA, T, D, 16>(grid, lds, A, x, u, tg, ldx, skip, bmask, s);
+        case 8: return launch_multi_k<TA, T, D, 8>(grid, lds, A, x, u, tg, ldx, skip, bmask, s);
+        case 4: return launch_multi_k<TA, T, D, 4>(grid, lds, A, x, u, tg, ldx, skip, bmask, s);
+        case 2: return launch_multi_k<TA, T, D, 2>(grid, lds, A, x, u, tg, ldx, skip, bmask, s);
+        default: return launch_multi_k<TA, T, D, 1>(grid, lds, A, x, u, tg, ldx, skip, bmask, s);
+    }
+}
+
+template <class TA, class T>
+static fkgp_status launch_multi(int d, int K, unsigned grid, size_t lds, const TA* A, const T* x,
+                                T* u, const TileGeom& tg, int64_t ldx, const int* skip,
+                                const uint32_t* bmask, hipStream_t s) {
+    if (d == 1) return launch_multi_d<TA, T, 1>(K, grid, lds, A, x, u, tg, ldx, skip, bmask, s);
+    if (d == 2) return launch_multi_d<TA, T, 2>(K, grid, lds, A, x, u, tg, ldx, skip, bmask, s);
+    return launch_multi_d<TA, T, 3>(K, grid, lds, A, x, u, tg, ldx, skip, bmask, s);
+}
+
 template <class TA, class T>
 static fkgp_status spmv_t(const GridDev& g, const TA* A, const uint32_t* bmask, const T* xpad,
                           T* u, int k, int64_t halo, const int* skip, hipStream_t s,
@@ -711,6 +806,24 @@ static fkgp_status spmv_t(const GridDev& g, const TA* A, const uint32_t* bmask, 
         return FKGP_OK;
     }
     if (nparts) *nparts = 0;
+    if (k > 1 && tile_geom(g, sizeof(T), tg, lds)) {
+        const int64_t ldxm = tg.M + 2 * tg.halo;
+        const unsigned grid = (unsigned)((tg.M + kTileRows - 1) / kTileRows);
+        const size_t wl_bytes = (size_t)tg.WL * sizeof(T);
+        for (int r0 = 0; r0 < k;) {
+            const int left = k - r0;
+            int K = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+            while (K > 1 && K * wl_bytes > kMultiLdsMax) K /= 2;
+            const T* xr = xpad + (int64_t)r0 * ldxm;
+            T* ur = u + (int64_t)r0 * tg.M;
+            const fkgp_status st = launch_multi<TA, T>(g.d, K, grid, K * wl_bytes, A, xr, ur, tg,
+                                                       ldxm, skip, bmask, s);
+            if (st != FKGP_OK) return st;
+            r0 += K;
+        }
+        FKGP_HIP(hipGetLastError());
+        return FKGP_OK;
+    }
     DiaGeom dg{};
     dg.d = g.d;
     dg.M = 1;
@@ -735,16 +848,16 @@ static fkgp_status spmv_t(const GridDev& g, const TA* A, const uint32_t* bmask, 
         const T* xr = xpad + (int64_t)r0 * ldx;
         T* ur = u + (int64_t)r0 * dg.M;
         if (left >= 8) {
-            spmv_dia_kernel<TA, T, 8><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip, bmask);
+            spmv_dia_kernel<TA, T, 8><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
             r0 += 8;
         } else if (left >= 4) {
-            spmv_dia_kernel<TA, T, 4><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip, bmask);
+            spmv_dia_kernel<TA, T, 4><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
             r0 += 4;
         } else if (left >= 2) {
-            spmv_dia_kernel<TA, T, 2><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip, bmask);
+            spmv_dia_kernel<TA, T, 2><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
             r0 += 2;
         } else {
-            spmv_dia_kernel<TA, T, 1><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip, bmask);
+            spmv_dia_kernel<TA, T, 1><<<grid, 256, 0, s>>>(A, xr, ur, dg, halo, ldx, skip);
             r0 += 1;
         }
     }
