@@ -392,9 +392,10 @@ __global__ __launch_bounds__(256) void spmv_tiled_kernel(const TA* __restrict__ 
     T* win = reinterpret_cast<T*>(lds_raw);
     constexpr int NW = D >= 2 ? 7 : 1;
     constexpr int kNB = D == 1 ? 7 : (D == 2 ? 49 : 343);
-    const int64_t j0 = (int64_t)blockIdx.x * kTileRows;
+    const unsigned tile = xcd_block();   // neighbouring tiles share window data
+    const int64_t j0 = (int64_t)tile * kTileRows;
     const int64_t ldx = tg.M + 2 * tg.halo;
-    const uint32_t mk = bmask ? bmask[blockIdx.x] : ~0u;
+    const uint32_t mk = bmask ? bmask[tile] : ~0u;
     // stage the windows (not needed when the whole tile is zero)
     if (mk != 0u) {
         for (int w = 0; w < NW; ++w) {
@@ -412,7 +413,7 @@ __global__ __launch_bounds__(256) void spmv_tiled_kernel(const TA* __restrict__ 
     const uint32_t wb = __builtin_amdgcn_readfirstlane((mk >> (kMaskSlabs * (t / kWaveRows))) &
                                                        ((1u << kMaskSlabs) - 1u));
     const T acc =
-        tile_row<TA, T, D>(A + (int64_t)blockIdx.x * kNB * kTileRows + t, win, tg, t, wb);
+        tile_row<TA, T, D>(A + (int64_t)tile * kNB * kTileRows + t, win, tg, t, wb);
     double part = 0.0;
     const int xc = (D >= 2 ? 3 * tg.WL : 0) + tg.margin + t;
     if (j0 + t < tg.M) {
@@ -458,12 +459,13 @@ __global__ __launch_bounds__(256) void spmv_multi_kernel(const TA* __restrict__ 
     constexpr int SW = D == 3 ? 49 : 7;       // entries per row and slab
     constexpr int kNB = NS * SW;
     const int t = threadIdx.x;
-    const int64_t j0 = (int64_t)blockIdx.x * kTileRows;
-    const uint32_t mk = bmask ? bmask[blockIdx.x] : ~0u;
+    const unsigned tile = xcd_block();
+    const int64_t j0 = (int64_t)tile * kTileRows;
+    const uint32_t mk = bmask ? bmask[tile] : ~0u;
     const uint32_t wb = __builtin_amdgcn_readfirstlane((mk >> (kMaskSlabs * (t / kWaveRows))) &
                                                        ((1u << kMaskSlabs) - 1u));
     constexpr uint32_t kWaveBits = 0x204081u;   // bit 0 of each wavefront's group
-    const TA* Ab = A + (int64_t)blockIdx.x * kNB * kTileRows + t;
+    const TA* Ab = A + (int64_t)tile * kNB * kTileRows + t;
     T acc[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) acc[r] = T(0);
