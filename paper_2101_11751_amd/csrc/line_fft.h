@@ -76,7 +76,9 @@ __device__ __forceinline__ double lane_xor<double>(double v, int S) {
     return __hiloint2double(hi, lo);
 }
 
-template <class T, int LOG2L>
+// TS: stride into the twiddle table (2 when tws belongs to a transform of
+// twice the length: the half-length twiddles are its even entries).
+template <class T, int LOG2L, int TS = 1>
 __device__ __forceinline__ void dif_regs(cplx<T> (&z)[line_regs<LOG2L>()], int e_lane,
                                          const cplx<T>* __restrict__ tws) {
     constexpr int L = 1 << LOG2L;
@@ -91,7 +93,7 @@ __device__ __forceinline__ void dif_regs(cplx<T> (&z)[line_regs<LOG2L>()], int e
             for (int r = 0; r < R; ++r) {
                 if (r & rs) continue;
                 const int e = r * 64 + e_lane;
-                const cplx<T> w = tws[(e & (S - 1)) * (L / (2 * S))];
+                const cplx<T> w = tws[(e & (S - 1)) * (L / (2 * S)) * TS];
                 const cplx<T> a = z[r], b = z[r + rs];
                 z[r] = {a.re + b.re, a.im + b.im};
                 z[r + rs] = cmul(cplx<T>{a.re - b.re, a.im - b.im}, w);
@@ -99,7 +101,7 @@ __device__ __forceinline__ void dif_regs(cplx<T> (&z)[line_regs<LOG2L>()], int e
         } else {
             const bool upper = (e_lane & S) != 0;
             // spans 1 and 2 use the twiddles 1 and -i only: no multiplication
-            const cplx<T> w = S > 2 ? tws[(e_lane & (S - 1)) * (L / (2 * S))] : cplx<T>{T(1), T(0)};
+            const cplx<T> w = S > 2 ? tws[(e_lane & (S - 1)) * (L / (2 * S)) * TS] : cplx<T>{T(1), T(0)};
             const bool odd = (e_lane & 1) != 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -118,7 +120,7 @@ __device__ __forceinline__ void dif_regs(cplx<T> (&z)[line_regs<LOG2L>()], int e
     }
 }
 
-template <class T, int LOG2L>
+template <class T, int LOG2L, int TS = 1>
 __device__ __forceinline__ void dit_regs(cplx<T> (&z)[line_regs<LOG2L>()], int e_lane,
                                          const cplx<T>* __restrict__ tws) {
     constexpr int L = 1 << LOG2L;
@@ -133,7 +135,7 @@ __device__ __forceinline__ void dit_regs(cplx<T> (&z)[line_regs<LOG2L>()], int e
             for (int r = 0; r < R; ++r) {
                 if (r & rs) continue;
                 const int e = r * 64 + e_lane;
-                const cplx<T> w = tws[(e & (S - 1)) * (L / (2 * S))];
+                const cplx<T> w = tws[(e & (S - 1)) * (L / (2 * S)) * TS];
                 const cplx<T> a = z[r];
                 const cplx<T> b = cmul_conj(z[r + rs], w);
                 z[r] = {a.re + b.re, a.im + b.im};
@@ -141,7 +143,7 @@ __device__ __forceinline__ void dit_regs(cplx<T> (&z)[line_regs<LOG2L>()], int e
             }
         } else {
             const bool upper = (e_lane & S) != 0;
-            const cplx<T> w = S > 2 ? tws[(e_lane & (S - 1)) * (L / (2 * S))] : cplx<T>{T(1), T(0)};
+            const cplx<T> w = S > 2 ? tws[(e_lane & (S - 1)) * (L / (2 * S)) * TS] : cplx<T>{T(1), T(0)};
             const bool odd = (e_lane & 1) != 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {

@@ -44,6 +44,68 @@ __device__ inline int64_t line_addr(const LineGeom& lg, int64_t l, int e) {
 
 constexpr int kLineBlock = 256;
 
+// Store of a line pass: element e = r*64 + e_lane of the (up to two) lines
+// at base[h] with stride S32 gets scale * z (+ add_coef * addv); or, with
+// fz.s set, the CG direction update of CgStep2 consumes the value in place
+// and the last workgroup finishes s^T z.  `active`: this wave holds results
+// (all threads of the block must call it when fz.s is set).
+template <class T, int R>
+__device__ __forceinline__ void line_store(const cplx<T> (&z)[R], int e_lane, bool active,
+                                           const bool (&ok)[2], const int64_t (&base)[2],
+                                           int S32, int m, T* out, T scale,
+                                           const T* __restrict__ addv, T add_coef,
+                                           const CgStep2& fz) {
+    if (fz.s) {
+        __shared__ double red[kLineBlock];
+        const int tid = threadIdx.x;
+        double acc = 0.0;
+        if (active) {
+            const double beta = fz.st->beta;
+            const T* uu = static_cast<const T*>(fz.u);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int e = r * 64 + e_lane;
+                if (e >= m) continue;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (!ok[h]) continue;
+                    const int64_t a = base[h] + (int64_t)(e * S32);
+                    T v = scale * (h == 0 ? z[r].re : z[r].im);
+                    if (addv) v += add_coef * addv[a];
+                    const double sn = fma(beta, fz.s[a], (double)uu[a]);
+                    const double zn = fma(beta, fz.z[a], (double)v);
+                    fz.s[a] = sn;
+                    fz.z[a] = zn;
+                    if (fz.p) fz.p[a] = fma(beta, fz.p[a], fz.r[a]);
+                    acc = fma(sn, zn, acc);
+                }
+            }
+        }
+        red[tid] = acc;
+        __syncthreads();
+        for (int s2 = kLineBlock / 2; s2 > 0; s2 >>= 1) {
+            if (tid < s2) red[tid] += red[tid + s2];
+            __syncthreads();
+        }
+        last_block_finish(fz.lb, red[0], red);
+        return;
+    }
+    if (!active) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = r * 64 + e_lane;
+        if (e >= m) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (!ok[h]) continue;
+            const int64_t a = base[h] + (int64_t)(e * S32);
+            T v = scale * (h == 0 ? z[r].re : z[r].im);
+            if (addv) v += add_coef * addv[a];
+            out[a] = v;
+        }
+    }
+}
+
 // Barrier-free variant: each wave convolves its own line pair (64/L pairs
 // when L < 64), loading the lines straight from global memory (strided
 // lines are gathered; the vector is small enough to stay in L2) with
@@ -85,51 +147,86 @@ __global__ __launch_bounds__(kLineBlock) void line_conv_direct(
         z[r].im = (in_line && ok[1]) ? in[base[1] + (int64_t)(e * S32)] : T(0);
     }
     conv_line_regs<T, LOG2L>(z, e_lane, tw, lam_br);
-    if (fz.s) {
-        __shared__ double red[kLineBlock];
-        const double beta = fz.st->beta;
-        const T* uu = static_cast<const T*>(fz.u);
-        double acc = 0.0;
+    line_store<T, R>(z, e_lane, true, ok, base, S32, m, out, scale, addv, add_coef, fz);
+}
+
+// Line pairs split over two waves (used for L >= 512; at 256 points the
+// duplicated gathers and the exchange cost more than the shorter chains
+// save).  The circulant input is zero in its upper half (m <= L/2), so the
+// first decimation-in-frequency stage (span L/2) needs no exchange: wave
+// half 0 keeps x[e], wave half 1 takes x[e] w^e (e < L/2, both load the same
+// entries).  Each wave then runs the
+// remaining length-L/2 transform (the even twiddles), the spectrum entries of
+// its half of the bit-reversed order and the inverse stages up to span L/4;
+// the last inverse stage (span L/2) adds the upper half's b conj(w^e)
+// through LDS, forming only the outputs e < L/2 (m <= L/2 are needed).
+// Half the registers and butterflies of a one-wave line per wave, twice the
+// waves: shorter dependent chains and more latency hiding.
+template <class T, int LOG2L>
+__global__ __launch_bounds__(kLineBlock) void line_conv_split(
+    const T* in, T* out, LineGeom lg, const T* __restrict__ lam_br,
+    const cplx<T>* __restrict__ tw, T scale, const T* __restrict__ addv, T add_coef,
+    const int* __restrict__ skip, CgStep2 fz) {
+    constexpr int L = 1 << LOG2L;
+    constexpr int H = L / 2;
+    constexpr int R = H / 64;
+    constexpr int kPairs = kLineBlock / 128;
+    static_assert(H >= 64, "split lines need L >= 128");
+    __shared__ cplx<T> xch[kPairs][H];
+    if (skip && *skip) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int half = wave & 1, slot = wave >> 1;
+    const int64_t npairs = (lg.nlines + 1) / 2;
+    const int64_t pair = (int64_t)xcd_block() * kPairs + slot;
+    const int m = lg.m_line;
+    const int S32 = (int)lg.S;
+    int64_t base[2] = {0, 0};
+    bool ok[2];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int e = r * 64 + e_lane;
-            if (e >= m) continue;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (!ok[h]) continue;
-                const int64_t a = base[h] + (int64_t)(e * S32);
-                T v = scale * (h == 0 ? z[r].re : z[r].im);
-                if (addv) v += add_coef * addv[a];
-                const double sn = fma(beta, fz.s[a], (double)uu[a]);
-                const double zn = fma(beta, fz.z[a], (double)v);
-                fz.s[a] = sn;
-                fz.z[a] = zn;
-                if (fz.p) fz.p[a] = fma(beta, fz.p[a], fz.r[a]);
-                acc = fma(sn, zn, acc);
-            }
-        }
-        red[tid] = acc;
-        __syncthreads();
-        for (int s2 = kLineBlock / 2; s2 > 0; s2 >>= 1) {
-            if (tid < s2) red[tid] += red[tid + s2];
-            __syncthreads();
-        }
-        last_block_finish(fz.lb, red[0], red);
-        return;
+    for (int h = 0; h < 2; ++h) {
+        const int64_t l = 2 * pair + h;
+        ok[h] = pair < npairs && l < lg.nlines;
+        if (ok[h]) base[h] = line_addr(lg, l, 0);
     }
+    cplx<T> z[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int e = r * 64 + e_lane;
-        if (e >= m) continue;
+        const int e = r * 64 + lane;
+        const bool in_line = e < m;
+        z[r].re = (in_line && ok[0]) ? in[base[0] + (int64_t)(e * S32)] : T(0);
+        z[r].im = (in_line && ok[1]) ? in[base[1] + (int64_t)(e * S32)] : T(0);
+    }
+    if (half) {   // first DIF stage, upper outputs: (x[e] - 0) w^e
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (!ok[h]) continue;
-            const int64_t a = base[h] + (int64_t)(e * S32);
-            T v = scale * (h == 0 ? z[r].re : z[r].im);
-            if (addv) v += add_coef * addv[a];
-            out[a] = v;
+        for (int r = 0; r < R; ++r) z[r] = cmul(z[r], tw[r * 64 + lane]);
+    }
+    dif_regs<T, LOG2L - 1, 2>(z, lane, tw);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const T lmb = lam_br[half * H + r * 64 + lane];
+        z[r].re *= lmb;
+        z[r].im *= lmb;
+    }
+    dit_regs<T, LOG2L - 1, 2>(z, lane, tw);
+    if (half) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = r * 64 + lane;
+            xch[slot][e] = cmul_conj(z[r], tw[e]);
         }
     }
+    __syncthreads();
+    if (!half) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const cplx<T> t = xch[slot][r * 64 + lane];
+            z[r].re += t.re;
+            z[r].im += t.im;
+        }
+    }
+    line_store<T, R>(z, lane, half == 0, ok, base, S32, m, out, scale, addv, add_coef, fz);
 }
 
 // Long lines: one workgroup per line pair at a time (grid-stride over the
@@ -161,9 +258,16 @@ __global__ __launch_bounds__(kLineBlock) void line_conv_long(
 
 // Blocks of a barrier-free pass: one line pair per wave (64/L per wave for
 // L < 64), four waves per block.
+// Lines of at least kSplitLog2 points are split over two waves per pair.
+constexpr int kSplitLog2 = 9;
+
+// Workgroups of a register-resident line pass (one per 4 pairs, one per 2
+// pairs when split, 64/L pairs per wave for L < 64).
 static unsigned line_direct_blocks(int log2L, const LineGeom& lg) {
-    const int64_t G = log2L >= 6 ? 1 : (64 >> log2L);
     const int64_t npairs = (lg.nlines + 1) / 2;
+    if (log2L >= kSplitLog2)
+        return (unsigned)std::max<int64_t>(1, (npairs + kLineBlock / 128 - 1) / (kLineBlock / 128));
+    const int64_t G = log2L >= 6 ? 1 : (64 >> log2L);
     const int64_t waves = (npairs + G - 1) / G;
     return (unsigned)std::max<int64_t>(1, (waves + kLineBlock / 64 - 1) / (kLineBlock / 64));
 }
@@ -218,14 +322,20 @@ fkgp_status launch_line_conv(int log2L, int lg1, const T* in, T* out, const Line
         line_conv_direct<T, LG><<<grid, kLineBlock, 0, s>>>(in, out, lg, lam, tw, scale,      \
                                                              addv, add_coef, skip, fz);      \
         break;
+#define FKGP_LS(LG)                                                                          \
+    case LG:                                                                                 \
+        line_conv_split<T, LG><<<grid, kLineBlock, 0, s>>>(in, out, lg, lam, tw, scale,       \
+                                                            addv, add_coef, skip, fz);       \
+        break;
     switch (log2L) {
-        FKGP_LC(3) FKGP_LC(4) FKGP_LC(5) FKGP_LC(6) FKGP_LC(7) FKGP_LC(8) FKGP_LC(9)
-        FKGP_LC(10) FKGP_LC(11)
+        FKGP_LC(3) FKGP_LC(4) FKGP_LC(5) FKGP_LC(6) FKGP_LC(7) FKGP_LC(8) FKGP_LS(9)
+        FKGP_LS(10) FKGP_LS(11)   // kSplitLog2 = 9
         default:
             set_error("grid dimension too long for the register-resident line FFT");
             return FKGP_EINVAL;
     }
 #undef FKGP_LC
+#undef FKGP_LS
     FKGP_HIP(hipGetLastError());
     return FKGP_OK;
 }
