@@ -1093,25 +1093,34 @@ __global__ void probe_init(PState* ps, int N, double n, double tol) {
     ps[j] = s;
 }
 
-// ap = z_p + c_p kappa_b (compressed A p); partials of s_p.ap and ap.b_hat
+// Direction update of the previous iteration, s_p = u_r + beta s_p and
+// z_p = v_r + beta z_p (beta = 0 and u_r = v_r = 0 before the first
+// iteration), then ap = z_p + c_p kappa_b (compressed A p) and the partials
+// of s_p.ap and ap.b_hat.
 __global__ __launch_bounds__(kRedBlock) void probe_ap(const PState* __restrict__ ps,
-                                                      const double* __restrict__ zp,
+                                                      double* __restrict__ zp,
                                                       const double* __restrict__ kb,
-                                                      const double* __restrict__ sp,
+                                                      double* __restrict__ sp,
                                                       const double* __restrict__ bh,
+                                                      const double* __restrict__ ur,
+                                                      const double* __restrict__ vr,
                                                       double* __restrict__ ap, int64_t M,
                                                       double* __restrict__ partials) {
     const int j = blockIdx.y;
     if (ps[j].done) return;
     __shared__ double sh[kRedBlock];
-    const double cp = ps[j].cp;
+    const double cp = ps[j].cp, beta = ps[j].beta;
     const int64_t o = (int64_t)j * M;
     double d1 = 0.0, d2 = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < M;
          i += (int64_t)gridDim.x * kRedBlock) {
-        const double a = fma(cp, kb[o + i], zp[o + i]);
+        const double sn = fma(beta, sp[o + i], ur[o + i]);
+        const double zn = fma(beta, zp[o + i], vr[o + i]);
+        sp[o + i] = sn;
+        zp[o + i] = zn;
+        const double a = fma(cp, kb[o + i], zn);
         ap[o + i] = a;
-        d1 = fma(sp[o + i], a, d1);
+        d1 = fma(sn, a, d1);
         d2 = fma(a, bh[o + i], d2);
     }
     const double t1 = block_sum(d1, sh);
@@ -1202,7 +1211,8 @@ __global__ __launch_bounds__(kRedBlock) void probe_dot_r(const PState* __restric
     }
 }
 
-// rho' = <r, r> (Claim 4); stop test; beta and the scalar parts of p.
+// rho' = <r, r> (Claim 4); stop test; beta and the scalar parts of p (the
+// vector parts are updated by the next probe_ap).
 __global__ __launch_bounds__(kRedBlock) void probe_fin_r(PState* ps,
                                                          const double* __restrict__ partials,
                                                          int nbv, double n,
@@ -1229,21 +1239,6 @@ __global__ __launch_bounds__(kRedBlock) void probe_fin_r(PState* ps,
     s.pb = d2 + beta * s.pb;
     s.cp = s.cr + beta * s.cp;
     ps[j] = s;
-}
-
-// s_p = u_r + beta s_p; z_p = v_r + beta z_p
-__global__ void probe_upd_sz(const PState* __restrict__ ps, double* __restrict__ sp,
-                             double* __restrict__ zp, const double* __restrict__ ur,
-                             const double* __restrict__ vr, int64_t M) {
-    const int j = blockIdx.y;
-    if (ps[j].done) return;
-    const double b = ps[j].beta;
-    const int64_t o = (int64_t)j * M;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        sp[o + i] = fma(b, sp[o + i], ur[o + i]);
-        zp[o + i] = fma(b, zp[o + i], vr[o + i]);
-    }
 }
 
 // W^T x_j = u_x + c_x b_hat
@@ -1387,7 +1382,7 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
     FKGP_HIP(sc.get(&rpad, ldx * N));
     const int nbv = vec_blocks(M);
     FKGP_HIP(sc.get(&partials, (size_t)2 * nbv * N));
-    for (double* v : {sp, zp, ux, rh})
+    for (double* v : {sp, zp, ux, rh, ur, vr})
         FKGP_HIP(hipMemsetAsync(v, 0, sizeof(double) * M * N, st));
     FKGP_HIP(hipMemsetAsync(rpad, 0, sizeof(double) * ldx * N, st));
     // kappa_b = K_G W^T z_j (FP64)
@@ -1408,7 +1403,7 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
         if (all || launched >= maxiter) break;
         const int nit = std::min(kBatch, maxiter - launched);
         for (int it = 0; it < nit; ++it) {
-            probe_ap<<<gv, kRedBlock, 0, st>>>(ps, zp, kb, sp, bh, ap, M, partials);
+            probe_ap<<<gv, kRedBlock, 0, st>>>(ps, zp, kb, sp, bh, ur, vr, ap, M, partials);
             probe_fin_ap<<<N, kRedBlock, 0, st>>>(ps, partials, nbv, c.s2, n, alphas);
             probe_upd_r<<<ge, 256, 0, st>>>(ps, ux, sp, rh, ap, rpad, M, ldx, c.halo);
             FKGP_HIP(hipGetLastError());
@@ -1418,7 +1413,6 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
             if (rs != FKGP_OK) return rs;
             probe_dot_r<<<gv, kRedBlock, 0, st>>>(ps, rh, ur, bh, M, partials);
             probe_fin_r<<<N, kRedBlock, 0, st>>>(ps, partials, nbv, n, betas);
-            probe_upd_sz<<<ge, 256, 0, st>>>(ps, sp, zp, ur, vr, M);
             FKGP_HIP(hipGetLastError());
         }
         launched += nit;

@@ -811,7 +811,10 @@ __global__ void transpose_to_dia(const double* __restrict__ in, T* __restrict__ 
             if (v != T(0)) bits |= 1u << (w * kMaskSlabs + o / 49);
         }
     }
-    if (bits) atomicOr(&occ, bits);   // integer OR: order-independent
+    // OR over the wavefront, then one LDS OR per wavefront (integer OR:
+    // order-independent)
+    for (int off = 32; off > 0; off >>= 1) bits |= (uint32_t)__shfl_xor((int)bits, off);
+    if (((threadIdx.y * 32 + threadIdx.x) & 63) == 0 && bits) atomicOr(&occ, bits);
     __syncthreads();
     if (threadIdx.x == 0 && threadIdx.y == 0 && occ) atomicOr(&bmask[j0 / kRowTile], occ);
 }
