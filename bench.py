@@ -30,10 +30,10 @@ import time
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the banded product on this workload, from the two
-# rocprofv3 --pmc runs (FETCH_SIZE x 1.9995, WRITE_SIZE x 1.0, calibrated on a
+# rocprofv3 --pmc runs (FETCH_SIZE x 1.9997, WRITE_SIZE x 1.0, calibrated on a
 # 256 MiB copy) recorded in profiles/radar3d_hbm_traffic_pmc.md.  Set to None
 # whenever spmv_tiled_kernel changes until the counters are taken again.
-SPMV_TRAFFIC_BYTES = None
+SPMV_TRAFFIC_BYTES = 340.9e6
 
 
 def _parse():
