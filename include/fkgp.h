@@ -84,6 +84,9 @@ typedef struct {
                                 (0..31, d <= 2), for fkgp_mll_and_grad */
     uint64_t probe_seed;     /* z_j[i] = 1 - 2*(SplitMix64((seed<<48) ^
                                 (j<<40) ^ i) >> 63) */
+    int keep_points;         /* 1: the handle also keeps the points in cell
+                                order (n * 4 values of the input dtype) and
+                                the cell bounds, for fkgp_ski_solve (d <= 2) */
 } fkgp_precompute_opts;
 
 /* One-shot O(n) pass (Sec. 3.1 "Precomputation", Claim 2).
@@ -255,6 +258,20 @@ fkgp_status fkgp_kg_matvec(const fkgp_handle* h, const fkgp_hypers* hyp,
  * for all k vectors.  Does not synchronise. */
 fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int k,
                             fkgp_dtype xdt, void* stream);
+
+/* The plain SKI posterior mean, as the comparison baseline of the method
+ * (Sec. 2.3: each CG iteration applies W K_G W^T + s2 I to an n-vector, so
+ * it costs O(n + m log m), where the factorized CG's costs O(m log m)).  CG
+ * in n-space on (W K_G W^T + s2 I) z = y from z = 0, stopped at
+ * ||r|| <= tol ||y||; mean_grid (m doubles) = K_G W^T z, the same grid
+ * weights fkgp_solve returns (Theorem 1 / Fact 2).  W^T v is formed
+ * deterministically from the points kept in cell order (per-cell moments,
+ * fixed-order sums), W v by gathering the 4^d stencil nodes of each point.
+ * Needs a handle made with keep_points (d <= 2), else FKGP_EINVAL.
+ * Synchronises `stream`. */
+fkgp_status fkgp_ski_solve(const fkgp_handle* h, const fkgp_hypers* hyp, double tol,
+                           int maxiter, double* mean_grid, fkgp_solve_info* info,
+                           void* stream);
 
 void fkgp_destroy(fkgp_handle* h);
 

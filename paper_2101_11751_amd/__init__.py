@@ -24,7 +24,8 @@ OK, ENOTCONV, EINVAL, EOUTOFGRID, ENOMEM, EDEVICE = 0, 1, -1, -2, -3, -4
 #: every symbol that include/fkgp.h declares
 EXPORTS = ("fkgp_precompute", "fkgp_describe", "fkgp_export_stats", "fkgp_export_sketches",
            "fkgp_solve", "fkgp_mll_and_grad", "fkgp_batch_mll_and_grad", "fkgp_interpolate", "fkgp_apply_B",
-           "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_destroy", "fkgp_last_error")
+           "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_ski_solve", "fkgp_destroy",
+           "fkgp_last_error")
 
 
 class FkgpError(RuntimeError):
@@ -49,7 +50,7 @@ class _Hypers(ctypes.Structure):
 
 class _PreOpts(ctypes.Structure):
     _fields_ = [("stats_dtype", ctypes.c_int), ("n_probes", ctypes.c_int),
-                ("probe_seed", ctypes.c_uint64)]
+                ("probe_seed", ctypes.c_uint64), ("keep_points", ctypes.c_int)]
 
 
 class _Desc(ctypes.Structure):
@@ -106,6 +107,8 @@ def load_library():
     L.fkgp_export_sketches.argtypes = [p, p, p]
     L.fkgp_solve.argtypes = [p, ctypes.POINTER(_Hypers), p, p, ctypes.POINTER(_SolveOpts),
                              ctypes.POINTER(_SolveInfo), p]
+    L.fkgp_ski_solve.argtypes = [p, ctypes.POINTER(_Hypers), ctypes.c_double, ctypes.c_int, p,
+                                 ctypes.POINTER(_SolveInfo), p]
     L.fkgp_mll_and_grad.argtypes = [p, ctypes.POINTER(_Hypers), ctypes.POINTER(_MllOpts),
                                     ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_MllInfo), p]
@@ -214,9 +217,11 @@ class Handle:
             pass
 
 
-def precompute(grid, x, y, stats_dtype=torch.float32, n_probes=0, probe_seed=0):
+def precompute(grid, x, y, stats_dtype=torch.float32, n_probes=0, probe_seed=0,
+               keep_points=False):
     """fkgp_precompute: x is a list of d device tensors (float32 or float64),
-    y a device tensor of the same dtype and length."""
+    y a device tensor of the same dtype and length.  keep_points: also keep
+    the points in cell order for ski_solve (d <= 2)."""
     L = load_library()
     d = int(grid["d"])
     xs = [t.contiguous() for t in x]
@@ -227,7 +232,7 @@ def precompute(grid, x, y, stats_dtype=torch.float32, n_probes=0, probe_seed=0):
         assert t.dtype == y.dtype and t.numel() == n and t.is_cuda
     arr = (ctypes.c_void_p * 3)(*([t.data_ptr() for t in xs] + [0] * (3 - d)))
     g = _grid_struct(grid)
-    o = _PreOpts(_dtype_code(stats_dtype), int(n_probes), int(probe_seed))
+    o = _PreOpts(_dtype_code(stats_dtype), int(n_probes), int(probe_seed), int(bool(keep_points)))
     out = ctypes.c_void_p()
     _check(L.fkgp_precompute(ctypes.byref(g), arr, _ptr(y), n, dt, ctypes.byref(o), _stream(),
                              ctypes.byref(out)))
@@ -269,6 +274,19 @@ def solve(h, hypers, rhs=None, tol=1e-6, maxiter=1000, op_precision="f64"):
                                                      OP_STATS if op_precision == "stats"
                                                      else OP_F64)),
                              ctypes.byref(info), _stream()))
+    return out, {"iterations": info.iterations, "converged": bool(info.converged),
+                 "rel_residual": info.rel_residual, "status": st}
+
+
+def ski_solve(h, hypers, tol=1e-6, maxiter=1000):
+    """fkgp_ski_solve: the plain SKI baseline (CG in n-space on
+    W K_G W^T + s2 I); returns (mean grid weights [M] float64, info dict)."""
+    L = load_library()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty(h.m_total, dtype=torch.float64, device=dev)
+    info = _SolveInfo()
+    st = _check(L.fkgp_ski_solve(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)), float(tol),
+                                 int(maxiter), _ptr(out), ctypes.byref(info), _stream()))
     return out, {"iterations": info.iterations, "converged": bool(info.converged),
                  "rel_residual": info.rel_residual, "status": st}
 

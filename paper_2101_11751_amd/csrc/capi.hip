@@ -34,6 +34,13 @@ struct fkgp_handle {
     uint32_t* bmask = nullptr;  // [mask_words(M)] block occupancy of W^T W
     double yty = 0.0;
     int64_t nzblocks = 0;
+    // points kept in cell order (keep_points): payload of dtype in_dt
+    // (coordinates, y, original index) and the cell bounds
+    void* pts_block = nullptr;
+    void* pay = nullptr;
+    uint32_t* cstart = nullptr;
+    uint32_t* cend = nullptr;
+    fkgp_dtype in_dt = FKGP_F32;
     void* block = nullptr;      // one pool allocation holding the arrays above
 };
 
@@ -713,6 +720,168 @@ fkgp_status solve_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const doubl
     return res;
 }
 
+// ---------------------------------------------------------------------------
+// Plain SKI baseline: CG in n-space on A z = y, A = W K_G W^T + s2 I (the
+// iteration the factorized CG replaces; Sec. 2.3), vectors in the kept cell
+// order.  Scalars stay on the device; the host polls the stop flag.
+// ---------------------------------------------------------------------------
+struct SkiCg {
+    double rho, alpha, beta, eps;
+    int done, iters;
+};
+
+// partials of a.b over n (grid-stride, fixed shape: deterministic)
+__global__ __launch_bounds__(kRedBlock) void nvec_dot(const double* __restrict__ a,
+                                                      const double* __restrict__ b, int64_t n,
+                                                      double* __restrict__ partials,
+                                                      const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    __shared__ double sh[kRedBlock];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kRedBlock)
+        acc = fma(a[i], b[i], acc);
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+enum SkiFin { SKI_INIT = 0, SKI_ALPHA = 1, SKI_RHO = 2 };
+
+__global__ __launch_bounds__(kRedBlock) void ski_fin(const double* __restrict__ partials,
+                                                     int nb, SkiCg* cg, int op, double tol) {
+    if (cg->done) return;
+    __shared__ double sh[kRedBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kRedBlock) acc += partials[i];
+    const double v = block_sum(acc, sh);
+    if (threadIdx.x != 0) return;
+    if (op == SKI_INIT) {   // v = y.y
+        cg->rho = v;
+        cg->eps = tol * tol * v;
+        cg->done = v > 0.0 ? 0 : 1;
+    } else if (op == SKI_ALPHA) {   // v = p.Ap
+        const double a = cg->rho / v;
+        if (!isfinite(a)) {
+            cg->done = 2;
+            return;
+        }
+        cg->alpha = a;
+    } else {   // v = r.r
+        cg->iters += 1;
+        if (!(v > cg->eps)) {
+            cg->rho = v;
+            cg->done = 1;
+            return;
+        }
+        cg->beta = v / cg->rho;
+        cg->rho = v;
+    }
+}
+
+__global__ void ski_upd_zr(const SkiCg* __restrict__ cg, double* __restrict__ z,
+                           double* __restrict__ r, const double* __restrict__ p,
+                           const double* __restrict__ q, int64_t n) {
+    if (cg->done) return;
+    const double a = cg->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        z[i] = fma(a, p[i], z[i]);
+        r[i] = fma(-a, q[i], r[i]);
+    }
+}
+
+__global__ void ski_upd_p(const SkiCg* __restrict__ cg, double* __restrict__ p,
+                          const double* __restrict__ r, int64_t n) {
+    if (cg->done) return;
+    const double b = cg->beta;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = fma(b, p[i], r[i]);
+}
+
+fkgp_status ski_solve_impl(const fkgp_handle* h, const fkgp_hypers* hyp, double tol, int maxiter,
+                           double* mean_grid, fkgp_solve_info* info, hipStream_t st) {
+    Scratch sc(st);
+    OpCtx c;
+    fkgp_status rs = make_ctx(h, hyp, FKGP_F64, c, sc);
+    if (rs != FKGP_OK) return rs;
+    const GridDev& g = h->g;
+    const int64_t n = h->n, M = h->M;
+    int64_t ncells = 1;
+    for (int k = 0; k < g.d; ++k) ncells *= g.nc[k];
+    const int64_t nn = std::max<int64_t>(n, 1);
+    double *z, *r, *p, *q, *R, *T1, *wt, *kv, *partials;
+    SkiCg* cg;
+    FKGP_HIP(sc.get(&z, nn));
+    FKGP_HIP(sc.get(&r, nn));
+    FKGP_HIP(sc.get(&p, nn));
+    FKGP_HIP(sc.get(&q, nn));
+    FKGP_HIP(sc.get(&R, ncells * (g.d == 1 ? 4 : 16)));
+    FKGP_HIP(sc.get(&T1, M * (g.d == 1 ? 1 : 4)));
+    FKGP_HIP(sc.get(&wt, M));
+    FKGP_HIP(sc.get(&kv, M));
+    const int nb = red_blocks(nn);
+    FKGP_HIP(sc.get(&partials, nb));
+    FKGP_HIP(sc.get(&cg, 1));
+    const unsigned ewg = ew_grid(nn);
+    const SkiCg init{};
+    FKGP_HIP(hipMemcpyAsync(cg, &init, sizeof(SkiCg), hipMemcpyHostToDevice, st));
+    FKGP_HIP(hipMemsetAsync(z, 0, sizeof(double) * nn, st));
+    rs = ski_y(g, h->in_dt, h->pay, n, r, st);
+    if (rs != FKGP_OK) return rs;
+    FKGP_HIP(hipMemcpyAsync(p, r, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+    const int* done = &cg->done;
+    nvec_dot<<<nb, kRedBlock, 0, st>>>(r, r, n, partials, nullptr);
+    ski_fin<<<1, kRedBlock, 0, st>>>(partials, nb, cg, SKI_INIT, tol);
+    FKGP_HIP(hipGetLastError());
+    // q = (W K_G W^T + s2 I) v
+    auto apply = [&](const double* v) -> fkgp_status {
+        fkgp_status e = ski_wt(g, h->in_dt, h->pay, h->cstart, h->cend, v, R, T1, wt, st);
+        if (e != FKGP_OK) return e;
+        e = kg_apply(g, c.sp64, FKGP_F64, wt, kv, 1, c.so, nullptr, 0.0, nullptr, st);
+        if (e != FKGP_OK) return e;
+        return ski_w(g, h->in_dt, h->pay, n, kv, v, c.s2, q, st);
+    };
+    SkiCg out{};
+    constexpr int kBatch = 8;
+    int launched = 0;
+    for (;;) {
+        FKGP_HIP(hipMemcpyAsync(&out, cg, sizeof(SkiCg), hipMemcpyDeviceToHost, st));
+        FKGP_HIP(hipStreamSynchronize(st));
+        if (out.done || launched >= maxiter) break;
+        const int nit = std::min(kBatch, maxiter - launched);
+        for (int it = 0; it < nit; ++it) {
+            rs = apply(p);
+            if (rs != FKGP_OK) return rs;
+            nvec_dot<<<nb, kRedBlock, 0, st>>>(p, q, n, partials, done);
+            ski_fin<<<1, kRedBlock, 0, st>>>(partials, nb, cg, SKI_ALPHA, tol);
+            ski_upd_zr<<<ewg, 256, 0, st>>>(cg, z, r, p, q, n);
+            nvec_dot<<<nb, kRedBlock, 0, st>>>(r, r, n, partials, done);
+            ski_fin<<<1, kRedBlock, 0, st>>>(partials, nb, cg, SKI_RHO, tol);
+            ski_upd_p<<<ewg, 256, 0, st>>>(cg, p, r, n);
+            FKGP_HIP(hipGetLastError());
+        }
+        launched += nit;
+    }
+    if (out.done == 2) {
+        set_error("SKI CG broke down (non-finite step)");
+        return FKGP_EDEVICE;
+    }
+    // mean_grid = K_G W^T z
+    rs = ski_wt(g, h->in_dt, h->pay, h->cstart, h->cend, z, R, T1, wt, st);
+    if (rs != FKGP_OK) return rs;
+    rs = kg_apply(g, c.sp64, FKGP_F64, wt, mean_grid, 1, c.so, nullptr, 0.0, nullptr, st);
+    if (rs != FKGP_OK) return rs;
+    FKGP_HIP(hipStreamSynchronize(st));
+    const double ynorm2 = h->yty;
+    if (info) {
+        info->iterations = out.iters;
+        info->converged = out.done == 1 ? 1 : 0;
+        info->rel_residual = std::sqrt(std::max(out.rho, 0.0) / (ynorm2 > 0 ? ynorm2 : 1.0));
+    }
+    return out.done == 1 ? FKGP_OK : FKGP_ENOTCONV;
+}
+
 }  // namespace
 }  // namespace fkgp
 
@@ -737,9 +906,10 @@ fkgp_status guarded(F&& f) {
 // scratch does): freed on the default stream once pending work is done.
 void free_handle(fkgp_handle* h) {
     if (!h) return;
-    if (h->block) {
+    if (h->block || h->pts_block) {
         (void)hipDeviceSynchronize();
-        (void)hipFreeAsync(h->block, nullptr);
+        if (h->block) (void)hipFreeAsync(h->block, nullptr);
+        if (h->pts_block) (void)hipFreeAsync(h->pts_block, nullptr);
         (void)hipStreamSynchronize(nullptr);
     }
     delete h;
@@ -785,8 +955,16 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
                     return FKGP_EINVAL;
                 }
         }
-        fkgp_precompute_opts o{FKGP_F32, 0, 0};
+        fkgp_precompute_opts o{FKGP_F32, 0, 0, 0};
         if (opts) o = *opts;
+        if (o.keep_points != 0 && o.keep_points != 1) {
+            set_error("keep_points must be 0 or 1");
+            return FKGP_EINVAL;
+        }
+        if (o.keep_points && g.d > 2) {
+            set_error("keep_points (the plain SKI operator) is supported for d <= 2");
+            return FKGP_EINVAL;
+        }
         if (o.stats_dtype != FKGP_F32 && o.stats_dtype != FKGP_F64) {
             set_error("stats dtype must be FKGP_F32 or FKGP_F64");
             return FKGP_EINVAL;
@@ -839,7 +1017,24 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
         (void)hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), s);
         (void)hipMemsetAsync(h->bmask, 0, bK, s);
         StatsOut so{h->A, h->wty, h->sketches, h->yty_dev, h->bmask,
-                    reinterpret_cast<unsigned long long*>(h->yty_dev + 2)};
+                    reinterpret_cast<unsigned long long*>(h->yty_dev + 2), nullptr, nullptr,
+                    nullptr};
+        if (o.keep_points) {
+            int64_t ncells = 1;
+            for (int k = 0; k < g.d; ++k) ncells *= g.nc[k];
+            const size_t bp = up((in == FKGP_F32 ? 16 : 32) * (size_t)std::max<int64_t>(n, 1));
+            const size_t bc = up(sizeof(uint32_t) * (size_t)ncells);
+            if ((e = hipMallocAsync(&h->pts_block, bp + 2 * bc, s)) != hipSuccess)
+                return fail(hip_fail(e, "hipMallocAsync(points)"));
+            unsigned char* pb = static_cast<unsigned char*>(h->pts_block);
+            h->pay = pb;
+            h->cstart = reinterpret_cast<uint32_t*>(pb + bp);
+            h->cend = reinterpret_cast<uint32_t*>(pb + bp + bc);
+            h->in_dt = in;
+            so.keep_pay = h->pay;
+            so.keep_cstart = h->cstart;
+            so.keep_cend = h->cend;
+        }
         st = run_precompute(g, x, y, n, in, h->dt, h->nprobe, h->seed, so, bad, s);
         unsigned long long hbad = ~0ull;
         double back[3] = {0.0, 0.0, 0.0};
@@ -1055,6 +1250,30 @@ fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int
         }
         return spmv_dia_any(h->g, h->dt, xdt, h->A, h->bmask, xpad, u, k, dia_halo(h->g), nullptr,
                             static_cast<hipStream_t>(stream));
+    });
+}
+
+fkgp_status fkgp_ski_solve(const fkgp_handle* h, const fkgp_hypers* hyp, double tol,
+                           int maxiter, double* mean_grid, fkgp_solve_info* info,
+                           void* stream) {
+    return guarded([&]() -> fkgp_status {
+        set_error("");
+        if (!h || !mean_grid) {
+            set_error("handle and mean_grid must be non-NULL");
+            return FKGP_EINVAL;
+        }
+        if (!h->pay) {
+            set_error("the handle keeps no points: precompute with keep_points = 1 (d <= 2)");
+            return FKGP_EINVAL;
+        }
+        fkgp_status st = check_hypers(h, hyp);
+        if (st != FKGP_OK) return st;
+        if (!(tol >= 0.0) || maxiter < 0) {
+            set_error("tol must be >= 0 and maxiter >= 0");
+            return FKGP_EINVAL;
+        }
+        return ski_solve_impl(h, hyp, tol, maxiter, mean_grid, info,
+                              static_cast<hipStream_t>(stream));
     });
 }
 

@@ -192,7 +192,25 @@ struct StatsOut {
     double* yty_dev;    // scalar
     uint32_t* bmask;    // [mask_words(M)] block occupancy, zeroed by the caller
     unsigned long long* nzblocks;   // number of set mask bits (written last)
+    // optional (d <= 2): copies of the points in cell order (payload of the
+    // input dtype: coordinates, y, original index) and the cell bounds
+    void* keep_pay;
+    uint32_t* keep_cstart;
+    uint32_t* keep_cend;
 };
+
+// Plain SKI operator pieces on kept points (precompute.hip).
+// wtv[M] = W^T v for v (n doubles, cell order); R: ncells * 4^d, T1: M * 4^(d-1)
+// doubles of scratch.
+fkgp_status ski_wt(const GridDev& g, fkgp_dtype in, const void* pay, const uint32_t* cstart,
+                   const uint32_t* cend, const double* v, double* R, double* T1, double* wtv,
+                   hipStream_t s);
+// out = W gv + s2 v (n doubles, cell order), gv on the grid.
+fkgp_status ski_w(const GridDev& g, fkgp_dtype in, const void* pay, int64_t n,
+                  const double* gv, const double* v, double s2, double* out, hipStream_t s);
+// y of the kept points (cell order).
+fkgp_status ski_y(const GridDev& g, fkgp_dtype in, const void* pay, int64_t n, double* y,
+                  hipStream_t s);
 
 fkgp_status run_precompute(const GridDev& g, const void* const* x, const void* y,
                            int64_t n, fkgp_dtype in, fkgp_dtype stats,

@@ -976,13 +976,14 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
             fkgp_status st = exclusive_scan(counts, offs, nc, sums, s);
             if (st != FKGP_OK) return st;
             const size_t lds = 4 * sizeof(uint32_t) << dbits[p];
+            const bool with_idx = nprobe > 0 || out.keep_pay != nullptr;
             if (p == 0)
                 radix_scatter<Tin, true><<<ntiles, kBlock, lds, s>>>(
-                    kin, nullptr, xs, y, d, nprobe > 0, n, offs, ntiles, dshift[p], dbits[p],
+                    kin, nullptr, xs, y, d, with_idx, n, offs, ntiles, dshift[p], dbits[p],
                     kout, pout);
             else
                 radix_scatter<Tin, false><<<ntiles, kBlock, lds, s>>>(
-                    kin, pin, xs, y, d, nprobe > 0, n, offs, ntiles, dshift[p], dbits[p],
+                    kin, pin, xs, y, d, with_idx, n, offs, ntiles, dshift[p], dbits[p],
                     kout, pout);
             FKGP_HIP(hipGetLastError());
             std::swap(kin, kout);
@@ -991,6 +992,9 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         // kin/pin now hold the sorted keys/payload
         cell_bounds<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(kin, n, cstart, cend);
         FKGP_HIP(hipGetLastError());
+        if (out.keep_pay)
+            FKGP_HIP(hipMemcpyAsync(out.keep_pay, pin, sizeof(P) * (size_t)n,
+                                    hipMemcpyDeviceToDevice, s));
         const size_t lds_mom = sizeof(double) * 64 * (kPw + nr);
         if (d == 1)
             cell_moments<1, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
@@ -1080,11 +1084,209 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
     }
     sum_fixed<<<1, 1024, 0, s>>>(Myy, ncells, out.yty_dev);
     FKGP_HIP(hipGetLastError());
+    if (out.keep_cstart) {   // cell bounds (all zero for n = 0)
+        FKGP_HIP(hipMemcpyAsync(out.keep_cstart, cstart, sizeof(uint32_t) * ncells,
+                                hipMemcpyDeviceToDevice, s));
+        FKGP_HIP(hipMemcpyAsync(out.keep_cend, cend, sizeof(uint32_t) * ncells,
+                                hipMemcpyDeviceToDevice, s));
+    }
     FKGP_HIP(hipFreeAsync(block, s));
     return FKGP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Plain SKI operator on the kept points (Sec. 2.3: W K_G W^T + s2 I applied
+// to an n-vector, O(n + m log m) per product).  The points are in cell
+// order, so W^T v is the vector assembly of the precompute with y replaced
+// by v: per-cell moments sum_p v_p prod_k t_k^{q_k} (q_k <= 3, one wave per
+// cell, lanes striding over the cell's points, a fixed xor-tree across the
+// wave), then the separable stages that turn moment digits into the 4
+// stencil offsets of each dimension.  W g gathers the 4^d stencil nodes of
+// each point with the Keys weights.
+// ---------------------------------------------------------------------------
+template <class Tin, int D>
+__global__ __launch_bounds__(64) void ski_cell_moments(
+    const typename PayloadOf<Tin>::type* __restrict__ pay, const uint32_t* __restrict__ cstart,
+    const uint32_t* __restrict__ cend, GridDev g, const double* __restrict__ v,
+    double* __restrict__ R) {
+    constexpr int NR = ipow_c<D>(4);
+    const int64_t cell = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t s0 = cstart[cell], s1 = cend[cell];
+    double acc[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] = 0.0;
+    for (uint32_t i = s0 + lane; i < s1; i += 64) {
+        const auto p = pay[i];
+        double tq[D][4];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            int base;
+            double t;
+            if (!locate((double)get_slot(p, k), g.g0[k], g.h[k], g.m[k], base, t)) t = 0.0;
+            tq[k][0] = 1.0;
+            tq[k][1] = t;
+            tq[k][2] = t * t;
+            tq[k][3] = t * t * t;
+        }
+        const double vi = v[i];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            double w = vi;
+            int rem = q;
+#pragma unroll
+            for (int k = D - 1; k >= 0; --k) {
+                w *= tq[k][rem & 3];
+                rem >>= 2;
+            }
+            acc[q] += w;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+        for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) R[cell * NR + q] = acc[q];
+    }
+}
+
+__device__ inline void keys_weights(double t, double w[4]) {
+    const double t2 = t * t, t3 = t2 * t;
+    w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
+    w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+    w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+    w[3] = 0.5 * (t3 - t2);
+}
+
+template <class Tin, int D>
+__global__ void ski_interp(const typename PayloadOf<Tin>::type* __restrict__ pay, int64_t n,
+                           GridDev g, const double* __restrict__ gv,
+                           const double* __restrict__ v, double s2, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const auto p = pay[i];
+    int base[D];
+    double w[D][4];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double t;
+        if (!locate((double)get_slot(p, k), g.g0[k], g.h[k], g.m[k], base[k], t)) {
+            base[k] = 1;   // not reached: the precompute rejected such points
+            t = 0.0;
+        }
+        keys_weights(t, w[k]);
+    }
+    double acc = 0.0;
+    if (D == 1) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc = fma(w[0][a], gv[base[0] - 1 + a], acc);
+    } else {
+        const int64_t m1 = g.m[D - 1];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            double r = 0.0;
+            const int64_t row = (int64_t)(base[0] - 1 + a) * m1 + (base[D - 1] - 1);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) r = fma(w[D - 1][b], gv[row + b], r);
+            acc = fma(w[0][a], r, acc);
+        }
+    }
+    out[i] = fma(s2, v[i], acc);
+}
+
+template <class Tin>
+__global__ void ski_extract_y(const typename PayloadOf<Tin>::type* __restrict__ pay, int64_t n,
+                              int d, double* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (double)get_slot(pay[i], d);
+}
+
 }  // namespace
+
+fkgp_status ski_wt(const GridDev& g, fkgp_dtype in, const void* pay, const uint32_t* cstart,
+                   const uint32_t* cend, const double* v, double* R, double* T1, double* wtv,
+                   hipStream_t s) {
+    const int d = g.d;
+    int64_t ncells = 1;
+    for (int k = 0; k < d; ++k) ncells *= g.nc[k];
+    if (d == 1) {
+        if (in == FKGP_F32)
+            ski_cell_moments<float, 1><<<(unsigned)ncells, 64, 0, s>>>(
+                static_cast<const float4*>(pay), cstart, cend, g, v, R);
+        else
+            ski_cell_moments<double, 1><<<(unsigned)ncells, 64, 0, s>>>(
+                static_cast<const double4*>(pay), cstart, cend, g, v, R);
+    } else if (d == 2) {
+        if (in == FKGP_F32)
+            ski_cell_moments<float, 2><<<(unsigned)ncells, 64, 0, s>>>(
+                static_cast<const float4*>(pay), cstart, cend, g, v, R);
+        else
+            ski_cell_moments<double, 2><<<(unsigned)ncells, 64, 0, s>>>(
+                static_cast<const double4*>(pay), cstart, cend, g, v, R);
+    } else {
+        set_error("the plain SKI operator covers d <= 2");
+        return FKGP_EINVAL;
+    }
+    FKGP_HIP(hipGetLastError());
+    const KeysTables tab = make_tables();
+    Dims3 cur{{1, 1, 1}};
+    for (int k = 0; k < d; ++k) cur.n[k] = g.nc[k];
+    const double* src = R;
+    int Pin = d == 1 ? 4 : 16;
+    for (int k = d - 1; k >= 0; --k) {
+        Dims3 nxt = cur;
+        nxt.n[k] = g.m[k];
+        const int Pout = Pin / 4;
+        const int64_t total = (int64_t)nxt.n[0] * nxt.n[1] * nxt.n[2] * Pout;
+        double* target = k == 0 ? wtv : T1;
+        assemble_vec_stage<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(src, target, cur, nxt,
+                                                                            k, Pout, 1, tab);
+        FKGP_HIP(hipGetLastError());
+        cur = nxt;
+        src = target;
+        Pin = Pout;
+    }
+    return FKGP_OK;
+}
+
+fkgp_status ski_w(const GridDev& g, fkgp_dtype in, const void* pay, int64_t n,
+                  const double* gv, const double* v, double s2, double* out, hipStream_t s) {
+    if (n == 0) return FKGP_OK;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (g.d == 1) {
+        if (in == FKGP_F32)
+            ski_interp<float, 1><<<nb, 256, 0, s>>>(static_cast<const float4*>(pay), n, g, gv, v,
+                                                    s2, out);
+        else
+            ski_interp<double, 1><<<nb, 256, 0, s>>>(static_cast<const double4*>(pay), n, g, gv,
+                                                     v, s2, out);
+    } else if (g.d == 2) {
+        if (in == FKGP_F32)
+            ski_interp<float, 2><<<nb, 256, 0, s>>>(static_cast<const float4*>(pay), n, g, gv, v,
+                                                    s2, out);
+        else
+            ski_interp<double, 2><<<nb, 256, 0, s>>>(static_cast<const double4*>(pay), n, g, gv,
+                                                     v, s2, out);
+    } else {
+        set_error("the plain SKI operator covers d <= 2");
+        return FKGP_EINVAL;
+    }
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+fkgp_status ski_y(const GridDev& g, fkgp_dtype in, const void* pay, int64_t n, double* y,
+                  hipStream_t s) {
+    if (n == 0) return FKGP_OK;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (in == FKGP_F32)
+        ski_extract_y<float><<<nb, 256, 0, s>>>(static_cast<const float4*>(pay), n, g.d, y);
+    else
+        ski_extract_y<double><<<nb, 256, 0, s>>>(static_cast<const double4*>(pay), n, g.d, y);
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
 
 fkgp_status run_precompute(const GridDev& g, const void* const* x, const void* y, int64_t n,
                            fkgp_dtype in, fkgp_dtype stats, int nprobe, uint64_t seed,
