@@ -11,6 +11,8 @@ generated on the device before timing.
 value            = n * steps / timed seconds  (Mpts/s through the whole step)
 mll_grad         = differentiation workload: batched FP32 vs plain FP64 path
 batch_mll_grad   = many-problem workload: one persistent launch vs a loop
+ski_sweep        = per-iteration time, factorized CG vs the plain SKI CG in
+                   n-space, on the synthetic sine with m = n, n/16, sqrt(n)
 precompute_*     = n / precompute time
 cg_mvms_per_s    = CG iterations (one operator B each) per second of solve
 roofline         = banded W^T W product (the dominant kernel of the solve),
@@ -53,6 +55,7 @@ def _parse():
     ap.add_argument("--mll-maxiter", type=int, default=20000)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--batch-tol", type=float, default=1e-4)
     ap.add_argument("--batch-maxiter", type=int, default=30000)
     return ap.parse_args()
@@ -215,6 +218,42 @@ def precompute_extra(P, workloads, torch, dev, reps=3):
     return out
 
 
+def ski_sweep(P, workloads, torch, dev, iters=200):
+    """Per-iteration time of the factorized CG (operator on m grid nodes,
+    independent of n) and of the plain SKI CG (n-space, O(n + m log m) per
+    iteration) on the synthetic sine with m = n, n/16 and sqrt(n): the
+    paper's per-iteration comparison (Sec. 5, Fig. 2).  Each solve runs
+    exactly `iters` iterations (tol 0) after a short warm-up; the time per
+    iteration includes each solver's set-up, amortised over the iterations."""
+    cases = [(1024, "n"), (4096, "n"), (8192, "n"), (16384, "n/16"), (65536, "n/16"),
+             (131072, "n/16"), (10_000, "sqrt(n)"), (1_000_000, "sqrt(n)"),
+             (64_000_000, "sqrt(n)")]
+    out = []
+    for n, rule in cases:
+        m = n if rule == "n" else (n // 16 if rule == "n/16" else int(round(math.sqrt(n))))
+        wl = workloads.sine1d_grid(n, m, device=dev)
+        h = P.precompute(wl["grid"], wl["x"], wl["y"], stats_dtype=torch.float64,
+                         keep_points=True)
+        hyp = wl["hypers"]
+        P.solve(h, hyp, tol=0.0, maxiter=5)
+        P.ski_solve(h, hyp, tol=0.0, maxiter=5)
+        rec = {"n": n, "m": m, "rule": rule}
+        for name, fn in (("gsgp", P.solve), ("ski", P.ski_solve)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = fn(h, hyp, tol=0.0, maxiter=iters)
+            torch.cuda.synchronize()
+            rec[f"{name}_us_per_iter"] = (time.perf_counter() - t0) / max(info["iterations"], 1) * 1e6
+        rec["ski_over_gsgp"] = rec["ski_us_per_iter"] / rec["gsgp_us_per_iter"]
+        log(f"sweep n={n} m={m} ({rule}): gsgp {rec['gsgp_us_per_iter']:.1f} us/it, "
+            f"ski {rec['ski_us_per_iter']:.1f} us/it")
+        out.append(rec)
+        h.close()
+        del wl
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -340,6 +379,9 @@ def main():
         bc = batch_compare(P, workloads, torch, dev, args.batch_tol, args.batch_maxiter)
         result["batch_mll_grad_s_per_eval"] = bc["batched_s_per_eval"]
         result["batch_mll_grad"] = bc
+    if not args.no_sweep:
+        torch.cuda.empty_cache()
+        result["ski_sweep"] = ski_sweep(P, workloads, torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cb = cpu_baseline(wl, n, iters_mean, args.cpu_seconds)

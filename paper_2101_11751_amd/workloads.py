@@ -70,6 +70,15 @@ def sine1d(n=10_000, seed=0, device="cpu"):
             "dtype": torch.float64, "tol": 1e-8}
 
 
+def sine1d_grid(n, m, seed=0, device="cpu"):
+    """The synthetic sine data on a padded grid of m nodes over [0, 1] (for
+    per-iteration sweeps over n and m)."""
+    wl = sine1d(n=n, seed=seed, device=device)
+    wl["grid"] = padded_grid([m], 0.0, 1.0)
+    wl["name"] = f"sine1d n={n} m={m}"
+    return wl
+
+
 def bumps2d(n=1_000_000, seed=1, device="cpu", m=(128, 128), nbumps=20):
     g = _gen(seed, device)
     f64 = torch.float64
