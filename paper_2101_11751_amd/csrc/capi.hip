@@ -312,7 +312,12 @@ fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtyp
         unsigned char *lam = nullptr, *tw = nullptr;
         FKGP_HIP(sc.get(&lam, es * sp.L[k]));
         FKGP_HIP(sc.get(&tw, 2 * es * (sp.L[k] / 2)));
-        if (sp.log2L[k] > reg_max) {
+        // four-step lines: beyond the register FFT, and for dimensions with
+        // few lines (e.g. 1-D), where one workgroup of many waves per line
+        // pair beats one or two waves per pair
+        const bool few_lines = reg_max == kMaxRegLog2 && sp.log2L[k] >= kFewLinesMinLog2 &&
+                               h->M / h->g.m[k] <= kFewLines;
+        if (sp.log2L[k] > reg_max || few_lines) {
             int lg2;
             long_split(sp.log2L[k], sp.lg1[k], lg2);
             if (reg_max == kMaxRegLog2) {

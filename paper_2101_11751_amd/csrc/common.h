@@ -221,6 +221,10 @@ fkgp_status run_precompute(const GridDev& g, const void* const* x, const void* y
 // Longest circulant handled by the register-resident line FFT, and by the
 // four-step path (grid dimensions up to 8192 nodes).
 constexpr int kMaxRegLog2 = 11;
+// Dimensions with at most kFewLines lines per vector and circulants of at
+// least 2^kFewLinesMinLog2 points also take the four-step path.
+constexpr int kFewLinesMinLog2 = 10;
+constexpr int64_t kFewLines = 64;
 constexpr int kMaxLineLog2 = 14;
 // Workgroups (each with its own L-point complex scratch) of a four-step pass.
 constexpr int kLongWGs = 256;

@@ -231,16 +231,16 @@ __global__ __launch_bounds__(kLineBlock) void line_conv_split(
 
 // Long lines: one workgroup per line pair at a time (grid-stride over the
 // pairs), four-step convolution through its own L-point scratch.
-template <class T, int LG1, int LG2>
-__global__ __launch_bounds__(kLineBlock) void line_conv_long(
+template <class T, int LG1, int LG2, int BS>
+__global__ __launch_bounds__(BS) void line_conv_long(
     const T* in, T* out, LineGeom lg, const T* __restrict__ lamp,
     const cplx<T>* __restrict__ twh, T scale, const T* addv, T add_coef,
     const int* __restrict__ skip, cplx<T>* __restrict__ scr) {
     constexpr int L1 = 1 << LG1, L2 = 1 << LG2;
     if (skip && *skip) return;
     __shared__ cplx<T> tw1[L1 / 2], tw2[L2 / 2];
-    for (int t = threadIdx.x; t < L1 / 2; t += kLineBlock) tw1[t] = twh[t * L2];
-    for (int t = threadIdx.x; t < L2 / 2; t += kLineBlock) tw2[t] = twh[t * L1];
+    for (int t = threadIdx.x; t < L1 / 2; t += BS) tw1[t] = twh[t * L2];
+    for (int t = threadIdx.x; t < L2 / 2; t += BS) tw2[t] = twh[t * L1];
     __syncthreads();
     cplx<T>* Y = scr + (int64_t)blockIdx.x * (L1 * L2);
     const int64_t npairs = (lg.nlines + 1) / 2;
@@ -280,30 +280,36 @@ fkgp_status launch_line_conv(int log2L, int lg1, const T* in, T* out, const Line
     if (lg1 > 0) {
         int want1, want2;
         long_split(log2L, want1, want2);
-        if (!scr || log2L <= kMaxRegLog2 || lg1 != want1) {
+        if (!scr || log2L < kFewLinesMinLog2 || lg1 != want1) {
             set_error("spectra not laid out for the standalone line FFT");
             return FKGP_EINVAL;
         }
         const int64_t npairs = (lg.nlines + 1) / 2;
         const unsigned grid = (unsigned)std::min<int64_t>(npairs, kLongWGs);
         if (grid == 0) return FKGP_OK;
+        // few pairs: 16 waves per pair (the phases' independent columns and
+        // rows spread over more waves); else 4 waves and more workgroups
+        const bool wide = npairs <= kFewLines;
+#define FKGP_LL(LG, A, B)                                                                      \
+    case LG:                                                                                   \
+        if (wide)                                                                              \
+            line_conv_long<T, A, B, 1024><<<grid, 1024, 0, s>>>(in, out, lg, lam, tw, scale,   \
+                                                                 addv, add_coef, skip, scr);   \
+        else                                                                                   \
+            line_conv_long<T, A, B, kLineBlock><<<grid, kLineBlock, 0, s>>>(                   \
+                in, out, lg, lam, tw, scale, addv, add_coef, skip, scr);                       \
+        break;
         switch (log2L) {
-            case 12:
-                line_conv_long<T, 6, 6><<<grid, kLineBlock, 0, s>>>(in, out, lg, lam, tw, scale,
-                                                                   addv, add_coef, skip, scr);
-                break;
-            case 13:
-                line_conv_long<T, 6, 7><<<grid, kLineBlock, 0, s>>>(in, out, lg, lam, tw, scale,
-                                                                   addv, add_coef, skip, scr);
-                break;
-            case 14:
-                line_conv_long<T, 7, 7><<<grid, kLineBlock, 0, s>>>(in, out, lg, lam, tw, scale,
-                                                                   addv, add_coef, skip, scr);
-                break;
+            FKGP_LL(10, 5, 5)
+            FKGP_LL(11, 5, 6)
+            FKGP_LL(12, 6, 6)
+            FKGP_LL(13, 6, 7)
+            FKGP_LL(14, 7, 7)
             default:
                 set_error("grid dimension too long for the line FFT (at most 8192 nodes)");
                 return FKGP_EINVAL;
         }
+#undef FKGP_LL
         FKGP_HIP(hipGetLastError());
         return FKGP_OK;
     }
