@@ -259,6 +259,20 @@ fkgp_status fkgp_kg_matvec(const fkgp_handle* h, const fkgp_hypers* hyp,
 fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int k,
                             fkgp_dtype xdt, void* stream);
 
+/* Saves the statistics of a handle (W^T W, its block mask, W^T y, y^T y, the
+ * probe sketches, grid and sizes) to the file `path`, so that they are
+ * computed once and reused by later sessions (Sec. 5, "Very large n").  A
+ * fixed header ("FKGPSTAT", version 1) and the arrays in host byte order;
+ * kept points are not saved.  Synchronises `stream`.  FKGP_EINVAL if the file
+ * cannot be written. */
+fkgp_status fkgp_save(const fkgp_handle* h, const char* path, void* stream);
+
+/* A new handle from a file written by fkgp_save (same results as the handle
+ * that was saved).  FKGP_EINVAL if the file is missing, of another kind or
+ * version, truncated or longer than its header says; *out is then NULL.
+ * Synchronises `stream`. */
+fkgp_status fkgp_load(const char* path, void* stream, fkgp_handle** out);
+
 /* The plain SKI posterior mean, as the comparison baseline of the method
  * (Sec. 2.3: each CG iteration applies W K_G W^T + s2 I to an n-vector, so
  * it costs O(n + m log m), where the factorized CG's costs O(m log m)).  CG

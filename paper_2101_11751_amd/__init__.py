@@ -12,6 +12,7 @@ not been built, every entry point raises.
 import ctypes
 import math
 import os
+import struct
 
 import torch
 
@@ -24,8 +25,8 @@ OK, ENOTCONV, EINVAL, EOUTOFGRID, ENOMEM, EDEVICE = 0, 1, -1, -2, -3, -4
 #: every symbol that include/fkgp.h declares
 EXPORTS = ("fkgp_precompute", "fkgp_describe", "fkgp_export_stats", "fkgp_export_sketches",
            "fkgp_solve", "fkgp_mll_and_grad", "fkgp_batch_mll_and_grad", "fkgp_interpolate", "fkgp_apply_B",
-           "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_ski_solve", "fkgp_destroy",
-           "fkgp_last_error")
+           "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_ski_solve", "fkgp_save", "fkgp_load",
+           "fkgp_destroy", "fkgp_last_error")
 
 
 class FkgpError(RuntimeError):
@@ -107,6 +108,8 @@ def load_library():
     L.fkgp_export_sketches.argtypes = [p, p, p]
     L.fkgp_solve.argtypes = [p, ctypes.POINTER(_Hypers), p, p, ctypes.POINTER(_SolveOpts),
                              ctypes.POINTER(_SolveInfo), p]
+    L.fkgp_save.argtypes = [p, ctypes.c_char_p, p]
+    L.fkgp_load.argtypes = [ctypes.c_char_p, p, ctypes.POINTER(ctypes.c_void_p)]
     L.fkgp_ski_solve.argtypes = [p, ctypes.POINTER(_Hypers), ctypes.c_double, ctypes.c_int, p,
                                  ctypes.POINTER(_SolveInfo), p]
     L.fkgp_mll_and_grad.argtypes = [p, ctypes.POINTER(_Hypers), ctypes.POINTER(_MllOpts),
@@ -276,6 +279,29 @@ def solve(h, hypers, rhs=None, tol=1e-6, maxiter=1000, op_precision="f64"):
                              ctypes.byref(info), _stream()))
     return out, {"iterations": info.iterations, "converged": bool(info.converged),
                  "rel_residual": info.rel_residual, "status": st}
+
+
+# header of a statistics file (fkgp_save): magic, version, d, m[3], origin[3],
+# spacing[3], n, stats dtype, probes, probe seed, y^T y, nonzero blocks
+_STATS_HEADER = struct.Struct("<8sIi3q3d3dqiiQdq")
+
+
+def save(h, path):
+    """fkgp_save: write the handle's statistics to `path`."""
+    _check(load_library().fkgp_save(h.ptr, os.fsencode(path), _stream()))
+
+
+def load(path):
+    """fkgp_load: a handle from a file written by save()."""
+    L = load_library()
+    out = ctypes.c_void_p()
+    _check(L.fkgp_load(os.fsencode(path), _stream(), ctypes.byref(out)))
+    with open(path, "rb") as f:
+        hd = _STATS_HEADER.unpack(f.read(_STATS_HEADER.size))
+    d = hd[2]
+    grid = {"d": d, "m": list(hd[3:6])[:d], "origin": list(hd[6:9])[:d],
+            "spacing": list(hd[9:12])[:d]}
+    return Handle(out, grid)
 
 
 def ski_solve(h, hypers, tol=1e-6, maxiter=1000):

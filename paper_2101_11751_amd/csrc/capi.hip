@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -907,6 +908,58 @@ fkgp_status guarded(F&& f) {
     }
 }
 
+// One pool allocation for a handle's arrays: W^T W (row-tiled), W^T y, the
+// sketches, the block mask, then y^T y, the out-of-grid flag and the block
+// count side by side (read back with one copy).
+fkgp_status alloc_handle_arrays(fkgp_handle* h, hipStream_t s) {
+    fkgp::ensure_pool();
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const int64_t M = h->M;
+    const size_t bA = up(dsize(h->dt) * (size_t)dia_elems(M, h->NB));
+    const size_t bW = up(sizeof(double) * M);
+    const size_t bS = up(sizeof(double) * M * h->nprobe);
+    const size_t bK = up(sizeof(uint32_t) * (size_t)mask_words(M));
+    hipError_t e;
+    if ((e = hipMallocAsync(&h->block, bA + bW + bS + bK + 256, s)) != hipSuccess)
+        return hip_fail(e, "hipMallocAsync(handle)");
+    unsigned char* hb = static_cast<unsigned char*>(h->block);
+    h->A = hb;
+    h->wty = reinterpret_cast<double*>(hb + bA);
+    h->sketches = h->nprobe > 0 ? reinterpret_cast<double*>(hb + bA + bW) : nullptr;
+    h->bmask = reinterpret_cast<uint32_t*>(hb + bA + bW + bS);
+    h->yty_dev = reinterpret_cast<double*>(hb + bA + bW + bS + bK);
+    return FKGP_OK;
+}
+
+// File of fkgp_save: this header, then W^T W (row-tiled, stats dtype), the
+// block mask, W^T y and the sketches, in host (little-endian) byte order.
+struct StatsFileHeader {
+    char magic[8];   // "FKGPSTAT"
+    uint32_t version;
+    int32_t d;
+    int64_t m[3];
+    double origin[3];
+    double spacing[3];
+    int64_t n;
+    int32_t stats_dtype;
+    int32_t nprobe;
+    uint64_t seed;
+    double yty;
+    int64_t nzblocks;
+};
+constexpr uint32_t kStatsFileVersion = 1;
+
+struct StatsSections {
+    size_t a, mask, wty, sk;
+    size_t total() const { return a + mask + wty + sk; }
+};
+
+StatsSections stats_sections(const fkgp_handle* h) {
+    return {dsize(h->dt) * (size_t)dia_elems(h->M, h->NB),
+            sizeof(uint32_t) * (size_t)mask_words(h->M), sizeof(double) * (size_t)h->M,
+            sizeof(double) * (size_t)h->M * h->nprobe};
+}
+
 // The handle's arrays come from the device's stream-ordered pool (as all
 // scratch does): freed on the default stream once pending work is done.
 void free_handle(fkgp_handle* h) {
@@ -1002,25 +1055,12 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
             return e;
         };
         hipError_t e;
-        fkgp::ensure_pool();
-        // one allocation: W^T W, W^T y, sketches, then y^T y and the
-        // out-of-grid flag side by side (read back with one copy)
         auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-        const size_t bA = up(dsize(h->dt) * (size_t)dia_elems(M, h->NB));
-        const size_t bW = up(sizeof(double) * M);
-        const size_t bS = up(sizeof(double) * M * h->nprobe);
-        const size_t bK = up(sizeof(uint32_t) * (size_t)mask_words(M));
-        if ((e = hipMallocAsync(&h->block, bA + bW + bS + bK + 256, s)) != hipSuccess)
-            return fail(hip_fail(e, "hipMallocAsync(handle)"));
-        unsigned char* hb = static_cast<unsigned char*>(h->block);
-        h->A = hb;
-        h->wty = reinterpret_cast<double*>(hb + bA);
-        h->sketches = h->nprobe > 0 ? reinterpret_cast<double*>(hb + bA + bW) : nullptr;
-        h->bmask = reinterpret_cast<uint32_t*>(hb + bA + bW + bS);
-        h->yty_dev = reinterpret_cast<double*>(hb + bA + bW + bS + bK);
+        st = alloc_handle_arrays(h, s);
+        if (st != FKGP_OK) return fail(st);
         unsigned long long* bad = reinterpret_cast<unsigned long long*>(h->yty_dev + 1);
         (void)hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), s);
-        (void)hipMemsetAsync(h->bmask, 0, bK, s);
+        (void)hipMemsetAsync(h->bmask, 0, sizeof(uint32_t) * (size_t)mask_words(M), s);
         StatsOut so{h->A, h->wty, h->sketches, h->yty_dev, h->bmask,
                     reinterpret_cast<unsigned long long*>(h->yty_dev + 2), nullptr, nullptr,
                     nullptr};
@@ -1255,6 +1295,147 @@ fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int
         }
         return spmv_dia_any(h->g, h->dt, xdt, h->A, h->bmask, xpad, u, k, dia_halo(h->g), nullptr,
                             static_cast<hipStream_t>(stream));
+    });
+}
+
+fkgp_status fkgp_save(const fkgp_handle* h, const char* path, void* stream) {
+    return guarded([&]() -> fkgp_status {
+        set_error("");
+        if (!h || !path) {
+            set_error("handle and path must be non-NULL");
+            return FKGP_EINVAL;
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        StatsFileHeader hd{};
+        std::memcpy(hd.magic, "FKGPSTAT", 8);
+        hd.version = kStatsFileVersion;
+        hd.d = h->g.d;
+        for (int k = 0; k < h->g.d; ++k) {
+            hd.m[k] = h->g.m[k];
+            hd.origin[k] = h->g.g0[k];
+            hd.spacing[k] = h->g.h[k];
+        }
+        hd.n = h->n;
+        hd.stats_dtype = h->dt;
+        hd.nprobe = h->nprobe;
+        hd.seed = h->seed;
+        hd.yty = h->yty;
+        hd.nzblocks = h->nzblocks;
+        const StatsSections sec = stats_sections(h);
+        std::vector<unsigned char> buf(sec.total());
+        unsigned char* p = buf.data();
+        FKGP_HIP(hipMemcpyAsync(p, h->A, sec.a, hipMemcpyDeviceToHost, s));
+        FKGP_HIP(hipMemcpyAsync(p + sec.a, h->bmask, sec.mask, hipMemcpyDeviceToHost, s));
+        FKGP_HIP(hipMemcpyAsync(p + sec.a + sec.mask, h->wty, sec.wty, hipMemcpyDeviceToHost, s));
+        if (sec.sk)
+            FKGP_HIP(hipMemcpyAsync(p + sec.a + sec.mask + sec.wty, h->sketches, sec.sk,
+                                    hipMemcpyDeviceToHost, s));
+        FKGP_HIP(hipStreamSynchronize(s));
+        FILE* f = std::fopen(path, "wb");
+        if (!f) {
+            set_error(std::string("cannot open ") + path + " for writing");
+            return FKGP_EINVAL;
+        }
+        const bool ok = std::fwrite(&hd, sizeof(hd), 1, f) == 1 &&
+                        (buf.empty() || std::fwrite(buf.data(), buf.size(), 1, f) == 1);
+        const bool closed = std::fclose(f) == 0;
+        if (!ok || !closed) {
+            set_error(std::string("write to ") + path + " failed");
+            return FKGP_EINVAL;
+        }
+        return FKGP_OK;
+    });
+}
+
+fkgp_status fkgp_load(const char* path, void* stream, fkgp_handle** out) {
+    return guarded([&]() -> fkgp_status {
+        set_error("");
+        if (!path || !out) {
+            set_error("path and out must be non-NULL");
+            return FKGP_EINVAL;
+        }
+        *out = nullptr;
+        FILE* f = std::fopen(path, "rb");
+        if (!f) {
+            set_error(std::string("cannot open ") + path);
+            return FKGP_EINVAL;
+        }
+        struct Closer {
+            FILE* f;
+            ~Closer() { std::fclose(f); }
+        } closer{f};
+        StatsFileHeader hd{};
+        if (std::fread(&hd, sizeof(hd), 1, f) != 1 || std::memcmp(hd.magic, "FKGPSTAT", 8) != 0 ||
+            hd.version != kStatsFileVersion) {
+            set_error(std::string(path) + " is not a statistics file of this version");
+            return FKGP_EINVAL;
+        }
+        fkgp_grid gr{};
+        gr.d = hd.d;
+        for (int k = 0; k < 3; ++k) {
+            gr.m[k] = hd.m[k];
+            gr.origin[k] = hd.origin[k];
+            gr.spacing[k] = hd.spacing[k];
+        }
+        GridDev g;
+        int64_t M;
+        fkgp_status st = grid_from_abi(&gr, g, M);
+        if (st != FKGP_OK) return st;
+        if (hd.n < 0 || (hd.stats_dtype != FKGP_F32 && hd.stats_dtype != FKGP_F64) ||
+            hd.nprobe < 0 || hd.nprobe > kMaxProbes || hd.nzblocks < 0) {
+            set_error(std::string(path) + ": corrupt header");
+            return FKGP_EINVAL;
+        }
+        for (int k = 0; k < g.d; ++k)
+            if (circulant_log2(g.m[k]) > kMaxLineLog2) {
+                set_error(std::string(path) + ": grid dimension longer than 8192 nodes");
+                return FKGP_EINVAL;
+            }
+        fkgp_handle* h = new fkgp_handle();
+        auto fail = [&](fkgp_status e) {
+            free_handle(h);
+            return e;
+        };
+        h->g = g;
+        h->n = hd.n;
+        h->M = M;
+        h->NB = 1;
+        for (int k = 0; k < g.d; ++k) h->NB *= 7;
+        h->dt = (fkgp_dtype)hd.stats_dtype;
+        h->nprobe = hd.nprobe;
+        h->seed = hd.seed;
+        h->yty = hd.yty;
+        h->nzblocks = hd.nzblocks;
+        const StatsSections sec = stats_sections(h);
+        std::vector<unsigned char> buf(sec.total());
+        if (!buf.empty() && std::fread(buf.data(), buf.size(), 1, f) != 1) {
+            set_error(std::string(path) + " is truncated");
+            return fail(FKGP_EINVAL);
+        }
+        unsigned char extra;
+        if (std::fread(&extra, 1, 1, f) != 0) {
+            set_error(std::string(path) + " is longer than its header says");
+            return fail(FKGP_EINVAL);
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        st = alloc_handle_arrays(h, s);
+        if (st != FKGP_OK) return fail(st);
+        const unsigned char* p = buf.data();
+        hipError_t e = hipSuccess;
+        auto put = [&](void* dst, const void* src, size_t bytes) {
+            if (e == hipSuccess && bytes)
+                e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+        };
+        put(h->A, p, sec.a);
+        put(h->bmask, p + sec.a, sec.mask);
+        put(h->wty, p + sec.a + sec.mask, sec.wty);
+        put(h->sketches, p + sec.a + sec.mask + sec.wty, sec.sk);
+        const double tail[3] = {hd.yty, 0.0, 0.0};
+        put(h->yty_dev, tail, sizeof(tail));
+        if (e == hipSuccess) e = hipStreamSynchronize(s);   // buf and tail leave scope
+        if (e != hipSuccess) return fail(hip_fail(e, "loading statistics"));
+        *out = h;
+        return FKGP_OK;
     });
 }
 

@@ -73,3 +73,21 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(P, "LIB_PATH", "/nonexistent/libfkgp.so")
     with pytest.raises(ImportError):
         P.load_library()
+
+
+def test_load_rejects_bad_files(tmp_path):
+    """fkgp_load checks the file before touching the device: a missing file,
+    another kind of file and a truncated header give FKGP_EINVAL."""
+    L = P.load_library()
+    out = ctypes.c_void_p()
+    assert L.fkgp_load(str(tmp_path / "missing.bin").encode(), None, ctypes.byref(out)) == P.EINVAL
+    assert out.value is None
+    junk = tmp_path / "junk.bin"
+    junk.write_bytes(b"not a statistics file" * 10)
+    assert L.fkgp_load(str(junk).encode(), None, ctypes.byref(out)) == P.EINVAL
+    assert b"statistics file" in L.fkgp_last_error()
+    short = tmp_path / "short.bin"
+    short.write_bytes(b"FKGPSTAT")
+    assert L.fkgp_load(str(short).encode(), None, ctypes.byref(out)) == P.EINVAL
+    assert L.fkgp_save(None, b"x", None) == P.EINVAL
+    assert P._STATS_HEADER.size == 128
