@@ -15,14 +15,15 @@ __all__ = [
     "B_apply", "solve_mean", "solve_grid_rhs", "fcg_probe", "lanczos_from_cg",
     "logm_e1", "mll_and_grad", "ski_dense_mean", "exact_gp_mean",
     "ski_dense_mll", "ski_dense_grad", "gsgp_mll_fact2", "lanczos_dense",
-    "se_kernel",
+    "se_kernel", "kernel_1d", "kernel_1d_dlog_ell",
 ]
 
 
 # ---------------------------------------------------------------------------
 # Grid and kernel (Sec. 2.3: K_G is the kernel on an equispaced grid, which is
-# multilevel Toeplitz for a stationary kernel; Sec. 5 uses a squared
-# exponential inside a scale kernel).
+# multilevel Toeplitz for a product stationary kernel; Sec. 5 uses a squared
+# exponential inside a scale kernel; the Matern kernels are the other
+# product stationary kernels offered).
 # ---------------------------------------------------------------------------
 def make_grid(m, lo=None, hi=None, origin=None, spacing=None):
     """Grid of prod(m) nodes.  Either explicit origin/spacing, or the padding
@@ -52,22 +53,61 @@ def se_kernel(xa, xb, ell, s):
     return s * np.exp(-0.5 * d2)
 
 
-def toeplitz_column(m, h, ell):
-    """First column of the per-dimension SE Toeplitz factor: exp(-(j h)^2/(2 l^2))."""
-    j = np.arange(m, dtype=np.float64)
-    return np.exp(-0.5 * (j * h / ell) ** 2)
+def kernel_1d(r, kind="se"):
+    """One-dimensional stationary kernel at scaled distance r = |x - x'| / l
+    (K_G is multilevel Toeplitz for a product of such kernels, Sec. 2.3):
+    squared exponential exp(-r^2/2) (Sec. 5), or the Matern kernels of
+    smoothness 1/2, 3/2, 5/2 in their closed forms."""
+    r = np.abs(np.asarray(r, np.float64))
+    if kind == "se":
+        return np.exp(-0.5 * r * r)
+    if kind == "matern12":
+        return np.exp(-r)
+    if kind == "matern32":
+        a = np.sqrt(3.0) * r
+        return (1.0 + a) * np.exp(-a)
+    if kind == "matern52":
+        a = np.sqrt(5.0) * r
+        return (1.0 + a + a * a / 3.0) * np.exp(-a)
+    raise ValueError(kind)
 
 
-def toeplitz_column_dlog_ell(m, h, ell):
-    """d/d(log l) of the column: c_j * (j h / l)^2."""
+def kernel_1d_dlog_ell(r, kind="se"):
+    """d/d(log l) of kernel_1d(|x - x'| / l): since dr/dlog l = -r, it is
+    -r k'(r): r^2 exp(-r^2/2); r exp(-r); 3 r^2 exp(-sqrt3 r);
+    (5/3) r^2 (1 + sqrt5 r) exp(-sqrt5 r)."""
+    r = np.abs(np.asarray(r, np.float64))
+    if kind == "se":
+        return r * r * np.exp(-0.5 * r * r)
+    if kind == "matern12":
+        return r * np.exp(-r)
+    if kind == "matern32":
+        return 3.0 * r * r * np.exp(-np.sqrt(3.0) * r)
+    if kind == "matern52":
+        a = np.sqrt(5.0) * r
+        return (5.0 / 3.0) * r * r * (1.0 + a) * np.exp(-a)
+    raise ValueError(kind)
+
+
+def toeplitz_column(m, h, ell, kind="se"):
+    """First column of the per-dimension Toeplitz factor: k1(j h / l)."""
     j = np.arange(m, dtype=np.float64)
-    r2 = (j * h / ell) ** 2
-    return np.exp(-0.5 * r2) * r2
+    return kernel_1d(j * h / ell, kind)
+
+
+def toeplitz_column_dlog_ell(m, h, ell, kind="se"):
+    """d/d(log l) of the column."""
+    j = np.arange(m, dtype=np.float64)
+    return kernel_1d_dlog_ell(j * h / ell, kind)
 
 
 def _hyp(hypers, d):
     ell = np.broadcast_to(np.asarray(hypers["lengthscale"], float), (d,))
     return ell, float(hypers["outputscale"]), float(hypers["noise"])
+
+
+def _kind(hypers):
+    return hypers.get("kernel", "se")
 
 
 def kg_dense(grid, hypers):
@@ -76,7 +116,8 @@ def kg_dense(grid, hypers):
     ell, s, _ = _hyp(hypers, d)
     K = np.ones((1, 1))
     for k in range(d):
-        T = sla.toeplitz(toeplitz_column(grid["m"][k], grid["spacing"][k], ell[k]))
+        T = sla.toeplitz(toeplitz_column(grid["m"][k], grid["spacing"][k], ell[k],
+                                         _kind(hypers)))
         K = np.kron(K, T)
     return s * K
 
@@ -112,7 +153,8 @@ def kg_matvec(grid, hypers, v):
     """K_G v (v: [..., M]) via per-dimension circulant embeddings."""
     d = grid["d"]
     ell, s, _ = _hyp(hypers, d)
-    cols = [toeplitz_column(grid["m"][k], grid["spacing"][k], ell[k]) for k in range(d)]
+    cols = [toeplitz_column(grid["m"][k], grid["spacing"][k], ell[k], _kind(hypers))
+            for k in range(d)]
     return _kron_apply(grid, cols, v, s)
 
 
@@ -124,9 +166,11 @@ def dkg_matvec(grid, hypers, v, which):
     cols = []
     for k in range(d):
         if k == which:
-            cols.append(toeplitz_column_dlog_ell(grid["m"][k], grid["spacing"][k], ell[k]))
+            cols.append(toeplitz_column_dlog_ell(grid["m"][k], grid["spacing"][k], ell[k],
+                                                 _kind(hypers)))
         else:
-            cols.append(toeplitz_column(grid["m"][k], grid["spacing"][k], ell[k]))
+            cols.append(toeplitz_column(grid["m"][k], grid["spacing"][k], ell[k],
+                                        _kind(hypers)))
     return _kron_apply(grid, cols, v, s)
 
 

@@ -316,7 +316,7 @@ def _fd_grad(f, hyp, d, h=1e-5):
     for th in range(d + 2):
         def shifted(e):
             hp = {"lengthscale": list(hyp["lengthscale"]), "outputscale": hyp["outputscale"],
-                  "noise": hyp["noise"]}
+                  "noise": hyp["noise"], "kernel": hyp.get("kernel", "se")}
             if th < d:
                 hp["lengthscale"][th] *= np.exp(e)
             elif th == d:
@@ -399,3 +399,71 @@ def test_hutchinson_gradient_close_to_exact():
     g_e = oracle.ski_dense_grad(grid, hyp, X, y)
     # loose statistical agreement (64 probes)
     assert np.all(np.abs(g_h - g_e) < 0.25 * np.abs(g_e) + 2.0), (g_h, g_e)
+
+
+# --------------------------------------------------------------------------
+# Other product stationary kernels (Matern 1/2, 3/2, 5/2; Sec. 2.3).
+# --------------------------------------------------------------------------
+MATERN_NU = {"matern12": 0.5, "matern32": 1.5, "matern52": 2.5}
+
+
+@pytest.mark.parametrize("kind", sorted(MATERN_NU))
+def test_matern_closed_forms_match_bessel_definition(kind):
+    """The Matern kernel of smoothness nu, 2^(1-nu)/Gamma(nu) (sqrt(2 nu) r)^nu
+    K_nu(sqrt(2 nu) r) through scipy's modified Bessel function, equals the
+    oracle's closed form (and 1 at r = 0)."""
+    from scipy.special import gamma, kv
+    nu = MATERN_NU[kind]
+    r = np.linspace(1e-3, 6.0, 400)
+    z = np.sqrt(2 * nu) * r
+    ref = 2 ** (1 - nu) / gamma(nu) * z ** nu * kv(nu, z)
+    np.testing.assert_allclose(oracle.kernel_1d(r, kind), ref, rtol=1e-12, atol=1e-15)
+    assert oracle.kernel_1d(0.0, kind) == 1.0
+
+
+@pytest.mark.parametrize("kind", ["se"] + sorted(MATERN_NU))
+def test_kernel_log_lengthscale_derivative(kind):
+    """d/dlog l of k1(|x|/l) by central differences in log l."""
+    x = np.linspace(0.0, 2.0, 101)
+    ell, h = 0.37, 1e-6
+    fd = (oracle.kernel_1d(x / (ell * np.exp(h)), kind)
+          - oracle.kernel_1d(x / (ell * np.exp(-h)), kind)) / (2 * h)
+    np.testing.assert_allclose(oracle.kernel_1d_dlog_ell(x / ell, kind), fd, rtol=1e-6,
+                               atol=1e-10)
+
+
+def test_matern12_grid_precision_is_tridiagonal():
+    """On an equispaced grid the Matern-1/2 (exponential) kernel matrix is
+    rho^|i-j| with rho = exp(-h/l), whose inverse is the tridiagonal AR(1)
+    precision (1/(1-rho^2)) tridiag(-rho, (1, 1+rho^2, ..., 1+rho^2, 1), -rho)."""
+    m, h, ell = 25, 0.05, 0.3
+    grid = oracle.make_grid([m], origin=[0.0], spacing=[h])
+    hyp = {"lengthscale": [ell], "outputscale": 1.0, "noise": 0.1, "kernel": "matern12"}
+    K = oracle.kg_dense(grid, hyp)
+    rho = np.exp(-h / ell)
+    Q = np.diag(np.r_[1.0, np.full(m - 2, 1 + rho * rho), 1.0])
+    Q += np.diag(np.full(m - 1, -rho), 1) + np.diag(np.full(m - 1, -rho), -1)
+    Q /= 1 - rho * rho
+    np.testing.assert_allclose(K @ Q, np.eye(m), atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", sorted(MATERN_NU))
+def test_matern_kg_matvec_and_gradient(kind):
+    """K_G by circulant embedding equals the dense product-kernel matrix on
+    the grid points, and the dense SKI gradient matches finite differences of
+    the dense log likelihood for the Matern kernels."""
+    grid = oracle.make_grid([9, 7], origin=[0.1, -0.2], spacing=[0.07, 0.11])
+    hyp = {"lengthscale": [0.13, 0.2], "outputscale": 1.7, "noise": 0.1, "kernel": kind}
+    coords = np.array(np.meshgrid(*[grid["origin"][k] + grid["spacing"][k] * np.arange(grid["m"][k])
+                                    for k in range(2)], indexing="ij")).reshape(2, -1).T
+    K = hyp["outputscale"] * np.prod(
+        [oracle.kernel_1d(np.abs(coords[:, None, k] - coords[None, :, k]) / hyp["lengthscale"][k],
+                          kind) for k in range(2)], axis=0)
+    np.testing.assert_allclose(oracle.kg_dense(grid, hyp), K, atol=1e-13)
+    v = np.random.default_rng(2).standard_normal(K.shape[0])
+    np.testing.assert_allclose(oracle.kg_matvec(grid, hyp, v), K @ v, atol=1e-12)
+    g2, X, y, h2 = small_problem(7, (7, 6), 120)
+    h2["kernel"] = kind
+    g = oracle.ski_dense_grad(g2, h2, X, y)
+    fd = _fd_grad(lambda hp: oracle.ski_dense_mll(g2, hp, X, y), h2, 2)
+    np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-6)
