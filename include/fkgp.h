@@ -64,14 +64,25 @@ typedef struct {
     double spacing[3];
 } fkgp_grid;
 
-/* Squared-exponential product kernel inside a scale kernel (the kernels of
- * Sec. 5): k(x,x') = outputscale * exp(-1/2 sum_k (x_k-x'_k)^2/l_k^2), and
- * Gaussian noise of standard deviation noise_std (Sec. 2.1), i.e. noise
- * variance noise_std^2 on the diagonal. */
+/* Product of one-dimensional stationary kernels inside a scale kernel,
+ * k(x,x') = outputscale * prod_k k1(|x_k - x'_k| / l_k) (a product stationary
+ * kernel makes K_G multilevel Toeplitz, Sec. 2.3), and Gaussian noise of
+ * standard deviation noise_std (Sec. 2.1), i.e. noise variance noise_std^2
+ * on the diagonal.  k1(r): squared exponential exp(-r^2/2) (the kernel of
+ * Sec. 5), or Matern nu = 1/2, 3/2, 5/2: exp(-r), (1 + sqrt3 r) exp(-sqrt3 r),
+ * (1 + sqrt5 r + 5 r^2/3) exp(-sqrt5 r). */
+typedef enum {
+    FKGP_KERNEL_SE = 0,
+    FKGP_KERNEL_MATERN12 = 1,
+    FKGP_KERNEL_MATERN32 = 2,
+    FKGP_KERNEL_MATERN52 = 3
+} fkgp_kernel;
+
 typedef struct {
     double lengthscale[3];
     double outputscale;
     double noise_std;
+    int kernel;              /* fkgp_kernel */
 } fkgp_hypers;
 
 typedef struct fkgp_handle fkgp_handle;

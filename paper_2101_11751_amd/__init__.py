@@ -46,7 +46,11 @@ class _Grid(ctypes.Structure):
 
 class _Hypers(ctypes.Structure):
     _fields_ = [("lengthscale", ctypes.c_double * 3), ("outputscale", ctypes.c_double),
-                ("noise_std", ctypes.c_double)]
+                ("noise_std", ctypes.c_double), ("kernel", ctypes.c_int)]
+
+
+# fkgp_kernel: the one-dimensional kernel of the product (hypers["kernel"])
+KERNELS = {"se": 0, "matern12": 1, "matern32": 2, "matern52": 3}
 
 
 class _PreOpts(ctypes.Structure):
@@ -172,6 +176,8 @@ def _hyp_struct(hyp, d):
         h.lengthscale[k] = float(ell[k])
     h.outputscale = float(hyp["outputscale"])
     h.noise_std = float(hyp["noise"])
+    kind = hyp.get("kernel", "se")
+    h.kernel = KERNELS[kind] if isinstance(kind, str) else int(kind)
     return h
 
 

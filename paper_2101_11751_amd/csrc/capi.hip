@@ -293,6 +293,10 @@ fkgp_status check_hypers(const fkgp_handle* h, const fkgp_hypers* hyp) {
         set_error("outputscale and noise_std must be positive and finite");
         return FKGP_EINVAL;
     }
+    if (hyp->kernel < FKGP_KERNEL_SE || hyp->kernel > FKGP_KERNEL_MATERN52) {
+        set_error("kernel must be one of the fkgp_kernel values");
+        return FKGP_EINVAL;
+    }
     return FKGP_OK;
 }
 
@@ -327,8 +331,8 @@ fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtyp
                 sp.scr[k] = scr;
             }
         }
-        fkgp_status st = build_spectrum(h->g, k, hyp->lengthscale[k], k == dderiv, dt, lam,
-                                        sp.log2L[k], sp.lg1[k], sc.s);
+        fkgp_status st = build_spectrum(h->g, k, hyp->lengthscale[k], k == dderiv, hyp->kernel,
+                                        dt, lam, sp.log2L[k], sp.lg1[k], sc.s);
         if (st != FKGP_OK) return st;
         st = build_twiddles(sp.log2L[k], dt, tw, sc.s);
         if (st != FKGP_OK) return st;

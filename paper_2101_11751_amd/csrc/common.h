@@ -248,9 +248,9 @@ struct Spectra {
 };
 
 int circulant_log2(int m);
-// Builds lam[k] for dimension k from the SE column (deriv: multiply the
-// column by (j h / l)^2).  Runs on the device (FP64 direct DFT).
-fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv,
+// Builds lam[k] for dimension k from the column of the 1-D kernel `kind`
+// (fkgp_kernel; deriv: its derivative in log l).  Runs on the device (FP64 direct DFT).
+fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv, int kind,
                            fkgp_dtype dt, void* lam, int log2L, int lg1, hipStream_t s);
 fkgp_status build_twiddles(int log2L, fkgp_dtype dt, void* tw, hipStream_t s);
 

@@ -349,10 +349,29 @@ fkgp_status launch_line_conv(int log2L, int lg1, const T* in, T* out, const Line
 // ---------------------------------------------------------------------------
 // Spectra and twiddles (FP64 on the device, cast to the working dtype).
 // ---------------------------------------------------------------------------
-__device__ inline double se_col(int j, double h, double ell, bool deriv) {
+// One-dimensional kernel at lag j (r = j h / l) or, with deriv, its
+// derivative in log l (r dk/dlog l = -r dk/dr).
+__device__ inline double kernel_col(int kind, int j, double h, double ell, bool deriv) {
     const double r = (double)j * h / ell;
-    const double c = exp(-0.5 * r * r);
-    return deriv ? c * r * r : c;
+    switch (kind) {
+        case FKGP_KERNEL_MATERN12: {
+            const double e = exp(-r);
+            return deriv ? r * e : e;
+        }
+        case FKGP_KERNEL_MATERN32: {
+            const double a = sqrt(3.0) * r, e = exp(-a);
+            return deriv ? 3.0 * r * r * e : (1.0 + a) * e;
+        }
+        case FKGP_KERNEL_MATERN52: {
+            const double a = sqrt(5.0) * r, e = exp(-a);
+            return deriv ? (5.0 / 3.0) * r * r * (1.0 + a) * e
+                         : (1.0 + a + (5.0 / 3.0) * r * r) * e;
+        }
+        default: {
+            const double c = exp(-0.5 * r * r);
+            return deriv ? c * r * r : c;
+        }
+    }
 }
 
 __device__ inline unsigned bitrev(unsigned v, int bits) {
@@ -365,7 +384,7 @@ __device__ inline unsigned bitrev(unsigned v, int bits) {
 // else 0 (symmetric, so the DFT is real).
 template <class T>
 __global__ void spectrum_kernel(T* __restrict__ lam_br, int log2L, int lg1, int m, double h,
-                                double ell, bool deriv) {
+                                double ell, bool deriv, int kind) {
     const int L = 1 << log2L;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= L) return;
@@ -377,12 +396,12 @@ __global__ void spectrum_kernel(T* __restrict__ lam_br, int log2L, int lg1, int 
     } else {
         f = bitrev((unsigned)e, log2L);
     }
-    double acc = se_col(0, h, ell, deriv);
+    double acc = kernel_col(kind, 0, h, ell, deriv);
     for (int j = 1; j < m; ++j) {
         if (L - j < j) break;
         const unsigned long long ph = ((unsigned long long)j * f) & (unsigned long long)(L - 1);
         const double c = cospi(2.0 * (double)ph / (double)L);
-        const double v = se_col(j, h, ell, deriv);
+        const double v = kernel_col(kind, j, h, ell, deriv);
         acc += (L - j == j) ? v * c : 2.0 * v * c;
     }
     lam_br[e] = (T)(acc / (double)L);
@@ -711,16 +730,16 @@ int circulant_log2(int m) {
     return l;
 }
 
-fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv, fkgp_dtype dt,
-                           void* lam, int log2L, int lg1, hipStream_t s) {
+fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv, int kind,
+                           fkgp_dtype dt, void* lam, int log2L, int lg1, hipStream_t s) {
     const int L = 1 << log2L;
     const unsigned grid = (unsigned)((L + 255) / 256);
     if (dt == FKGP_F32)
         spectrum_kernel<float><<<grid, 256, 0, s>>>(static_cast<float*>(lam), log2L, lg1,
-                                                    g.m[k], g.h[k], ell, deriv);
+                                                    g.m[k], g.h[k], ell, deriv, kind);
     else
         spectrum_kernel<double><<<grid, 256, 0, s>>>(static_cast<double*>(lam), log2L, lg1,
-                                                     g.m[k], g.h[k], ell, deriv);
+                                                     g.m[k], g.h[k], ell, deriv, kind);
     FKGP_HIP(hipGetLastError());
     return FKGP_OK;
 }
