@@ -270,6 +270,21 @@ fkgp_status fkgp_kg_matvec(const fkgp_handle* h, const fkgp_hypers* hyp,
 fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int k,
                             fkgp_dtype xdt, void* stream);
 
+/* fkgp_precompute from points in host memory (x: d host pointers, y: host
+ * pointer, dtype `in`), for data sets larger than one transfer or device
+ * copy (Sec. 5, "Very large n").  n > chunk: the points stream in chunks of
+ * `chunk` points (0: 2^24): each chunk is copied into pinned staging memory
+ * and sent to the device on a second stream while the previous chunk is
+ * sorted and reduced; the per-cell moments of the chunks are summed in chunk
+ * order (deterministic; equal to the one-shot statistics up to the order of
+ * the per-cell sums), then assembled once.  n <= chunk: one copy and the
+ * one-shot precompute.  n_probes and keep_points must be 0.  Out-of-grid
+ * points are reported with their global index.  Synchronises `stream`. */
+fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x,
+                                 const void* y, int64_t n, fkgp_dtype in,
+                                 const fkgp_precompute_opts* opts, int64_t chunk,
+                                 void* stream, fkgp_handle** out);
+
 /* Saves the statistics of a handle (W^T W, its block mask, W^T y, y^T y, the
  * probe sketches, grid and sizes) to the file `path`, so that they are
  * computed once and reused by later sessions (Sec. 5, "Very large n").  A

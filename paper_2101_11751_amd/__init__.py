@@ -14,6 +14,7 @@ import math
 import os
 import struct
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -26,7 +27,7 @@ OK, ENOTCONV, EINVAL, EOUTOFGRID, ENOMEM, EDEVICE = 0, 1, -1, -2, -3, -4
 EXPORTS = ("fkgp_precompute", "fkgp_describe", "fkgp_export_stats", "fkgp_export_sketches",
            "fkgp_solve", "fkgp_mll_and_grad", "fkgp_batch_mll_and_grad", "fkgp_interpolate", "fkgp_apply_B",
            "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_ski_solve", "fkgp_save", "fkgp_load",
-           "fkgp_destroy", "fkgp_last_error")
+           "fkgp_precompute_host", "fkgp_destroy", "fkgp_last_error")
 
 
 class FkgpError(RuntimeError):
@@ -112,6 +113,9 @@ def load_library():
     L.fkgp_export_sketches.argtypes = [p, p, p]
     L.fkgp_solve.argtypes = [p, ctypes.POINTER(_Hypers), p, p, ctypes.POINTER(_SolveOpts),
                              ctypes.POINTER(_SolveInfo), p]
+    L.fkgp_precompute_host.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(p), p,
+                                       ctypes.c_int64, ctypes.c_int, ctypes.POINTER(_PreOpts),
+                                       ctypes.c_int64, p, ctypes.POINTER(p)]
     L.fkgp_save.argtypes = [p, ctypes.c_char_p, p]
     L.fkgp_load.argtypes = [ctypes.c_char_p, p, ctypes.POINTER(ctypes.c_void_p)]
     L.fkgp_ski_solve.argtypes = [p, ctypes.POINTER(_Hypers), ctypes.c_double, ctypes.c_int, p,
@@ -245,6 +249,27 @@ def precompute(grid, x, y, stats_dtype=torch.float32, n_probes=0, probe_seed=0,
     out = ctypes.c_void_p()
     _check(L.fkgp_precompute(ctypes.byref(g), arr, _ptr(y), n, dt, ctypes.byref(o), _stream(),
                              ctypes.byref(out)))
+    return Handle(out, grid)
+
+
+def precompute_host(grid, x, y, stats_dtype=torch.float32, chunk=0):
+    """fkgp_precompute_host: x is a list of d host arrays (numpy or CPU
+    tensors, float32 or float64), y a host array of the same dtype; the
+    points stream to the device in chunks of `chunk` points (0: 2^24)."""
+    L = load_library()
+    d = int(grid["d"])
+    xs = [np.ascontiguousarray(t.numpy() if isinstance(t, torch.Tensor) else t) for t in x]
+    yv = np.ascontiguousarray(y.numpy() if isinstance(y, torch.Tensor) else y)
+    n = yv.shape[0]
+    for t in xs:
+        assert t.dtype == yv.dtype and t.shape == (n,)
+    dt = F32 if yv.dtype == np.float32 else F64
+    arr = (ctypes.c_void_p * 3)(*([t.ctypes.data for t in xs] + [0] * (3 - d)))
+    g = _grid_struct(grid)
+    o = _PreOpts(_dtype_code(stats_dtype), 0, 0, 0)
+    out = ctypes.c_void_p()
+    _check(L.fkgp_precompute_host(ctypes.byref(g), arr, yv.ctypes.data, n, dt, ctypes.byref(o),
+                                  int(chunk), _stream(), ctypes.byref(out)))
     return Handle(out, grid)
 
 

@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -1299,6 +1300,225 @@ fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int
         }
         return spmv_dia_any(h->g, h->dt, xdt, h->A, h->bmask, xpad, u, k, dia_halo(h->g), nullptr,
                             static_cast<hipStream_t>(stream));
+    });
+}
+
+}  // extern "C"
+
+namespace {
+
+// Host copy into pinned staging on several threads (one thread moves only a
+// few GB/s from pageable memory).
+void parallel_copy(unsigned char* dst, const unsigned char* src, size_t bytes) {
+    const size_t kMinPiece = size_t(4) << 20;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>(std::min<size_t>(hw, 16), (bytes + kMinPiece - 1) / kMinPiece);
+    if (nt <= 1) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t piece = (bytes + nt - 1) / nt;
+    std::vector<std::thread> ts;
+    for (size_t t = 1; t < nt; ++t) {
+        const size_t b = t * piece, e = std::min(bytes, b + piece);
+        if (b < e) ts.emplace_back([=] { std::memcpy(dst + b, src + b, e - b); });
+    }
+    std::memcpy(dst, src, std::min(bytes, piece));
+    for (auto& t : ts) t.join();
+}
+
+}  // namespace
+
+extern "C" {
+
+fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, const void* y,
+                                 int64_t n, fkgp_dtype in, const fkgp_precompute_opts* opts,
+                                 int64_t chunk, void* stream, fkgp_handle** out) {
+    return guarded([&]() -> fkgp_status {
+        set_error("");
+        if (!out) {
+            set_error("out is NULL");
+            return FKGP_EINVAL;
+        }
+        *out = nullptr;
+        GridDev g;
+        int64_t M;
+        fkgp_status st = grid_from_abi(grid, g, M);
+        if (st != FKGP_OK) return st;
+        if (n < 0 || n >= (int64_t(1) << 40)) {
+            set_error("n must be in [0, 2^40)");
+            return FKGP_EINVAL;
+        }
+        if (in != FKGP_F32 && in != FKGP_F64) {
+            set_error("input dtype must be FKGP_F32 or FKGP_F64");
+            return FKGP_EINVAL;
+        }
+        if (n > 0) {
+            if (!x || !y) {
+                set_error("x and y must be non-NULL when n > 0");
+                return FKGP_EINVAL;
+            }
+            for (int k = 0; k < g.d; ++k)
+                if (!x[k]) {
+                    set_error("x[k] is NULL");
+                    return FKGP_EINVAL;
+                }
+        }
+        fkgp_precompute_opts o{FKGP_F32, 0, 0, 0};
+        if (opts) o = *opts;
+        if (o.stats_dtype != FKGP_F32 && o.stats_dtype != FKGP_F64) {
+            set_error("stats dtype must be FKGP_F32 or FKGP_F64");
+            return FKGP_EINVAL;
+        }
+        if (o.n_probes != 0 || o.keep_points != 0) {
+            set_error("the streamed precompute builds no probe sketches and keeps no points");
+            return FKGP_EINVAL;
+        }
+        if (chunk == 0) chunk = int64_t(1) << 24;
+        if (chunk < 1 || chunk >= (int64_t(1) << 31) - 1) {
+            set_error("chunk must be in [1, 2^31 - 1) points (0: 2^24)");
+            return FKGP_EINVAL;
+        }
+        for (int k = 0; k < g.d; ++k)
+            if (circulant_log2(g.m[k]) > kMaxLineLog2) {
+                set_error("grid dimension longer than 8192 nodes is not supported");
+                return FKGP_EINVAL;
+            }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        fkgp_handle* h = new fkgp_handle();
+        h->g = g;
+        h->n = n;
+        h->M = M;
+        h->NB = 1;
+        for (int k = 0; k < g.d; ++k) h->NB *= 7;
+        h->dt = o.stats_dtype;
+        // resources of the stream: released on every exit path
+        const size_t es = in == FKGP_F32 ? 4 : 8;
+        const int nplanes = g.d + 1;
+        const int64_t cpts = std::min<int64_t>(chunk, std::max<int64_t>(n, 1));
+        struct Res {
+            unsigned char* pinned[2] = {nullptr, nullptr};
+            unsigned char* devbuf = nullptr;
+            double* acc = nullptr;
+            hipStream_t cs = nullptr;
+            hipEvent_t copied[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
+            hipStream_t s = nullptr;
+            ~Res() {
+                (void)hipStreamSynchronize(s);
+                if (cs) (void)hipStreamSynchronize(cs);
+                for (int i = 0; i < 2; ++i) {
+                    if (pinned[i]) (void)hipHostFree(pinned[i]);
+                    if (copied[i]) (void)hipEventDestroy(copied[i]);
+                    if (used[i]) (void)hipEventDestroy(used[i]);
+                }
+                if (devbuf) (void)hipFreeAsync(devbuf, s);
+                if (acc) (void)hipFreeAsync(acc, s);
+                if (cs) (void)hipStreamDestroy(cs);
+                (void)hipStreamSynchronize(s);
+            }
+        } res;
+        res.s = s;
+        auto fail = [&](fkgp_status e) {
+            free_handle(h);
+            return e;
+        };
+        hipError_t e;
+        st = alloc_handle_arrays(h, s);
+        if (st != FKGP_OK) return fail(st);
+        unsigned long long* bad = reinterpret_cast<unsigned long long*>(h->yty_dev + 1);
+        (void)hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), s);
+        (void)hipMemsetAsync(h->bmask, 0, sizeof(uint32_t) * (size_t)mask_words(M), s);
+        StatsOut so{h->A, h->wty, h->sketches, h->yty_dev, h->bmask,
+                    reinterpret_cast<unsigned long long*>(h->yty_dev + 2), nullptr, nullptr,
+                    nullptr};
+        if (n <= chunk) {   // one piece: the one-shot precompute from a device copy
+            if ((e = hipMallocAsync(&res.devbuf, es * nplanes * (size_t)cpts, s)) != hipSuccess)
+                return fail(hip_fail(e, "hipMallocAsync(points)"));
+            const void* xd[3] = {nullptr, nullptr, nullptr};
+            for (int k = 0; k < nplanes && n > 0; ++k) {
+                const void* src = k < g.d ? x[k] : y;
+                if ((e = hipMemcpyAsync(res.devbuf + es * k * (size_t)cpts, src, es * (size_t)n,
+                                        hipMemcpyHostToDevice, s)) != hipSuccess)
+                    return fail(hip_fail(e, "hipMemcpyAsync(points)"));
+                if (k < g.d) xd[k] = res.devbuf + es * k * (size_t)cpts;
+            }
+            st = run_precompute(g, xd, res.devbuf + es * g.d * (size_t)cpts, n, in, h->dt, 0, 0,
+                                so, bad, s);
+        } else {
+            int64_t ncells = 1;
+            for (int k = 0; k < g.d; ++k) ncells *= g.nc[k];
+            int NR = 1;
+            for (int k = 0; k < g.d; ++k) NR *= 4;
+            const size_t nacc = (size_t)ncells * (h->NB + NR + 1);
+            if ((e = hipMallocAsync(&res.acc, sizeof(double) * nacc, s)) != hipSuccess ||
+                (e = hipMallocAsync(&res.devbuf, 2 * es * nplanes * (size_t)cpts, s)) != hipSuccess)
+                return fail(hip_fail(e, "hipMallocAsync(chunk buffers)"));
+            for (int i = 0; i < 2; ++i)
+                if ((e = hipHostMalloc(&res.pinned[i], es * nplanes * (size_t)cpts,
+                                       hipHostMallocDefault)) != hipSuccess ||
+                    (e = hipEventCreateWithFlags(&res.copied[i], hipEventDisableTiming)) !=
+                        hipSuccess ||
+                    (e = hipEventCreateWithFlags(&res.used[i], hipEventDisableTiming)) != hipSuccess)
+                    return fail(hip_fail(e, "chunk staging"));
+            if ((e = hipStreamCreateWithFlags(&res.cs, hipStreamNonBlocking)) != hipSuccess)
+                return fail(hip_fail(e, "hipStreamCreateWithFlags"));
+            ChunkCtl cc{res.acc, res.acc + (size_t)ncells * h->NB,
+                        res.acc + (size_t)ncells * (h->NB + NR), 1, 0, 0};
+            const int64_t nchunks = (n + chunk - 1) / chunk;
+            for (int64_t c = 0; c < nchunks && st == FKGP_OK; ++c) {
+                const int slot = (int)(c & 1);
+                const int64_t base = c * chunk;
+                const int64_t cn = std::min(chunk, n - base);
+                // the slot's previous chunk has left the staging and device buffers
+                if (c >= 2 && (e = hipEventSynchronize(res.used[slot])) != hipSuccess)
+                    return fail(hip_fail(e, "hipEventSynchronize"));
+                unsigned char* pin = res.pinned[slot];
+                unsigned char* dev = res.devbuf + (size_t)slot * es * nplanes * cpts;
+                for (int k = 0; k < nplanes; ++k) {
+                    const unsigned char* src =
+                        static_cast<const unsigned char*>(k < g.d ? x[k] : y) + es * base;
+                    parallel_copy(pin + es * k * (size_t)cpts, src, es * (size_t)cn);
+                }
+                for (int k = 0; k < nplanes; ++k)
+                    if ((e = hipMemcpyAsync(dev + es * k * (size_t)cpts, pin + es * k * (size_t)cpts,
+                                            es * (size_t)cn, hipMemcpyHostToDevice, res.cs)) !=
+                        hipSuccess)
+                        return fail(hip_fail(e, "hipMemcpyAsync(chunk)"));
+                if ((e = hipEventRecord(res.copied[slot], res.cs)) != hipSuccess ||
+                    (e = hipStreamWaitEvent(s, res.copied[slot], 0)) != hipSuccess)
+                    return fail(hip_fail(e, "chunk ordering"));
+                const void* xd[3] = {nullptr, nullptr, nullptr};
+                for (int k = 0; k < g.d; ++k) xd[k] = dev + es * k * (size_t)cpts;
+                cc.first = c == 0 ? 1 : 0;
+                cc.last = c == nchunks - 1 ? 1 : 0;
+                cc.idx_base = base;
+                st = run_precompute(g, xd, dev + es * g.d * (size_t)cpts, cn, in, h->dt, 0, 0, so,
+                                    bad, s, &cc);
+                if (st == FKGP_OK && (e = hipEventRecord(res.used[slot], s)) != hipSuccess)
+                    return fail(hip_fail(e, "hipEventRecord"));
+            }
+        }
+        unsigned long long hbad = ~0ull;
+        double back[3] = {0.0, 0.0, 0.0};
+        if (st == FKGP_OK) {
+            if ((e = hipMemcpyAsync(back, h->yty_dev, sizeof(back), hipMemcpyDeviceToHost, s)) !=
+                hipSuccess)
+                st = hip_fail(e, "hipMemcpyAsync(y^T y, flag)");
+        }
+        if ((e = hipStreamSynchronize(s)) != hipSuccess && st == FKGP_OK)
+            st = hip_fail(e, "hipStreamSynchronize");
+        if (st != FKGP_OK) return fail(st);
+        h->yty = back[0];
+        std::memcpy(&hbad, &back[1], sizeof(hbad));
+        unsigned long long nzb = 0;
+        std::memcpy(&nzb, &back[2], sizeof(nzb));
+        h->nzblocks = (int64_t)nzb;
+        if (hbad != ~0ull) {
+            set_error("point " + std::to_string(hbad) + " lies outside the interpolable region");
+            return fail(FKGP_EOUTOFGRID);
+        }
+        *out = h;
+        return FKGP_OK;
     });
 }
 

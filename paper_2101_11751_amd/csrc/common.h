@@ -212,10 +212,23 @@ fkgp_status ski_w(const GridDev& g, fkgp_dtype in, const void* pay, int64_t n,
 fkgp_status ski_y(const GridDev& g, fkgp_dtype in, const void* pay, int64_t n, double* y,
                   hipStream_t s);
 
+// One chunk of a streamed precompute: the chunk's per-cell moments are added
+// to the running totals (first: copied); only the last chunk assembles the
+// statistics (from the totals).  idx_base: global index of the chunk's first
+// point (out-of-grid reports).
+struct ChunkCtl {
+    double* acc_w;    // [ncells * 7^d]
+    double* acc_r;    // [ncells * 4^d]
+    double* acc_yy;   // [ncells]
+    int first, last;
+    int64_t idx_base;
+};
+
 fkgp_status run_precompute(const GridDev& g, const void* const* x, const void* y,
                            int64_t n, fkgp_dtype in, fkgp_dtype stats,
                            int nprobe, uint64_t seed, const StatsOut& out,
-                           unsigned long long* bad_dev, hipStream_t s);
+                           unsigned long long* bad_dev, hipStream_t s,
+                           const ChunkCtl* cc = nullptr);
 
 // ---- operators (ops.hip) -------------------------------------------------
 // Longest circulant handled by the register-resident line FFT, and by the

@@ -129,7 +129,7 @@ template <class Tin>
 __global__ __launch_bounds__(kBlock) void keys_and_counts(
     Coords<Tin> xs, int64_t n, GridDev g, uint32_t* __restrict__ keys,
     uint32_t* __restrict__ counts, int ntiles, int shift, int bits,
-    unsigned long long* bad) {
+    unsigned long long* bad, int64_t idx_base) {
     extern __shared__ uint32_t hist[];
     const int nd = 1 << bits;
     for (int i = threadIdx.x; i < nd; i += kBlock) hist[i] = 0;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void keys_and_counts(
     const int64_t end = min(n, base + tile_size<Tin>());
     for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
         uint32_t key;
-        if (!cell_of<Tin>(g, xs.p, i, key)) atomicMin(bad, (unsigned long long)i);
+        if (!cell_of<Tin>(g, xs.p, i, key)) atomicMin(bad, (unsigned long long)(idx_base + i));
         keys[i] = key;
         atomicAdd(&hist[(key >> shift) & (nd - 1)], 1u);
     }
@@ -868,10 +868,20 @@ struct Carver {
     }
 };
 
+// Element-wise acc (+)= v (chunked precompute: moments of the chunks summed
+// in chunk order).
+__global__ void add_moments(double* __restrict__ acc, const double* __restrict__ v, int64_t n,
+                            int first) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        acc[i] = first ? v[i] : acc[i] + v[i];
+}
+
 template <class Tin>
 fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void* yv,
                              int64_t n, fkgp_dtype stats, int nprobe, uint64_t seed,
-                             const StatsOut& out, unsigned long long* bad, hipStream_t s) {
+                             const StatsOut& out, unsigned long long* bad, hipStream_t s,
+                             const ChunkCtl* cc) {
     using P = typename PayloadOf<Tin>::type;
     const int d = g.d;
     int64_t ncells = 1, M = 1;
@@ -960,7 +970,7 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         uint32_t* sums = c.take<uint32_t>((ncount + kScanChunk - 1) / kScanChunk + 1);
 
         keys_and_counts<Tin><<<ntiles, kBlock, sizeof(uint32_t) << dbits[0], s>>>(
-            xs, n, g, ka, counts, ntiles, dshift[0], dbits[0], bad);
+            xs, n, g, ka, counts, ntiles, dshift[0], dbits[0], bad, cc ? cc->idx_base : 0);
         FKGP_HIP(hipGetLastError());
         uint32_t* kin = ka;
         uint32_t* kout = kb;
@@ -1014,6 +1024,23 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         FKGP_HIP(hipMemsetAsync(Mw, 0, sizeof(double) * ncells * NB, s));
         FKGP_HIP(hipMemsetAsync(Mr, 0, sizeof(double) * ncells * NR * nr, s));
         FKGP_HIP(hipMemsetAsync(Myy, 0, sizeof(double) * ncells, s));
+    }
+    if (cc) {   // one chunk of a streamed precompute: fold its moments in
+        const int64_t nm[3] = {ncells * NB, ncells * NR * nr, ncells};
+        double* acc[3] = {cc->acc_w, cc->acc_r, cc->acc_yy};
+        const double* loc[3] = {Mw, Mr, Myy};
+        for (int i = 0; i < 3; ++i) {
+            const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nm[i] + 255) / 256, 4096));
+            add_moments<<<nb, 256, 0, s>>>(acc[i], loc[i], nm[i], cc->first ? 1 : 0);
+            FKGP_HIP(hipGetLastError());
+        }
+        if (!cc->last) {
+            FKGP_HIP(hipFreeAsync(block, s));
+            return FKGP_OK;
+        }
+        Mw = cc->acc_w;   // the assembly reads the totals
+        Mr = cc->acc_r;
+        Myy = cc->acc_yy;
     }
 
     const KeysTables tab = make_tables();
@@ -1290,10 +1317,11 @@ fkgp_status ski_y(const GridDev& g, fkgp_dtype in, const void* pay, int64_t n, d
 
 fkgp_status run_precompute(const GridDev& g, const void* const* x, const void* y, int64_t n,
                            fkgp_dtype in, fkgp_dtype stats, int nprobe, uint64_t seed,
-                           const StatsOut& out, unsigned long long* bad, hipStream_t s) {
+                           const StatsOut& out, unsigned long long* bad, hipStream_t s,
+                           const ChunkCtl* cc) {
     if (in == FKGP_F32)
-        return precompute_typed<float>(g, x, y, n, stats, nprobe, seed, out, bad, s);
-    return precompute_typed<double>(g, x, y, n, stats, nprobe, seed, out, bad, s);
+        return precompute_typed<float>(g, x, y, n, stats, nprobe, seed, out, bad, s, cc);
+    return precompute_typed<double>(g, x, y, n, stats, nprobe, seed, out, bad, s, cc);
 }
 
 }  // namespace fkgp
