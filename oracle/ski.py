@@ -15,7 +15,7 @@ __all__ = [
     "B_apply", "solve_mean", "solve_grid_rhs", "fcg_probe", "lanczos_from_cg",
     "logm_e1", "mll_and_grad", "ski_dense_mean", "exact_gp_mean",
     "ski_dense_mll", "ski_dense_grad", "gsgp_mll_fact2", "lanczos_dense",
-    "se_kernel", "kernel_1d", "kernel_1d_dlog_ell",
+    "se_kernel", "kernel_1d", "kernel_1d_dlog_ell", "ski_dense_cov",
 ]
 
 
@@ -468,6 +468,19 @@ def ski_dense_mean(grid, hypers, x, y):
     A = W @ KG @ W.T + sig * sig * np.eye(W.shape[0])
     z = sla.cho_solve(sla.cho_factor(A), np.asarray(y, float))
     return KG @ (W.T @ z), z, W
+
+
+def ski_dense_cov(grid, hypers, x, xq):
+    """Posterior covariance of the SKI model (Def. 2) between query points
+    xq [d, nq], covariance form: Wq K_G Wq^T - Wq K_G W^T A^{-1} W K_G Wq^T
+    with A = W K_G W^T + sigma^2 I (dense, small n)."""
+    _, _, sig = _hyp(hypers, grid["d"])
+    W = dense_w(grid, x)
+    Wq = dense_w(grid, xq)
+    KG = kg_dense(grid, hypers)
+    A = W @ KG @ W.T + sig * sig * np.eye(W.shape[0])
+    B = W @ KG @ Wq.T
+    return Wq @ KG @ Wq.T - B.T @ sla.cho_solve(sla.cho_factor(A), B)
 
 
 def ski_dense_mll(grid, hypers, x, y):

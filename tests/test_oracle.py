@@ -467,3 +467,22 @@ def test_matern_kg_matvec_and_gradient(kind):
     g = oracle.ski_dense_grad(g2, h2, X, y)
     fd = _fd_grad(lambda hp: oracle.ski_dense_mll(g2, hp, X, y), h2, 2)
     np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-6)
+
+
+def test_ski_posterior_covariance_information_form():
+    """SKI as Bayesian linear regression on the grid values (f_G ~ N(0, K_G),
+    y = W f_G + noise): the posterior covariance of f_G is
+    (K_G^{-1} + W^T W / sigma^2)^{-1}, so the covariance between query points
+    is Wq (K_G^{-1} + W^T W / sigma^2)^{-1} Wq^T; the oracle's covariance form
+    (Woodbury) must agree, and the matrix is symmetric positive definite."""
+    grid, X, y, hyp = small_problem(8, (9, 8), 200)
+    rng = np.random.default_rng(9)
+    Xq = rand_points(rng, grid, 12)
+    C = oracle.ski_dense_cov(grid, hyp, X, Xq)
+    W = oracle.dense_w(grid, X)
+    Wq = oracle.dense_w(grid, Xq)
+    KG = oracle.kg_dense(grid, hyp)
+    S = np.linalg.inv(np.linalg.inv(KG) + W.T @ W / hyp["noise"] ** 2)
+    np.testing.assert_allclose(C, Wq @ S @ Wq.T, rtol=1e-7, atol=1e-10)
+    np.testing.assert_allclose(C, C.T, atol=1e-12)
+    assert np.linalg.eigvalsh(C).min() > 0
