@@ -57,6 +57,7 @@ def _parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cov", action="store_true")
     ap.add_argument("--batch-tol", type=float, default=1e-4)
     ap.add_argument("--batch-maxiter", type=int, default=30000)
     return ap.parse_args()
@@ -276,6 +277,37 @@ def ski_sweep(P, workloads, torch, dev, iters=200):
     return out
 
 
+def cov_leg(P, workloads, torch, dev, nq=691, tol=1e-4, maxiter=5000):
+    """Exact SKI posterior covariance between nq query points (one solve per
+    query point; Sec. 5 computes a 691 x 691 matrix on the sound data, n =
+    59.3K) on the synthetic sine of the same size, for a small and a large
+    grid: seconds per call after a warm-up."""
+    out = []
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    xq = torch.rand(nq, generator=g, device=dev, dtype=torch.float64)
+    for m in (8000, 60000):
+        wl = workloads.sine1d_grid(59_300, m, device=dev)
+        h = P.precompute(wl["grid"], wl["x"], wl["y"], stats_dtype=torch.float64)
+        hyp = wl["hypers"]
+        P.posterior_cov(h, hyp, [xq[:64]], tol=tol, maxiter=maxiter)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        C, info = P.posterior_cov(h, hyp, [xq], tol=tol, maxiter=maxiter)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        rec = {"n": 59_300, "m": m, "nq": nq, "tol": tol, "s": t,
+               "iterations_max": info["iterations"], "converged": info["converged"],
+               "min_diag": float(C.diagonal().min())}
+        log(f"posterior covariance {nq}x{nq}, m={m}: {t*1e3:.1f} ms, "
+            f"{info['iterations']} iterations")
+        out.append(rec)
+        h.close()
+        del wl, C
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -405,6 +437,9 @@ def main():
     if not args.no_sweep:
         torch.cuda.empty_cache()
         result["ski_sweep"] = ski_sweep(P, workloads, torch, dev)
+    if not args.no_cov:
+        torch.cuda.empty_cache()
+        result["posterior_cov"] = cov_leg(P, workloads, torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cb = cpu_baseline(wl, n, iters_mean, args.cpu_seconds)

@@ -247,6 +247,30 @@ fkgp_status fkgp_interpolate(const fkgp_handle* h, const double* mean_grid,
                              const void* const* xq, int64_t nq, fkgp_dtype in,
                              double* out, void* stream);
 
+/* Posterior covariance of the SKI model between nq query points (the
+ * covariance expression of SKI inference, Def. 2; by Fact 2
+ * and Claim 5 it is also w_x^T C w_x' with C the posterior covariance of the
+ * grid values):
+ *   cov = Wq K_G Wq^T - Wq K_G W^T (W K_G W^T + s2 I)^{-1} W K_G Wq^T.
+ * Column j of K_G Wq^T is the grid vector v_j = K_G w_{xq_j}; each
+ * right-hand side b_j = W v_j is solved by the factorized CG from x_0 = 0,
+ * which needs only W^T b_j = W^T W v_j and ||b_j||^2 = v_j^T W^T W v_j, so
+ * the cost is independent of n (batches of 64 right-hand sides, one W^T W
+ * read per iteration for the batch).  Then
+ * cov[i][j] = w_i^T v_j - v_i^T W^T A^{-1} b_j, returned symmetrised
+ * ((c_ij + c_ji)/2, FP64, fixed-order sums).  Each solve stops at
+ * ||r|| <= tol ||b_j||.  xq: d device pointers of dtype `in`; cov: device
+ * doubles [nq][nq], row-major; 1 <= nq <= 4096, FKGP_EINVAL otherwise.
+ * Device memory: about 3 nq m doubles plus the solver's workspace for 64
+ * right-hand sides.  FKGP_EOUTOFGRID if a query point is not interpolable;
+ * FKGP_ENOTCONV if a solve reached maxiter (cov still written); info
+ * (optional): the most iterations of any solve, and the largest relative
+ * residual.  Synchronises `stream`. */
+fkgp_status fkgp_posterior_cov(const fkgp_handle* h, const fkgp_hypers* hyp,
+                               const void* const* xq, int64_t nq, fkgp_dtype in,
+                               double tol, int maxiter, double* cov,
+                               fkgp_solve_info* info, void* stream);
+
 /* Operator-level entry points (for tests and benchmarks).
  * fkgp_apply_B: for k right-hand sides stored as [k][m] in the handle's stats
  * dtype, v = (K_G W^T W + s2 I) x and u = W^T W x (the operator B of the

@@ -25,7 +25,8 @@ OK, ENOTCONV, EINVAL, EOUTOFGRID, ENOMEM, EDEVICE = 0, 1, -1, -2, -3, -4
 
 #: every symbol that include/fkgp.h declares
 EXPORTS = ("fkgp_precompute", "fkgp_describe", "fkgp_export_stats", "fkgp_export_sketches",
-           "fkgp_solve", "fkgp_mll_and_grad", "fkgp_batch_mll_and_grad", "fkgp_interpolate", "fkgp_apply_B",
+           "fkgp_solve", "fkgp_mll_and_grad", "fkgp_batch_mll_and_grad", "fkgp_interpolate",
+           "fkgp_posterior_cov", "fkgp_apply_B",
            "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_ski_solve", "fkgp_save", "fkgp_load",
            "fkgp_precompute_host", "fkgp_destroy", "fkgp_last_error")
 
@@ -129,6 +130,9 @@ def load_library():
                                           ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(_MllInfo), p]
     L.fkgp_interpolate.argtypes = [p, p, ctypes.POINTER(p), ctypes.c_int64, ctypes.c_int, p, p]
+    L.fkgp_posterior_cov.argtypes = [p, ctypes.POINTER(_Hypers), ctypes.POINTER(p), ctypes.c_int64,
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_int, p,
+                                     ctypes.POINTER(_SolveInfo), p]
     L.fkgp_apply_B.argtypes = [p, ctypes.POINTER(_Hypers), p, p, p, ctypes.c_int, p]
     L.fkgp_kg_matvec.argtypes = [p, ctypes.POINTER(_Hypers), p, p, ctypes.c_int, p]
     L.fkgp_wtw_matvec.argtypes = [p, p, p, ctypes.c_int, ctypes.c_int, p]
@@ -357,6 +361,23 @@ def interpolate(h, mean_grid, xq):
     _check(L.fkgp_interpolate(h.ptr, _ptr(mean_grid.contiguous()), arr, nq,
                               _dtype_code(xs[0].dtype), _ptr(out), _stream()))
     return out
+
+
+def posterior_cov(h, hypers, xq, tol=1e-8, maxiter=1000):
+    """fkgp_posterior_cov: SKI posterior covariance [nq, nq] (float64) between
+    the query points xq (d device tensors of nq coordinates); returns
+    (cov, info dict)."""
+    L = load_library()
+    xs = [t.contiguous() for t in xq]
+    nq = xs[0].numel()
+    out = torch.empty(nq, nq, dtype=torch.float64, device=xs[0].device)
+    arr = (ctypes.c_void_p * 3)(*([t.data_ptr() for t in xs] + [0] * (3 - len(xs))))
+    info = _SolveInfo()
+    st = _check(L.fkgp_posterior_cov(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)), arr, nq,
+                                     _dtype_code(xs[0].dtype), float(tol), int(maxiter),
+                                     _ptr(out), ctypes.byref(info), _stream()))
+    return out, {"iterations": info.iterations, "converged": bool(info.converged),
+                 "rel_residual": info.rel_residual, "status": st}
 
 
 def apply_B(h, hypers, x):

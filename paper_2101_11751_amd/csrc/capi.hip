@@ -1710,15 +1710,20 @@ void fkgp_destroy(fkgp_handle* h) {
 namespace fkgp {
 namespace {
 
-__global__ void probe_init(PState* ps, int N, double n, double tol) {
+// Right-hand side j: ||b||^2 = bb[j] when given (grid right-hand sides
+// b = W v), else n (a Rademacher probe).
+__global__ void probe_init(PState* ps, int N, double n, double tol,
+                           const double* __restrict__ bb) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
+    const double b2 = bb ? bb[j] : n;
     PState s{};
-    s.rho = n;
+    s.bb = b2;
+    s.rho = b2;
     s.cr = 1.0;
     s.cp = 1.0;
-    s.eps = tol * tol * n;
-    s.done = n > 0 ? 0 : 1;
+    s.eps = tol * tol * b2;
+    s.done = b2 > 0 ? 0 : 1;
     ps[j] = s;
 }
 
@@ -1774,7 +1779,7 @@ __device__ inline void sum_pairs(const double* partials, int j, int nbv, double*
 // alpha = rho / <p, A p> (Claim 4), scalar updates of x and r.
 __global__ __launch_bounds__(kRedBlock) void probe_fin_ap(PState* ps,
                                                           const double* __restrict__ partials,
-                                                          int nbv, double s2, double n,
+                                                          int nbv, double s2,
                                                           double* __restrict__ alphas) {
     const int j = blockIdx.x;
     if (ps[j].done) return;
@@ -1784,7 +1789,7 @@ __global__ __launch_bounds__(kRedBlock) void probe_fin_ap(PState* ps,
     if (threadIdx.x != 0) return;
     PState s = ps[j];
     const double apc = s2 * s.cp;
-    const double pap = d1 + apc * s.pb + s.cp * d2 + s.cp * apc * n;
+    const double pap = d1 + apc * s.pb + s.cp * d2 + s.cp * apc * s.bb;
     const double alpha = s.rho / pap;
     if (!isfinite(alpha)) {
         ps[j].done = 2;
@@ -1844,7 +1849,7 @@ __global__ __launch_bounds__(kRedBlock) void probe_dot_r(const PState* __restric
 // vector parts are updated by the next probe_ap).
 __global__ __launch_bounds__(kRedBlock) void probe_fin_r(PState* ps,
                                                          const double* __restrict__ partials,
-                                                         int nbv, double n,
+                                                         int nbv,
                                                          double* __restrict__ betas) {
     const int j = blockIdx.x;
     if (ps[j].done) return;
@@ -1853,7 +1858,7 @@ __global__ __launch_bounds__(kRedBlock) void probe_fin_r(PState* ps,
     sum_pairs(partials, j, nbv, sh, d1, d2);
     if (threadIdx.x != 0) return;
     PState s = ps[j];
-    const double rho_new = d1 + 2.0 * s.cr * d2 + s.cr * s.cr * n;
+    const double rho_new = d1 + 2.0 * s.cr * d2 + s.cr * s.cr * s.bb;
     s.iters += 1;
     if (!(rho_new > s.eps)) {
         s.done = 1;
@@ -1991,11 +1996,14 @@ fkgp_status dots_dev(const double* A, const double* B, int64_t M, int k, double*
     return FKGP_OK;
 }
 
-// Factorized CG from x_0 = 0 for N probes at once (sketches bh [N][M]).
-// Outputs W^T x_j (wx [N][M]), the CG coefficients and the final states.
+// Factorized CG from x_0 = 0 for N right-hand sides b_j at once, given
+// b_hat_j = W^T b_j (bh [N][M]) and ||b_j||^2 (bb_dev [N] on the device; null:
+// Rademacher probes, ||z_j||^2 = n).  Outputs W^T x_j (wx [N][M]), the CG
+// coefficients and the final states.
 fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double tol,
                      int maxiter, double* wx, double* alphas, double* betas, PState* ps,
-                     Scratch& sc, hipStream_t st, int& iters_max) {
+                     Scratch& sc, hipStream_t st, int& iters_max,
+                     const double* bb_dev = nullptr) {
     const fkgp_handle* h = c.h;
     const int64_t M = c.M;
     const int64_t ldx = M + 2 * c.halo;
@@ -2017,7 +2025,7 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
     // kappa_b = K_G W^T z_j (FP64)
     fkgp_status rs = kg_apply(h->g, c.sp64, FKGP_F64, bh, kb, N, c.so, nullptr, 0.0, nullptr, st);
     if (rs != FKGP_OK) return rs;
-    probe_init<<<(N + 63) / 64, 64, 0, st>>>(ps, N, n, tol);
+    probe_init<<<(N + 63) / 64, 64, 0, st>>>(ps, N, n, tol, bb_dev);
     FKGP_HIP(hipGetLastError());
     const dim3 gv(nbv, N);
     const dim3 ge((unsigned)std::min<int64_t>((M + 255) / 256, 1024), N);
@@ -2033,7 +2041,7 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
         const int nit = std::min(kBatch, maxiter - launched);
         for (int it = 0; it < nit; ++it) {
             probe_ap<<<gv, kRedBlock, 0, st>>>(ps, zp, kb, sp, bh, ur, vr, ap, M, partials);
-            probe_fin_ap<<<N, kRedBlock, 0, st>>>(ps, partials, nbv, c.s2, n, alphas);
+            probe_fin_ap<<<N, kRedBlock, 0, st>>>(ps, partials, nbv, c.s2, alphas);
             probe_upd_r<<<ge, 256, 0, st>>>(ps, ux, sp, rh, ap, rpad, M, ldx, c.halo);
             FKGP_HIP(hipGetLastError());
             rs = spmv_dia_any(h->g, h->dt, FKGP_F64, h->A, h->bmask, rpad, ur, N, c.halo, nullptr, st);
@@ -2041,7 +2049,7 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
             rs = kg_apply(h->g, c.sp64, FKGP_F64, ur, vr, N, c.so, rh, c.s2, nullptr, st);
             if (rs != FKGP_OK) return rs;
             probe_dot_r<<<gv, kRedBlock, 0, st>>>(ps, rh, ur, bh, M, partials);
-            probe_fin_r<<<N, kRedBlock, 0, st>>>(ps, partials, nbv, n, betas);
+            probe_fin_r<<<N, kRedBlock, 0, st>>>(ps, partials, nbv, betas);
             FKGP_HIP(hipGetLastError());
         }
         launched += nit;
@@ -2442,6 +2450,176 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
     return res;
 }
 
+// ---------------------------------------------------------------------------
+// Posterior covariance between query points (Def. 2 model):
+//   cov = Wq K_G Wq^T - Wq K_G W^T A^{-1} W K_G Wq^T,  A = W K_G W^T + s2 I.
+// Column j of K_G Wq^T is v_j = K_G g_j (g_j: weights of query point j), so
+// the data-side right-hand side is b_j = W v_j, with W^T b_j = W^T W v_j and
+// ||b_j||^2 = v_j . W^T W v_j; the factorized CG from x_0 = 0 returns
+// W^T A^{-1} b_j, and
+//   cov[i][j] = g_i . v_j - v_i . (W^T A^{-1} b_j).
+// Everything is FP64 on the device; n enters only through W^T W.
+// ---------------------------------------------------------------------------
+constexpr int kCovMaxQ = 4096;  // query points per call
+constexpr int kCovRhs = 64;     // right-hand sides per batched CG
+constexpr int kCovTile = 64;    // query points per side of a pair tile
+constexpr int kCovChunk = 16;
+constexpr int kCovPairs = kCovTile * kCovTile / 256;  // pairs per thread
+
+// For the tile (rows i0.., columns j0..) of the pair matrix: partial sums of
+// g_i . v_j - v_i . x_j over the grid chunks of this block (chunk c goes to
+// block c mod gridDim.x, in increasing order).
+// partials[(tile * gridDim.x + block) * kCovTile^2 + a * kCovTile + b].
+__global__ __launch_bounds__(256) void cov_partial(const double* __restrict__ G,
+                                                   const double* __restrict__ V,
+                                                   const double* __restrict__ X, int64_t M,
+                                                   int nq, double* __restrict__ partials) {
+    __shared__ double sG[kCovTile][kCovChunk + 1];
+    __shared__ double sVi[kCovTile][kCovChunk + 1];
+    __shared__ double sVj[kCovTile][kCovChunk + 1];
+    __shared__ double sX[kCovTile][kCovChunk + 1];
+    const int i0 = blockIdx.y * kCovTile, j0 = blockIdx.z * kCovTile;
+    const int ni = min(kCovTile, nq - i0), nj = min(kCovTile, nq - j0);
+    double acc[kCovPairs];
+#pragma unroll
+    for (int r = 0; r < kCovPairs; ++r) acc[r] = 0.0;
+    const int64_t nchunk = (M + kCovChunk - 1) / kCovChunk;
+    for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        const int64_t k0 = ch * kCovChunk;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kCovTile * kCovChunk; e += 256) {
+            const int a = e / kCovChunk, kk = e % kCovChunk;
+            const int64_t k = k0 + kk;
+            const bool oki = k < M && a < ni, okj = k < M && a < nj;
+            const int64_t oi = (int64_t)(i0 + a) * M + k, oj = (int64_t)(j0 + a) * M + k;
+            sG[a][kk] = oki ? G[oi] : 0.0;
+            sVi[a][kk] = oki ? V[oi] : 0.0;
+            sVj[a][kk] = okj ? V[oj] : 0.0;
+            sX[a][kk] = okj ? X[oj] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kCovPairs; ++r) {
+            const int p = threadIdx.x + 256 * r;
+            const int a = p / kCovTile, b = p % kCovTile;
+            double t = 0.0;
+#pragma unroll 8
+            for (int kk = 0; kk < kCovChunk; ++kk)
+                t = fma(sG[a][kk], sVj[b][kk], fma(-sVi[a][kk], sX[b][kk], t));
+            acc[r] += t;
+        }
+    }
+    const int tile = blockIdx.y * gridDim.z + blockIdx.z;
+    double* out = partials + ((int64_t)tile * gridDim.x + blockIdx.x) * (kCovTile * kCovTile);
+#pragma unroll
+    for (int r = 0; r < kCovPairs; ++r) out[threadIdx.x + 256 * r] = acc[r];
+}
+
+// cov[i][j] = symmetric part of the summed partials (fixed order).
+__global__ void cov_fin(const double* __restrict__ partials, int nb, int nq, int nt,
+                        double* __restrict__ cov) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)nq * nq) return;
+    const int i = (int)(p / nq), j = (int)(p % nq);
+    auto sum = [&](int r, int c) {
+        const int tile = (r / kCovTile) * nt + c / kCovTile;
+        const double* q = partials + (int64_t)tile * nb * (kCovTile * kCovTile) +
+                          (r % kCovTile) * kCovTile + c % kCovTile;
+        double a = 0.0;
+        for (int k = 0; k < nb; ++k) a += q[(int64_t)k * (kCovTile * kCovTile)];
+        return a;
+    };
+    cov[p] = 0.5 * (sum(i, j) + sum(j, i));
+}
+
+fkgp_status posterior_cov_impl(const fkgp_handle* h, const fkgp_hypers* hyp,
+                               const void* const* xq, int64_t nq64, fkgp_dtype in, double tol,
+                               int maxiter, double* cov, fkgp_solve_info* info,
+                               hipStream_t st) {
+    Scratch sc(st);
+    OpCtx c;
+    fkgp_status rs = make_ctx(h, hyp, FKGP_F64, c, sc);
+    if (rs != FKGP_OK) return rs;
+    const int nq = (int)nq64;
+    const int64_t M = h->M;
+    const int64_t ldx = M + 2 * c.halo;
+    double *G, *V, *WX;
+    unsigned long long* bad;
+    FKGP_HIP(sc.get(&G, M * nq));
+    FKGP_HIP(sc.get(&V, M * nq));
+    FKGP_HIP(sc.get(&WX, M * nq));
+    FKGP_HIP(sc.get(&bad, 1));
+    FKGP_HIP(hipMemsetAsync(G, 0, sizeof(double) * M * nq, st));
+    FKGP_HIP(hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), st));
+    rs = query_weights(h->g, xq, nq, in, G, bad, st);
+    if (rs != FKGP_OK) return rs;
+    unsigned long long hbad = ~0ull;
+    FKGP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipStreamSynchronize(st));
+    if (hbad != ~0ull) {
+        set_error("query point " + std::to_string(hbad) + " lies outside the interpolable region");
+        return FKGP_EOUTOFGRID;
+    }
+    int iters_max = 0;
+    double rel = 0.0;
+    bool conv = true;
+    for (int q0 = 0; q0 < nq; q0 += kCovRhs) {
+        const int nr = std::min(kCovRhs, nq - q0);
+        Scratch sj(st);
+        double *Vpad, *BH, *bb, *alphas, *betas, *dotp;
+        PState* ps;
+        FKGP_HIP(sj.get(&Vpad, ldx * nr));
+        FKGP_HIP(sj.get(&BH, M * nr));
+        FKGP_HIP(sj.get(&bb, nr));
+        FKGP_HIP(sj.get(&alphas, (size_t)kMaxLanczos * nr));
+        FKGP_HIP(sj.get(&betas, (size_t)kMaxLanczos * nr));
+        FKGP_HIP(sj.get(&dotp, (size_t)vec_blocks(M) * nr));
+        FKGP_HIP(sj.get(&ps, nr));
+        double* Vq = V + (int64_t)q0 * M;
+        // v_j = K_G g_j, b_hat_j = W^T W v_j, ||b_j||^2 = v_j . b_hat_j
+        rs = kg_apply(h->g, c.sp64, FKGP_F64, G + (int64_t)q0 * M, Vq, nr, c.so, nullptr, 0.0,
+                      nullptr, st);
+        if (rs != FKGP_OK) return rs;
+        FKGP_HIP(hipMemsetAsync(Vpad, 0, sizeof(double) * ldx * nr, st));
+        FKGP_HIP(hipMemcpy2DAsync(Vpad + c.halo, sizeof(double) * ldx, Vq, sizeof(double) * M,
+                                  sizeof(double) * M, nr, hipMemcpyDeviceToDevice, st));
+        rs = spmv_dia_any(h->g, h->dt, FKGP_F64, h->A, h->bmask, Vpad, BH, nr, c.halo, nullptr,
+                          st);
+        if (rs != FKGP_OK) return rs;
+        rs = dots_dev(Vq, BH, M, nr, dotp, bb, st);
+        if (rs != FKGP_OK) return rs;
+        int it = 0;
+        const fkgp_status cres = probe_cg(c, BH, nr, (double)h->n, tol, maxiter,
+                                          WX + (int64_t)q0 * M, alphas, betas, ps, sj, st, it, bb);
+        if (cres != FKGP_OK && cres != FKGP_ENOTCONV) return cres;
+        conv &= cres == FKGP_OK;
+        iters_max = std::max(iters_max, it);
+        std::vector<PState> hs(nr);
+        FKGP_HIP(hipMemcpyAsync(hs.data(), ps, sizeof(PState) * nr, hipMemcpyDeviceToHost, st));
+        FKGP_HIP(hipStreamSynchronize(st));
+        for (int j = 0; j < nr; ++j)
+            if (hs[j].bb > 0) rel = std::max(rel, std::sqrt(std::max(hs[j].rho, 0.0) / hs[j].bb));
+    }
+    const int nt = (nq + kCovTile - 1) / kCovTile;
+    const int64_t nchunk = (M + kCovChunk - 1) / kCovChunk;
+    // about 2048 blocks in all, 8 to 256 per tile, at most one per chunk
+    const int64_t per_tile = std::min<int64_t>(256, std::max<int64_t>(8, 2048 / ((int64_t)nt * nt)));
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(nchunk, per_tile));
+    double* partials;
+    FKGP_HIP(sc.get(&partials, (size_t)nt * nt * nb * kCovTile * kCovTile));
+    cov_partial<<<dim3(nb, nt, nt), 256, 0, st>>>(G, V, WX, M, nq, partials);
+    const int64_t P = (int64_t)nq * nq;
+    cov_fin<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(partials, nb, nq, nt, cov);
+    FKGP_HIP(hipGetLastError());
+    FKGP_HIP(hipStreamSynchronize(st));
+    if (info) {
+        info->iterations = iters_max;
+        info->converged = conv ? 1 : 0;
+        info->rel_residual = rel;
+    }
+    return conv ? FKGP_OK : FKGP_ENOTCONV;
+}
+
 }  // namespace
 }  // namespace fkgp
 
@@ -2472,6 +2650,40 @@ extern "C" fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers
             return FKGP_EINVAL;
         }
         return fkgp::mll_impl(h, hyp, o, mll, grad, info, static_cast<hipStream_t>(stream));
+    });
+}
+
+extern "C" fkgp_status fkgp_posterior_cov(const fkgp_handle* h, const fkgp_hypers* hyp,
+                                          const void* const* xq, int64_t nq, fkgp_dtype in,
+                                          double tol, int maxiter, double* cov,
+                                          fkgp_solve_info* info, void* stream) {
+    return guarded([&]() -> fkgp_status {
+        fkgp::set_error("");
+        if (!h || !xq || !cov) {
+            fkgp::set_error("handle, xq and cov must be non-NULL");
+            return FKGP_EINVAL;
+        }
+        fkgp_status st = fkgp::check_hypers(h, hyp);
+        if (st != FKGP_OK) return st;
+        if (nq < 1 || nq > fkgp::kCovMaxQ) {
+            fkgp::set_error("nq must be in [1, 4096]");
+            return FKGP_EINVAL;
+        }
+        if (in != FKGP_F32 && in != FKGP_F64) {
+            fkgp::set_error("unknown point dtype");
+            return FKGP_EINVAL;
+        }
+        for (int k = 0; k < h->g.d; ++k)
+            if (!xq[k]) {
+                fkgp::set_error("xq[k] is NULL");
+                return FKGP_EINVAL;
+            }
+        if (!(tol >= 0.0) || maxiter < 1) {
+            fkgp::set_error("tol must be >= 0 and maxiter >= 1");
+            return FKGP_EINVAL;
+        }
+        return fkgp::posterior_cov_impl(h, hyp, xq, nq, in, tol, maxiter, cov, info,
+                                        static_cast<hipStream_t>(stream));
     });
 }
 

@@ -309,6 +309,10 @@ int64_t dia_halo(const GridDev& g);
 // Upper bound on the dot partials spmv_dia_any writes (one per row tile).
 int64_t spmv_dot_parts(const GridDev& g);
 
+// G[i] (M doubles each, zeroed by the caller) = interpolation weights of
+// query point i on the grid; out-of-grid points set *bad (min index).
+fkgp_status query_weights(const GridDev& g, const void* const* xq, int64_t nq, fkgp_dtype in,
+                          double* G, unsigned long long* bad, hipStream_t s);
 fkgp_status interpolate_points(const GridDev& g, const double* mu,
                                const void* const* xq, int64_t nq,
                                fkgp_dtype in, double* out,
@@ -324,6 +328,7 @@ constexpr int kBatchRegMaxLog2 = 8;
 // State of one factorized CG from x_0 = 0 (r = W r_hat + c_r b, ...).
 struct PState {
     double rho, cr, cp, cx, pb, alpha, beta, eps;
+    double bb;   // ||b||^2 of the right-hand side b (n for a probe)
     int done, iters;
 };
 

@@ -703,6 +703,47 @@ __global__ void interp_kernel(GridDev g, const double* __restrict__ mu, const Ti
     out[i] = acc;
 }
 
+// Interpolation weights of query point i as a grid vector: G[i][node] =
+// w_i(node) for its 4^d stencil nodes (G zeroed by the caller).
+template <class Tin>
+__global__ void weights_kernel(GridDev g, const Tin* x0, const Tin* x1, const Tin* x2,
+                               int64_t nq, int64_t M, double* __restrict__ G,
+                               unsigned long long* bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const Tin* xs[3] = {x0, x1, x2};
+    int base[3] = {1, 1, 1};
+    double w[3][4] = {{0, 1, 0, 0}, {0, 1, 0, 0}, {0, 1, 0, 0}};
+    for (int k = 0; k < g.d; ++k) {
+        const double u = ((double)xs[k][i] - g.g0[k]) / g.h[k];
+        if (!(u >= 1.0 && u <= (double)(g.m[k] - 2))) {
+            atomicMin(bad, (unsigned long long)i);
+            return;
+        }
+        int b = (int)floor(u);
+        if (b > g.m[k] - 3) b = g.m[k] - 3;
+        base[k] = b;
+        keys4(u - (double)b, w[k]);
+    }
+    const int e1 = g.d > 1 ? 4 : 1, e2 = g.d > 2 ? 4 : 1;
+    double* Gi = G + i * M;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < e1; ++b)
+            for (int c = 0; c < e2; ++c) {
+                int64_t j = base[0] - 1 + a;
+                double wt = w[0][a];
+                if (g.d > 1) {
+                    j = j * g.m[1] + (base[1] - 1 + b);
+                    wt *= w[1][b];
+                }
+                if (g.d > 2) {
+                    j = j * g.m[2] + (base[2] - 1 + c);
+                    wt *= w[2][c];
+                }
+                Gi[j] = wt;
+            }
+}
+
 template <class T>
 __global__ void dia_to_canonical_kernel(const T* __restrict__ A, T* __restrict__ out,
                                         int64_t M, int NB) {
@@ -1060,6 +1101,25 @@ fkgp_status interpolate_points(const GridDev& g, const double* mu, const void* c
         const double* p[3] = {nullptr, nullptr, nullptr};
         for (int k = 0; k < g.d; ++k) p[k] = static_cast<const double*>(xq[k]);
         interp_kernel<double><<<grid, 256, 0, s>>>(g, mu, p[0], p[1], p[2], nq, out, bad);
+    }
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+fkgp_status query_weights(const GridDev& g, const void* const* xq, int64_t nq, fkgp_dtype in,
+                          double* G, unsigned long long* bad, hipStream_t s) {
+    if (nq == 0) return FKGP_OK;
+    int64_t M = 1;
+    for (int i = 0; i < g.d; ++i) M *= g.m[i];
+    const unsigned grid = (unsigned)((nq + 255) / 256);
+    if (in == FKGP_F32) {
+        const float* p[3] = {nullptr, nullptr, nullptr};
+        for (int k = 0; k < g.d; ++k) p[k] = static_cast<const float*>(xq[k]);
+        weights_kernel<float><<<grid, 256, 0, s>>>(g, p[0], p[1], p[2], nq, M, G, bad);
+    } else {
+        const double* p[3] = {nullptr, nullptr, nullptr};
+        for (int k = 0; k < g.d; ++k) p[k] = static_cast<const double*>(xq[k]);
+        weights_kernel<double><<<grid, 256, 0, s>>>(g, p[0], p[1], p[2], nq, M, G, bad);
     }
     FKGP_HIP(hipGetLastError());
     return FKGP_OK;
