@@ -15,7 +15,7 @@ __all__ = [
     "B_apply", "solve_mean", "solve_grid_rhs", "fcg_probe", "lanczos_from_cg",
     "logm_e1", "mll_and_grad", "ski_dense_mean", "exact_gp_mean",
     "ski_dense_mll", "ski_dense_grad", "gsgp_mll_fact2", "lanczos_dense",
-    "se_kernel", "kernel_1d", "kernel_1d_dlog_ell", "ski_dense_cov",
+    "se_kernel", "kernel_1d", "kernel_1d_dlog_ell", "ski_dense_cov", "efla", "love_cov",
 ]
 
 
@@ -481,6 +481,83 @@ def ski_dense_cov(grid, hypers, x, xq):
     A = W @ KG @ W.T + sig * sig * np.eye(W.shape[0])
     B = W @ KG @ Wq.T
     return Wq @ KG @ Wq.T - B.T @ sla.cho_solve(sla.cho_factor(A), B)
+
+
+def efla(grid, hypers, wtw, bhat, bb, k, reorth=2, tol_break=1e-10):
+    """Lanczos with full reorthogonalisation on A = W K_G W^T + sigma^2 I from
+    b / ||b||, in the factorized form of the appendix (FLA and EFLA, Algs. 6
+    and 7): the i-th Lanczos vector is Q_i = W qh_i + d_i b, kept as the pair
+    (qh_i, d_i) together with p_i = W^T W qh_i and s_i = (K_G W^T W +
+    sigma^2 I) qh_i.  Then A Q_i = W (s_i + d_i K_G bhat) + sigma^2 d_i b, and
+    the n-space inner product of two pairs needs only p, bhat = W^T b and
+    ||b||^2 = bb:
+        <(a, ca), (e, ce)> = p_a . e + ca (bhat . e) + ce (bhat . a) + ca ce bb.
+    One operator B per step, applied to the new vector after it has been
+    orthogonalised (`reorth` classical Gram-Schmidt passes against all earlier
+    vectors).  Stops early when beta_{i+1} <= tol_break * max |alpha| (the
+    Krylov space is exhausted).
+    Returns (alpha [kk], beta [kk-1], Qh [kk, M], P [kk, M], d [kk])."""
+    _, _, sig = _hyp(hypers, grid["d"])
+    s2 = sig * sig
+    bhat = np.asarray(bhat, np.float64)
+    M = bhat.shape[0]
+    kb = kg_matvec(grid, hypers, bhat)
+    Qh = np.zeros((k, M))
+    P = np.zeros((k, M))
+    d = np.zeros(k)
+    d[0] = 1.0 / np.sqrt(bb)
+    s_cur = np.zeros(M)
+    al = np.zeros(k)
+    be = np.zeros(k)
+    kk = k
+
+    def inner(a, ca, pa, e, ce):
+        return float(pa @ e + ca * (bhat @ e) + ce * (bhat @ a) + ca * ce * bb)
+
+    for i in range(k):
+        # w = A Q_i - beta_i Q_{i-1}
+        wq = s_cur + d[i] * kb
+        wc = s2 * d[i]
+        if i > 0:
+            wq = wq - be[i - 1] * Qh[i - 1]
+            wc -= be[i - 1] * d[i - 1]
+        al[i] = inner(Qh[i], d[i], P[i], wq, wc)
+        if i == k - 1:
+            break
+        wq = wq - al[i] * Qh[i]
+        wc -= al[i] * d[i]
+        for _ in range(reorth):
+            lam = (P[:i + 1] @ wq + d[:i + 1] * (bhat @ wq) + wc * (Qh[:i + 1] @ bhat)
+                   + d[:i + 1] * wc * bb)
+            wq = wq - lam @ Qh[:i + 1]
+            wc -= float(lam @ d[:i + 1])
+        v, u = B_apply(grid, hypers, wtw, wq)
+        b2 = float(u @ wq + 2.0 * wc * (bhat @ wq) + wc * wc * bb)
+        beta = np.sqrt(max(b2, 0.0))
+        if beta <= tol_break * np.max(np.abs(al[:i + 1])):
+            kk = i + 1
+            break
+        be[i] = beta
+        Qh[i + 1] = wq / beta
+        d[i + 1] = wc / beta
+        P[i + 1] = u / beta
+        s_cur = v / beta
+    return al[:kk], be[:kk - 1], Qh[:kk], P[:kk], d[:kk]
+
+
+def love_cov(grid, hypers, wtw, wty, yty, xq, k):
+    """Rank-k posterior covariance between query points xq [d, nq] from the
+    factorized Lanczos decomposition A ~ Q T Q^T started at y (the low-rank
+    covariance of Sec. 5): with u_j(x) = <Q_j, W K_G w_x> = (p_j + d_j W^T y)
+    . (K_G w_x),
+        cov(x, x') ~ w_x^T K_G w_x' - u(x)^T T^{-1} u(x').
+    Exact when the Krylov space holds every W K_G w_x (k large enough)."""
+    al, be, Qh, P, d = efla(grid, hypers, wtw, wty, yty, k)
+    T = np.diag(al) + np.diag(be, 1) + np.diag(be, -1)
+    Wq = dense_w(grid, xq)
+    V = np.column_stack([kg_matvec(grid, hypers, w) for w in Wq])
+    U = (P + np.outer(d, np.asarray(wty, np.float64))) @ V
+    return Wq @ V - U.T @ np.linalg.solve(T, U)
 
 
 def ski_dense_mll(grid, hypers, x, y):

@@ -486,3 +486,68 @@ def test_ski_posterior_covariance_information_form():
     np.testing.assert_allclose(C, Wq @ S @ Wq.T, rtol=1e-7, atol=1e-10)
     np.testing.assert_allclose(C, C.T, atol=1e-12)
     assert np.linalg.eigvalsh(C).min() > 0
+
+
+# --------------------------------------------------------------------------
+# Factorized Lanczos (Algs. 6-7) and the rank-k covariance built on it.
+# --------------------------------------------------------------------------
+def test_efla_matches_dense_lanczos():
+    """The factorized iterates Q_i = W qh_i + d_i y reproduce plain Lanczos
+    with one reorthogonalisation pass on the dense A = W K_G W^T + s2 I."""
+    grid, X, y, hyp = small_problem(8, (9, 8), 200)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    W = oracle.dense_w(grid, X)
+    A = W @ oracle.kg_dense(grid, hyp) @ W.T + hyp["noise"] ** 2 * np.eye(W.shape[0])
+    T_d, Q_d = oracle.lanczos_dense(A, y, 15)
+    al, be, Qh, P, d = oracle.efla(grid, hyp, wtw, wty, yty, 15, reorth=1)
+    T = np.diag(al) + np.diag(be, 1) + np.diag(be, -1)
+    np.testing.assert_allclose(T, T_d, rtol=1e-9, atol=1e-9 * np.abs(T_d).max())
+    Q = W @ Qh.T + np.outer(y, d)
+    np.testing.assert_allclose(Q, Q_d, atol=1e-9)
+    np.testing.assert_allclose(P, Qh @ (W.T @ W), atol=1e-10)
+
+
+def test_efla_orthonormal_and_projects_A():
+    """With two passes the Lanczos vectors stay orthonormal in n-space over
+    many steps, and Q^T A Q is the tridiagonal T."""
+    grid, X, y, hyp = small_problem(3, (11, 10), 300)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    W = oracle.dense_w(grid, X)
+    A = W @ oracle.kg_dense(grid, hyp) @ W.T + hyp["noise"] ** 2 * np.eye(W.shape[0])
+    al, be, Qh, P, d = oracle.efla(grid, hyp, wtw, wty, yty, 60)
+    Q = W @ Qh.T + np.outer(y, d)
+    k = Q.shape[1]
+    np.testing.assert_allclose(Q.T @ Q, np.eye(k), atol=1e-9)
+    T = np.diag(al) + np.diag(be, 1) + np.diag(be, -1)
+    np.testing.assert_allclose(Q.T @ A @ Q, T, atol=1e-8 * np.abs(T).max())
+
+
+def test_love_cov_full_rank_is_exact():
+    """Once the Krylov space is exhausted it holds range(W), so the rank-k
+    covariance equals the exact SKI covariance (Def. 2)."""
+    grid, X, y, hyp = small_problem(8, (9, 8), 200)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    Xq = rand_points(np.random.default_rng(2), grid, 10)
+    M = oracle.grid_size(grid)
+    al, _, _, _, _ = oracle.efla(grid, hyp, wtw, wty, yty, M + 1)
+    assert len(al) <= M + 1
+    C = oracle.love_cov(grid, hyp, wtw, wty, yty, Xq, M + 1)
+    ref = oracle.ski_dense_cov(grid, hyp, X, Xq)
+    np.testing.assert_allclose(C, ref, rtol=0, atol=1e-8 * np.abs(np.diag(ref)).max())
+
+
+def test_love_variance_decreases_with_rank():
+    """u^T T^{-1} u is the A^{-1}-norm of the projection of W K_G w_x onto a
+    growing Krylov space: the rank-k variances fall with k and stay above
+    the exact ones."""
+    grid, X, y, hyp = small_problem(5, (12, 10), 400)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    Xq = rand_points(np.random.default_rng(4), grid, 15)
+    exact = np.diag(oracle.ski_dense_cov(grid, hyp, X, Xq))
+    prev = None
+    for k in (3, 8, 20, 50):
+        v = np.diag(oracle.love_cov(grid, hyp, wtw, wty, yty, Xq, k))
+        assert np.all(v >= exact - 1e-10)
+        if prev is not None:
+            assert np.all(v <= prev + 1e-10)
+        prev = v
