@@ -271,6 +271,43 @@ fkgp_status fkgp_posterior_cov(const fkgp_handle* h, const fkgp_hypers* hyp,
                                double tol, int maxiter, double* cov,
                                fkgp_solve_info* info, void* stream);
 
+/* Rank-k posterior covariance (the low-rank covariance of Sec. 5) from the
+ * efficiently factorized Lanczos algorithm (Alg. 7): k Lanczos steps on
+ * A = W K_G W^T + s2 I started at y / ||y||, with the Lanczos vectors kept in
+ * the factorized form Q_i = W qh_i + d_i y (only W^T W, W^T y and y^T y
+ * enter; one operator B per step) and orthogonalised against all earlier
+ * ones (two Gram-Schmidt passes).  The cache keeps C = L^{-1} (Q^T W K_G)
+ * with T = L L^T (m x k doubles, owned by the cache), so that afterwards
+ *   cov(x, x') ~ w_x^T K_G w_x' - (C w_x) . (C w_x')
+ * costs O(k 4^d) per query point and O(k) per pair.  The approximation
+ * replaces A^{-1} by its restriction to the Krylov space; it is exact once
+ * the space holds every W K_G w_x, and the variances fall towards the exact
+ * ones as k grows. */
+typedef struct fkgp_love fkgp_love;
+
+/* Builds the cache for the hypers `hyp`.  1 <= k <= 10000 (clamped to
+ * m + 1, the largest Krylov dimension); fewer steps are taken when the
+ * Krylov space is exhausted (beta_{i+1} <= 1e-10 max |alpha|).  Needs
+ * y^T y > 0.  Device memory during the build: about 2 k m doubles.
+ * Synchronises `stream`.  *out is NULL on error. */
+fkgp_status fkgp_love_build(const fkgp_handle* h, const fkgp_hypers* hyp, int k,
+                            void* stream, fkgp_love** out);
+
+/* The Lanczos coefficients of a cache: *rank = steps taken; alpha (rank),
+ * beta (rank - 1) and d (rank: the y-coefficients of the Lanczos vectors)
+ * are host arrays, each may be NULL. */
+fkgp_status fkgp_love_tridiag(const fkgp_love* c, int* rank, double* alpha,
+                              double* beta, double* d);
+
+/* cov [nq][nq] (device doubles, row-major) between nq query points (xq: d
+ * device pointers of dtype `in`), 1 <= nq <= 4096; symmetric.
+ * FKGP_EOUTOFGRID if a query point is not interpolable.  Synchronises
+ * `stream`. */
+fkgp_status fkgp_love_cov(const fkgp_love* c, const void* const* xq, int64_t nq,
+                          fkgp_dtype in, double* cov, void* stream);
+
+void fkgp_love_destroy(fkgp_love* c);
+
 /* Operator-level entry points (for tests and benchmarks).
  * fkgp_apply_B: for k right-hand sides stored as [k][m] in the handle's stats
  * dtype, v = (K_G W^T W + s2 I) x and u = W^T W x (the operator B of the

@@ -26,7 +26,8 @@ OK, ENOTCONV, EINVAL, EOUTOFGRID, ENOMEM, EDEVICE = 0, 1, -1, -2, -3, -4
 #: every symbol that include/fkgp.h declares
 EXPORTS = ("fkgp_precompute", "fkgp_describe", "fkgp_export_stats", "fkgp_export_sketches",
            "fkgp_solve", "fkgp_mll_and_grad", "fkgp_batch_mll_and_grad", "fkgp_interpolate",
-           "fkgp_posterior_cov", "fkgp_apply_B",
+           "fkgp_posterior_cov", "fkgp_love_build", "fkgp_love_tridiag", "fkgp_love_cov",
+           "fkgp_love_destroy", "fkgp_apply_B",
            "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_ski_solve", "fkgp_save", "fkgp_load",
            "fkgp_precompute_host", "fkgp_destroy", "fkgp_last_error")
 
@@ -130,6 +131,12 @@ def load_library():
                                           ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(_MllInfo), p]
     L.fkgp_interpolate.argtypes = [p, p, ctypes.POINTER(p), ctypes.c_int64, ctypes.c_int, p, p]
+    L.fkgp_love_build.argtypes = [p, ctypes.POINTER(_Hypers), ctypes.c_int, p,
+                                  ctypes.POINTER(ctypes.c_void_p)]
+    L.fkgp_love_tridiag.argtypes = [p, ctypes.POINTER(ctypes.c_int), p, p, p]
+    L.fkgp_love_cov.argtypes = [p, ctypes.POINTER(p), ctypes.c_int64, ctypes.c_int, p, p]
+    L.fkgp_love_destroy.argtypes = [p]
+    L.fkgp_love_destroy.restype = None
     L.fkgp_posterior_cov.argtypes = [p, ctypes.POINTER(_Hypers), ctypes.POINTER(p), ctypes.c_int64,
                                      ctypes.c_int, ctypes.c_double, ctypes.c_int, p,
                                      ctypes.POINTER(_SolveInfo), p]
@@ -378,6 +385,63 @@ def posterior_cov(h, hypers, xq, tol=1e-8, maxiter=1000):
                                      _ptr(out), ctypes.byref(info), _stream()))
     return out, {"iterations": info.iterations, "converged": bool(info.converged),
                  "rel_residual": info.rel_residual, "status": st}
+
+
+class LoveCache:
+    """Rank-k covariance cache (fkgp_love_build); `rank` is the number of
+    Lanczos steps taken."""
+
+    def __init__(self, ptr, d):
+        self.ptr = ptr
+        self.d = d
+        L = load_library()
+        r = ctypes.c_int(0)
+        _check(L.fkgp_love_tridiag(ptr, ctypes.byref(r), None, None, None))
+        self.rank = r.value
+
+    def tridiag(self):
+        """(alpha [rank], beta [rank-1], d [rank]) as float64 numpy arrays."""
+        L = load_library()
+        k = self.rank
+        a = np.zeros(k)
+        b = np.zeros(max(k - 1, 0))
+        dd = np.zeros(k)
+        r = ctypes.c_int(0)
+        _check(L.fkgp_love_tridiag(self.ptr, ctypes.byref(r), a.ctypes.data_as(ctypes.c_void_p),
+                                   b.ctypes.data_as(ctypes.c_void_p) if k > 1 else None,
+                                   dd.ctypes.data_as(ctypes.c_void_p)))
+        return a, b, dd
+
+    def cov(self, xq):
+        L = load_library()
+        xs = [t.contiguous() for t in xq]
+        nq = xs[0].numel()
+        out = torch.empty(nq, nq, dtype=torch.float64, device=xs[0].device)
+        arr = (ctypes.c_void_p * 3)(*([t.data_ptr() for t in xs] + [0] * (3 - len(xs))))
+        _check(L.fkgp_love_cov(self.ptr, arr, nq, _dtype_code(xs[0].dtype), _ptr(out),
+                               _stream()))
+        return out
+
+    def close(self):
+        if self.ptr:
+            load_library().fkgp_love_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def love_build(h, hypers, k):
+    """fkgp_love_build: factorized Lanczos (k steps from y) and the rank-k
+    covariance cache."""
+    L = load_library()
+    out = ctypes.c_void_p()
+    _check(L.fkgp_love_build(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)), int(k), _stream(),
+                             ctypes.byref(out)))
+    return LoveCache(out, h.d)
 
 
 def apply_B(h, hypers, x):

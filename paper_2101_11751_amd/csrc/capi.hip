@@ -9,6 +9,7 @@
 // test has fired, so the host only polls a flag every few iterations.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -44,6 +45,19 @@ struct fkgp_handle {
     uint32_t* cend = nullptr;
     fkgp_dtype in_dt = FKGP_F32;
     void* block = nullptr;      // one pool allocation holding the arrays above
+};
+
+// Rank-k covariance cache: C^T [M][k] (row j = C_j over the rank), the
+// hypers the prior term needs, and the Lanczos tridiagonal for inspection.
+struct fkgp_love {
+    fkgp::GridDev g;
+    int kind = 0;
+    double ell[3] = {1.0, 1.0, 1.0};
+    double so = 1.0;
+    int k = 0;
+    int dev = 0;
+    double* Ct = nullptr;
+    std::vector<double> alpha, beta, d;
 };
 
 namespace fkgp {
@@ -2620,6 +2634,379 @@ fkgp_status posterior_cov_impl(const fkgp_handle* h, const fkgp_hypers* hyp,
     return conv ? FKGP_OK : FKGP_ENOTCONV;
 }
 
+// ---------------------------------------------------------------------------
+// Rank-k posterior covariance (the low-rank covariance of Sec. 5) from the
+// efficiently factorized Lanczos algorithm (Alg. 7) on A = W K_G W^T + s2 I
+// started at y / ||y||.  The i-th Lanczos vector is Q_i = W qh_i + d_i y,
+// kept as (qh_i, d_i) with p_i = W^T W qh_i and s_i = (K_G W^T W + s2 I) qh_i;
+// A Q_i = W (s_i + d_i K_G W^T y) + s2 d_i y, and for two such vectors
+//   <(a, ca), (e, ce)> = p_a . e + ca (W^T y . e) + ce (W^T y . a) + ca ce y^T y,
+// so one operator B per step and only the statistics enter.  The new vector
+// is orthogonalised against all earlier ones by two classical Gram-Schmidt
+// passes (lambda_j = <Q_j, w>, with e_j = qh_j . W^T y kept per vector).
+// The cache holds C = L^{-1} (K_G (P + W^T y d^T))^T with T = L L^T (L lower
+// bidiagonal), so that for query weights w_x
+//   cov(x, x') ~ w_x^T K_G w_x' - (C^T w_x) . (C^T w_x').
+// ---------------------------------------------------------------------------
+constexpr int kLoveMaxRank = 10000;
+constexpr int kMdRows = 8;
+
+// w = s_cur + d_i kb - beta_prev qprev (s_cur, qprev may be null: zero);
+// state[0] = wc0 (the y-coefficient of the new vector).
+__global__ void lz_start(double* __restrict__ wq, const double* __restrict__ s_cur,
+                         const double* __restrict__ kb, const double* __restrict__ qprev,
+                         double di, double bprev, int64_t M, double* state, double wc0) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0) state[0] = wc0;
+    if (r >= M) return;
+    double v = di * kb[r];
+    if (s_cur) v += s_cur[r];
+    if (qprev) v = fma(-bprev, qprev[r], v);
+    wq[r] = v;
+}
+
+// Partial dot products of x with rows 0..nr-1 of R (stride M) and with xb
+// (row nr): partials[row][gridDim.x].
+__global__ __launch_bounds__(kRedBlock) void mdot_kernel(const double* __restrict__ R, int nr,
+                                                         const double* __restrict__ xb,
+                                                         const double* __restrict__ x, int64_t M,
+                                                         double* __restrict__ partials) {
+    __shared__ double sh[kRedBlock];
+    const int r0 = blockIdx.y * kMdRows;
+    const int nrows = min(kMdRows, nr + 1 - r0);
+    double acc[kMdRows];
+#pragma unroll
+    for (int q = 0; q < kMdRows; ++q) acc[q] = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; t < M;
+         t += (int64_t)gridDim.x * kRedBlock) {
+        const double xv = x[t];
+#pragma unroll
+        for (int q = 0; q < kMdRows; ++q) {
+            if (q >= nrows) continue;
+            const int row = r0 + q;
+            const double* rp = row < nr ? R + (int64_t)row * M : xb;
+            acc[q] = fma(rp[t], xv, acc[q]);
+        }
+    }
+    for (int q = 0; q < nrows; ++q) {
+        const double t = block_sum(acc[q], sh);
+        if (threadIdx.x == 0) partials[(int64_t)(r0 + q) * gridDim.x + blockIdx.x] = t;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kRedBlock) void mdot_fin(const double* __restrict__ partials,
+                                                      int nbk, double* __restrict__ raw) {
+    __shared__ double sh[kRedBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nbk; i += kRedBlock)
+        acc += partials[(int64_t)blockIdx.x * nbk + i];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) raw[blockIdx.x] = t;
+}
+
+int mdot_blocks(int64_t M, int nrows) {
+    const int ny = (nrows + kMdRows - 1) / kMdRows;
+    const int64_t want = std::max<int64_t>(4, 4096 / ny);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(vec_blocks(M), want));
+}
+
+// raw[j] = R_j . x (j < nr), raw[nr] = xb . x
+fkgp_status mdot(const double* R, int nr, const double* xb, const double* x, int64_t M,
+                 double* partials, double* raw, hipStream_t st) {
+    const int nbk = mdot_blocks(M, nr + 1);
+    const int ny = (nr + 1 + kMdRows - 1) / kMdRows;
+    mdot_kernel<<<dim3(nbk, ny), kRedBlock, 0, st>>>(R, nr, xb, x, M, partials);
+    mdot_fin<<<nr + 1, kRedBlock, 0, st>>>(partials, nbk, raw);
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+// alpha_i = <Q_i, w> from raw = [p_i . w, yhat . w]; then wc -= alpha_i d_i.
+__global__ void lz_alpha(const double* __restrict__ raw, double di, double ei, double bb,
+                         double* state, double* alpha_i) {
+    const double wc = state[0];
+    const double al = raw[0] + di * raw[1] + wc * ei + di * wc * bb;
+    *alpha_i = al;
+    state[1] = al;
+    state[0] = wc - al * di;
+}
+
+// w -= alpha_i qh_i
+__global__ void lz_axpy(double* __restrict__ wq, const double* __restrict__ qi,
+                        const double* __restrict__ state, int64_t M) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < M) wq[r] = fma(-state[1], qi[r], wq[r]);
+}
+
+// lambda_j = <Q_j, w> for j < nj from raw = [p_j . w (j < nj), yhat . w];
+// wc -= sum_j lambda_j d_j (fixed-order block sum).
+__global__ __launch_bounds__(kRedBlock) void lz_lambda(const double* __restrict__ raw,
+                                                       const double* __restrict__ d,
+                                                       const double* __restrict__ e, int nj,
+                                                       double bb, double* state,
+                                                       double* __restrict__ lam) {
+    __shared__ double sh[kRedBlock];
+    const double wc = state[0];
+    const double rb = raw[nj];
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < nj; j += kRedBlock) {
+        const double l = raw[j] + d[j] * rb + wc * e[j] + d[j] * wc * bb;
+        lam[j] = l;
+        acc = fma(l, d[j], acc);
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) state[0] = wc - t;
+}
+
+// w -= sum_j lambda_j qh_j (rows of Qh, j < nj), one thread per grid node.
+constexpr int kLamChunk = 1024;
+__global__ __launch_bounds__(256) void lz_update(double* __restrict__ wq,
+                                                 const double* __restrict__ Qh,
+                                                 const double* __restrict__ lam, int nj,
+                                                 int64_t M) {
+    __shared__ double sl[kLamChunk];
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = r < M ? wq[r] : 0.0;
+    for (int j0 = 0; j0 < nj; j0 += kLamChunk) {
+        const int nc = min(kLamChunk, nj - j0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nc; t += blockDim.x) sl[t] = lam[j0 + t];
+        __syncthreads();
+        if (r < M) {
+            const double* q = Qh + (int64_t)j0 * M + r;
+#pragma unroll 4
+            for (int j = 0; j < nc; ++j) acc = fma(-sl[j], q[(int64_t)j * M], acc);
+        }
+    }
+    if (r < M) wq[r] = acc;
+}
+
+__global__ void lz_beta(const double* __restrict__ raw, double bb, double* state) {
+    const double wc = state[0];
+    const double b2 = raw[0] + 2.0 * wc * raw[1] + wc * wc * bb;
+    state[2] = sqrt(fmax(b2, 0.0));
+    state[3] = raw[1];
+}
+
+// qh_{i+1} = w / beta, p_{i+1} /= beta, s_{i+1} = s_next / beta; d, e entries.
+__global__ void lz_norm(const double* __restrict__ wq, double* __restrict__ qn,
+                        double* __restrict__ pn, const double* __restrict__ s_next,
+                        double* __restrict__ s_cur, double inv, int64_t M, double* d_slot,
+                        double dv, double* e_slot, double ev) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0) {
+        *d_slot = dv;
+        *e_slot = ev;
+    }
+    if (r >= M) return;
+    qn[r] = wq[r] * inv;
+    pn[r] *= inv;
+    s_cur[r] = s_next[r] * inv;
+}
+
+// rows j < kk of P: P_j += d_j yhat
+__global__ void lz_addb(double* __restrict__ P, const double* __restrict__ d,
+                        const double* __restrict__ yhat, int kk, int64_t M) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= M) return;
+    const double b = yhat[r];
+    for (int j = 0; j < kk; ++j) P[(int64_t)j * M + r] = fma(d[j], b, P[(int64_t)j * M + r]);
+}
+
+// C_j = (K_j - lsub_j C_{j-1}) / ldiag_j  (forward substitution with the
+// lower bidiagonal Cholesky factor of T), C stored [kk][M].
+__global__ void lz_forward(const double* __restrict__ K, const double* __restrict__ ldiag,
+                           const double* __restrict__ lsub, int kk, int64_t M,
+                           double* __restrict__ C) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= M) return;
+    double prev = 0.0;
+    for (int j = 0; j < kk; ++j) {
+        const double c = (K[(int64_t)j * M + r] - lsub[j] * prev) / ldiag[j];
+        C[(int64_t)j * M + r] = c;
+        prev = c;
+    }
+}
+
+// out [cols][rows] = in [rows][cols]^T through 32 x 32 LDS tiles.
+__global__ void transpose_kernel(const double* __restrict__ in, int64_t rows, int64_t cols,
+                                 double* __restrict__ out) {
+    __shared__ double t[32][33];
+    const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+    for (int y = threadIdx.y; y < 32; y += 8) {
+        const int64_t r = r0 + y, c = c0 + threadIdx.x;
+        if (r < rows && c < cols) t[y][threadIdx.x] = in[r * cols + c];
+    }
+    __syncthreads();
+    for (int y = threadIdx.y; y < 32; y += 8) {
+        const int64_t c = c0 + y, r = r0 + threadIdx.x;
+        if (c < cols && r < rows) out[c * rows + r] = t[threadIdx.x][y];
+    }
+}
+
+fkgp_status love_build_impl(const fkgp_handle* h, const fkgp_hypers* hyp, int k, hipStream_t st,
+                            fkgp_love* L) {
+    Scratch sc(st);
+    OpCtx c;
+    fkgp_status rs = make_ctx(h, hyp, FKGP_F64, c, sc);
+    if (rs != FKGP_OK) return rs;
+    const int64_t M = h->M;
+    const int64_t ldx = M + 2 * c.halo;
+    const double bb = h->yty;
+    const double* yhat = h->wty;
+    double *Qh, *P, *s_cur, *s_next, *wq, *wpad, *kb, *raw, *lam, *partials, *d, *e, *alpha,
+        *state;
+    FKGP_HIP(sc.get(&Qh, (size_t)k * M));
+    FKGP_HIP(sc.get(&P, (size_t)k * M));
+    FKGP_HIP(sc.get(&s_cur, M));
+    FKGP_HIP(sc.get(&s_next, M));
+    FKGP_HIP(sc.get(&wq, M));
+    FKGP_HIP(sc.get(&wpad, ldx));
+    FKGP_HIP(sc.get(&kb, M));
+    FKGP_HIP(sc.get(&raw, (size_t)k + 2));
+    FKGP_HIP(sc.get(&lam, (size_t)k + 1));
+    FKGP_HIP(sc.get(&partials, (size_t)(k + 8) * mdot_blocks(M, 1)));
+    FKGP_HIP(sc.get(&d, k));
+    FKGP_HIP(sc.get(&e, k));
+    FKGP_HIP(sc.get(&alpha, k));
+    FKGP_HIP(sc.get(&state, 4));
+    FKGP_HIP(hipMemsetAsync(Qh, 0, sizeof(double) * M, st));
+    FKGP_HIP(hipMemsetAsync(P, 0, sizeof(double) * M, st));
+    FKGP_HIP(hipMemsetAsync(wpad, 0, sizeof(double) * ldx, st));
+    rs = kg_apply(h->g, c.sp64, FKGP_F64, yhat, kb, 1, c.so, nullptr, 0.0, nullptr, st);
+    if (rs != FKGP_OK) return rs;
+    std::vector<double> hd(k, 0.0), he(k, 0.0), hal(k, 0.0), hbe(k, 0.0);
+    hd[0] = 1.0 / std::sqrt(bb);
+    FKGP_HIP(hipMemcpyAsync(d, hd.data(), sizeof(double), hipMemcpyHostToDevice, st));
+    FKGP_HIP(hipMemcpyAsync(e, he.data(), sizeof(double), hipMemcpyHostToDevice, st));
+    const unsigned ge = (unsigned)((M + 255) / 256);
+    int kk = k;
+    double maxal = 0.0;
+    double hs[4];
+    for (int i = 0; i < k; ++i) {
+        const double* qi = Qh + (int64_t)i * M;
+        const double wc0 = c.s2 * hd[i] - (i > 0 ? hbe[i - 1] * hd[i - 1] : 0.0);
+        lz_start<<<ge, 256, 0, st>>>(wq, i > 0 ? s_cur : nullptr, kb,
+                                     i > 0 ? Qh + (int64_t)(i - 1) * M : nullptr, hd[i],
+                                     i > 0 ? hbe[i - 1] : 0.0, M, state, wc0);
+        FKGP_HIP(hipGetLastError());
+        rs = mdot(P + (int64_t)i * M, 1, yhat, wq, M, partials, raw, st);
+        if (rs != FKGP_OK) return rs;
+        lz_alpha<<<1, 1, 0, st>>>(raw, hd[i], he[i], bb, state, alpha + i);
+        FKGP_HIP(hipGetLastError());
+        if (i == k - 1) break;
+        lz_axpy<<<ge, 256, 0, st>>>(wq, qi, state, M);
+        FKGP_HIP(hipGetLastError());
+        for (int pass = 0; pass < 2; ++pass) {
+            rs = mdot(P, i + 1, yhat, wq, M, partials, raw, st);
+            if (rs != FKGP_OK) return rs;
+            lz_lambda<<<1, kRedBlock, 0, st>>>(raw, d, e, i + 1, bb, state, lam);
+            lz_update<<<ge, 256, 0, st>>>(wq, Qh, lam, i + 1, M);
+            FKGP_HIP(hipGetLastError());
+        }
+        double* pn = P + (int64_t)(i + 1) * M;
+        FKGP_HIP(hipMemcpyAsync(wpad + c.halo, wq, sizeof(double) * M, hipMemcpyDeviceToDevice,
+                                st));
+        rs = spmv_dia_any(h->g, h->dt, FKGP_F64, h->A, h->bmask, wpad, pn, 1, c.halo, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+        rs = kg_apply(h->g, c.sp64, FKGP_F64, pn, s_next, 1, c.so, wq, c.s2, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+        rs = mdot(pn, 1, yhat, wq, M, partials, raw, st);
+        if (rs != FKGP_OK) return rs;
+        lz_beta<<<1, 1, 0, st>>>(raw, bb, state);
+        FKGP_HIP(hipGetLastError());
+        FKGP_HIP(hipMemcpyAsync(hs, state, sizeof(hs), hipMemcpyDeviceToHost, st));
+        FKGP_HIP(hipStreamSynchronize(st));
+        hal[i] = hs[1];
+        maxal = std::max(maxal, std::fabs(hs[1]));
+        const double beta = hs[2];
+        if (!std::isfinite(beta) || !std::isfinite(hs[1])) {
+            set_error("factorized Lanczos broke down (non-finite coefficient)");
+            return FKGP_EDEVICE;
+        }
+        if (!(beta > 1e-10 * maxal)) {
+            kk = i + 1;
+            break;
+        }
+        hbe[i] = beta;
+        hd[i + 1] = hs[0] / beta;
+        he[i + 1] = hs[3] / beta;
+        lz_norm<<<ge, 256, 0, st>>>(wq, Qh + (int64_t)(i + 1) * M, pn, s_next, s_cur, 1.0 / beta,
+                                    M, d + i + 1, hd[i + 1], e + i + 1, he[i + 1]);
+        FKGP_HIP(hipGetLastError());
+    }
+    FKGP_HIP(hipMemcpyAsync(hal.data(), alpha, sizeof(double) * kk, hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipStreamSynchronize(st));
+    // Cholesky of the tridiagonal T = L L^T (L lower bidiagonal)
+    std::vector<double> ld(kk), ls(kk, 0.0);
+    for (int j = 0; j < kk; ++j) {
+        double t = hal[j];
+        if (j > 0) {
+            ls[j] = hbe[j - 1] / ld[j - 1];
+            t -= ls[j] * ls[j];
+        }
+        if (!(t > 0.0) || !std::isfinite(t)) {
+            set_error("Lanczos tridiagonal is not positive definite");
+            return FKGP_EDEVICE;
+        }
+        ld[j] = std::sqrt(t);
+    }
+    double *dld, *dls;
+    FKGP_HIP(sc.get(&dld, kk));
+    FKGP_HIP(sc.get(&dls, kk));
+    FKGP_HIP(hipMemcpyAsync(dld, ld.data(), sizeof(double) * kk, hipMemcpyHostToDevice, st));
+    FKGP_HIP(hipMemcpyAsync(dls, ls.data(), sizeof(double) * kk, hipMemcpyHostToDevice, st));
+    // rows P_j + d_j yhat, then K_G of them (into Qh), then C (into P)
+    lz_addb<<<ge, 256, 0, st>>>(P, d, yhat, kk, M);
+    FKGP_HIP(hipGetLastError());
+    for (int j0 = 0; j0 < kk; j0 += 64) {
+        const int nr = std::min(64, kk - j0);
+        rs = kg_apply(h->g, c.sp64, FKGP_F64, P + (int64_t)j0 * M, Qh + (int64_t)j0 * M, nr, c.so,
+                      nullptr, 0.0, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+    }
+    lz_forward<<<ge, 256, 0, st>>>(Qh, dld, dls, kk, M, P);
+    FKGP_HIP(hipGetLastError());
+    FKGP_HIP(hipMalloc(reinterpret_cast<void**>(&L->Ct), sizeof(double) * M * kk));
+    transpose_kernel<<<dim3((unsigned)((M + 31) / 32), (unsigned)((kk + 31) / 32)), dim3(32, 8), 0,
+                       st>>>(P, kk, M, L->Ct);
+    FKGP_HIP(hipGetLastError());
+    FKGP_HIP(hipStreamSynchronize(st));
+    L->k = kk;
+    L->alpha.assign(hal.begin(), hal.begin() + kk);
+    L->beta.assign(hbe.begin(), hbe.begin() + std::max(kk - 1, 0));
+    L->d.assign(hd.begin(), hd.begin() + kk);
+    return FKGP_OK;
+}
+
+fkgp_status love_cov_impl(const fkgp_love* L, const void* const* xq, int nq, fkgp_dtype in,
+                          double* cov, hipStream_t st) {
+    Scratch sc(st);
+    int* first;
+    double *w, *U, *partials;
+    unsigned long long* bad;
+    FKGP_HIP(sc.get(&first, (size_t)nq * 3));
+    FKGP_HIP(sc.get(&w, (size_t)nq * 12));
+    FKGP_HIP(sc.get(&U, (size_t)nq * L->k));
+    FKGP_HIP(sc.get(&partials, love_partials_doubles(nq, L->k, nullptr)));
+    FKGP_HIP(sc.get(&bad, 1));
+    FKGP_HIP(hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), st));
+    fkgp_status rs = query_stencils(L->g, xq, nq, in, first, w, bad, st);
+    if (rs != FKGP_OK) return rs;
+    unsigned long long hbad = ~0ull;
+    FKGP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipStreamSynchronize(st));
+    if (hbad != ~0ull) {
+        set_error("query point " + std::to_string(hbad) + " lies outside the interpolable region");
+        return FKGP_EOUTOFGRID;
+    }
+    rs = love_query(L->g, L->kind, L->ell, L->so, L->Ct, L->k, first, w, nq, U, partials, cov, st);
+    if (rs != FKGP_OK) return rs;
+    FKGP_HIP(hipStreamSynchronize(st));
+    return FKGP_OK;
+}
+
 }  // namespace
 }  // namespace fkgp
 
@@ -2685,6 +3072,95 @@ extern "C" fkgp_status fkgp_posterior_cov(const fkgp_handle* h, const fkgp_hyper
         return fkgp::posterior_cov_impl(h, hyp, xq, nq, in, tol, maxiter, cov, info,
                                         static_cast<hipStream_t>(stream));
     });
+}
+
+extern "C" fkgp_status fkgp_love_build(const fkgp_handle* h, const fkgp_hypers* hyp, int k,
+                                       void* stream, fkgp_love** out) {
+    return guarded([&]() -> fkgp_status {
+        fkgp::set_error("");
+        if (!out) {
+            fkgp::set_error("out must be non-NULL");
+            return FKGP_EINVAL;
+        }
+        *out = nullptr;
+        if (!h) {
+            fkgp::set_error("handle must be non-NULL");
+            return FKGP_EINVAL;
+        }
+        fkgp_status st = fkgp::check_hypers(h, hyp);
+        if (st != FKGP_OK) return st;
+        if (k < 1 || k > fkgp::kLoveMaxRank) {
+            fkgp::set_error("k must be in [1, 10000]");
+            return FKGP_EINVAL;
+        }
+        if (!(h->yty > 0.0)) {
+            fkgp::set_error("the factorized Lanczos starts at y: needs y^T y > 0");
+            return FKGP_EINVAL;
+        }
+        const int kc = (int)std::min<int64_t>(k, h->M + 1);
+        auto* L = new fkgp_love();
+        L->g = h->g;
+        L->kind = hyp->kernel;
+        for (int i = 0; i < 3; ++i) L->ell[i] = i < h->g.d ? hyp->lengthscale[i] : 1.0;
+        L->so = hyp->outputscale;
+        (void)hipGetDevice(&L->dev);
+        st = fkgp::love_build_impl(h, hyp, kc, static_cast<hipStream_t>(stream), L);
+        if (st != FKGP_OK) {
+            if (L->Ct) (void)hipFree(L->Ct);
+            delete L;
+            return st;
+        }
+        *out = L;
+        return FKGP_OK;
+    });
+}
+
+extern "C" fkgp_status fkgp_love_tridiag(const fkgp_love* c, int* rank, double* alpha,
+                                         double* beta, double* d) {
+    return guarded([&]() -> fkgp_status {
+        fkgp::set_error("");
+        if (!c || !rank) {
+            fkgp::set_error("cache and rank must be non-NULL");
+            return FKGP_EINVAL;
+        }
+        *rank = c->k;
+        if (alpha) std::copy(c->alpha.begin(), c->alpha.end(), alpha);
+        if (beta) std::copy(c->beta.begin(), c->beta.end(), beta);
+        if (d) std::copy(c->d.begin(), c->d.end(), d);
+        return FKGP_OK;
+    });
+}
+
+extern "C" fkgp_status fkgp_love_cov(const fkgp_love* c, const void* const* xq, int64_t nq,
+                                     fkgp_dtype in, double* cov, void* stream) {
+    return guarded([&]() -> fkgp_status {
+        fkgp::set_error("");
+        if (!c || !xq || !cov) {
+            fkgp::set_error("cache, xq and cov must be non-NULL");
+            return FKGP_EINVAL;
+        }
+        if (nq < 1 || nq > fkgp::kCovMaxQ) {
+            fkgp::set_error("nq must be in [1, 4096]");
+            return FKGP_EINVAL;
+        }
+        if (in != FKGP_F32 && in != FKGP_F64) {
+            fkgp::set_error("unknown point dtype");
+            return FKGP_EINVAL;
+        }
+        for (int k = 0; k < c->g.d; ++k)
+            if (!xq[k]) {
+                fkgp::set_error("xq[k] is NULL");
+                return FKGP_EINVAL;
+            }
+        return fkgp::love_cov_impl(c, xq, (int)nq, in, cov, static_cast<hipStream_t>(stream));
+    });
+}
+
+extern "C" void fkgp_love_destroy(fkgp_love* c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    if (c->Ct) (void)hipFree(c->Ct);
+    delete c;
 }
 
 extern "C" fkgp_status fkgp_batch_mll_and_grad(const fkgp_handle* const* hs, int nprob,

@@ -313,6 +313,16 @@ int64_t spmv_dot_parts(const GridDev& g);
 // query point i on the grid; out-of-grid points set *bad (min index).
 fkgp_status query_weights(const GridDev& g, const void* const* xq, int64_t nq, fkgp_dtype in,
                           double* G, unsigned long long* bad, hipStream_t s);
+// Stencils of nq query points: first[i][3] (first node per dimension) and
+// w[i][3][4] (Keys weights); out-of-grid points set *bad (min index).
+fkgp_status query_stencils(const GridDev& g, const void* const* xq, int64_t nq, fkgp_dtype in,
+                           int* first, double* w, unsigned long long* bad, hipStream_t s);
+// Rank-k covariance queries: U [nq][k] and partials (love_partials_doubles)
+// are workspace; Ct [M][k]; cov [nq][nq] = w_i^T K_G w_j - U_i . U_j.
+size_t love_partials_doubles(int nq, int k, int* nb_out);
+fkgp_status love_query(const GridDev& g, int kind, const double* ell, double so,
+                       const double* Ct, int k, const int* first, const double* w, int nq,
+                       double* U, double* partials, double* cov, hipStream_t s);
 fkgp_status interpolate_points(const GridDev& g, const double* mu,
                                const void* const* xq, int64_t nq,
                                fkgp_dtype in, double* out,

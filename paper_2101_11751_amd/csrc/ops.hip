@@ -744,6 +744,143 @@ __global__ void weights_kernel(GridDev g, const Tin* x0, const Tin* x1, const Ti
             }
 }
 
+// Stencil of query point i: first node per dimension and the four Keys
+// weights per dimension (first[i][k], w[i][k][a]).
+template <class Tin>
+__global__ void stencil_kernel(GridDev g, const Tin* x0, const Tin* x1, const Tin* x2,
+                               int64_t nq, int* __restrict__ first, double* __restrict__ w,
+                               unsigned long long* bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const Tin* xs[3] = {x0, x1, x2};
+    for (int k = 0; k < 3; ++k) {
+        double wk[4] = {1.0, 0.0, 0.0, 0.0};
+        int f = 0;
+        if (k < g.d) {
+            const double u = ((double)xs[k][i] - g.g0[k]) / g.h[k];
+            if (!(u >= 1.0 && u <= (double)(g.m[k] - 2))) {
+                atomicMin(bad, (unsigned long long)i);
+                return;
+            }
+            int b = (int)floor(u);
+            if (b > g.m[k] - 3) b = g.m[k] - 3;
+            keys4(u - (double)b, wk);
+            f = b - 1;
+        }
+        first[i * 3 + k] = f;
+        for (int a = 0; a < 4; ++a) w[(i * 3 + k) * 4 + a] = wk[a];
+    }
+}
+
+// U[i][l] = sum over the stencil nodes j of query i of w_ij Ct[j][l]
+// (one workgroup per query point, threads over l).
+__global__ void love_project_kernel(GridDev g, const double* __restrict__ Ct, int k,
+                                    const int* __restrict__ first,
+                                    const double* __restrict__ w, double* __restrict__ U) {
+    const int64_t i = blockIdx.x;
+    const int e1 = g.d > 1 ? 4 : 1, e2 = g.d > 2 ? 4 : 1;
+    const int f0 = first[i * 3], f1 = first[i * 3 + 1], f2 = first[i * 3 + 2];
+    const double* wi = w + i * 12;
+    for (int l = threadIdx.x; l < k; l += blockDim.x) {
+        double acc = 0.0;
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < e1; ++b)
+                for (int c = 0; c < e2; ++c) {
+                    int64_t j = f0 + a;
+                    if (g.d > 1) j = j * g.m[1] + (f1 + b);
+                    if (g.d > 2) j = j * g.m[2] + (f2 + c);
+                    const double wt = wi[a] * wi[4 + b] * wi[8 + c];
+                    acc = fma(wt, Ct[j * k + l], acc);
+                }
+        U[i * k + l] = acc;
+    }
+}
+
+constexpr int kGramTile = 64;
+constexpr int kGramChunk = 16;
+constexpr int kGramPairs = kGramTile * kGramTile / 256;
+
+// For the tile (rows i0.., columns j0..) of the pair matrix: partial sums of
+// U_i . U_j over the column chunks of this block (chunk c to block c mod
+// gridDim.x, increasing order).
+__global__ __launch_bounds__(256) void gram_partial_kernel(const double* __restrict__ U, int k,
+                                                           int nq,
+                                                           double* __restrict__ partials) {
+    __shared__ double sA[kGramTile][kGramChunk + 1];
+    __shared__ double sB[kGramTile][kGramChunk + 1];
+    const int i0 = blockIdx.y * kGramTile, j0 = blockIdx.z * kGramTile;
+    const int ni = min(kGramTile, nq - i0), nj = min(kGramTile, nq - j0);
+    double acc[kGramPairs];
+#pragma unroll
+    for (int r = 0; r < kGramPairs; ++r) acc[r] = 0.0;
+    const int nchunk = (k + kGramChunk - 1) / kGramChunk;
+    for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        const int l0 = ch * kGramChunk;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kGramTile * kGramChunk; e += 256) {
+            const int a = e / kGramChunk, ll = e % kGramChunk;
+            const int l = l0 + ll;
+            sA[a][ll] = (l < k && a < ni) ? U[(int64_t)(i0 + a) * k + l] : 0.0;
+            sB[a][ll] = (l < k && a < nj) ? U[(int64_t)(j0 + a) * k + l] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kGramPairs; ++r) {
+            const int p = threadIdx.x + 256 * r;
+            const int a = p / kGramTile, b = p % kGramTile;
+            double t = 0.0;
+#pragma unroll 8
+            for (int ll = 0; ll < kGramChunk; ++ll) t = fma(sA[a][ll], sB[b][ll], t);
+            acc[r] += t;
+        }
+    }
+    const int tile = blockIdx.y * gridDim.z + blockIdx.z;
+    double* out = partials + ((int64_t)tile * gridDim.x + blockIdx.x) * (kGramTile * kGramTile);
+#pragma unroll
+    for (int r = 0; r < kGramPairs; ++r) out[threadIdx.x + 256 * r] = acc[r];
+}
+
+// cov[i][j] = w_i^T K_G w_j - (U_i . U_j + U_j . U_i) / 2.  The prior term
+// is separable: K_G and the stencil weights are products over dimensions,
+// so w_i^T K_G w_j = so prod_k sum_{a,b} w_ik[a] w_jk[b] k1(|node distance|).
+__global__ void love_fin_kernel(GridDev g, int kind, double ell0, double ell1, double ell2,
+                                double so, const int* __restrict__ first,
+                                const double* __restrict__ w,
+                                const double* __restrict__ partials, int nb, int nq, int nt,
+                                double* __restrict__ cov) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)nq * nq) return;
+    const int i = (int)(p / nq), j = (int)(p % nq);
+    const double ell[3] = {ell0, ell1, ell2};
+    // evaluated in the order of (min, max) so that cov is exactly symmetric
+    const int lo = min(i, j), hi = max(i, j);
+    double prior = so;
+    for (int k = 0; k < g.d; ++k) {
+        const int fi = first[lo * 3 + k], fj = first[hi * 3 + k];
+        const double* wi = w + ((int64_t)lo * 3 + k) * 4;
+        const double* wj = w + ((int64_t)hi * 3 + k) * 4;
+        double t = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            double ta = 0.0;
+            for (int b = 0; b < 4; ++b) {
+                const int dist = abs((fi + a) - (fj + b));
+                ta = fma(wj[b], kernel_col(kind, dist, g.h[k], ell[k], false), ta);
+            }
+            t = fma(wi[a], ta, t);
+        }
+        prior *= t;
+    }
+    auto sum = [&](int r, int c) {
+        const int tile = (r / kGramTile) * nt + c / kGramTile;
+        const double* q = partials + (int64_t)tile * nb * (kGramTile * kGramTile) +
+                          (r % kGramTile) * kGramTile + c % kGramTile;
+        double a = 0.0;
+        for (int b = 0; b < nb; ++b) a += q[(int64_t)b * (kGramTile * kGramTile)];
+        return a;
+    };
+    cov[p] = prior - 0.5 * (sum(i, j) + sum(j, i));
+}
+
 template <class T>
 __global__ void dia_to_canonical_kernel(const T* __restrict__ A, T* __restrict__ out,
                                         int64_t M, int NB) {
@@ -1121,6 +1258,47 @@ fkgp_status query_weights(const GridDev& g, const void* const* xq, int64_t nq, f
         for (int k = 0; k < g.d; ++k) p[k] = static_cast<const double*>(xq[k]);
         weights_kernel<double><<<grid, 256, 0, s>>>(g, p[0], p[1], p[2], nq, M, G, bad);
     }
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+fkgp_status query_stencils(const GridDev& g, const void* const* xq, int64_t nq, fkgp_dtype in,
+                           int* first, double* w, unsigned long long* bad, hipStream_t s) {
+    if (nq == 0) return FKGP_OK;
+    const unsigned grid = (unsigned)((nq + 255) / 256);
+    if (in == FKGP_F32) {
+        const float* p[3] = {nullptr, nullptr, nullptr};
+        for (int k = 0; k < g.d; ++k) p[k] = static_cast<const float*>(xq[k]);
+        stencil_kernel<float><<<grid, 256, 0, s>>>(g, p[0], p[1], p[2], nq, first, w, bad);
+    } else {
+        const double* p[3] = {nullptr, nullptr, nullptr};
+        for (int k = 0; k < g.d; ++k) p[k] = static_cast<const double*>(xq[k]);
+        stencil_kernel<double><<<grid, 256, 0, s>>>(g, p[0], p[1], p[2], nq, first, w, bad);
+    }
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+size_t love_partials_doubles(int nq, int k, int* nb_out) {
+    const int nt = (nq + kGramTile - 1) / kGramTile;
+    const int nchunk = (k + kGramChunk - 1) / kGramChunk;
+    const int per_tile = std::min(256, std::max(8, 2048 / (nt * nt)));
+    const int nb = std::max(1, std::min(nchunk, per_tile));
+    if (nb_out) *nb_out = nb;
+    return (size_t)nt * nt * nb * kGramTile * kGramTile;
+}
+
+fkgp_status love_query(const GridDev& g, int kind, const double* ell, double so,
+                       const double* Ct, int k, const int* first, const double* w, int nq,
+                       double* U, double* partials, double* cov, hipStream_t s) {
+    int nb = 1;
+    (void)love_partials_doubles(nq, k, &nb);
+    const int nt = (nq + kGramTile - 1) / kGramTile;
+    love_project_kernel<<<nq, 256, 0, s>>>(g, Ct, k, first, w, U);
+    gram_partial_kernel<<<dim3(nb, nt, nt), 256, 0, s>>>(U, k, nq, partials);
+    const int64_t P = (int64_t)nq * nq;
+    love_fin_kernel<<<(unsigned)((P + 255) / 256), 256, 0, s>>>(
+        g, kind, ell[0], ell[1], ell[2], so, first, w, partials, nb, nq, nt, cov);
     FKGP_HIP(hipGetLastError());
     return FKGP_OK;
 }

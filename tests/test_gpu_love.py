@@ -1,0 +1,126 @@
+"""Rank-k posterior covariance from the efficiently factorized Lanczos
+algorithm (Alg. 7): the Lanczos coefficients and the rank-k covariance match
+the oracle's factorized Lanczos, the covariance is exact once the Krylov space
+is exhausted, and the variances fall towards the exact ones with k."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2101_11751_amd")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+HYP = {1: {"lengthscale": [0.08], "outputscale": 1.2, "noise": 0.2},
+       2: {"lengthscale": [0.15, 0.12], "outputscale": 0.9, "noise": 0.25},
+       3: {"lengthscale": [0.3, 0.25, 0.35], "outputscale": 1.1, "noise": 0.3}}
+
+
+def case(d, n, m, seed, nq=12, dtype=np.float64):
+    rng = np.random.default_rng(seed)
+    grid = oracle.make_grid(m, lo=0.0, hi=1.0)
+    X = rng.uniform(0, 1, (d, n)).astype(dtype)
+    y = (np.sin(6 * X[0].astype(np.float64)) + 0.3 * rng.standard_normal(n)).astype(dtype)
+    Xq = rng.uniform(0, 1, (d, nq)).astype(dtype)
+    xs = [torch.from_numpy(np.ascontiguousarray(X[k])).cuda() for k in range(d)]
+    xq = [torch.from_numpy(np.ascontiguousarray(Xq[k])).cuda() for k in range(d)]
+    return grid, X.astype(np.float64), y.astype(np.float64), Xq.astype(np.float64), xs, \
+        torch.from_numpy(y).cuda(), xq
+
+
+@pytest.mark.parametrize("d,n,m,k", [(1, 3000, [200], 20), (2, 20000, [30, 25], 60),
+                                     (3, 5000, [10, 9, 8], 50)])
+def test_lanczos_and_cov_match_oracle(d, n, m, k):
+    _need_gpu()
+    grid, X, y, Xq, xs, yt, xq = case(d, n, m, 60 + d)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float64)
+    c = P.love_build(h, HYP[d], k)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    al_o, be_o, _, _, d_o = oracle.efla(grid, HYP[d], wtw, wty, yty, k)
+    assert c.rank == len(al_o) == k
+    al, be, dd = c.tridiag()
+    np.testing.assert_allclose(al, al_o, rtol=1e-8, atol=1e-10 * np.abs(al_o).max())
+    np.testing.assert_allclose(be, be_o, rtol=1e-7, atol=1e-9 * np.abs(al_o).max())
+    np.testing.assert_allclose(dd, d_o, rtol=1e-7, atol=1e-9 * abs(d_o[0]))
+    C = c.cov(xq).cpu().numpy()
+    ref = oracle.love_cov(grid, HYP[d], wtw, wty, yty, Xq, k)
+    scale = np.abs(np.diag(ref)).max()
+    assert np.abs(C - ref).max() <= 1e-8 * scale
+    assert np.array_equal(C, C.T)
+    c.close()
+
+
+def test_full_rank_is_exact_and_stops_early():
+    """k above the Krylov dimension: the build stops when the space is
+    exhausted (rank <= m + 1) and the covariance equals the exact SKI one."""
+    _need_gpu()
+    grid, X, y, Xq, xs, yt, xq = case(2, 400, [9, 8], 8)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float64)
+    M = 72
+    c = P.love_build(h, HYP[2], 500)
+    assert c.rank <= M + 1
+    ref = oracle.ski_dense_cov(grid, HYP[2], X, Xq)
+    C = c.cov(xq).cpu().numpy()
+    assert np.abs(C - ref).max() <= 1e-8 * np.abs(np.diag(ref)).max()
+
+
+def test_variances_fall_with_rank():
+    """Against the oracle's dense exact covariance: the rank-k variances stay
+    above the exact ones and fall with k, down to the exact values once the
+    Krylov space is exhausted (k = 200 stops early)."""
+    _need_gpu()
+    grid, X, y, Xq, xs, yt, xq = case(1, 3000, [300], 9, nq=30)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float64)
+    exact = np.diag(oracle.ski_dense_cov(grid, HYP[1], X, Xq))
+    tol = 1e-8 * exact.max()
+    prev = None
+    for k in (5, 12, 20, 200):
+        c = P.love_build(h, HYP[1], k)
+        v = np.diag(c.cov(xq).cpu().numpy())
+        assert np.all(v >= exact - tol), k
+        if prev is not None:
+            assert np.all(v <= prev + tol), k
+        prev = v
+        if k == 200:
+            assert c.rank < 200
+            assert np.abs(v - exact).max() <= tol
+        c.close()
+
+
+def test_many_queries_tiles():
+    """150 query points (3 x 3 pair tiles, ragged) in FP32 coordinates:
+    pairwise entries equal the oracle's."""
+    _need_gpu()
+    grid, X, y, Xq, xs, yt, xq = case(2, 10000, [24, 20], 12, nq=150, dtype=np.float32)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float64)
+    c = P.love_build(h, HYP[2], 70)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    ref = oracle.love_cov(grid, HYP[2], wtw, wty, yty, Xq, 70)
+    C = c.cov(xq).cpu().numpy()
+    assert np.abs(C - ref).max() <= 1e-8 * np.abs(np.diag(ref)).max()
+
+
+def test_errors():
+    _need_gpu()
+    grid, X, y, Xq, xs, yt, xq = case(1, 500, [60], 5)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float64)
+    with pytest.raises(P.FkgpError):
+        P.love_build(h, HYP[1], 0)
+    with pytest.raises(P.FkgpError):
+        P.love_build(h, HYP[1], 10001)
+    c = P.love_build(h, HYP[1], 10)
+    with pytest.raises(P.OutOfGridError):
+        c.cov([torch.tensor([0.5, 9.0], device="cuda", dtype=torch.float64)])
+    with pytest.raises(P.FkgpError):
+        c.cov([torch.empty(0, device="cuda", dtype=torch.float64)])
+    e = torch.empty(0, device="cuda", dtype=torch.float64)
+    h0 = P.precompute(grid, [e], e, stats_dtype=torch.float64)
+    with pytest.raises(P.FkgpError):
+        P.love_build(h0, HYP[1], 10)
