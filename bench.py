@@ -277,16 +277,19 @@ def ski_sweep(P, workloads, torch, dev, iters=200):
     return out
 
 
-def cov_leg(P, workloads, torch, dev, nq=691, tol=1e-4, maxiter=5000):
+def cov_leg(P, workloads, torch, dev, nq=691, tol=1e-10, maxiter=20000):
     """Exact SKI posterior covariance between nq query points (one solve per
     query point; Sec. 5 computes a 691 x 691 matrix on the sound data, n =
     59.3K) on the synthetic sine of the same size, for a small and a large
-    grid: seconds per call after a warm-up."""
+    grid (1-D grids are limited to 8192 nodes here): seconds per call after a
+    warm-up; then the rank-k covariance (k = min(m, 10000)) built from the
+    factorized Lanczos, its build and query times and its relative Frobenius
+    distance from the exact matrix."""
     out = []
     g = torch.Generator(device=dev)
     g.manual_seed(5)
     xq = torch.rand(nq, generator=g, device=dev, dtype=torch.float64)
-    for m in (8000, 60000):
+    for m in (1000, 8000):
         wl = workloads.sine1d_grid(59_300, m, device=dev)
         h = P.precompute(wl["grid"], wl["x"], wl["y"], stats_dtype=torch.float64)
         hyp = wl["hypers"]
@@ -301,6 +304,25 @@ def cov_leg(P, workloads, torch, dev, nq=691, tol=1e-4, maxiter=5000):
                "min_diag": float(C.diagonal().min())}
         log(f"posterior covariance {nq}x{nq}, m={m}: {t*1e3:.1f} ms, "
             f"{info['iterations']} iterations")
+        # rank-k covariance (k = min(m, 10000), Sec. 5): build once, then query
+        k = min(m, 10000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cache = P.love_build(h, hyp, k)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        C_k = cache.cov([xq])
+        torch.cuda.synchronize()
+        t_query = time.perf_counter() - t0
+        rec.update({"lowrank_k": k, "lowrank_rank": cache.rank, "lowrank_build_s": t_build,
+                    "lowrank_query_s": t_query,
+                    "lowrank_rel_frobenius": float(torch.linalg.norm(C_k - C) /
+                                                   torch.linalg.norm(C))})
+        log(f"rank-k covariance m={m}: rank {cache.rank}, build {t_build*1e3:.1f} ms, "
+            f"query {t_query*1e3:.2f} ms, rel. Frobenius diff {rec['lowrank_rel_frobenius']:.2e}")
+        cache.close()
+        del C_k
         out.append(rec)
         h.close()
         del wl, C

@@ -35,6 +35,8 @@ def _lib():
         L.oracle_splitmix64.restype = ctypes.c_uint64
         L.oracle_interpolate.argtypes = [ctypes.c_int, p, p, p, p, p, i64, p, p]
         L.oracle_wtw_matvec.argtypes = [ctypes.c_int, p, p, p, p, ctypes.c_int]
+        L.oracle_set_interp.argtypes = [ctypes.c_int]
+        L.oracle_set_interp.restype = None
         for f in (L.oracle_stencils, L.oracle_precompute, L.oracle_probe_sketches,
                   L.oracle_interpolate):
             f.restype = ctypes.c_int
@@ -46,7 +48,13 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+INTERP = {"cubic": 0, "linear": 1}
+
+
 def _grid_arrays(grid):
+    """Grid geometry as C arrays; also selects the interpolation scheme
+    (grid["interp"]: "cubic" (default) or "linear") for the next C call."""
+    _lib().oracle_set_interp(INTERP[grid.get("interp", "cubic")])
     d = grid["d"]
     m = np.ascontiguousarray(np.array(grid["m"][:d], dtype=np.int64))
     g0 = np.ascontiguousarray(np.array(grid["origin"][:d], dtype=np.float64))

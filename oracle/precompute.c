@@ -9,7 +9,9 @@
  *   - the cubic-convolution interpolation stencil w_x of a point (Sec. 3,
  *     Def. 3 and the basis-function description under Fig. 1: basis j is
  *     centred at grid node j and supported on [j-2, j+2); Keys' cubic kernel
- *     with a = -1/2);
+ *     with a = -1/2), or the linear-interpolation stencil (Sec. 2.3: 2^d
+ *     nonzeros; Claim 2 with r = 1), selected by oracle_set_interp and kept
+ *     in the same four-node frame with zero outer weights;
  *   - the sufficient statistics W^T W = sum_i w_i w_i^T, W^T y = sum_i y_i w_i
  *     and y^T y = sum_i y_i^2 (Sec. 3.1 "Precomputation"; proof of Claim 2),
  *     accumulated serially in input order;
@@ -49,6 +51,27 @@ static void keys_weights(double t, double w[4]) {
     w[3] = 0.5 * (t3 - t2);
 }
 
+/* Linear interpolation between nodes i and i+1, in the same frame. */
+static void linear_weights(double t, double w[4]) {
+    w[0] = 0.0;
+    w[1] = 1.0 - t;
+    w[2] = t;
+    w[3] = 0.0;
+}
+
+/* 0: Keys cubic (default); 1: linear.  Set before each call by the Python
+ * wrapper from the grid description. */
+static int g_interp = 0;
+
+void oracle_set_interp(int kind) { g_interp = kind == 1 ? 1 : 0; }
+
+static void stencil_weights(double t, double w[4]) {
+    if (g_interp == 1)
+        linear_weights(t, w);
+    else
+        keys_weights(t, w);
+}
+
 /* Per-dimension grid coordinate, base node and fractional offset.
  * Returns 0 if interpolable, -2 otherwise (including NaN). */
 static int locate_1d(double x, double g0, double h, int64_t m, int64_t *base,
@@ -74,7 +97,7 @@ static int stencil(int d, const int64_t *m, const double *g0, const double *h,
     for (int k = 0; k < d; ++k) {
         double t;
         if (locate_1d(xs[k], g0[k], h[k], m[k], &base[k], &t)) return -2;
-        keys_weights(t, w1[k]);
+        stencil_weights(t, w1[k]);
     }
     int64_t c = 0;
     for (int k = 0; k < d; ++k) c = c * (m[k] - 3) + (base[k] - 1);

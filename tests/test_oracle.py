@@ -21,17 +21,24 @@ def keys_kernel(s):
                     np.where(s < 2, -0.5 * s ** 3 + 2.5 * s ** 2 - 4 * s + 2, 0.0))
 
 
+def hat_kernel(s):
+    """Linear-interpolation basis function max(0, 1 - |s|)."""
+    return np.maximum(0.0, 1.0 - np.abs(s))
+
+
 def dense_w_textbook(grid, X):
-    """W[i, j] = prod_k keys(u_ik - j_k) over all grid nodes (brute force)."""
+    """W[i, j] = prod_k phi(u_ik - j_k) over all grid nodes (brute force),
+    phi the Keys kernel, or the hat function for linear interpolation."""
     d = grid["d"]
     m = grid["m"]
     n = X.shape[1]
     M = int(np.prod(m))
+    phi = hat_kernel if grid.get("interp", "cubic") == "linear" else keys_kernel
     coords = np.array(np.unravel_index(np.arange(M), m))  # [d, M]
     W = np.ones((n, M))
     for k in range(d):
         u = (X[k] - grid["origin"][k]) / grid["spacing"][k]
-        W *= keys_kernel(u[:, None] - coords[k][None, :])
+        W *= phi(u[:, None] - coords[k][None, :])
     return W
 
 
@@ -110,6 +117,49 @@ def test_wtw_bruteforce_dense(m):
     assert abs(yty - y @ y) <= 1e-12 * n
     # the DIA layout holds every nonzero: at most 7^d per row (Claim 2)
     assert np.count_nonzero(np.abs(W.T @ W) > 1e-14, axis=1).max() <= 7 ** len(m)
+
+
+@pytest.mark.parametrize("m", [[11], [7, 9], [6, 5, 7]])
+def test_linear_wtw_bruteforce_dense(m):
+    """Linear interpolation (Sec. 2.3: 2^d nonzeros per row of W): the
+    statistics equal the brute-force hat-function W, and W^T W has at most
+    3^d nonzeros per row, all within offsets -1..1 (Claim 2, r = 1)."""
+    rng = np.random.default_rng(10 + len(m))
+    grid = oracle.make_grid(m, origin=[0.5] * len(m), spacing=[0.3] * len(m))
+    grid["interp"] = "linear"
+    n = 400
+    X = rand_points(rng, grid, n)
+    y = rng.standard_normal(n)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    W = dense_w_textbook(grid, X)
+    assert np.count_nonzero(W, axis=1).max() <= 2 ** len(m)
+    A = oracle.wtw_dense_from_dia(grid, wtw)
+    np.testing.assert_allclose(A, W.T @ W, atol=1e-12 * n)
+    np.testing.assert_allclose(wty, W.T @ y, atol=1e-12 * n)
+    np.testing.assert_allclose(oracle.dense_w(grid, X), W, atol=1e-14)
+    d = len(m)
+    offs = np.array(np.unravel_index(np.arange(7 ** d), (7,) * d)).T - 3
+    outer = np.abs(offs).max(axis=1) > 1
+    assert np.all(wtw[:, outer] == 0.0)
+    assert np.count_nonzero(np.abs(W.T @ W) > 1e-14, axis=1).max() <= 3 ** d
+
+
+def test_linear_reproduces_affine_only():
+    """Linear interpolation is exact for affine functions and not for a
+    quadratic (which the cubic Keys weights do reproduce)."""
+    rng = np.random.default_rng(4)
+    grid = oracle.make_grid([9, 8], origin=[0.0, 1.0], spacing=[0.5, 0.25])
+    X = rand_points(rng, grid, 200)
+    coords = np.array(np.unravel_index(np.arange(72), (9, 8)), float)
+    G = np.array([grid["origin"][k] + coords[k] * grid["spacing"][k] for k in range(2)])
+    aff = 0.7 - 1.3 * G[0] + 2.1 * G[1]
+    quad = G[0] ** 2
+    lin = dict(grid, interp="linear")
+    Wl = oracle.dense_w(lin, X)
+    Wc = oracle.dense_w(grid, X)
+    np.testing.assert_allclose(Wl @ aff, 0.7 - 1.3 * X[0] + 2.1 * X[1], atol=1e-12)
+    np.testing.assert_allclose(Wc @ quad, X[0] ** 2, atol=1e-12)
+    assert np.abs(Wl @ quad - X[0] ** 2).max() > 1e-3
 
 
 def test_wtw_invariants():
@@ -211,9 +261,11 @@ def small_problem(seed=0, m=(14, 12), n=600):
     return grid, X, y, hyp
 
 
+@pytest.mark.parametrize("interp", ["cubic", "linear"])
 @pytest.mark.parametrize("m", [(30,), (14, 12), (6, 7, 5)])
-def test_m_space_mean_equals_dense_ski(m):
+def test_m_space_mean_equals_dense_ski(m, interp):
     grid, X, y, hyp = small_problem(1, m, 500)
+    grid["interp"] = interp
     wtw, wty, yty = oracle.precompute(grid, X, y)
     mu, wtz, info = oracle.solve_mean(grid, hyp, wtw, wty, yty, tol=1e-13)
     mu_d, z_d, W = oracle.ski_dense_mean(grid, hyp, X, y)
