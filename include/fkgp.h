@@ -87,6 +87,16 @@ typedef struct {
 
 typedef struct fkgp_handle fkgp_handle;
 
+/* Interpolation scheme of W (Sec. 2.3: SKI may use any local scheme).
+ * Cubic: Keys' cubic convolution (a = -1/2), 4^d weights per point, W^T W
+ * within offsets -3..3 per dimension (Claim 2, r = 2).  Linear: 2^d weights
+ * per point (the nodes either side of the point in each dimension), W^T W
+ * within offsets -1..1 (r = 1).  Both use the same interpolable region
+ * (1 <= (x_k - origin_k) / spacing_k <= m_k - 2) and the same stencil-
+ * diagonal storage; for linear W^T W the offset slabs outside -1..1 are all
+ * zero and the products skip them through the block mask. */
+typedef enum { FKGP_INTERP_CUBIC = 0, FKGP_INTERP_LINEAR = 1 } fkgp_interp;
+
 typedef struct {
     fkgp_dtype stats_dtype;  /* storage of W^T W and precision of the operator
                                 B(x) = ((K_G W^T W + s2 I)x, W^T W x); FP32
@@ -98,6 +108,8 @@ typedef struct {
     int keep_points;         /* 1: the handle also keeps the points in cell
                                 order (n * 4 values of the input dtype) and
                                 the cell bounds, for fkgp_ski_solve (d <= 2) */
+    int interp;              /* fkgp_interp: the interpolation scheme of W,
+                                used by every later call on the handle */
 } fkgp_precompute_opts;
 
 /* One-shot O(n) pass (Sec. 3.1 "Precomputation", Claim 2).
@@ -132,6 +144,7 @@ typedef struct {
                                 product reads only these (points that do not
                                 fill the grid's box leave whole blocks zero) */
     int64_t wtw_block_entries;  /* stored entries per block (64 * 49 or 64 * 7) */
+    int interp;              /* fkgp_interp of the handle */
 } fkgp_handle_desc;
 
 fkgp_status fkgp_describe(const fkgp_handle* h, fkgp_handle_desc* desc);
@@ -349,7 +362,8 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x,
 /* Saves the statistics of a handle (W^T W, its block mask, W^T y, y^T y, the
  * probe sketches, grid and sizes) to the file `path`, so that they are
  * computed once and reused by later sessions (Sec. 5, "Very large n").  A
- * fixed header ("FKGPSTAT", version 1) and the arrays in host byte order;
+ * fixed 136-byte header ("FKGPSTAT", version 2; it also records the
+ * interpolation scheme) and the arrays in host byte order;
  * kept points are not saved.  Synchronises `stream`.  FKGP_EINVAL if the file
  * cannot be written. */
 fkgp_status fkgp_save(const fkgp_handle* h, const char* path, void* stream);

@@ -58,7 +58,16 @@ KERNELS = {"se": 0, "matern12": 1, "matern32": 2, "matern52": 3}
 
 class _PreOpts(ctypes.Structure):
     _fields_ = [("stats_dtype", ctypes.c_int), ("n_probes", ctypes.c_int),
-                ("probe_seed", ctypes.c_uint64), ("keep_points", ctypes.c_int)]
+                ("probe_seed", ctypes.c_uint64), ("keep_points", ctypes.c_int),
+                ("interp", ctypes.c_int)]
+
+
+#: interpolation schemes (fkgp_interp); a grid dict selects one with "interp"
+INTERP = {"cubic": 0, "linear": 1}
+
+
+def _interp_code(grid):
+    return INTERP[grid.get("interp", "cubic")]
 
 
 class _Desc(ctypes.Structure):
@@ -67,7 +76,7 @@ class _Desc(ctypes.Structure):
                 ("yty", ctypes.c_double), ("bytes_wtw", ctypes.c_int64),
                 ("nnz_wtw", ctypes.c_int64), ("halo", ctypes.c_int64),
                 ("wtw_blocks", ctypes.c_int64), ("wtw_blocks_nonzero", ctypes.c_int64),
-                ("wtw_block_entries", ctypes.c_int64)]
+                ("wtw_block_entries", ctypes.c_int64), ("interp", ctypes.c_int)]
 
 
 OP_F64, OP_STATS = 0, 1
@@ -224,6 +233,7 @@ class Handle:
         self.wtw_blocks = d.wtw_blocks
         self.wtw_blocks_nonzero = d.wtw_blocks_nonzero
         self.wtw_block_entries = d.wtw_block_entries
+        self.interp = "linear" if d.interp == INTERP["linear"] else "cubic"
 
     @property
     def ptr(self):
@@ -256,7 +266,8 @@ def precompute(grid, x, y, stats_dtype=torch.float32, n_probes=0, probe_seed=0,
         assert t.dtype == y.dtype and t.numel() == n and t.is_cuda
     arr = (ctypes.c_void_p * 3)(*([t.data_ptr() for t in xs] + [0] * (3 - d)))
     g = _grid_struct(grid)
-    o = _PreOpts(_dtype_code(stats_dtype), int(n_probes), int(probe_seed), int(bool(keep_points)))
+    o = _PreOpts(_dtype_code(stats_dtype), int(n_probes), int(probe_seed), int(bool(keep_points)),
+                 _interp_code(grid))
     out = ctypes.c_void_p()
     _check(L.fkgp_precompute(ctypes.byref(g), arr, _ptr(y), n, dt, ctypes.byref(o), _stream(),
                              ctypes.byref(out)))
@@ -277,7 +288,7 @@ def precompute_host(grid, x, y, stats_dtype=torch.float32, chunk=0):
     dt = F32 if yv.dtype == np.float32 else F64
     arr = (ctypes.c_void_p * 3)(*([t.ctypes.data for t in xs] + [0] * (3 - d)))
     g = _grid_struct(grid)
-    o = _PreOpts(_dtype_code(stats_dtype), 0, 0, 0)
+    o = _PreOpts(_dtype_code(stats_dtype), 0, 0, 0, _interp_code(grid))
     out = ctypes.c_void_p()
     _check(L.fkgp_precompute_host(ctypes.byref(g), arr, yv.ctypes.data, n, dt, ctypes.byref(o),
                                   int(chunk), _stream(), ctypes.byref(out)))
@@ -324,8 +335,9 @@ def solve(h, hypers, rhs=None, tol=1e-6, maxiter=1000, op_precision="f64"):
 
 
 # header of a statistics file (fkgp_save): magic, version, d, m[3], origin[3],
-# spacing[3], n, stats dtype, probes, probe seed, y^T y, nonzero blocks
-_STATS_HEADER = struct.Struct("<8sIi3q3d3dqiiQdq")
+# spacing[3], n, stats dtype, probes, probe seed, y^T y, nonzero blocks,
+# interpolation scheme, reserved
+_STATS_HEADER = struct.Struct("<8sIi3q3d3dqiiQdqii")
 
 
 def save(h, path):
@@ -343,6 +355,8 @@ def load(path):
     d = hd[2]
     grid = {"d": d, "m": list(hd[3:6])[:d], "origin": list(hd[6:9])[:d],
             "spacing": list(hd[9:12])[:d]}
+    if hd[18] == INTERP["linear"]:
+        grid["interp"] = "linear"
     return Handle(out, grid)
 
 

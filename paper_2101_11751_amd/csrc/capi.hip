@@ -251,6 +251,7 @@ hipError_t convert_any(const void* in, fkgp_dtype din, void* out, fkgp_dtype dou
 // Host helpers
 // ---------------------------------------------------------------------------
 fkgp_status grid_from_abi(const fkgp_grid* gr, GridDev& g, int64_t& M) {
+    g.interp = 0;
     if (!gr) {
         set_error("grid is NULL");
         return FKGP_EINVAL;
@@ -965,8 +966,11 @@ struct StatsFileHeader {
     uint64_t seed;
     double yty;
     int64_t nzblocks;
+    int32_t interp;    // 0: cubic, 1: linear
+    int32_t reserved;
 };
-constexpr uint32_t kStatsFileVersion = 1;
+constexpr uint32_t kStatsFileVersion = 2;
+static_assert(sizeof(StatsFileHeader) == 136, "statistics file header layout");
 
 struct StatsSections {
     size_t a, mask, wty, sk;
@@ -1032,8 +1036,13 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
                     return FKGP_EINVAL;
                 }
         }
-        fkgp_precompute_opts o{FKGP_F32, 0, 0, 0};
+        fkgp_precompute_opts o{FKGP_F32, 0, 0, 0, FKGP_INTERP_CUBIC};
         if (opts) o = *opts;
+        if (o.interp != FKGP_INTERP_CUBIC && o.interp != FKGP_INTERP_LINEAR) {
+            set_error("interp must be FKGP_INTERP_CUBIC or FKGP_INTERP_LINEAR");
+            return FKGP_EINVAL;
+        }
+        g.interp = o.interp;
         if (o.keep_points != 0 && o.keep_points != 1) {
             set_error("keep_points must be 0 or 1");
             return FKGP_EINVAL;
@@ -1142,6 +1151,7 @@ fkgp_status fkgp_describe(const fkgp_handle* h, fkgp_handle_desc* desc) {
     desc->wtw_blocks = mask_words(h->M) * (kRowTile / kWaveRows) * slabs;
     desc->wtw_blocks_nonzero = h->nzblocks;
     desc->wtw_block_entries = (int64_t)kWaveRows * mask_slab_width(h->g.d);
+    desc->interp = h->g.interp;
     return FKGP_OK;
 }
 
@@ -1378,8 +1388,13 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
                     return FKGP_EINVAL;
                 }
         }
-        fkgp_precompute_opts o{FKGP_F32, 0, 0, 0};
+        fkgp_precompute_opts o{FKGP_F32, 0, 0, 0, FKGP_INTERP_CUBIC};
         if (opts) o = *opts;
+        if (o.interp != FKGP_INTERP_CUBIC && o.interp != FKGP_INTERP_LINEAR) {
+            set_error("interp must be FKGP_INTERP_CUBIC or FKGP_INTERP_LINEAR");
+            return FKGP_EINVAL;
+        }
+        g.interp = o.interp;
         if (o.stats_dtype != FKGP_F32 && o.stats_dtype != FKGP_F64) {
             set_error("stats dtype must be FKGP_F32 or FKGP_F64");
             return FKGP_EINVAL;
@@ -1559,6 +1574,8 @@ fkgp_status fkgp_save(const fkgp_handle* h, const char* path, void* stream) {
         hd.seed = h->seed;
         hd.yty = h->yty;
         hd.nzblocks = h->nzblocks;
+        hd.interp = h->g.interp;
+        hd.reserved = 0;
         const StatsSections sec = stats_sections(h);
         std::vector<unsigned char> buf(sec.total());
         unsigned char* p = buf.data();
@@ -1620,10 +1637,12 @@ fkgp_status fkgp_load(const char* path, void* stream, fkgp_handle** out) {
         fkgp_status st = grid_from_abi(&gr, g, M);
         if (st != FKGP_OK) return st;
         if (hd.n < 0 || (hd.stats_dtype != FKGP_F32 && hd.stats_dtype != FKGP_F64) ||
-            hd.nprobe < 0 || hd.nprobe > kMaxProbes || hd.nzblocks < 0) {
+            hd.nprobe < 0 || hd.nprobe > kMaxProbes || hd.nzblocks < 0 ||
+            (hd.interp != FKGP_INTERP_CUBIC && hd.interp != FKGP_INTERP_LINEAR)) {
             set_error(std::string(path) + ": corrupt header");
             return FKGP_EINVAL;
         }
+        g.interp = hd.interp;
         for (int k = 0; k < g.d; ++k)
             if (circulant_log2(g.m[k]) > kMaxLineLog2) {
                 set_error(std::string(path) + ": grid dimension longer than 8192 nodes");

@@ -17,7 +17,27 @@ struct GridDev {
     int nc[3];      // cells per dimension (m - 3)
     double g0[3];   // origin
     double h[3];    // spacing
+    int interp;     // 0: Keys cubic convolution, 1: linear interpolation
 };
+
+// Weights of the nodes i-1, i, i+1, i+2 of a point at fractional offset t in
+// [0, 1] from node i: Keys' cubic convolution (a = -1/2; Sec. 3, Fig. 1), or
+// linear interpolation between i and i+1 (Sec. 2.3: 2^d nonzeros per row of
+// W), kept in the same four-node frame with zero outer weights.
+__device__ inline void stencil_weights(int interp, double t, double w[4]) {
+    if (interp == 1) {
+        w[0] = 0.0;
+        w[1] = 1.0 - t;
+        w[2] = t;
+        w[3] = 0.0;
+        return;
+    }
+    const double t2 = t * t, t3 = t2 * t;
+    w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
+    w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+    w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+    w[3] = 0.5 * (t3 - t2);
+}
 
 constexpr int kMaxProbes = 31;
 

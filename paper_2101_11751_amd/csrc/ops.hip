@@ -649,14 +649,6 @@ __global__ __launch_bounds__(256) void spmv_multi_kernel(const TA* __restrict__ 
 // ---------------------------------------------------------------------------
 // Interpolation mu(x) = sum_a w_a(x) mu_G[node_a] (FP64).
 // ---------------------------------------------------------------------------
-__device__ inline void keys4(double t, double w[4]) {
-    const double t2 = t * t, t3 = t2 * t;
-    w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
-    w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
-    w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
-    w[3] = 0.5 * (t3 - t2);
-}
-
 template <class Tin>
 __global__ void interp_kernel(GridDev g, const double* __restrict__ mu, const Tin* x0,
                               const Tin* x1, const Tin* x2, int64_t nq,
@@ -676,7 +668,7 @@ __global__ void interp_kernel(GridDev g, const double* __restrict__ mu, const Ti
         int b = (int)floor(u);
         if (b > g.m[k] - 3) b = g.m[k] - 3;
         base[k] = b;
-        keys4(u - (double)b, w[k]);
+        stencil_weights(g.interp, u - (double)b, w[k]);
     }
     if (!ok) {
         atomicMin(bad, (unsigned long long)i);
@@ -723,7 +715,7 @@ __global__ void weights_kernel(GridDev g, const Tin* x0, const Tin* x1, const Ti
         int b = (int)floor(u);
         if (b > g.m[k] - 3) b = g.m[k] - 3;
         base[k] = b;
-        keys4(u - (double)b, w[k]);
+        stencil_weights(g.interp, u - (double)b, w[k]);
     }
     const int e1 = g.d > 1 ? 4 : 1, e2 = g.d > 2 ? 4 : 1;
     double* Gi = G + i * M;
@@ -764,7 +756,7 @@ __global__ void stencil_kernel(GridDev g, const Tin* x0, const Tin* x1, const Ti
             }
             int b = (int)floor(u);
             if (b > g.m[k] - 3) b = g.m[k] - 3;
-            keys4(u - (double)b, wk);
+            stencil_weights(g.interp, u - (double)b, wk);
             f = b - 1;
         }
         first[i * 3 + k] = f;

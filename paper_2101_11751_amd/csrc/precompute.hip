@@ -29,19 +29,25 @@ namespace {
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------
-// Keys cubic convolution (a = -1/2) as polynomials in t (ascending powers):
-// weights of the nodes i-1, i, i+1, i+2 of a point at offset t from node i.
+// Interpolation weights as polynomials in t (ascending powers): weights of
+// the nodes i-1, i, i+1, i+2 of a point at offset t from node i; Keys cubic
+// convolution (a = -1/2), or linear interpolation (1 - t, t on i, i+1).
 // ---------------------------------------------------------------------------
 struct KeysTables {
     double E[7][4][7];   // [o+3][a][q]: coeff of t^q in w_a(t) w_{a+o}(t)
     double C[4][4];      // [a][q]: coeff of t^q in w_a(t)
 };
 
-KeysTables make_tables() {
-    const double w[4][4] = {{0.0, -0.5, 1.0, -0.5},
-                            {1.0, 0.0, -2.5, 1.5},
-                            {0.0, 0.5, 2.0, -1.5},
-                            {0.0, 0.0, -0.5, 0.5}};
+KeysTables make_tables(int interp) {
+    const double keys[4][4] = {{0.0, -0.5, 1.0, -0.5},
+                               {1.0, 0.0, -2.5, 1.5},
+                               {0.0, 0.5, 2.0, -1.5},
+                               {0.0, 0.0, -0.5, 0.5}};
+    const double lin[4][4] = {{0.0, 0.0, 0.0, 0.0},
+                              {1.0, -1.0, 0.0, 0.0},
+                              {0.0, 1.0, 0.0, 0.0},
+                              {0.0, 0.0, 0.0, 0.0}};
+    const double (&w)[4][4] = interp == 1 ? lin : keys;
     KeysTables t{};
     for (int a = 0; a < 4; ++a)
         for (int q = 0; q < 4; ++q) t.C[a][q] = w[a][q];
@@ -1043,7 +1049,7 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         Myy = cc->acc_yy;
     }
 
-    const KeysTables tab = make_tables();
+    const KeysTables tab = make_tables(g.interp);
     // --- W^T W: stages over k = d-1 .. 0 ---
     {
         Dims3 cur{{1, 1, 1}};
@@ -1178,14 +1184,6 @@ __global__ __launch_bounds__(64) void ski_cell_moments(
     }
 }
 
-__device__ inline void keys_weights(double t, double w[4]) {
-    const double t2 = t * t, t3 = t2 * t;
-    w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
-    w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
-    w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
-    w[3] = 0.5 * (t3 - t2);
-}
-
 template <class Tin, int D>
 __global__ void ski_interp(const typename PayloadOf<Tin>::type* __restrict__ pay, int64_t n,
                            GridDev g, const double* __restrict__ gv,
@@ -1202,7 +1200,7 @@ __global__ void ski_interp(const typename PayloadOf<Tin>::type* __restrict__ pay
             base[k] = 1;   // not reached: the precompute rejected such points
             t = 0.0;
         }
-        keys_weights(t, w[k]);
+        stencil_weights(g.interp, t, w[k]);
     }
     double acc = 0.0;
     if (D == 1) {
@@ -1256,7 +1254,7 @@ fkgp_status ski_wt(const GridDev& g, fkgp_dtype in, const void* pay, const uint3
         return FKGP_EINVAL;
     }
     FKGP_HIP(hipGetLastError());
-    const KeysTables tab = make_tables();
+    const KeysTables tab = make_tables(g.interp);
     Dims3 cur{{1, 1, 1}};
     for (int k = 0; k < d; ++k) cur.n[k] = g.nc[k];
     const double* src = R;

@@ -90,4 +90,4 @@ def test_load_rejects_bad_files(tmp_path):
     short.write_bytes(b"FKGPSTAT")
     assert L.fkgp_load(str(short).encode(), None, ctypes.byref(out)) == P.EINVAL
     assert L.fkgp_save(None, b"x", None) == P.EINVAL
-    assert P._STATS_HEADER.size == 128
+    assert P._STATS_HEADER.size == 136
