@@ -1744,7 +1744,10 @@ namespace fkgp {
 namespace {
 
 // Right-hand side j: ||b||^2 = bb[j] when given (grid right-hand sides
-// b = W v), else n (a Rademacher probe).
+// b = W v), else n (a Rademacher probe).  A grid right-hand side starts as
+// r = W v (c_r = c_p = 0, r_hat = v), so every later residual stays W r_hat
+// and ||r||^2 = r_hat . W^T W r_hat has no cancelling b-terms; a probe
+// starts as r = z (r_hat = 0, c_r = c_p = 1).
 __global__ void probe_init(PState* ps, int N, double n, double tol,
                            const double* __restrict__ bb) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1753,8 +1756,8 @@ __global__ void probe_init(PState* ps, int N, double n, double tol,
     PState s{};
     s.bb = b2;
     s.rho = b2;
-    s.cr = 1.0;
-    s.cp = 1.0;
+    s.cr = bb ? 0.0 : 1.0;
+    s.cp = bb ? 0.0 : 1.0;
     s.eps = tol * tol * b2;
     s.done = b2 > 0 ? 0 : 1;
     ps[j] = s;
@@ -2030,13 +2033,14 @@ fkgp_status dots_dev(const double* A, const double* B, int64_t M, int k, double*
 }
 
 // Factorized CG from x_0 = 0 for N right-hand sides b_j at once, given
-// b_hat_j = W^T b_j (bh [N][M]) and ||b_j||^2 (bb_dev [N] on the device; null:
-// Rademacher probes, ||z_j||^2 = n).  Outputs W^T x_j (wx [N][M]), the CG
-// coefficients and the final states.
+// b_hat_j = W^T b_j (bh [N][M]).  Rademacher probes (v = null): ||z_j||^2 = n.
+// Grid right-hand sides b_j = W v_j (v0 [N][M], bh = W^T W v, bb_dev [N] =
+// v_j . bh_j on the device): the iteration starts from r_hat = v.  Outputs
+// W^T x_j (wx [N][M]), the CG coefficients and the final states.
 fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double tol,
                      int maxiter, double* wx, double* alphas, double* betas, PState* ps,
                      Scratch& sc, hipStream_t st, int& iters_max,
-                     const double* bb_dev = nullptr) {
+                     const double* bb_dev = nullptr, const double* v0 = nullptr) {
     const fkgp_handle* h = c.h;
     const int64_t M = c.M;
     const int64_t ldx = M + 2 * c.halo;
@@ -2058,6 +2062,13 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
     // kappa_b = K_G W^T z_j (FP64)
     fkgp_status rs = kg_apply(h->g, c.sp64, FKGP_F64, bh, kb, N, c.so, nullptr, 0.0, nullptr, st);
     if (rs != FKGP_OK) return rs;
+    if (v0) {
+        // r_hat = v, u_r = W^T W v = bh, v_r = K_G u_r + s2 r_hat
+        FKGP_HIP(hipMemcpyAsync(rh, v0, sizeof(double) * M * N, hipMemcpyDeviceToDevice, st));
+        FKGP_HIP(hipMemcpyAsync(ur, bh, sizeof(double) * M * N, hipMemcpyDeviceToDevice, st));
+        rs = kg_apply(h->g, c.sp64, FKGP_F64, bh, vr, N, c.so, v0, c.s2, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+    }
     probe_init<<<(N + 63) / 64, 64, 0, st>>>(ps, N, n, tol, bb_dev);
     FKGP_HIP(hipGetLastError());
     const dim3 gv(nbv, N);
@@ -2623,7 +2634,8 @@ fkgp_status posterior_cov_impl(const fkgp_handle* h, const fkgp_hypers* hyp,
         if (rs != FKGP_OK) return rs;
         int it = 0;
         const fkgp_status cres = probe_cg(c, BH, nr, (double)h->n, tol, maxiter,
-                                          WX + (int64_t)q0 * M, alphas, betas, ps, sj, st, it, bb);
+                                          WX + (int64_t)q0 * M, alphas, betas, ps, sj, st, it, bb,
+                                          Vq);
         if (cres != FKGP_OK && cres != FKGP_ENOTCONV) return cres;
         conv &= cres == FKGP_OK;
         iters_max = std::max(iters_max, it);
