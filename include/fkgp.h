@@ -52,9 +52,10 @@ typedef enum {
 
 typedef enum { FKGP_F32 = 0, FKGP_F64 = 1 } fkgp_dtype;
 
-/* Equispaced grid, 1 <= d <= 3, 4 <= m[k] <= 8192 (the K_G line FFTs embed
- * each dimension in a circulant of at most 16384 points; fkgp_precompute
- * returns FKGP_EINVAL beyond that), spacing[k] > 0.  A point x is
+/* Equispaced grid, 1 <= d <= 3, 4 <= m[k] <= 65536 (the K_G line FFTs embed
+ * each dimension in a circulant of at most 131072 points; fkgp_precompute
+ * returns FKGP_EINVAL beyond that; fkgp_batch_mll_and_grad takes dimensions
+ * of at most 8192 nodes), spacing[k] > 0.  A point x is
  * interpolable iff 1 <= (x_k - origin_k)/spacing_k <= m_k - 2 for every k, so
  * that all four cubic stencil nodes exist. */
 typedef struct {

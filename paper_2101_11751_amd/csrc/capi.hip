@@ -325,8 +325,10 @@ fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtyp
     const size_t es = dsize(dt);
     for (int k = 0; k < h->g.d; ++k) {
         sp.log2L[k] = circulant_log2(h->g.m[k]);
-        if (sp.log2L[k] > kMaxLineLog2) {
-            set_error("grid dimension longer than 8192 nodes is not supported by the line FFT");
+        if (sp.log2L[k] > (reg_max == kMaxRegLog2 ? kMaxLineLog2 : kMaxBatchLineLog2)) {
+            set_error(reg_max == kMaxRegLog2
+                          ? "grid dimension longer than 65536 nodes is not supported by the line FFT"
+                          : "the batched solver takes grid dimensions of at most 8192 nodes");
             return FKGP_EINVAL;
         }
         sp.L[k] = 1 << sp.log2L[k];
@@ -348,7 +350,7 @@ fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtyp
             }
         }
         fkgp_status st = build_spectrum(h->g, k, hyp->lengthscale[k], k == dderiv, hyp->kernel,
-                                        dt, lam, sp.log2L[k], sp.lg1[k], sc.s);
+                                        dt, lam, sp.log2L[k], sp.lg1[k], sp.scr[k], sc.s);
         if (st != FKGP_OK) return st;
         st = build_twiddles(sp.log2L[k], dt, tw, sc.s);
         if (st != FKGP_OK) return st;
@@ -1065,7 +1067,7 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
         }
         for (int k = 0; k < g.d; ++k)
             if (circulant_log2(g.m[k]) > kMaxLineLog2) {
-                set_error("grid dimension longer than 8192 nodes is not supported");
+                set_error("grid dimension longer than 65536 nodes is not supported");
                 return FKGP_EINVAL;
             }
         hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1410,7 +1412,7 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
         }
         for (int k = 0; k < g.d; ++k)
             if (circulant_log2(g.m[k]) > kMaxLineLog2) {
-                set_error("grid dimension longer than 8192 nodes is not supported");
+                set_error("grid dimension longer than 65536 nodes is not supported");
                 return FKGP_EINVAL;
             }
         hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1645,7 +1647,7 @@ fkgp_status fkgp_load(const char* path, void* stream, fkgp_handle** out) {
         g.interp = hd.interp;
         for (int k = 0; k < g.d; ++k)
             if (circulant_log2(g.m[k]) > kMaxLineLog2) {
-                set_error(std::string(path) + ": grid dimension longer than 8192 nodes");
+                set_error(std::string(path) + ": grid dimension longer than 65536 nodes");
                 return FKGP_EINVAL;
             }
         fkgp_handle* h = new fkgp_handle();

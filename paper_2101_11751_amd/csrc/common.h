@@ -252,13 +252,18 @@ fkgp_status run_precompute(const GridDev& g, const void* const* x, const void* y
 
 // ---- operators (ops.hip) -------------------------------------------------
 // Longest circulant handled by the register-resident line FFT, and by the
-// four-step path (grid dimensions up to 8192 nodes).
+// four-step path (grid dimensions up to 65536 nodes; the batched solver's
+// passes up to 8192).
 constexpr int kMaxRegLog2 = 11;
 // Dimensions with at most kFewLines lines per vector and circulants of at
 // least 2^kFewLinesMinLog2 points also take the four-step path.
 constexpr int kFewLinesMinLog2 = 10;
 constexpr int64_t kFewLines = 64;
-constexpr int kMaxLineLog2 = 14;
+constexpr int kMaxLineLog2 = 17;
+constexpr int kMaxBatchLineLog2 = 14;
+// Spectra of circulants up to 2^kMaxDftLog2 points are direct FP64 sums;
+// longer ones come from a forward four-step FFT of the embedded column.
+constexpr int kMaxDftLog2 = 14;
 // Workgroups (each with its own L-point complex scratch) of a four-step pass.
 constexpr int kLongWGs = 256;
 
@@ -282,9 +287,12 @@ struct Spectra {
 
 int circulant_log2(int m);
 // Builds lam[k] for dimension k from the column of the 1-D kernel `kind`
-// (fkgp_kernel; deriv: its derivative in log l).  Runs on the device (FP64 direct DFT).
+// (fkgp_kernel; deriv: its derivative in log l).  Runs on the device in
+// FP64: direct DFT sums, or (log2L > kMaxDftLog2) a four-step FFT through
+// `scr` (at least L FP64 complex values).
 fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv, int kind,
-                           fkgp_dtype dt, void* lam, int log2L, int lg1, hipStream_t s);
+                           fkgp_dtype dt, void* lam, int log2L, int lg1, void* scr,
+                           hipStream_t s);
 fkgp_status build_twiddles(int log2L, fkgp_dtype dt, void* tw, hipStream_t s);
 
 // y = scale * (T_0 (x) .. (x) T_{d-1}) x (+ add_coef * addv), batched over k

@@ -305,8 +305,11 @@ fkgp_status launch_line_conv(int log2L, int lg1, const T* in, T* out, const Line
             FKGP_LL(12, 6, 6)
             FKGP_LL(13, 6, 7)
             FKGP_LL(14, 7, 7)
+            FKGP_LL(15, 7, 8)
+            FKGP_LL(16, 8, 8)
+            FKGP_LL(17, 8, 9)
             default:
-                set_error("grid dimension too long for the line FFT (at most 8192 nodes)");
+                set_error("grid dimension too long for the line FFT (at most 65536 nodes)");
                 return FKGP_EINVAL;
         }
 #undef FKGP_LL
@@ -405,6 +408,63 @@ __global__ void spectrum_kernel(T* __restrict__ lam_br, int log2L, int lg1, int 
         acc += (L - j == j) ? v * c : 2.0 * v * c;
     }
     lam_br[e] = (T)(acc / (double)L);
+}
+
+// The same spectrum for a long circulant (four-step order, lg1 = LG1) from
+// its forward four-step FFT, one workgroup: (1) length-L1 DIF over n1 of the
+// embedded column c_emb[L2 n1 + n2] for every n2, times w_L^{n2 k1}; (2) per
+// row p1, length-L2 DIF over n2, which leaves lambda[k1 + L1 k2] at
+// (p1, p2) with k1 = bitrev(p1), k2 = bitrev(p2).  FP64 throughout, with
+// twiddles from sincospi; Y: L complex FP64 scratch.
+template <class T, int LG1, int LG2>
+__global__ __launch_bounds__(1024) void spectrum_long_kernel(T* __restrict__ lam, int m,
+                                                             double h, double ell, bool deriv,
+                                                             int kind,
+                                                             cplx<double>* __restrict__ Y) {
+    constexpr int L1 = 1 << LG1, L2 = 1 << LG2, L = L1 * L2;
+    constexpr int R1 = line_regs<LG1>(), R2 = line_regs<LG2>();
+    static_assert(L1 >= 64 && L2 >= 64, "one column or row per wave");
+    __shared__ cplx<double> tw1[L1 / 2], tw2[L2 / 2];
+    for (int t = threadIdx.x; t < L1 / 2; t += blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * (double)t / (double)L1, &sn, &cs);
+        tw1[t] = {cs, -sn};
+    }
+    for (int t = threadIdx.x; t < L2 / 2; t += blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * (double)t / (double)L2, &sn, &cs);
+        tw2[t] = {cs, -sn};
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int n2 = wave; n2 < L2; n2 += nw) {
+        cplx<double> z[R1];
+#pragma unroll
+        for (int q = 0; q < R1; ++q) {
+            const int n = L2 * (q * 64 + lane) + n2;
+            const int j = min(n, L - n);
+            z[q] = {j < m ? kernel_col(kind, j, h, ell, deriv) : 0.0, 0.0};
+        }
+        dif_regs<double, LG1>(z, lane, tw1);
+#pragma unroll
+        for (int q = 0; q < R1; ++q) {
+            const int p1 = q * 64 + lane;
+            const unsigned long long t =
+                ((unsigned long long)n2 * bitrev_bits((unsigned)p1, LG1)) & (unsigned long long)(L - 1);
+            double sn, cs;
+            sincospi(2.0 * (double)t / (double)L, &sn, &cs);
+            Y[p1 * L2 + n2] = cmul(z[q], cplx<double>{cs, -sn});
+        }
+    }
+    __syncthreads();
+    for (int p1 = wave; p1 < L1; p1 += nw) {
+        cplx<double> z[R2];
+#pragma unroll
+        for (int q = 0; q < R2; ++q) z[q] = Y[p1 * L2 + q * 64 + lane];
+        dif_regs<double, LG2>(z, lane, tw2);
+#pragma unroll
+        for (int q = 0; q < R2; ++q) lam[p1 * L2 + q * 64 + lane] = (T)(z[q].re / (double)L);
+    }
 }
 
 template <class T>
@@ -900,9 +960,45 @@ int circulant_log2(int m) {
     return l;
 }
 
+template <class T>
+static fkgp_status launch_spectrum_long(T* lam, int log2L, int m, double h, double ell,
+                                        bool deriv, int kind, cplx<double>* Y, hipStream_t s) {
+    switch (log2L) {
+        case 15:
+            spectrum_long_kernel<T, 7, 8><<<1, 1024, 0, s>>>(lam, m, h, ell, deriv, kind, Y);
+            break;
+        case 16:
+            spectrum_long_kernel<T, 8, 8><<<1, 1024, 0, s>>>(lam, m, h, ell, deriv, kind, Y);
+            break;
+        case 17:
+            spectrum_long_kernel<T, 8, 9><<<1, 1024, 0, s>>>(lam, m, h, ell, deriv, kind, Y);
+            break;
+        default:
+            set_error("no long-circulant spectrum for this length");
+            return FKGP_EINVAL;
+    }
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
 fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv, int kind,
-                           fkgp_dtype dt, void* lam, int log2L, int lg1, hipStream_t s) {
+                           fkgp_dtype dt, void* lam, int log2L, int lg1, void* scr,
+                           hipStream_t s) {
     const int L = 1 << log2L;
+    if (log2L > kMaxDftLog2) {
+        int want1, want2;
+        long_split(log2L, want1, want2);
+        if (!scr || lg1 != want1) {
+            set_error("long circulant spectrum needs the four-step order and its scratch");
+            return FKGP_EINVAL;
+        }
+        cplx<double>* Y = static_cast<cplx<double>*>(scr);
+        if (dt == FKGP_F32)
+            return launch_spectrum_long<float>(static_cast<float*>(lam), log2L, g.m[k], g.h[k],
+                                               ell, deriv, kind, Y, s);
+        return launch_spectrum_long<double>(static_cast<double*>(lam), log2L, g.m[k], g.h[k],
+                                            ell, deriv, kind, Y, s);
+    }
     const unsigned grid = (unsigned)((L + 255) / 256);
     if (dt == FKGP_F32)
         spectrum_kernel<float><<<grid, 256, 0, s>>>(static_cast<float*>(lam), log2L, lg1,

@@ -56,11 +56,11 @@ def test_host_validation_without_device():
     # n > 0 requires pointers
     assert L.fkgp_precompute(ctypes.byref(g), None, None, 10, 0, None, None,
                              ctypes.byref(out)) == P.EINVAL
-    # grid lines longer than the line FFT supports (circulant > 16384 points)
-    g.m[1] = 8193
+    # grid lines longer than the line FFT supports (circulant > 131072 points)
+    g.m[1] = 65537
     assert L.fkgp_precompute(ctypes.byref(g), None, None, 0, 0, None, None,
                              ctypes.byref(out)) == P.EINVAL
-    assert b"8192" in L.fkgp_last_error()
+    assert b"65536" in L.fkgp_last_error()
     assert L.fkgp_precompute(ctypes.byref(g), None, None, 0, 0, None, None, None) == P.EINVAL
     d = P._Desc()
     assert L.fkgp_describe(None, ctypes.byref(d)) == P.EINVAL

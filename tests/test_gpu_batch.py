@@ -69,6 +69,11 @@ def test_batch_deterministic_and_errors():
     h3, hyp3, *_ = problem(7, 2, [20, 20], 1000, 0)
     with pytest.raises(P.FkgpError):
         P.batch_mll_and_grad(hs + [h3], hyps + [hyp3])
+    # the batched passes take grid dimensions of at most 8192 nodes (the
+    # standalone solver goes to 65536)
+    h4, hyp4, *_ = problem(8, 1, [9000], 4000, 4)
+    with pytest.raises(P.FkgpError, match="8192"):
+        P.batch_mll_and_grad([h4], [hyp4])
 
 
 def test_batch_long_lines():

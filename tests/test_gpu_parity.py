@@ -101,7 +101,10 @@ def test_precompute_empty_and_out_of_grid():
                                  # four-step long lines: L = 4096, 8192, 16384; long
                                  # contiguous and long strided dimensions
                                  (1, [1500]), (1, [3000]), (1, [8192]), (2, [2100, 20]),
-                                 (2, [19, 2100]), (3, [4100, 4, 5])])
+                                 (2, [19, 2100]), (3, [4100, 4, 5]),
+                                 # L = 32768 .. 131072: spectra from the four-step FFT
+                                 (1, [12000]), (1, [30000]), (1, [65536]),
+                                 (2, [20000, 5]), (2, [5, 20000]), (3, [17000, 4, 4])])
 @pytest.mark.parametrize("stats", ["f64", "f32"])
 def test_kg_matvec_parity(d, m, stats):
     _need_gpu()
@@ -118,7 +121,7 @@ def test_kg_matvec_parity(d, m, stats):
         assert rel(out[r], ref[r]) <= tol
 
 
-@pytest.mark.parametrize("m", [[5000], [2500, 6]])
+@pytest.mark.parametrize("m", [[5000], [2500, 6], [20000], [40000, 4]])
 def test_solve_mean_long_lines(m):
     """Posterior mean with a grid dimension on the four-step line FFT."""
     _need_gpu()
