@@ -248,9 +248,9 @@ def ski_sweep(P, workloads, torch, dev, iters=200):
     paper's per-iteration comparison (Sec. 5, Fig. 2).  Each solve runs
     exactly `iters` iterations (tol 0) after a short warm-up; the time per
     iteration includes each solver's set-up, amortised over the iterations."""
-    cases = [(1024, "n"), (4096, "n"), (8192, "n"), (16384, "n/16"), (65536, "n/16"),
-             (131072, "n/16"), (10_000, "sqrt(n)"), (1_000_000, "sqrt(n)"),
-             (64_000_000, "sqrt(n)")]
+    cases = [(1024, "n"), (4096, "n"), (8192, "n"), (32768, "n"), (65536, "n"),
+             (16384, "n/16"), (65536, "n/16"), (131072, "n/16"), (1_048_576, "n/16"),
+             (10_000, "sqrt(n)"), (1_000_000, "sqrt(n)"), (64_000_000, "sqrt(n)")]
     out = []
     for n, rule in cases:
         m = n if rule == "n" else (n // 16 if rule == "n/16" else int(round(math.sqrt(n))))
@@ -281,15 +281,15 @@ def cov_leg(P, workloads, torch, dev, nq=691, tol=1e-10, maxiter=20000):
     """Exact SKI posterior covariance between nq query points (one solve per
     query point; Sec. 5 computes a 691 x 691 matrix on the sound data, n =
     59.3K) on the synthetic sine of the same size, for a small and a large
-    grid (1-D grids are limited to 8192 nodes here): seconds per call after a
-    warm-up; then the rank-k covariance (k = min(m, 10000)) built from the
+    grid (m = 1000, 8000 and 60000, the paper's largest sound grid): seconds
+    per call after a warm-up; then the rank-k covariance (k = min(m, 10000)) built from the
     factorized Lanczos, its build and query times and its relative Frobenius
     distance from the exact matrix."""
     out = []
     g = torch.Generator(device=dev)
     g.manual_seed(5)
     xq = torch.rand(nq, generator=g, device=dev, dtype=torch.float64)
-    for m in (1000, 8000):
+    for m in (1000, 8000, 60000):
         wl = workloads.sine1d_grid(59_300, m, device=dev)
         h = P.precompute(wl["grid"], wl["x"], wl["y"], stats_dtype=torch.float64)
         hyp = wl["hypers"]

@@ -256,6 +256,139 @@ __global__ __launch_bounds__(BS) void line_conv_long(
     }
 }
 
+// Long lines with few line pairs: the three phases of the four-step
+// convolution (see wg_conv_long) as three launches, one column or row per
+// wave, so that a single long line spreads over the whole chip instead of
+// one workgroup.  Block b of a phase handles pair b / per_pair and the four
+// columns (rows) 4 (b % per_pair) .. + 3.  Y: L complex per pair.
+template <class T, int LG1, int LG2>
+__global__ __launch_bounds__(256) void fs_cols_fwd(const T* in, LineGeom lg,
+                                                   const cplx<T>* __restrict__ twh,
+                                                   const int* __restrict__ skip,
+                                                   cplx<T>* __restrict__ scr) {
+    constexpr int L1 = 1 << LG1, L2 = 1 << LG2, L = L1 * L2;
+    constexpr int R1 = line_regs<LG1>();
+    if (skip && *skip) return;
+    __shared__ cplx<T> tw1[L1 / 2];
+    for (int t = threadIdx.x; t < L1 / 2; t += 256) tw1[t] = twh[t * L2];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t pair = blockIdx.x / (L2 / 4);
+    const int n2 = (int)(blockIdx.x % (L2 / 4)) * 4 + wave;
+    const int64_t la = 2 * pair, lb = la + 1;
+    const bool hb = lb < lg.nlines;
+    const T* srcA = in + line_addr(lg, la, 0);
+    const T* srcB = hb ? in + line_addr(lg, lb, 0) : nullptr;
+    cplx<T> z[R1];
+#pragma unroll
+    for (int q = 0; q < R1; ++q) {
+        const int n = L2 * (q * 64 + lane) + n2;
+        z[q].re = (n < lg.m_line) ? srcA[(int64_t)n * lg.S] : T(0);
+        z[q].im = (n < lg.m_line && srcB) ? srcB[(int64_t)n * lg.S] : T(0);
+    }
+    dif_regs<T, LG1>(z, lane, tw1);
+    cplx<T>* Y = scr + pair * L;
+#pragma unroll
+    for (int q = 0; q < R1; ++q) {
+        const int p1 = q * 64 + lane;
+        unsigned t = ((unsigned)n2 * bitrev_bits((unsigned)p1, LG1)) & (unsigned)(L - 1);
+        cplx<T> w;
+        if (t < (unsigned)(L / 2)) {
+            w = twh[t];
+        } else {
+            const cplx<T> v = twh[t - L / 2];
+            w = {-v.re, -v.im};
+        }
+        Y[p1 * L2 + n2] = cmul(z[q], w);
+    }
+}
+
+template <class T, int LG1, int LG2>
+__global__ __launch_bounds__(256) void fs_rows(const cplx<T>* __restrict__ twh,
+                                               const T* __restrict__ lamp,
+                                               const int* __restrict__ skip,
+                                               cplx<T>* __restrict__ scr) {
+    constexpr int L1 = 1 << LG1, L2 = 1 << LG2, L = L1 * L2;
+    constexpr int R2 = line_regs<LG2>();
+    if (skip && *skip) return;
+    __shared__ cplx<T> tw2[L2 / 2];
+    for (int t = threadIdx.x; t < L2 / 2; t += 256) tw2[t] = twh[t * L1];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t pair = blockIdx.x / (L1 / 4);
+    const int p1 = (int)(blockIdx.x % (L1 / 4)) * 4 + wave;
+    cplx<T>* Y = scr + pair * L;
+    cplx<T> z[R2];
+#pragma unroll
+    for (int q = 0; q < R2; ++q) z[q] = Y[p1 * L2 + q * 64 + lane];
+    dif_regs<T, LG2>(z, lane, tw2);
+#pragma unroll
+    for (int q = 0; q < R2; ++q) {
+        const T lm = lamp[p1 * L2 + q * 64 + lane];
+        z[q].re *= lm;
+        z[q].im *= lm;
+    }
+    dit_regs<T, LG2>(z, lane, tw2);
+    const unsigned br = bitrev_bits((unsigned)p1, LG1);
+#pragma unroll
+    for (int q = 0; q < R2; ++q) {
+        const int n2 = q * 64 + lane;
+        const unsigned t = ((unsigned)n2 * br) & (unsigned)(L - 1);
+        cplx<T> w;
+        if (t < (unsigned)(L / 2)) {
+            w = twh[t];
+        } else {
+            const cplx<T> v = twh[t - L / 2];
+            w = {-v.re, -v.im};
+        }
+        Y[p1 * L2 + n2] = cmul_conj(z[q], w);
+    }
+}
+
+template <class T, int LG1, int LG2>
+__global__ __launch_bounds__(256) void fs_cols_inv(T* out, LineGeom lg,
+                                                   const cplx<T>* __restrict__ twh, T scale,
+                                                   const T* addv, T add_coef,
+                                                   const int* __restrict__ skip,
+                                                   const cplx<T>* __restrict__ scr) {
+    constexpr int L1 = 1 << LG1, L2 = 1 << LG2, L = L1 * L2;
+    constexpr int R1 = line_regs<LG1>();
+    if (skip && *skip) return;
+    __shared__ cplx<T> tw1[L1 / 2];
+    for (int t = threadIdx.x; t < L1 / 2; t += 256) tw1[t] = twh[t * L2];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t pair = blockIdx.x / (L2 / 4);
+    const int n2 = (int)(blockIdx.x % (L2 / 4)) * 4 + wave;
+    const int64_t la = 2 * pair, lb = la + 1;
+    const bool hb = lb < lg.nlines;
+    const int64_t ba = line_addr(lg, la, 0), bb = hb ? line_addr(lg, lb, 0) : 0;
+    const cplx<T>* Y = scr + pair * L;
+    cplx<T> z[R1];
+#pragma unroll
+    for (int q = 0; q < R1; ++q) z[q] = Y[(q * 64 + lane) * L2 + n2];
+    dit_regs<T, LG1>(z, lane, tw1);
+#pragma unroll
+    for (int q = 0; q < R1; ++q) {
+        const int n = L2 * (q * 64 + lane) + n2;
+        if (n >= lg.m_line) continue;
+        const int64_t o = (int64_t)n * lg.S;
+        T va = scale * z[q].re;
+        if (addv) va += add_coef * addv[ba + o];
+        out[ba + o] = va;
+        if (hb) {
+            T vb = scale * z[q].im;
+            if (addv) vb += add_coef * addv[bb + o];
+            out[bb + o] = vb;
+        }
+    }
+}
+
+// Few pairs of circulants of at least 2^kSplitPhasesLog2 points take the
+// three-launch path.
+constexpr int kSplitPhasesLog2 = 12;
+constexpr int64_t kSplitPhasesMaxPairs = 128;
+
 // Blocks of a barrier-free pass: one line pair per wave (64/L per wave for
 // L < 64), four waves per block.
 // Lines of at least kSplitLog2 points are split over two waves per pair.
@@ -287,6 +420,23 @@ fkgp_status launch_line_conv(int log2L, int lg1, const T* in, T* out, const Line
         const int64_t npairs = (lg.nlines + 1) / 2;
         const unsigned grid = (unsigned)std::min<int64_t>(npairs, kLongWGs);
         if (grid == 0) return FKGP_OK;
+        if (log2L >= kSplitPhasesLog2 && npairs <= kSplitPhasesMaxPairs) {
+#define FKGP_FS(LG, A, B)                                                                          case LG: {                                                                                         const unsigned gc = (unsigned)(npairs * ((1 << B) / 4));                                       const unsigned gr = (unsigned)(npairs * ((1 << A) / 4));                                       fs_cols_fwd<T, A, B><<<gc, 256, 0, s>>>(in, lg, tw, skip, scr);                                fs_rows<T, A, B><<<gr, 256, 0, s>>>(tw, lam, skip, scr);                                       fs_cols_inv<T, A, B><<<gc, 256, 0, s>>>(out, lg, tw, scale, addv, add_coef, skip, scr);         break;                                                                                     }
+            switch (log2L) {
+                FKGP_FS(12, 6, 6)
+                FKGP_FS(13, 6, 7)
+                FKGP_FS(14, 7, 7)
+                FKGP_FS(15, 7, 8)
+                FKGP_FS(16, 8, 8)
+                FKGP_FS(17, 8, 9)
+                default:
+                    set_error("no split four-step pass for this length");
+                    return FKGP_EINVAL;
+            }
+#undef FKGP_FS
+            FKGP_HIP(hipGetLastError());
+            return FKGP_OK;
+        }
         // few pairs: 16 waves per pair (the phases' independent columns and
         // rows spread over more waves); else 4 waves and more workgroups
         const bool wide = npairs <= kFewLines;

@@ -102,9 +102,12 @@ def test_precompute_empty_and_out_of_grid():
                                  # contiguous and long strided dimensions
                                  (1, [1500]), (1, [3000]), (1, [8192]), (2, [2100, 20]),
                                  (2, [19, 2100]), (3, [4100, 4, 5]),
-                                 # L = 32768 .. 131072: spectra from the four-step FFT
+                                 # L = 32768 .. 131072: spectra from the four-step FFT,
+                                 # few line pairs: the three-launch passes
                                  (1, [12000]), (1, [30000]), (1, [65536]),
-                                 (2, [20000, 5]), (2, [5, 20000]), (3, [17000, 4, 4])])
+                                 (2, [20000, 5]), (2, [5, 20000]), (3, [17000, 4, 4]),
+                                 # many long lines: one workgroup per line pair
+                                 (2, [16400, 300])])
 @pytest.mark.parametrize("stats", ["f64", "f32"])
 def test_kg_matvec_parity(d, m, stats):
     _need_gpu()
