@@ -151,3 +151,32 @@ def test_cov_dense_data_small_posterior():
     errk = np.abs(c.cov([torch.from_numpy(Xq[0]).cuda()]).cpu().numpy() - ref).max()
     print(f"rank {c.rank}: max error {errk:.3e}")
     assert errk <= 1e-6 * scale
+
+
+def test_cov_maximum_query_count_sampled():
+    """nq = 4096 (the largest call): 64 batches of right-hand sides and a
+    64 x 64 tiling of the pair matrix; sampled rows and columns against Fact
+    2's grid form, symmetry, and the rank-k covariance on the same points."""
+    _need_gpu()
+    rng = np.random.default_rng(31)
+    grid = oracle.make_grid([40, 30], lo=0.0, hi=1.0)
+    X = rng.uniform(0, 1, (2, 20000))
+    y = np.sin(5 * X[0]) + 0.2 * rng.standard_normal(20000)
+    Xq = rng.uniform(0, 1, (2, 4096))
+    hyp = {"lengthscale": [0.15, 0.12], "outputscale": 0.9, "noise": 0.25}
+    xs = [torch.from_numpy(X[k]).cuda() for k in range(2)]
+    xq = [torch.from_numpy(Xq[k]).cuda() for k in range(2)]
+    h = P.precompute(grid, xs, torch.from_numpy(y).cuda(), stats_dtype=torch.float64)
+    C, info = P.posterior_cov(h, hyp, xq, tol=1e-12, maxiter=20000)
+    assert info["converged"]
+    C = C.cpu().numpy()
+    assert np.array_equal(C, C.T)
+    idx = np.concatenate([np.arange(5), rng.choice(4096, 20, replace=False), [4095]])
+    ref = fact2_cov(grid, hyp, X, Xq[:, idx])
+    scale = np.abs(np.diag(ref)).max()
+    assert np.abs(C[np.ix_(idx, idx)] - ref).max() <= 1e-7 * scale
+    c = P.love_build(h, hyp, 120)
+    Ck = c.cov(xq).cpu().numpy()
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    ref_k = oracle.love_cov(grid, hyp, wtw, wty, yty, Xq[:, idx], c.rank)
+    assert np.abs(Ck[np.ix_(idx, idx)] - ref_k).max() <= 1e-8 * np.abs(np.diag(ref_k)).max()
