@@ -261,20 +261,22 @@ __global__ __launch_bounds__(BS) void line_conv_long(
 // wave, so that a single long line spreads over the whole chip instead of
 // one workgroup.  Block b of a phase handles pair b / per_pair and the four
 // columns (rows) 4 (b % per_pair) .. + 3.  Y: L complex per pair.
-template <class T, int LG1, int LG2>
-__global__ __launch_bounds__(256) void fs_cols_fwd(const T* in, LineGeom lg,
+template <class T, int LG1, int LG2, int BS>
+__global__ __launch_bounds__(BS) void fs_cols_fwd(const T* in, LineGeom lg,
                                                    const cplx<T>* __restrict__ twh,
                                                    const int* __restrict__ skip,
                                                    cplx<T>* __restrict__ scr) {
     constexpr int L1 = 1 << LG1, L2 = 1 << LG2, L = L1 * L2;
     constexpr int R1 = line_regs<LG1>();
+    constexpr int W = BS / 64;   // consecutive columns per block
     if (skip && *skip) return;
     __shared__ cplx<T> tw1[L1 / 2];
-    for (int t = threadIdx.x; t < L1 / 2; t += 256) tw1[t] = twh[t * L2];
+    for (int t = threadIdx.x; t < L1 / 2; t += BS) tw1[t] = twh[t * L2];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t pair = blockIdx.x / (L2 / 4);
-    const int n2 = (int)(blockIdx.x % (L2 / 4)) * 4 + wave;
+    const unsigned b = xcd_block();
+    const int64_t pair = b / (L2 / W);
+    const int n2 = (int)(b % (L2 / W)) * W + wave;
     const int64_t la = 2 * pair, lb = la + 1;
     const bool hb = lb < lg.nlines;
     const T* srcA = in + line_addr(lg, la, 0);
@@ -315,8 +317,9 @@ __global__ __launch_bounds__(256) void fs_rows(const cplx<T>* __restrict__ twh,
     for (int t = threadIdx.x; t < L2 / 2; t += 256) tw2[t] = twh[t * L1];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t pair = blockIdx.x / (L1 / 4);
-    const int p1 = (int)(blockIdx.x % (L1 / 4)) * 4 + wave;
+    const unsigned b = xcd_block();
+    const int64_t pair = b / (L1 / 4);
+    const int p1 = (int)(b % (L1 / 4)) * 4 + wave;
     cplx<T>* Y = scr + pair * L;
     cplx<T> z[R2];
 #pragma unroll
@@ -345,21 +348,23 @@ __global__ __launch_bounds__(256) void fs_rows(const cplx<T>* __restrict__ twh,
     }
 }
 
-template <class T, int LG1, int LG2>
-__global__ __launch_bounds__(256) void fs_cols_inv(T* out, LineGeom lg,
+template <class T, int LG1, int LG2, int BS>
+__global__ __launch_bounds__(BS) void fs_cols_inv(T* out, LineGeom lg,
                                                    const cplx<T>* __restrict__ twh, T scale,
                                                    const T* addv, T add_coef,
                                                    const int* __restrict__ skip,
                                                    const cplx<T>* __restrict__ scr) {
     constexpr int L1 = 1 << LG1, L2 = 1 << LG2, L = L1 * L2;
     constexpr int R1 = line_regs<LG1>();
+    constexpr int W = BS / 64;   // consecutive columns per block
     if (skip && *skip) return;
     __shared__ cplx<T> tw1[L1 / 2];
-    for (int t = threadIdx.x; t < L1 / 2; t += 256) tw1[t] = twh[t * L2];
+    for (int t = threadIdx.x; t < L1 / 2; t += BS) tw1[t] = twh[t * L2];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t pair = blockIdx.x / (L2 / 4);
-    const int n2 = (int)(blockIdx.x % (L2 / 4)) * 4 + wave;
+    const unsigned b = xcd_block();
+    const int64_t pair = b / (L2 / W);
+    const int n2 = (int)(b % (L2 / W)) * W + wave;
     const int64_t la = 2 * pair, lb = la + 1;
     const bool hb = lb < lg.nlines;
     const int64_t ba = line_addr(lg, la, 0), bb = hb ? line_addr(lg, lb, 0) : 0;
@@ -387,6 +392,10 @@ __global__ __launch_bounds__(256) void fs_cols_inv(T* out, LineGeom lg,
 // Few pairs of circulants of at least 2^kSplitPhasesLog2 points take the
 // three-launch path.
 constexpr int kSplitPhasesLog2 = 12;
+// Column phases: 16 consecutive columns per block (one per wave), so the
+// strided accesses of neighbouring columns meet in one L2, when that still
+// gives kFsWideMinBlocks blocks; else 4 columns per block (more blocks).
+constexpr int64_t kFsWideMinBlocks = 512;
 constexpr int64_t kSplitPhasesMaxPairs = 128;
 
 // Blocks of a barrier-free pass: one line pair per wave (64/L per wave for
@@ -421,7 +430,25 @@ fkgp_status launch_line_conv(int log2L, int lg1, const T* in, T* out, const Line
         const unsigned grid = (unsigned)std::min<int64_t>(npairs, kLongWGs);
         if (grid == 0) return FKGP_OK;
         if (log2L >= kSplitPhasesLog2 && npairs <= kSplitPhasesMaxPairs) {
-#define FKGP_FS(LG, A, B)                                                                          case LG: {                                                                                         const unsigned gc = (unsigned)(npairs * ((1 << B) / 4));                                       const unsigned gr = (unsigned)(npairs * ((1 << A) / 4));                                       fs_cols_fwd<T, A, B><<<gc, 256, 0, s>>>(in, lg, tw, skip, scr);                                fs_rows<T, A, B><<<gr, 256, 0, s>>>(tw, lam, skip, scr);                                       fs_cols_inv<T, A, B><<<gc, 256, 0, s>>>(out, lg, tw, scale, addv, add_coef, skip, scr);         break;                                                                                     }
+#define FKGP_FS(LG, A, B)                                                                      \
+    case LG: {                                                                                 \
+        const int64_t c16 = npairs * ((1 << B) / 16);                                          \
+        const unsigned gr = (unsigned)(npairs * ((1 << A) / 4));                               \
+        if (c16 >= kFsWideMinBlocks) {                                                         \
+            fs_cols_fwd<T, A, B, 1024><<<(unsigned)c16, 1024, 0, s>>>(in, lg, tw, skip, scr);  \
+            fs_rows<T, A, B><<<gr, 256, 0, s>>>(tw, lam, skip, scr);                           \
+            fs_cols_inv<T, A, B, 1024><<<(unsigned)c16, 1024, 0, s>>>(out, lg, tw, scale,      \
+                                                                      addv, add_coef, skip,    \
+                                                                      scr);                    \
+        } else {                                                                               \
+            const unsigned c4 = (unsigned)(npairs * ((1 << B) / 4));                           \
+            fs_cols_fwd<T, A, B, 256><<<c4, 256, 0, s>>>(in, lg, tw, skip, scr);               \
+            fs_rows<T, A, B><<<gr, 256, 0, s>>>(tw, lam, skip, scr);                           \
+            fs_cols_inv<T, A, B, 256><<<c4, 256, 0, s>>>(out, lg, tw, scale, addv, add_coef,   \
+                                                          skip, scr);                          \
+        }                                                                                      \
+        break;                                                                                 \
+    }
             switch (log2L) {
                 FKGP_FS(12, 6, 6)
                 FKGP_FS(13, 6, 7)
