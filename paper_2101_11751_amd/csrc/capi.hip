@@ -481,6 +481,36 @@ __global__ __launch_bounds__(kRedBlock) void cg_step2x(const CgState* __restrict
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// Two pinned host slots and two events per host thread and device for the
+// CG loop's convergence checks (allocated once, kept until the process ends).
+struct CgSnap {
+    CgState* host = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+hipError_t cg_snap_get(CgSnap& out) {
+    thread_local CgSnap cache[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    CgSnap& c = cache[dev];
+    if (!c.host) {
+        e = hipHostMalloc(reinterpret_cast<void**>(&c.host), 2 * sizeof(CgState),
+                          hipHostMallocDefault);
+        if (e != hipSuccess) {
+            c.host = nullptr;
+            return e;
+        }
+        for (int i = 0; i < 2; ++i) {
+            e = hipEventCreateWithFlags(&c.ev[i], hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+    }
+    out = c;
+    return hipSuccess;
+}
+
 // Simplified efficiently-factorized CG (appendix): the residual stays in the
 // span of W, r = W r_hat, and each iteration applies B once.  On entry b.r
 // holds r_hat_0; on exit b.xd += sum_k alpha_k s_k (= W^T W x_hat) and
@@ -536,12 +566,22 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
     const LastBlockRed rho_lb{b.partials, b.tickets, b.st, FIN_RHO};
     const CgStep2 step2f{b.st, b.s, b.z, pp, b.r, b.u,
                          LastBlockRed{b.partials2, b.tickets + 1, b.st, FIN_SZ}};
+    // Pipelined convergence checks: the state after each batch of kBatch
+    // iterations is copied to pinned host memory behind that batch while the
+    // next batch is already queued, so the device does not idle while the
+    // host reads it; once the state is converged the queued launches are
+    // no-ops (every kernel of the loop tests b.st->done).
     constexpr int kBatch = 8;
-    int launched = 0;
+    CgSnap snapbuf;
+    FKGP_HIP(cg_snap_get(snapbuf));
+    CgState* snap = snapbuf.host;
+    int launched = 0, slot = 0;
+    FKGP_HIP(hipMemcpyAsync(&snap[0], b.st, sizeof(CgState), hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipEventRecord(snapbuf.ev[0], st));
     for (;;) {
-        FKGP_HIP(hipMemcpyAsync(&out, b.st, sizeof(CgState), hipMemcpyDeviceToHost, st));
-        FKGP_HIP(hipStreamSynchronize(st));
-        if (out.done || launched >= maxiter) break;
+        const int next = slot ^ 1;
+        const bool queued = launched < maxiter;
+        if (queued) {
         const int nit = std::min(kBatch, maxiter - launched);
         for (int it = 0; it < nit; ++it) {
             if (c.op == FKGP_F32)
@@ -573,7 +613,16 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
             FKGP_HIP(hipGetLastError());
         }
         launched += nit;
+        FKGP_HIP(hipMemcpyAsync(&snap[next], b.st, sizeof(CgState), hipMemcpyDeviceToHost, st));
+        FKGP_HIP(hipEventRecord(snapbuf.ev[next], st));
+        }
+        FKGP_HIP(hipEventSynchronize(snapbuf.ev[slot]));
+        out = snap[slot];
+        if (out.done || !queued) break;
+        slot = next;
     }
+    // the batch queued behind the last snapshot read (no-ops once converged)
+    FKGP_HIP(hipStreamSynchronize(st));
     if (out.done == 2) {
         set_error("factorized CG broke down (non-finite step)");
         return FKGP_EDEVICE;
