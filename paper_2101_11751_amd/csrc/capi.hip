@@ -2083,6 +2083,37 @@ fkgp_status dots_dev(const double* A, const double* B, int64_t M, int k, double*
     return FKGP_OK;
 }
 
+// Pinned snapshot slots (2 x kSnapStates states) and two events per host
+// thread and device for the probe solver's convergence checks.
+constexpr int kSnapStates = 64;
+struct ProbeSnap {
+    PState* host = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+hipError_t probe_snap_get(ProbeSnap& out) {
+    thread_local ProbeSnap cache[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    ProbeSnap& c = cache[dev];
+    if (!c.host) {
+        e = hipHostMalloc(reinterpret_cast<void**>(&c.host), 2 * kSnapStates * sizeof(PState),
+                          hipHostMallocDefault);
+        if (e != hipSuccess) {
+            c.host = nullptr;
+            return e;
+        }
+        for (int i = 0; i < 2; ++i) {
+            e = hipEventCreateWithFlags(&c.ev[i], hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+    }
+    out = c;
+    return hipSuccess;
+}
+
 // Factorized CG from x_0 = 0 for N right-hand sides b_j at once, given
 // b_hat_j = W^T b_j (bh [N][M]).  Rademacher probes (v = null): ||z_j||^2 = n.
 // Grid right-hand sides b_j = W v_j (v0 [N][M], bh = W^T W v, bb_dev [N] =
@@ -2124,15 +2155,24 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
     FKGP_HIP(hipGetLastError());
     const dim3 gv(nbv, N);
     const dim3 ge((unsigned)std::min<int64_t>((M + 255) / 256, 1024), N);
+    // pipelined convergence checks, as in run_cg: the states after each
+    // batch go to pinned memory while the next batch is queued (converged
+    // right-hand sides skip their vector updates)
+    if (N > kSnapStates) {
+        set_error("too many right-hand sides for one probe solve");
+        return FKGP_EINVAL;
+    }
+    ProbeSnap snapbuf;
+    FKGP_HIP(probe_snap_get(snapbuf));
     std::vector<PState> hs(N);
-    int launched = 0;
+    int launched = 0, slot = 0;
     constexpr int kBatch = 8;
+    FKGP_HIP(hipMemcpyAsync(snapbuf.host, ps, sizeof(PState) * N, hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipEventRecord(snapbuf.ev[0], st));
     for (;;) {
-        FKGP_HIP(hipMemcpyAsync(hs.data(), ps, sizeof(PState) * N, hipMemcpyDeviceToHost, st));
-        FKGP_HIP(hipStreamSynchronize(st));
-        bool all = true;
-        for (int j = 0; j < N; ++j) all &= hs[j].done != 0;
-        if (all || launched >= maxiter) break;
+        const int next = slot ^ 1;
+        const bool queued = launched < maxiter;
+        if (queued) {
         const int nit = std::min(kBatch, maxiter - launched);
         for (int it = 0; it < nit; ++it) {
             probe_ap<<<gv, kRedBlock, 0, st>>>(ps, zp, kb, sp, bh, ur, vr, ap, M, partials);
@@ -2148,7 +2188,19 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
             FKGP_HIP(hipGetLastError());
         }
         launched += nit;
+        FKGP_HIP(hipMemcpyAsync(snapbuf.host + (size_t)next * kSnapStates, ps,
+                                sizeof(PState) * N, hipMemcpyDeviceToHost, st));
+        FKGP_HIP(hipEventRecord(snapbuf.ev[next], st));
+        }
+        FKGP_HIP(hipEventSynchronize(snapbuf.ev[slot]));
+        std::copy(snapbuf.host + (size_t)slot * kSnapStates,
+                  snapbuf.host + (size_t)slot * kSnapStates + N, hs.begin());
+        bool all = true;
+        for (int j = 0; j < N; ++j) all &= hs[j].done != 0;
+        if (all || !queued) break;
+        slot = next;
     }
+    FKGP_HIP(hipStreamSynchronize(st));
     iters_max = 0;
     for (int j = 0; j < N; ++j) {
         iters_max = std::max(iters_max, hs[j].iters);
