@@ -200,6 +200,20 @@ fkgp_status fkgp_solve(const fkgp_handle* h, const fkgp_hypers* hyp,
                        const fkgp_solve_opts* opts, fkgp_solve_info* info,
                        void* stream);
 
+/* k grid right-hand sides at once: out_j = W^T (W K_G W^T + s2 I)^{-1} W rhs_j
+ * (the rhs_grid case of fkgp_solve for each column).  rhs_grid, out: device
+ * doubles [k][m].  The solves advance together, 64 at a time, from x_0 = 0
+ * with the residual kept as W r_hat (r_hat_0 = rhs_j), so each iteration
+ * reads W^T W once for the batch; each stops at ||r|| <= tol ||W rhs_j||
+ * (Claim 4 inner products; only W^T W enters).  opts->op_precision must be
+ * FKGP_OP_F64.  info: the most iterations of any column, and the largest
+ * relative residual.  FKGP_ENOTCONV if a column reached maxiter (out still
+ * written).  Synchronises `stream`. */
+fkgp_status fkgp_solve_multi(const fkgp_handle* h, const fkgp_hypers* hyp,
+                             const double* rhs_grid, int k, double* out,
+                             const fkgp_solve_opts* opts, fkgp_solve_info* info,
+                             void* stream);
+
 typedef struct {
     int lanczos_steps;  /* tridiagonal size used for each probe (<= iters,
                            at most 64) */

@@ -25,7 +25,7 @@ OK, ENOTCONV, EINVAL, EOUTOFGRID, ENOMEM, EDEVICE = 0, 1, -1, -2, -3, -4
 
 #: every symbol that include/fkgp.h declares
 EXPORTS = ("fkgp_precompute", "fkgp_describe", "fkgp_export_stats", "fkgp_export_sketches",
-           "fkgp_solve", "fkgp_mll_and_grad", "fkgp_batch_mll_and_grad", "fkgp_interpolate",
+           "fkgp_solve", "fkgp_solve_multi", "fkgp_mll_and_grad", "fkgp_batch_mll_and_grad", "fkgp_interpolate",
            "fkgp_posterior_cov", "fkgp_love_build", "fkgp_love_tridiag", "fkgp_love_cov",
            "fkgp_love_destroy", "fkgp_apply_B",
            "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_ski_solve", "fkgp_save", "fkgp_load",
@@ -129,6 +129,8 @@ def load_library():
                                        ctypes.c_int64, p, ctypes.POINTER(p)]
     L.fkgp_save.argtypes = [p, ctypes.c_char_p, p]
     L.fkgp_load.argtypes = [ctypes.c_char_p, p, ctypes.POINTER(ctypes.c_void_p)]
+    L.fkgp_solve_multi.argtypes = [p, ctypes.POINTER(_Hypers), p, ctypes.c_int, p,
+                                   ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo), p]
     L.fkgp_ski_solve.argtypes = [p, ctypes.POINTER(_Hypers), ctypes.c_double, ctypes.c_int, p,
                                  ctypes.POINTER(_SolveInfo), p]
     L.fkgp_mll_and_grad.argtypes = [p, ctypes.POINTER(_Hypers), ctypes.POINTER(_MllOpts),
@@ -330,6 +332,21 @@ def solve(h, hypers, rhs=None, tol=1e-6, maxiter=1000, op_precision="f64"):
                                                      OP_STATS if op_precision == "stats"
                                                      else OP_F64)),
                              ctypes.byref(info), _stream()))
+    return out, {"iterations": info.iterations, "converged": bool(info.converged),
+                 "rel_residual": info.rel_residual, "status": st}
+
+
+def solve_multi(h, hypers, rhs, tol=1e-6, maxiter=1000):
+    """fkgp_solve_multi: W^T A^{-1} W rhs_j for k grid right-hand sides
+    (rhs [k, M]); returns (out [k, M] float64, info dict)."""
+    L = load_library()
+    R = rhs.to(torch.float64).reshape(-1, h.m_total).contiguous()
+    out = torch.empty_like(R)
+    info = _SolveInfo()
+    st = _check(L.fkgp_solve_multi(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)), _ptr(R),
+                                   R.shape[0], _ptr(out),
+                                   ctypes.byref(_SolveOpts(float(tol), int(maxiter), OP_F64)),
+                                   ctypes.byref(info), _stream()))
     return out, {"iterations": info.iterations, "converged": bool(info.converged),
                  "rel_residual": info.rel_residual, "status": st}
 

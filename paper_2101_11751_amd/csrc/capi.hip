@@ -3141,6 +3141,63 @@ fkgp_status love_cov_impl(const fkgp_love* L, const void* const* xq, int nq, fkg
     return FKGP_OK;
 }
 
+// k grid right-hand sides b_j = W rhs_j at once: out_j = W^T A^{-1} W rhs_j,
+// batches of 64 through the batched factorized CG (FP64, started from
+// r_hat = rhs_j; one W^T W read per iteration for the batch).
+fkgp_status solve_multi_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const double* rhs,
+                             int k, double* out, double tol, int maxiter, fkgp_solve_info* info,
+                             hipStream_t st) {
+    Scratch sc(st);
+    OpCtx c;
+    fkgp_status rs = make_ctx(h, hyp, FKGP_F64, c, sc);
+    if (rs != FKGP_OK) return rs;
+    const int64_t M = h->M;
+    const int64_t ldx = M + 2 * c.halo;
+    int iters_max = 0;
+    double rel = 0.0;
+    bool conv = true;
+    for (int q0 = 0; q0 < k; q0 += kCovRhs) {
+        const int nr = std::min(kCovRhs, k - q0);
+        Scratch sj(st);
+        double *Vpad, *BH, *bb, *alphas, *betas, *dotp;
+        PState* ps;
+        FKGP_HIP(sj.get(&Vpad, ldx * nr));
+        FKGP_HIP(sj.get(&BH, M * nr));
+        FKGP_HIP(sj.get(&bb, nr));
+        FKGP_HIP(sj.get(&alphas, (size_t)kMaxLanczos * nr));
+        FKGP_HIP(sj.get(&betas, (size_t)kMaxLanczos * nr));
+        FKGP_HIP(sj.get(&dotp, (size_t)vec_blocks(M) * nr));
+        FKGP_HIP(sj.get(&ps, nr));
+        const double* R = rhs + (int64_t)q0 * M;
+        FKGP_HIP(hipMemsetAsync(Vpad, 0, sizeof(double) * ldx * nr, st));
+        FKGP_HIP(hipMemcpy2DAsync(Vpad + c.halo, sizeof(double) * ldx, R, sizeof(double) * M,
+                                  sizeof(double) * M, nr, hipMemcpyDeviceToDevice, st));
+        rs = spmv_dia_any(h->g, h->dt, FKGP_F64, h->A, h->bmask, Vpad, BH, nr, c.halo, nullptr,
+                          st);
+        if (rs != FKGP_OK) return rs;
+        rs = dots_dev(R, BH, M, nr, dotp, bb, st);
+        if (rs != FKGP_OK) return rs;
+        int it = 0;
+        const fkgp_status cres = probe_cg(c, BH, nr, (double)h->n, tol, maxiter,
+                                          out + (int64_t)q0 * M, alphas, betas, ps, sj, st, it,
+                                          bb, R);
+        if (cres != FKGP_OK && cres != FKGP_ENOTCONV) return cres;
+        conv &= cres == FKGP_OK;
+        iters_max = std::max(iters_max, it);
+        std::vector<PState> hs(nr);
+        FKGP_HIP(hipMemcpyAsync(hs.data(), ps, sizeof(PState) * nr, hipMemcpyDeviceToHost, st));
+        FKGP_HIP(hipStreamSynchronize(st));
+        for (int j = 0; j < nr; ++j)
+            if (hs[j].bb > 0) rel = std::max(rel, std::sqrt(std::max(hs[j].rho, 0.0) / hs[j].bb));
+    }
+    if (info) {
+        info->iterations = iters_max;
+        info->converged = conv ? 1 : 0;
+        info->rel_residual = rel;
+    }
+    return conv ? FKGP_OK : FKGP_ENOTCONV;
+}
+
 }  // namespace
 }  // namespace fkgp
 
@@ -3295,6 +3352,37 @@ extern "C" void fkgp_love_destroy(fkgp_love* c) {
     (void)hipDeviceSynchronize();
     if (c->Ct) (void)hipFree(c->Ct);
     delete c;
+}
+
+extern "C" fkgp_status fkgp_solve_multi(const fkgp_handle* h, const fkgp_hypers* hyp,
+                                        const double* rhs_grid, int k, double* out,
+                                        const fkgp_solve_opts* opts, fkgp_solve_info* info,
+                                        void* stream) {
+    return guarded([&]() -> fkgp_status {
+        fkgp::set_error("");
+        if (!h || (k > 0 && (!rhs_grid || !out)) || k < 0) {
+            fkgp::set_error("handle must be non-NULL, k >= 0, rhs_grid and out non-NULL");
+            return FKGP_EINVAL;
+        }
+        fkgp_status st = fkgp::check_hypers(h, hyp);
+        if (st != FKGP_OK) return st;
+        fkgp_solve_opts o{1e-6, 1000, FKGP_OP_F64};
+        if (opts) o = *opts;
+        if (!(o.tol >= 0.0) || o.maxiter < 1) {
+            fkgp::set_error("tol must be >= 0 and maxiter >= 1");
+            return FKGP_EINVAL;
+        }
+        if (o.op_precision != FKGP_OP_F64) {
+            fkgp::set_error("fkgp_solve_multi runs with op_precision FKGP_OP_F64");
+            return FKGP_EINVAL;
+        }
+        if (k == 0) {
+            if (info) *info = fkgp_solve_info{0, 1, 0.0};
+            return FKGP_OK;
+        }
+        return fkgp::solve_multi_impl(h, hyp, rhs_grid, k, out, o.tol, o.maxiter, info,
+                                      static_cast<hipStream_t>(stream));
+    });
 }
 
 extern "C" fkgp_status fkgp_batch_mll_and_grad(const fkgp_handle* const* hs, int nprob,

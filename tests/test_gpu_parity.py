@@ -358,3 +358,28 @@ def test_zero_block_skipping(d):
     mu, info = P.solve(h, HYP[d], tol=1e-7, maxiter=5000)
     assert info["converged"]
     assert rel(mu.cpu(), mu_o) <= 1e-5
+
+
+def test_solve_multi_grid_rhs():
+    """k = 70 grid right-hand sides in one call (a batch of 64 and a ragged
+    batch of 6): each column equals the single-right-hand-side solve and the
+    oracle's factorized CG from x_0 = 0; k = 0 is a no-op."""
+    _need_gpu()
+    grid, X, y = make_case(2, 20000, 17, m=[30, 25], dtype=np.float64)
+    xs, yt = to_dev(X, y)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float64)
+    R = np.random.default_rng(4).standard_normal((70, h.m_total))
+    out, info = P.solve_multi(h, HYP[2], torch.from_numpy(R).cuda(), tol=1e-12, maxiter=5000)
+    assert info["converged"] and info["rel_residual"] <= 1e-12
+    out = out.cpu().numpy()
+    wtw_o, _, _ = oracle.precompute(grid, X, y)
+    for j in (0, 37, 63, 64, 69):
+        single, inf1 = P.solve(h, HYP[2], rhs=torch.from_numpy(R[j]).cuda(), tol=1e-12,
+                               maxiter=5000)
+        assert inf1["converged"]
+        assert rel(out[j], single.cpu()) <= 1e-9
+        ref, _ = oracle.solve_grid_rhs(grid, HYP[2], wtw_o, R[j], tol=1e-13)
+        assert rel(out[j], ref) <= 1e-9
+    empty, info0 = P.solve_multi(h, HYP[2], torch.empty(0, h.m_total, dtype=torch.float64,
+                                                         device="cuda"))
+    assert empty.shape[0] == 0 and info0["converged"]
