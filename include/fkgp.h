@@ -35,6 +35,7 @@
 #ifndef FKGP_H
 #define FKGP_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -402,6 +403,26 @@ fkgp_status fkgp_load(const char* path, void* stream, fkgp_handle** out);
 fkgp_status fkgp_ski_solve(const fkgp_handle* h, const fkgp_hypers* hyp, double tol,
                            int maxiter, double* mean_grid, fkgp_solve_info* info,
                            void* stream);
+
+/* Device memory allocator of the library.  alloc(bytes, stream, ctx) returns
+ * device memory usable in stream order on `stream` (NULL on failure, which
+ * the calling entry point reports as FKGP_ENOMEM); free(ptr, stream, ctx)
+ * releases it after the work queued on `stream` (stream NULL: the device's
+ * null stream, after a device synchronisation).  Pinned host staging and the
+ * small pinned slots of the solvers' convergence checks stay with HIP. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* ctx);
+    void (*free)(void* ptr, void* stream, void* ctx);
+    void* ctx;
+} fkgp_allocator;
+
+/* Sets the allocator for all later device allocations of the library (the
+ * handles' statistics, the rank-k caches and every call's workspace); NULL
+ * restores stream-ordered allocation from the device's default pool.
+ * Process-wide; each allocation is freed through the allocator that made it,
+ * so handles made before a change stay valid.  FKGP_EINVAL if alloc or free
+ * is NULL. */
+fkgp_status fkgp_set_allocator(const fkgp_allocator* a);
 
 void fkgp_destroy(fkgp_handle* h);
 

@@ -29,7 +29,7 @@ EXPORTS = ("fkgp_precompute", "fkgp_describe", "fkgp_export_stats", "fkgp_export
            "fkgp_posterior_cov", "fkgp_love_build", "fkgp_love_tridiag", "fkgp_love_cov",
            "fkgp_love_destroy", "fkgp_apply_B",
            "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_ski_solve", "fkgp_save", "fkgp_load",
-           "fkgp_precompute_host", "fkgp_destroy", "fkgp_last_error")
+           "fkgp_precompute_host", "fkgp_set_allocator", "fkgp_destroy", "fkgp_last_error")
 
 
 class FkgpError(RuntimeError):
@@ -54,6 +54,14 @@ class _Hypers(ctypes.Structure):
 
 # fkgp_kernel: the one-dimensional kernel of the product (hypers["kernel"])
 KERNELS = {"se": 0, "matern12": 1, "matern32": 2, "matern52": 3}
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
 
 
 class _PreOpts(ctypes.Structure):
@@ -154,6 +162,7 @@ def load_library():
     L.fkgp_apply_B.argtypes = [p, ctypes.POINTER(_Hypers), p, p, p, ctypes.c_int, p]
     L.fkgp_kg_matvec.argtypes = [p, ctypes.POINTER(_Hypers), p, p, ctypes.c_int, p]
     L.fkgp_wtw_matvec.argtypes = [p, p, p, ctypes.c_int, ctypes.c_int, p]
+    L.fkgp_set_allocator.argtypes = [ctypes.POINTER(_Allocator)]
     L.fkgp_destroy.argtypes = [p]
     L.fkgp_destroy.restype = None
     L.fkgp_last_error.argtypes = []
@@ -334,6 +343,38 @@ def solve(h, hypers, rhs=None, tol=1e-6, maxiter=1000, op_precision="f64"):
                              ctypes.byref(info), _stream()))
     return out, {"iterations": info.iterations, "converged": bool(info.converged),
                  "rel_residual": info.rel_residual, "status": st}
+
+
+_ALLOCATOR_KEEPALIVE = None
+
+
+def set_allocator(alloc=None, free=None):
+    """fkgp_set_allocator: alloc(nbytes, stream) -> device pointer (int, 0 on
+    failure) and free(ptr, stream) for the library's device memory; no
+    arguments restore the default pool."""
+    global _ALLOCATOR_KEEPALIVE
+    L = load_library()
+    if alloc is None:
+        _check(L.fkgp_set_allocator(None))
+        _ALLOCATOR_KEEPALIVE = None
+        return
+    a = _ALLOC_FN(lambda n, s, c: alloc(int(n), s) or None)
+    f = _FREE_FN(lambda ptr, s, c: free(ptr, s))
+    st = _Allocator(a, f, None)
+    _check(L.fkgp_set_allocator(ctypes.byref(st)))
+    _ALLOCATOR_KEEPALIVE = (a, f, st)
+
+
+def torch_allocator():
+    """(alloc, free) taking the library's device memory from torch's caching
+    allocator on the current stream."""
+    def alloc(n, stream):
+        return torch.cuda.caching_allocator_alloc(n)
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, free
 
 
 def solve_multi(h, hypers, rhs, tol=1e-6, maxiter=1000):

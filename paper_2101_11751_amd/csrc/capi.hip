@@ -45,6 +45,7 @@ struct fkgp_handle {
     uint32_t* cend = nullptr;
     fkgp_dtype in_dt = FKGP_F32;
     void* block = nullptr;      // one pool allocation holding the arrays above
+    fkgp::DevAlloc alloc;       // the allocator block and pts_block came from
 };
 
 // Rank-k covariance cache: C^T [M][k] (row j = C_j over the rank), the
@@ -57,6 +58,7 @@ struct fkgp_love {
     int k = 0;
     int dev = 0;
     double* Ct = nullptr;
+    fkgp::DevAlloc alloc;   // the allocator Ct came from
     std::vector<double> alpha, beta, d;
 };
 
@@ -101,16 +103,50 @@ void ensure_pool() {
     g_pool_ready[dev] = true;
 }
 
+}  // namespace
+
+namespace {
+std::mutex g_alloc_mu;
+DevAlloc g_alloc;
+}  // namespace
+
+DevAlloc current_alloc() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+
+void set_alloc(const DevAlloc& a) {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = a;
+}
+
+hipError_t dev_malloc(const DevAlloc& a, void** p, size_t bytes, hipStream_t s) {
+    if (!a.alloc) return hipMallocAsync(p, bytes, s);
+    *p = a.alloc(bytes, static_cast<void*>(s), a.ctx);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void dev_free(const DevAlloc& a, void* p, hipStream_t s) {
+    if (!p) return;
+    if (!a.alloc)
+        (void)hipFreeAsync(p, s);
+    else
+        a.free(p, static_cast<void*>(s), a.ctx);
+}
+
+namespace {
+
 struct Scratch {
     hipStream_t s;
+    DevAlloc a;
     std::vector<void*> ptrs;
-    explicit Scratch(hipStream_t st) : s(st) { ensure_pool(); }
+    explicit Scratch(hipStream_t st) : s(st), a(current_alloc()) { ensure_pool(); }
     ~Scratch() {
-        for (void* p : ptrs) (void)hipFreeAsync(p, s);
+        for (void* p : ptrs) dev_free(a, p, s);
     }
     template <class T>
     hipError_t get(T** p, size_t count) {
-        hipError_t e = alloc_async(p, count, s);
+        hipError_t e = alloc_async(a, p, count, s);
         if (e == hipSuccess) ptrs.push_back(*p);
         return e;
     }
@@ -991,8 +1027,9 @@ fkgp_status alloc_handle_arrays(fkgp_handle* h, hipStream_t s) {
     const size_t bS = up(sizeof(double) * M * h->nprobe);
     const size_t bK = up(sizeof(uint32_t) * (size_t)mask_words(M));
     hipError_t e;
-    if ((e = hipMallocAsync(&h->block, bA + bW + bS + bK + 256, s)) != hipSuccess)
-        return hip_fail(e, "hipMallocAsync(handle)");
+    h->alloc = current_alloc();
+    if ((e = dev_malloc(h->alloc, &h->block, bA + bW + bS + bK + 256, s)) != hipSuccess)
+        return hip_fail(e, "device allocation (handle)");
     unsigned char* hb = static_cast<unsigned char*>(h->block);
     h->A = hb;
     h->wty = reinterpret_cast<double*>(hb + bA);
@@ -1040,8 +1077,8 @@ void free_handle(fkgp_handle* h) {
     if (!h) return;
     if (h->block || h->pts_block) {
         (void)hipDeviceSynchronize();
-        if (h->block) (void)hipFreeAsync(h->block, nullptr);
-        if (h->pts_block) (void)hipFreeAsync(h->pts_block, nullptr);
+        dev_free(h->alloc, h->block, nullptr);
+        dev_free(h->alloc, h->pts_block, nullptr);
         (void)hipStreamSynchronize(nullptr);
     }
     delete h;
@@ -1148,8 +1185,8 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
             for (int k = 0; k < g.d; ++k) ncells *= g.nc[k];
             const size_t bp = up((in == FKGP_F32 ? 16 : 32) * (size_t)std::max<int64_t>(n, 1));
             const size_t bc = up(sizeof(uint32_t) * (size_t)ncells);
-            if ((e = hipMallocAsync(&h->pts_block, bp + 2 * bc, s)) != hipSuccess)
-                return fail(hip_fail(e, "hipMallocAsync(points)"));
+            if ((e = dev_malloc(h->alloc, &h->pts_block, bp + 2 * bc, s)) != hipSuccess)
+                return fail(hip_fail(e, "device allocation (points)"));
             unsigned char* pb = static_cast<unsigned char*>(h->pts_block);
             h->pay = pb;
             h->cstart = reinterpret_cast<uint32_t*>(pb + bp);
@@ -1295,13 +1332,14 @@ fkgp_status fkgp_interpolate(const fkgp_handle* h, const double* mean_grid,
                 }
         hipStream_t s = static_cast<hipStream_t>(stream);
         unsigned long long* bad = nullptr;
-        FKGP_HIP(hipMallocAsync(reinterpret_cast<void**>(&bad), sizeof(unsigned long long), s));
+        const DevAlloc dalloc = current_alloc();
+        FKGP_HIP(dev_malloc(dalloc, reinterpret_cast<void**>(&bad), sizeof(unsigned long long), s));
         FKGP_HIP(hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), s));
         fkgp_status st = interpolate_points(h->g, mean_grid, xq, nq, in, out, bad, s);
         unsigned long long hbad = ~0ull;
         if (st == FKGP_OK)
             FKGP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s));
-        (void)hipFreeAsync(bad, s);
+        dev_free(dalloc, bad, s);
         FKGP_HIP(hipStreamSynchronize(s));
         if (st != FKGP_OK) return st;
         if (hbad != ~0ull) {
@@ -1483,6 +1521,7 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
             hipStream_t cs = nullptr;
             hipEvent_t copied[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
             hipStream_t s = nullptr;
+            DevAlloc a = current_alloc();
             ~Res() {
                 (void)hipStreamSynchronize(s);
                 if (cs) (void)hipStreamSynchronize(cs);
@@ -1491,8 +1530,8 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
                     if (copied[i]) (void)hipEventDestroy(copied[i]);
                     if (used[i]) (void)hipEventDestroy(used[i]);
                 }
-                if (devbuf) (void)hipFreeAsync(devbuf, s);
-                if (acc) (void)hipFreeAsync(acc, s);
+                dev_free(a, devbuf, s);
+                dev_free(a, acc, s);
                 if (cs) (void)hipStreamDestroy(cs);
                 (void)hipStreamSynchronize(s);
             }
@@ -1512,8 +1551,9 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
                     reinterpret_cast<unsigned long long*>(h->yty_dev + 2), nullptr, nullptr,
                     nullptr};
         if (n <= chunk) {   // one piece: the one-shot precompute from a device copy
-            if ((e = hipMallocAsync(&res.devbuf, es * nplanes * (size_t)cpts, s)) != hipSuccess)
-                return fail(hip_fail(e, "hipMallocAsync(points)"));
+            if ((e = dev_malloc(res.a, reinterpret_cast<void**>(&res.devbuf),
+                                es * nplanes * (size_t)cpts, s)) != hipSuccess)
+                return fail(hip_fail(e, "device allocation (points)"));
             const void* xd[3] = {nullptr, nullptr, nullptr};
             for (int k = 0; k < nplanes && n > 0; ++k) {
                 const void* src = k < g.d ? x[k] : y;
@@ -1530,9 +1570,11 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
             int NR = 1;
             for (int k = 0; k < g.d; ++k) NR *= 4;
             const size_t nacc = (size_t)ncells * (h->NB + NR + 1);
-            if ((e = hipMallocAsync(&res.acc, sizeof(double) * nacc, s)) != hipSuccess ||
-                (e = hipMallocAsync(&res.devbuf, 2 * es * nplanes * (size_t)cpts, s)) != hipSuccess)
-                return fail(hip_fail(e, "hipMallocAsync(chunk buffers)"));
+            if ((e = dev_malloc(res.a, reinterpret_cast<void**>(&res.acc), sizeof(double) * nacc,
+                                s)) != hipSuccess ||
+                (e = dev_malloc(res.a, reinterpret_cast<void**>(&res.devbuf),
+                                2 * es * nplanes * (size_t)cpts, s)) != hipSuccess)
+                return fail(hip_fail(e, "device allocation (chunk buffers)"));
             for (int i = 0; i < 2; ++i)
                 if ((e = hipHostMalloc(&res.pinned[i], es * nplanes * (size_t)cpts,
                                        hipHostMallocDefault)) != hipSuccess ||
@@ -1768,6 +1810,26 @@ fkgp_status fkgp_ski_solve(const fkgp_handle* h, const fkgp_hypers* hyp, double 
         }
         return ski_solve_impl(h, hyp, tol, maxiter, mean_grid, info,
                               static_cast<hipStream_t>(stream));
+    });
+}
+
+fkgp_status fkgp_set_allocator(const fkgp_allocator* a) {
+    return guarded([&]() -> fkgp_status {
+        set_error("");
+        if (!a) {
+            set_alloc(DevAlloc{});
+            return FKGP_OK;
+        }
+        if (!a->alloc || !a->free) {
+            set_error("allocator needs both alloc and free");
+            return FKGP_EINVAL;
+        }
+        DevAlloc d;
+        d.alloc = a->alloc;
+        d.free = a->free;
+        d.ctx = a->ctx;
+        set_alloc(d);
+        return FKGP_OK;
     });
 }
 
@@ -3102,7 +3164,8 @@ fkgp_status love_build_impl(const fkgp_handle* h, const fkgp_hypers* hyp, int k,
     }
     lz_forward<<<ge, 256, 0, st>>>(Qh, dld, dls, kk, M, P);
     FKGP_HIP(hipGetLastError());
-    FKGP_HIP(hipMalloc(reinterpret_cast<void**>(&L->Ct), sizeof(double) * M * kk));
+    L->alloc = current_alloc();
+    FKGP_HIP(dev_malloc(L->alloc, reinterpret_cast<void**>(&L->Ct), sizeof(double) * M * kk, st));
     transpose_kernel<<<dim3((unsigned)((M + 31) / 32), (unsigned)((kk + 31) / 32)), dim3(32, 8), 0,
                        st>>>(P, kk, M, L->Ct);
     FKGP_HIP(hipGetLastError());
@@ -3297,7 +3360,9 @@ extern "C" fkgp_status fkgp_love_build(const fkgp_handle* h, const fkgp_hypers* 
         (void)hipGetDevice(&L->dev);
         st = fkgp::love_build_impl(h, hyp, kc, static_cast<hipStream_t>(stream), L);
         if (st != FKGP_OK) {
-            if (L->Ct) (void)hipFree(L->Ct);
+            (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+            fkgp::dev_free(L->alloc, L->Ct, static_cast<hipStream_t>(stream));
+            (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
             delete L;
             return st;
         }
@@ -3350,7 +3415,8 @@ extern "C" fkgp_status fkgp_love_cov(const fkgp_love* c, const void* const* xq, 
 extern "C" void fkgp_love_destroy(fkgp_love* c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
-    if (c->Ct) (void)hipFree(c->Ct);
+    fkgp::dev_free(c->alloc, c->Ct, nullptr);
+    (void)hipStreamSynchronize(nullptr);
     delete c;
 }
 

@@ -196,12 +196,23 @@ fkgp_status hip_fail(hipError_t e, const char* what);
     } while (0)
 
 // ---- device buffers -------------------------------------------------------
-// Stream-ordered scratch allocation (freed with hipFreeAsync on the same
-// stream).
+// Device memory of the library comes from the caller's allocator when one is
+// set (fkgp_set_allocator), else from stream-ordered allocations of the
+// device's default pool.  Each allocation is freed through the allocator
+// that made it: callers keep the DevAlloc they allocated with.
+struct DevAlloc {
+    void* (*alloc)(size_t bytes, void* stream, void* ctx) = nullptr;
+    void (*free)(void* ptr, void* stream, void* ctx) = nullptr;
+    void* ctx = nullptr;
+};
+DevAlloc current_alloc();
+hipError_t dev_malloc(const DevAlloc& a, void** p, size_t bytes, hipStream_t s);
+void dev_free(const DevAlloc& a, void* p, hipStream_t s);
+
 template <class T>
-inline hipError_t alloc_async(T** p, size_t count, hipStream_t s) {
+inline hipError_t alloc_async(const DevAlloc& a, T** p, size_t count, hipStream_t s) {
     if (count == 0) count = 1;
-    return hipMallocAsync(reinterpret_cast<void**>(p), count * sizeof(T), s);
+    return dev_malloc(a, reinterpret_cast<void**>(p), count * sizeof(T), s);
 }
 
 // ---- precompute (precompute.hip) -------------------------------------------

@@ -953,7 +953,8 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
     Carver z0;
     const size_t region = std::max({sort_bytes(z0), asm_bytes(z0), vec_bytes(z0)});
     unsigned char* block = nullptr;
-    FKGP_HIP(alloc_async(&block, shared_off + region, s));
+    const DevAlloc dalloc = current_alloc();
+    FKGP_HIP(alloc_async(dalloc, &block, shared_off + region, s));
     auto rebase = [&](auto* p) {
         return reinterpret_cast<decltype(p)>(block + reinterpret_cast<uintptr_t>(p));
     };
@@ -1041,7 +1042,7 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
             FKGP_HIP(hipGetLastError());
         }
         if (!cc->last) {
-            FKGP_HIP(hipFreeAsync(block, s));
+            dev_free(dalloc, block, s);
             return FKGP_OK;
         }
         Mw = cc->acc_w;   // the assembly reads the totals
@@ -1123,7 +1124,7 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         FKGP_HIP(hipMemcpyAsync(out.keep_cend, cend, sizeof(uint32_t) * ncells,
                                 hipMemcpyDeviceToDevice, s));
     }
-    FKGP_HIP(hipFreeAsync(block, s));
+    dev_free(dalloc, block, s);
     return FKGP_OK;
 }
 

@@ -91,3 +91,16 @@ def test_load_rejects_bad_files(tmp_path):
     assert L.fkgp_load(str(short).encode(), None, ctypes.byref(out)) == P.EINVAL
     assert L.fkgp_save(None, b"x", None) == P.EINVAL
     assert P._STATS_HEADER.size == 136
+
+
+def test_allocator_validation_without_device():
+    """fkgp_set_allocator: NULL restores the default; a table without both
+    functions is rejected."""
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    L = P.load_library()
+    assert L.fkgp_set_allocator(None) == P.OK
+    bad = P._Allocator()
+    assert L.fkgp_set_allocator(ctypes.byref(bad)) == P.EINVAL
+    assert b"alloc and free" in L.fkgp_last_error()
+    assert L.fkgp_set_allocator(None) == P.OK
