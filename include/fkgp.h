@@ -230,6 +230,13 @@ typedef struct {
                            workgroup (256 or 512); 0 = autotune.  Autotuning
                            times a short trial of each candidate and caches
                            the fastest per batch shape for the process. */
+    int trace_mode;     /* gradient traces tr(A^{-1} dA): 0 = Hutchinson over
+                           the probes (the solves the MLL already ran);
+                           1 = exact, through S = W^T A^{-1} W from m grid
+                           right-hand-side solves (fkgp_mll_and_grad only,
+                           m <= 4096; for checks against finite differences
+                           of the exact MLL).  The log-determinant stays the
+                           stochastic Lanczos estimate either way. */
 } fkgp_mll_opts;
 
 typedef struct {

@@ -103,7 +103,8 @@ class _SolveInfo(ctypes.Structure):
 class _MllOpts(ctypes.Structure):
     _fields_ = [("lanczos_steps", ctypes.c_int), ("tol", ctypes.c_double),
                 ("maxiter", ctypes.c_int), ("batched", ctypes.c_int),
-                ("batch_rhs", ctypes.c_int), ("batch_block", ctypes.c_int)]
+                ("batch_rhs", ctypes.c_int), ("batch_block", ctypes.c_int),
+                ("trace_mode", ctypes.c_int)]
 
 
 class _MllInfo(ctypes.Structure):
@@ -563,16 +564,20 @@ def wtw_matvec(h, x, dtype=None):
     return u[0] if squeeze else u
 
 
-def mll_and_grad(h, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000, batched=True):
+def mll_and_grad(h, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000, batched=True,
+                 trace="hutchinson"):
     """(mll, grad [d+2] w.r.t. (log l_k, log s, log sigma), info).  batched:
-    all probes advance together (one W^T W read per iteration)."""
+    all probes advance together (one W^T W read per iteration).  trace:
+    "hutchinson" (over the probes) or "exact" (m grid solves, m <= 4096)."""
     L = load_library()
     mll = ctypes.c_double()
     grad = (ctypes.c_double * (h.d + 2))()
     info = _MllInfo()
+    tm = {"hutchinson": 0, "exact": 1}[trace]
     st = _check(L.fkgp_mll_and_grad(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)),
                                     ctypes.byref(_MllOpts(int(lanczos_steps), float(tol),
-                                                          int(maxiter), int(bool(batched)), 0, 0)),
+                                                          int(maxiter), int(bool(batched)), 0, 0,
+                                                          tm)),
                                     ctypes.byref(mll), grad, ctypes.byref(info), _stream()))
     return mll.value, [grad[i] for i in range(h.d + 2)], {
         "logdet": info.logdet, "quad": info.quad, "iterations_y": info.iterations_y,

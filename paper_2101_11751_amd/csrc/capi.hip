@@ -2284,7 +2284,8 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
 fkgp_status mll_post(const OpCtx& c, const fkgp_hypers* hyp, const fkgp_mll_opts& o,
                      const double* V, const double* wx, const double* alphas,
                      const double* betas, const PState* ps, double* mll, double* grad,
-                     Scratch& sc, hipStream_t st, double& logdet_out, double& q_out) {
+                     Scratch& sc, hipStream_t st, double& logdet_out, double& q_out,
+                     const double* tr_exact = nullptr) {
     const fkgp_handle* h = c.h;
     const int d = h->g.d;
     const int N = h->nprobe;
@@ -2351,6 +2352,10 @@ fkgp_status mll_post(const OpCtx& c, const fkgp_hypers* hyp, const fkgp_mll_opts
     double trs = 0.0;
     for (int j = 0; j < N; ++j) trs += (n - hd[j]) / s2;
     trs = 2.0 * s2 * trs / N;
+    if (tr_exact) {   // exact traces: tr(S dK) per theta, then tr(A^{-1})
+        for (int th = 0; th <= d; ++th) tr[th] = tr_exact[th];
+        trs = 2.0 * s2 * tr_exact[d + 1];
+    }
     *mll = -0.5 * (logdet + q + n * std::log(2.0 * M_PI));
     for (int th = 0; th <= d; ++th) grad[th] = 0.5 * (quad[th] - tr[th]);
     grad[d + 1] = 0.5 * (2.0 * s2 * zz - trs);
@@ -2360,6 +2365,80 @@ fkgp_status mll_post(const OpCtx& c, const fkgp_hypers* hyp, const fkgp_mll_opts
         set_error("Lanczos quadrature failed (non-finite log-determinant)");
         return FKGP_EDEVICE;
     }
+    return FKGP_OK;
+}
+
+// E[j] = unit vector e_{q0 + j} (E zeroed by the caller), j < nr.
+__global__ void unit_columns(double* __restrict__ E, int nr, int64_t M, int64_t q0) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nr) E[(int64_t)j * M + q0 + j] = 1.0;
+}
+
+// Exact traces through S = W^T A^{-1} W, built from m grid right-hand-side
+// solves (S e_i = W^T A^{-1} W e_i, 64 columns per batched solve):
+//   tr(A^{-1} W dK W^T) = tr(S dK) = sum_i (S e_i) . (dK e_i)  (theta <= d)
+//   tr(A^{-1}) = (n - tr(K_G S)) / s2.
+// out[0..d]: the first kind for log l_0.., log s; out[d+1]: tr(A^{-1}).
+fkgp_status exact_traces(const OpCtx& c, const fkgp_hypers* hyp, double tol, int maxiter,
+                         double* out, hipStream_t st) {
+    const fkgp_handle* h = c.h;
+    const int d = h->g.d;
+    const int64_t M = h->M;
+    const int64_t ldx = M + 2 * c.halo;
+    Scratch sc(st);
+    std::vector<Spectra> dsp(d + 1);
+    for (int th = 0; th <= d; ++th) {
+        fkgp_status rs = make_spectra(h, hyp, FKGP_F64, th < d ? th : -1, dsp[th], sc);
+        if (rs != FKGP_OK) return rs;
+    }
+    std::vector<double> acc(d + 2, 0.0);
+    for (int64_t q0 = 0; q0 < M; q0 += kSnapStates) {
+        const int nr = (int)std::min<int64_t>(kSnapStates, M - q0);
+        Scratch sj(st);
+        double *E, *Epad, *BH, *bb, *S, *D, *alphas, *betas, *dotp, *dots;
+        PState* ps;
+        FKGP_HIP(sj.get(&E, M * nr));
+        FKGP_HIP(sj.get(&Epad, ldx * nr));
+        FKGP_HIP(sj.get(&BH, M * nr));
+        FKGP_HIP(sj.get(&bb, nr));
+        FKGP_HIP(sj.get(&S, M * nr));
+        FKGP_HIP(sj.get(&D, M * nr));
+        FKGP_HIP(sj.get(&alphas, (size_t)kMaxLanczos * nr));
+        FKGP_HIP(sj.get(&betas, (size_t)kMaxLanczos * nr));
+        FKGP_HIP(sj.get(&dotp, (size_t)vec_blocks(M) * nr));
+        FKGP_HIP(sj.get(&dots, nr));
+        FKGP_HIP(sj.get(&ps, nr));
+        FKGP_HIP(hipMemsetAsync(E, 0, sizeof(double) * M * nr, st));
+        unit_columns<<<(nr + 63) / 64, 64, 0, st>>>(E, nr, M, q0);
+        FKGP_HIP(hipGetLastError());
+        FKGP_HIP(hipMemsetAsync(Epad, 0, sizeof(double) * ldx * nr, st));
+        FKGP_HIP(hipMemcpy2DAsync(Epad + c.halo, sizeof(double) * ldx, E, sizeof(double) * M,
+                                  sizeof(double) * M, nr, hipMemcpyDeviceToDevice, st));
+        fkgp_status rs = spmv_dia_any(h->g, h->dt, FKGP_F64, h->A, h->bmask, Epad, BH, nr,
+                                      c.halo, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+        rs = dots_dev(E, BH, M, nr, dotp, bb, st);
+        if (rs != FKGP_OK) return rs;
+        int it = 0;
+        rs = probe_cg(c, BH, nr, (double)h->n, tol, maxiter, S, alphas, betas, ps, sj, st, it,
+                      bb, E);
+        if (rs != FKGP_OK && rs != FKGP_ENOTCONV) return rs;
+        std::vector<double> hd(nr);
+        for (int th = 0; th <= d + 1; ++th) {
+            // theta <= d: dK e_i; last: K_G e_i
+            const Spectra& sp = th <= d ? dsp[th] : c.sp64;
+            rs = kg_apply(h->g, sp, FKGP_F64, E, D, nr, c.so, nullptr, 0.0, nullptr, st);
+            if (rs != FKGP_OK) return rs;
+            rs = dots_dev(S, D, M, nr, dotp, dots, st);
+            if (rs != FKGP_OK) return rs;
+            FKGP_HIP(hipMemcpyAsync(hd.data(), dots, sizeof(double) * nr, hipMemcpyDeviceToHost,
+                                    st));
+            FKGP_HIP(hipStreamSynchronize(st));
+            for (int j = 0; j < nr; ++j) acc[th] += hd[j];
+        }
+    }
+    for (int th = 0; th <= d; ++th) out[th] = acc[th];
+    out[d + 1] = ((double)h->n - acc[d + 1]) / c.s2;
     return FKGP_OK;
 }
 
@@ -2404,7 +2483,14 @@ fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_ml
     }
     if (pres != FKGP_OK && pres != FKGP_ENOTCONV) return pres;
     double logdet = 0.0, q = 0.0;
-    rs = mll_post(c, hyp, o, V, wx, alphas, betas, ps, mll, grad, sc, st, logdet, q);
+    std::vector<double> trx;
+    if (o.trace_mode == 1) {
+        trx.resize(h->g.d + 2);
+        rs = exact_traces(c, hyp, o.tol, o.maxiter, trx.data(), st);
+        if (rs != FKGP_OK) return rs;
+    }
+    rs = mll_post(c, hyp, o, V, wx, alphas, betas, ps, mll, grad, sc, st, logdet, q,
+                  trx.empty() ? nullptr : trx.data());
     if (rs != FKGP_OK) return rs;
     if (info) {
         info->logdet = logdet;
@@ -3283,11 +3369,19 @@ extern "C" fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers
             fkgp::set_error("the marginal likelihood needs n > 0");
             return FKGP_EINVAL;
         }
-        fkgp_mll_opts o{30, 1e-6, 1000, 1, 0, 0};
+        fkgp_mll_opts o{30, 1e-6, 1000, 1, 0, 0, 0};
         if (opts) o = *opts;
         if (o.lanczos_steps < 1 || o.lanczos_steps > fkgp::kMaxLanczos || !(o.tol >= 0.0) ||
             o.maxiter < 1) {
             fkgp::set_error("lanczos_steps must be in [1, 64], tol >= 0, maxiter >= 1");
+            return FKGP_EINVAL;
+        }
+        if (o.trace_mode != 0 && o.trace_mode != 1) {
+            fkgp::set_error("trace_mode must be 0 (Hutchinson) or 1 (exact)");
+            return FKGP_EINVAL;
+        }
+        if (o.trace_mode == 1 && h->M > 4096) {
+            fkgp::set_error("exact traces need m <= 4096 (one solve per grid node)");
             return FKGP_EINVAL;
         }
         return fkgp::mll_impl(h, hyp, o, mll, grad, info, static_cast<hipStream_t>(stream));
@@ -3476,11 +3570,15 @@ extern "C" fkgp_status fkgp_batch_mll_and_grad(const fkgp_handle* const* hs, int
                 return FKGP_EINVAL;
             }
         }
-        fkgp_mll_opts o{30, 1e-6, 1000, 1, 0, 0};
+        fkgp_mll_opts o{30, 1e-6, 1000, 1, 0, 0, 0};
         if (opts) o = *opts;
         if (o.lanczos_steps < 1 || o.lanczos_steps > fkgp::kMaxLanczos || !(o.tol >= 0.0) ||
             o.maxiter < 1) {
             fkgp::set_error("lanczos_steps must be in [1, 64], tol >= 0, maxiter >= 1");
+            return FKGP_EINVAL;
+        }
+        if (o.trace_mode != 0) {
+            fkgp::set_error("the batched solver uses Hutchinson traces (trace_mode 0)");
             return FKGP_EINVAL;
         }
         if ((o.batch_rhs != 0 && o.batch_rhs != 2 && o.batch_rhs != 4 && o.batch_rhs != 8) ||

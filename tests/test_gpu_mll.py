@@ -126,3 +126,45 @@ def test_mll_errors():
     with pytest.raises(P.FkgpError):
         P.precompute(oracle.make_grid([10, 10, 10], lo=0.0, hi=1.0),
                      [xs[0], xs[1], xs[0]], yt, n_probes=4)
+
+
+def test_mll_exact_trace_gradient():
+    """trace="exact": the traces tr(A^{-1} dA) come from S = W^T A^{-1} W
+    (one grid solve per node: 120 nodes, batches of 64 and 56), so the
+    gradient is deterministic: it equals the oracle's exact-trace gradient
+    and central differences of the oracle's dense Def. 2 MLL."""
+    _need_gpu()
+    grid, X, y, hyp = case(seed=4, m=(12, 10), n=1500, dtype=np.float64)
+    N, seed = 4, 5
+    xs, yt = dev(X, y)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float64, n_probes=N, probe_seed=seed)
+    mll, g, inf = P.mll_and_grad(h, hyp, lanczos_steps=10, tol=1e-12, maxiter=5000,
+                                 trace="exact")
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    sk_o = oracle.probe_sketches(grid, X, seed, N)
+    _, g_o, _ = oracle.mll_and_grad(grid, hyp, wtw, wty, yty, X.shape[1], sk_o,
+                                    lanczos_steps=10, tol=1e-13, exact_trace=True)
+    np.testing.assert_allclose(g, g_o, rtol=0, atol=1e-7 * np.abs(g_o).max())
+    # central differences of the dense exact MLL in (log l_k, log s, log sigma)
+    eps = 1e-4
+    fd = []
+    for i in range(len(g)):
+        vals = []
+        for sgn in (1, -1):
+            hp = {"lengthscale": list(hyp["lengthscale"]), "outputscale": hyp["outputscale"],
+                  "noise": hyp["noise"]}
+            f = math.exp(sgn * eps)
+            if i < 2:
+                hp["lengthscale"][i] *= f
+            elif i == 2:
+                hp["outputscale"] *= f
+            else:
+                hp["noise"] *= f
+            vals.append(oracle.ski_dense_mll(grid, hp, X, y))
+        fd.append((vals[0] - vals[1]) / (2 * eps))
+    np.testing.assert_allclose(g, fd, rtol=0, atol=1e-5 * np.abs(fd).max())
+    # exact traces need one solve per node: refused above 4096 nodes
+    g2, X2, y2, hyp2 = case(seed=5, m=(70, 60), n=2000, dtype=np.float64)
+    h2 = P.precompute(g2, *dev(X2, y2), stats_dtype=torch.float64, n_probes=2, probe_seed=1)
+    with pytest.raises(P.FkgpError, match="4096"):
+        P.mll_and_grad(h2, hyp2, trace="exact")
