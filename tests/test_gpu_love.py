@@ -124,3 +124,18 @@ def test_errors():
     h0 = P.precompute(grid, [e], e, stats_dtype=torch.float64)
     with pytest.raises(P.FkgpError):
         P.love_build(h0, HYP[1], 10)
+
+
+def test_covariances_bitwise_deterministic():
+    """Repeated calls give bitwise the same matrices (fixed-order sums, no
+    floating-point atomics), for the exact and the rank-k covariance."""
+    _need_gpu()
+    grid, X, y, Xq, xs, yt, xq = case(2, 8000, [20, 18], 14, nq=70)
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float32)
+    a, _ = P.posterior_cov(h, HYP[2], xq, tol=1e-10, maxiter=3000)
+    b, _ = P.posterior_cov(h, HYP[2], xq, tol=1e-10, maxiter=3000)
+    assert torch.equal(a, b)
+    c1 = P.love_build(h, HYP[2], 40)
+    c2 = P.love_build(h, HYP[2], 40)
+    assert np.array_equal(np.concatenate(c1.tridiag()), np.concatenate(c2.tridiag()))
+    assert torch.equal(c1.cov(xq), c2.cov(xq))

@@ -107,7 +107,9 @@ def test_precompute_empty_and_out_of_grid():
                                  (1, [12000]), (1, [30000]), (1, [65536]),
                                  (2, [20000, 5]), (2, [5, 20000]), (3, [17000, 4, 4]),
                                  # many long lines: one workgroup per line pair
-                                 (2, [16400, 300])])
+                                 (2, [16400, 300]),
+                                 # 3-D grids with 100-node inner dimensions
+                                 (3, [5, 60, 100]), (3, [6, 90, 33])])
 @pytest.mark.parametrize("stats", ["f64", "f32"])
 def test_kg_matvec_parity(d, m, stats):
     _need_gpu()
