@@ -75,6 +75,7 @@ thread_local std::string g_last_error;
 }
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+std::string last_error_copy() { return g_last_error; }
 
 fkgp_status hip_fail(hipError_t e, const char* what) {
     set_error(std::string("HIP error in ") + what + ": " + hipGetErrorString(e));
@@ -2458,12 +2459,49 @@ fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_ml
     FKGP_HIP(sc.get(&alphas, (size_t)kMaxLanczos * N));
     FKGP_HIP(sc.get(&betas, (size_t)kMaxLanczos * N));
     FKGP_HIP(sc.get(&ps, N));
-    // mean solve: w_y = W^T z~
-    fkgp_solve_info sinfo{};
-    fkgp_status sres = solve_core(c, nullptr, o.tol, o.maxiter, V, &sinfo, sc, st);
-    if (sres != FKGP_OK && sres != FKGP_ENOTCONV) return sres;
-    FKGP_HIP(hipMemcpyAsync(wx, V, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
     FKGP_HIP(hipMemcpyAsync(V + M, h->sketches, sizeof(double) * M * N, hipMemcpyDeviceToDevice, st));
+    // The response's mean solve (w_y = W^T z~) and the probe solves are
+    // independent until the post-processing: the mean solve runs on a second
+    // stream, driven by a second host thread, while this thread drives the
+    // probe solves on `st`.
+    struct Fork {
+        hipStream_t s = nullptr;
+        hipEvent_t ev = nullptr;
+        std::thread t;
+        ~Fork() {
+            if (t.joinable()) t.join();
+            if (s) {
+                (void)hipStreamSynchronize(s);
+                (void)hipStreamDestroy(s);
+            }
+            if (ev) (void)hipEventDestroy(ev);
+        }
+    } fork;
+    FKGP_HIP(hipStreamCreateWithFlags(&fork.s, hipStreamNonBlocking));
+    FKGP_HIP(hipEventCreateWithFlags(&fork.ev, hipEventDisableTiming));
+    FKGP_HIP(hipEventRecord(fork.ev, st));
+    FKGP_HIP(hipStreamWaitEvent(fork.s, fork.ev, 0));
+    int dev = 0;
+    FKGP_HIP(hipGetDevice(&dev));
+    fkgp_solve_info sinfo{};
+    fkgp_status sres = FKGP_OK;
+    std::string serr;
+    const hipStream_t sy = fork.s;
+    fork.t = std::thread([&, sy, dev] {
+        if (hipSetDevice(dev) != hipSuccess) {
+            sres = FKGP_EDEVICE;
+            serr = "hipSetDevice failed in the mean-solve thread";
+            return;
+        }
+        {
+            Scratch sy_sc(sy);
+            sres = solve_core(c, nullptr, o.tol, o.maxiter, V, &sinfo, sy_sc, sy);
+            // the workspace goes back only once its work is done (a caller's
+            // allocator may not order frees on this private stream)
+            (void)hipStreamSynchronize(sy);
+        }
+        if (sres != FKGP_OK) serr = last_error_copy();
+    });
     // probe solves (batched, or one probe at a time)
     int iters_max = 0;
     fkgp_status pres = FKGP_OK;
@@ -2481,7 +2519,17 @@ fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_ml
             iters_max = std::max(iters_max, it);
         }
     }
-    if (pres != FKGP_OK && pres != FKGP_ENOTCONV) return pres;
+    const std::string perr = last_error_copy();
+    fork.t.join();
+    if (sres != FKGP_OK && sres != FKGP_ENOTCONV) {
+        set_error(serr);
+        return sres;
+    }
+    if (pres != FKGP_OK && pres != FKGP_ENOTCONV) {
+        set_error(perr);
+        return pres;
+    }
+    FKGP_HIP(hipMemcpyAsync(wx, V, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
     double logdet = 0.0, q = 0.0;
     std::vector<double> trx;
     if (o.trace_mode == 1) {
