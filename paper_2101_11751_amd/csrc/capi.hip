@@ -2494,8 +2494,13 @@ fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_ml
             return;
         }
         {
+            // own spectra and four-step scratch: the long-line passes of the
+            // two streams must not share their workspace
             Scratch sy_sc(sy);
-            sres = solve_core(c, nullptr, o.tol, o.maxiter, V, &sinfo, sy_sc, sy);
+            OpCtx cy;
+            sres = make_ctx(h, hyp, FKGP_F64, cy, sy_sc);
+            if (sres == FKGP_OK)
+                sres = solve_core(cy, nullptr, o.tol, o.maxiter, V, &sinfo, sy_sc, sy);
             // the workspace goes back only once its work is done (a caller's
             // allocator may not order frees on this private stream)
             (void)hipStreamSynchronize(sy);
