@@ -44,6 +44,27 @@ __device__ inline int64_t line_addr(const LineGeom& lg, int64_t l, int e) {
 
 constexpr int kLineBlock = 256;
 
+// Two adjacent values as one vector access (16 bytes for FP64, 8 for FP32).
+template <class T>
+struct Vec2Of;
+template <>
+struct Vec2Of<double> { using type = double2; };
+template <>
+struct Vec2Of<float> { using type = float2; };
+
+// The two lines of a pair are adjacent in memory (the next inner index of a
+// strided dimension with an even stride) and start at an even element:
+// element e of both lines is then one 2-vector, aligned wherever the array
+// pointer is (checked with vec2_aligned).
+__device__ inline bool pair_adjacent(const bool (&ok)[2], const int64_t (&base)[2], int S32) {
+    return ok[0] && ok[1] && base[1] == base[0] + 1 && (base[0] & 1) == 0 && (S32 & 1) == 0;
+}
+
+template <class T>
+__device__ inline bool vec2_aligned(const T* p) {
+    return (reinterpret_cast<uintptr_t>(p) & (2 * sizeof(T) - 1)) == 0;
+}
+
 // Store of a line pass: element e = r*64 + e_lane of the (up to two) lines
 // at base[h] with stride S32 gets scale * z (+ add_coef * addv); or, with
 // fz.s set, the CG direction update of CgStep2 consumes the value in place
@@ -54,7 +75,8 @@ __device__ __forceinline__ void line_store(const cplx<T> (&z)[R], int e_lane, bo
                                            const bool (&ok)[2], const int64_t (&base)[2],
                                            int S32, int m, T* out, T scale,
                                            const T* __restrict__ addv, T add_coef,
-                                           const CgStep2& fz) {
+                                           const CgStep2& fz, bool adj = false) {
+    using V2 = typename Vec2Of<T>::type;
     if (fz.s) {
         __shared__ double red[kLineBlock];
         const int tid = threadIdx.x;
@@ -66,6 +88,32 @@ __device__ __forceinline__ void line_store(const cplx<T> (&z)[R], int e_lane, bo
             for (int r = 0; r < R; ++r) {
                 const int e = r * 64 + e_lane;
                 if (e >= m) continue;
+                if (adj) {   // both lines through 2-vector accesses
+                    const int64_t a = base[0] + (int64_t)(e * S32);
+                    T v0 = scale * z[r].re, v1 = scale * z[r].im;
+                    if (addv) {
+                        v0 += add_coef * addv[a];
+                        v1 += add_coef * addv[a + 1];
+                    }
+                    const V2 u2 = *reinterpret_cast<const V2*>(uu + a);
+                    const double2 s2 = *reinterpret_cast<const double2*>(fz.s + a);
+                    const double2 z2 = *reinterpret_cast<const double2*>(fz.z + a);
+                    const double sn0 = fma(beta, s2.x, (double)u2.x);
+                    const double sn1 = fma(beta, s2.y, (double)u2.y);
+                    const double zn0 = fma(beta, z2.x, (double)v0);
+                    const double zn1 = fma(beta, z2.y, (double)v1);
+                    *reinterpret_cast<double2*>(fz.s + a) = double2{sn0, sn1};
+                    *reinterpret_cast<double2*>(fz.z + a) = double2{zn0, zn1};
+                    if (fz.p) {
+                        const double2 p2 = *reinterpret_cast<const double2*>(fz.p + a);
+                        const double2 r2 = *reinterpret_cast<const double2*>(fz.r + a);
+                        *reinterpret_cast<double2*>(fz.p + a) =
+                            double2{fma(beta, p2.x, r2.x), fma(beta, p2.y, r2.y)};
+                    }
+                    acc = fma(sn0, zn0, acc);
+                    acc = fma(sn1, zn1, acc);
+                    continue;
+                }
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     if (!ok[h]) continue;
@@ -95,6 +143,19 @@ __device__ __forceinline__ void line_store(const cplx<T> (&z)[R], int e_lane, bo
     for (int r = 0; r < R; ++r) {
         const int e = r * 64 + e_lane;
         if (e >= m) continue;
+        if (adj) {
+            const int64_t a = base[0] + (int64_t)(e * S32);
+            T v0 = scale * z[r].re, v1 = scale * z[r].im;
+            if (addv) {
+                v0 += add_coef * addv[a];
+                v1 += add_coef * addv[a + 1];
+            }
+            V2 o;
+            o.x = v0;
+            o.y = v1;
+            *reinterpret_cast<V2*>(out + a) = o;
+            continue;
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (!ok[h]) continue;
@@ -138,16 +199,33 @@ __global__ __launch_bounds__(kLineBlock) void line_conv_direct(
         ok[h] = pair < npairs && l < lg.nlines;
         if (ok[h]) base[h] = line_addr(lg, l, 0);
     }
+    using V2 = typename Vec2Of<T>::type;
+    const bool pair_adj = pair_adjacent(ok, base, S32);
+    const bool adj = pair_adj && vec2_aligned(in + base[0]);
+    bool adj_st = pair_adj && vec2_aligned(out + base[0]);
+    if (fz.s)
+        adj_st = pair_adj && vec2_aligned(fz.s + base[0]) && vec2_aligned(fz.z + base[0]) &&
+                 vec2_aligned(static_cast<const T*>(fz.u) + base[0]) &&
+                 (!fz.p || (vec2_aligned(fz.p + base[0]) && vec2_aligned(fz.r + base[0])));
     cplx<T> z[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int e = r * 64 + e_lane;
         const bool in_line = e < m;
-        z[r].re = (in_line && ok[0]) ? in[base[0] + (int64_t)(e * S32)] : T(0);
-        z[r].im = (in_line && ok[1]) ? in[base[1] + (int64_t)(e * S32)] : T(0);
+        if (adj) {
+            V2 v;
+            v.x = T(0);
+            v.y = T(0);
+            if (in_line) v = *reinterpret_cast<const V2*>(in + base[0] + (int64_t)(e * S32));
+            z[r].re = v.x;
+            z[r].im = v.y;
+        } else {
+            z[r].re = (in_line && ok[0]) ? in[base[0] + (int64_t)(e * S32)] : T(0);
+            z[r].im = (in_line && ok[1]) ? in[base[1] + (int64_t)(e * S32)] : T(0);
+        }
     }
     conv_line_regs<T, LOG2L>(z, e_lane, tw, lam_br);
-    line_store<T, R>(z, e_lane, true, ok, base, S32, m, out, scale, addv, add_coef, fz);
+    line_store<T, R>(z, e_lane, true, ok, base, S32, m, out, scale, addv, add_coef, fz, adj_st);
 }
 
 // Line pairs split over two waves (used for L >= 512; at 256 points the
