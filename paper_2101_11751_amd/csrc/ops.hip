@@ -268,13 +268,30 @@ __global__ __launch_bounds__(kLineBlock) void line_conv_split(
         ok[h] = pair < npairs && l < lg.nlines;
         if (ok[h]) base[h] = line_addr(lg, l, 0);
     }
+    using V2 = typename Vec2Of<T>::type;
+    const bool pair_adj = pair_adjacent(ok, base, S32);
+    const bool adj = pair_adj && vec2_aligned(in + base[0]);
+    bool adj_st = pair_adj && vec2_aligned(out + base[0]);
+    if (fz.s)
+        adj_st = pair_adj && vec2_aligned(fz.s + base[0]) && vec2_aligned(fz.z + base[0]) &&
+                 vec2_aligned(static_cast<const T*>(fz.u) + base[0]) &&
+                 (!fz.p || (vec2_aligned(fz.p + base[0]) && vec2_aligned(fz.r + base[0])));
     cplx<T> z[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int e = r * 64 + lane;
         const bool in_line = e < m;
-        z[r].re = (in_line && ok[0]) ? in[base[0] + (int64_t)(e * S32)] : T(0);
-        z[r].im = (in_line && ok[1]) ? in[base[1] + (int64_t)(e * S32)] : T(0);
+        if (adj) {
+            V2 v;
+            v.x = T(0);
+            v.y = T(0);
+            if (in_line) v = *reinterpret_cast<const V2*>(in + base[0] + (int64_t)(e * S32));
+            z[r].re = v.x;
+            z[r].im = v.y;
+        } else {
+            z[r].re = (in_line && ok[0]) ? in[base[0] + (int64_t)(e * S32)] : T(0);
+            z[r].im = (in_line && ok[1]) ? in[base[1] + (int64_t)(e * S32)] : T(0);
+        }
     }
     if (half) {   // first DIF stage, upper outputs: (x[e] - 0) w^e
 #pragma unroll
@@ -304,7 +321,8 @@ __global__ __launch_bounds__(kLineBlock) void line_conv_split(
             z[r].im += t.im;
         }
     }
-    line_store<T, R>(z, lane, half == 0, ok, base, S32, m, out, scale, addv, add_coef, fz);
+    line_store<T, R>(z, lane, half == 0, ok, base, S32, m, out, scale, addv, add_coef, fz,
+                     adj_st);
 }
 
 // Long lines: one workgroup per line pair at a time (grid-stride over the
