@@ -104,3 +104,31 @@ def test_allocator_validation_without_device():
     assert L.fkgp_set_allocator(ctypes.byref(bad)) == P.EINVAL
     assert b"alloc and free" in L.fkgp_last_error()
     assert L.fkgp_set_allocator(None) == P.OK
+
+
+def test_new_entry_points_validate_on_the_host():
+    """The covariance, rank-k, multi-right-hand-side and exact-trace entry
+    points reject NULL handles and bad sizes before touching a device."""
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    L = P.load_library()
+    hyp = P._Hypers()
+    info = P._SolveInfo()
+    cov = ctypes.c_void_p(1)
+    assert L.fkgp_posterior_cov(None, ctypes.byref(hyp), None, 4, P.F64, 1e-8, 10, cov,
+                                ctypes.byref(info), None) == P.EINVAL
+    out = ctypes.c_void_p()
+    assert L.fkgp_love_build(None, ctypes.byref(hyp), 10, None, ctypes.byref(out)) == P.EINVAL
+    assert out.value is None
+    assert L.fkgp_love_build(None, ctypes.byref(hyp), 10, None, None) == P.EINVAL
+    r = ctypes.c_int(0)
+    assert L.fkgp_love_tridiag(None, ctypes.byref(r), None, None, None) == P.EINVAL
+    assert L.fkgp_love_cov(None, None, 1, P.F64, None, None) == P.EINVAL
+    L.fkgp_love_destroy(None)
+    assert L.fkgp_solve_multi(None, ctypes.byref(hyp), None, 3, None, None, None,
+                              None) == P.EINVAL
+    opts = P._MllOpts(30, 1e-6, 1000, 1, 0, 0, 1)
+    mll = ctypes.c_double()
+    grad = (ctypes.c_double * 5)()
+    assert L.fkgp_mll_and_grad(None, ctypes.byref(hyp), ctypes.byref(opts), ctypes.byref(mll),
+                               grad, None, None) == P.EINVAL
