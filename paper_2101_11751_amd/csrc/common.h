@@ -272,8 +272,9 @@ constexpr int kFewLinesMinLog2 = 10;
 constexpr int64_t kFewLines = 64;
 constexpr int kMaxLineLog2 = 17;
 constexpr int kMaxBatchLineLog2 = 14;
-// Spectra of circulants up to 2^kMaxDftLog2 points are direct FP64 sums;
-// longer ones come from a forward four-step FFT of the embedded column.
+// Spectra of circulants up to 2^kMaxDftLog2 points may be direct FP64 sums;
+// longer ones, and four-step layouts from 2^12 points when the scratch is
+// there, come from a forward four-step FFT of the embedded column.
 constexpr int kMaxDftLog2 = 14;
 // Workgroups (each with its own L-point complex scratch) of a four-step pass.
 constexpr int kLongWGs = 256;

@@ -1237,6 +1237,15 @@ template <class T>
 static fkgp_status launch_spectrum_long(T* lam, int log2L, int m, double h, double ell,
                                         bool deriv, int kind, cplx<double>* Y, hipStream_t s) {
     switch (log2L) {
+        case 12:
+            spectrum_long_kernel<T, 6, 6><<<1, 1024, 0, s>>>(lam, m, h, ell, deriv, kind, Y);
+            break;
+        case 13:
+            spectrum_long_kernel<T, 6, 7><<<1, 1024, 0, s>>>(lam, m, h, ell, deriv, kind, Y);
+            break;
+        case 14:
+            spectrum_long_kernel<T, 7, 7><<<1, 1024, 0, s>>>(lam, m, h, ell, deriv, kind, Y);
+            break;
         case 15:
             spectrum_long_kernel<T, 7, 8><<<1, 1024, 0, s>>>(lam, m, h, ell, deriv, kind, Y);
             break;
@@ -1258,7 +1267,10 @@ fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv, int 
                            fkgp_dtype dt, void* lam, int log2L, int lg1, void* scr,
                            hipStream_t s) {
     const int L = 1 << log2L;
-    if (log2L > kMaxDftLog2) {
+    // four-step layouts of 2^12 points and more take the FFT whenever its
+    // scratch is there (O(L log L) instead of O(L m) direct sums); beyond
+    // 2^kMaxDftLog2 points they must
+    if (log2L > kMaxDftLog2 || (scr && lg1 > 0 && log2L >= 12)) {
         int want1, want2;
         long_split(log2L, want1, want2);
         if (!scr || lg1 != want1) {

@@ -168,3 +168,28 @@ def test_mll_exact_trace_gradient():
     h2 = P.precompute(g2, *dev(X2, y2), stats_dtype=torch.float64, n_probes=2, probe_seed=1)
     with pytest.raises(P.FkgpError, match="4096"):
         P.mll_and_grad(h2, hyp2, trace="exact")
+
+
+def test_mll_long_1d_lines_fft_spectra():
+    """1-D grid of 3000 nodes (circulant of 8192 points, four-step passes,
+    spectra and derivative spectra from the forward four-step FFT): MLL and
+    gradient against the oracle's estimator with the same probes."""
+    _need_gpu()
+    rng = np.random.default_rng(12)
+    grid = oracle.make_grid([3000], lo=0.0, hi=1.0)
+    X = rng.uniform(0, 1, (1, 30000))
+    y = np.sin(9 * X[0]) + 0.2 * rng.standard_normal(30000)
+    hyp = {"lengthscale": [0.01], "outputscale": 1.1, "noise": 0.2}
+    N, seed = 4, 21
+    h = P.precompute(grid, [torch.from_numpy(X[0]).cuda()], torch.from_numpy(y).cuda(),
+                     stats_dtype=torch.float64, n_probes=N, probe_seed=seed)
+    mll, g, inf = P.mll_and_grad(h, hyp, lanczos_steps=10, tol=1e-10, maxiter=5000)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    sk = oracle.probe_sketches(grid, X, seed, N)
+    mll_o, g_o, inf_o = oracle.mll_and_grad(grid, hyp, wtw, wty, yty, X.shape[1], sk,
+                                            lanczos_steps=10, tol=1e-10)
+    s2 = hyp["noise"] ** 2
+    q_bound = 2 * 1e-10 * float(np.dot(y, y)) / s2
+    scale = abs(inf_o["logdet"]) + abs(inf_o["q"]) + X.shape[1] * math.log(2 * math.pi)
+    assert abs(mll - mll_o) <= 1e-10 * scale + 0.5 * q_bound, (mll, mll_o)
+    np.testing.assert_allclose(g, g_o, rtol=0, atol=1e-7 * np.abs(g_o).max())
