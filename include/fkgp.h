@@ -104,7 +104,9 @@ typedef struct {
                                 B(x) = ((K_G W^T W + s2 I)x, W^T W x); FP32
                                 or FP64.  CG vectors and scalars are FP64. */
     int n_probes;            /* Rademacher probe sketches W^T z_j to build
-                                (0..31, d <= 2), for fkgp_mll_and_grad */
+                                (0..31), for fkgp_mll_and_grad (in 3-D the
+                                sort carries the point index in the slot of
+                                y, which the moments then read by index) */
     uint64_t probe_seed;     /* z_j[i] = 1 - 2*(SplitMix64((seed<<48) ^
                                 (j<<40) ^ i) >> 63) */
     int keep_points;         /* 1: the handle also keeps the points in cell

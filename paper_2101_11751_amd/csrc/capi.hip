@@ -1148,10 +1148,6 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
             set_error("n_probes must be in [0, 31]");
             return FKGP_EINVAL;
         }
-        if (o.n_probes > 0 && g.d > 2) {
-            set_error("probe sketches are supported for d <= 2");
-            return FKGP_EINVAL;
-        }
         for (int k = 0; k < g.d; ++k)
             if (circulant_log2(g.m[k]) > kMaxLineLog2) {
                 set_error("grid dimension longer than 65536 nodes is not supported");

@@ -284,8 +284,14 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(
             k = keys_in[i];
             if constexpr (kRaw) {
                 for (int c = 0; c < d; ++c) set_slot(p, c, xs.p[c][i]);
-                set_slot(p, d, yin[i]);
-                if (with_idx) set_slot(p, d + 1, idx_to_slot((uint32_t)i, Tin(0)));
+                if (with_idx && d == 3) {
+                    // no fifth slot: the index takes y's place, and the
+                    // moments read y through it
+                    set_slot(p, 3, idx_to_slot((uint32_t)i, Tin(0)));
+                } else {
+                    set_slot(p, d, yin[i]);
+                    if (with_idx) set_slot(p, d + 1, idx_to_slot((uint32_t)i, Tin(0)));
+                }
             } else {
                 p = pay_in[i];
             }
@@ -368,8 +374,8 @@ template <int D, class Tin>
 __global__ __launch_bounds__(64) void cell_moments(
     const typename PayloadOf<Tin>::type* __restrict__ pay,
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, GridDev g,
-    int nprobe, uint64_t seed, int ncells, double* __restrict__ Mw,
-    double* __restrict__ Mr, double* __restrict__ Myy) {
+    int nprobe, uint64_t seed, int ncells, const Tin* __restrict__ yin,
+    double* __restrict__ Mw, double* __restrict__ Mr, double* __restrict__ Myy) {
     constexpr int NW = ipow_c<D>(7);
     constexpr int NR = ipow_c<D>(4);
     extern __shared__ double smem[];
@@ -389,7 +395,7 @@ __global__ __launch_bounds__(64) void cell_moments(
     for (int r = 0; r < WROWS; ++r) accw[r] = 0.0;
     // rhs moments: columns (r, trailing q) with 4 rows q0 (D>=2: trailing
     // index over dims 1..D-1; D=1: one column per rhs, 4 rows).
-    constexpr int MAXG = 2;   // up to 128 rhs-moment columns
+    constexpr int MAXG = D == 3 ? 8 : 2;   // up to 512 (3-D) or 128 columns
     double accr[MAXG][4];
 #pragma unroll
     for (int gi = 0; gi < MAXG; ++gi)
@@ -412,10 +418,14 @@ __global__ __launch_bounds__(64) void cell_moments(
                     v *= t;
                 }
             }
-            const double yv = (double)get_slot(p, D);
+            // 3-D with probes: slot 3 holds the original index, y is read
+            // through it; else slot D holds y and slot D + 1 the index
+            const bool y_by_idx = D == 3 && nprobe > 0;
+            const uint32_t orig =
+                nprobe > 0 ? slot_to_idx(get_slot(p, y_by_idx ? D : D + 1)) : 0u;
+            const double yv = y_by_idx ? (double)yin[orig] : (double)get_slot(p, D);
             rvb[lane * nr] = yv;
             if (nprobe > 0) {
-                const uint32_t orig = slot_to_idx(get_slot(p, D + 1));
                 for (int j = 0; j < nprobe; ++j) rvb[lane * nr + 1 + j] = rademacher(seed, j, orig);
             }
         } else {
@@ -1015,17 +1025,17 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         const size_t lds_mom = sizeof(double) * 64 * (kPw + nr);
         if (d == 1)
             cell_moments<1, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
-                                                                 (int)ncells, Mw, Mr, Myy);
+                                                                 (int)ncells, y, Mw, Mr, Myy);
         else if (d == 2 && nprobe == 0)
             cell_moments2<Tin><<<(unsigned)ncells, 64, 0, s>>>(pin, cstart, cend, g, Mw, Mr, Myy);
         else if (d == 2)
             cell_moments<2, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
-                                                                 (int)ncells, Mw, Mr, Myy);
+                                                                 (int)ncells, y, Mw, Mr, Myy);
         else if (nprobe == 0)
             cell_moments3<Tin><<<(unsigned)ncells, 64, 0, s>>>(pin, cstart, cend, g, Mw, Mr, Myy);
         else
             cell_moments<3, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
-                                                                 (int)ncells, Mw, Mr, Myy);
+                                                                 (int)ncells, y, Mw, Mr, Myy);
         FKGP_HIP(hipGetLastError());
     } else {
         FKGP_HIP(hipMemsetAsync(Mw, 0, sizeof(double) * ncells * NB, s));

@@ -123,9 +123,9 @@ def test_mll_errors():
     h = P.precompute(grid, xs, yt)
     with pytest.raises(P.FkgpError):
         P.mll_and_grad(h, hyp)
-    with pytest.raises(P.FkgpError):
+    with pytest.raises(P.FkgpError):   # at most 31 probes
         P.precompute(oracle.make_grid([10, 10, 10], lo=0.0, hi=1.0),
-                     [xs[0], xs[1], xs[0]], yt, n_probes=4)
+                     [xs[0], xs[1], xs[0]], yt, n_probes=32)
 
 
 def test_mll_exact_trace_gradient():
@@ -191,5 +191,39 @@ def test_mll_long_1d_lines_fft_spectra():
     s2 = hyp["noise"] ** 2
     q_bound = 2 * 1e-10 * float(np.dot(y, y)) / s2
     scale = abs(inf_o["logdet"]) + abs(inf_o["q"]) + X.shape[1] * math.log(2 * math.pi)
+    assert abs(mll - mll_o) <= 1e-10 * scale + 0.5 * q_bound, (mll, mll_o)
+    np.testing.assert_allclose(g, g_o, rtol=0, atol=1e-7 * np.abs(g_o).max())
+
+
+@pytest.mark.parametrize("indt", [np.float32, np.float64])
+def test_mll_3d_probe_sketches(indt):
+    """3-D handles with probe sketches (the sort carries each point's index
+    in the slot of y, which the moments read back by index): sketches, W^T y,
+    W^T W and the MLL with its gradient against the oracle."""
+    _need_gpu()
+    rng = np.random.default_rng(33)
+    grid = oracle.make_grid([10, 9, 8], lo=0.0, hi=1.0)
+    n = 20000
+    X = rng.uniform(0, 1, (3, n)).astype(indt)
+    y = (np.sin(3 * X[0].astype(np.float64)) * X[1] + 0.2 * rng.standard_normal(n)).astype(indt)
+    hyp = {"lengthscale": [0.3, 0.25, 0.35], "outputscale": 1.1, "noise": 0.3}
+    N, seed = 31, 17
+    xs = [torch.from_numpy(np.ascontiguousarray(X[k])).cuda() for k in range(3)]
+    h = P.precompute(grid, xs, torch.from_numpy(y).cuda(), stats_dtype=torch.float64,
+                     n_probes=N, probe_seed=seed)
+    sk = P.export_sketches(h).cpu().numpy()
+    sk_o = oracle.probe_sketches(grid, X, seed, N)
+    np.testing.assert_allclose(sk, sk_o, rtol=0, atol=1e-11 * np.abs(sk_o).max())
+    wtw, wty, yty = P.export_stats(h)
+    wtw_o, wty_o, yty_o = oracle.precompute(grid, X, y)
+    assert np.linalg.norm(wtw.cpu().numpy() - wtw_o) <= 1e-13 * np.linalg.norm(wtw_o)
+    assert np.linalg.norm(wty.cpu().numpy() - wty_o) <= 1e-13 * np.linalg.norm(wty_o)
+    assert abs(yty - yty_o) <= 1e-13 * yty_o
+    mll, g, inf = P.mll_and_grad(h, hyp, lanczos_steps=10, tol=1e-10, maxiter=3000)
+    mll_o, g_o, inf_o = oracle.mll_and_grad(grid, hyp, wtw_o, wty_o, yty_o, n, sk_o,
+                                            lanczos_steps=10, tol=1e-10)
+    yd = y.astype(np.float64)
+    q_bound = 2 * 1e-10 * float(yd @ yd) / hyp["noise"] ** 2
+    scale = abs(inf_o["logdet"]) + abs(inf_o["q"]) + n * math.log(2 * math.pi)
     assert abs(mll - mll_o) <= 1e-10 * scale + 0.5 * q_bound, (mll, mll_o)
     np.testing.assert_allclose(g, g_o, rtol=0, atol=1e-7 * np.abs(g_o).max())
