@@ -111,7 +111,8 @@ typedef struct {
                                 (j<<40) ^ i) >> 63) */
     int keep_points;         /* 1: the handle also keeps the points in cell
                                 order (n * 4 values of the input dtype) and
-                                the cell bounds, for fkgp_ski_solve (d <= 2) */
+                                the cell bounds, for fkgp_ski_solve (in 3-D
+                                not together with probe sketches) */
     int interp;              /* fkgp_interp: the interpolation scheme of W,
                                 used by every later call on the handle */
 } fkgp_precompute_opts;
@@ -407,7 +408,7 @@ fkgp_status fkgp_load(const char* path, void* stream, fkgp_handle** out);
  * weights fkgp_solve returns (Theorem 1 / Fact 2).  W^T v is formed
  * deterministically from the points kept in cell order (per-cell moments,
  * fixed-order sums), W v by gathering the 4^d stencil nodes of each point.
- * Needs a handle made with keep_points (d <= 2), else FKGP_EINVAL.
+ * Needs a handle made with keep_points, else FKGP_EINVAL.
  * Synchronises `stream`. */
 fkgp_status fkgp_ski_solve(const fkgp_handle* h, const fkgp_hypers* hyp, double tol,
                            int maxiter, double* mean_grid, fkgp_solve_info* info,

@@ -930,8 +930,10 @@ fkgp_status ski_solve_impl(const fkgp_handle* h, const fkgp_hypers* hyp, double 
     FKGP_HIP(sc.get(&r, nn));
     FKGP_HIP(sc.get(&p, nn));
     FKGP_HIP(sc.get(&q, nn));
-    FKGP_HIP(sc.get(&R, ncells * (g.d == 1 ? 4 : 16)));
-    FKGP_HIP(sc.get(&T1, M * (g.d == 1 ? 1 : 4)));
+    // per-cell moments (4^d per cell) and the assembly stages' workspace
+    // (3-D: two intermediate stages of 16 and 4 values per node)
+    FKGP_HIP(sc.get(&R, ncells * (g.d == 1 ? 4 : (g.d == 2 ? 16 : 64))));
+    FKGP_HIP(sc.get(&T1, M * (g.d == 1 ? 1 : (g.d == 2 ? 4 : 20))));
     FKGP_HIP(sc.get(&wt, M));
     FKGP_HIP(sc.get(&kv, M));
     const int nb = red_blocks(nn);
@@ -1136,8 +1138,9 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
             set_error("keep_points must be 0 or 1");
             return FKGP_EINVAL;
         }
-        if (o.keep_points && g.d > 2) {
-            set_error("keep_points (the plain SKI operator) is supported for d <= 2");
+        if (o.keep_points && g.d > 2 && o.n_probes > 0) {
+            set_error("in 3-D keep_points and probe sketches exclude each other (the point "
+                      "index takes the slot of y)");
             return FKGP_EINVAL;
         }
         if (o.stats_dtype != FKGP_F32 && o.stats_dtype != FKGP_F64) {
@@ -1796,7 +1799,7 @@ fkgp_status fkgp_ski_solve(const fkgp_handle* h, const fkgp_hypers* hyp, double 
             return FKGP_EINVAL;
         }
         if (!h->pay) {
-            set_error("the handle keeps no points: precompute with keep_points = 1 (d <= 2)");
+            set_error("the handle keeps no points: precompute with keep_points = 1");
             return FKGP_EINVAL;
         }
         fkgp_status st = check_hypers(h, hyp);

@@ -231,8 +231,8 @@ struct StatsOut {
 };
 
 // Plain SKI operator pieces on kept points (precompute.hip).
-// wtv[M] = W^T v for v (n doubles, cell order); R: ncells * 4^d, T1: M * 4^(d-1)
-// doubles of scratch.
+// wtv[M] = W^T v for v (n doubles, cell order); R: ncells * 4^d and
+// T1: M * (1, 4, 20 for d = 1, 2, 3) doubles of scratch.
 fkgp_status ski_wt(const GridDev& g, fkgp_dtype in, const void* pay, const uint32_t* cstart,
                    const uint32_t* cend, const double* v, double* R, double* T1, double* wtv,
                    hipStream_t s);

@@ -1003,7 +1003,9 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
             fkgp_status st = exclusive_scan(counts, offs, nc, sums, s);
             if (st != FKGP_OK) return st;
             const size_t lds = 4 * sizeof(uint32_t) << dbits[p];
-            const bool with_idx = nprobe > 0 || out.keep_pay != nullptr;
+            // the index rides along for the probes (and, for d <= 2, in the
+            // kept payload); 3-D kept points keep y in its slot instead
+            const bool with_idx = nprobe > 0 || (out.keep_pay != nullptr && d <= 2);
             if (p == 0)
                 radix_scatter<Tin, true><<<ntiles, kBlock, lds, s>>>(
                     kin, nullptr, xs, y, d, with_idx, n, offs, ntiles, dshift[p], dbits[p],
@@ -1217,6 +1219,22 @@ __global__ void ski_interp(const typename PayloadOf<Tin>::type* __restrict__ pay
     if (D == 1) {
 #pragma unroll
         for (int a = 0; a < 4; ++a) acc = fma(w[0][a], gv[base[0] - 1 + a], acc);
+    } else if (D == 3) {
+        const int64_t m1 = g.m[1], m2 = g.m[2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            double ra = 0.0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                double r = 0.0;
+                const int64_t row =
+                    ((int64_t)(base[0] - 1 + a) * m1 + (base[1] - 1 + b)) * m2 + (base[D - 1] - 1);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) r = fma(w[D - 1][c], gv[row + c], r);
+                ra = fma(w[1][b], r, ra);
+            }
+            acc = fma(w[0][a], ra, acc);
+        }
     } else {
         const int64_t m1 = g.m[D - 1];
 #pragma unroll
@@ -1261,21 +1279,27 @@ fkgp_status ski_wt(const GridDev& g, fkgp_dtype in, const void* pay, const uint3
             ski_cell_moments<double, 2><<<(unsigned)ncells, 64, 0, s>>>(
                 static_cast<const double4*>(pay), cstart, cend, g, v, R);
     } else {
-        set_error("the plain SKI operator covers d <= 2");
-        return FKGP_EINVAL;
+        if (in == FKGP_F32)
+            ski_cell_moments<float, 3><<<(unsigned)ncells, 64, 0, s>>>(
+                static_cast<const float4*>(pay), cstart, cend, g, v, R);
+        else
+            ski_cell_moments<double, 3><<<(unsigned)ncells, 64, 0, s>>>(
+                static_cast<const double4*>(pay), cstart, cend, g, v, R);
     }
     FKGP_HIP(hipGetLastError());
     const KeysTables tab = make_tables(g.interp);
     Dims3 cur{{1, 1, 1}};
     for (int k = 0; k < d; ++k) cur.n[k] = g.nc[k];
     const double* src = R;
-    int Pin = d == 1 ? 4 : 16;
+    int Pin = d == 1 ? 4 : (d == 2 ? 16 : 64);
     for (int k = d - 1; k >= 0; --k) {
         Dims3 nxt = cur;
         nxt.n[k] = g.m[k];
         const int Pout = Pin / 4;
         const int64_t total = (int64_t)nxt.n[0] * nxt.n[1] * nxt.n[2] * Pout;
-        double* target = k == 0 ? wtv : T1;
+        // intermediate stages alternate between the two halves of T1 (the
+        // first holds nc0 nc1 m2 x 16 values in 3-D, the second follows it)
+        double* target = k == 0 ? wtv : (k == d - 1 ? T1 : T1 + (int64_t)g.nc[0] * g.nc[1] * g.m[2] * 16);
         assemble_vec_stage<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(src, target, cur, nxt,
                                                                             k, Pout, 1, tab);
         FKGP_HIP(hipGetLastError());
@@ -1305,8 +1329,12 @@ fkgp_status ski_w(const GridDev& g, fkgp_dtype in, const void* pay, int64_t n,
             ski_interp<double, 2><<<nb, 256, 0, s>>>(static_cast<const double4*>(pay), n, g, gv,
                                                      v, s2, out);
     } else {
-        set_error("the plain SKI operator covers d <= 2");
-        return FKGP_EINVAL;
+        if (in == FKGP_F32)
+            ski_interp<float, 3><<<nb, 256, 0, s>>>(static_cast<const float4*>(pay), n, g, gv, v,
+                                                    s2, out);
+        else
+            ski_interp<double, 3><<<nb, 256, 0, s>>>(static_cast<const double4*>(pay), n, g, gv,
+                                                     v, s2, out);
     }
     FKGP_HIP(hipGetLastError());
     return FKGP_OK;

@@ -26,7 +26,8 @@ def rel(a, b):
 
 
 HYP = {1: {"lengthscale": [0.08], "outputscale": 1.2, "noise": 0.2},
-       2: {"lengthscale": [0.15, 0.12], "outputscale": 0.9, "noise": 0.25}}
+       2: {"lengthscale": [0.15, 0.12], "outputscale": 0.9, "noise": 0.25},
+       3: {"lengthscale": [0.3, 0.25, 0.35], "outputscale": 1.1, "noise": 0.3}}
 
 
 def case(d, n, m, seed, dtype):
@@ -38,7 +39,7 @@ def case(d, n, m, seed, dtype):
     return grid, X, y, xs, torch.from_numpy(y).cuda()
 
 
-@pytest.mark.parametrize("d,n,m", [(1, 1500, [60]), (2, 1200, [12, 10])])
+@pytest.mark.parametrize("d,n,m", [(1, 1500, [60]), (2, 1200, [12, 10]), (3, 900, [8, 7, 6])])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_ski_solve_matches_dense_def2(d, n, m, dtype):
     _need_gpu()
@@ -50,7 +51,7 @@ def test_ski_solve_matches_dense_def2(d, n, m, dtype):
     assert rel(mu.cpu(), mu_o) <= 1e-8
 
 
-@pytest.mark.parametrize("d,m", [(1, [800]), (2, [40, 33])])
+@pytest.mark.parametrize("d,m", [(1, [800]), (2, [40, 33]), (3, [14, 12, 10])])
 def test_ski_solve_matches_factorized(d, m):
     _need_gpu()
     grid, X, y, xs, yt = case(d, 30000, m, 50 + d, np.float32)
@@ -71,9 +72,9 @@ def test_ski_solve_errors_and_empty():
     with pytest.raises(P.FkgpError):
         P.ski_solve(h, HYP[1])
     g3 = oracle.make_grid([8, 8, 8], lo=0.0, hi=1.0)
-    x3 = [torch.rand(100, device="cuda") for _ in range(3)]
-    with pytest.raises(P.FkgpError):
-        P.precompute(g3, x3, torch.rand(100, device="cuda"), keep_points=True)
+    x3 = [torch.rand(100, device="cuda") * 0.9 + 0.05 for _ in range(3)]
+    with pytest.raises(P.FkgpError):   # 3-D: kept points exclude probe sketches
+        P.precompute(g3, x3, torch.rand(100, device="cuda"), keep_points=True, n_probes=2)
     e = torch.empty(0, device="cuda", dtype=torch.float32)
     h0 = P.precompute(grid, [e], e, keep_points=True)
     mu, info = P.ski_solve(h0, HYP[1])
