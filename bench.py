@@ -277,6 +277,32 @@ def ski_sweep(P, workloads, torch, dev, iters=200):
     return out
 
 
+def radar_iter_leg(P, workloads, torch, dev, iters=200):
+    """Per-iteration time of the factorized CG and of the plain SKI CG on the
+    radar-shaped 3-D workload at the size of the paper's per-iteration
+    comparison on radar data (Table 1: n = 10.5M, m = 51.2K = 40 x 40 x 32);
+    each solve runs exactly `iters` iterations after a short warm-up."""
+    wl = workloads.radar3d(n=10_500_000, device=dev, m=(40, 40, 32))
+    h = P.precompute(wl["grid"], wl["x"], wl["y"], stats_dtype=torch.float64, keep_points=True)
+    hyp = wl["hypers"]
+    P.solve(h, hyp, tol=0.0, maxiter=5)
+    P.ski_solve(h, hyp, tol=0.0, maxiter=5)
+    rec = {"n": 10_500_000, "m": 51200, "grid": [40, 40, 32]}
+    for name, fn in (("gsgp", P.solve), ("ski", P.ski_solve)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = fn(h, hyp, tol=0.0, maxiter=iters)
+        torch.cuda.synchronize()
+        rec[f"{name}_us_per_iter"] = (time.perf_counter() - t0) / max(info["iterations"], 1) * 1e6
+    rec["gsgp_over_ski"] = rec["gsgp_us_per_iter"] / rec["ski_us_per_iter"]
+    log(f"radar n=10.5M m=51.2K: gsgp {rec['gsgp_us_per_iter']:.1f} us/it, "
+        f"ski {rec['ski_us_per_iter']:.1f} us/it (ratio {rec['gsgp_over_ski']:.4f})")
+    h.close()
+    del wl
+    torch.cuda.empty_cache()
+    return rec
+
+
 def cov_leg(P, workloads, torch, dev, nq=691, tol=1e-10, maxiter=20000):
     """Exact SKI posterior covariance between nq query points (one solve per
     query point; Sec. 5 computes a 691 x 691 matrix on the sound data, n =
@@ -459,6 +485,9 @@ def main():
     if not args.no_sweep:
         torch.cuda.empty_cache()
         result["ski_sweep"] = ski_sweep(P, workloads, torch, dev)
+    if not args.no_sweep:
+        torch.cuda.empty_cache()
+        result["radar_per_iteration"] = radar_iter_leg(P, workloads, torch, dev)
     if not args.no_cov:
         torch.cuda.empty_cache()
         result["posterior_cov"] = cov_leg(P, workloads, torch, dev)
