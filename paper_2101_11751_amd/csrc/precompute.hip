@@ -1145,23 +1145,36 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
 // to an n-vector, O(n + m log m) per product).  The points are in cell
 // order, so W^T v is the vector assembly of the precompute with y replaced
 // by v: per-cell moments sum_p v_p prod_k t_k^{q_k} (q_k <= 3, one wave per
-// cell, lanes striding over the cell's points, a fixed xor-tree across the
-// wave), then the separable stages that turn moment digits into the 4
+// cell in 1-D and 2-D, four in 3-D, lanes striding over the cell's points,
+// fixed xor-trees across each wave), then the separable stages that turn moment digits into the 4
 // stencil offsets of each dimension.  W g gathers the 4^d stencil nodes of
 // each point with the Keys weights.
 // ---------------------------------------------------------------------------
+// Waves per cell of ski_cell_moments: in 3-D the 64 moments are split over
+// four waves by the power of the first coordinate (16 accumulators each, so
+// the kernel is not held to one wave per SIMD by its registers); the four
+// waves read the same points, which the first one brings into the caches.
+// (Splitting the points of a 1-D or 2-D cell over four waves was slower:
+// most cells hold few points.)
+template <int D>
+constexpr int ski_waves() { return D == 3 ? 4 : 1; }
+
 template <class Tin, int D>
-__global__ __launch_bounds__(64) void ski_cell_moments(
+__global__ __launch_bounds__(64 * ski_waves<D>()) void ski_cell_moments(
     const typename PayloadOf<Tin>::type* __restrict__ pay, const uint32_t* __restrict__ cstart,
     const uint32_t* __restrict__ cend, GridDev g, const double* __restrict__ v,
     double* __restrict__ R) {
     constexpr int NR = ipow_c<D>(4);
+    constexpr int NW = ski_waves<D>();
+    constexpr int QW = NR / NW;          // moments per wave
+    constexpr int KLO = NW > 1 ? 1 : 0;  // first dimension with compile-time digits
     const int64_t cell = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;     // power of the first coordinate when NW > 1
     const uint32_t s0 = cstart[cell], s1 = cend[cell];
-    double acc[NR];
+    double acc[QW];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) acc[q] = 0.0;
+    for (int q = 0; q < QW; ++q) acc[q] = 0.0;
     for (uint32_t i = s0 + lane; i < s1; i += 64) {
         const auto p = pay[i];
         double tq[D][4];
@@ -1175,13 +1188,14 @@ __global__ __launch_bounds__(64) void ski_cell_moments(
             tq[k][2] = t * t;
             tq[k][3] = t * t * t;
         }
-        const double vi = v[i];
+        double lead = v[i];
+        if (NW > 1) lead *= wv == 0 ? tq[0][0] : wv == 1 ? tq[0][1] : wv == 2 ? tq[0][2] : tq[0][3];
 #pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            double w = vi;
+        for (int q = 0; q < QW; ++q) {
+            double w = lead;
             int rem = q;
 #pragma unroll
-            for (int k = D - 1; k >= 0; --k) {
+            for (int k = D - 1; k >= KLO; --k) {
                 w *= tq[k][rem & 3];
                 rem >>= 2;
             }
@@ -1189,11 +1203,11 @@ __global__ __launch_bounds__(64) void ski_cell_moments(
         }
     }
 #pragma unroll
-    for (int q = 0; q < NR; ++q)
+    for (int q = 0; q < QW; ++q)
         for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off);
     if (lane == 0) {
 #pragma unroll
-        for (int q = 0; q < NR; ++q) R[cell * NR + q] = acc[q];
+        for (int q = 0; q < QW; ++q) R[cell * NR + wv * QW + q] = acc[q];
     }
 }
 
@@ -1266,24 +1280,24 @@ fkgp_status ski_wt(const GridDev& g, fkgp_dtype in, const void* pay, const uint3
     for (int k = 0; k < d; ++k) ncells *= g.nc[k];
     if (d == 1) {
         if (in == FKGP_F32)
-            ski_cell_moments<float, 1><<<(unsigned)ncells, 64, 0, s>>>(
+            ski_cell_moments<float, 1><<<(unsigned)ncells, 64 * ski_waves<1>(), 0, s>>>(
                 static_cast<const float4*>(pay), cstart, cend, g, v, R);
         else
-            ski_cell_moments<double, 1><<<(unsigned)ncells, 64, 0, s>>>(
+            ski_cell_moments<double, 1><<<(unsigned)ncells, 64 * ski_waves<1>(), 0, s>>>(
                 static_cast<const double4*>(pay), cstart, cend, g, v, R);
     } else if (d == 2) {
         if (in == FKGP_F32)
-            ski_cell_moments<float, 2><<<(unsigned)ncells, 64, 0, s>>>(
+            ski_cell_moments<float, 2><<<(unsigned)ncells, 64 * ski_waves<2>(), 0, s>>>(
                 static_cast<const float4*>(pay), cstart, cend, g, v, R);
         else
-            ski_cell_moments<double, 2><<<(unsigned)ncells, 64, 0, s>>>(
+            ski_cell_moments<double, 2><<<(unsigned)ncells, 64 * ski_waves<2>(), 0, s>>>(
                 static_cast<const double4*>(pay), cstart, cend, g, v, R);
     } else {
         if (in == FKGP_F32)
-            ski_cell_moments<float, 3><<<(unsigned)ncells, 64, 0, s>>>(
+            ski_cell_moments<float, 3><<<(unsigned)ncells, 64 * ski_waves<3>(), 0, s>>>(
                 static_cast<const float4*>(pay), cstart, cend, g, v, R);
         else
-            ski_cell_moments<double, 3><<<(unsigned)ncells, 64, 0, s>>>(
+            ski_cell_moments<double, 3><<<(unsigned)ncells, 64 * ski_waves<3>(), 0, s>>>(
                 static_cast<const double4*>(pay), cstart, cend, g, v, R);
     }
     FKGP_HIP(hipGetLastError());
