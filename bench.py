@@ -359,7 +359,7 @@ def cov_leg(P, workloads, torch, dev, nq=691, tol=1e-10, maxiter=20000):
 def main():
     args = _parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU per process and this benchmark on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
