@@ -150,6 +150,8 @@ typedef struct {
                                 fill the grid's box leave whole blocks zero) */
     int64_t wtw_block_entries;  /* stored entries per block (64 * 49 or 64 * 7) */
     int interp;              /* fkgp_interp of the handle */
+    int64_t nnz_wtw_nonzero; /* stored entries of W^T W that are nonzero (the
+                                exact nonzero count, counted on the device) */
 } fkgp_handle_desc;
 
 fkgp_status fkgp_describe(const fkgp_handle* h, fkgp_handle_desc* desc);
@@ -250,6 +252,11 @@ typedef struct {
     int batch_rhs;      /* fkgp_batch_mll_and_grad: right-hand sides per
                            workgroup used (0 for fkgp_mll_and_grad) */
     int batch_block;    /* fkgp_batch_mll_and_grad: threads per workgroup used */
+    double dquad[5];    /* gradient of quad = y^T A^{-1} y with respect to
+                           (log l_0 .. log l_{d-1}, log outputscale,
+                           log noise_std): -x_y^T (dA/dtheta) x_y with
+                           x_y = A^{-1} y (the deterministic part of the
+                           gradient; entries past d + 1 are 0) */
 } fkgp_mll_info;
 
 /* Log marginal likelihood (Def. 2 / Fact 2) and its gradient with respect to

@@ -27,6 +27,7 @@ def _lib():
         i64 = ctypes.c_int64
         L.oracle_stencils.argtypes = [ctypes.c_int, p, p, p, p, i64, p, p, p, p]
         L.oracle_precompute.argtypes = [ctypes.c_int, p, p, p, p, p, i64, p, p, p, p]
+        L.oracle_precompute_abs.argtypes = [ctypes.c_int, p, p, p, p, p, i64, p, p, p, p]
         L.oracle_probe_sketches.argtypes = [ctypes.c_int, p, p, p, p, i64,
                                             ctypes.c_uint64, ctypes.c_int, p, p]
         L.oracle_probe_value.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
@@ -37,7 +38,8 @@ def _lib():
         L.oracle_wtw_matvec.argtypes = [ctypes.c_int, p, p, p, p, ctypes.c_int]
         L.oracle_set_interp.argtypes = [ctypes.c_int]
         L.oracle_set_interp.restype = None
-        for f in (L.oracle_stencils, L.oracle_precompute, L.oracle_probe_sketches,
+        for f in (L.oracle_stencils, L.oracle_precompute, L.oracle_precompute_abs,
+                  L.oracle_probe_sketches,
                   L.oracle_interpolate):
             f.restype = ctypes.c_int
         _LIB = L
@@ -102,9 +104,11 @@ def stencils(grid, x):
     return nodes, w, cells
 
 
-def precompute(grid, x, y):
+def precompute(grid, x, y, absolute=False):
     """Sufficient statistics (W^T W in [M, 7^d] stencil-diagonal layout,
-    W^T y [M], y^T y), accumulated serially in FP64 in input order."""
+    W^T y [M], y^T y), accumulated serially in FP64 in input order.  With
+    `absolute`, the same sums over |w| and |y| (|W|^T |W|, |W|^T |y|): the
+    scale of the rounding error of any summation order, for error bounds."""
     d, m, g0, h = _grid_arrays(grid)
     X = _coords(x, d)
     n = X.shape[1]
@@ -115,8 +119,9 @@ def precompute(grid, x, y):
     wty = np.zeros(M, np.float64)
     yty = ctypes.c_double(0.0)
     bad = ctypes.c_int64(-1)
-    rc = _lib().oracle_precompute(d, _ptr(m), _ptr(g0), _ptr(h), _ptr(X), _ptr(Y), n,
-                                  _ptr(wtw), _ptr(wty), ctypes.byref(yty), ctypes.byref(bad))
+    fn = _lib().oracle_precompute_abs if absolute else _lib().oracle_precompute
+    rc = fn(d, _ptr(m), _ptr(g0), _ptr(h), _ptr(X), _ptr(Y), n,
+            _ptr(wtw), _ptr(wty), ctypes.byref(yty), ctypes.byref(bad))
     _check(rc, bad)
     return wtw, wty, float(yty.value)
 

@@ -151,12 +151,15 @@ int oracle_stencils(int d, const int64_t *m, const double *g0, const double *h,
     return 0;
 }
 
-/* Sufficient statistics, serially in input order.
+/* Sufficient statistics, serially in input order (absw = 0), or the same
+ * sums over the absolute weights, |W|^T |W| and |W|^T |y| (absw = 1): the
+ * scale of the rounding error of any summation order of W^T W, used by the
+ * tests' error bounds.
  * wtw: [M][7^d] zero-initialised here; wty: [M]; yty: scalar. */
-int oracle_precompute(int d, const int64_t *m, const double *g0,
-                      const double *h, const double *x /* [d][n] */,
-                      const double *y, int64_t n, double *wtw, double *wty,
-                      double *yty, int64_t *bad) {
+static int precompute_impl(int d, const int64_t *m, const double *g0,
+                           const double *h, const double *x, const double *y,
+                           int64_t n, double *wtw, double *wty, double *yty,
+                           int64_t *bad, int absw) {
     if (d < 1 || d > 3 || n < 0) return -1;
     int64_t M = 1;
     for (int k = 0; k < d; ++k) {
@@ -177,8 +180,11 @@ int oracle_precompute(int d, const int64_t *m, const double *g0,
             if (bad) *bad = i;
             return -2;
         }
+        if (absw)
+            for (int a = 0; a < s; ++a) wts[a] = fabs(wts[a]);
+        const double yi = absw ? fabs(y[i]) : y[i];
         for (int a = 0; a < s; ++a) {
-            wty[nodes[a]] += y[i] * wts[a];
+            wty[nodes[a]] += yi * wts[a];
             for (int b = 0; b < s; ++b) {
                 int oi = offset_index(d, m, nodes[a], nodes[b]);
                 wtw[nodes[a] * nb + oi] += wts[a] * wts[b];
@@ -188,6 +194,20 @@ int oracle_precompute(int d, const int64_t *m, const double *g0,
     }
     *yty = acc_yy;
     return 0;
+}
+
+int oracle_precompute(int d, const int64_t *m, const double *g0,
+                      const double *h, const double *x /* [d][n] */,
+                      const double *y, int64_t n, double *wtw, double *wty,
+                      double *yty, int64_t *bad) {
+    return precompute_impl(d, m, g0, h, x, y, n, wtw, wty, yty, bad, 0);
+}
+
+int oracle_precompute_abs(int d, const int64_t *m, const double *g0,
+                          const double *h, const double *x /* [d][n] */,
+                          const double *y, int64_t n, double *wtw, double *wty,
+                          double *yty, int64_t *bad) {
+    return precompute_impl(d, m, g0, h, x, y, n, wtw, wty, yty, bad, 1);
 }
 
 /* SplitMix64 finaliser (Vigna, public domain) applied to a counter. */

@@ -84,7 +84,8 @@ class _Desc(ctypes.Structure):
                 ("yty", ctypes.c_double), ("bytes_wtw", ctypes.c_int64),
                 ("nnz_wtw", ctypes.c_int64), ("halo", ctypes.c_int64),
                 ("wtw_blocks", ctypes.c_int64), ("wtw_blocks_nonzero", ctypes.c_int64),
-                ("wtw_block_entries", ctypes.c_int64), ("interp", ctypes.c_int)]
+                ("wtw_block_entries", ctypes.c_int64), ("interp", ctypes.c_int),
+                ("nnz_wtw_nonzero", ctypes.c_int64)]
 
 
 OP_F64, OP_STATS = 0, 1
@@ -110,7 +111,8 @@ class _MllOpts(ctypes.Structure):
 class _MllInfo(ctypes.Structure):
     _fields_ = [("logdet", ctypes.c_double), ("quad", ctypes.c_double),
                 ("iterations_y", ctypes.c_int), ("iterations_probes_max", ctypes.c_int),
-                ("batch_rhs", ctypes.c_int), ("batch_block", ctypes.c_int)]
+                ("batch_rhs", ctypes.c_int), ("batch_block", ctypes.c_int),
+                ("dquad", ctypes.c_double * 5)]
 
 
 _lib = None
@@ -245,6 +247,7 @@ class Handle:
         self.wtw_blocks = d.wtw_blocks
         self.wtw_blocks_nonzero = d.wtw_blocks_nonzero
         self.wtw_block_entries = d.wtw_block_entries
+        self.nnz_wtw_nonzero = d.nnz_wtw_nonzero
         self.interp = "linear" if d.interp == INTERP["linear"] else "cubic"
 
     @property
@@ -581,7 +584,8 @@ def mll_and_grad(h, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000, batched=Tr
                                     ctypes.byref(mll), grad, ctypes.byref(info), _stream()))
     return mll.value, [grad[i] for i in range(h.d + 2)], {
         "logdet": info.logdet, "quad": info.quad, "iterations_y": info.iterations_y,
-        "iterations_probes_max": info.iterations_probes_max, "status": st}
+        "iterations_probes_max": info.iterations_probes_max,
+        "dquad": [info.dquad[i] for i in range(h.d + 2)], "status": st}
 
 
 def batch_mll_and_grad(handles, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000,
@@ -606,6 +610,7 @@ def batch_mll_and_grad(handles, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000
     return ([mll[i] for i in range(n)],
             [[grad[5 * i + k] for k in range(handles[i].d + 2)] for i in range(n)],
             [{"logdet": infos[i].logdet, "quad": infos[i].quad,
+              "dquad": [infos[i].dquad[k] for k in range(handles[i].d + 2)],
               "iterations_y": infos[i].iterations_y,
               "iterations_probes_max": infos[i].iterations_probes_max,
               "batch_rhs": infos[i].batch_rhs, "batch_block": infos[i].batch_block,

@@ -32,11 +32,12 @@ struct fkgp_handle {
     void* A = nullptr;          // [NB][M] stats dtype
     double* wty = nullptr;      // [M]
     double* sketches = nullptr; // [nprobe][M]
-    double* yty_dev = nullptr;  // [3]: y^T y, the out-of-grid flag, the
+    double* yty_dev = nullptr;  // [4]: y^T y, the out-of-grid flag, the
                                 // number of nonzero blocks of W^T W (bits)
     uint32_t* bmask = nullptr;  // [mask_words(M)] block occupancy of W^T W
     double yty = 0.0;
     int64_t nzblocks = 0;
+    int64_t nnz = 0;            // nonzero stored entries of W^T W
     // points kept in cell order (keep_points): payload of dtype in_dt
     // (coordinates, y, original index) and the cell bounds
     void* pts_block = nullptr;
@@ -1177,8 +1178,10 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
         unsigned long long* bad = reinterpret_cast<unsigned long long*>(h->yty_dev + 1);
         (void)hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), s);
         (void)hipMemsetAsync(h->bmask, 0, sizeof(uint32_t) * (size_t)mask_words(M), s);
+        (void)hipMemsetAsync(h->yty_dev + 3, 0, sizeof(double), s);
         StatsOut so{h->A, h->wty, h->sketches, h->yty_dev, h->bmask,
-                    reinterpret_cast<unsigned long long*>(h->yty_dev + 2), nullptr, nullptr,
+                    reinterpret_cast<unsigned long long*>(h->yty_dev + 2),
+                    reinterpret_cast<unsigned long long*>(h->yty_dev + 3), nullptr, nullptr,
                     nullptr};
         if (o.keep_points) {
             int64_t ncells = 1;
@@ -1198,7 +1201,7 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
         }
         st = run_precompute(g, x, y, n, in, h->dt, h->nprobe, h->seed, so, bad, s);
         unsigned long long hbad = ~0ull;
-        double back[3] = {0.0, 0.0, 0.0};
+        double back[4] = {0.0, 0.0, 0.0, 0.0};
         if (st == FKGP_OK) {
             if ((e = hipMemcpyAsync(back, h->yty_dev, sizeof(back), hipMemcpyDeviceToHost, s)) !=
                 hipSuccess)
@@ -1212,6 +1215,9 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
         unsigned long long nzb = 0;
         std::memcpy(&nzb, &back[2], sizeof(nzb));
         h->nzblocks = (int64_t)nzb;
+        unsigned long long nnz = 0;
+        std::memcpy(&nnz, &back[3], sizeof(nnz));
+        h->nnz = (int64_t)nnz;
         if (hbad != ~0ull) {
             set_error("point " + std::to_string(hbad) + " lies outside the interpolable region");
             return fail(FKGP_EOUTOFGRID);
@@ -1240,6 +1246,7 @@ fkgp_status fkgp_describe(const fkgp_handle* h, fkgp_handle_desc* desc) {
     desc->wtw_blocks_nonzero = h->nzblocks;
     desc->wtw_block_entries = (int64_t)kWaveRows * mask_slab_width(h->g.d);
     desc->interp = h->g.interp;
+    desc->nnz_wtw_nonzero = h->nnz;
     return FKGP_OK;
 }
 
@@ -1547,8 +1554,10 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
         unsigned long long* bad = reinterpret_cast<unsigned long long*>(h->yty_dev + 1);
         (void)hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), s);
         (void)hipMemsetAsync(h->bmask, 0, sizeof(uint32_t) * (size_t)mask_words(M), s);
+        (void)hipMemsetAsync(h->yty_dev + 3, 0, sizeof(double), s);
         StatsOut so{h->A, h->wty, h->sketches, h->yty_dev, h->bmask,
-                    reinterpret_cast<unsigned long long*>(h->yty_dev + 2), nullptr, nullptr,
+                    reinterpret_cast<unsigned long long*>(h->yty_dev + 2),
+                    reinterpret_cast<unsigned long long*>(h->yty_dev + 3), nullptr, nullptr,
                     nullptr};
         if (n <= chunk) {   // one piece: the one-shot precompute from a device copy
             if ((e = dev_malloc(res.a, reinterpret_cast<void**>(&res.devbuf),
@@ -1621,7 +1630,7 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
             }
         }
         unsigned long long hbad = ~0ull;
-        double back[3] = {0.0, 0.0, 0.0};
+        double back[4] = {0.0, 0.0, 0.0, 0.0};
         if (st == FKGP_OK) {
             if ((e = hipMemcpyAsync(back, h->yty_dev, sizeof(back), hipMemcpyDeviceToHost, s)) !=
                 hipSuccess)
@@ -1635,6 +1644,9 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
         unsigned long long nzb = 0;
         std::memcpy(&nzb, &back[2], sizeof(nzb));
         h->nzblocks = (int64_t)nzb;
+        unsigned long long nnz = 0;
+        std::memcpy(&nnz, &back[3], sizeof(nnz));
+        h->nnz = (int64_t)nnz;
         if (hbad != ~0ull) {
             set_error("point " + std::to_string(hbad) + " lies outside the interpolable region");
             return fail(FKGP_EOUTOFGRID);
@@ -1780,10 +1792,18 @@ fkgp_status fkgp_load(const char* path, void* stream, fkgp_handle** out) {
         put(h->bmask, p + sec.a, sec.mask);
         put(h->wty, p + sec.a + sec.mask, sec.wty);
         put(h->sketches, p + sec.a + sec.mask + sec.wty, sec.sk);
-        const double tail[3] = {hd.yty, 0.0, 0.0};
+        const double tail[4] = {hd.yty, 0.0, 0.0, 0.0};
         put(h->yty_dev, tail, sizeof(tail));
+        unsigned long long* nnz_dev = reinterpret_cast<unsigned long long*>(h->yty_dev + 3);
+        if (e == hipSuccess && count_wtw_nonzeros(h->dt, h->A, dia_elems(M, h->NB), nnz_dev, s) !=
+                                   FKGP_OK)
+            e = hipErrorLaunchFailure;
+        unsigned long long nnz = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&nnz, nnz_dev, sizeof(nnz), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);   // buf and tail leave scope
         if (e != hipSuccess) return fail(hip_fail(e, "loading statistics"));
+        h->nnz = (int64_t)nnz;
         *out = h;
         return FKGP_OK;
     });
@@ -2285,7 +2305,7 @@ fkgp_status mll_post(const OpCtx& c, const fkgp_hypers* hyp, const fkgp_mll_opts
                      const double* V, const double* wx, const double* alphas,
                      const double* betas, const PState* ps, double* mll, double* grad,
                      Scratch& sc, hipStream_t st, double& logdet_out, double& q_out,
-                     const double* tr_exact = nullptr) {
+                     const double* tr_exact = nullptr, double* dq_out = nullptr) {
     const fkgp_handle* h = c.h;
     const int d = h->g.d;
     const int N = h->nprobe;
@@ -2361,6 +2381,11 @@ fkgp_status mll_post(const OpCtx& c, const fkgp_hypers* hyp, const fkgp_mll_opts
     grad[d + 1] = 0.5 * (2.0 * s2 * zz - trs);
     logdet_out = logdet;
     q_out = q;
+    if (dq_out) {   // dq/dtheta = -x_y^T (dA/dtheta) x_y
+        for (int k = 0; k < 5; ++k) dq_out[k] = 0.0;
+        for (int th = 0; th <= d; ++th) dq_out[th] = -quad[th];
+        dq_out[d + 1] = -2.0 * s2 * zz;
+    }
     if (!std::isfinite(logdet)) {
         set_error("Lanczos quadrature failed (non-finite log-determinant)");
         return FKGP_EDEVICE;
@@ -2534,7 +2559,7 @@ fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_ml
         return pres;
     }
     FKGP_HIP(hipMemcpyAsync(wx, V, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
-    double logdet = 0.0, q = 0.0;
+    double logdet = 0.0, q = 0.0, dq[5];
     std::vector<double> trx;
     if (o.trace_mode == 1) {
         trx.resize(h->g.d + 2);
@@ -2542,11 +2567,12 @@ fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_ml
         if (rs != FKGP_OK) return rs;
     }
     rs = mll_post(c, hyp, o, V, wx, alphas, betas, ps, mll, grad, sc, st, logdet, q,
-                  trx.empty() ? nullptr : trx.data());
+                  trx.empty() ? nullptr : trx.data(), dq);
     if (rs != FKGP_OK) return rs;
     if (info) {
         info->logdet = logdet;
         info->quad = q;
+        for (int k = 0; k < 5; ++k) info->dquad[k] = dq[k];
         info->iterations_y = sinfo.iterations;
         info->iterations_probes_max = iters_max;
     }
@@ -2777,16 +2803,17 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
             conv &= hsv[j].done == 1;
             if (j > 0) itmax = std::max(itmax, hsv[j].iters);
         }
-        double logdet = 0.0, q = 0.0;
+        double logdet = 0.0, q = 0.0, dq[5];
         Scratch sp_(st);
         rs = mll_post(ctx[p], &hyps[p], o, Vs[p], wxs[p], alph[p] + kMaxLanczos,
                       bet[p] + kMaxLanczos, pss[p] + 1, &mll[p], grad + 5 * p, sp_, st, logdet,
-                      q);
+                      q, nullptr, dq);
         if (rs != FKGP_OK) return rs;
         for (int k = h->g.d + 2; k < 5; ++k) grad[5 * p + k] = 0.0;
         if (infos) {
             infos[p].logdet = logdet;
             infos[p].quad = q;
+            for (int k = 0; k < 5; ++k) infos[p].dquad[k] = dq[k];
             infos[p].iterations_y = hsv[0].iters;
             infos[p].iterations_probes_max = itmax;
             infos[p].batch_rhs = NR;

@@ -223,6 +223,7 @@ struct StatsOut {
     double* yty_dev;    // scalar
     uint32_t* bmask;    // [mask_words(M)] block occupancy, zeroed by the caller
     unsigned long long* nzblocks;   // number of set mask bits (written last)
+    unsigned long long* nnz;        // nonzero stored entries of W^T W, zeroed by the caller
     // optional (d <= 2): copies of the points in cell order (payload of the
     // input dtype: coordinates, y, original index) and the cell bounds
     void* keep_pay;
@@ -260,6 +261,10 @@ fkgp_status run_precompute(const GridDev& g, const void* const* x, const void* y
                            int nprobe, uint64_t seed, const StatsOut& out,
                            unsigned long long* bad_dev, hipStream_t s,
                            const ChunkCtl* cc = nullptr);
+
+// *out += number of nonzero entries among the first `elems` of A (stats dtype).
+fkgp_status count_wtw_nonzeros(fkgp_dtype dt, const void* A, int64_t elems,
+                               unsigned long long* out, hipStream_t s);
 
 // ---- operators (ops.hip) -------------------------------------------------
 // Longest circulant handled by the register-resident line FFT, and by the

@@ -11,8 +11,14 @@
 //   3. per-cell moments in FP64, in sorted (= input) order within the cell:
 //      the cubic weights are polynomials of degree 3 in the fractional
 //      offset t, so sum_i w_i w_i^T over a cell is fixed by the 7^d moments
-//      sum_i prod_k t_k^{q_k} (q_k <= 6), and sum_i y_i w_i by the 4^d moments
-//      sum_i y_i prod_k t_k^{q_k} (q_k <= 3);
+//      sum_i prod_k b6_{q_k}(t_k) (q_k <= 6), and sum_i y_i w_i by the 4^d
+//      moments sum_i y_i prod_k b3_{q_k}(t_k) (q_k <= 3), in the Bernstein-
+//      type bases b6_q(t) = t^q (1-t)^(6-q) and b3_q(t) = t^q (1-t)^(3-q):
+//      every term is non-negative, and each product of two weights has
+//      Bernstein coefficients of one sign, so an entry of W^T W assembled
+//      from the moments carries no cancellation beyond that of its own
+//      defining sum (monomial moments t^q cancel badly for the small
+//      products near t = 0 or 1, e.g. w_{i+2}^2 = t^4 (1-t)^2 / 4);
 //   4. separable assembly: one pass per dimension turns a cell moment index
 //      q_k into a stencil offset o_k (resp. sums it out for the vectors),
 //      giving W^T W in stencil-diagonal form, W^T y and the sketches.
@@ -29,14 +35,29 @@ namespace {
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------
-// Interpolation weights as polynomials in t (ascending powers): weights of
-// the nodes i-1, i, i+1, i+2 of a point at offset t from node i; Keys cubic
-// convolution (a = -1/2), or linear interpolation (1 - t, t on i, i+1).
+// Interpolation weights as polynomials in t: weights of the nodes i-1, i,
+// i+1, i+2 of a point at offset t from node i; Keys cubic convolution
+// (a = -1/2), or linear interpolation (1 - t, t on i, i+1).  The tables hold
+// their coefficients in the bases b6 / b3 of the moments (see above).
 // ---------------------------------------------------------------------------
 struct KeysTables {
-    double E[7][4][7];   // [o+3][a][q]: coeff of t^q in w_a(t) w_{a+o}(t)
-    double C[4][4];      // [a][q]: coeff of t^q in w_a(t)
+    double E[7][4][7];   // [o+3][a][q]: coeff of b6_q in w_a(t) w_{a+o}(t)
+    double C[4][4];      // [a][q]: coeff of b3_q in w_a(t)
 };
+
+// Coefficients of sum_k c_k t^k (degree <= deg) on t^q (1-t)^(deg-q):
+// t^k = t^k (t + (1-t))^(deg-k) = sum_j binom(deg-k, j) t^(k+j) (1-t)^(deg-k-j).
+// Exact in FP64 here (dyadic coefficients times small binomials).
+void monomial_to_bernstein(const double* c, int deg, double* out) {
+    for (int q = 0; q <= deg; ++q) out[q] = 0.0;
+    for (int k = 0; k <= deg; ++k) {
+        double binom = 1.0;   // binom(deg-k, j)
+        for (int j = 0; j + k <= deg; ++j) {
+            out[k + j] += c[k] * binom;
+            binom = binom * (double)(deg - k - j) / (double)(j + 1);
+        }
+    }
+}
 
 KeysTables make_tables(int interp) {
     const double keys[4][4] = {{0.0, -0.5, 1.0, -0.5},
@@ -49,16 +70,34 @@ KeysTables make_tables(int interp) {
                               {0.0, 0.0, 0.0, 0.0}};
     const double (&w)[4][4] = interp == 1 ? lin : keys;
     KeysTables t{};
-    for (int a = 0; a < 4; ++a)
-        for (int q = 0; q < 4; ++q) t.C[a][q] = w[a][q];
+    for (int a = 0; a < 4; ++a) monomial_to_bernstein(w[a], 3, t.C[a]);
     for (int o = -3; o <= 3; ++o)
         for (int a = 0; a < 4; ++a) {
             int b = a + o;
             if (b < 0 || b > 3) continue;
+            double prod[7] = {};
             for (int p = 0; p < 4; ++p)
-                for (int q = 0; q < 4; ++q) t.E[o + 3][a][p + q] += w[a][p] * w[b][q];
+                for (int q = 0; q < 4; ++q) prod[p + q] += w[a][p] * w[b][q];
+            monomial_to_bernstein(prod, 6, t.E[o + 3][a]);
         }
     return t;
+}
+
+// The moment bases at t in [0,1]: b6[q] = t^q (1-t)^(6-q), b3[q] = t^q (1-t)^(3-q).
+__device__ inline void moment_basis(double t, double* b6, double* b3) {
+    const double s = 1.0 - t;
+    double tp[7], sp[7];
+    tp[0] = 1.0;
+    sp[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q < 7; ++q) {
+        tp[q] = tp[q - 1] * t;
+        sp[q] = sp[q - 1] * s;
+    }
+#pragma unroll
+    for (int q = 0; q < 7; ++q) b6[q] = tp[q] * sp[6 - q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b3[q] = tp[q] * sp[3 - q];
 }
 
 // Grid coordinate of one dimension: u = (x - g0)/h in FP64, interpolable iff
@@ -368,7 +407,8 @@ constexpr int ipow_c(int b) {
     return r;
 }
 
-constexpr int kPw = 22;   // LDS row: 7 powers per dimension (+ pad)
+constexpr int kPw = 34;   // LDS row: b6 (7 per dimension), then b3 (4 per dimension), pad
+constexpr int kB3 = 21;   // offset of the b3 values in a row
 
 template <int D, class Tin>
 __global__ __launch_bounds__(64) void cell_moments(
@@ -412,11 +452,10 @@ __global__ __launch_bounds__(64) void cell_moments(
                 int base;
                 double t;
                 locate((double)get_slot(p, k), g.g0[k], g.h[k], g.m[k], base, t);
-                double v = 1.0;
-                for (int q = 0; q < 7; ++q) {
-                    pw[lane][k * 7 + q] = v;
-                    v *= t;
-                }
+                double b6[7], b3[4];
+                moment_basis(t, b6, b3);
+                for (int q = 0; q < 7; ++q) pw[lane][k * 7 + q] = b6[q];
+                for (int q = 0; q < 4; ++q) pw[lane][kB3 + k * 4 + q] = b3[q];
             }
             // 3-D with probes: slot 3 holds the original index, y is read
             // through it; else slot D holds y and slot D + 1 the index
@@ -429,7 +468,7 @@ __global__ __launch_bounds__(64) void cell_moments(
                 for (int j = 0; j < nprobe; ++j) rvb[lane * nr + 1 + j] = rademacher(seed, j, orig);
             }
         } else {
-            for (int q = 0; q < 7 * D; ++q) pw[lane][q] = 0.0;
+            for (int q = 0; q < kPw; ++q) pw[lane][q] = 0.0;
             for (int j = 0; j < nr; ++j) rvb[lane * nr + j] = 0.0;
         }
         __syncthreads();
@@ -462,21 +501,24 @@ __global__ __launch_bounds__(64) void cell_moments(
                     for (int p = 0; p < cnt; ++p) {
                         const double yv = rvb[p * nr + r];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) accr[gi][q] = fma(yv, pw[p][q], accr[gi][q]);
+                        for (int q = 0; q < 4; ++q) accr[gi][q] = fma(yv, pw[p][kB3 + q], accr[gi][q]);
                     }
                 } else if constexpr (D == 2) {
                     const int r = col / 4, q1 = col % 4;
                     for (int p = 0; p < cnt; ++p) {
-                        const double yb = rvb[p * nr + r] * pw[p][7 + q1];
+                        const double yb = rvb[p * nr + r] * pw[p][kB3 + 4 + q1];
 #pragma unroll
-                        for (int q0 = 0; q0 < 4; ++q0) accr[gi][q0] = fma(pw[p][q0], yb, accr[gi][q0]);
+                        for (int q0 = 0; q0 < 4; ++q0)
+                            accr[gi][q0] = fma(pw[p][kB3 + q0], yb, accr[gi][q0]);
                     }
                 } else {
                     const int r = col / 16, q1 = (col / 4) % 4, q2 = col % 4;
                     for (int p = 0; p < cnt; ++p) {
-                        const double ybc = rvb[p * nr + r] * pw[p][7 + q1] * pw[p][14 + q2];
+                        const double ybc =
+                            rvb[p * nr + r] * pw[p][kB3 + 4 + q1] * pw[p][kB3 + 8 + q2];
 #pragma unroll
-                        for (int q0 = 0; q0 < 4; ++q0) accr[gi][q0] = fma(pw[p][q0], ybc, accr[gi][q0]);
+                        for (int q0 = 0; q0 < 4; ++q0)
+                            accr[gi][q0] = fma(pw[p][kB3 + q0], ybc, accr[gi][q0]);
                     }
                 }
             }
@@ -512,128 +554,126 @@ __global__ __launch_bounds__(64) void cell_moments(
     if (lane == 0) Myy[cell] = accyy;
 }
 
-// 3-D moments (no probes), accumulated in registers.  Lane l < 63 of the
-// wave belongs to point group g = l / 7 (points g, g + 9, g + 18, ... of the
-// cell, in sorted order) and owns the moments with q2 = l % 7: 49 sums over
-// (q0, q1) of t0^q0 t1^q1 t2^q2, and for q2 <= 3 the 16 response moments
-// y t0^q0 t1^q1 t2^q2 (q0, q1 <= 3).  Points are located in batches of 64
-// (one per lane) into LDS; at the end the 9 groups are summed in group
-// order through LDS.  Deterministic: every sum has a fixed order.
-constexpr int kMomGroups = 9;
+// 3-D moments (no probes), accumulated in registers.  The wave walks the
+// cell's points in batches of 64: each lane loads one point (the next
+// batch's load is in flight while the current batch is reduced), locates it
+// and writes its basis values b6, b3 of the three coordinates and y to one
+// LDS row.  Then lane l = 8 g + j of point group g (points g, g + 8, ... of
+// the batch, in sorted order) accumulates, for q2 = j (j < 7; lane j = 7
+// repeats q2 = 6 to keep the instruction stream uniform and discards it), the
+// 49 W moments b6_q0(t0) b6_q1(t1) b6_q2(t2), and the response moments
+// y b3_q0 b3_q1 b3_q2 with q2 = j / 2 and q1 = 2 (j % 2) + {0, 1} (8 of the
+// 64 per lane, so the y work is spread evenly over the group).  At the end
+// the 8 groups are summed in group order through LDS.  Deterministic: every
+// sum has a fixed order.
+constexpr int kRow3 = 34;   // LDS row: b6 x 3 (0..20), b3 x 3 (21..32), y (33)
 
 template <class Tin>
 __global__ __launch_bounds__(64) void cell_moments3(
     const typename PayloadOf<Tin>::type* __restrict__ pay,
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, GridDev g,
     double* __restrict__ Mw, double* __restrict__ Mr, double* __restrict__ Myy) {
-    __shared__ double pts[64][4];                     // t0, t1, t2, y
-    __shared__ double red[kMomGroups * 7][17];        // one chunk of 16 sums per lane
+    using P = typename PayloadOf<Tin>::type;
+    __shared__ __align__(16) double pts[64 * kRow3];
     const int cell = blockIdx.x;
     const int lane = threadIdx.x;
-    const int grp = lane / 7, q2 = lane % 7;
-    const bool act = lane < kMomGroups * 7;
+    const int grp = lane >> 3, j = lane & 7;
+    const int q2 = j < 7 ? j : 6;
+    const int q2y = j >> 1, q1y = 2 * (j & 1);
     const uint32_t s0 = cstart[cell];
     const uint32_t s1 = cend[cell];
-    double acc[7][7], accy[4][4];
+    double acc[7][7], accy[2][4];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
 #pragma unroll
-        for (int j = 0; j < 7; ++j) acc[i][j] = 0.0;
+        for (int k = 0; k < 7; ++k) acc[i][k] = 0.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) accy[i][j] = 0.0;
+        for (int k = 0; k < 4; ++k) accy[i][k] = 0.0;
     double accyy = 0.0;
+    P cur{};
+    if (s0 + lane < s1) cur = pay[s0 + lane];
     for (uint32_t b0 = s0; b0 < s1; b0 += 64) {
         const int cnt = (int)min(64u, s1 - b0);
         if (lane < cnt) {
-            const auto p = pay[b0 + lane];
+            double* row = pts + lane * kRow3;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 int base;
                 double t;
-                if (!locate((double)get_slot(p, k), g.g0[k], g.h[k], g.m[k], base, t)) t = 0.0;
-                pts[lane][k] = t;
+                if (!locate((double)get_slot(cur, k), g.g0[k], g.h[k], g.m[k], base, t)) t = 0.0;
+                moment_basis(t, row + 7 * k, row + 21 + 4 * k);
             }
-            pts[lane][3] = (double)get_slot(p, 3);
+            row[33] = (double)get_slot(cur, 3);
         }
+        if (b0 + 64 + lane < s1) cur = pay[b0 + 64 + lane];
         __syncthreads();
-        if (act) {
-            for (int p = grp; p < cnt; p += kMomGroups) {
-                const double t0 = pts[p][0], t1 = pts[p][1], t2 = pts[p][2], yv = pts[p][3];
-                double av[7], bv[7];
-                av[0] = 1.0;
-                bv[0] = 1.0;
+        for (int p = grp; p < cnt; p += 8) {
+            const double* r = pts + p * kRow3;
+            double av[7], bv[7];
 #pragma unroll
-                for (int q = 1; q < 7; ++q) {
-                    av[q] = av[q - 1] * t0;
-                    bv[q] = bv[q - 1] * t1;
-                }
-                const double t22 = t2 * t2;
-                double c = (q2 & 1) ? t2 : 1.0;
-                if (q2 & 2) c *= t22;
-                if (q2 & 4) c *= t22 * t22;
-#pragma unroll
-                for (int q0 = 0; q0 < 7; ++q0) {
-                    const double ac = av[q0] * c;
-#pragma unroll
-                    for (int q1 = 0; q1 < 7; ++q1) acc[q0][q1] = fma(ac, bv[q1], acc[q0][q1]);
-                }
-                if (q2 < 4) {
-                    const double yc = yv * c;
-#pragma unroll
-                    for (int q0 = 0; q0 < 4; ++q0) {
-                        const double ayc = av[q0] * yc;
-#pragma unroll
-                        for (int q1 = 0; q1 < 4; ++q1)
-                            accy[q0][q1] = fma(ayc, bv[q1], accy[q0][q1]);
-                    }
-                }
-                if (q2 == 0) accyy = fma(yv, yv, accyy);
+            for (int q = 0; q < 7; ++q) {
+                av[q] = r[q];
+                bv[q] = r[7 + q];
             }
+            const double c = r[14 + q2];
+#pragma unroll
+            for (int q0 = 0; q0 < 7; ++q0) {
+                const double ac = av[q0] * c;
+#pragma unroll
+                for (int q1 = 0; q1 < 7; ++q1) acc[q0][q1] = fma(ac, bv[q1], acc[q0][q1]);
+            }
+            const double yv = r[33];
+            const double yc = yv * r[29 + q2y];
+            const double y0 = yc * r[25 + q1y], y1 = yc * r[26 + q1y];
+#pragma unroll
+            for (int q0 = 0; q0 < 4; ++q0) {
+                const double a3 = r[21 + q0];
+                accy[0][q0] = fma(y0, a3, accy[0][q0]);
+                accy[1][q0] = fma(y1, a3, accy[1][q0]);
+            }
+            accyy = fma(yv, yv, accyy);
         }
         __syncthreads();
     }
-    // sum the 9 groups: 65 values per lane (49 W moments, 16 response
-    // moments), in chunks of 16 through LDS
+    // sum the 8 groups: 58 values per lane (49 W, 8 response, 1 y^2), in two
+    // chunks of 29 through the LDS table
+    constexpr int kCh = 29;
 #pragma unroll
-    for (int ch = 0; ch < 5; ++ch) {
-        if (act) {
+    for (int ch = 0; ch < 2; ++ch) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int v = ch * 16 + j;
-                double x = 0.0;
-                if (v < 49) x = acc[v / 7][v % 7];
-                else if (v < 65) x = accy[(v - 49) / 4][(v - 49) % 4];
-                red[lane][j] = x;
-            }
+        for (int i = 0; i < kCh; ++i) {
+            const int v = ch * kCh + i;
+            double x;
+            if (v < 49) x = acc[v / 7][v % 7];
+            else if (v < 57) x = accy[(v - 49) / 4][(v - 49) % 4];
+            else x = accyy;
+            pts[lane * kCh + i] = x;
         }
         __syncthreads();
-        for (int o = lane; o < 7 * 16; o += 64) {
-            const int oq2 = o / 16, j = o % 16;
-            const int v = ch * 16 + j;
+        for (int o = lane; o < 8 * kCh; o += 64) {
+            const int oj = o / kCh, i = o % kCh;
+            const int v = ch * kCh + i;
             double sum = 0.0;
-            for (int gg = 0; gg < kMomGroups; ++gg) sum += red[gg * 7 + oq2][j];
+            for (int gg = 0; gg < 8; ++gg) sum += pts[(gg * 8 + oj) * kCh + i];
             if (v < 49) {
-                Mw[(size_t)cell * 343 + v * 7 + oq2] = sum;   // q0*49 + q1*7 + q2
-            } else if (v < 65 && oq2 < 4) {
-                Mr[(size_t)cell * 64 + (v - 49) * 4 + oq2] = sum;   // q0*16 + q1*4 + q2
+                if (oj < 7) Mw[(size_t)cell * 343 + (v / 7) * 49 + (v % 7) * 7 + oj] = sum;
+            } else if (v < 57) {
+                const int k = v - 49;   // (pair, q0)
+                const int q1 = 2 * (oj & 1) + k / 4, q0 = k % 4;
+                Mr[(size_t)cell * 64 + q0 * 16 + q1 * 4 + (oj >> 1)] = sum;
+            } else if (oj == 0) {
+                Myy[cell] = sum;
             }
         }
         __syncthreads();
-    }
-    if (q2 == 0 && act) red[grp][0] = accyy;
-    __syncthreads();
-    if (lane == 0) {
-        double sum = 0.0;
-        for (int gg = 0; gg < kMomGroups; ++gg) sum += red[gg][0];
-        Myy[cell] = sum;
     }
 }
 
 // 2-D moments (no probes): lane l accumulates, over the points l, l + 64,
-// ... of the cell (sorted order), all 49 moments t0^q0 t1^q1 (q <= 6) and the
-// 16 response moments y t0^q0 t1^q1 (q <= 3) in registers; the 64 lanes are
+// ... of the cell (sorted order), all 49 moments b6_q0(t0) b6_q1(t1) and the
+// 16 response moments y b3_q0(t0) b3_q1(t1) in registers; the 64 lanes are
 // then summed in lane order through LDS.  Cells of the 2-D workloads hold
 // hundreds to thousands of points, so every lane stays busy.
 template <class Tin>
@@ -665,23 +705,18 @@ __global__ __launch_bounds__(64) void cell_moments2(
             if (!locate((double)get_slot(p, k), g.g0[k], g.h[k], g.m[k], base, t[k])) t[k] = 0.0;
         }
         const double yv = (double)get_slot(p, 2);
-        double av[7], bv[7];
-        av[0] = 1.0;
-        bv[0] = 1.0;
-#pragma unroll
-        for (int q = 1; q < 7; ++q) {
-            av[q] = av[q - 1] * t[0];
-            bv[q] = bv[q - 1] * t[1];
-        }
+        double av[7], bv[7], a3[4], b3[4];
+        moment_basis(t[0], av, a3);
+        moment_basis(t[1], bv, b3);
 #pragma unroll
         for (int q0 = 0; q0 < 7; ++q0)
 #pragma unroll
             for (int q1 = 0; q1 < 7; ++q1) acc[q0][q1] = fma(av[q0], bv[q1], acc[q0][q1]);
 #pragma unroll
         for (int q0 = 0; q0 < 4; ++q0) {
-            const double ay = av[q0] * yv;
+            const double ay = a3[q0] * yv;
 #pragma unroll
-            for (int q1 = 0; q1 < 4; ++q1) accy[q0][q1] = fma(ay, bv[q1], accy[q0][q1]);
+            for (int q1 = 0; q1 < 4; ++q1) accy[q0][q1] = fma(ay, b3[q1], accy[q0][q1]);
         }
         accyy = fma(yv, yv, accyy);
     }
@@ -803,7 +838,8 @@ __global__ void assemble_vec_stage(const double* __restrict__ in, double* __rest
 // rows past M in the last tile are written as zeros.
 template <class T>
 __global__ void transpose_to_dia(const double* __restrict__ in, T* __restrict__ out, int64_t M,
-                                 int NB, uint32_t* __restrict__ bmask) {
+                                 int NB, uint32_t* __restrict__ bmask,
+                                 unsigned long long* __restrict__ nnz) {
     __shared__ double tile[32][33];
     __shared__ uint32_t occ;
     const int64_t j0 = (int64_t)blockIdx.x * 32;
@@ -818,18 +854,27 @@ __global__ void transpose_to_dia(const double* __restrict__ in, T* __restrict__ 
     // the block's 32 rows lie in one wavefront chunk of one row tile
     const int w = (int)((j0 % kRowTile) / kWaveRows);
     uint32_t bits = 0u;
+    unsigned cnt = 0u;
     for (int r = threadIdx.y; r < 32; r += 8) {
         int o = o0 + r;
         int64_t j = j0 + threadIdx.x;
         if (o < NB) {
             const T v = (T)tile[threadIdx.x][r];
             out[dia_index(j, o, NB)] = v;
-            if (v != T(0)) bits |= 1u << (w * kMaskSlabs + o / 49);
+            if (v != T(0)) {
+                bits |= 1u << (w * kMaskSlabs + o / 49);
+                ++cnt;
+            }
         }
     }
-    // OR over the wavefront, then one LDS OR per wavefront (integer OR:
-    // order-independent)
-    for (int off = 32; off > 0; off >>= 1) bits |= (uint32_t)__shfl_xor((int)bits, off);
+    // OR and count over the wavefront, then one LDS OR and one counter add
+    // per wavefront (integer operations: order-independent)
+    for (int off = 32; off > 0; off >>= 1) {
+        bits |= (uint32_t)__shfl_xor((int)bits, off);
+        cnt += (unsigned)__shfl_xor((int)cnt, off);
+    }
+    if (((threadIdx.y * 32 + threadIdx.x) & 63) == 0 && cnt)
+        atomicAdd(nnz, (unsigned long long)cnt);
     if (((threadIdx.y * 32 + threadIdx.x) & 63) == 0 && bits) atomicOr(&occ, bits);
     __syncthreads();
     if (threadIdx.x == 0 && threadIdx.y == 0 && occ) atomicOr(&bmask[j0 / kRowTile], occ);
@@ -1092,10 +1137,10 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         dim3 tb(32, 8), tg((unsigned)(Mpad / 32), (unsigned)((NB + 31) / 32));
         if (stats == FKGP_F32)
             transpose_to_dia<float><<<tg, tb, 0, s>>>(src, static_cast<float*>(out.wtw), M, NB,
-                                                      out.bmask);
+                                                      out.bmask, out.nnz);
         else
             transpose_to_dia<double><<<tg, tb, 0, s>>>(src, static_cast<double*>(out.wtw), M, NB,
-                                                       out.bmask);
+                                                       out.bmask, out.nnz);
         FKGP_HIP(hipGetLastError());
         count_mask_bits<<<1, 256, 0, s>>>(out.bmask, mask_words(M), out.nzblocks);
         FKGP_HIP(hipGetLastError());
@@ -1144,7 +1189,7 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
 // Plain SKI operator on the kept points (Sec. 2.3: W K_G W^T + s2 I applied
 // to an n-vector, O(n + m log m) per product).  The points are in cell
 // order, so W^T v is the vector assembly of the precompute with y replaced
-// by v: per-cell moments sum_p v_p prod_k t_k^{q_k} (q_k <= 3, one wave per
+// by v: per-cell moments sum_p v_p prod_k b3_{q_k}(t_k) (q_k <= 3, one wave per
 // cell in 1-D and 2-D, four in 3-D, lanes striding over the cell's points,
 // fixed xor-trees across each wave), then the separable stages that turn moment digits into the 4
 // stencil offsets of each dimension.  W g gathers the 4^d stencil nodes of
@@ -1183,9 +1228,10 @@ __global__ __launch_bounds__(64 * ski_waves<D>()) void ski_cell_moments(
             int base;
             double t;
             if (!locate((double)get_slot(p, k), g.g0[k], g.h[k], g.m[k], base, t)) t = 0.0;
-            tq[k][0] = 1.0;
-            tq[k][1] = t;
-            tq[k][2] = t * t;
+            const double sk = 1.0 - t;   // b3_q(t) = t^q (1-t)^(3-q)
+            tq[k][0] = sk * sk * sk;
+            tq[k][1] = t * sk * sk;
+            tq[k][2] = t * t * sk;
             tq[k][3] = t * t * t;
         }
         double lead = v[i];
@@ -1362,6 +1408,29 @@ fkgp_status ski_y(const GridDev& g, fkgp_dtype in, const void* pay, int64_t n, d
         ski_extract_y<float><<<nb, 256, 0, s>>>(static_cast<const float4*>(pay), n, g.d, y);
     else
         ski_extract_y<double><<<nb, 256, 0, s>>>(static_cast<const double4*>(pay), n, g.d, y);
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+namespace {
+template <class T>
+__global__ __launch_bounds__(256) void count_nonzero(const T* __restrict__ a, int64_t n,
+                                                     unsigned long long* __restrict__ out) {
+    unsigned cnt = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        cnt += a[i] != T(0);
+    for (int off = 32; off > 0; off >>= 1) cnt += (unsigned)__shfl_xor((int)cnt, off);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(out, (unsigned long long)cnt);
+}
+}  // namespace
+
+fkgp_status count_wtw_nonzeros(fkgp_dtype dt, const void* A, int64_t elems,
+                               unsigned long long* out, hipStream_t s) {
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((elems + 255) / 256, 4096));
+    if (dt == FKGP_F32)
+        count_nonzero<float><<<nb, 256, 0, s>>>(static_cast<const float*>(A), elems, out);
+    else
+        count_nonzero<double><<<nb, 256, 0, s>>>(static_cast<const double*>(A), elems, out);
     FKGP_HIP(hipGetLastError());
     return FKGP_OK;
 }

@@ -223,32 +223,25 @@ def test_solve_errors():
     assert info["status"] == P.ENOTCONV and info["iterations"] == 2
 
 
-def moment_error_bound(grid, X, absx):
-    """Per-row bound on |(W^T W - A) |x|| for entries assembled from per-cell
-    monomial moments: an entry is sum_q c_q M_q with M_q = sum_p prod_k t^q
-    (0 <= t <= 1, so |M_q| <= count), the products of two Keys weights have
-    at most 25 in absolute coefficient sum per dimension, and the FP64
-    accumulation of the moments and their evaluation err by at most
-    (64 + count) eps64 times sum_q |c_q| M_q.  An entry that
-    is tiny against its moments (a node reached only by near-zero weights of
-    a few points) can so be far from the oracle's value relative to itself,
-    though never by more than this.  S_j = points in the cells whose stencils
-    contain node j; B_j = sum of |x| over the 7^d offsets of row j."""
-    from scipy import ndimage
+def entry_rounding_bound(grid, X, y, absx):
+    """Per-row bound on |(W^T W - A) |x|| from the rounding of the entries
+    themselves: any summation order of an entry sum_p w_a(p) w_b(p) errs by
+    at most c eps64 (|W|^T |W|)_entry, with c the number of terms plus the
+    FP64 operations of each (here 64 + the most points in a cell); the GPU
+    forms entries from per-cell moments in a Bernstein basis, where every
+    moment term is non-negative and every weight product has coefficients
+    of one sign, so it meets the same bound."""
+    wabs, _, _ = oracle.precompute(grid, X, y, absolute=True)
     d = grid["d"]
     m = list(grid["m"])
     idx = []
     for k in range(d):
         u = (X[k].astype(np.float64) - grid["origin"][k]) / grid["spacing"][k]
-        idx.append(np.minimum(np.floor(u).astype(np.int64), m[k] - 3) - 1)   # cell = base - 1
+        idx.append(np.minimum(np.floor(u).astype(np.int64), m[k] - 3) - 1)
     counts = np.zeros([mk - 3 for mk in m])
     np.add.at(counts, tuple(idx), 1.0)
-    # cell c (nodes c .. c+3 per dimension) reaches nodes c .. c+3
-    S = np.zeros(m)
-    for off in np.ndindex(*([4] * d)):
-        S[tuple(slice(o, o + mk - 3) for o, mk in zip(off, m))] += counts
-    B = ndimage.convolve(absx.reshape(m), np.ones([7] * d), mode="constant", cval=0.0)
-    return ((64 + S) * 2.0 ** -52 * 25.0 ** d * S * B).reshape(-1)
+    c = 2.0 * (64 + counts.max())
+    return c * 2.0 ** -52 * oracle.wtw_matvec(grid, wabs, absx)
 
 
 @pytest.mark.parametrize("d,m", [(1, [1000]), (2, [37, 29]), (2, [256, 250]), (3, [14, 11, 9]),
@@ -269,8 +262,8 @@ def test_wtw_matvec_tiled_parity(d, m, xdt):
     # The rows are 7^d-term sums with cancellation, so the bound is the
     # standard dot-product bound n_terms * eps * (|A| |x|) per row, plus one
     # FP32 ulp of |A| |x|: the stored FP32 entries are rounded from the GPU's
-    # own FP64 moments and may sit one FP32 ulp from the rounded oracle values,
-    # plus the moment-form error of the entries (moment_error_bound).
+    # own FP64 entries and may sit one FP32 ulp from the rounded oracle
+    # values, plus the FP64 rounding of the entries (entry_rounding_bound).
     w32 = wtw_o.astype(np.float32).astype(np.float64)
     eps = 2.0 ** -52 if xdt == "f64" else 2.0 ** -23
     nt = 7 ** d
@@ -280,7 +273,7 @@ def test_wtw_matvec_tiled_parity(d, m, xdt):
         ref = oracle.wtw_matvec(grid, w32, vr)
         absax = oracle.wtw_matvec(grid, np.abs(w32), np.abs(vr))
         bound = ((2 * nt * eps + 2.0 ** -23) * absax
-                 + moment_error_bound(grid, X, np.abs(vr)) + 1e-300)
+                 + entry_rounding_bound(grid, X, y, np.abs(vr)) + 1e-300)
         assert np.all(np.abs(uv - ref) <= bound), float(np.max(np.abs(uv - ref) / bound))
 
     check(u, v)
@@ -351,7 +344,7 @@ def test_zero_block_skipping(d):
                 # one FP32 ulp of |A||x| for the stored entries (rounded from
                 # the GPU's own FP64 moments) on top of the dot-product bound
                 bound = ((2 * nterm * eps + 2.0 ** -23) * absax
-                         + moment_error_bound(grid, X, np.abs(vr)) + 1e-300)
+                         + entry_rounding_bound(grid, X, y, np.abs(vr)) + 1e-300)
                 err = np.abs(U[r] - ref)
                 i = int(np.argmax(err / bound))
                 assert err[i] <= bound[i], (dt, k, r, i, err[i], absax[i], U[r][i], ref[i])

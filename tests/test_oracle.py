@@ -443,6 +443,44 @@ def test_slq_logdet_unbiased():
     assert abs(samples.mean() - exact) < 4 * se + 1e-6 * abs(exact), (samples.mean(), exact, se)
 
 
+def test_mll_value_with_unit_probes_equals_dense_def2():
+    """Pins the assembled value -1/2 (logdet + q + n log 2 pi) deterministically
+    (Fact 2 / Def. 2).  With the n probes z_i = sqrt(n) e_i (||z_i||^2 = n,
+    as for a Rademacher probe) and each probe's Lanczos run until its Krylov
+    space is exhausted (A = W K_G W^T + s2 I is a rank-M update of s2 I, so
+    at most M + 1 steps), Gauss quadrature gives e_i^T log(A) e_i exactly and
+    the estimator sums to tr log A = logdet A: the oracle's MLL must then
+    equal the Cholesky MLL of Def. 2.  A dropped n log 2 pi, a sign slip or
+    a wrong factor on q or on the log-determinant fails this test."""
+    for seed, m, n in ((12, (6, 5), 90), (13, (20,), 70)):
+        grid, X, y, hyp = small_problem(seed, m, n)
+        wtw, wty, yty = oracle.precompute(grid, X, y)
+        sk = np.sqrt(n) * oracle.dense_w(grid, X)      # rows: W^T (sqrt(n) e_i)
+        mll, _, info = oracle.mll_and_grad(grid, hyp, wtw, wty, yty, n, sk,
+                                           lanczos_steps=10 ** 6, tol=1e-13, maxiter=400)
+        W = oracle.dense_w(grid, X)
+        A = W @ oracle.kg_dense(grid, hyp) @ W.T + hyp["noise"] ** 2 * np.eye(n)
+        exact_logdet = np.linalg.slogdet(A)[1]
+        ref = oracle.ski_dense_mll(grid, hyp, X, y)
+        assert abs(info["logdet"] - exact_logdet) <= 1e-9 * abs(exact_logdet), (
+            info["logdet"], exact_logdet)
+        assert abs(mll - ref) <= 1e-9 * abs(ref), (mll, ref)
+
+
+def test_mll_value_rademacher_within_standard_errors():
+    """The same value with 256 Rademacher probes and full-length Lanczos:
+    unbiased (Hutchinson), so it lands within 4 standard errors (from the
+    per-probe log-determinant samples) of the Def. 2 MLL."""
+    grid, X, y, hyp = small_problem(14, (7, 6), 130)
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    sk = oracle.probe_sketches(grid, X, 41, 256)
+    mll, _, info = oracle.mll_and_grad(grid, hyp, wtw, wty, yty, 130, sk,
+                                       lanczos_steps=10 ** 6, tol=1e-12, maxiter=400)
+    ref = oracle.ski_dense_mll(grid, hyp, X, y)
+    se = 0.5 * info["logdet_samples"].std(ddof=1) / np.sqrt(256)
+    assert abs(mll - ref) <= 4 * se + 1e-9 * abs(ref), (mll, ref, se)
+
+
 def test_hutchinson_gradient_close_to_exact():
     grid, X, y, hyp = small_problem(10, (6, 6), 140)
     wtw, wty, yty = oracle.precompute(grid, X, y)
