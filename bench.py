@@ -3,10 +3,11 @@
 
 A step is one pass of the hot path over the 3-D sweep-shaped workload
 (n = 1e8 points in a cylinder, m = 100 x 100 x 30 = 300,000 grid nodes, FP32
-inputs and statistics, FP64 CG scalars): the one-shot O(n) precompute of
-W^T W, W^T y, y^T y followed by the posterior-mean solve (spectra, factorized
-CG with FP32 operator and FP64 refinement, final K_G product).  Inputs are
-generated on the device before timing.
+inputs, W^T W stored in FP32): the one-shot O(n) precompute of W^T W, W^T y,
+y^T y followed by the posterior-mean solve (spectra, the simplified
+factorized CG with FP64 operator arithmetic on the FP32-stored W^T W and FP64
+vectors and scalars, final K_G product).  Inputs are generated on the device
+before timing.
 
 value            = n * steps / timed seconds  (Mpts/s through the whole step)
 mll_grad         = differentiation workload: batched FP32 vs plain FP64 path
@@ -16,12 +17,18 @@ ski_sweep        = per-iteration time, factorized CG vs the plain SKI CG in
 precompute_*     = n / precompute time (precompute_host: from host memory,
                    PCIe transfers included)
 cg_mvms_per_s    = CG iterations (one operator B each) per second of solve
-roofline         = banded W^T W product (the dominant kernel of the solve),
-                   algorithmic bytes / average launch duration (HIP events);
-                   the algorithmic bytes are the nonzero 64-row blocks of the
-                   stored W^T W (the kernel reads only these) plus x and u
+roofline         = banded W^T W product as the CG loop launches it (with its
+                   fused u^T r reduction), algorithmic bytes / average launch
+                   duration (HIP events on the library's stream, hot); the
+                   algorithmic bytes are the exact nonzero entries of W^T W
+                   (FP32) plus x and u (FP64); the fraction on the nonzero
+                   64-row blocks (what the kernel reads) and a cold figure
+                   (512 MiB written between launches) are reported beside it
+mean_rel_err_vs_f64_tight = the timed solve's mu_G against an FP64-statistics
+                   solve to relative residual 1e-8 on the same points
 cpu_baseline     = the FP64 CPU oracle on a bounded sample, scaled to the
-                   same per-step work (see "sample")
+                   same per-step work (see "sample"), on all host cores
+                   (OpenMP statistics and product, threaded FFTs) and on one
 """
 import argparse
 import json
@@ -67,39 +74,75 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """CPU model and the number of cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
 def cpu_baseline(wl, n_total, iters, budget_s):
-    """Times the oracle (plain serial FP64 C precompute + NumPy/SciPy operator)
-    on a bounded sample and scales it to one step of the full workload."""
+    """Times the oracle (FP64 C statistics + NumPy/SciPy operator) on a
+    bounded sample and scales it to one step of the full workload: on all
+    the cores this process may use (OpenMP statistics with per-thread
+    accumulators combined in thread order, row-parallel banded product,
+    threaded FFTs) and on one core (the serial reference)."""
     import numpy as np
     import oracle
     grid = wl["grid"]
-    # precompute: calibrate on 20k points, then size the sample to the budget
-    n_cal = 20_000
-    xs = [c[:n_cal].cpu().numpy() for c in wl["x"]]
-    ys = wl["y"][:n_cal].cpu().numpy()
-    t0 = time.perf_counter()
-    oracle.precompute(grid, xs, ys)
-    per_pt = (time.perf_counter() - t0) / n_cal
-    n_s = int(min(n_total, max(n_cal, 0.6 * budget_s / per_pt)))
-    xs = [c[:n_s].cpu().numpy() for c in wl["x"]]
-    ys = wl["y"][:n_s].cpu().numpy()
-    t0 = time.perf_counter()
-    wtw, wty, yty = oracle.precompute(grid, xs, ys)
-    t_pre = time.perf_counter() - t0
-    # operator B at the full grid size (the oracle's MVM), 2 reps
-    v = np.random.default_rng(0).standard_normal(wty.shape[0])
-    reps = 2
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        oracle.B_apply(grid, wl["hypers"], wtw, v)
-    t_mvm = (time.perf_counter() - t0) / reps
-    t_step = t_pre * (n_total / n_s) + iters * t_mvm
-    return {"value": n_total / t_step / 1e6, "unit": "Mpts/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle precompute on the first {n_s} points ({t_pre:.1f} s, "
-                       f"{n_s / t_pre / 1e6:.4f} Mpts/s) scaled to n={n_total}, plus "
-                       f"{iters} oracle operator applications at m={wty.shape[0]} "
-                       f"({t_mvm:.3f} s each, {reps} timed)"),
-            "precompute_mpts_per_s": n_s / t_pre / 1e6, "mvm_per_s": 1.0 / t_mvm}
+    model, avail = host_cpu()
+    threads = max(1, min(avail, int(os.environ.get("OMP_NUM_THREADS", avail))))
+    out = {}
+    for name, th, share in (("all", threads, 0.6), ("one", 1, 0.25)):
+        # precompute: calibrate on a small sample, then size it to the budget
+        n_cal = 20_000 * th
+        xs = [c[:n_cal].cpu().numpy() for c in wl["x"]]
+        ys = wl["y"][:n_cal].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.precompute(grid, xs, ys, threads=th)
+        per_pt = (time.perf_counter() - t0) / n_cal
+        n_s = int(min(n_total, max(n_cal, share * budget_s / per_pt)))
+        xs = [c[:n_s].cpu().numpy() for c in wl["x"]]
+        ys = wl["y"][:n_s].cpu().numpy()
+        t0 = time.perf_counter()
+        wtw, wty, yty = oracle.precompute(grid, xs, ys, threads=th)
+        t_pre = time.perf_counter() - t0
+        # operator B at the full grid size (the oracle's MVM), 2 reps
+        v = np.random.default_rng(0).standard_normal(wty.shape[0])
+        reps = 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            oracle.B_apply(grid, wl["hypers"], wtw, v, threads=th)
+        t_mvm = (time.perf_counter() - t0) / reps
+        t_step = t_pre * (n_total / n_s) + iters * t_mvm
+        out[name] = {"value": n_total / t_step / 1e6, "threads": th, "n_sample": n_s,
+                     "precompute_s": t_pre, "precompute_mpts_per_s": n_s / t_pre / 1e6,
+                     "mvm_s": t_mvm, "mvm_per_s": 1.0 / t_mvm}
+        log(f"cpu oracle, {th} thread(s): precompute {n_s / t_pre / 1e6:.4f} Mpts/s on {n_s} "
+            f"points, operator {1.0 / t_mvm:.2f} MVM/s, scaled step {out[name]['value']:.5f} Mpts/s")
+        del wtw, wty
+    a, o = out["all"], out["one"]
+    return {"value": a["value"], "unit": "Mpts/s", "cores": a["threads"], "kind": "oracle",
+            "cpu": model, "cores_available": avail,
+            "sample": (f"oracle statistics on the first {a['n_sample']} points "
+                       f"({a['precompute_s']:.1f} s, {a['precompute_mpts_per_s']:.4f} Mpts/s on "
+                       f"{a['threads']} threads) scaled to n={n_total}, plus {iters:.0f} oracle "
+                       f"operator applications at m={int(np.prod(grid['m']))} "
+                       f"({a['mvm_s']:.3f} s each, 2 timed)"),
+            "precompute_mpts_per_s": a["precompute_mpts_per_s"], "mvm_per_s": a["mvm_per_s"],
+            "one_core": {"value": o["value"], "precompute_mpts_per_s": o["precompute_mpts_per_s"],
+                         "mvm_per_s": o["mvm_per_s"], "n_sample": o["n_sample"]}}
 
 
 def mll_compare(P, workloads, torch, dev, reps, tol, maxiter):
@@ -133,12 +176,34 @@ def mll_compare(P, workloads, torch, dev, reps, tol, maxiter):
     import numpy as np
     gdiff = float(np.max(np.abs(np.array(a["grad"]) - np.array(b["grad"])))
                   / np.max(np.abs(np.array(b["grad"]))))
+    # accuracy of both timed paths against a tight FP64 reference with the
+    # same probes and Lanczos size (FP64 statistics, solves to 1e-10)
+    h = P.precompute(wl["grid"], wl["x"], wl["y"], stats_dtype=torch.float64,
+                     n_probes=wl["nprobes"], probe_seed=wl["probe_seed"])
+    ref_tol = 1e-10
+    rv, rg, ri = P.mll_and_grad(h, hyp, wl["lanczos_steps"], ref_tol, 200000, batched=True)
+    h.close()
+    rg = np.array(rg)
+    for rec in (a, b):
+        rec["mll_rel_err_vs_ref"] = abs(rec["mll"] - rv) / abs(rv)
+        rec["grad_rel_err_vs_ref"] = float(np.max(np.abs(np.array(rec["grad"]) - rg))
+                                           / np.max(np.abs(rg)))
+    log(f"mll reference (FP64, tol {ref_tol:g}): {rv:.6f}; errors: batched FP32 "
+        f"{a['mll_rel_err_vs_ref']:.2e} / {a['grad_rel_err_vs_ref']:.2e}, plain FP64 "
+        f"{b['mll_rel_err_vs_ref']:.2e} / {b['grad_rel_err_vs_ref']:.2e}")
     return {"workload": "prior2d: n=4e6 x~U[0,1]^2, grid 256x256, GSGP-prior y (l=0.04, "
                         "s=1.5, sigma=0.1), evaluated at l=0.05, s=1.0, sigma=0.15; 16 probes, "
                         "30 Lanczos steps, tol %g" % tol,
             "batched_f32_s_per_eval": a["s_per_eval"], "plain_f64_s_per_eval": b["s_per_eval"],
             "speedup": b["s_per_eval"] / a["s_per_eval"],
             "mll_rel_diff": abs(a["mll"] - b["mll"]) / abs(b["mll"]), "grad_rel_diff": gdiff,
+            "reference": {"stats": "f64", "tol": ref_tol, "mll": rv, "grad": rg.tolist(),
+                          "iterations_y": ri["iterations_y"],
+                          "iterations_probes_max": ri["iterations_probes_max"]},
+            "batched_f32_mll_rel_err": a["mll_rel_err_vs_ref"],
+            "batched_f32_grad_rel_err": a["grad_rel_err_vs_ref"],
+            "plain_f64_mll_rel_err": b["mll_rel_err_vs_ref"],
+            "plain_f64_grad_rel_err": b["grad_rel_err_vs_ref"],
             "mll": b["mll"], "grad": b["grad"],
             "converged": a["status"] == 0 and b["status"] == 0,
             "iterations_y": b["iterations_y"], "iterations_probes_max": b["iterations_probes_max"]}
@@ -418,26 +483,53 @@ def main():
     log(f"timed {args.steps} steps: {elapsed:.3f} s; precompute {t_pre*1e3:.2f} ms, "
         f"solve {t_sol*1e3:.2f} ms, iterations {iters}")
 
-    # dominant kernel: the banded W^T W product (one per CG iteration)
+    # dominant kernel: the banded W^T W product, launched as the CG loop
+    # launches it (FP32 entries, FP64 vectors, u^T r reduced in the same
+    # launch), timed with HIP events on the library's stream
     M = h.m_total
-    # the product as the FP64-arithmetic CG runs it: FP32 entries, FP64 vectors
     x = torch.randn(M, device=dev, dtype=torch.float64)
     xp = P.padded(h, x, torch.float64)
     u = torch.empty(1, M, device=dev, dtype=torch.float64)
-    for _ in range(3):
-        P.wtw_matvec_padded(h, xp, u)
+    P.wtw_matvec_dot(h, xp, u, reps=3)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(args.mvm_reps):
-        P.wtw_matvec_padded(h, xp, u)
+    P.wtw_matvec_dot(h, xp, u, reps=args.mvm_reps)
     e1.record()
     torch.cuda.synchronize()
     t_spmv = e0.elapsed_time(e1) / args.mvm_reps / 1e3
-    # FP32 entries of the nonzero blocks, FP64 x read + u written
-    alg_bytes = 4 * h.wtw_blocks_nonzero * h.wtw_block_entries + 8 * 2 * M
-    log(f"W^T W blocks: {h.wtw_blocks_nonzero} of {h.wtw_blocks} nonzero")
+    # cold: 512 MiB written between launches (flushes the 256 MiB MALL and L2)
+    flush = torch.empty(128 << 20, device=dev, dtype=torch.float32)
+    cold = []
+    for r in range(10):
+        flush.fill_(float(r))
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        P.wtw_matvec_dot(h, xp, u, reps=1)
+        c1.record()
+        torch.cuda.synchronize()
+        cold.append(c0.elapsed_time(c1) / 1e3)
+    del flush
+    t_cold = sum(cold) / len(cold)
+    # algorithmic bytes: the exact nonzero FP32 entries, FP64 x read and u
+    # written; beside it the bytes of the nonzero 64-row blocks it reads
+    alg_bytes = 4 * h.nnz_wtw_nonzero + 8 * 2 * M
+    block_bytes = 4 * h.wtw_blocks_nonzero * h.wtw_block_entries + 8 * 2 * M
+    log(f"W^T W: {h.nnz_wtw_nonzero} nonzero entries; {h.wtw_blocks_nonzero} of "
+        f"{h.wtw_blocks} blocks nonzero")
     achieved = alg_bytes / t_spmv / 1e9
-    log(f"spmv avg {t_spmv*1e6:.1f} us, {achieved:.0f} GB/s algorithmic")
+    log(f"spmv (in-loop form) avg {t_spmv*1e6:.1f} us hot, {t_cold*1e6:.1f} us cold; "
+        f"{achieved:.0f} GB/s on exact nonzeros, {block_bytes / t_spmv / 1e9:.0f} GB/s on blocks")
+    # precompute: algorithmic bytes = the points read (x, y: 16 B each) and
+    # the statistics written once (W^T W FP32 exact nonzeros, W^T y)
+    pre_bytes = n * 4 * (h.d + 1) + 4 * h.nnz_wtw_nonzero + 8 * M
+    # accuracy of the timed solve: against an FP64-statistics solve to 1e-8
+    h64 = P.precompute(grid, wl["x"], wl["y"], stats_dtype=torch.float64)
+    mu64, info64 = P.solve(h64, hyp, tol=1e-8, maxiter=200000)
+    mean_err = float(torch.linalg.norm(mu - mu64) / torch.linalg.norm(mu64))
+    log(f"timed solve's mean vs FP64 statistics at tol 1e-8 ({info64['iterations']} "
+        f"iterations): rel. err {mean_err:.2e}")
+    h64.close()
+    del mu64
 
     iters_mean = sum(iters) / len(iters)
     result = {
@@ -455,17 +547,27 @@ def main():
         "data": "synthetic",
         "config": {"workload": "radar3d: n=1e8 cylinder r<=1, 0<=z<0.3, areal density ~1/(r+0.05), "
                                "50 anisotropic blobs + N(0,0.1^2); grid 100x100x30 (m=300000); "
-                               "SE l=(0.05,0.05,0.02) s=1 sigma=0.1; FP32 stats/operator, FP64 CG",
+                               "SE l=(0.05,0.05,0.02) s=1 sigma=0.1; FP32 inputs and stored W^T W, "
+                               "FP64 operator arithmetic, FP64 CG vectors and scalars",
                    "n": n, "m": M, "tol": args.tol, "step": "precompute + posterior-mean solve"},
         "precompute_mpts_per_s": n / t_pre / 1e6,
         "precompute_ms": t_pre * 1e3,
+        "precompute_alg_bytes": pre_bytes,
+        "precompute_hbm_frac": pre_bytes / t_pre / 1e9 / HBM_PEAK_GBS,
         "solve_ms": t_sol * 1e3,
         "cg_iterations": iters_mean,
         "cg_mvms_per_s": iters_mean / t_sol,
+        "mean_rel_err_vs_f64_tight": mean_err,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": SPMV_TRAFFIC_BYTES,
-                     "kernel": "spmv_tiled_kernel<float,double,3> (banded W^T W product)",
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_us": t_spmv * 1e6},
+                     "kernel": "spmv_tiled_kernel<float,double,3> (banded W^T W product with "
+                               "the fused u^T r reduction, as in the CG loop)",
+                     "alg_bytes_per_launch": alg_bytes, "nnz_exact": h.nnz_wtw_nonzero,
+                     "avg_launch_us": t_spmv * 1e6,
+                     "block_bytes_per_launch": block_bytes,
+                     "frac_on_nonzero_blocks": block_bytes / t_spmv / 1e9 / HBM_PEAK_GBS,
+                     "cold_avg_launch_us": t_cold * 1e6,
+                     "cold_frac": alg_bytes / t_cold / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_mll:
         torch.cuda.empty_cache()

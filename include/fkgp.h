@@ -206,6 +206,25 @@ fkgp_status fkgp_solve(const fkgp_handle* h, const fkgp_hypers* hyp,
                        const fkgp_solve_opts* opts, fkgp_solve_info* info,
                        void* stream);
 
+/* fkgp_solve for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid device or pinned
+ * allocations): the same solve and the same results as fkgp_solve, with
+ * every buffer of the call (spectra, CG vectors, reduction partials, state)
+ * carved from a fixed 64 MiB device workspace that the library holds, one
+ * per GPU, until the process ends; no hipMalloc, hipFree, pinned host memory
+ * or other allocating routine is called, and convergence is checked by a
+ * synchronous copy of the solver state after every 8 iterations.
+ * Returns FKGP_EINVAL (before any launch) when the grid needs more workspace
+ * than that, as grids of more than about 500,000 nodes do, or grids with a
+ * dimension of more than 1024 nodes that takes the four-step line FFT.  All
+ * calls on one GPU share its workspace: calls that overlap on one GPU (other
+ * host threads, other streams) race and must not be made.
+ * Synchronises `stream`. */
+fkgp_status fkgp_solve_noalloc(const fkgp_handle* h, const fkgp_hypers* hyp,
+                               const double* rhs_grid, double* out,
+                               const fkgp_solve_opts* opts, fkgp_solve_info* info,
+                               void* stream);
+
 /* k grid right-hand sides at once: out_j = W^T (W K_G W^T + s2 I)^{-1} W rhs_j
  * (the rhs_grid case of fkgp_solve for each column).  rhs_grid, out: device
  * doubles [k][m].  The solves advance together, 64 at a time, from x_0 = 0
@@ -376,6 +395,17 @@ fkgp_status fkgp_kg_matvec(const fkgp_handle* h, const fkgp_hypers* hyp,
  * for all k vectors.  Does not synchronise. */
 fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int k,
                             fkgp_dtype xdt, void* stream);
+
+/* The banded product as the factorized CG's loop launches it (Claim 2; one
+ * per iteration of the simplified factorized CG of the appendix): u = (W^T W) x
+ * for one FP64 vector (xdt must be FKGP_F64; x padded as for
+ * fkgp_wtw_matvec) with the dot product u^T x reduced inside the same launch
+ * (the last workgroup sums the per-tile partials in index order) when the
+ * tiled kernel runs, else by a separate reduction.  The launch is repeated
+ * `reps` >= 1 times on the same input (a timing aid); *dot (a device double)
+ * receives u^T x.  Does not synchronise. */
+fkgp_status fkgp_wtw_matvec_dot(const fkgp_handle* h, const void* xpad, void* u,
+                                fkgp_dtype xdt, double* dot, int reps, void* stream);
 
 /* fkgp_precompute from points in host memory (x: d host pointers, y: host
  * pointer, dtype `in`), for data sets larger than one transfer or device

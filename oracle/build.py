@@ -2,7 +2,7 @@
 
 ``python oracle/build.py`` compiles ``precompute.c`` into ``liboracle.so``
 next to it with gcc, without fast-math or FMA contraction, so every result is
-the plain serial FP64 definition.
+the plain FP64 definition (OpenMP serves only the *_omp timing variants).
 """
 import os
 import subprocess
@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-fno-fast-math", "-fopenmp", "-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -36,6 +36,11 @@ def _lib():
         L.oracle_splitmix64.restype = ctypes.c_uint64
         L.oracle_interpolate.argtypes = [ctypes.c_int, p, p, p, p, p, i64, p, p]
         L.oracle_wtw_matvec.argtypes = [ctypes.c_int, p, p, p, p, ctypes.c_int]
+        L.oracle_precompute_omp.argtypes = [ctypes.c_int, p, p, p, p, p, i64, p, p, p, p,
+                                            ctypes.c_int]
+        L.oracle_precompute_omp.restype = ctypes.c_int
+        L.oracle_wtw_matvec_omp.argtypes = [ctypes.c_int, p, p, p, p, ctypes.c_int, ctypes.c_int]
+        L.oracle_wtw_matvec_omp.restype = None
         L.oracle_set_interp.argtypes = [ctypes.c_int]
         L.oracle_set_interp.restype = None
         for f in (L.oracle_stencils, L.oracle_precompute, L.oracle_precompute_abs,
@@ -104,11 +109,13 @@ def stencils(grid, x):
     return nodes, w, cells
 
 
-def precompute(grid, x, y, absolute=False):
+def precompute(grid, x, y, absolute=False, threads=1):
     """Sufficient statistics (W^T W in [M, 7^d] stencil-diagonal layout,
     W^T y [M], y^T y), accumulated serially in FP64 in input order.  With
     `absolute`, the same sums over |w| and |y| (|W|^T |W|, |W|^T |y|): the
-    scale of the rounding error of any summation order, for error bounds."""
+    scale of the rounding error of any summation order, for error bounds.
+    threads > 1: the OpenMP variant (contiguous point chunks per thread,
+    combined in thread order; deterministic per thread count)."""
     d, m, g0, h = _grid_arrays(grid)
     X = _coords(x, d)
     n = X.shape[1]
@@ -119,9 +126,14 @@ def precompute(grid, x, y, absolute=False):
     wty = np.zeros(M, np.float64)
     yty = ctypes.c_double(0.0)
     bad = ctypes.c_int64(-1)
-    fn = _lib().oracle_precompute_abs if absolute else _lib().oracle_precompute
-    rc = fn(d, _ptr(m), _ptr(g0), _ptr(h), _ptr(X), _ptr(Y), n,
-            _ptr(wtw), _ptr(wty), ctypes.byref(yty), ctypes.byref(bad))
+    if threads > 1 and not absolute:
+        rc = _lib().oracle_precompute_omp(d, _ptr(m), _ptr(g0), _ptr(h), _ptr(X), _ptr(Y), n,
+                                          _ptr(wtw), _ptr(wty), ctypes.byref(yty),
+                                          ctypes.byref(bad), int(threads))
+    else:
+        fn = _lib().oracle_precompute_abs if absolute else _lib().oracle_precompute
+        rc = fn(d, _ptr(m), _ptr(g0), _ptr(h), _ptr(X), _ptr(Y), n,
+                _ptr(wtw), _ptr(wty), ctypes.byref(yty), ctypes.byref(bad))
     _check(rc, bad)
     return wtw, wty, float(yty.value)
 
@@ -164,13 +176,18 @@ def interpolate(grid, mu_grid, xq):
     return out
 
 
-def wtw_matvec(grid, wtw, v):
-    """u = (W^T W) v; v is [M] or [k, M]."""
+def wtw_matvec(grid, wtw, v, threads=1):
+    """u = (W^T W) v; v is [M] or [k, M] (threads > 1: rows split between
+    OpenMP threads, same result)."""
     d, m, g0, h = _grid_arrays(grid)
     V = np.ascontiguousarray(np.asarray(v, np.float64))
     squeeze = V.ndim == 1
     V = V.reshape(-1, int(np.prod(m)))
     U = np.zeros_like(V)
     A = np.ascontiguousarray(wtw, np.float64)
-    _lib().oracle_wtw_matvec(d, _ptr(m), _ptr(A), _ptr(V), _ptr(U), V.shape[0])
+    if threads > 1:
+        _lib().oracle_wtw_matvec_omp(d, _ptr(m), _ptr(A), _ptr(V), _ptr(U), V.shape[0],
+                                     int(threads))
+    else:
+        _lib().oracle_wtw_matvec(d, _ptr(m), _ptr(A), _ptr(V), _ptr(U), V.shape[0])
     return U[0] if squeeze else U

@@ -32,6 +32,12 @@
  * whose partner node j+o lies outside the grid are zero (Claim 2: at most
  * (4r-1)^d = 7^d nonzeros per row for cubic interpolation, r = 2).
  *
+ * The *_omp variants (for timing the oracle on all host cores) split the
+ * points into one contiguous chunk per thread, accumulate each chunk
+ * serially into the thread's own arrays and add the threads' arrays in
+ * thread order, so their result is deterministic for a given thread count
+ * (the serial functions stay the reference).
+ *
  * Error behaviour: functions return 0 on success, -2 when a point lies outside
  * the interpolable region (index of the first such point in *bad), -1 on
  * invalid arguments.
@@ -40,6 +46,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* Keys cubic-convolution weights (a = -1/2) for the nodes i-1, i, i+1, i+2 of
  * a point at fractional offset t in [0,1] from node i. */
@@ -157,9 +166,9 @@ int oracle_stencils(int d, const int64_t *m, const double *g0, const double *h,
  * tests' error bounds.
  * wtw: [M][7^d] zero-initialised here; wty: [M]; yty: scalar. */
 static int precompute_impl(int d, const int64_t *m, const double *g0,
-                           const double *h, const double *x, const double *y,
-                           int64_t n, double *wtw, double *wty, double *yty,
-                           int64_t *bad, int absw) {
+                           const double *h, const double *x, int64_t ldx,
+                           const double *y, int64_t n, double *wtw, double *wty,
+                           double *yty, int64_t *bad, int absw) {
     if (d < 1 || d > 3 || n < 0) return -1;
     int64_t M = 1;
     for (int k = 0; k < d; ++k) {
@@ -175,7 +184,7 @@ static int precompute_impl(int d, const int64_t *m, const double *g0,
     double xs[3];
     for (int64_t i = 0; i < n; ++i) {
         int64_t cell;
-        for (int k = 0; k < d; ++k) xs[k] = x[(int64_t)k * n + i];
+        for (int k = 0; k < d; ++k) xs[k] = x[(int64_t)k * ldx + i];
         if (stencil(d, m, g0, h, xs, nodes, wts, &cell)) {
             if (bad) *bad = i;
             return -2;
@@ -200,14 +209,14 @@ int oracle_precompute(int d, const int64_t *m, const double *g0,
                       const double *h, const double *x /* [d][n] */,
                       const double *y, int64_t n, double *wtw, double *wty,
                       double *yty, int64_t *bad) {
-    return precompute_impl(d, m, g0, h, x, y, n, wtw, wty, yty, bad, 0);
+    return precompute_impl(d, m, g0, h, x, n, y, n, wtw, wty, yty, bad, 0);
 }
 
 int oracle_precompute_abs(int d, const int64_t *m, const double *g0,
                           const double *h, const double *x /* [d][n] */,
                           const double *y, int64_t n, double *wtw, double *wty,
                           double *yty, int64_t *bad) {
-    return precompute_impl(d, m, g0, h, x, y, n, wtw, wty, yty, bad, 1);
+    return precompute_impl(d, m, g0, h, x, n, y, n, wtw, wty, yty, bad, 1);
 }
 
 /* SplitMix64 finaliser (Vigna, public domain) applied to a counter. */
@@ -289,6 +298,121 @@ void oracle_wtw_matvec(int d, const int64_t *m, const double *wtw,
     for (int q = 0; q < d; ++q) M *= m[q];
     int nb = ipow(7, d);
     for (int r = 0; r < k; ++r) {
+        for (int64_t j = 0; j < M; ++j) {
+            int64_t c[3], rem = j;
+            for (int q = d - 1; q >= 0; --q) { c[q] = rem % m[q]; rem /= m[q]; }
+            double acc = 0.0;
+            for (int oi = 0; oi < nb; ++oi) {
+                int o[3], orem = oi;
+                for (int q = d - 1; q >= 0; --q) { o[q] = orem % 7 - 3; orem /= 7; }
+                int64_t jj = 0;
+                int inside = 1;
+                for (int q = 0; q < d; ++q) {
+                    int64_t cq = c[q] + o[q];
+                    if (cq < 0 || cq >= m[q]) { inside = 0; break; }
+                    jj = jj * m[q] + cq;
+                }
+                if (inside) acc += wtw[j * nb + oi] * v[(int64_t)r * M + jj];
+            }
+            u[(int64_t)r * M + j] = acc;
+        }
+    }
+}
+
+/* oracle_precompute on `nthreads` threads (<= 0: all available). */
+int oracle_precompute_omp(int d, const int64_t *m, const double *g0,
+                          const double *h, const double *x, const double *y,
+                          int64_t n, double *wtw, double *wty, double *yty,
+                          int64_t *bad, int nthreads) {
+    if (d < 1 || d > 3 || n < 0) return -1;
+    int64_t M = 1;
+    for (int k = 0; k < d; ++k) {
+        if (m[k] < 4) return -1;
+        M *= m[k];
+    }
+    int T = 1;
+#ifdef _OPENMP
+    T = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    const int nb = ipow(7, d);
+    double **tw = calloc((size_t)T, sizeof(double *));
+    double **ty = calloc((size_t)T, sizeof(double *));
+    double *tyy = calloc((size_t)T, sizeof(double));
+    int64_t *tbad = malloc(sizeof(int64_t) * (size_t)T);
+    int *trc = calloc((size_t)T, sizeof(int));
+    int rc = 0;
+    if (!tw || !ty || !tyy || !tbad || !trc) rc = -1;
+    for (int t = 0; t < T && rc == 0; ++t) {
+        tw[t] = malloc(sizeof(double) * (size_t)(M * nb));
+        ty[t] = malloc(sizeof(double) * (size_t)M);
+        if (!tw[t] || !ty[t]) rc = -1;
+    }
+    if (rc == 0) {
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(T) schedule(static, 1)
+#endif
+        for (int t = 0; t < T; ++t) {
+            const int64_t b0 = n * t / T, b1 = n * (t + 1) / T;
+            int64_t bi = -1;
+            trc[t] = precompute_impl(d, m, g0, h, x + b0, n, y + b0, b1 - b0, tw[t], ty[t],
+                                     &tyy[t], &bi, 0);
+            tbad[t] = bi >= 0 ? b0 + bi : -1;
+        }
+    }
+    if (rc == 0) {
+        for (int t = 0; t < T; ++t)
+            if (trc[t] != 0) {
+                rc = trc[t];
+                if (rc == -2 && bad) *bad = tbad[t];
+                break;
+            }
+    }
+    if (rc == 0) {
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(T) schedule(static)
+#endif
+        for (int64_t i = 0; i < M * nb; ++i) {
+            double acc = 0.0;
+            for (int t = 0; t < T; ++t) acc += tw[t][i];
+            wtw[i] = acc;
+        }
+        for (int64_t j = 0; j < M; ++j) {
+            double acc = 0.0;
+            for (int t = 0; t < T; ++t) acc += ty[t][j];
+            wty[j] = acc;
+        }
+        double acc = 0.0;
+        for (int t = 0; t < T; ++t) acc += tyy[t];
+        *yty = acc;
+    }
+    for (int t = 0; t < T; ++t) {
+        if (tw) free(tw[t]);
+        if (ty) free(ty[t]);
+    }
+    free(tw);
+    free(ty);
+    free(tyy);
+    free(tbad);
+    free(trc);
+    return rc;
+}
+
+/* oracle_wtw_matvec on `nthreads` threads (rows split between threads; each
+ * row's sum in the serial order, so the result equals the serial one). */
+void oracle_wtw_matvec_omp(int d, const int64_t *m, const double *wtw,
+                           const double *v, double *u, int k, int nthreads) {
+    int64_t M = 1;
+    for (int q = 0; q < d; ++q) M *= m[q];
+    int nb = ipow(7, d);
+    int T = 1;
+#ifdef _OPENMP
+    T = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    (void)T;
+    for (int r = 0; r < k; ++r) {
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(T) schedule(static)
+#endif
         for (int64_t j = 0; j < M; ++j) {
             int64_t c[3], rem = j;
             for (int q = d - 1; q >= 0; --q) { c[q] = rem % m[q]; rem /= m[q]; }

@@ -16,6 +16,7 @@ __all__ = [
     "logm_e1", "mll_and_grad", "ski_dense_mean", "exact_gp_mean",
     "ski_dense_mll", "ski_dense_grad", "gsgp_mll_fact2", "lanczos_dense",
     "se_kernel", "kernel_1d", "kernel_1d_dlog_ell", "ski_dense_cov", "efla", "love_cov",
+    "logm_e1_grad", "slq_logdet_grad_dense", "slq_logdet_grad",
 ]
 
 
@@ -122,7 +123,7 @@ def kg_dense(grid, hypers):
     return s * K
 
 
-def _toeplitz_apply_axis(V, col, axis):
+def _toeplitz_apply_axis(V, col, axis, workers=1):
     """Symmetric Toeplitz (first column col) applied along `axis` of V through a
     circulant embedding of length 2m (exact up to rounding)."""
     m = col.shape[0]
@@ -131,31 +132,32 @@ def _toeplitz_apply_axis(V, col, axis):
     emb[:m] = col
     emb[L - m + 1:] = col[1:][::-1]
     lam = sfft.rfft(emb)
-    F = sfft.rfft(V, n=L, axis=axis)
+    F = sfft.rfft(V, n=L, axis=axis, workers=workers)
     shape = [1] * V.ndim
     shape[axis] = lam.shape[0]
-    out = sfft.irfft(F * lam.reshape(shape), n=L, axis=axis)
+    out = sfft.irfft(F * lam.reshape(shape), n=L, axis=axis, workers=workers)
     return np.take(out, np.arange(m), axis=axis)
 
 
-def _kron_apply(grid, cols, v, scale):
+def _kron_apply(grid, cols, v, scale, workers=1):
     d = grid["d"]
     V = np.asarray(v, np.float64)
     lead = V.shape[:-1]
     V = V.reshape(lead + tuple(grid["m"]))
     base = len(lead)
     for k in range(d):
-        V = _toeplitz_apply_axis(V, cols[k], base + k)
+        V = _toeplitz_apply_axis(V, cols[k], base + k, workers)
     return scale * V.reshape(lead + (-1,))
 
 
-def kg_matvec(grid, hypers, v):
-    """K_G v (v: [..., M]) via per-dimension circulant embeddings."""
+def kg_matvec(grid, hypers, v, workers=1):
+    """K_G v (v: [..., M]) via per-dimension circulant embeddings (`workers`:
+    threads of the FFTs)."""
     d = grid["d"]
     ell, s, _ = _hyp(hypers, d)
     cols = [toeplitz_column(grid["m"][k], grid["spacing"][k], ell[k], _kind(hypers))
             for k in range(d)]
-    return _kron_apply(grid, cols, v, s)
+    return _kron_apply(grid, cols, v, s, workers)
 
 
 def dkg_matvec(grid, hypers, v, which):
@@ -208,10 +210,10 @@ def wtw_dense_from_dia(grid, wtw):
 # The GSGP operator B(x) = ((K_G W^T W + sigma^2 I) x, W^T W x)  (App. B,
 # efficient factorized CG), with W^T W in stencil-diagonal form.
 # ---------------------------------------------------------------------------
-def B_apply(grid, hypers, wtw, x):
+def B_apply(grid, hypers, wtw, x, threads=1):
     _, _, sig = _hyp(hypers, grid["d"])
-    u = native.wtw_matvec(grid, wtw, x)
-    v = kg_matvec(grid, hypers, u) + sig * sig * np.asarray(x, np.float64)
+    u = native.wtw_matvec(grid, wtw, x, threads)
+    v = kg_matvec(grid, hypers, u, threads) + sig * sig * np.asarray(x, np.float64)
     return v, u
 
 
@@ -276,14 +278,17 @@ def _efcg_core(grid, hypers, wtw, r, eps, maxiter, history):
     return xd, it, hist, rhos
 
 
-def fcg_probe(grid, hypers, wtw, bhat, bnorm2, tol=1e-8, maxiter=1000, history=False):
+def fcg_probe(grid, hypers, wtw, bhat, bnorm2, tol=1e-8, maxiter=1000, history=False,
+              residuals=0):
     """Factorized CG from x_0 = 0 for an n-space right-hand side b that is not
     in the span of W (Claims 3 and 4, efficient variant with one B per
     iteration).  Iterates: r = W r_hat + c_r b, p = W p_hat + c_p b,
     x = W x_hat + c_x b.  Needs only bhat = W^T b and ||b||^2.
 
     Returns (W^T x, info) with the CG coefficients alpha, beta (for the
-    Lanczos tridiagonal) and, on request, the W^T x_k history."""
+    Lanczos tridiagonal) and, on request, the W^T x_k history and the first
+    `residuals` residuals r_k = W r_hat_k + c_r,k b (k = 0, 1, ...) as
+    (r_hat_k, c_r,k, ||r_k||^2)."""
     _, _, sig = _hyp(hypers, grid["d"])
     s2 = sig * sig
     kb = kg_matvec(grid, hypers, bhat)
@@ -296,6 +301,7 @@ def fcg_probe(grid, hypers, wtw, bhat, bnorm2, tol=1e-8, maxiter=1000, history=F
     rho = float(rh @ ur) + 2 * cr * float(rh @ bhat) + cr * cr * bnorm2
     eps = tol * tol * bnorm2
     alphas, betas, hist = [], [], []
+    res = [(rh.copy(), cr, rho)] if residuals > 0 else []
     it = 0
     for k in range(maxiter):
         ap = zp + cp * kb               # compressed A p (Claim 3)
@@ -312,6 +318,8 @@ def fcg_probe(grid, hypers, wtw, bhat, bnorm2, tol=1e-8, maxiter=1000, history=F
         it = k + 1
         if history:
             hist.append(ux + cx * bhat)
+        if len(res) < residuals:
+            res.append((rh.copy(), cr, rho_new))
         if rho_new <= eps:
             break
         beta = rho_new / rho
@@ -324,6 +332,8 @@ def fcg_probe(grid, hypers, wtw, bhat, bnorm2, tol=1e-8, maxiter=1000, history=F
     info = {"iterations": it, "alpha": np.array(alphas), "beta": np.array(betas)}
     if history:
         info["wtx_history"] = hist
+    if residuals:
+        info["residuals"] = res
     return ux + cx * bhat, info
 
 
@@ -344,6 +354,144 @@ def logm_e1(T):
     (Gauss quadrature of log at the Ritz values)."""
     ev, V = np.linalg.eigh(T)
     return float(np.sum(V[0, :] ** 2 * np.log(ev)))
+
+
+def logm_e1_grad(T):
+    """Gradient of e_1^T log(T) e_1 with respect to the entries of the
+    symmetric T = V diag(lam) V^T (the derivative of a matrix function):
+    V (F o (v v^T)) V^T with v = V^T e_1, F_ll = 1/lam_l and
+    F_lm = (log lam_l - log lam_m)/(lam_l - lam_m) (l != m).  Returns
+    (d/d diag [k], d/d off-diagonal [k-1]): a change of an off-diagonal
+    entry moves both T_{i,i+1} and T_{i+1,i}."""
+    lam, V = np.linalg.eigh(T)
+    k = lam.shape[0]
+    L = np.log(lam)
+    F = np.empty((k, k))
+    for a in range(k):
+        for b in range(k):
+            gap = lam[a] - lam[b]
+            F[a, b] = (L[a] - L[b]) / gap if abs(gap) > 1e-13 * abs(lam[a]) else 1.0 / lam[a]
+    v = V[0, :]
+    G = V @ (F * np.outer(v, v)) @ V.T
+    return np.diag(G).copy(), 2.0 * np.diag(G, 1).copy()
+
+
+def slq_logdet_grad_dense(A, dA, z, k):
+    """Reverse-mode derivative of ||z||^2 e_1^T log(T_k) e_1, T_k the k-step
+    Lanczos tridiagonal of the dense symmetric A from z / ||z|| (plain
+    Lanczos, as the CG coefficients give it), with respect to the
+    parameters whose matrices dA[t] = dA/dtheta_t are given.  Forward:
+    u_i = A q_i, alpha_i = q_i^T u_i, r_i = u_i - alpha_i q_i - beta_{i-1}
+    q_{i-1}, beta_i = ||r_i||, q_{i+1} = r_i / beta_i; the reverse sweep runs
+    these statements backwards with adjoints (checkpointed q_i, u_i) and
+    collects d/dtheta_t = sum_i ubar_i^T dA[t] q_i.
+    Returns (value, gradient [len(dA)])."""
+    zz = float(z @ z)
+    Q = [z / np.sqrt(zz)]
+    U, al, be = [], [], []
+    for i in range(k):
+        u = A @ Q[i]
+        a = float(Q[i] @ u)
+        r = u - a * Q[i] - (be[i - 1] * Q[i - 1] if i > 0 else 0.0)
+        U.append(u)
+        al.append(a)
+        if i == k - 1:
+            break
+        b = float(np.linalg.norm(r))
+        be.append(b)
+        Q.append(r / b)
+    T = np.diag(al) + np.diag(be, 1) + np.diag(be, -1)
+    abar, bbar = logm_e1_grad(T)
+    qbar = [np.zeros_like(z) for _ in range(k)]
+    g = np.zeros(len(dA))
+    for i in range(k - 1, -1, -1):
+        rbar = np.zeros_like(z)
+        if i < k - 1:
+            rbar = qbar[i + 1] / be[i]
+            bbar[i] -= float(qbar[i + 1] @ Q[i + 1]) / be[i]
+            rbar = rbar + bbar[i] * Q[i + 1]
+        ubar = rbar.copy()
+        abar[i] -= float(rbar @ Q[i])
+        qbar[i] = qbar[i] - al[i] * rbar
+        if i > 0:
+            bbar[i - 1] -= float(rbar @ Q[i - 1])
+            qbar[i - 1] = qbar[i - 1] - be[i - 1] * rbar
+        qbar[i] = qbar[i] + abar[i] * U[i]
+        ubar = ubar + abar[i] * Q[i]
+        for t in range(len(dA)):
+            g[t] += float(ubar @ (dA[t] @ Q[i]))
+        qbar[i] = qbar[i] + A @ ubar
+    return zz * logm_e1(T), zz * g
+
+
+def slq_logdet_grad(grid, hypers, wtw, bhat, n, k, tol=1e-10, maxiter=2000):
+    """The same derivative for one probe z (||z||^2 = n, W^T z = bhat) in
+    m-space, as the factorized method forms it: T from the first k CG
+    coefficients of the factorized CG from x_0 = 0 (Claims 3 and 4), the
+    Lanczos vectors from its residuals, q_{i+1} = (-1)^i r_i / ||r_i||, all
+    n-vectors kept as pairs (a, c) for W a + c z.  Then
+        A (a, c) = (K_G (W^T W a + c bhat) + s2 a, s2 c),
+        <(a, c), (e, f)> = (W^T W a).e + c bhat.e + f bhat.a + c f n,
+    and for theta = log l_d, log s (dA = W dK_G W^T):
+        ubar^T dA q = (W^T ubar)^T dK_G (W^T q),  W^T (a, c) = W^T W a + c bhat,
+    for log sigma (dA = 2 s2 I): 2 s2 <ubar, q>.
+    Returns (value ||z||^2 e_1^T log T e_1, gradient [d + 2])."""
+    d = grid["d"]
+    _, _, sig = _hyp(hypers, d)
+    s2 = sig * sig
+    bhat = np.asarray(bhat, np.float64)
+    _, info = fcg_probe(grid, hypers, wtw, bhat, float(n), tol=tol, maxiter=maxiter,
+                        residuals=k)
+    kk = min(k, len(info["alpha"]))
+    T = lanczos_from_cg(info["alpha"], info["beta"], kk)
+    kb = kg_matvec(grid, hypers, bhat)
+
+    def wtw_of(a):
+        return native.wtw_matvec(grid, wtw, a)
+
+    def inner(a, ca, e, ce):
+        return float(wtw_of(a) @ e + ca * (bhat @ e) + ce * (bhat @ a) + ca * ce * n)
+
+    def apply_A(a, ca):
+        return kg_matvec(grid, hypers, wtw_of(a) + ca * bhat) + s2 * a, s2 * ca
+
+    def wt(a, ca):
+        return wtw_of(a) + ca * bhat
+
+    Qa, Qc = [], []
+    for i in range(kk):
+        rh, cr, rho = info["residuals"][i]
+        sgn = 1.0 if i % 2 == 0 else -1.0
+        Qa.append(sgn * rh / np.sqrt(rho))
+        Qc.append(sgn * cr / np.sqrt(rho))
+    Ua, Uc = zip(*[apply_A(Qa[i], Qc[i]) for i in range(kk)])
+    al = np.diag(T).copy()
+    be = np.diag(T, 1).copy()
+    abar, bbar = logm_e1_grad(T)
+    qa = [np.zeros_like(bhat) for _ in range(kk)]
+    qc = [0.0] * kk
+    g = np.zeros(d + 2)
+    for i in range(kk - 1, -1, -1):
+        ra, rc = np.zeros_like(bhat), 0.0
+        if i < kk - 1:
+            ra, rc = qa[i + 1] / be[i], qc[i + 1] / be[i]
+            bbar[i] -= inner(qa[i + 1], qc[i + 1], Qa[i + 1], Qc[i + 1]) / be[i]
+            ra, rc = ra + bbar[i] * Qa[i + 1], rc + bbar[i] * Qc[i + 1]
+        ua, uc = ra.copy(), rc
+        abar[i] -= inner(ra, rc, Qa[i], Qc[i])
+        qa[i], qc[i] = qa[i] - al[i] * ra, qc[i] - al[i] * rc
+        if i > 0:
+            bbar[i - 1] -= inner(ra, rc, Qa[i - 1], Qc[i - 1])
+            qa[i - 1], qc[i - 1] = qa[i - 1] - be[i - 1] * ra, qc[i - 1] - be[i - 1] * rc
+        qa[i], qc[i] = qa[i] + abar[i] * Ua[i], qc[i] + abar[i] * Uc[i]
+        ua, uc = ua + abar[i] * Qa[i], uc + abar[i] * Qc[i]
+        wu, wq = wt(ua, uc), wt(Qa[i], Qc[i])
+        for th in range(d + 1):
+            g[th] += float(wu @ dkg_matvec(grid, hypers, wq, th))
+        g[d + 1] += 2.0 * s2 * inner(ua, uc, Qa[i], Qc[i])
+        Aa, Ac = apply_A(ua, uc)
+        qa[i], qc[i] = qa[i] + Aa, qc[i] + Ac
+    return n * logm_e1(T), n * g
 
 
 def lanczos_dense(A, b, k):
@@ -382,7 +530,7 @@ def lanczos_dense(A, b, k):
 # Sec. 2.2; stochastic Lanczos quadrature as used in Sec. 5).
 # ---------------------------------------------------------------------------
 def mll_and_grad(grid, hypers, wtw, wty, yty, n, sketches, lanczos_steps=30,
-                 tol=1e-10, maxiter=2000, exact_trace=False, x=None):
+                 tol=1e-10, maxiter=2000, exact_trace=False, x=None, slq_grad=False):
     """MLL = -1/2 [ logdet(A) + y^T A^{-1} y + n log 2 pi ],
     A = W K_G W^T + sigma^2 I.
 
@@ -393,7 +541,10 @@ def mll_and_grad(grid, hypers, wtw, wty, yty, n, sketches, lanczos_steps=30,
     Gradient w.r.t. (log l_0..log l_{d-1}, log s, log sigma):
       g = 1/2 [ x_y^T dA x_y - tr(A^{-1} dA) ],
     with tr(A^{-1} dA) ~ (1/N) sum_j x_j^T dA z_j (x_j = A^{-1} z_j), or, with
-    exact_trace, the exact trace through S = W^T A^{-1} W (small M only).
+    exact_trace, the exact trace through S = W^T A^{-1} W (small M only), or,
+    with slq_grad, the exact derivative of the log-determinant estimate
+    itself (reverse mode through each probe's Lanczos steps,
+    slq_logdet_grad), so that the gradient is that of the returned MLL.
     Returns (mll, grad, info)."""
     d = grid["d"]
     ell, s, sig = _hyp(hypers, d)
@@ -417,9 +568,14 @@ def mll_and_grad(grid, hypers, wtw, wty, yty, n, sketches, lanczos_steps=30,
     grad = np.zeros(d + 2)
     # ||z~||^2 = (y^T y - 2 (W^T y)^T mu + mu^T W^T W mu) / sigma^4
     zz = (yty - 2 * float(wty @ mu) + float(mu @ native.wtw_matvec(grid, wtw, mu))) / (s2 * s2)
+    if slq_grad:
+        dld = np.mean([slq_logdet_grad(grid, hypers, wtw, sketches[j], n, lanczos_steps,
+                                       tol=tol, maxiter=maxiter)[1] for j in range(N)], axis=0)
     for th in range(d + 1):
         quad = float(wtz @ dkg_matvec(grid, hypers, wtz, th))
-        if exact_trace:
+        if slq_grad:
+            tr = dld[th]
+        elif exact_trace:
             tr = _exact_trace(grid, hypers, wtw, th, n)
         else:
             tr = float(np.mean([wtx[j] @ dkg_matvec(grid, hypers, sketches[j], th)
@@ -427,7 +583,9 @@ def mll_and_grad(grid, hypers, wtw, wty, yty, n, sketches, lanczos_steps=30,
         grad[th] = 0.5 * (quad - tr)
     # sigma: dA/dlog sigma = 2 sigma^2 I
     quad = 2 * s2 * zz
-    if exact_trace:
+    if slq_grad:
+        tr = dld[d + 1]
+    elif exact_trace:
         tr = 2 * s2 * _exact_trace(grid, hypers, wtw, "inv", n)
     else:
         # z^T A^{-1} z = (n - (W^T z)^T K_G (W^T A^{-1} z)) / sigma^2

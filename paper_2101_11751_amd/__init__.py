@@ -25,10 +25,10 @@ OK, ENOTCONV, EINVAL, EOUTOFGRID, ENOMEM, EDEVICE = 0, 1, -1, -2, -3, -4
 
 #: every symbol that include/fkgp.h declares
 EXPORTS = ("fkgp_precompute", "fkgp_describe", "fkgp_export_stats", "fkgp_export_sketches",
-           "fkgp_solve", "fkgp_solve_multi", "fkgp_mll_and_grad", "fkgp_batch_mll_and_grad", "fkgp_interpolate",
+           "fkgp_solve", "fkgp_solve_noalloc", "fkgp_solve_multi", "fkgp_mll_and_grad", "fkgp_batch_mll_and_grad", "fkgp_interpolate",
            "fkgp_posterior_cov", "fkgp_love_build", "fkgp_love_tridiag", "fkgp_love_cov",
            "fkgp_love_destroy", "fkgp_apply_B",
-           "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_ski_solve", "fkgp_save", "fkgp_load",
+           "fkgp_kg_matvec", "fkgp_wtw_matvec", "fkgp_wtw_matvec_dot", "fkgp_ski_solve", "fkgp_save", "fkgp_load",
            "fkgp_precompute_host", "fkgp_set_allocator", "fkgp_destroy", "fkgp_last_error")
 
 
@@ -135,6 +135,8 @@ def load_library():
     L.fkgp_export_sketches.argtypes = [p, p, p]
     L.fkgp_solve.argtypes = [p, ctypes.POINTER(_Hypers), p, p, ctypes.POINTER(_SolveOpts),
                              ctypes.POINTER(_SolveInfo), p]
+    L.fkgp_solve_noalloc.argtypes = [p, ctypes.POINTER(_Hypers), p, p,
+                                     ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo), p]
     L.fkgp_precompute_host.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(p), p,
                                        ctypes.c_int64, ctypes.c_int, ctypes.POINTER(_PreOpts),
                                        ctypes.c_int64, p, ctypes.POINTER(p)]
@@ -165,6 +167,7 @@ def load_library():
     L.fkgp_apply_B.argtypes = [p, ctypes.POINTER(_Hypers), p, p, p, ctypes.c_int, p]
     L.fkgp_kg_matvec.argtypes = [p, ctypes.POINTER(_Hypers), p, p, ctypes.c_int, p]
     L.fkgp_wtw_matvec.argtypes = [p, p, p, ctypes.c_int, ctypes.c_int, p]
+    L.fkgp_wtw_matvec_dot.argtypes = [p, p, p, ctypes.c_int, p, ctypes.c_int, p]
     L.fkgp_set_allocator.argtypes = [ctypes.POINTER(_Allocator)]
     L.fkgp_destroy.argtypes = [p]
     L.fkgp_destroy.restype = None
@@ -329,18 +332,24 @@ def export_sketches(h):
     return out
 
 
-def solve(h, hypers, rhs=None, tol=1e-6, maxiter=1000, op_precision="f64"):
+def solve(h, hypers, rhs=None, tol=1e-6, maxiter=1000, op_precision="f64", out=None,
+          noalloc=False):
     """Posterior-mean grid weights mu_G (rhs None), or W^T A^{-1} W rhs.
     op_precision "f64": operator arithmetic in FP64 on the stored W^T W;
     "stats": arithmetic in the stats dtype (FP32 handles: FP32 inner CG with
-    FP64 iterative refinement).  Returns (out [M] float64, info dict)."""
+    FP64 iterative refinement).  out: optional [M] float64 device tensor to
+    write.  noalloc: fkgp_solve_noalloc (the library's fixed workspace, no
+    allocation).  Returns (out [M] float64, info dict)."""
     L = load_library()
     dev = torch.device("cuda", torch.cuda.current_device())
-    out = torch.empty(h.m_total, dtype=torch.float64, device=dev)
+    if out is None:
+        out = torch.empty(h.m_total, dtype=torch.float64, device=dev)
+    assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == h.m_total
     if rhs is not None:
         rhs = rhs.to(torch.float64).contiguous()
     info = _SolveInfo()
-    st = _check(L.fkgp_solve(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)), _ptr(rhs), _ptr(out),
+    fn = L.fkgp_solve_noalloc if noalloc else L.fkgp_solve
+    st = _check(fn(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)), _ptr(rhs), _ptr(out),
                              ctypes.byref(_SolveOpts(float(tol), int(maxiter),
                                                      OP_STATS if op_precision == "stats"
                                                      else OP_F64)),
@@ -557,6 +566,19 @@ def wtw_matvec_padded(h, xpad, u):
     _check(load_library().fkgp_wtw_matvec(h.ptr, _ptr(xpad), _ptr(u), xpad.shape[0],
                                           _dtype_code(xpad.dtype), _stream()))
     return u
+
+
+def wtw_matvec_dot(h, xpad, u, reps=1):
+    """fkgp_wtw_matvec_dot: u = (W^T W) x with u^T x reduced in the same launch
+    (the product as the CG loop runs it), repeated `reps` times; xpad: one
+    padded FP64 vector [1, M + 2 halo]; u: [1, M] float64.  Returns u^T x
+    (a 1-element float64 device tensor)."""
+    L = load_library()
+    assert xpad.dtype == torch.float64 and u.dtype == torch.float64
+    dot = torch.empty(1, dtype=torch.float64, device=u.device)
+    _check(L.fkgp_wtw_matvec_dot(h.ptr, _ptr(xpad), _ptr(u), F64, _ptr(dot), int(reps),
+                                 _stream()))
+    return dot
 
 
 def wtw_matvec(h, x, dtype=None):

@@ -63,6 +63,12 @@ struct fkgp_love {
     std::vector<double> alpha, beta, d;
 };
 
+// Workspace of fkgp_solve_noalloc: one copy per GPU, held until the process
+// ends.  Host code must not use this name as a device address (it is a host
+// stand-in); the device address comes from hipGetSymbolAddress.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace fkgp {
 
 fkgp_status kg_apply_skip(const GridDev& g, const Spectra& sp, fkgp_dtype dt, const void* x,
@@ -138,21 +144,37 @@ void dev_free(const DevAlloc& a, void* p, hipStream_t s) {
 
 namespace {
 
+// Arena mode (base != nullptr): pieces are carved, 256-byte aligned, from a
+// caller-provided device buffer of `cap` bytes and nothing is allocated or
+// freed; a request past the end fails with hipErrorOutOfMemory.
 struct Scratch {
     hipStream_t s;
     DevAlloc a;
     std::vector<void*> ptrs;
+    unsigned char* arena = nullptr;
+    size_t cap = 0, off = 0;
     explicit Scratch(hipStream_t st) : s(st), a(current_alloc()) { ensure_pool(); }
+    Scratch(hipStream_t st, unsigned char* base, size_t capacity)
+        : s(st), arena(base), cap(capacity) {}
     ~Scratch() {
         for (void* p : ptrs) dev_free(a, p, s);
     }
     template <class T>
     hipError_t get(T** p, size_t count) {
+        if (arena) {
+            const size_t b = ((count ? count : 1) * sizeof(T) + 255) & ~size_t(255);
+            if (off + b > cap) return hipErrorOutOfMemory;
+            *p = reinterpret_cast<T*>(arena + off);
+            off += b;
+            return hipSuccess;
+        }
         hipError_t e = alloc_async(a, p, count, s);
         if (e == hipSuccess) ptrs.push_back(*p);
         return e;
     }
 };
+
+size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t dsize(fkgp_dtype dt) { return dt == FKGP_F32 ? 4 : 8; }
 
@@ -354,6 +376,26 @@ fkgp_status check_hypers(const fkgp_handle* h, const fkgp_hypers* hyp) {
     return FKGP_OK;
 }
 
+// Four-step lines: beyond the register FFT, and for dimensions with few lines
+// (e.g. 1-D), where one workgroup of many waves per line pair beats one or
+// two waves per pair.
+bool few_lines(const fkgp_handle* h, int k, int log2L) {
+    return log2L >= kFewLinesMinLog2 && h->M / h->g.m[k] <= kFewLines;
+}
+
+// Device bytes make_spectra takes from its Scratch (reg_max = kMaxRegLog2).
+size_t spectra_bytes(const fkgp_handle* h, fkgp_dtype dt) {
+    const size_t es = dsize(dt);
+    size_t t = 0;
+    for (int k = 0; k < h->g.d; ++k) {
+        const int lg = circulant_log2(h->g.m[k]);
+        const size_t L = size_t(1) << lg;
+        t += up256(es * L) + up256(2 * es * (L / 2));
+        if (lg > kMaxRegLog2 || few_lines(h, k, lg)) t += up256(2 * es * L * kLongWGs);
+    }
+    return t;
+}
+
 // Spectra in dtype `dt` (derivative column for dimension `dderiv`, or none).
 // Circulants longer than 2^reg_max take the four-step order; the standalone
 // passes (reg_max = kMaxRegLog2) also get their four-step scratch.
@@ -373,12 +415,7 @@ fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtyp
         unsigned char *lam = nullptr, *tw = nullptr;
         FKGP_HIP(sc.get(&lam, es * sp.L[k]));
         FKGP_HIP(sc.get(&tw, 2 * es * (sp.L[k] / 2)));
-        // four-step lines: beyond the register FFT, and for dimensions with
-        // few lines (e.g. 1-D), where one workgroup of many waves per line
-        // pair beats one or two waves per pair
-        const bool few_lines = reg_max == kMaxRegLog2 && sp.log2L[k] >= kFewLinesMinLog2 &&
-                               h->M / h->g.m[k] <= kFewLines;
-        if (sp.log2L[k] > reg_max || few_lines) {
+        if (sp.log2L[k] > reg_max || (reg_max == kMaxRegLog2 && few_lines(h, k, sp.log2L[k]))) {
             int lg2;
             long_split(sp.log2L[k], sp.lg1[k], lg2);
             if (reg_max == kMaxRegLog2) {
@@ -407,6 +444,9 @@ struct OpCtx {
     int64_t M, halo;
     Spectra sp;     // spectra in dtype `op`
     Spectra sp64;   // FP64 spectra (same as sp when op is FP64)
+    // convergence checks by a synchronous copy of the state after each batch
+    // (no pinned host slots, which are allocated on first use)
+    bool sync_checks = false;
 };
 
 fkgp_status make_ctx(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtype op, OpCtx& c,
@@ -549,6 +589,44 @@ hipError_t cg_snap_get(CgSnap& out) {
     return hipSuccess;
 }
 
+// One iteration of the loop below (5 launches when the tiled product and the
+// fused K_G passes run; every kernel returns at once when b.st->done is set).
+template <class DotUr, class Step2>
+fkgp_status cg_iteration(const OpCtx& c, CgBufs& b, double* px, double* pp, unsigned char* rin,
+                         const LastBlockRed& rho_lb, const CgStep2& step2f, DotUr& dot_ur,
+                         Step2& step2, int nb, unsigned ewg, hipStream_t st) {
+    const fkgp_handle* h = c.h;
+    const int64_t M = c.M;
+    if (c.op == FKGP_F32)
+        cg_step1x<float><<<ewg, 256, 0, st>>>(b.st, b.xd, px, b.r, b.s, b.z, pp,
+                                              reinterpret_cast<float*>(rin), M);
+    else
+        cg_step1x<double><<<ewg, 256, 0, st>>>(b.st, b.xd, px, b.r, b.s, b.z, pp,
+                                               reinterpret_cast<double*>(rin), M);
+    FKGP_HIP(hipGetLastError());
+    // u = W^T W r_hat; the product's last workgroup finishes u^T r_hat
+    // (rho, beta) when the tiled kernel runs
+    int np = 0;
+    fkgp_status rs = spmv_dia_any(h->g, h->dt, c.op, h->A, h->bmask, b.rpad, b.u, 1, c.halo,
+                                  &b.st->done, st, b.partials, &np, &rho_lb);
+    if (rs != FKGP_OK) return rs;
+    if (np == 0) {
+        FKGP_HIP(dot_ur(&b.st->done));
+        finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_RHO);
+    }
+    // v = s K_G u + s2 r_hat, consumed by the fused direction update
+    bool fused = false;
+    rs = kg_apply_fused(h->g, c.sp, c.op, b.u, b.v, c.so, rin, c.s2, &b.st->done, step2f, &fused,
+                        st);
+    if (rs != FKGP_OK) return rs;
+    if (!fused) {
+        FKGP_HIP(step2());
+        finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_SZ);
+    }
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
 // Simplified efficiently-factorized CG (appendix): the residual stays in the
 // span of W, r = W r_hat, and each iteration applies B once.  On entry b.r
 // holds r_hat_0; on exit b.xd += sum_k alpha_k s_k (= W^T W x_hat) and
@@ -610,6 +688,24 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
     // host reads it; once the state is converged the queued launches are
     // no-ops (every kernel of the loop tests b.st->done).
     constexpr int kBatch = 8;
+    if (c.sync_checks) {
+        for (int launched = 0;;) {
+            const int nit = std::min(kBatch, maxiter - launched);
+            for (int it = 0; it < nit; ++it) {
+                rs = cg_iteration(c, b, px, pp, rin, rho_lb, step2f, dot_ur, step2, nb, ewg, st);
+                if (rs != FKGP_OK) return rs;
+            }
+            launched += nit;
+            FKGP_HIP(hipMemcpyAsync(&out, b.st, sizeof(CgState), hipMemcpyDeviceToHost, st));
+            FKGP_HIP(hipStreamSynchronize(st));
+            if (out.done || launched >= maxiter) break;
+        }
+        if (out.done == 2) {
+            set_error("factorized CG broke down (non-finite step)");
+            return FKGP_EDEVICE;
+        }
+        return FKGP_OK;
+    }
     CgSnap snapbuf;
     FKGP_HIP(cg_snap_get(snapbuf));
     CgState* snap = snapbuf.host;
@@ -622,33 +718,8 @@ fkgp_status run_cg(const OpCtx& c, CgBufs& b, double eps_abs, double eps_rel, in
         if (queued) {
         const int nit = std::min(kBatch, maxiter - launched);
         for (int it = 0; it < nit; ++it) {
-            if (c.op == FKGP_F32)
-                cg_step1x<float><<<ewg, 256, 0, st>>>(b.st, b.xd, px, b.r, b.s, b.z, pp,
-                                                      reinterpret_cast<float*>(rin), M);
-            else
-                cg_step1x<double><<<ewg, 256, 0, st>>>(b.st, b.xd, px, b.r, b.s, b.z, pp,
-                                                       reinterpret_cast<double*>(rin), M);
-            FKGP_HIP(hipGetLastError());
-            // u = W^T W r_hat; the product's last workgroup finishes u^T r_hat
-            // (rho, beta) when the tiled kernel runs
-            int np = 0;
-            rs = spmv_dia_any(h->g, h->dt, c.op, h->A, h->bmask, b.rpad, b.u, 1, c.halo, &b.st->done, st,
-                              b.partials, &np, &rho_lb);
+            rs = cg_iteration(c, b, px, pp, rin, rho_lb, step2f, dot_ur, step2, nb, ewg, st);
             if (rs != FKGP_OK) return rs;
-            if (np == 0) {
-                FKGP_HIP(dot_ur(&b.st->done));
-                finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_RHO);
-            }
-            // v = s K_G u + s2 r_hat, consumed by the fused direction update
-            bool fused = false;
-            rs = kg_apply_fused(h->g, c.sp, c.op, b.u, b.v, c.so, rin, c.s2, &b.st->done, step2f,
-                                &fused, st);
-            if (rs != FKGP_OK) return rs;
-            if (!fused) {
-                FKGP_HIP(step2());
-                finalize<<<1, kRedBlock, 0, st>>>(b.partials, nb, b.st, FIN_SZ);
-            }
-            FKGP_HIP(hipGetLastError());
         }
         launched += nit;
         FKGP_HIP(hipMemcpyAsync(&snap[next], b.st, sizeof(CgState), hipMemcpyDeviceToHost, st));
@@ -813,13 +884,36 @@ fkgp_status solve_core(const OpCtx& c, const double* rhs, double tol, int maxite
     return converged ? FKGP_OK : FKGP_ENOTCONV;
 }
 
+// Device bytes solve_impl takes from its Scratch (mirrors make_ctx, the
+// output buffer, alloc_cg, r_hat_0 and solve_core's FP32 refinement buffers).
+size_t solve_scratch_bytes(const fkgp_handle* h, fkgp_dtype op) {
+    const size_t M = (size_t)h->M;
+    const size_t halo = (size_t)dia_halo(h->g);
+    const size_t es = dsize(op);
+    size_t t = spectra_bytes(h, op) + (op == FKGP_F64 ? 0 : spectra_bytes(h, FKGP_F64));
+    t += up256(8 * M);                                                   // wtz
+    t += 6 * up256(8 * M);                                               // r s z p x xd
+    t += up256(8 * (size_t)std::max<int64_t>(kRedMaxBlocks, spmv_dot_parts(h->g)));
+    t += up256(es * (M + 2 * halo)) + 2 * up256(es * M);                 // rpad, u, v
+    t += up256(sizeof(CgState));
+    t += up256(8 * (size_t)std::max<int64_t>(1, kg_last_pass_blocks(h->g)));
+    t += up256(2 * sizeof(unsigned));                                    // tickets
+    t += up256(8 * M);                                                   // r0
+    if (op == FKGP_F32) t += 3 * up256(8 * M) + up256(8 * (M + 2 * halo));
+    return t;
+}
+
+// arena != nullptr: every device buffer is carved from it (nothing is
+// allocated, no pinned host memory is used).
 fkgp_status solve_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const double* rhs,
                        double* out, double tol, int maxiter, fkgp_dtype op,
-                       fkgp_solve_info* info, hipStream_t st) {
-    Scratch sc(st);
+                       fkgp_solve_info* info, hipStream_t st, unsigned char* arena = nullptr,
+                       size_t arena_cap = 0) {
+    Scratch sc = arena ? Scratch(st, arena, arena_cap) : Scratch(st);
     OpCtx c;
     fkgp_status rs = make_ctx(h, hyp, op, c, sc);
     if (rs != FKGP_OK) return rs;
+    c.sync_checks = arena != nullptr;
     double* wtz = nullptr;
     FKGP_HIP(sc.get(&wtz, h->M));
     fkgp_status res = solve_core(c, rhs, tol, maxiter, wtz, info, sc, st);
@@ -1318,6 +1412,75 @@ fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers* hyp,
                               const fkgp_mll_opts* opts, double* mll, double* grad,
                               fkgp_mll_info* info, void* stream);
 
+}  // extern "C"
+
+namespace {
+
+// Device address of `scratch` on each device, looked up once per device
+// (with that device current) on the first fkgp_solve_noalloc call there.
+std::mutex g_noalloc_mu;
+unsigned char* g_noalloc_ptr[64] = {};
+
+fkgp_status noalloc_scratch(unsigned char** out) {
+    int dev = 0;
+    FKGP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) {
+        set_error("device index out of range for the no-allocation workspace");
+        return FKGP_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_noalloc_ptr[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_noalloc_ptr[dev];
+    return FKGP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fkgp_status fkgp_solve_noalloc(const fkgp_handle* h, const fkgp_hypers* hyp,
+                               const double* rhs_grid, double* out, const fkgp_solve_opts* opts,
+                               fkgp_solve_info* info, void* stream) {
+    return guarded([&]() -> fkgp_status {
+        set_error("");
+        if (!h || !out) {
+            set_error("handle and out must be non-NULL");
+            return FKGP_EINVAL;
+        }
+        fkgp_status st = check_hypers(h, hyp);
+        if (st != FKGP_OK) return st;
+        fkgp_solve_opts o{1e-6, 1000, FKGP_OP_F64};
+        if (opts) o = *opts;
+        if (!(o.tol >= 0.0) || o.maxiter < 0) {
+            set_error("tol must be >= 0 and maxiter >= 0");
+            return FKGP_EINVAL;
+        }
+        if (o.op_precision != FKGP_OP_F64 && o.op_precision != FKGP_OP_STATS) {
+            set_error("op_precision must be FKGP_OP_F64 or FKGP_OP_STATS");
+            return FKGP_EINVAL;
+        }
+        const fkgp_dtype op = o.op_precision == FKGP_OP_STATS ? h->dt : FKGP_F64;
+        const size_t need = solve_scratch_bytes(h, op);
+        if (need > kNoAllocScratchBytes) {
+            set_error("fkgp_solve_noalloc: this grid needs " + std::to_string(need) +
+                      " bytes of workspace, more than the " +
+                      std::to_string(kNoAllocScratchBytes) +
+                      " bytes of its fixed workspace (use fkgp_solve)");
+            return FKGP_EINVAL;
+        }
+        unsigned char* base = nullptr;
+        st = noalloc_scratch(&base);
+        if (st != FKGP_OK) return st;
+        return solve_impl(h, hyp, rhs_grid, out, o.tol, o.maxiter, op, info,
+                          static_cast<hipStream_t>(stream), base, kNoAllocScratchBytes);
+    });
+}
+
 fkgp_status fkgp_interpolate(const fkgp_handle* h, const double* mean_grid,
                              const void* const* xq, int64_t nq, fkgp_dtype in, double* out,
                              void* stream) {
@@ -1420,6 +1583,50 @@ fkgp_status fkgp_wtw_matvec(const fkgp_handle* h, const void* xpad, void* u, int
         }
         return spmv_dia_any(h->g, h->dt, xdt, h->A, h->bmask, xpad, u, k, dia_halo(h->g), nullptr,
                             static_cast<hipStream_t>(stream));
+    });
+}
+
+fkgp_status fkgp_wtw_matvec_dot(const fkgp_handle* h, const void* xpad, void* u,
+                                fkgp_dtype xdt, double* dot, int reps, void* stream) {
+    return guarded([&]() -> fkgp_status {
+        if (!h || !xpad || !u || !dot || reps < 1) {
+            set_error("invalid argument");
+            return FKGP_EINVAL;
+        }
+        if (xdt != FKGP_F64) {
+            set_error("fkgp_wtw_matvec_dot takes FP64 vectors (those of the FP64-arithmetic CG)");
+            return FKGP_EINVAL;
+        }
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        Scratch sc(st);
+        CgState* cs = nullptr;
+        double* partials = nullptr;
+        unsigned* tickets = nullptr;
+        const int nb = red_blocks(h->M);
+        FKGP_HIP(sc.get(&cs, 1));
+        FKGP_HIP(sc.get(&partials, std::max<int64_t>(kRedMaxBlocks, spmv_dot_parts(h->g))));
+        FKGP_HIP(sc.get(&tickets, 1));
+        CgState init{};
+        init.eps = -1.0;   // never "converged": every launch runs
+        FKGP_HIP(hipMemcpyAsync(cs, &init, sizeof(CgState), hipMemcpyHostToDevice, st));
+        FKGP_HIP(hipMemsetAsync(tickets, 0, sizeof(unsigned), st));
+        const LastBlockRed lb{partials, tickets, cs, FIN_RHO};
+        const int64_t halo = dia_halo(h->g);
+        for (int r = 0; r < reps; ++r) {
+            int np = 0;
+            fkgp_status rs = spmv_dia_any(h->g, h->dt, xdt, h->A, h->bmask, xpad, u, 1, halo,
+                                          &cs->done, st, partials, &np, &lb);
+            if (rs != FKGP_OK) return rs;
+            if (np == 0) {   // untiled product: separate dot and finalisation
+                const double* x = static_cast<const double*>(xpad) + halo;
+                dot_partial<double><<<nb, kRedBlock, 0, st>>>(static_cast<const double*>(u), x,
+                                                              h->M, partials, nullptr);
+                finalize<<<1, kRedBlock, 0, st>>>(partials, nb, cs, FIN_RHO);
+                FKGP_HIP(hipGetLastError());
+            }
+        }
+        FKGP_HIP(hipMemcpyAsync(dot, &cs->rho, sizeof(double), hipMemcpyDeviceToDevice, st));
+        return FKGP_OK;
     });
 }
 

@@ -291,7 +291,23 @@ fkgp_status exclusive_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t
 // 2. Stable scatter of one radix pass.  Wave w of a tile owns the contiguous
 // chunk [w*64*IT, (w+1)*64*IT) and walks it in steps of 64; lanes with equal
 // digits in a step are matched by ballots, so ranks follow input order.
+// From the per-wave digit counts the tile's items get their positions in the
+// tile sorted by digit (stable); the tile then writes that sequence out in
+// kStageChunks chunks of consecutive positions staged through LDS, so each
+// digit's run of the tile leaves as one contiguous, coalesced range of the
+// output (items stay in registers; a chunk holds a quarter of the tile).
 // ---------------------------------------------------------------------------
+constexpr int kStageChunks = 4;
+
+template <class Tin>
+constexpr size_t scatter_lds_bytes(int bits) {
+    // whist [4][nd] (then the per-wave offsets), local start [nd], global
+    // base [nd], scan scratch [kBlock], staged keys and payloads of a chunk
+    return sizeof(uint32_t) * ((size_t)4 * (1u << bits) + 2 * (1u << bits) + kBlock) +
+           (sizeof(uint32_t) + sizeof(typename PayloadOf<Tin>::type)) *
+               (tile_size<Tin>() / kStageChunks);
+}
+
 template <class Tin, bool kRaw>
 __global__ __launch_bounds__(kBlock) void radix_scatter(
     const uint32_t* __restrict__ keys_in,
@@ -301,14 +317,23 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(
     uint32_t* __restrict__ keys_out, typename PayloadOf<Tin>::type* __restrict__ pay_out) {
     using P = typename PayloadOf<Tin>::type;
     constexpr int IT = items_per_thread<Tin>();
-    extern __shared__ uint32_t whist[];   // [4 waves][1 << bits]
+    constexpr int CH = tile_size<Tin>() / kStageChunks;
+    extern __shared__ __align__(16) unsigned char lds_scatter[];
     const int nd = 1 << bits;
+    // the payload stage first (16-byte aligned), then the 32-bit arrays
+    P* stage_pay = reinterpret_cast<P*>(lds_scatter);
+    uint32_t* stage_key = reinterpret_cast<uint32_t*>(stage_pay + CH);
+    uint32_t* whist = stage_key + CH;          // [4][nd]
+    uint32_t* lstart = whist + 4 * nd;         // [nd]
+    uint32_t* gbase = lstart + nd;             // [nd]
+    uint32_t* scan_sh = gbase + nd;            // [kBlock]
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < 4 * nd; i += kBlock) whist[i] = 0;
     __syncthreads();
 
-    const int64_t wbase = (int64_t)blockIdx.x * tile_size<Tin>() + (int64_t)wave * 64 * IT;
+    const int64_t tbase = (int64_t)blockIdx.x * tile_size<Tin>();
+    const int64_t wbase = tbase + (int64_t)wave * 64 * IT;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t key[IT];
     uint32_t rank[IT];
@@ -356,23 +381,61 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(
         pay[s] = p;
     }
     __syncthreads();
-    // exclusive prefix over waves, plus the tile's global offset per digit
-    for (int dg = threadIdx.x; dg < nd; dg += kBlock) {
-        uint32_t run = offsets[(size_t)dg * ntiles + blockIdx.x];
-        for (int w = 0; w < 4; ++w) {
-            uint32_t c = whist[w * nd + dg];
-            whist[w * nd + dg] = run;
-            run += c;
+    // tile-local digit starts: exclusive scan of the tile's digit counts
+    // (each thread owns nd / kBlock consecutive digits, or one)
+    const int per = (nd + kBlock - 1) / kBlock;
+    uint32_t tsum = 0;
+    for (int q = 0; q < per; ++q) {
+        const int dg = threadIdx.x * per + q;
+        if (dg < nd) tsum += whist[dg] + whist[nd + dg] + whist[2 * nd + dg] + whist[3 * nd + dg];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(tsum, scan_sh, total);
+    for (int q = 0; q < per; ++q) {
+        const int dg = threadIdx.x * per + q;
+        if (dg < nd) {
+            lstart[dg] = run;
+            gbase[dg] = offsets[(size_t)dg * ntiles + blockIdx.x];
+            uint32_t w_run = run;
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t c = whist[w * nd + dg];
+                whist[w * nd + dg] = w_run;   // the wave's first tile position
+                w_run += c;
+            }
+            run = w_run;
         }
     }
     __syncthreads();
+    // position of each item in the digit-sorted tile
 #pragma unroll
     for (int s = 0; s < IT; ++s) {
         if (key[s] == 0xffffffffu) continue;
         const uint32_t dg = (key[s] >> shift) & (nd - 1);
-        const uint32_t pos = whist[wave * nd + dg] + rank[s];
-        keys_out[pos] = key[s];
-        pay_out[pos] = pay[s];
+        rank[s] += whist[wave * nd + dg];
+    }
+    // write the sorted tile out, one chunk of CH consecutive positions at a time
+    for (int c = 0; c < kStageChunks; ++c) {
+        const uint32_t lo = (uint32_t)(c * CH);
+        if ((int)lo >= (int)total) break;   // uniform: total is the tile's item count
+#pragma unroll
+        for (int s = 0; s < IT; ++s) {
+            if (key[s] == 0xffffffffu) continue;
+            const uint32_t q = rank[s] - lo;
+            if (q < (uint32_t)CH) {
+                stage_key[q] = key[s];
+                stage_pay[q] = pay[s];
+            }
+        }
+        __syncthreads();
+        const int cnt = min(CH, (int)total - (int)lo);
+        for (int q = threadIdx.x; q < cnt; q += kBlock) {
+            const uint32_t k = stage_key[q];
+            const uint32_t dg = (k >> shift) & (nd - 1);
+            const uint32_t pos = gbase[dg] + (lo + (uint32_t)q - lstart[dg]);
+            keys_out[pos] = k;
+            pay_out[pos] = stage_pay[q];
+        }
+        __syncthreads();
     }
 }
 
@@ -1047,7 +1110,7 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
             }
             fkgp_status st = exclusive_scan(counts, offs, nc, sums, s);
             if (st != FKGP_OK) return st;
-            const size_t lds = 4 * sizeof(uint32_t) << dbits[p];
+            const size_t lds = scatter_lds_bytes<Tin>(dbits[p]);
             // the index rides along for the probes (and, for d <= 2, in the
             // kept payload); 3-D kept points keep y in its slot instead
             const bool with_idx = nprobe > 0 || (out.keep_pay != nullptr && d <= 2);

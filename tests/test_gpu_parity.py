@@ -284,6 +284,30 @@ def test_wtw_matvec_tiled_parity(d, m, xdt):
         check(U[r], V[r])
 
 
+@pytest.mark.parametrize("d,m", [(1, [1000]), (2, [37, 29]), (3, [14, 11, 9]),
+                                 (3, [60, 61, 40])])
+@pytest.mark.parametrize("stats", [torch.float32, torch.float64])
+def test_wtw_matvec_dot_in_loop_form(d, m, stats):
+    """The product as the CG loop launches it (u^T x reduced in the same
+    launch): u equals the plain product bit for bit, u^T x its FP64 dot to
+    rounding, also after repeated launches."""
+    _need_gpu()
+    grid, X, y = make_case(d, 20000, 23, m=m)
+    xs, yt = to_dev(X, y)
+    h = P.precompute(grid, xs, yt, stats_dtype=stats)
+    x = torch.from_numpy(np.random.default_rng(6).standard_normal(h.m_total)).cuda()
+    xp = P.padded(h, x, torch.float64)
+    u_ref = torch.empty(1, h.m_total, dtype=torch.float64, device="cuda")
+    P.wtw_matvec_padded(h, xp, u_ref)
+    u = torch.empty_like(u_ref)
+    for reps in (1, 5):
+        dot = P.wtw_matvec_dot(h, xp, u, reps=reps)
+        assert torch.equal(u, u_ref)
+        ref = float(torch.dot(u_ref[0], x))
+        absref = float(torch.dot(u_ref[0].abs(), x.abs()))
+        assert abs(float(dot) - ref) <= 1e-13 * absref
+
+
 def sparse_case(d, n, seed):
     """Points filling only part of the grid's box (an interval, a disk, a
     cylinder), so that whole 64-row blocks of W^T W are zero.  The region is

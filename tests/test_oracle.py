@@ -641,3 +641,153 @@ def test_love_variance_decreases_with_rank():
         if prev is not None:
             assert np.all(v <= prev + 1e-10)
         prev = v
+
+
+# --------------------------------------------------------------------------
+# The OpenMP timing variants of the oracle (all-cores CPU baseline).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [(50,), (20, 17), (9, 8, 7)])
+def test_openmp_oracle_equals_serial(m):
+    """Per-thread chunks combined in thread order: the statistics equal the
+    serial ones to rounding and repeat bit for bit; the banded product splits
+    rows only, so it equals the serial product exactly; an out-of-grid point
+    is reported with its global index."""
+    d = len(m)
+    grid = oracle.make_grid(list(m), lo=0.0, hi=1.0)
+    rng = np.random.default_rng(17)
+    X = rng.uniform(0, 1, (d, 20011))
+    y = rng.standard_normal(20011)
+    a = oracle.precompute(grid, X, y)
+    b = oracle.precompute(grid, X, y, threads=5)
+    c = oracle.precompute(grid, X, y, threads=5)
+    assert np.abs(a[0] - b[0]).max() <= 1e-13 * np.abs(a[0]).max()
+    assert np.abs(a[1] - b[1]).max() <= 1e-13 * np.abs(a[1]).max()
+    assert abs(a[2] - b[2]) <= 1e-13 * a[2]
+    assert np.array_equal(b[0], c[0]) and np.array_equal(b[1], c[1]) and b[2] == c[2]
+    v = rng.standard_normal(a[1].shape[0])
+    assert np.array_equal(oracle.wtw_matvec(grid, a[0], v), oracle.wtw_matvec(grid, a[0], v, threads=4))
+    X[d - 1, 15000] = 5.0
+    with pytest.raises(oracle.native.OutOfGrid, match="15000"):
+        oracle.precompute(grid, X, y, threads=3)
+
+
+def test_oracle_c_under_address_and_ub_sanitizers(tmp_path):
+    """The oracle's C code built with -fsanitize=address,undefined and run
+    through every entry point (serial and threaded, both interpolation
+    schemes, 1-3 dimensions, error paths): no invalid access, leak or
+    undefined behaviour, and the invariants hold."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    here = os.path.join(os.path.dirname(os.path.dirname(__file__)), "oracle")
+    exe = str(tmp_path / "oracle_sanitize_check")
+    cmd = ["gcc", "-O1", "-g", "-std=c99", "-fopenmp", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-ffp-contract=off",
+           os.path.join(here, "precompute.c"), os.path.join(here, "sanitize_check.c"),
+           "-lm", "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="print_stacktrace=1")
+    env.pop("LD_PRELOAD", None)
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "all checks passed" in r.stdout
+
+
+# --------------------------------------------------------------------------
+# Reverse-mode derivative of the stochastic Lanczos log-determinant (the
+# gradient of the estimate itself, through each probe's Lanczos steps).
+# --------------------------------------------------------------------------
+def _hyp_shift(hyp, i, d, e):
+    hp = {"lengthscale": list(hyp["lengthscale"]), "outputscale": hyp["outputscale"],
+          "noise": hyp["noise"]}
+    f = np.exp(e)
+    if i < d:
+        hp["lengthscale"][i] *= f
+    elif i == d:
+        hp["outputscale"] *= f
+    else:
+        hp["noise"] *= f
+    return hp
+
+
+def test_logm_e1_gradient_vs_finite_differences():
+    rng = np.random.default_rng(3)
+    k = 9
+    al = 2.0 + rng.uniform(0, 1, k)
+    be = 0.5 * rng.uniform(0.1, 1, k - 1)
+    T = np.diag(al) + np.diag(be, 1) + np.diag(be, -1)
+    ga, gb = oracle.logm_e1_grad(T)
+    h = 1e-6
+    for i in range(k):
+        E = np.zeros((k, k)); E[i, i] = h
+        fd = (oracle.logm_e1(T + E) - oracle.logm_e1(T - E)) / (2 * h)
+        assert abs(ga[i] - fd) <= 1e-8
+    for i in range(k - 1):
+        E = np.zeros((k, k)); E[i, i + 1] = E[i + 1, i] = h
+        fd = (oracle.logm_e1(T + E) - oracle.logm_e1(T - E)) / (2 * h)
+        assert abs(gb[i] - fd) <= 1e-8
+
+
+def _dense_A(grid, X, hp):
+    W = oracle.dense_w(grid, X)
+    return W @ oracle.kg_dense(grid, hp) @ W.T + hp["noise"] ** 2 * np.eye(X.shape[1])
+
+
+@pytest.mark.parametrize("k", [10, 30])
+def test_slq_gradient_dense_vs_finite_differences(k):
+    """The reverse sweep through k plain Lanczos steps equals central
+    differences (h = 1e-4) of the same deterministic k-step value."""
+    grid, X, y, hyp = small_problem(21, (7, 6), 150)
+    n = X.shape[1]
+    z = oracle.probe_values(3, 0, n)
+    A = _dense_A(grid, X, hyp)
+    eps = 1e-6
+    dA = [(_dense_A(grid, X, _hyp_shift(hyp, i, 2, eps)) - _dense_A(grid, X, _hyp_shift(hyp, i, 2, -eps)))
+          / (2 * eps) for i in range(4)]
+    val, g = oracle.slq_logdet_grad_dense(A, dA, z, k)
+    h = 1e-4
+    for i in range(4):
+        fp, _ = oracle.slq_logdet_grad_dense(_dense_A(grid, X, _hyp_shift(hyp, i, 2, h)), [], z, k)
+        fm, _ = oracle.slq_logdet_grad_dense(_dense_A(grid, X, _hyp_shift(hyp, i, 2, -h)), [], z, k)
+        fd = (fp - fm) / (2 * h)
+        assert abs(g[i] - fd) <= 1e-6 * np.abs(g).max(), (i, g[i], fd)
+
+
+def test_slq_gradient_factorized_equals_dense():
+    """The m-space form (CG coefficients, Lanczos vectors from the factorized
+    CG residuals, compressed inner products) equals the dense n-space sweep:
+    value and gradient."""
+    for seed, m, n, k in ((22, (7, 6), 160, 10), (23, (25,), 120, 12)):
+        grid, X, y, hyp = small_problem(seed, m, n)
+        d = grid["d"]
+        wtw, _, _ = oracle.precompute(grid, X, y)
+        z = oracle.probe_values(5, 1, n)
+        bhat = oracle.probe_sketches(grid, X, 5, 2)[1]
+        A = _dense_A(grid, X, hyp)
+        eps = 1e-6
+        dA = [(_dense_A(grid, X, _hyp_shift(hyp, i, d, eps))
+               - _dense_A(grid, X, _hyp_shift(hyp, i, d, -eps))) / (2 * eps) for i in range(d + 2)]
+        v_d, g_d = oracle.slq_logdet_grad_dense(A, dA, z, k)
+        v_f, g_f = oracle.slq_logdet_grad(grid, hyp, wtw, bhat, n, k)
+        assert abs(v_f - v_d) <= 1e-10 * abs(v_d)
+        np.testing.assert_allclose(g_f, g_d, rtol=0, atol=1e-7 * np.abs(g_d).max())
+
+
+def test_mll_slq_gradient_matches_finite_differences_of_its_value():
+    """With slq_grad the oracle's gradient is that of its own (stochastic)
+    MLL value: central differences of mll_and_grad's MLL with the same
+    probes agree tightly, where the Hutchinson gradient differs by the
+    estimator's noise."""
+    grid, X, y, hyp = small_problem(24, (8, 7), 300)
+    n = X.shape[1]
+    wtw, wty, yty = oracle.precompute(grid, X, y)
+    sk = oracle.probe_sketches(grid, X, 9, 4)
+    kw = dict(lanczos_steps=15, tol=1e-12, maxiter=2000)
+    _, g, _ = oracle.mll_and_grad(grid, hyp, wtw, wty, yty, n, sk, slq_grad=True, **kw)
+    h = 1e-4
+    for i in range(4):
+        fp, _, _ = oracle.mll_and_grad(grid, _hyp_shift(hyp, i, 2, h), wtw, wty, yty, n, sk, **kw)
+        fm, _, _ = oracle.mll_and_grad(grid, _hyp_shift(hyp, i, 2, -h), wtw, wty, yty, n, sk, **kw)
+        fd = (fp - fm) / (2 * h)
+        assert abs(g[i] - fd) <= 1e-6 * np.abs(g).max() + 1e-6, (i, g[i], fd)
