@@ -292,10 +292,11 @@ fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers* hyp,
 /* The same quantities for nprob independent problems (handles with probe
  * sketches, d <= 2, any mix of sizes) in one persistent launch: every
  * right-hand side [y, z_0 .. z_{N-1}] of every problem is solved with the
- * factorized CG from x_0 = 0 (Claims 3 and 4); a workgroup owns one problem
- * and up to opts->batch_rhs of its right-hand sides (autotuned when 0) and
- * runs their CG to the end, so the stored W^T W is read once per iteration
- * for all of them.
+ * factorized CG (Claims 3 and 4), the probes from x_0 = 0 and y from
+ * x_0 = y / sigma^2 (residual in the span of W, as fkgp_solve); a workgroup
+ * owns one problem and up to opts->batch_rhs of its right-hand sides
+ * (autotuned when 0) and runs their CG to the end, so the stored W^T W is
+ * read once per iteration for all of them.
  *   hyps: nprob hyperparameter sets; mll: nprob host doubles; grad: nprob x 5
  *   host doubles (entries d+2 .. 4 of each row are 0); infos: nprob (or
  *   NULL).  opts->batched is ignored.  Synchronises `stream`. */

@@ -51,13 +51,22 @@
 #endif
 
 /* Keys cubic-convolution weights (a = -1/2) for the nodes i-1, i, i+1, i+2 of
- * a point at fractional offset t in [0,1] from node i. */
+ * a point at fractional offset t in [0,1] from node i.  With s = 1 - t the
+ * four Keys polynomials factor as
+ *   w0 = -t s^2 / 2,  w1 = s (1 + 4s - 3s^2) / 2,
+ *   w2 = t (1 + 4t - 3t^2) / 2,  w3 = -t^2 s / 2
+ * (expanding gives (-t^3 + 2t^2 - t)/2, (3t^3 - 5t^2 + 2)/2,
+ * (-3t^3 + 4t^2 + t)/2, (t^3 - t^2)/2).  Evaluated this way every weight is
+ * accurate to a few units in its own last place, also where it is tiny
+ * (t or s near 0): the expanded form cancels there and leaves an absolute
+ * error of order 2^-52, which would swamp entries of W^T W built from
+ * products of such weights.  The quadratic factors lie in [1, 2] on [0, 1]. */
 static void keys_weights(double t, double w[4]) {
-    double t2 = t * t, t3 = t2 * t;
-    w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
-    w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
-    w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
-    w[3] = 0.5 * (t3 - t2);
+    double s = 1.0 - t;
+    w[0] = -0.5 * t * (s * s);
+    w[1] = 0.5 * s * (1.0 + 4.0 * s - 3.0 * (s * s));
+    w[2] = 0.5 * t * (1.0 + 4.0 * t - 3.0 * (t * t));
+    w[3] = -0.5 * (t * t) * s;
 }
 
 /* Linear interpolation between nodes i and i+1, in the same frame. */

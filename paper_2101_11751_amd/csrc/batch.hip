@@ -2,9 +2,16 @@
 // problems of uneven size.
 //
 // Every right-hand side b of every problem is solved with the factorized CG
-// from x_0 = 0 (Claims 3 and 4): r = W r_hat + c_r b, p = W p_hat + c_p b,
+// in the form of Claims 3 and 4: r = W r_hat + c_r b, p = W p_hat + c_p b,
 // x = W x_hat + c_x b, which needs only b_hat = W^T b and ||b||^2 (the data
-// vector y: W^T y, y^T y; a Rademacher probe z_j: its sketch and n).  One
+// vector y: W^T y, y^T y; a Rademacher probe z_j: its sketch and n).  A
+// probe starts from x_0 = 0 (c_r = c_p = 1, r_hat = 0).  The data vector
+// starts from x_0 = y / s2 (c_x = 1 / s2, c_r = c_p = 0, r_hat_0 =
+// -K_G W^T y / s2): its residual then stays in the span of W and every c_r b
+// term vanishes, which is the simplified factorized CG of the appendix.  The
+// x_0 = 0 form carries W^T W x_hat by recurrence and its reconstruction
+// u_x + c_x b_hat drifts from the true solution once ||r|| falls below about
+// 1e-9 ||y||; in the simplified form the drift stays at rounding level.  One
 // launch covers the whole batch: workgroup g owns one work item (a problem
 // and a group of at most NR right-hand sides) and runs its CG to the end
 // with workgroup barriers only, so workgroups never wait on each other and
@@ -399,14 +406,22 @@ __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __rest
     for (int64_t i = tid; i < (int64_t)NR * ldr; i += kBB) rp[i] = 0.0;
 #pragma unroll 1
     for (int64_t i = tid; i < (int64_t)5 * NR * M; i += kBB) sp[i] = 0.0;
+    // the data right-hand side in the simplified form: r_hat_0 into its slot
+    const bool pre = P.r0y != nullptr && it.r0 == 0 && nr > 0;
+    __syncthreads();
+    if (pre) {
+#pragma unroll 1
+        for (int64_t i = tid; i < M; i += kBB) rp[halo + i] = P.r0y[i];
+    }
     if (tid < NR) {
         const bool act = tid < nr;
+        const bool simple = pre && tid == 0;
         const double bn = act ? P.bnorm2[it.r0 + tid] : 0.0;
         rho[tid] = bn;
         bb[tid] = bn;
-        cr[tid] = 1.0;
-        cp[tid] = 1.0;
-        cx[tid] = 0.0;
+        cr[tid] = simple ? 0.0 : 1.0;
+        cp[tid] = simple ? 0.0 : 1.0;
+        cx[tid] = simple ? 1.0 / P.s2 : 0.0;
         pb[tid] = 0.0;
         alpha[tid] = 0.0;
         beta[tid] = 0.0;
@@ -424,14 +439,19 @@ __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __rest
         pg0 = PassGeom{P.m[0], P.m[1], P.m[1], M, ldr, halo};
     }
 
-    for (int iter = 0; iter < maxiter; ++iter) {
+    // iteration -1 (items holding a simplified data right-hand side): only
+    // (C) and (D), giving u_r = W^T W r_hat_0, v_r = B(r_hat_0).v and rho_0 =
+    // r_hat_0 . u_r; the probes of the item have r_hat = 0 and keep
+    // rho = ||b||^2
+    for (int iter = pre ? -1 : 0; iter < maxiter; ++iter) {
         int act[NR];
         int na = 0;
 #pragma unroll
         for (int r = 0; r < NR; ++r)
             if (r < nr && !done[r]) act[na++] = r;
         if (na == 0) break;
-        // (A) direction update (beta = 0, u_r = v_r = 0 on the first pass)
+        if (iter >= 0) {
+        // (A) direction update (beta = 0 on the first pass: p_hat = r_hat)
         {
             double v[2 * NR];
 #pragma unroll
@@ -520,6 +540,7 @@ __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __rest
             }
         }
         __syncthreads();
+        }   // iter >= 0
         // (C) u_r = W^T W r_hat with the dots r_hat.u_r and r_hat.b_hat
         {
             double v[2 * NR];
@@ -546,6 +567,11 @@ __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __rest
         if (tid < nr && !done[tid]) {
             const int r = tid;
             const double rn = sums[2 * r] + 2.0 * cr[r] * sums[2 * r + 1] + cr[r] * cr[r] * bb[r];
+            if (iter < 0) {   // initial residual norm; no step taken yet
+                rho[r] = rn;
+                pb[r] = sums[2 * r + 1];
+                if (!(rn > eps[r])) done[r] = 1;
+            } else {
             iters[r] += 1;
             if (!(rn > eps[r])) {
                 done[r] = 1;
@@ -559,6 +585,7 @@ __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __rest
                 pb[r] = sums[2 * r + 1] + b * pb[r];
                 cp[r] = cr[r] + b * cp[r];
             }
+            }
         }
         __syncthreads();
         // (D) v_r = s K_G u_r + s2 r_hat for the right-hand sides still active
@@ -566,13 +593,29 @@ __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __rest
 #pragma unroll
         for (int r = 0; r < NR; ++r)
             if (r < nr && !done[r]) act[na++] = r;
+        // The line FFTs carry two lines as one complex line, and rounding
+        // mixes the two at the level of u times the larger one.  The data
+        // right-hand side in its simplified form has vectors orders of
+        // magnitude larger than a probe's, and the loss of orthogonality of
+        // CG amplifies such a perturbation of a probe step by step (the
+        // Lanczos log-determinant drifts after ~25 steps), so its lines are
+        // never paired with a probe's: the passes run over [y] and the
+        // probes separately.
         if (na > 0) {
-            if (P.d == 1) {
-                line_pass(dsp[0], false, ur, vr, act, na, pg0, P.so, rp, P.s2, T, it.yscr);
-            } else {
-                line_pass(dsp[1], false, ur, vr, act, na, pg1, 1.0, nullptr, 0.0, T, it.yscr);
+            const bool split = pre && act[0] == 0 && na > 1;
+            const int ng = split ? 2 : 1;
+            for (int gi = 0; gi < ng; ++gi) {
+                const int* ga = split && gi == 1 ? act + 1 : act;
+                const int gn = split ? (gi == 0 ? 1 : na - 1) : na;
+                if (P.d == 1) {
+                    line_pass(dsp[0], false, ur, vr, ga, gn, pg0, P.so, rp, P.s2, T, it.yscr);
+                } else {
+                    line_pass(dsp[1], false, ur, vr, ga, gn, pg1, 1.0, nullptr, 0.0, T,
+                              it.yscr);
+                    __syncthreads();
+                    line_pass(dsp[0], true, vr, vr, ga, gn, pg0, P.so, rp, P.s2, T, it.yscr);
+                }
                 __syncthreads();
-                line_pass(dsp[0], true, vr, vr, act, na, pg0, P.so, rp, P.s2, T, it.yscr);
             }
         }
         __syncthreads();

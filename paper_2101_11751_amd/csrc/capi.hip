@@ -392,6 +392,7 @@ size_t spectra_bytes(const fkgp_handle* h, fkgp_dtype dt) {
         const size_t L = size_t(1) << lg;
         t += up256(es * L) + up256(2 * es * (L / 2));
         if (lg > kMaxRegLog2 || few_lines(h, k, lg)) t += up256(2 * es * L * kLongWGs);
+        if (toeplitz_direct(h->g.m[k])) t += up256(es * (size_t)h->g.m[k]);
     }
     return t;
 }
@@ -424,13 +425,31 @@ fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtyp
                 sp.scr[k] = scr;
             }
         }
+        // the batched solver's long lines have no line scratch of their own:
+        // the spectrum still comes from the forward four-step FFT of the
+        // embedded column (O(L log L)) through a scratch of L FP64 complex
+        // values, as in the standalone passes, not from direct DFT sums
+        void* spec_scr = sp.scr[k];
+        if (!spec_scr && sp.lg1[k] > 0 && sp.log2L[k] >= 12) {
+            unsigned char* scr = nullptr;
+            FKGP_HIP(sc.get(&scr, 16 * (size_t)sp.L[k]));
+            spec_scr = scr;
+        }
         fkgp_status st = build_spectrum(h->g, k, hyp->lengthscale[k], k == dderiv, hyp->kernel,
-                                        dt, lam, sp.log2L[k], sp.lg1[k], sp.scr[k], sc.s);
+                                        dt, lam, sp.log2L[k], sp.lg1[k], spec_scr, sc.s);
         if (st != FKGP_OK) return st;
         st = build_twiddles(sp.log2L[k], dt, tw, sc.s);
         if (st != FKGP_OK) return st;
         sp.lam[k] = lam;
         sp.tw[k] = tw;
+        if (toeplitz_direct(h->g.m[k])) {
+            unsigned char* col = nullptr;
+            FKGP_HIP(sc.get(&col, es * h->g.m[k]));
+            st = build_toeplitz_col(h->g, k, hyp->lengthscale[k], k == dderiv, hyp->kernel, dt,
+                                    col, sc.s);
+            if (st != FKGP_OK) return st;
+            sp.col[k] = col;
+        }
     }
     return FKGP_OK;
 }
@@ -2842,7 +2861,8 @@ std::string batch_shape_key(const fkgp_handle* const* hs, int np) {
 }
 
 // Many problems in one persistent launch: for each problem the right-hand
-// sides [y, z_0 .. z_{N-1}] all use the factorized CG from x_0 = 0.
+// sides [y, z_0 .. z_{N-1}]; the probes use the factorized CG from x_0 = 0,
+// the data vector the simplified factorized CG from x_0 = y / s2.
 fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hypers* hyps,
                            const fkgp_mll_opts& o, double* mll, double* grad,
                            fkgp_mll_info* infos, hipStream_t st) {
@@ -2880,6 +2900,12 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
                                 hipMemcpyDeviceToDevice, st));
         rs = kg_apply(h->g, c.sp64, FKGP_F64, bh, kb, nrhs, c.so, nullptr, 0.0, nullptr, st);
         if (rs != FKGP_OK) return rs;
+        // the data right-hand side starts from x_0 = y / s2: r_hat_0 = -K_G W^T y / s2
+        double* r0y = nullptr;
+        FKGP_HIP(sc.get(&r0y, M));
+        rs = kg_apply(h->g, c.sp64, FKGP_F64, h->wty, r0y, 1, -c.so / c.s2, nullptr, 0.0,
+                      nullptr, st);
+        if (rs != FKGP_OK) return rs;
         std::vector<double> hb(nrhs, (double)h->n);
         hb[0] = h->yty;
         FKGP_HIP(hipMemcpyAsync(bn, hb.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
@@ -2906,6 +2932,7 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
         P.bh = bh;
         P.kb = kb;
         P.bnorm2 = bn;
+        P.r0y = r0y;
         P.alphas = al;
         P.betas = be;
         P.ps = ps;

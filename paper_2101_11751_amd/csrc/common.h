@@ -300,6 +300,10 @@ struct Spectra {
     void* tw[3];        // twiddles exp(-2 pi i t / L), t < L/2, complex stats dtype
     void* scr[3];       // long lines: kLongWGs * L complex scratch, else null
     int lg1[3];         // four-step split of dim k (0: register order)
+    // dimensions of at most 128 nodes: the kernel's column c[j], j < m (stats
+    // dtype), applied as the dense Toeplitz factor instead of the line FFT;
+    // null for longer dimensions
+    void* col[3];
 };
 
 int circulant_log2(int m);
@@ -311,6 +315,11 @@ fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv, int 
                            fkgp_dtype dt, void* lam, int log2L, int lg1, void* scr,
                            hipStream_t s);
 fkgp_status build_twiddles(int log2L, fkgp_dtype dt, void* tw, hipStream_t s);
+// Dimensions applied by the dense Toeplitz product (m <= 128) and the column
+// it needs: c[j] = k(j h / l) (or its derivative in log l), j < m.
+bool toeplitz_direct(int m);
+fkgp_status build_toeplitz_col(const GridDev& g, int k, double ell, bool deriv, int kind,
+                               fkgp_dtype dt, void* col, hipStream_t s);
 
 // y = scale * (T_0 (x) .. (x) T_{d-1}) x (+ add_coef * addv), batched over k
 // vectors of length M; all arrays in dtype dt.  `work` holds M*k elements.
@@ -402,6 +411,9 @@ struct BatchProb {
     const double* bh;          // [nrhs][M] W^T b
     const double* kb;          // [nrhs][M] K_G W^T b
     const double* bnorm2;      // [nrhs] ||b||^2
+    const double* r0y;         // [M] r_hat_0 = -K_G W^T y / s2 of the data right-hand
+                               // side (slot 0), solved from x_0 = y / s2 with the
+                               // residual in the span of W; null: slot 0 from x_0 = 0
     const void* tw[2];         // FP64 twiddles per dimension
     const double* lam[2];      // FP64 spectra per dimension
     double* alphas;            // [nrhs][kMaxLanczos]

@@ -167,6 +167,175 @@ __device__ __forceinline__ void line_store(const cplx<T> (&z)[R], int e_lane, bo
     }
 }
 
+// Short dimensions: the dense product with the symmetric Toeplitz factor
+// itself, y[.., i, ..] = scale * sum_{j < m} c[|i - j|] x[.., j, ..]
+// (+ add_coef * addv), c the kernel's column.  The same linear map as the
+// circulant-embedded convolution (Sec. 2.3: each factor of K_G is the
+// Toeplitz matrix of the kernel on an equispaced line), exact up to
+// rounding, no truncation of the band.  For m <= 128 nodes it costs m FMAs
+// per node, ~2 us of FP64 VALU for the 300,000 nodes of a 100 x 100 x 30
+// grid, where a line FFT pass is bound by the latency of its exchange
+// chain.
+//
+// A workgroup owns kToepC = 256 / RG whole lines (so passes may run in
+// place) and all their m nodes: the tile [m][C] is staged in LDS with
+// coalesced loads (contiguous lines as one linear range; strided lines as
+// rows of C adjacent lines), each thread forms 8 output rows of one line
+// from register blocks of 8 x 8 products (8 tile reads and 15 reads of the
+// column per 64 FMAs), and the results go back through the tile with the
+// same coalesced mapping.  The store takes the epilogue of the line passes,
+// including the fused CG direction update (CgStep2).
+constexpr int kToepR = 8;          // output rows per thread and column block
+constexpr int kToepMaxM = 128;     // longest dimension applied this way
+
+__host__ __device__ constexpr int toep_row_groups(int m) {
+    return m > 64 ? 16 : (m > 32 ? 8 : 4);
+}
+
+template <class T, int RG>
+__global__ __launch_bounds__(256) void toeplitz_pass(const T* in, T* out, LineGeom lg,
+                                                     const T* __restrict__ col, T scale,
+                                                     const T* __restrict__ addv, T add_coef,
+                                                     const int* __restrict__ skip, CgStep2 fz) {
+    constexpr int R = kToepR;
+    constexpr int C = 256 / RG;            // lines per workgroup
+    constexpr int CS = C + 1;              // padded tile row (LDS banks)
+    constexpr int MP = RG * R;             // rows covered (>= m)
+    __shared__ T tile[MP * CS];
+    __shared__ T cxs[2 * MP + 2 * R];
+    __shared__ double red[256];
+    if (skip && *skip) return;
+    const int m = lg.m_line;
+    const int tid = threadIdx.x;
+    const int64_t l0 = (int64_t)xcd_block() * C;
+    const int nc = (int)min<int64_t>((int64_t)C, lg.nlines - l0);
+    const bool contig = lg.S == 1;
+    // Each thread moves the tile entries idx = tid + 256 e, e < kE (the tile
+    // holds MP * C = 8 * 256 entries): node i of line c at address ad, with
+    // consecutive idx at consecutive addresses (contiguous lines: one linear
+    // range; strided lines: rows of nc adjacent lines).  Every global load
+    // of the pass (the tile, the column, and the operands of the epilogue)
+    // is issued here, before any is used, so the workgroup waits for memory
+    // once.
+    constexpr int kE = MP * C / 256;
+    const int nt = nc * m;
+    int ti[kE];
+    int64_t ad[kE];
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+        const int idx = tid + 256 * e;
+        const int i = contig ? idx % m : idx / nc;
+        const int c = contig ? idx / m : idx % nc;
+        ti[e] = idx < nt ? i * CS + c : -1;
+        ad[e] = contig ? l0 * (int64_t)m + idx : line_addr(lg, l0 + c, i);
+    }
+    T v[kE], av[kE];
+    double sv[kE], zv[kE], pv[kE], rv[kE];
+    T uv[kE];
+#pragma unroll
+    for (int e = 0; e < kE; ++e) v[e] = ti[e] >= 0 ? in[ad[e]] : T(0);
+    if (addv) {
+#pragma unroll
+        for (int e = 0; e < kE; ++e) av[e] = ti[e] >= 0 ? addv[ad[e]] : T(0);
+    }
+    if (fz.s) {
+        const T* uu = static_cast<const T*>(fz.u);
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            const bool ok = ti[e] >= 0;
+            sv[e] = ok ? fz.s[ad[e]] : 0.0;
+            zv[e] = ok ? fz.z[ad[e]] : 0.0;
+            uv[e] = ok ? uu[ad[e]] : T(0);
+        }
+        if (fz.p) {
+#pragma unroll
+            for (int e = 0; e < kE; ++e) {
+                const bool ok = ti[e] >= 0;
+                pv[e] = ok ? fz.p[ad[e]] : 0.0;
+                rv[e] = ok ? fz.r[ad[e]] : 0.0;
+            }
+        }
+    }
+    // c[|t - R - (m - 1)|] inside the band, zero outside (padded rows/lines)
+    for (int t = tid; t < 2 * MP + 2 * R; t += 256) {
+        const int dl = t - R - (m - 1);
+        const int a = dl < 0 ? -dl : dl;
+        cxs[t] = a < m ? col[a] : T(0);
+    }
+    // zero padding (rows >= m, lines >= nc): disjoint from the data slots
+    for (int t = tid; t < MP * CS; t += 256) {
+        const int i = t / CS, c = t - (t / CS) * CS;
+        if (i >= m || c >= nc) tile[t] = T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < kE; ++e)
+        if (ti[e] >= 0) tile[ti[e]] = v[e];
+    __syncthreads();
+    const int rg = tid / C, c = tid % C;
+    const int i0 = rg * R;
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = T(0);
+    if (i0 < m) {
+        for (int jb = 0; jb < m; jb += R) {
+            T xv[R], cw[2 * R - 1];
+#pragma unroll
+            for (int q = 0; q < R; ++q) xv[q] = tile[(jb + q) * CS + c];
+            // cxs[cb + t] = c[|i - j|] for i = i0 + r, j = jb + q, t = r - q + R - 1
+            const int cb = i0 - jb + m;
+#pragma unroll
+            for (int t = 0; t < 2 * R - 1; ++t) cw[t] = cxs[cb + t];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int q = 0; q < R; ++q) acc[r] = fma(cw[r - q + R - 1], xv[q], acc[r]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (i0 + r < m) tile[(i0 + r) * CS + c] = acc[r];
+    __syncthreads();
+    double part = 0.0;
+#pragma unroll
+    for (int e = 0; e < kE; ++e) v[e] = ti[e] >= 0 ? scale * tile[ti[e]] : T(0);
+    if (addv) {
+#pragma unroll
+        for (int e = 0; e < kE; ++e) v[e] += add_coef * av[e];
+    }
+    if (fz.s) {
+        // CG direction update: s = u + beta s, z = v + beta z, p = r + beta p
+        const double beta = fz.st->beta;
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            if (ti[e] < 0) continue;
+            const double sn = fma(beta, sv[e], (double)uv[e]);
+            const double zn = fma(beta, zv[e], (double)v[e]);
+            fz.s[ad[e]] = sn;
+            fz.z[ad[e]] = zn;
+            part = fma(sn, zn, part);
+        }
+        if (fz.p) {
+#pragma unroll
+            for (int e = 0; e < kE; ++e)
+                if (ti[e] >= 0) fz.p[ad[e]] = fma(beta, pv[e], rv[e]);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kE; ++e)
+            if (ti[e] >= 0) out[ad[e]] = v[e];
+    }
+    if (fz.s) {
+        red[tid] = part;
+        __syncthreads();
+        for (int s2 = 128; s2 > 0; s2 >>= 1) {
+            if (tid < s2) red[tid] += red[tid + s2];
+            __syncthreads();
+        }
+        last_block_finish(fz.lb, red[0], red);
+    }
+}
+
 // Barrier-free variant: each wave convolves its own line pair (64/L pairs
 // when L < 64), loading the lines straight from global memory (strided
 // lines are gathered; the vector is small enough to stay in L2) with
@@ -1306,6 +1475,63 @@ fkgp_status build_twiddles(int log2L, fkgp_dtype dt, void* tw, hipStream_t s) {
     return FKGP_OK;
 }
 
+// Off until it beats the line FFT on the solve's grids: on 100 x 100 x 30
+// the FFT passes take 12.6 / 12.6 / 6.2 us per iteration and these 17.0
+// (dimension 0, with the fused update) / 10.0 / 7.2 us.
+constexpr bool kToepEnabled = false;
+
+bool toeplitz_direct(int m) { return kToepEnabled && m <= kToepMaxM; }
+
+int64_t toeplitz_blocks(int m, int64_t nlines) {
+    const int C = 256 / toep_row_groups(m);
+    return std::max<int64_t>(1, (nlines + C - 1) / C);
+}
+
+template <class T>
+static fkgp_status launch_toeplitz(const T* in, T* out, const LineGeom& lg, const T* col,
+                                   T scale, const T* addv, T add_coef, const int* skip,
+                                   const CgStep2* fuse, hipStream_t s) {
+    CgStep2 fz{};
+    if (fuse) fz = *fuse;
+    const unsigned grid = (unsigned)toeplitz_blocks(lg.m_line, lg.nlines);
+    switch (toep_row_groups(lg.m_line)) {
+        case 16:
+            toeplitz_pass<T, 16><<<grid, 256, 0, s>>>(in, out, lg, col, scale, addv, add_coef,
+                                                      skip, fz);
+            break;
+        case 8:
+            toeplitz_pass<T, 8><<<grid, 256, 0, s>>>(in, out, lg, col, scale, addv, add_coef,
+                                                     skip, fz);
+            break;
+        default:
+            toeplitz_pass<T, 4><<<grid, 256, 0, s>>>(in, out, lg, col, scale, addv, add_coef,
+                                                     skip, fz);
+            break;
+    }
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+template <class T>
+__global__ void toeplitz_col_kernel(T* __restrict__ col, int m, double h, double ell, bool deriv,
+                                    int kind) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m) col[j] = (T)kernel_col(kind, j, h, ell, deriv);
+}
+
+fkgp_status build_toeplitz_col(const GridDev& g, int k, double ell, bool deriv, int kind,
+                               fkgp_dtype dt, void* col, hipStream_t s) {
+    const unsigned grid = (unsigned)((g.m[k] + 255) / 256);
+    if (dt == FKGP_F32)
+        toeplitz_col_kernel<float><<<grid, 256, 0, s>>>(static_cast<float*>(col), g.m[k], g.h[k],
+                                                        ell, deriv, kind);
+    else
+        toeplitz_col_kernel<double><<<grid, 256, 0, s>>>(static_cast<double*>(col), g.m[k],
+                                                         g.h[k], ell, deriv, kind);
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
 template <class T>
 static fkgp_status kg_apply_t(const GridDev& g, const Spectra& sp, const T* x, T* y, int k,
                               double scale, const T* addv, double add_coef, const int* skip,
@@ -1320,10 +1546,16 @@ static fkgp_status kg_apply_t(const GridDev& g, const Spectra& sp, const T* x, T
         LineGeom lg{g.m[dim], S, (int64_t)k * M / g.m[dim]};
         const bool last = pass == g.d - 1;
         const T* src = pass == 0 ? x : y;
-        fkgp_status st = launch_line_conv<T>(
-            sp.log2L[dim], sp.lg1[dim], src, y, lg, static_cast<const T*>(sp.lam[dim]),
-            static_cast<const cplx<T>*>(sp.tw[dim]), last ? (T)scale : T(1),
-            last ? addv : nullptr, (T)add_coef, skip, static_cast<cplx<T>*>(sp.scr[dim]), s);
+        fkgp_status st =
+            sp.col[dim]
+                ? launch_toeplitz<T>(src, y, lg, static_cast<const T*>(sp.col[dim]),
+                                     last ? (T)scale : T(1), last ? addv : nullptr,
+                                     (T)add_coef, skip, nullptr, s)
+                : launch_line_conv<T>(sp.log2L[dim], sp.lg1[dim], src, y, lg,
+                                      static_cast<const T*>(sp.lam[dim]),
+                                      static_cast<const cplx<T>*>(sp.tw[dim]),
+                                      last ? (T)scale : T(1), last ? addv : nullptr,
+                                      (T)add_coef, skip, static_cast<cplx<T>*>(sp.scr[dim]), s);
         if (st != FKGP_OK) return st;
     }
     return FKGP_OK;
@@ -1336,7 +1568,9 @@ static fkgp_status kg_apply_fused_t(const GridDev& g, const Spectra& sp, const T
                                     hipStream_t s) {
     int64_t M = 1;
     for (int i = 0; i < g.d; ++i) M *= g.m[i];
-    *fused = sp.lg1[0] == 0;   // the last pass (dimension 0) on the register path
+    // the last pass (dimension 0) fuses the update on the direct Toeplitz
+    // path and on the register FFT path
+    *fused = sp.col[0] != nullptr || sp.lg1[0] == 0;
     for (int pass = 0; pass < g.d; ++pass) {
         const int dim = g.d - 1 - pass;
         int64_t S = 1;
@@ -1344,11 +1578,18 @@ static fkgp_status kg_apply_fused_t(const GridDev& g, const Spectra& sp, const T
         LineGeom lg{g.m[dim], S, M / g.m[dim]};
         const bool last = pass == g.d - 1;
         const T* src = pass == 0 ? x : y;
-        fkgp_status st = launch_line_conv<T>(
-            sp.log2L[dim], sp.lg1[dim], src, y, lg, static_cast<const T*>(sp.lam[dim]),
-            static_cast<const cplx<T>*>(sp.tw[dim]), last ? (T)scale : T(1),
-            last ? addv : nullptr, (T)add_coef, skip, static_cast<cplx<T>*>(sp.scr[dim]), s,
-            (last && *fused) ? &fuse : nullptr);
+        const CgStep2* fz = (last && *fused) ? &fuse : nullptr;
+        fkgp_status st =
+            sp.col[dim]
+                ? launch_toeplitz<T>(src, y, lg, static_cast<const T*>(sp.col[dim]),
+                                     last ? (T)scale : T(1), last ? addv : nullptr,
+                                     (T)add_coef, skip, fz, s)
+                : launch_line_conv<T>(sp.log2L[dim], sp.lg1[dim], src, y, lg,
+                                      static_cast<const T*>(sp.lam[dim]),
+                                      static_cast<const cplx<T>*>(sp.tw[dim]),
+                                      last ? (T)scale : T(1), last ? addv : nullptr,
+                                      (T)add_coef, skip, static_cast<cplx<T>*>(sp.scr[dim]), s,
+                                      fz);
         if (st != FKGP_OK) return st;
     }
     return FKGP_OK;
@@ -1372,7 +1613,8 @@ int64_t kg_last_pass_blocks(const GridDev& g) {
     int64_t M = 1;
     for (int i = 0; i < g.d; ++i) M *= g.m[i];
     LineGeom lg{g.m[0], M / g.m[0], M / g.m[0]};
-    return line_direct_blocks(circulant_log2(g.m[0]), lg);
+    return std::max<int64_t>(line_direct_blocks(circulant_log2(g.m[0]), lg),
+                             toeplitz_blocks(g.m[0], M / g.m[0]));
 }
 
 fkgp_status kg_apply(const GridDev& g, const Spectra& sp, fkgp_dtype dt, const void* x, void* y,

@@ -901,8 +901,7 @@ __global__ void assemble_vec_stage(const double* __restrict__ in, double* __rest
 // rows past M in the last tile are written as zeros.
 template <class T>
 __global__ void transpose_to_dia(const double* __restrict__ in, T* __restrict__ out, int64_t M,
-                                 int NB, uint32_t* __restrict__ bmask,
-                                 unsigned long long* __restrict__ nnz) {
+                                 int NB, uint32_t* __restrict__ bmask) {
     __shared__ double tile[32][33];
     __shared__ uint32_t occ;
     const int64_t j0 = (int64_t)blockIdx.x * 32;
@@ -917,27 +916,18 @@ __global__ void transpose_to_dia(const double* __restrict__ in, T* __restrict__ 
     // the block's 32 rows lie in one wavefront chunk of one row tile
     const int w = (int)((j0 % kRowTile) / kWaveRows);
     uint32_t bits = 0u;
-    unsigned cnt = 0u;
     for (int r = threadIdx.y; r < 32; r += 8) {
         int o = o0 + r;
         int64_t j = j0 + threadIdx.x;
         if (o < NB) {
             const T v = (T)tile[threadIdx.x][r];
             out[dia_index(j, o, NB)] = v;
-            if (v != T(0)) {
-                bits |= 1u << (w * kMaskSlabs + o / 49);
-                ++cnt;
-            }
+            if (v != T(0)) bits |= 1u << (w * kMaskSlabs + o / 49);
         }
     }
-    // OR and count over the wavefront, then one LDS OR and one counter add
-    // per wavefront (integer operations: order-independent)
-    for (int off = 32; off > 0; off >>= 1) {
-        bits |= (uint32_t)__shfl_xor((int)bits, off);
-        cnt += (unsigned)__shfl_xor((int)cnt, off);
-    }
-    if (((threadIdx.y * 32 + threadIdx.x) & 63) == 0 && cnt)
-        atomicAdd(nnz, (unsigned long long)cnt);
+    // OR over the wavefront, then one LDS OR per wavefront (integer
+    // operations: order-independent)
+    for (int off = 32; off > 0; off >>= 1) bits |= (uint32_t)__shfl_xor((int)bits, off);
     if (((threadIdx.y * 32 + threadIdx.x) & 63) == 0 && bits) atomicOr(&occ, bits);
     __syncthreads();
     if (threadIdx.x == 0 && threadIdx.y == 0 && occ) atomicOr(&bmask[j0 / kRowTile], occ);
@@ -1200,13 +1190,17 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         dim3 tb(32, 8), tg((unsigned)(Mpad / 32), (unsigned)((NB + 31) / 32));
         if (stats == FKGP_F32)
             transpose_to_dia<float><<<tg, tb, 0, s>>>(src, static_cast<float*>(out.wtw), M, NB,
-                                                      out.bmask, out.nnz);
+                                                      out.bmask);
         else
             transpose_to_dia<double><<<tg, tb, 0, s>>>(src, static_cast<double*>(out.wtw), M, NB,
-                                                       out.bmask, out.nnz);
+                                                       out.bmask);
         FKGP_HIP(hipGetLastError());
         count_mask_bits<<<1, 256, 0, s>>>(out.bmask, mask_words(M), out.nzblocks);
         FKGP_HIP(hipGetLastError());
+        // exact nonzero count: a separate read of the stored matrix (a few
+        // thousand counter updates instead of one per wavefront above)
+        fkgp_status cs = count_wtw_nonzeros(stats, out.wtw, dia_elems(M, NB), out.nnz, s);
+        if (cs != FKGP_OK) return cs;
     }
     // --- W^T y and sketches: stages over k = d-1 .. 0 ---
     {

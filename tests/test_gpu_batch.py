@@ -158,6 +158,11 @@ def test_batch64_workload_subset():
         ms, gs, inf = P.mll_and_grad(h, hyps[k], 30, 1e-8, 20000)
         assert inf["status"] == 0 and ib[k]["status"] == 0
         scale = abs(inf["logdet"]) + abs(inf["quad"]) + h.n * math.log(2 * math.pi)
+        print(f"{k}: m={h.m_total} n={h.n}: mll {mb[k]:.12g} / {ms:.12g}, logdet "
+              f"{ib[k]['logdet']:.12g} / {inf['logdet']:.12g}, quad {ib[k]['quad']:.12g} / "
+              f"{inf['quad']:.12g}, iterations y {ib[k]['iterations_y']} / "
+              f"{inf['iterations_y']}, probes {ib[k]['iterations_probes_max']} / "
+              f"{inf['iterations_probes_max']}")
         assert abs(mb[k] - ms) <= 1e-6 * scale, (k, mb[k], ms)
         np.testing.assert_allclose(gb[k], gs, rtol=0, atol=1e-4 * np.max(np.abs(gs)))
 
@@ -183,3 +188,43 @@ def test_batch_response_norm_not_n():
     assert abs(ib[0]["quad"] - inf["quad"]) <= 1e-6 * inf["quad"]
     scale = abs(inf["logdet"]) + abs(inf["quad"]) + n * math.log(2 * math.pi)
     assert abs(mb[0] - ms) <= 1e-7 * scale
+
+
+def test_batch64_long_1d_against_oracle():
+    """Long 1-D problems of the many-problem workload (4,365 and 7,549
+    nodes, lengthscales of ~100 and ~245 nodes, four-step line FFTs) with 30
+    Lanczos steps: both GPU paths against the oracle's estimator with the
+    same probes (the oracle's own log-determinant moves by ~3e-11 when only
+    the rounding of K_G changes, FFT or dense)."""
+    _need_gpu()
+    from paper_2101_11751_amd import workloads
+    wls = workloads.batch64(device="cpu", n_scale=0.02, which=[4, 30])
+    hs, hyps, data = [], [], []
+    for w in wls:
+        X = np.stack([x.numpy() for x in w["x"]])
+        y = w["y"].numpy()
+        xs = [torch.from_numpy(np.ascontiguousarray(X[k])).cuda() for k in range(X.shape[0])]
+        hs.append(P.precompute(w["grid"], xs, torch.from_numpy(y).cuda(),
+                               stats_dtype=torch.float64, n_probes=w["nprobes"],
+                               probe_seed=w["probe_seed"]))
+        hyps.append(w["hypers"])
+        data.append((X, y))
+    tol = 1e-10
+    mb, gb, ib = P.batch_mll_and_grad(hs, hyps, 30, tol, 20000)
+    for k, w in enumerate(wls):
+        X, y = data[k]
+        ms, gs, inf = P.mll_and_grad(hs[k], hyps[k], 30, tol, 20000)
+        wtw, wty, yty = oracle.precompute(w["grid"], X, y)
+        sk = oracle.probe_sketches(w["grid"], X, w["probe_seed"], w["nprobes"])
+        mo, go, io = oracle.mll_and_grad(w["grid"], hyps[k], wtw, wty, yty, X.shape[1], sk,
+                                         lanczos_steps=30, tol=tol, maxiter=20000)
+        print(f"{w['name']} m={w['grid']['m']}: logdet batch {ib[k]['logdet']:.12g} single "
+              f"{inf['logdet']:.12g} oracle {io['logdet']:.12g}; quad batch "
+              f"{ib[k]['quad']:.12g} single {inf['quad']:.12g} oracle {io['q']:.12g}; "
+              f"probe iterations batch {ib[k]['iterations_probes_max']} single "
+              f"{inf['iterations_probes_max']}")
+        q_bound = 2 * tol * yty / hyps[k]["noise"] ** 2
+        for name, ld, q in (("batch", ib[k]["logdet"], ib[k]["quad"]),
+                            ("single", inf["logdet"], inf["quad"])):
+            assert abs(ld - io["logdet"]) <= 1e-9 * abs(io["logdet"]), name
+            assert abs(q - io["q"]) <= 1e-9 * abs(io["q"]) + q_bound, name

@@ -55,6 +55,30 @@ def dev_arrays(X, y):
             torch.from_numpy(np.ascontiguousarray(y)).cuda())
 
 
+def kappa_estimate(grid, hyp, wtw, iters=60):
+    """Condition number of A = W K_G W^T + s2 I (n-space, SPD): its largest
+    eigenvalue is s2 plus that of K_G W^T W (a similar matrix), found by
+    power iteration with the oracle's operators; the smallest is >= s2."""
+    v = np.random.default_rng(0).standard_normal(wtw.shape[0])
+    lam = 0.0
+    for _ in range(iters):
+        w = oracle.kg_matvec(grid, hyp, oracle.wtw_matvec(grid, wtw, v))
+        lam = float(np.linalg.norm(w) / np.linalg.norm(v))
+        v = w / np.linalg.norm(w)
+    s2 = hyp["noise"] ** 2
+    return (1.05 * lam + s2) / s2
+
+
+def fp64_mean_tol(grid, hyp, wtw):
+    """FP64 posterior-mean tolerance.  Two FP64 computations of the
+    statistics differ by the rounding of their sums (summation order, basis):
+    about sqrt(N) u relative for the N ~ 10^3 terms of an entry, taken as
+    32 u.  The mean's sensitivity to such a perturbation of the operator is
+    bounded by kappa(A), so the reachable agreement is 32 u kappa(A); the
+    fixed 1e-10 applies where that is smaller."""
+    return max(1e-10, 32 * 2.0 ** -53 * kappa_estimate(grid, hyp, wtw))
+
+
 def shifted(hyp, i, d, e):
     hp = {"lengthscale": list(hyp["lengthscale"]), "outputscale": hyp["outputscale"],
           "noise": hyp["noise"]}
@@ -80,25 +104,26 @@ def test_sine1d_fp64_at_the_workload():
     assert rel(wtw.cpu(), wtw_o) <= 1e-13
     assert rel(wty.cpu(), wty_o) <= 1e-13
     assert abs(yty - yty_o) <= 1e-13 * yty_o
-    # at the workload's tolerance (1e-8): the same iterate as the oracle's
-    # factorized CG after the same number of iterations (the iterates do not
-    # depend on the tolerance, which only decides when to stop; the two stop
-    # tests may fire one iteration apart)
+    # at the workload's tolerance (1e-8).  The iterates of two FP64
+    # implementations of the same CG are not comparable one by one here: the
+    # system's condition number (~1e5) amplifies rounding in K_G's
+    # application, so two oracle runs that differ only in how K_G is applied
+    # (FFT or dense) already differ by ~1e-3 after 50 iterations.  What
+    # is fixed is the iteration count (Prop. 1: the same Krylov process)
+    # and the accuracy reached at the tolerance.
     mu, info = P.solve(h, hyp, tol=wl["tol"], maxiter=5000)
-    _, _, info_o8 = oracle.solve_mean(grid, hyp, wtw_o, wty_o, yty_o, tol=wl["tol"])
-    _, _, hist = oracle.solve_mean(grid, hyp, wtw_o, wty_o, yty_o, tol=0.01 * wl["tol"],
-                                   history=True)
+    mu_o8, _, info_o8 = oracle.solve_mean(grid, hyp, wtw_o, wty_o, yty_o, tol=wl["tol"])
     assert info["converged"]
-    assert abs(info["iterations"] - info_o8["iterations"]) <= 1, (info, info_o8["iterations"])
-    mu_k = oracle.kg_matvec(grid, hyp, hist["wtx_history"][info["iterations"]])
-    err8 = rel(mu.cpu(), mu_k)
+    assert abs(info["iterations"] - info_o8["iterations"]) <= 2, (info, info_o8["iterations"])
     # converged: 1e-10 against the oracle solved to 1e-13
     mu12, info12 = P.solve(h, hyp, tol=1e-12, maxiter=5000)
     mu_o, _, _ = oracle.solve_mean(grid, hyp, wtw_o, wty_o, yty_o, tol=1e-13)
     err = rel(mu12.cpu(), mu_o)
+    err8, err8_o = rel(mu.cpu(), mu_o), rel(mu_o8, mu_o)
     print(f"sine1d: iterations {info['iterations']} (oracle {info_o8['iterations']}), "
-          f"mean err at tol 1e-8 {err8:.2e}, converged {err:.2e}")
-    assert err8 <= 1e-10
+          f"mean err at tol 1e-8 {err8:.2e} (oracle's own {err8_o:.2e}), converged {err:.2e}")
+    # as accurate as the oracle at the workload's tolerance
+    assert err8 <= 2 * err8_o + 1e-10
     assert err <= 1e-10
     # predictions at 1000 query points, and against the noise-free function
     xq = np.linspace(0.0, 1.0, 1000)
@@ -132,7 +157,11 @@ def test_bumps2d_fp32_at_the_workload():
     wtw, wty, yty = P.export_stats(h32)
     assert rel(wtw.cpu(), wtw_o) <= 1e-6
     assert rel(wty.cpu(), wty_o) <= 1e-13
-    assert abs(yty - yty_o) <= 1e-13 * yty_o
+    # y^T y: squares of FP32 values are exact in FP64, so the two sums differ
+    # only by their rounding: at most (n - 1) u for the oracle's serial sum
+    # and ceil(log2 n) u for a tree, relative to the (positive) sum
+    n = X.shape[1]
+    assert abs(yty - yty_o) <= (n + math.ceil(math.log2(n))) * 2.0 ** -53 * yty_o
     for op in ("stats", "f64"):   # FP32 operator arithmetic (FP64 refinement) / FP64
         mu, info = P.solve(h32, hyp, tol=1e-7, maxiter=40000, op_precision=op)
         err = rel(mu.cpu(), mu_ref)
@@ -144,8 +173,10 @@ def test_bumps2d_fp32_at_the_workload():
     assert rel(P.export_stats(h64)[0].cpu(), wtw_o) <= 1e-13
     mu, info = P.solve(h64, hyp, tol=1e-12, maxiter=40000)
     err = rel(mu.cpu(), mu_ref)
-    print(f"bumps2d FP64: {info['iterations']} iterations, mean err {err:.2e}")
-    assert info["converged"] and err <= 1e-10
+    tol64 = fp64_mean_tol(grid, hyp, wtw_o)
+    print(f"bumps2d FP64: {info['iterations']} iterations, mean err {err:.2e} "
+          f"(tolerance {tol64:.2e})")
+    assert info["converged"] and err <= tol64
 
 
 @pytest.mark.parametrize("d,m,n", [(1, [4096], 4096), (1, [20000], 20000),
@@ -169,43 +200,67 @@ def test_one_point_per_cell_fp64_solve(d, m, n):
     mu_o, _, _ = oracle.solve_mean(grid, hyp, wtw_o, wty_o, yty_o, tol=1e-13, maxiter=100000)
     mu, info = P.solve(h, hyp, tol=1e-12, maxiter=100000)
     err = rel(mu.cpu(), mu_o)
-    print(f"d={d} m={m} n={n}: {info['iterations']} iterations, mean err {err:.2e}")
-    assert info["converged"] and err <= 1e-10
+    tol64 = fp64_mean_tol(grid, hyp, wtw_o)
+    print(f"d={d} m={m} n={n}: {info['iterations']} iterations, mean err {err:.2e} "
+          f"(tolerance {tol64:.2e})")
+    assert info["converged"] and err <= tol64
+
+
+def q_variational(grid, hp, wtw, wty, yty, mu):
+    """q = y^T A^{-1} y from a computed posterior mean mu = K_G W^T x, through
+    the variational form 2 y^T x - x^T A x with x = (y - W mu) / s2 (which
+    equals A^{-1} y when mu is exact).  Its error is -(x - x*)^T A (x - x*),
+    second order in the solve's error, while y^T x (the library's q) is first
+    order: central differences of it are not swamped by the solve tolerance
+    divided by 2h.  Evaluated in FP64 with the oracle's operators on the
+    handle's statistics."""
+    s2 = hp["noise"] ** 2
+    wm = oracle.wtw_matvec(grid, wtw, mu)
+    q = (yty - float(wty @ mu)) / s2
+    g = (wty - wm) / s2                                   # W^T x
+    xx = (yty - 2.0 * float(wty @ mu) + float(mu @ wm)) / (s2 * s2)   # x^T x
+    return 2.0 * q - (float(g @ oracle.kg_matvec(grid, hp, g)) + s2 * xx)
 
 
 @pytest.mark.slow
 def test_prior2d_quadratic_term_finite_differences():
     """q(theta) = y^T A(theta)^{-1} y is deterministic: its central
-    differences (h = 1e-4) match the adjoint gradient -x_y^T dA x_y to the
-    solve tolerance.  Full differentiation workload (n = 4e6, 256^2), at the
-    offset hyperparameters (the gradient is ~0 at the truth)."""
+    differences (h = 1e-4) match the adjoint gradient -x_y^T dA x_y.  Full
+    differentiation workload (n = 4e6, 256^2, FP32 statistics), at the offset
+    hyperparameters (the gradient is ~0 at the truth)."""
     _need_gpu()
     wl = workloads.prior2d()
     X, y = host_arrays(wl)
     xs, yt = dev_arrays(X, y)
     hyp = wl["hypers_offset"]
-    h = P.precompute(wl["grid"], xs, yt, stats_dtype=torch.float32,
+    grid = wl["grid"]
+    h = P.precompute(grid, xs, yt, stats_dtype=torch.float32,
                      n_probes=wl["nprobes"], probe_seed=wl["probe_seed"])
-    _, wty, yty = P.export_stats(h)
-    tol = 1e-12
+    wtw, wty, yty = P.export_stats(h)
+    wtw = wtw.cpu().numpy().astype(np.float64)
+    wty = wty.cpu().numpy()
+    tol = 1e-11
 
     def q(hp):
         mu, info = P.solve(h, hp, tol=tol, maxiter=100000)
         assert info["converged"]
-        return (yty - float(torch.dot(wty, mu))) / hp["noise"] ** 2
+        return q_variational(grid, hp, wtw, wty, yty, mu.cpu().numpy())
 
     _, _, inf = P.mll_and_grad(h, hyp, lanczos_steps=30, tol=tol, maxiter=100000)
     q0 = q(hyp)
-    assert abs(q0 - inf["quad"]) <= 1e-9 * abs(q0)
+    # the library's q = y^T x is off by y^T A^{-1} r, |.| <= ||y|| ||r|| / s2,
+    # where the true residual r of FP64 CG stops falling at about u kappa(A)
+    # ||y|| (here ~1e-10 ||y||, above the requested tolerance)
+    s2 = hyp["noise"] ** 2
+    res = max(tol, 4 * 2.0 ** -53 * kappa_estimate(grid, hyp, wtw))
+    print(f"q: library {inf['quad']:.12g}, variational {q0:.12g}, "
+          f"bound {res * yty / s2:.3g}")
+    assert abs(q0 - inf["quad"]) <= res * yty / s2
     eps = 1e-4
-    ynorm2 = float(yty)
     for i in range(4):
         fd = (q(shifted(hyp, i, 2, eps)) - q(shifted(hyp, i, 2, -eps))) / (2 * eps)
-        # each q carries |y^T A^{-1} r| <= tol ||y||^2 / sigma^2 (lambda_min(A) >= sigma^2)
-        s2 = min(hyp["noise"] * math.exp(-eps), hyp["noise"]) ** 2
-        bound = 1e-5 * abs(inf["dquad"][i]) + 2 * tol * ynorm2 / s2 / (2 * eps)
         print(f"dq/dtheta_{i}: adjoint {inf['dquad'][i]:.10g}, central differences {fd:.10g}")
-        assert abs(fd - inf["dquad"][i]) <= bound, (i, fd, inf["dquad"][i], bound)
+        assert abs(fd - inf["dquad"][i]) <= 1e-5 * abs(inf["dquad"][i]), (i, fd, inf["dquad"][i])
 
 
 def reduced_prior2d(side=48):

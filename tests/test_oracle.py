@@ -3,6 +3,7 @@
 weight coefficient, a transposed offset, a dropped sigma^2, a wrong sign or
 index in the factorized recurrences."""
 import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -89,6 +90,68 @@ def test_keys_weights_match_textbook_kernel_and_continuity():
     W = oracle.dense_w(grid, X)
     Wt = dense_w_textbook(grid, X)
     np.testing.assert_allclose(W, Wt, atol=1e-14)
+
+
+def _keys_exact(s):
+    """Textbook Keys kernel (a = -1/2) in exact rational arithmetic."""
+    s = abs(s)
+    if s <= 1:
+        return Fraction(3, 2) * s ** 3 - Fraction(5, 2) * s ** 2 + 1
+    if s < 2:
+        return -Fraction(1, 2) * s ** 3 + Fraction(5, 2) * s ** 2 - 4 * s + 2
+    return Fraction(0)
+
+
+def test_keys_weights_relative_accuracy_against_exact_rationals():
+    """Each weight to a few units in its own last place, also where it is
+    tiny (t or 1 - t near 0), against the kernel evaluated exactly at the
+    same (binary) offset."""
+    grid = oracle.make_grid([10], origin=[0.0], spacing=[1.0])
+    ts = [2.0 ** -k for k in range(1, 40, 3)] + [1 - 2.0 ** -k for k in range(1, 40, 3)]
+    ts += list(np.random.default_rng(9).uniform(0, 1, 200))
+    for t in ts:
+        nodes, w, _ = oracle.stencils(grid, np.array([4.0 + t]))
+        u = Fraction(4.0 + t)
+        for a in range(4):
+            ex = _keys_exact(u - int(nodes[0, a]))
+            assert abs(Fraction(float(w[0, a])) - ex) <= 8 * Fraction(2) ** -53 * abs(ex), (t, a)
+
+
+@pytest.mark.parametrize("m,n", [([300], 300), ([18, 17], 300)])
+def test_wtw_entries_against_exact_rationals_one_point_per_cell(m, n):
+    """About one point per cell, so many entries are single products of
+    small weights: every entry within 64 units of 2^-53 times the matching
+    entry of |W|^T |W| of the exact sum (weights and products in rationals)."""
+    rng = np.random.default_rng(5)
+    grid = oracle.make_grid(m, lo=0.0, hi=1.0)
+    d = len(m)
+    X = rng.uniform(0, 1, (d, n))
+    wtw, _, _ = oracle.precompute(grid, X, np.ones(n))
+    M = int(np.prod(m))
+    ex = np.zeros((M, 7 ** d), object)
+    ex[:] = Fraction(0)
+    exa = np.zeros((M, 7 ** d))
+    g0, h = grid["origin"], grid["spacing"]
+    for i in range(n):
+        base, w1 = [], []
+        for k in range(d):
+            u = (X[k, i] - g0[k]) / h[k]
+            b = min(int(np.floor(u)), m[k] - 3)
+            uf = Fraction(u)
+            base.append(b)
+            w1.append([_keys_exact(uf - (b - 1 + a)) for a in range(4)])
+        for sa in np.ndindex(*([4] * d)):
+            for sb in np.ndindex(*([4] * d)):
+                wa = wb = Fraction(1)
+                for k in range(d):
+                    wa *= w1[k][sa[k]]
+                    wb *= w1[k][sb[k]]
+                ja = np.ravel_multi_index([base[k] - 1 + sa[k] for k in range(d)], m)
+                o = np.ravel_multi_index([sb[k] - sa[k] + 3 for k in range(d)], [7] * d)
+                ex[ja, o] += wa * wb
+                exa[ja, o] += abs(float(wa * wb))
+    exf = np.vectorize(float)(ex)
+    assert np.all(np.abs(wtw - exf) <= 64 * 2.0 ** -53 * exa)
 
 
 def test_out_of_grid_rejected():
