@@ -254,13 +254,22 @@ typedef struct {
                            workgroup (256 or 512); 0 = autotune.  Autotuning
                            times a short trial of each candidate and caches
                            the fastest per batch shape for the process. */
-    int trace_mode;     /* gradient traces tr(A^{-1} dA): 0 = Hutchinson over
-                           the probes (the solves the MLL already ran);
-                           1 = exact, through S = W^T A^{-1} W from m grid
+    int trace_mode;     /* gradient of the log-determinant term: 0 =
+                           Hutchinson traces tr(A^{-1} dA) over the probes
+                           (the solves the MLL already ran); 1 = exact
+                           traces, through S = W^T A^{-1} W from m grid
                            right-hand-side solves (fkgp_mll_and_grad only,
                            m <= 4096; for checks against finite differences
-                           of the exact MLL).  The log-determinant stays the
-                           stochastic Lanczos estimate either way. */
+                           of the exact MLL); 2 = the derivative of the
+                           stochastic Lanczos estimate itself, by reverse
+                           mode through each probe's lanczos_steps Lanczos
+                           steps (the first residuals of its factorized CG
+                           are checkpointed as the Lanczos vectors; Sec. 2.1
+                           and the appendix's factorized Lanczos), so the
+                           gradient is exactly that of the returned MLL
+                           (fkgp_mll_and_grad only; probes batched; at most
+                           64 probes).  The log-determinant value is the
+                           stochastic Lanczos estimate in every mode. */
 } fkgp_mll_opts;
 
 typedef struct {

@@ -593,12 +593,13 @@ def mll_and_grad(h, hypers, lanczos_steps=30, tol=1e-6, maxiter=1000, batched=Tr
                  trace="hutchinson"):
     """(mll, grad [d+2] w.r.t. (log l_k, log s, log sigma), info).  batched:
     all probes advance together (one W^T W read per iteration).  trace:
-    "hutchinson" (over the probes) or "exact" (m grid solves, m <= 4096)."""
+    "hutchinson" (over the probes), "exact" (m grid solves, m <= 4096) or
+    "slq" (the derivative of the returned Lanczos estimate itself)."""
     L = load_library()
     mll = ctypes.c_double()
     grad = (ctypes.c_double * (h.d + 2))()
     info = _MllInfo()
-    tm = {"hutchinson": 0, "exact": 1}[trace]
+    tm = {"hutchinson": 0, "exact": 1, "slq": 2}[trace]
     st = _check(L.fkgp_mll_and_grad(h.ptr, ctypes.byref(_hyp_struct(hypers, h.d)),
                                     ctypes.byref(_MllOpts(int(lanczos_steps), float(tol),
                                                           int(maxiter), int(bool(batched)), 0, 0,

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -392,7 +393,7 @@ size_t spectra_bytes(const fkgp_handle* h, fkgp_dtype dt) {
         const size_t L = size_t(1) << lg;
         t += up256(es * L) + up256(2 * es * (L / 2));
         if (lg > kMaxRegLog2 || few_lines(h, k, lg)) t += up256(2 * es * L * kLongWGs);
-        if (toeplitz_direct(h->g.m[k])) t += up256(es * (size_t)h->g.m[k]);
+        if (toeplitz_slab_applies(h->g)) t += up256(es * (size_t)h->g.m[k]);
     }
     return t;
 }
@@ -442,7 +443,7 @@ fkgp_status make_spectra(const fkgp_handle* h, const fkgp_hypers* hyp, fkgp_dtyp
         if (st != FKGP_OK) return st;
         sp.lam[k] = lam;
         sp.tw[k] = tw;
-        if (toeplitz_direct(h->g.m[k])) {
+        if (toeplitz_slab_applies(h->g)) {
             unsigned char* col = nullptr;
             FKGP_HIP(sc.get(&col, es * h->g.m[k]));
             st = build_toeplitz_col(h->g, k, hyp->lengthscale[k], k == dderiv, hyp->kernel, dt,
@@ -2427,10 +2428,23 @@ hipError_t probe_snap_get(ProbeSnap& out) {
 // Grid right-hand sides b_j = W v_j (v0 [N][M], bh = W^T W v, bb_dev [N] =
 // v_j . bh_j on the device): the iteration starts from r_hat = v.  Outputs
 // W^T x_j (wx [N][M]), the CG coefficients and the final states.
+// c_r and rho of every probe after an iteration (residual history)
+__global__ void probe_hist(const PState* __restrict__ ps, int N, double* __restrict__ sh) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < N) {
+        sh[2 * j] = ps[j].cr;
+        sh[2 * j + 1] = ps[j].rho;
+    }
+}
+
+// rhist (optional, [khist][N][M]) and shist ([khist][N][2]) receive the
+// residuals r_i = W r_hat_i + c_r,i z_j of the first khist iterations
+// (r_hat_i, then (c_r,i, ||r_i||^2)); r_0 = z_j: r_hat = 0, c_r = 1, n.
 fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double tol,
                      int maxiter, double* wx, double* alphas, double* betas, PState* ps,
                      Scratch& sc, hipStream_t st, int& iters_max,
-                     const double* bb_dev = nullptr, const double* v0 = nullptr) {
+                     const double* bb_dev = nullptr, const double* v0 = nullptr,
+                     double* rhist = nullptr, double* shist = nullptr, int khist = 0) {
     const fkgp_handle* h = c.h;
     const int64_t M = c.M;
     const int64_t ldx = M + 2 * c.halo;
@@ -2461,6 +2475,11 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
     }
     probe_init<<<(N + 63) / 64, 64, 0, st>>>(ps, N, n, tol, bb_dev);
     FKGP_HIP(hipGetLastError());
+    if (rhist && khist > 0) {
+        FKGP_HIP(hipMemsetAsync(rhist, 0, sizeof(double) * M * N, st));
+        probe_hist<<<(N + 63) / 64, 64, 0, st>>>(ps, N, shist);
+        FKGP_HIP(hipGetLastError());
+    }
     const dim3 gv(nbv, N);
     const dim3 ge((unsigned)std::min<int64_t>((M + 255) / 256, 1024), N);
     // pipelined convergence checks, as in run_cg: the states after each
@@ -2494,6 +2513,13 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
             probe_dot_r<<<gv, kRedBlock, 0, st>>>(ps, rh, ur, bh, M, partials);
             probe_fin_r<<<N, kRedBlock, 0, st>>>(ps, partials, nbv, betas);
             FKGP_HIP(hipGetLastError());
+            const int gi = launched + it + 1;   // index of the residual just formed
+            if (rhist && gi < khist) {
+                FKGP_HIP(hipMemcpyAsync(rhist + (size_t)gi * N * M, rh, sizeof(double) * M * N,
+                                        hipMemcpyDeviceToDevice, st));
+                probe_hist<<<(N + 63) / 64, 64, 0, st>>>(ps, N, shist + (size_t)gi * N * 2);
+                FKGP_HIP(hipGetLastError());
+            }
         }
         launched += nit;
         FKGP_HIP(hipMemcpyAsync(snapbuf.host + (size_t)next * kSnapStates, ps,
@@ -2693,6 +2719,369 @@ fkgp_status exact_traces(const OpCtx& c, const fkgp_hypers* hyp, double tol, int
     return FKGP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Reverse-mode derivative of the stochastic Lanczos log-determinant estimate
+// itself: for each probe, Gamma_j = n e_1^T log(T_j) e_1 with T_j the
+// Lanczos tridiagonal that the first k factorized-CG coefficients give, and
+// its derivative in every hyperparameter through the k Lanczos steps run
+// backwards (the checkpointed Krylov vectors are the CG residuals,
+// q_i = (-1)^i r_i / ||r_i||; Claims 3-4 keep them as pairs r = W a + c z).
+// ---------------------------------------------------------------------------
+
+// Eigenvalues (d) and eigenvectors (Z, Z[r * k + col]) of the symmetric
+// tridiagonal matrix with diagonal d and off-diagonal e (e[i] couples i and
+// i + 1), by implicit QL iterations with Wilkinson-type shifts.
+bool tridiag_eig(int k, std::vector<double>& d, std::vector<double> e, std::vector<double>& Z) {
+    Z.assign((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) Z[(size_t)i * k + i] = 1.0;
+    e.resize(k, 0.0);
+    if (k > 0) e[k - 1] = 0.0;
+    for (int l = 0; l < k; ++l) {
+        int iter = 0;
+        for (;;) {
+            int m = l;
+            for (; m < k - 1; ++m) {
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= 4.0 * DBL_EPSILON * dd) break;
+            }
+            if (m == l) break;
+            if (++iter > 100) return false;
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+            double sn = 1.0, cs = 1.0, p = 0.0;
+            bool early = false;
+            for (int i = m - 1; i >= l; --i) {
+                double f = sn * e[i];
+                const double b = cs * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {
+                    d[i + 1] -= p;
+                    e[m] = 0.0;
+                    early = true;
+                    break;
+                }
+                sn = f / r;
+                cs = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * sn + 2.0 * cs * b;
+                p = sn * r;
+                d[i + 1] = g + p;
+                g = cs * r - b;
+                for (int t = 0; t < k; ++t) {
+                    f = Z[(size_t)t * k + i + 1];
+                    Z[(size_t)t * k + i + 1] = sn * Z[(size_t)t * k + i] + cs * f;
+                    Z[(size_t)t * k + i] = cs * Z[(size_t)t * k + i] - sn * f;
+                }
+            }
+            if (early) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+    return true;
+}
+
+// d/dT of e_1^T log(T) e_1 for T = V diag(lam) V^T: G = V (F o v v^T) V^T,
+// v = V^T e_1, F_ab the divided difference of log at (lam_a, lam_b) (1/lam_a
+// when they coincide).  gd[i] = G_ii; go[i] = 2 G_{i,i+1} (an off-diagonal
+// entry appears twice in T).  false if T is not positive definite.
+bool logm_e1_grad_host(int k, const std::vector<double>& al, const std::vector<double>& be,
+                       std::vector<double>& gd, std::vector<double>& go) {
+    std::vector<double> lam = al, Z;
+    if (!tridiag_eig(k, lam, be, Z)) return false;
+    for (int a = 0; a < k; ++a)
+        if (!(lam[a] > 0.0)) return false;
+    std::vector<double> v(k), L(k);
+    for (int a = 0; a < k; ++a) {
+        v[a] = Z[a];   // first row
+        L[a] = std::log(lam[a]);
+    }
+    std::vector<double> Fv((size_t)k * k);
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) {
+            const double gap = lam[a] - lam[b];
+            const double f = std::fabs(gap) > 1e-13 * std::fabs(lam[a]) ? (L[a] - L[b]) / gap
+                                                                        : 1.0 / lam[a];
+            Fv[(size_t)a * k + b] = f * v[a] * v[b];
+        }
+    gd.assign(k, 0.0);
+    go.assign(k > 0 ? k - 1 : 0, 0.0);
+    // G_rs = sum_ab Z_ra Fv_ab Z_sb, needed for s = r and s = r + 1
+    std::vector<double> H((size_t)k * k, 0.0);   // H = Fv Z^T: H_as = sum_b Fv_ab Z_sb
+    for (int a = 0; a < k; ++a)
+        for (int sI = 0; sI < k; ++sI) {
+            double acc = 0.0;
+            for (int b = 0; b < k; ++b) acc += Fv[(size_t)a * k + b] * Z[(size_t)sI * k + b];
+            H[(size_t)a * k + sI] = acc;
+        }
+    for (int r = 0; r < k; ++r) {
+        double g0 = 0.0, g1 = 0.0;
+        for (int a = 0; a < k; ++a) {
+            g0 += Z[(size_t)r * k + a] * H[(size_t)a * k + r];
+            if (r + 1 < k) g1 += Z[(size_t)r * k + a] * H[(size_t)a * k + r + 1];
+        }
+        gd[r] = g0;
+        if (r + 1 < k) go[r] = 2.0 * g1;
+    }
+    return true;
+}
+
+// Per-column coefficients of the sweep's vector updates (one per probe).
+struct ColCoef {
+    double v[kSnapStates];
+};
+
+// y_j = a_j y_j + b_j x1_j + c_j x2_j for N columns of length M (x1, x2
+// optional)
+__global__ void col_lin3(double* __restrict__ y, const double* __restrict__ x1,
+                         const double* __restrict__ x2, ColCoef a, ColCoef b, ColCoef cc,
+                         int64_t M) {
+    const int j = blockIdx.y;
+    const double aj = a.v[j], bj = b.v[j], cj = cc.v[j];
+    const int64_t o = (int64_t)j * M;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double v = aj * y[o + i];
+        if (x1) v = fma(bj, x1[o + i], v);
+        if (x2) v = fma(cj, x2[o + i], v);
+        y[o + i] = v;
+    }
+}
+
+// tr_out[theta] = (1/N) sum_j dGamma_j / dtheta, theta = log l_0 .. log
+// l_{d-1}, log s, log sigma.  Qa holds the residual history r_hat_i
+// ([k][N][M], overwritten with the Lanczos vectors' W-parts), shist the
+// (c_r,i, ||r_i||^2) history, alphas/betas/ps the probes' CG record.
+fkgp_status slq_logdet_grad(const OpCtx& c, const fkgp_hypers* hyp, int k, int N,
+                            const double* bh, double* Qa, const double* shist,
+                            const double* alphas, const double* betas, const PState* ps,
+                            double* tr_out, Scratch& sc, hipStream_t st) {
+    const fkgp_handle* h = c.h;
+    const int d = h->g.d;
+    const int64_t M = h->M;
+    const int64_t ldx = M + 2 * c.halo;
+    const double n = (double)h->n;
+    const double s2 = c.s2;
+    if (N > kSnapStates) {
+        set_error("too many probes for the Lanczos-estimate gradient");
+        return FKGP_EINVAL;
+    }
+    std::vector<double> ha((size_t)N * kMaxLanczos), hb((size_t)N * kMaxLanczos),
+        hs((size_t)k * N * 2);
+    std::vector<PState> hps(N);
+    FKGP_HIP(hipMemcpyAsync(ha.data(), alphas, sizeof(double) * ha.size(), hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipMemcpyAsync(hb.data(), betas, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipMemcpyAsync(hs.data(), shist, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipMemcpyAsync(hps.data(), ps, sizeof(PState) * N, hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipStreamSynchronize(st));
+    // tridiagonals, their log-quadrature gradients, Lanczos-vector scalars
+    std::vector<int> kk(N);
+    int K = 0;
+    std::vector<std::vector<double>> al(N), be(N), abar(N), bbar(N), Qc(N), qs(N);
+    for (int j = 0; j < N; ++j) {
+        kk[j] = std::min(k, std::min(hps[j].iters, kMaxLanczos));
+        K = std::max(K, kk[j]);
+        const double* a = &ha[(size_t)j * kMaxLanczos];
+        const double* b = &hb[(size_t)j * kMaxLanczos];
+        al[j].resize(kk[j]);
+        be[j].resize(kk[j] > 0 ? kk[j] - 1 : 0);
+        for (int i = 0; i < kk[j]; ++i) {
+            al[j][i] = 1.0 / a[i] + (i > 0 ? b[i - 1] / a[i - 1] : 0.0);
+            if (i + 1 < kk[j]) be[j][i] = std::sqrt(b[i]) / a[i];
+        }
+        if (!logm_e1_grad_host(kk[j], al[j], be[j], abar[j], bbar[j])) {
+            set_error("Lanczos tridiagonal not positive definite in the log-determinant gradient");
+            return FKGP_EDEVICE;
+        }
+        Qc[j].resize(kk[j]);
+        qs[j].resize(kk[j]);
+        for (int i = 0; i < kk[j]; ++i) {
+            const double sgn = (i % 2 == 0) ? 1.0 : -1.0;
+            const double cr = hs[((size_t)i * N + j) * 2], rho = hs[((size_t)i * N + j) * 2 + 1];
+            qs[j][i] = sgn / std::sqrt(rho);
+            Qc[j][i] = sgn * cr / std::sqrt(rho);
+        }
+    }
+    for (int t = 0; t < d + 2; ++t) tr_out[t] = 0.0;
+    if (K == 0) return FKGP_OK;
+    const dim3 gcol((unsigned)std::min<int64_t>((M + 255) / 256, 1024), N);
+    ColCoef zero{}, one{};
+    for (int j = 0; j < N; ++j) one.v[j] = 1.0;
+    auto lin3 = [&](double* y, const double* x1, const double* x2, const ColCoef& a,
+                    const ColCoef& b, const ColCoef& cc) -> fkgp_status {
+        col_lin3<<<gcol, 256, 0, st>>>(y, x1, x2, a, b, cc, M);
+        FKGP_HIP(hipGetLastError());
+        return FKGP_OK;
+    };
+    double *WQ, *pad, *r, *u, *Wu, *KW, *D, *dotp, *dots;
+    FKGP_HIP(sc.get(&WQ, (size_t)K * N * M));
+    FKGP_HIP(sc.get(&pad, (size_t)ldx * N));
+    FKGP_HIP(sc.get(&r, (size_t)N * M));
+    FKGP_HIP(sc.get(&u, (size_t)N * M));
+    FKGP_HIP(sc.get(&Wu, (size_t)N * M));
+    FKGP_HIP(sc.get(&KW, (size_t)N * M));
+    FKGP_HIP(sc.get(&D, (size_t)N * M));
+    FKGP_HIP(sc.get(&dotp, (size_t)vec_blocks(M) * N));
+    FKGP_HIP(sc.get(&dots, (size_t)N));
+    double* qb[3];
+    for (int t = 0; t < 3; ++t) {
+        FKGP_HIP(sc.get(&qb[t], (size_t)N * M));
+        FKGP_HIP(hipMemsetAsync(qb[t], 0, sizeof(double) * N * M, st));
+    }
+    FKGP_HIP(hipMemsetAsync(pad, 0, sizeof(double) * ldx * N, st));
+    std::vector<double> hdot(N);
+    auto dots_host = [&](const double* A, const double* B) -> fkgp_status {
+        fkgp_status rs = dots_dev(A, B, M, N, dotp, dots, st);
+        if (rs != FKGP_OK) return rs;
+        FKGP_HIP(hipMemcpyAsync(hdot.data(), dots, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+        FKGP_HIP(hipStreamSynchronize(st));
+        return FKGP_OK;
+    };
+    // W^T x for pairs (xa, xc): W^T W xa + xc b_hat
+    auto wt = [&](const double* xa, const ColCoef& xc, double* out) -> fkgp_status {
+        FKGP_HIP(hipMemcpy2DAsync(pad + c.halo, sizeof(double) * ldx, xa, sizeof(double) * M,
+                                  sizeof(double) * M, N, hipMemcpyDeviceToDevice, st));
+        fkgp_status rs = spmv_dia_any(h->g, h->dt, FKGP_F64, h->A, h->bmask, pad, out, N,
+                                      c.halo, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+        return lin3(out, bh, nullptr, one, xc, zero);
+    };
+    // Lanczos vectors q_i = (qs r_hat_i, Qc_i), W^T q_i and s_i = b_hat . a_i + Qc_i n
+    std::vector<std::vector<double>> sv(K, std::vector<double>(N, 0.0));
+    for (int i = 0; i < K; ++i) {
+        ColCoef sc_q{}, qc{};
+        for (int j = 0; j < N; ++j) {
+            sc_q.v[j] = i < kk[j] ? qs[j][i] : 0.0;
+            qc.v[j] = i < kk[j] ? Qc[j][i] : 0.0;
+        }
+        double* Qi = Qa + (size_t)i * N * M;
+        fkgp_status rs = lin3(Qi, nullptr, nullptr, sc_q, zero, zero);
+        if (rs != FKGP_OK) return rs;
+        rs = wt(Qi, qc, WQ + (size_t)i * N * M);
+        if (rs != FKGP_OK) return rs;
+        rs = dots_host(bh, Qi);
+        if (rs != FKGP_OK) return rs;
+        for (int j = 0; j < N; ++j) sv[i][j] = hdot[j] + qc.v[j] * n;
+    }
+    // derivative spectra: theta < d: d/dlog l_theta; theta = d: K_G itself
+    std::vector<Spectra> dsp(d);
+    for (int th = 0; th < d; ++th) {
+        fkgp_status rs = make_spectra(h, hyp, FKGP_F64, th, dsp[th], sc);
+        if (rs != FKGP_OK) return rs;
+    }
+    std::vector<std::vector<double>> g(N, std::vector<double>(d + 2, 0.0));
+    std::vector<double> qbc_next(N, 0.0), qbc_cur(N, 0.0), qbc_prev(N, 0.0);
+    for (int i = K - 1; i >= 0; --i) {
+        double* QBn = qb[(i + 1) % 3];   // qbar[i + 1], final
+        double* QBc = qb[i % 3];         // qbar[i]
+        double* QBp = qb[(i + 2) % 3];   // qbar[i - 1]
+        const double* Qi = Qa + (size_t)i * N * M;
+        const double* WQi = WQ + (size_t)i * N * M;
+        // r = qbar[i+1] / be_i + bbar_i q_{i+1} (columns with i + 1 < kk)
+        ColCoef ca{}, cb{}, rc{};
+        bool any_next = false;
+        for (int j = 0; j < N; ++j) any_next |= i + 1 < kk[j];
+        if (any_next) {
+            fkgp_status rs = dots_host(QBn, WQ + (size_t)(i + 1) * N * M);
+            if (rs != FKGP_OK) return rs;
+            for (int j = 0; j < N; ++j) {
+                if (!(i + 1 < kk[j])) continue;
+                const double in1 = hdot[j] + qbc_next[j] * sv[i + 1][j];
+                bbar[j][i] -= in1 / be[j][i];
+                ca.v[j] = 1.0 / be[j][i];
+                cb.v[j] = bbar[j][i];
+                rc.v[j] = qbc_next[j] / be[j][i] + bbar[j][i] * Qc[j][i + 1];
+            }
+        }
+        FKGP_HIP(hipMemsetAsync(r, 0, sizeof(double) * N * M, st));
+        fkgp_status rs = lin3(r, QBn, Qa + (size_t)(i + 1 < K ? i + 1 : i) * N * M, zero, ca,
+                              any_next ? cb : zero);
+        if (rs != FKGP_OK) return rs;
+        // abar_i -= <r, q_i>; bbar_{i-1} -= <r, q_{i-1}>
+        rs = dots_host(r, WQi);
+        if (rs != FKGP_OK) return rs;
+        for (int j = 0; j < N; ++j)
+            if (i < kk[j]) abar[j][i] -= hdot[j] + rc.v[j] * sv[i][j];
+        if (i > 0) {
+            rs = dots_host(r, WQ + (size_t)(i - 1) * N * M);
+            if (rs != FKGP_OK) return rs;
+            for (int j = 0; j < N; ++j)
+                if (i < kk[j]) bbar[j][i - 1] -= hdot[j] + rc.v[j] * sv[i - 1][j];
+        }
+        // u = r + abar_i q_i
+        ColCoef ab{}, uc{}, mal{}, mbe{};
+        for (int j = 0; j < N; ++j) {
+            if (!(i < kk[j])) continue;
+            ab.v[j] = abar[j][i];
+            uc.v[j] = rc.v[j] + abar[j][i] * Qc[j][i];
+            mal.v[j] = -al[j][i];
+            if (i > 0) mbe.v[j] = -be[j][i - 1];
+        }
+        FKGP_HIP(hipMemcpyAsync(u, r, sizeof(double) * N * M, hipMemcpyDeviceToDevice, st));
+        rs = lin3(u, Qi, nullptr, one, ab, zero);
+        if (rs != FKGP_OK) return rs;
+        // qbar_i += -al_i r + abar_i A q_i, A q = (K_G W^T q + s2 a, s2 c)
+        rs = kg_apply(h->g, c.sp64, FKGP_F64, WQi, KW, N, c.so, nullptr, 0.0, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+        ColCoef abs2{};
+        for (int j = 0; j < N; ++j) abs2.v[j] = ab.v[j] * s2;
+        rs = lin3(QBc, r, KW, one, mal, ab);
+        if (rs != FKGP_OK) return rs;
+        rs = lin3(QBc, Qi, nullptr, one, abs2, zero);
+        if (rs != FKGP_OK) return rs;
+        for (int j = 0; j < N; ++j)
+            if (i < kk[j]) qbc_cur[j] += -al[j][i] * rc.v[j] + ab.v[j] * s2 * Qc[j][i];
+        // qbar_{i-1} -= be_{i-1} r
+        if (i > 0) {
+            rs = lin3(QBp, r, nullptr, one, mbe, zero);
+            if (rs != FKGP_OK) return rs;
+            for (int j = 0; j < N; ++j)
+                if (i < kk[j]) qbc_prev[j] += mbe.v[j] * rc.v[j];
+        }
+        // gradient terms: ubar^T dA q_i = (W^T u)^T dK (W^T q_i) for log l and
+        // log s, 2 s2 <u, q_i> for log sigma
+        rs = wt(u, uc, Wu);
+        if (rs != FKGP_OK) return rs;
+        for (int th = 0; th <= d; ++th) {
+            const double* DK = KW;   // d/dlog s: K_G itself
+            if (th < d) {
+                rs = kg_apply(h->g, dsp[th], FKGP_F64, WQi, D, N, c.so, nullptr, 0.0, nullptr, st);
+                if (rs != FKGP_OK) return rs;
+                DK = D;
+            }
+            rs = dots_host(Wu, DK);
+            if (rs != FKGP_OK) return rs;
+            for (int j = 0; j < N; ++j)
+                if (i < kk[j]) g[j][th] += hdot[j];
+        }
+        rs = dots_host(u, WQi);
+        if (rs != FKGP_OK) return rs;
+        for (int j = 0; j < N; ++j)
+            if (i < kk[j]) g[j][d + 1] += 2.0 * s2 * (hdot[j] + uc.v[j] * sv[i][j]);
+        // qbar_i += A u = (K_G W^T u + s2 u_a, s2 u_c)
+        rs = kg_apply(h->g, c.sp64, FKGP_F64, Wu, KW, N, c.so, u, s2, nullptr, st);
+        if (rs != FKGP_OK) return rs;
+        rs = lin3(QBc, KW, nullptr, one, one, zero);
+        if (rs != FKGP_OK) return rs;
+        for (int j = 0; j < N; ++j)
+            if (i < kk[j]) qbc_cur[j] += s2 * uc.v[j];
+        // rotate: qbar[i] becomes the next step's qbar[i + 1]
+        qbc_next = qbc_cur;
+        qbc_cur = qbc_prev;
+        qbc_prev.assign(N, 0.0);
+        FKGP_HIP(hipMemsetAsync(qb[(i + 1) % 3], 0, sizeof(double) * N * M, st));
+    }
+    for (int t = 0; t < d + 2; ++t) {
+        double acc = 0.0;
+        for (int j = 0; j < N; ++j) acc += n * g[j][t];
+        tr_out[t] = acc / N;
+    }
+    return FKGP_OK;
+}
+
 fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_mll_opts& o,
                      double* mll, double* grad, fkgp_mll_info* info, hipStream_t st) {
     Scratch sc(st);
@@ -2757,12 +3146,20 @@ fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_ml
         }
         if (sres != FKGP_OK) serr = last_error_copy();
     });
-    // probe solves (batched, or one probe at a time)
+    // probe solves (batched, or one probe at a time); the gradient of the
+    // Lanczos estimate itself (trace_mode 2) checkpoints the first
+    // lanczos_steps residuals of every probe
     int iters_max = 0;
     fkgp_status pres = FKGP_OK;
-    if (o.batched) {
+    const int kslq = std::min(o.lanczos_steps, kMaxLanczos);
+    double *rhist = nullptr, *shist = nullptr;
+    if (o.trace_mode == 2) {
+        FKGP_HIP(sc.get(&rhist, (size_t)kslq * N * M));
+        FKGP_HIP(sc.get(&shist, (size_t)kslq * N * 2));
+    }
+    if (o.batched || o.trace_mode == 2) {
         pres = probe_cg(c, V + M, N, n, o.tol, o.maxiter, wx + M, alphas, betas, ps, sc, st,
-                        iters_max);
+                        iters_max, nullptr, nullptr, rhist, shist, kslq);
     } else {
         for (int j = 0; j < N && (pres == FKGP_OK || pres == FKGP_ENOTCONV); ++j) {
             int it = 0;
@@ -2791,6 +3188,14 @@ fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_ml
         trx.resize(h->g.d + 2);
         rs = exact_traces(c, hyp, o.tol, o.maxiter, trx.data(), st);
         if (rs != FKGP_OK) return rs;
+    } else if (o.trace_mode == 2) {
+        // d Gamma / d theta in place of the trace estimates (the last one as
+        // the coefficient mll_post scales by 2 s2)
+        trx.resize(h->g.d + 2);
+        rs = slq_logdet_grad(c, hyp, kslq, N, V + M, rhist, shist, alphas, betas, ps, trx.data(),
+                             sc, st);
+        if (rs != FKGP_OK) return rs;
+        trx[h->g.d + 1] /= 2.0 * c.s2;
     }
     rs = mll_post(c, hyp, o, V, wx, alphas, betas, ps, mll, grad, sc, st, logdet, q,
                   trx.empty() ? nullptr : trx.data(), dq);
@@ -3689,8 +4094,9 @@ extern "C" fkgp_status fkgp_mll_and_grad(const fkgp_handle* h, const fkgp_hypers
             fkgp::set_error("lanczos_steps must be in [1, 64], tol >= 0, maxiter >= 1");
             return FKGP_EINVAL;
         }
-        if (o.trace_mode != 0 && o.trace_mode != 1) {
-            fkgp::set_error("trace_mode must be 0 (Hutchinson) or 1 (exact)");
+        if (o.trace_mode < 0 || o.trace_mode > 2) {
+            fkgp::set_error("trace_mode must be 0 (Hutchinson), 1 (exact) or 2 (gradient of "
+                            "the Lanczos estimate)");
             return FKGP_EINVAL;
         }
         if (o.trace_mode == 1 && h->M > 4096) {

@@ -300,9 +300,11 @@ struct Spectra {
     void* tw[3];        // twiddles exp(-2 pi i t / L), t < L/2, complex stats dtype
     void* scr[3];       // long lines: kLongWGs * L complex scratch, else null
     int lg1[3];         // four-step split of dim k (0: register order)
-    // dimensions of at most 128 nodes: the kernel's column c[j], j < m (stats
-    // dtype), applied as the dense Toeplitz factor instead of the line FFT;
-    // null for longer dimensions
+    // 3-D grids with m_0 <= 128 whose two inner dimensions form small slabs
+    // (m_1 <= 128, m_2 <= 64, m_1 m_2 <= 4096): the kernel's columns c[j],
+    // j < m_k, of all three dimensions (dtype of the spectra), applied as
+    // dense Toeplitz factors (a slab pass for dimensions 1 and 2, a column
+    // pass for dimension 0); null otherwise
     void* col[3];
 };
 
@@ -315,9 +317,10 @@ fkgp_status build_spectrum(const GridDev& g, int k, double ell, bool deriv, int 
                            fkgp_dtype dt, void* lam, int log2L, int lg1, void* scr,
                            hipStream_t s);
 fkgp_status build_twiddles(int log2L, fkgp_dtype dt, void* tw, hipStream_t s);
-// Dimensions applied by the dense Toeplitz product (m <= 128) and the column
-// it needs: c[j] = k(j h / l) (or its derivative in log l), j < m.
-bool toeplitz_direct(int m);
+// Grids whose dimensions 1 and 2 are applied by the dense Toeplitz slab pass,
+// and the column it needs: c[j] = k(j h / l) (or its derivative in log l),
+// j < m_k.
+bool toeplitz_slab_applies(const GridDev& g);
 fkgp_status build_toeplitz_col(const GridDev& g, int k, double ell, bool deriv, int kind,
                                fkgp_dtype dt, void* col, hipStream_t s);
 

@@ -167,163 +167,240 @@ __device__ __forceinline__ void line_store(const cplx<T> (&z)[R], int e_lane, bo
     }
 }
 
-// Short dimensions: the dense product with the symmetric Toeplitz factor
-// itself, y[.., i, ..] = scale * sum_{j < m} c[|i - j|] x[.., j, ..]
-// (+ add_coef * addv), c the kernel's column.  The same linear map as the
-// circulant-embedded convolution (Sec. 2.3: each factor of K_G is the
-// Toeplitz matrix of the kernel on an equispaced line), exact up to
-// rounding, no truncation of the band.  For m <= 128 nodes it costs m FMAs
-// per node, ~2 us of FP64 VALU for the 300,000 nodes of a 100 x 100 x 30
-// grid, where a line FFT pass is bound by the latency of its exchange
-// chain.
+// The two innermost dimensions of a 3-D grid in one pass, by the dense
+// products with their symmetric Toeplitz factors (Sec. 2.3: each factor of
+// K_G is the Toeplitz matrix of the kernel on an equispaced line):
+// y[o, :, :] = T_1 x[o, :, :] T_2, exact up to rounding (no truncation of
+// the band), for slabs of m_1 x m_2 <= 4096 nodes with m_1 <= 128, m_2 <= 64.
+// Where the line FFT spends its time in the latency of each pass's exchange
+// chain (two launches and two round trips through memory), this is one
+// launch at m_1 + m_2 FMAs per node.
 //
-// A workgroup owns kToepC = 256 / RG whole lines (so passes may run in
-// place) and all their m nodes: the tile [m][C] is staged in LDS with
-// coalesced loads (contiguous lines as one linear range; strided lines as
-// rows of C adjacent lines), each thread forms 8 output rows of one line
-// from register blocks of 8 x 8 products (8 tile reads and 15 reads of the
-// column per 64 FMAs), and the results go back through the tile with the
-// same coalesced mapping.  The store takes the epilogue of the line passes,
-// including the fused CG direction update (CgStep2).
-constexpr int kToepR = 8;          // output rows per thread and column block
-constexpr int kToepMaxM = 128;     // longest dimension applied this way
+// Workgroup (slab o, part p): the slab (contiguous in memory) is loaded into
+// LDS once, T_2 is applied along every row (all rows: the next product
+// needs them), then T_1 along the columns for this part's output rows, which
+// are written straight out (parts read the whole slab and write disjoint
+// rows, so an in-place call takes one part).  Both products use register
+// blocks of 8 x 8: per block, 8 reads of the data, 15 of the column
+// c[|i - j|] (held in LDS padded with zeros beyond the band) and 64 FMAs.
+// No divisions in the index arithmetic except per-thread setup.
+constexpr int kSlabR = 8;
+constexpr int kSlabMaxM1 = 128, kSlabMaxM2 = 64, kSlabMaxNodes = 4096;
 
-__host__ __device__ constexpr int toep_row_groups(int m) {
-    return m > 64 ? 16 : (m > 32 ? 8 : 4);
+__host__ __device__ inline int slab_pad(int m) { return (m + kSlabR - 1) / kSlabR * kSlabR; }
+
+// Rows of the column product per part: 8-row blocks times the column count
+// that fills 256 threads.
+__host__ __device__ inline int slab_part_rows(int m2) {
+    const int blocks = 256 / m2 > 0 ? 256 / m2 : 1;
+    return blocks * kSlabR;
 }
 
-template <class T, int RG>
-__global__ __launch_bounds__(256) void toeplitz_pass(const T* in, T* out, LineGeom lg,
-                                                     const T* __restrict__ col, T scale,
-                                                     const T* __restrict__ addv, T add_coef,
-                                                     const int* __restrict__ skip, CgStep2 fz) {
-    constexpr int R = kToepR;
-    constexpr int C = 256 / RG;            // lines per workgroup
-    constexpr int CS = C + 1;              // padded tile row (LDS banks)
-    constexpr int MP = RG * R;             // rows covered (>= m)
-    __shared__ T tile[MP * CS];
-    __shared__ T cxs[2 * MP + 2 * R];
-    __shared__ double red[256];
+// register-blocked Toeplitz product along one direction of an LDS tile:
+// out(i0 + r) = sum_j c[|i0 + r - j|] v(j), r < R, with v(j) = V[j * sv] and
+// cx[t] = c[|t - R - (m - 1)|] (zero outside the band).
+template <class T>
+__device__ __forceinline__ void slab_block(const T* V, int sv, const T* cx, int m, int i0,
+                                           T (&acc)[kSlabR]) {
+    constexpr int R = kSlabR;
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = T(0);
+    const int mp = slab_pad(m);
+    for (int jb = 0; jb < mp; jb += R) {
+        T xv[R], cw[2 * R - 1];
+#pragma unroll
+        for (int q = 0; q < R; ++q) xv[q] = V[(jb + q) * sv];
+        const int cb = i0 - jb + m;   // cx[cb + t] = c[|i - j|], t = r - q + R - 1
+#pragma unroll
+        for (int t = 0; t < 2 * R - 1; ++t) cw[t] = cx[cb + t];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[r] = fma(cw[r - q + R - 1], xv[q], acc[r]);
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void toeplitz_slab(const T* in, T* out, int m1, int m2,
+                                                     int parts, int prow,
+                                                     const T* __restrict__ col1,
+                                                     const T* __restrict__ col2,
+                                                     const int* __restrict__ skip) {
+    constexpr int R = kSlabR;
+    extern __shared__ unsigned char slab_lds[];
     if (skip && *skip) return;
-    const int m = lg.m_line;
     const int tid = threadIdx.x;
-    const int64_t l0 = (int64_t)xcd_block() * C;
-    const int nc = (int)min<int64_t>((int64_t)C, lg.nlines - l0);
-    const bool contig = lg.S == 1;
-    // Each thread moves the tile entries idx = tid + 256 e, e < kE (the tile
-    // holds MP * C = 8 * 256 entries): node i of line c at address ad, with
-    // consecutive idx at consecutive addresses (contiguous lines: one linear
-    // range; strided lines: rows of nc adjacent lines).  Every global load
-    // of the pass (the tile, the column, and the operands of the epilogue)
-    // is issued here, before any is used, so the workgroup waits for memory
-    // once.
-    constexpr int kE = MP * C / 256;
-    const int nt = nc * m;
-    int ti[kE];
-    int64_t ad[kE];
+    const int mp1 = slab_pad(m1), mp2 = slab_pad(m2);
+    const int sx = mp2 + 1;                      // row stride of X and Y (odd: LDS banks)
+    T* X = reinterpret_cast<T*>(slab_lds);       // [mp1][sx], zero padded
+    T* Y = X + mp1 * sx;                         // [mp1][sx]
+    T* c1x = Y + mp1 * sx;                       // [2 mp1 + 2R]
+    T* c2x = c1x + 2 * mp1 + 2 * R;              // [2 mp2 + 2R]
+    const unsigned b = xcd_block();
+    const int64_t slab = b / (unsigned)parts;
+    const int part = (int)(b - slab * (unsigned)parts);
+    const int ns = m1 * m2;
+    const T* src = in + slab * ns;
+    T* dst = out + slab * ns;
+    // load the slab: element idx = tid + 256 e sits at (idx / m2, idx % m2),
+    // stepped without per-element division
+    {
+        constexpr int kMaxE = kSlabMaxNodes / 256;
+        T v[kMaxE];
 #pragma unroll
-    for (int e = 0; e < kE; ++e) {
-        const int idx = tid + 256 * e;
-        const int i = contig ? idx % m : idx / nc;
-        const int c = contig ? idx / m : idx % nc;
-        ti[e] = idx < nt ? i * CS + c : -1;
-        ad[e] = contig ? l0 * (int64_t)m + idx : line_addr(lg, l0 + c, i);
-    }
-    T v[kE], av[kE];
-    double sv[kE], zv[kE], pv[kE], rv[kE];
-    T uv[kE];
-#pragma unroll
-    for (int e = 0; e < kE; ++e) v[e] = ti[e] >= 0 ? in[ad[e]] : T(0);
-    if (addv) {
-#pragma unroll
-        for (int e = 0; e < kE; ++e) av[e] = ti[e] >= 0 ? addv[ad[e]] : T(0);
-    }
-    if (fz.s) {
-        const T* uu = static_cast<const T*>(fz.u);
-#pragma unroll
-        for (int e = 0; e < kE; ++e) {
-            const bool ok = ti[e] >= 0;
-            sv[e] = ok ? fz.s[ad[e]] : 0.0;
-            zv[e] = ok ? fz.z[ad[e]] : 0.0;
-            uv[e] = ok ? uu[ad[e]] : T(0);
+        for (int e = 0; e < kMaxE; ++e) {
+            const int idx = tid + 256 * e;
+            v[e] = idx < ns ? src[idx] : T(0);
         }
-        if (fz.p) {
+        for (int t = tid; t < mp1 * sx; t += 256) {   // zero everything first
+            X[t] = T(0);
+            Y[t] = T(0);
+        }
+        for (int t = tid; t < 2 * mp1 + 2 * R; t += 256) {
+            const int dl = t - R - (m1 - 1);
+            const int a = dl < 0 ? -dl : dl;
+            c1x[t] = a < m1 ? col1[a] : T(0);
+        }
+        for (int t = tid; t < 2 * mp2 + 2 * R; t += 256) {
+            const int dl = t - R - (m2 - 1);
+            const int a = dl < 0 ? -dl : dl;
+            c2x[t] = a < m2 ? col2[a] : T(0);
+        }
+        __syncthreads();
+        const int q256 = 256 / m2, r256 = 256 - q256 * m2;
+        int row = tid / m2, cl = tid - (tid / m2) * m2;
 #pragma unroll
-            for (int e = 0; e < kE; ++e) {
-                const bool ok = ti[e] >= 0;
-                pv[e] = ok ? fz.p[ad[e]] : 0.0;
-                rv[e] = ok ? fz.r[ad[e]] : 0.0;
+        for (int e = 0; e < kMaxE; ++e) {
+            if (tid + 256 * e < ns) X[row * sx + cl] = v[e];
+            row += q256;
+            cl += r256;
+            if (cl >= m2) {
+                cl -= m2;
+                ++row;
             }
         }
     }
-    // c[|t - R - (m - 1)|] inside the band, zero outside (padded rows/lines)
-    for (int t = tid; t < 2 * MP + 2 * R; t += 256) {
-        const int dl = t - R - (m - 1);
-        const int a = dl < 0 ? -dl : dl;
-        cxs[t] = a < m ? col[a] : T(0);
-    }
-    // zero padding (rows >= m, lines >= nc): disjoint from the data slots
-    for (int t = tid; t < MP * CS; t += 256) {
-        const int i = t / CS, c = t - (t / CS) * CS;
-        if (i >= m || c >= nc) tile[t] = T(0);
-    }
-#pragma unroll
-    for (int e = 0; e < kE; ++e)
-        if (ti[e] >= 0) tile[ti[e]] = v[e];
     __syncthreads();
-    const int rg = tid / C, c = tid % C;
-    const int i0 = rg * R;
-    T acc[R];
+    // T_2 along the rows: task (row i, column block k), column blocks fastest
+    {
+        const int nb2 = mp2 / R;
+        const int ntask = m1 * nb2;
+        for (int task = tid; task < ntask; task += 256) {
+            const int i = task / nb2, k = task - (task / nb2) * nb2;
+            T acc[R];
+            slab_block<T>(X + i * sx, 1, c2x, m2, k * R, acc);
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = T(0);
-    if (i0 < m) {
-        for (int jb = 0; jb < m; jb += R) {
-            T xv[R], cw[2 * R - 1];
-#pragma unroll
-            for (int q = 0; q < R; ++q) xv[q] = tile[(jb + q) * CS + c];
-            // cxs[cb + t] = c[|i - j|] for i = i0 + r, j = jb + q, t = r - q + R - 1
-            const int cb = i0 - jb + m;
-#pragma unroll
-            for (int t = 0; t < 2 * R - 1; ++t) cw[t] = cxs[cb + t];
+            for (int r = 0; r < R; ++r) Y[i * sx + k * R + r] = acc[r];
+        }
+    }
+    __syncthreads();
+    // T_1 along the columns for this part's prow rows: task (row block,
+    // column), columns fastest (consecutive lanes read consecutive Y entries
+    // and write consecutive outputs)
+    {
+        const int r_lo = part * prow;
+        const int r_hi = min(m1, r_lo + prow);
+        const int nbr = (r_hi - r_lo + R - 1) / R;
+        const int ntask = nbr * m2;
+        for (int task = tid; task < ntask; task += 256) {
+            const int kb = task / m2, c = task - (task / m2) * m2;
+            const int i0 = r_lo + kb * R;
+            T acc[R];
+            slab_block<T>(Y + c, sx, c1x, m1, i0, acc);
 #pragma unroll
             for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int q = 0; q < R; ++q) acc[r] = fma(cw[r - q + R - 1], xv[q], acc[r]);
+                if (i0 + r < r_hi) dst[(i0 + r) * m2 + c] = acc[r];
         }
     }
-    __syncthreads();
+}
+
+// The outermost dimension (stride S = M / m_0 per vector, m_0 <= 128) by
+// the dense product with its Toeplitz factor, the last pass of K_G after the
+// slab pass: y[i, c] = scale * sum_j c0[|i - j|] x[j, c] (+ add_coef *
+// addv), c < S, for k vectors.  A workgroup owns 16 adjacent columns c of
+// one vector and all m_0 rows (rows are 16 consecutive values: one 128-byte
+// chunk per row), thread (row block, column) forms 8 rows of one column by
+// the register-blocked product; the store takes the line passes' epilogue,
+// including the fused CG direction update (CgStep2).  Every global load of
+// the pass (tile, column, epilogue operands) is issued up front; all index
+// arithmetic is multiplications and additions.
+constexpr int kColsC = 16;
+
+template <class T>
+__global__ __launch_bounds__(256) void toeplitz_cols(const T* x, T* y, int m0, int64_t S,
+                                                     int64_t tiles_per_vec,
+                                                     const T* __restrict__ col, T scale,
+                                                     const T* __restrict__ addv, T add_coef,
+                                                     const int* __restrict__ skip, CgStep2 fz) {
+    constexpr int R = kSlabR, C = kColsC, CS = C + 1;
+    constexpr int MP = 16 * R;                     // rows covered (m_0 <= 128)
+    constexpr int kE = MP * C / 256;               // tile entries per thread (8)
+    __shared__ T tile[MP * CS];
+    __shared__ T cx[2 * MP + 2 * R];
+    __shared__ double red[256];
+    if (skip && *skip) return;
+    const int tid = threadIdx.x;
+    const unsigned b = xcd_block();
+    const int64_t vec = b / tiles_per_vec;
+    const int64_t c0 = (int64_t)(b - vec * tiles_per_vec) * C;
+    const int64_t base = vec * (int64_t)m0 * S + c0;
+    const int c = tid % C, rb = tid / C;           // column, row block / load row offset
+    const bool cok = c0 + c < S;
+    // entries (i = rb + 16 e, c): address base + i S + c
+    T v[kE], av[kE], uv[kE];
+    double sv[kE], zv[kE], pv[kE], rv[kE];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (i0 + r < m) tile[(i0 + r) * CS + c] = acc[r];
+    for (int e = 0; e < kE; ++e) {
+        const int i = rb + 16 * e;
+        v[e] = (cok && i < m0) ? x[base + (int64_t)i * S + c] : T(0);
+    }
+    // epilogue operands of this thread's outputs (rows rb * R + r)
+    const int i0 = rb * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = i0 + r;
+        const bool ok = cok && i < m0;
+        const int64_t a = base + (int64_t)i * S + c;
+        av[r] = (ok && addv) ? addv[a] : T(0);
+        if (fz.s) {
+            sv[r] = ok ? fz.s[a] : 0.0;
+            zv[r] = ok ? fz.z[a] : 0.0;
+            uv[r] = ok ? static_cast<const T*>(fz.u)[a] : T(0);
+            if (fz.p) {
+                pv[r] = ok ? fz.p[a] : 0.0;
+                rv[r] = ok ? fz.r[a] : 0.0;
+            }
+        }
+    }
+    for (int t = tid; t < 2 * MP + 2 * R; t += 256) {
+        const int dl = t - R - (m0 - 1);
+        const int a = dl < 0 ? -dl : dl;
+        cx[t] = a < m0 ? col[a] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < kE; ++e) tile[(rb + 16 * e) * CS + c] = v[e];   // zeros where absent
     __syncthreads();
+    T acc[R];
+    slab_block<T>(tile + c, CS, cx, m0, i0, acc);
     double part = 0.0;
+    const double beta = fz.s ? fz.st->beta : 0.0;
 #pragma unroll
-    for (int e = 0; e < kE; ++e) v[e] = ti[e] >= 0 ? scale * tile[ti[e]] : T(0);
-    if (addv) {
-#pragma unroll
-        for (int e = 0; e < kE; ++e) v[e] += add_coef * av[e];
-    }
-    if (fz.s) {
-        // CG direction update: s = u + beta s, z = v + beta z, p = r + beta p
-        const double beta = fz.st->beta;
-#pragma unroll
-        for (int e = 0; e < kE; ++e) {
-            if (ti[e] < 0) continue;
-            const double sn = fma(beta, sv[e], (double)uv[e]);
-            const double zn = fma(beta, zv[e], (double)v[e]);
-            fz.s[ad[e]] = sn;
-            fz.z[ad[e]] = zn;
+    for (int r = 0; r < R; ++r) {
+        const int i = i0 + r;
+        if (!cok || i >= m0) continue;
+        const int64_t a = base + (int64_t)i * S + c;
+        T w = scale * acc[r];
+        if (addv) w += add_coef * av[r];
+        if (fz.s) {
+            const double sn = fma(beta, sv[r], (double)uv[r]);
+            const double zn = fma(beta, zv[r], (double)w);
+            fz.s[a] = sn;
+            fz.z[a] = zn;
+            if (fz.p) fz.p[a] = fma(beta, pv[r], rv[r]);
             part = fma(sn, zn, part);
+        } else {
+            y[a] = w;
         }
-        if (fz.p) {
-#pragma unroll
-            for (int e = 0; e < kE; ++e)
-                if (ti[e] >= 0) fz.p[ad[e]] = fma(beta, pv[e], rv[e]);
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < kE; ++e)
-            if (ti[e] >= 0) out[ad[e]] = v[e];
     }
     if (fz.s) {
         red[tid] = part;
@@ -1475,39 +1552,55 @@ fkgp_status build_twiddles(int log2L, fkgp_dtype dt, void* tw, hipStream_t s) {
     return FKGP_OK;
 }
 
-// Off until it beats the line FFT on the solve's grids: on 100 x 100 x 30
-// the FFT passes take 12.6 / 12.6 / 6.2 us per iteration and these 17.0
-// (dimension 0, with the fused update) / 10.0 / 7.2 us.
-constexpr bool kToepEnabled = false;
-
-bool toeplitz_direct(int m) { return kToepEnabled && m <= kToepMaxM; }
-
-int64_t toeplitz_blocks(int m, int64_t nlines) {
-    const int C = 256 / toep_row_groups(m);
-    return std::max<int64_t>(1, (nlines + C - 1) / C);
+bool toeplitz_slab_applies(const GridDev& g) {
+    return g.d == 3 && g.m[0] <= 16 * kSlabR && g.m[1] <= kSlabMaxM1 && g.m[2] <= kSlabMaxM2 &&
+           g.m[1] * g.m[2] <= kSlabMaxNodes;
 }
 
+static size_t slab_lds_bytes(int m1, int m2, size_t es) {
+    const int mp1 = slab_pad(m1), mp2 = slab_pad(m2);
+    return es * ((size_t)2 * mp1 * (mp2 + 1) + 2 * mp1 + 2 * mp2 + 4 * kSlabR);
+}
+
+int64_t toeplitz_cols_blocks(const GridDev& g, int k) {
+    const int64_t S = (int64_t)g.m[1] * g.m[2];
+    return (int64_t)k * ((S + kColsC - 1) / kColsC);
+}
+
+// the outermost dimension after the slab pass (in place: each workgroup
+// reads and writes only its own columns)
 template <class T>
-static fkgp_status launch_toeplitz(const T* in, T* out, const LineGeom& lg, const T* col,
-                                   T scale, const T* addv, T add_coef, const int* skip,
-                                   const CgStep2* fuse, hipStream_t s) {
+static fkgp_status launch_toeplitz_cols(const GridDev& g, const T* x, T* y, int k,
+                                        const T* col, T scale, const T* addv, T add_coef,
+                                        const int* skip, const CgStep2* fuse, hipStream_t s) {
     CgStep2 fz{};
     if (fuse) fz = *fuse;
-    const unsigned grid = (unsigned)toeplitz_blocks(lg.m_line, lg.nlines);
-    switch (toep_row_groups(lg.m_line)) {
-        case 16:
-            toeplitz_pass<T, 16><<<grid, 256, 0, s>>>(in, out, lg, col, scale, addv, add_coef,
-                                                      skip, fz);
-            break;
-        case 8:
-            toeplitz_pass<T, 8><<<grid, 256, 0, s>>>(in, out, lg, col, scale, addv, add_coef,
-                                                     skip, fz);
-            break;
-        default:
-            toeplitz_pass<T, 4><<<grid, 256, 0, s>>>(in, out, lg, col, scale, addv, add_coef,
-                                                     skip, fz);
-            break;
-    }
+    const int64_t S = (int64_t)g.m[1] * g.m[2];
+    const int64_t tpv = (S + kColsC - 1) / kColsC;
+    const int64_t grid = (int64_t)k * tpv;
+    if (grid <= 0) return FKGP_OK;
+    toeplitz_cols<T><<<(unsigned)grid, 256, 0, s>>>(x, y, g.m[0], S, tpv, col, scale, addv,
+                                                    add_coef, skip, fz);
+    FKGP_HIP(hipGetLastError());
+    return FKGP_OK;
+}
+
+// y[o] = T_1 x[o] T_2 for the nslab = k * m_0 slabs of k vectors
+template <class T>
+static fkgp_status launch_toeplitz_slab(const GridDev& g, const T* x, T* y, int64_t nslab,
+                                        const T* col1, const T* col2, const int* skip,
+                                        hipStream_t s) {
+    const int m1 = g.m[1], m2 = g.m[2];
+    const int prow = x == y ? slab_pad(m1) : slab_part_rows(m2);
+    const int parts = (m1 + prow - 1) / prow;
+    const size_t lds = slab_lds_bytes(m1, m2, sizeof(T));
+    const int64_t grid = nslab * parts;
+    if (grid <= 0) return FKGP_OK;
+    if (lds > 64 * 1024)
+        FKGP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&toeplitz_slab<T>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    toeplitz_slab<T><<<(unsigned)grid, 256, lds, s>>>(x, y, m1, m2, parts, prow, col1, col2,
+                                                      skip);
     FKGP_HIP(hipGetLastError());
     return FKGP_OK;
 }
@@ -1538,7 +1631,17 @@ static fkgp_status kg_apply_t(const GridDev& g, const Spectra& sp, const T* x, T
                               hipStream_t s) {
     int64_t M = 1;
     for (int i = 0; i < g.d; ++i) M *= g.m[i];
-    // innermost dimension first (contiguous lines), then the strided ones
+    // innermost dimension first (contiguous lines), then the strided ones;
+    // for 3-D grids with small inner slabs the two innermost dimensions in
+    // one dense Toeplitz pass
+    if (sp.col[0] && sp.col[1] && sp.col[2]) {
+        fkgp_status st = launch_toeplitz_slab<T>(g, x, y, (int64_t)k * g.m[0],
+                                                 static_cast<const T*>(sp.col[1]),
+                                                 static_cast<const T*>(sp.col[2]), skip, s);
+        if (st != FKGP_OK) return st;
+        return launch_toeplitz_cols<T>(g, y, y, k, static_cast<const T*>(sp.col[0]), (T)scale,
+                                       addv, (T)add_coef, skip, nullptr, s);
+    }
     for (int pass = 0; pass < g.d; ++pass) {
         const int dim = g.d - 1 - pass;
         int64_t S = 1;
@@ -1546,16 +1649,10 @@ static fkgp_status kg_apply_t(const GridDev& g, const Spectra& sp, const T* x, T
         LineGeom lg{g.m[dim], S, (int64_t)k * M / g.m[dim]};
         const bool last = pass == g.d - 1;
         const T* src = pass == 0 ? x : y;
-        fkgp_status st =
-            sp.col[dim]
-                ? launch_toeplitz<T>(src, y, lg, static_cast<const T*>(sp.col[dim]),
-                                     last ? (T)scale : T(1), last ? addv : nullptr,
-                                     (T)add_coef, skip, nullptr, s)
-                : launch_line_conv<T>(sp.log2L[dim], sp.lg1[dim], src, y, lg,
-                                      static_cast<const T*>(sp.lam[dim]),
-                                      static_cast<const cplx<T>*>(sp.tw[dim]),
-                                      last ? (T)scale : T(1), last ? addv : nullptr,
-                                      (T)add_coef, skip, static_cast<cplx<T>*>(sp.scr[dim]), s);
+        fkgp_status st = launch_line_conv<T>(
+            sp.log2L[dim], sp.lg1[dim], src, y, lg, static_cast<const T*>(sp.lam[dim]),
+            static_cast<const cplx<T>*>(sp.tw[dim]), last ? (T)scale : T(1),
+            last ? addv : nullptr, (T)add_coef, skip, static_cast<cplx<T>*>(sp.scr[dim]), s);
         if (st != FKGP_OK) return st;
     }
     return FKGP_OK;
@@ -1568,9 +1665,15 @@ static fkgp_status kg_apply_fused_t(const GridDev& g, const Spectra& sp, const T
                                     hipStream_t s) {
     int64_t M = 1;
     for (int i = 0; i < g.d; ++i) M *= g.m[i];
-    // the last pass (dimension 0) fuses the update on the direct Toeplitz
-    // path and on the register FFT path
-    *fused = sp.col[0] != nullptr || sp.lg1[0] == 0;
+    if (sp.col[0] && sp.col[1] && sp.col[2]) {
+        *fused = true;
+        fkgp_status st = launch_toeplitz_slab<T>(g, x, y, g.m[0], static_cast<const T*>(sp.col[1]),
+                                                 static_cast<const T*>(sp.col[2]), skip, s);
+        if (st != FKGP_OK) return st;
+        return launch_toeplitz_cols<T>(g, y, y, 1, static_cast<const T*>(sp.col[0]), (T)scale,
+                                       addv, (T)add_coef, skip, &fuse, s);
+    }
+    *fused = sp.lg1[0] == 0;   // the last pass (dimension 0) on the register path
     for (int pass = 0; pass < g.d; ++pass) {
         const int dim = g.d - 1 - pass;
         int64_t S = 1;
@@ -1578,18 +1681,11 @@ static fkgp_status kg_apply_fused_t(const GridDev& g, const Spectra& sp, const T
         LineGeom lg{g.m[dim], S, M / g.m[dim]};
         const bool last = pass == g.d - 1;
         const T* src = pass == 0 ? x : y;
-        const CgStep2* fz = (last && *fused) ? &fuse : nullptr;
-        fkgp_status st =
-            sp.col[dim]
-                ? launch_toeplitz<T>(src, y, lg, static_cast<const T*>(sp.col[dim]),
-                                     last ? (T)scale : T(1), last ? addv : nullptr,
-                                     (T)add_coef, skip, fz, s)
-                : launch_line_conv<T>(sp.log2L[dim], sp.lg1[dim], src, y, lg,
-                                      static_cast<const T*>(sp.lam[dim]),
-                                      static_cast<const cplx<T>*>(sp.tw[dim]),
-                                      last ? (T)scale : T(1), last ? addv : nullptr,
-                                      (T)add_coef, skip, static_cast<cplx<T>*>(sp.scr[dim]), s,
-                                      fz);
+        fkgp_status st = launch_line_conv<T>(
+            sp.log2L[dim], sp.lg1[dim], src, y, lg, static_cast<const T*>(sp.lam[dim]),
+            static_cast<const cplx<T>*>(sp.tw[dim]), last ? (T)scale : T(1),
+            last ? addv : nullptr, (T)add_coef, skip, static_cast<cplx<T>*>(sp.scr[dim]), s,
+            (last && *fused) ? &fuse : nullptr);
         if (st != FKGP_OK) return st;
     }
     return FKGP_OK;
@@ -1614,7 +1710,7 @@ int64_t kg_last_pass_blocks(const GridDev& g) {
     for (int i = 0; i < g.d; ++i) M *= g.m[i];
     LineGeom lg{g.m[0], M / g.m[0], M / g.m[0]};
     return std::max<int64_t>(line_direct_blocks(circulant_log2(g.m[0]), lg),
-                             toeplitz_blocks(g.m[0], M / g.m[0]));
+                             toeplitz_cols_blocks(g, 1));
 }
 
 fkgp_status kg_apply(const GridDev& g, const Spectra& sp, fkgp_dtype dt, const void* x, void* y,
