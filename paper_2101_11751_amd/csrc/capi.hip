@@ -3210,24 +3210,72 @@ fkgp_status mll_impl(const fkgp_handle* h, const fkgp_hypers* hyp, const fkgp_ml
     return (sres == FKGP_ENOTCONV || pres == FKGP_ENOTCONV) ? FKGP_ENOTCONV : FKGP_OK;
 }
 
-// Work items of a batch for NR right-hand sides per item (device arrays in
-// `sc`): each problem's right-hand sides in groups of NR, each group with its
-// own vectors and, for four-step lines, its own L-point scratch.
+// Work items of a batch (device arrays in `sc`): each problem's right-hand
+// sides in groups of at most NR, each group with its own vectors and, for
+// four-step lines, its own L-point scratch.  One workgroup runs one item to
+// convergence, so the batch takes at least as long as its longest item and
+// at least its total work over the items that run at once (`slots`).  The
+// items are sized and ordered for both (longest processing time first):
+//  * cost of an item = iterations x M log2 M x (1 + right-hand sides): the
+//    stored matrix is read once per iteration for all of the item's
+//    right-hand sides, the rest scales with their number; the iterations are
+//    those of the previous evaluation of the same batch shape when known
+//    (`iters`, else equal for all problems);
+//  * a problem whose item would still run after the batch's average load per
+//    slot is reached gets smaller groups (down to one right-hand side), so
+//    its work spreads over more workgroups;
+//  * the items are launched in decreasing cost: workgroups are dispatched in
+//    index order, so the long items start first and the short ones fill in.
 fkgp_status build_batch_items(const std::vector<BatchProb>& probs, const std::vector<int>& nrhs,
-                              const std::vector<int>& long_L, int NR, Scratch& sc,
+                              const std::vector<int>& long_L, int NR, int slots,
+                              const std::vector<int>* iters, Scratch& sc,
                               BatchItem** items_dev, int& nitems) {
-    std::vector<BatchItem> items;
-    for (size_t p = 0; p < probs.size(); ++p) {
+    const size_t np = probs.size();
+    std::vector<double> w(np);   // cost of one iteration of one right-hand side
+    for (size_t p = 0; p < np; ++p) {
+        const double M = (double)probs[p].M;
+        const double it = (iters && p < iters->size() && (*iters)[p] > 0) ? (*iters)[p] : 1.0;
+        w[p] = it * M * std::log2(M + 2.0);
+    }
+    auto item_cost = [&](size_t p, int nr) { return w[p] * (1.0 + nr); };
+    std::vector<int> g(np, NR);   // group size per problem
+    for (int pass = 0; pass < 2; ++pass) {
+        double total = 0.0, longest1 = 0.0;
+        for (size_t p = 0; p < np; ++p) {
+            const int nit = (nrhs[p] + g[p] - 1) / g[p];
+            total += nit * item_cost(p, g[p]);
+            longest1 = std::max(longest1, item_cost(p, 1));
+        }
+        const double target = std::max(total / std::max(1, slots), longest1);
+        for (size_t p = 0; p < np; ++p) {
+            int nr = NR;
+            while (nr > 1 && item_cost(p, std::min(nr, nrhs[p])) > target) nr /= 2;
+            g[p] = std::max(1, nr);
+        }
+    }
+    struct Pending {
+        BatchItem it;
+        double cost;
+    };
+    std::vector<Pending> pend;
+    for (size_t p = 0; p < np; ++p) {
         const size_t wd = batch_work_doubles(probs[p].M, probs[p].halo, NR);
-        for (int r0 = 0; r0 < nrhs[p]; r0 += NR) {
+        for (int r0 = 0; r0 < nrhs[p]; r0 += g[p]) {
             double* work = nullptr;
             FKGP_HIP(sc.get(&work, wd));
             double* yscr = nullptr;
             if (long_L[p] > 0) FKGP_HIP(sc.get(&yscr, (size_t)2 * long_L[p]));
-            items.push_back(BatchItem{(int)p, r0, std::min(NR, nrhs[p] - r0), work,
-                                      reinterpret_cast<cplx<double>*>(yscr)});
+            const int nr = std::min(g[p], nrhs[p] - r0);
+            pend.push_back(Pending{BatchItem{(int)p, r0, nr, work,
+                                             reinterpret_cast<cplx<double>*>(yscr)},
+                                   item_cost(p, nr)});
         }
     }
+    std::stable_sort(pend.begin(), pend.end(),
+                     [](const Pending& x, const Pending& y) { return x.cost > y.cost; });
+    std::vector<BatchItem> items;
+    items.reserve(pend.size());
+    for (const Pending& q : pend) items.push_back(q.it);
     nitems = (int)items.size();
     FKGP_HIP(sc.get(items_dev, items.size()));
     FKGP_HIP(hipMemcpyAsync(*items_dev, items.data(), sizeof(BatchItem) * items.size(),
@@ -3250,6 +3298,8 @@ struct BatchTile {
 };
 std::mutex g_tune_mu;
 std::map<std::string, BatchTile> g_tune_cache;
+// iterations of each problem at the last evaluation of a batch shape
+std::map<std::string, std::vector<int>> g_iter_cache;
 constexpr BatchTile kTuneCandidates[6] = {{8, 256}, {4, 256}, {2, 256},
                                           {8, 512}, {4, 512}, {2, 512}};
 constexpr int kTuneIters = 16;
@@ -3352,6 +3402,19 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
     FKGP_HIP(sc.get(&probs_dev, np));
     FKGP_HIP(hipMemcpyAsync(probs_dev, probs.data(), sizeof(BatchProb) * np,
                             hipMemcpyHostToDevice, st));
+    // scheduling inputs: concurrent items per launch and the iterations of
+    // the previous evaluation of this batch shape
+    int ncu = 0;
+    FKGP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, 0));
+    const std::string shape = batch_shape_key(hs, np);
+    std::vector<int> iters_hint;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto f = g_iter_cache.find(shape);
+        if (f != g_iter_cache.end()) iters_hint = f->second;
+    }
+    const std::vector<int>* hint = iters_hint.empty() ? nullptr : &iters_hint;
+    auto slots_for = [&](int block) { return std::max(1, ncu) * (block == 256 ? 2 : 1); };
     // tile: forced, cached or tuned
     BatchTile tile{o.batch_rhs, o.batch_block};
     if (tile.nr == 0 || tile.block == 0) {
@@ -3380,7 +3443,8 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
                 BatchItem* it_dev = nullptr;
                 int nit = 0;
                 fkgp_status rs =
-                    build_batch_items(probs, nrhs_v, long_L, cand.nr, tsc, &it_dev, nit);
+                    build_batch_items(probs, nrhs_v, long_L, cand.nr, slots_for(cand.block),
+                                      hint, tsc, &it_dev, nit);
                 if (rs == FKGP_OK)   // warm-up launch (code object load), then the trial
                     rs = launch_batch_cg(probs_dev, it_dev, nit, lds, o.tol, 1, cand.nr,
                                          cand.block, st);
@@ -3414,12 +3478,14 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
     const int NR = tile.nr;
     BatchItem* items_dev = nullptr;
     int nitems = 0;
-    fkgp_status rs = build_batch_items(probs, nrhs_v, long_L, NR, sc, &items_dev, nitems);
+    fkgp_status rs = build_batch_items(probs, nrhs_v, long_L, NR, slots_for(tile.block), hint,
+                                       sc, &items_dev, nitems);
     if (rs != FKGP_OK) return rs;
     rs = launch_batch_cg(probs_dev, items_dev, nitems, lds, o.tol, o.maxiter, NR, tile.block, st);
     if (rs != FKGP_OK) return rs;
     FKGP_HIP(hipStreamSynchronize(st));
     fkgp_status res = FKGP_OK;
+    std::vector<int> iters_now(np, 0);
     for (int p = 0; p < np; ++p) {
         const fkgp_handle* h = hs[p];
         const int N = h->nprobe;
@@ -3441,6 +3507,7 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
             }
             conv &= hsv[j].done == 1;
             if (j > 0) itmax = std::max(itmax, hsv[j].iters);
+            iters_now[p] = std::max(iters_now[p], hsv[j].iters);
         }
         double logdet = 0.0, q = 0.0, dq[5];
         Scratch sp_(st);
@@ -3459,6 +3526,10 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
             infos[p].batch_block = tile.block;
         }
         if (!conv) res = FKGP_ENOTCONV;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_iter_cache[shape] = iters_now;
     }
     return res;
 }

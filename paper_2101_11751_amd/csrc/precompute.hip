@@ -129,6 +129,25 @@ __device__ inline bool cell_of(const GridDev& g, const Tin* const* xs, int64_t i
     return ok;
 }
 
+// The same from coordinates already in registers (unused ones ignored).
+template <class Tin>
+__device__ inline bool cell_of_vals(const GridDev& g, Tin x0, Tin x1, Tin x2, uint32_t& key) {
+    const Tin xv[3] = {x0, x1, x2};
+    uint32_t c = 0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (k >= g.d) break;
+        int b;
+        double t;
+        ok &= locate((double)xv[k], g.g0[k], g.h[k], g.m[k], b, t);
+        if (!ok) b = 1;
+        c = c * (uint32_t)g.nc[k] + (uint32_t)(b - 1);
+    }
+    key = ok ? c : 0u;
+    return ok;
+}
+
 template <class Tin>
 struct Coords {
     const Tin* p[3];
@@ -181,9 +200,22 @@ __global__ __launch_bounds__(kBlock) void keys_and_counts(
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * tile_size<Tin>();
     const int64_t end = min(n, base + tile_size<Tin>());
-    for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
+    // all of the thread's coordinates are requested before the first is used
+    constexpr int IT = items_per_thread<Tin>();
+    Tin xv[3][IT];
+#pragma unroll
+    for (int s = 0; s < IT; ++s) {
+        const int64_t i = base + (int64_t)s * kBlock + threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xv[k][s] = (i < end && k < g.d) ? xs.p[k][i] : Tin(0);
+    }
+#pragma unroll
+    for (int s = 0; s < IT; ++s) {
+        const int64_t i = base + (int64_t)s * kBlock + threadIdx.x;
+        if (i >= end) break;
         uint32_t key;
-        if (!cell_of<Tin>(g, xs.p, i, key)) atomicMin(bad, (unsigned long long)(idx_base + i));
+        if (!cell_of_vals<Tin>(g, xv[0][s], xv[1][s], xv[2][s], key))
+            atomicMin(bad, (unsigned long long)(idx_base + i));
         keys[i] = key;
         atomicAdd(&hist[(key >> shift) & (nd - 1)], 1u);
     }
@@ -439,14 +471,34 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(
     }
 }
 
-// Segment bounds of each cell in the sorted keys.
+// Segment bounds of each cell in the sorted keys: one thread per 4 keys
+// (one 16-byte load plus the two neighbours).
 __global__ void cell_bounds(const uint32_t* __restrict__ keys, int64_t n,
                             uint32_t* __restrict__ start, uint32_t* __restrict__ end) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t k = keys[i];
-    if (i == 0 || keys[i - 1] != k) start[k] = (uint32_t)i;
-    if (i == n - 1 || keys[i + 1] != k) end[k] = (uint32_t)(i + 1);
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 >= n) return;
+    constexpr uint32_t kNone = 0xffffffffu;   // no cell has this key
+    uint32_t k[6];
+    k[0] = i0 > 0 ? keys[i0 - 1] : kNone;
+    if (i0 + 4 <= n) {
+        const uint4 v = *reinterpret_cast<const uint4*>(keys + i0);
+        k[1] = v.x;
+        k[2] = v.y;
+        k[3] = v.z;
+        k[4] = v.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) k[1 + j] = i0 + j < n ? keys[i0 + j] : kNone;
+    }
+    k[5] = i0 + 4 < n ? keys[i0 + 4] : kNone;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t i = i0 + j;
+        if (i >= n) break;
+        const uint32_t kk = k[1 + j];
+        if (k[j] != kk) start[kk] = (uint32_t)i;
+        if (k[j + 2] != kk) end[kk] = (uint32_t)(i + 1);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -829,17 +881,31 @@ __global__ __launch_bounds__(256) void assemble_wtw_stage(const double* __restri
     constexpr int P = D == 1 ? 7 : (D == 2 ? 49 : 343);
     constexpr int P0 = P / 7;
     const int64_t tot_sp = (int64_t)sout.n[0] * sout.n[1] * sout.n[2];
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // workgroups are dealt to the 8 XCDs in turn; the grid is a multiple of 8
+    // and XCD x takes the x-th contiguous eighth of the node order, so the
+    // neighbours that share input cells share one L2
+    const unsigned per_xcd = gridDim.x / 8;
+    const unsigned lb = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int64_t idx = (int64_t)lb * blockDim.x + threadIdx.x;
     if (idx >= tot_sp * P0) return;
     const int p0i = (int)(idx % P0);
     const int sp = (int)(idx / P0);
     int pstride = 1;
     for (int i = D - 1; i > k; --i) pstride *= 7;
     const int pay0 = (p0i / pstride) * pstride * 7 + p0i % pstride;
+    // output node: dimension k varies fastest over the launch (then the
+    // other two in C order), so the four nodes that read the same input
+    // cell run in the same or neighbouring workgroups
     int s[3];
-    s[2] = sp % sout.n[2];
-    s[1] = (sp / sout.n[2]) % sout.n[1];
-    s[0] = sp / (sout.n[2] * sout.n[1]);
+    {
+        const int ka = k == 0 ? 1 : 0, kb = k == 2 ? 1 : 2;   // the other two, in order
+        int r = sp;
+        s[k] = r % sout.n[k];
+        r /= sout.n[k];
+        s[kb] = r % sout.n[kb];
+        s[ka] = r / sout.n[kb];
+    }
+    const int64_t spl = ((int64_t)s[0] * sout.n[1] + s[1]) * sout.n[2] + s[2];
     double acc[7];
 #pragma unroll
     for (int o = 0; o < 7; ++o) acc[o] = 0.0;
@@ -858,7 +924,7 @@ __global__ __launch_bounds__(256) void assemble_wtw_stage(const double* __restri
 #pragma unroll
             for (int q = 0; q < 7; ++q) acc[o] = fma(tab.E[o][a][q], v[q], acc[o]);
     }
-    const int64_t ob = (int64_t)sp * P + pay0;
+    const int64_t ob = spl * P + pay0;
 #pragma unroll
     for (int o = 0; o < 7; ++o) out[ob + o * pstride] = acc[o];
 }
@@ -949,7 +1015,27 @@ __global__ __launch_bounds__(256) void count_mask_bits(const uint32_t* __restric
     if (threadIdx.x == 0) *out = sh[0];
 }
 
-// Deterministic sum of the per-cell sums of y^2 (single block, fixed tree).
+// Deterministic sum of the per-cell sums of y^2 in two launches: 256
+// workgroups each reduce one contiguous chunk in a fixed order, then one
+// workgroup reduces the 256 partial sums (fixed trees throughout).
+__global__ __launch_bounds__(256) void sum_chunks(const double* __restrict__ v, int64_t n,
+                                                  double* __restrict__ part) {
+    __shared__ double sh[256];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = min(n, lo + chunk);
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += v[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Deterministic sum of a short array (single block, fixed tree).
 __global__ __launch_bounds__(1024) void sum_fixed(const double* __restrict__ v, int64_t n,
                                                   double* __restrict__ out) {
     __shared__ double sh[1024];
@@ -1015,7 +1101,11 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
     // key bits and digit plan
     int key_bits = 1;
     while ((int64_t(1) << key_bits) < ncells) ++key_bits;
-    const int npass = (key_bits + 9) / 10;
+    // at most 8 bits a pass: a tile of 4096 items then leaves in runs of 16
+    // or more items per digit, long enough that partial cache lines at the
+    // run ends cost less than another pass (9-10 bit digits left runs of 4-8
+    // items and wrote 2-3x the bytes moved)
+    const int npass = (key_bits + 7) / 8;
     int dbits[8], dshift[8];
     {
         int sh = 0;
@@ -1117,7 +1207,7 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
             std::swap(pin, pout);
         }
         // kin/pin now hold the sorted keys/payload
-        cell_bounds<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(kin, n, cstart, cend);
+        cell_bounds<<<(unsigned)((n + 1023) / 1024), 256, 0, s>>>(kin, n, cstart, cend);
         FKGP_HIP(hipGetLastError());
         if (out.keep_pay)
             FKGP_HIP(hipMemcpyAsync(out.keep_pay, pin, sizeof(P) * (size_t)n,
@@ -1174,7 +1264,7 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
             Dims3 nxt = cur;
             nxt.n[k] = g.m[k];
             const int64_t total = (int64_t)nxt.n[0] * nxt.n[1] * nxt.n[2] * (NB / 7);
-            const unsigned nbk = (unsigned)((total + 255) / 256);
+            const unsigned nbk = (unsigned)((total + 255) / 256 + 7) / 8 * 8;
             if (d == 1)
                 assemble_wtw_stage<1><<<nbk, 256, 0, s>>>(src, dst, cur, nxt, k, tab);
             else if (d == 2)
@@ -1230,8 +1320,15 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
             FKGP_HIP(hipMemcpyAsync(out.sketches, src + M, sizeof(double) * M * nprobe,
                                     hipMemcpyDeviceToDevice, s));
     }
-    sum_fixed<<<1, 1024, 0, s>>>(Myy, ncells, out.yty_dev);
-    FKGP_HIP(hipGetLastError());
+    {
+        // the shared region is free again: the assembly and sketch stages
+        // that used it are ordered before these launches on the stream
+        Carver c{block + shared_off, 0};
+        double* part = c.take<double>(256);
+        sum_chunks<<<256, 256, 0, s>>>(Myy, ncells, part);
+        sum_fixed<<<1, 1024, 0, s>>>(part, 256, out.yty_dev);
+        FKGP_HIP(hipGetLastError());
+    }
     if (out.keep_cstart) {   // cell bounds (all zero for n = 0)
         FKGP_HIP(hipMemcpyAsync(out.keep_cstart, cstart, sizeof(uint32_t) * ncells,
                                 hipMemcpyDeviceToDevice, s));
@@ -1473,17 +1570,48 @@ namespace {
 template <class T>
 __global__ __launch_bounds__(256) void count_nonzero(const T* __restrict__ a, int64_t n,
                                                      unsigned long long* __restrict__ out) {
+    // 16-byte loads over the bulk (the array is 256-byte aligned), then the tail
+    constexpr int V = 16 / sizeof(T);
+    struct alignas(16) Vec { T v[V]; };
+    const Vec* av = reinterpret_cast<const Vec*>(a);
+    const int64_t nv = n / V;
     unsigned cnt = 0u;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    // four independent 16-byte loads in flight per thread and step
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x; i0 < nv; i0 += 4 * stride) {
+        Vec x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i < nv) x[u] = av[i];
+            else
+#pragma unroll
+                for (int j = 0; j < V; ++j) x[u].v[j] = T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int j = 0; j < V; ++j) cnt += x[u].v[j] != T(0);
+    }
+    for (int64_t i = nv * V + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         cnt += a[i] != T(0);
+    // one counter update per workgroup: updates of one address serialise
+    // (about 15 ns each), so their number, not the read, would set the time
+    __shared__ unsigned wsum[4];
     for (int off = 32; off > 0; off >>= 1) cnt += (unsigned)__shfl_xor((int)cnt, off);
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(out, (unsigned long long)cnt);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long tot =
+            (unsigned long long)wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (tot) atomicAdd(out, tot);
+    }
 }
 }  // namespace
 
 fkgp_status count_wtw_nonzeros(fkgp_dtype dt, const void* A, int64_t elems,
                                unsigned long long* out, hipStream_t s) {
-    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((elems + 255) / 256, 4096));
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((elems + 255) / 256, 1024));
     if (dt == FKGP_F32)
         count_nonzero<float><<<nb, 256, 0, s>>>(static_cast<const float*>(A), elems, out);
     else
