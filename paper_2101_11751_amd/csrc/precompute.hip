@@ -201,13 +201,17 @@ __global__ __launch_bounds__(kBlock) void keys_and_counts(
     const int64_t base = (int64_t)blockIdx.x * tile_size<Tin>();
     const int64_t end = min(n, base + tile_size<Tin>());
     // all of the thread's coordinates are requested before the first is used
+    // (no branches around the loads: past the tile's end they repeat its
+    // first item, past d they read dimension 0 again; both are discarded)
     constexpr int IT = items_per_thread<Tin>();
+    const Tin* px[3] = {xs.p[0], g.d > 1 ? xs.p[1] : xs.p[0], g.d > 2 ? xs.p[2] : xs.p[0]};
     Tin xv[3][IT];
 #pragma unroll
     for (int s = 0; s < IT; ++s) {
         const int64_t i = base + (int64_t)s * kBlock + threadIdx.x;
+        const int64_t ic = i < end ? i : base;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) xv[k][s] = (i < end && k < g.d) ? xs.p[k][i] : Tin(0);
+        for (int k = 0; k < 3; ++k) xv[k][s] = px[k][ic];
     }
 #pragma unroll
     for (int s = 0; s < IT; ++s) {
@@ -235,8 +239,20 @@ __global__ __launch_bounds__(kBlock) void digit_counts(
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * tile_size<Tin>();
     const int64_t end = min(n, base + tile_size<Tin>());
-    for (int64_t i = base + threadIdx.x; i < end; i += kBlock)
-        atomicAdd(&hist[(keys[i] >> shift) & (nd - 1)], 1u);
+    // the thread's keys are requested together (clamped past the tile's end,
+    // then not counted), then counted
+    constexpr int IT = items_per_thread<Tin>();
+    uint32_t kv[IT];
+#pragma unroll
+    for (int s = 0; s < IT; ++s) {
+        const int64_t i = base + (int64_t)s * kBlock + threadIdx.x;
+        kv[s] = keys[i < end ? i : base];
+    }
+#pragma unroll
+    for (int s = 0; s < IT; ++s) {
+        const int64_t i = base + (int64_t)s * kBlock + threadIdx.x;
+        if (i < end) atomicAdd(&hist[(kv[s] >> shift) & (nd - 1)], 1u);
+    }
     __syncthreads();
     for (int dgt = threadIdx.x; dgt < nd; dgt += kBlock)
         counts[(size_t)dgt * ntiles + blockIdx.x] = hist[dgt];
@@ -370,28 +386,47 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(
     uint32_t key[IT];
     uint32_t rank[IT];
     P pay[IT];
+    // all of the thread's keys and payloads are requested before the first
+    // is ranked (the ranking's wavefront barriers would otherwise hold each
+    // item's loads until the previous item is done); past the end of the
+    // input the loads repeat the last item (n > 0) and the key marks it void
+#pragma unroll
+    for (int s = 0; s < IT; ++s) {
+        const int64_t i = wbase + (int64_t)s * 64 + lane;
+        const int64_t ic = i < n ? i : n - 1;
+        uint32_t k = keys_in[ic];
+        P p{};
+        if constexpr (kRaw) {
+            // no branches around the loads: a dimension past d reads
+            // dimension 0 again and discards it
+            const Tin* p1 = d > 1 ? xs.p[1] : xs.p[0];
+            const Tin* p2 = d > 2 ? xs.p[2] : xs.p[0];
+            const Tin v0 = xs.p[0][ic];
+            const Tin v1 = p1[ic];
+            const Tin v2 = p2[ic];
+            const Tin yv = yin[ic];
+            // slots: the d coordinates, then y, then the index when asked
+            // for; in 3-D there is no fifth slot, so the index takes y's
+            // place and the moments read y through it (selects on uniform
+            // d and with_idx, no branches)
+            const Tin idx = with_idx ? idx_to_slot((uint32_t)ic, Tin(0)) : Tin(0);
+            p.x = v0;
+            p.y = d > 1 ? v1 : yv;
+            p.z = d > 2 ? v2 : (d == 2 ? yv : idx);
+            p.w = d == 3 ? (with_idx ? idx : yv) : (d == 2 ? idx : Tin(0));
+        } else {
+            p = pay_in[ic];
+        }
+        key[s] = i < n ? k : 0xffffffffu;
+        pay[s] = p;
+    }
+    // keep the scheduler from sinking those loads back next to their uses
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int s = 0; s < IT; ++s) {
         const int64_t i = wbase + (int64_t)s * 64 + lane;
         const bool valid = i < n;
-        uint32_t k = 0;
-        P p{};
-        if (valid) {
-            k = keys_in[i];
-            if constexpr (kRaw) {
-                for (int c = 0; c < d; ++c) set_slot(p, c, xs.p[c][i]);
-                if (with_idx && d == 3) {
-                    // no fifth slot: the index takes y's place, and the
-                    // moments read y through it
-                    set_slot(p, 3, idx_to_slot((uint32_t)i, Tin(0)));
-                } else {
-                    set_slot(p, d, yin[i]);
-                    if (with_idx) set_slot(p, d + 1, idx_to_slot((uint32_t)i, Tin(0)));
-                }
-            } else {
-                p = pay_in[i];
-            }
-        }
+        const uint32_t k = valid ? key[s] : 0u;
         const uint32_t dg = (k >> shift) & (nd - 1);
         unsigned long long peers = __ballot(valid);
         for (int b = 0; b < bits; ++b) {
@@ -408,9 +443,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(
         if (valid && before + 1 == cnt) whist[wave * nd + dg] = r + 1;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        key[s] = valid ? k : 0xffffffffu;
         rank[s] = r;
-        pay[s] = p;
     }
     __syncthreads();
     // tile-local digit starts: exclusive scan of the tile's digit counts
@@ -909,20 +942,29 @@ __global__ __launch_bounds__(256) void assemble_wtw_stage(const double* __restri
     double acc[7];
 #pragma unroll
     for (int o = 0; o < 7; ++o) acc[o] = 0.0;
+    // the 4 x 7 loads are issued together: a cell outside the grid is read
+    // at a clamped position and its values zeroed (no branch around loads)
+    double v[4][7];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         const int c = s[k] - a;
-        if (c < 0 || c >= sin.n[k]) continue;
+        const int cc = min(max(c, 0), sin.n[k] - 1);
         int t[3] = {s[0], s[1], s[2]};
-        t[k] = c;
+        t[k] = cc;
         const int64_t ib = (int64_t)((t[0] * sin.n[1] + t[1]) * sin.n[2] + t[2]) * P + pay0;
-        double v[7];
 #pragma unroll
-        for (int q = 0; q < 7; ++q) v[q] = in[ib + q * pstride];
+        for (int q = 0; q < 7; ++q) v[a][q] = in[ib + q * pstride];
+    }
 #pragma unroll
-        for (int o = 0; o < 7; ++o)
+    for (int a = 0; a < 4; ++a) {
+        const int c = s[k] - a;
+        const bool ok = c >= 0 && c < sin.n[k];
 #pragma unroll
-            for (int q = 0; q < 7; ++q) acc[o] = fma(tab.E[o][a][q], v[q], acc[o]);
+        for (int q = 0; q < 7; ++q) {
+            const double x = ok ? v[a][q] : 0.0;
+#pragma unroll
+            for (int o = 0; o < 7; ++o) acc[o] = fma(tab.E[o][a][q], x, acc[o]);
+        }
     }
     const int64_t ob = spl * P + pay0;
 #pragma unroll
