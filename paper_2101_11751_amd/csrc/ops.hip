@@ -1110,14 +1110,23 @@ __global__ __launch_bounds__(256) void spmv_tiled_kernel(const TA* __restrict__ 
     const int64_t j0 = (int64_t)tile * kTileRows;
     const int64_t ldx = tg.M + 2 * tg.halo;
     const uint32_t mk = bmask ? bmask[tile] : ~0u;
-    // stage the windows (not needed when the whole tile is zero)
+    // stage the windows (not needed when the whole tile is zero): at each
+    // position the NW windows' loads are issued together, unconditionally
+    // (an index past the padded vector reads its last entry and stores 0;
+    // indices are never negative, the halo covers the margin)
     if (mk != 0u) {
-        for (int w = 0; w < NW; ++w) {
-            const int64_t start =
-                tg.halo + j0 + (D >= 2 ? (int64_t)(w - 3) * tg.S0 : 0) - tg.margin;
-            for (int i = threadIdx.x; i < tg.WL; i += 256) {
-                const int64_t idx = start + i;
-                win[w * tg.WL + i] = idx < ldx ? xpad[idx] : T(0);
+        const int64_t start0 = tg.halo + j0 - tg.margin;
+        for (int i = threadIdx.x; i < tg.WL; i += 256) {
+            T v[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const int64_t idx = start0 + (D >= 2 ? (int64_t)(w - 3) * tg.S0 : 0) + i;
+                v[w] = xpad[idx < ldx ? idx : ldx - 1];
+            }
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const int64_t idx = start0 + (D >= 2 ? (int64_t)(w - 3) * tg.S0 : 0) + i;
+                win[w * tg.WL + i] = idx < ldx ? v[w] : T(0);
             }
         }
     }
