@@ -425,8 +425,10 @@ fkgp_status fkgp_wtw_matvec_dot(const fkgp_handle* h, const void* xpad, void* u,
  * sorted and reduced; the per-cell moments of the chunks are summed in chunk
  * order (deterministic; equal to the one-shot statistics up to the order of
  * the per-cell sums), then assembled once.  n <= chunk: one copy and the
- * one-shot precompute.  n_probes and keep_points must be 0.  Out-of-grid
- * points are reported with their global index.  Synchronises `stream`. */
+ * one-shot precompute.  Probe sketches (n_probes) follow each point's index
+ * in the whole data set, so they equal the one-shot sketches; keep_points
+ * must be 0.  Out-of-grid points are reported with their global index.
+ * Synchronises `stream`. */
 fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x,
                                  const void* y, int64_t n, fkgp_dtype in,
                                  const fkgp_precompute_opts* opts, int64_t chunk,

@@ -292,10 +292,11 @@ def precompute(grid, x, y, stats_dtype=torch.float32, n_probes=0, probe_seed=0,
     return Handle(out, grid)
 
 
-def precompute_host(grid, x, y, stats_dtype=torch.float32, chunk=0):
+def precompute_host(grid, x, y, stats_dtype=torch.float32, chunk=0, n_probes=0, probe_seed=0):
     """fkgp_precompute_host: x is a list of d host arrays (numpy or CPU
     tensors, float32 or float64), y a host array of the same dtype; the
-    points stream to the device in chunks of `chunk` points (0: 2^24)."""
+    points stream to the device in chunks of `chunk` points (0: 2^24).
+    n_probes / probe_seed: probe sketches as in `precompute`."""
     L = load_library()
     d = int(grid["d"])
     xs = [np.ascontiguousarray(t.numpy() if isinstance(t, torch.Tensor) else t) for t in x]
@@ -306,7 +307,7 @@ def precompute_host(grid, x, y, stats_dtype=torch.float32, chunk=0):
     dt = F32 if yv.dtype == np.float32 else F64
     arr = (ctypes.c_void_p * 3)(*([t.ctypes.data for t in xs] + [0] * (3 - d)))
     g = _grid_struct(grid)
-    o = _PreOpts(_dtype_code(stats_dtype), 0, 0, 0, _interp_code(grid))
+    o = _PreOpts(_dtype_code(stats_dtype), int(n_probes), int(probe_seed), 0, _interp_code(grid))
     out = ctypes.c_void_p()
     _check(L.fkgp_precompute_host(ctypes.byref(g), arr, yv.ctypes.data, n, dt, ctypes.byref(o),
                                   int(chunk), _stream(), ctypes.byref(out)))

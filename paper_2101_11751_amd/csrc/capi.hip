@@ -1722,8 +1722,12 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
             set_error("stats dtype must be FKGP_F32 or FKGP_F64");
             return FKGP_EINVAL;
         }
-        if (o.n_probes != 0 || o.keep_points != 0) {
-            set_error("the streamed precompute builds no probe sketches and keeps no points");
+        if (o.keep_points != 0) {
+            set_error("the streamed precompute keeps no points");
+            return FKGP_EINVAL;
+        }
+        if (o.n_probes < 0 || o.n_probes > kMaxProbes) {
+            set_error("n_probes must be in [0, 31]");
             return FKGP_EINVAL;
         }
         if (chunk == 0) chunk = int64_t(1) << 24;
@@ -1744,6 +1748,8 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
         h->NB = 1;
         for (int k = 0; k < g.d; ++k) h->NB *= 7;
         h->dt = o.stats_dtype;
+        h->nprobe = o.n_probes;
+        h->seed = o.probe_seed;
         // resources of the stream: released on every exit path
         const size_t es = in == FKGP_F32 ? 4 : 8;
         const int nplanes = g.d + 1;
@@ -1798,13 +1804,14 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
                     return fail(hip_fail(e, "hipMemcpyAsync(points)"));
                 if (k < g.d) xd[k] = res.devbuf + es * k * (size_t)cpts;
             }
-            st = run_precompute(g, xd, res.devbuf + es * g.d * (size_t)cpts, n, in, h->dt, 0, 0,
-                                so, bad, s);
+            st = run_precompute(g, xd, res.devbuf + es * g.d * (size_t)cpts, n, in, h->dt,
+                                h->nprobe, h->seed, so, bad, s);
         } else {
             int64_t ncells = 1;
             for (int k = 0; k < g.d; ++k) ncells *= g.nc[k];
             int NR = 1;
             for (int k = 0; k < g.d; ++k) NR *= 4;
+            NR *= 1 + h->nprobe;   // response moments of y and of every probe
             const size_t nacc = (size_t)ncells * (h->NB + NR + 1);
             if ((e = dev_malloc(res.a, reinterpret_cast<void**>(&res.acc), sizeof(double) * nacc,
                                 s)) != hipSuccess ||
@@ -1850,8 +1857,8 @@ fkgp_status fkgp_precompute_host(const fkgp_grid* grid, const void* const* x, co
                 cc.first = c == 0 ? 1 : 0;
                 cc.last = c == nchunks - 1 ? 1 : 0;
                 cc.idx_base = base;
-                st = run_precompute(g, xd, dev + es * g.d * (size_t)cpts, cn, in, h->dt, 0, 0, so,
-                                    bad, s, &cc);
+                st = run_precompute(g, xd, dev + es * g.d * (size_t)cpts, cn, in, h->dt,
+                                    h->nprobe, h->seed, so, bad, s, &cc);
                 if (st == FKGP_OK && (e = hipEventRecord(res.used[slot], s)) != hipSuccess)
                     return fail(hip_fail(e, "hipEventRecord"));
             }

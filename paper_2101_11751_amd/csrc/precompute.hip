@@ -562,7 +562,7 @@ template <int D, class Tin>
 __global__ __launch_bounds__(64) void cell_moments(
     const typename PayloadOf<Tin>::type* __restrict__ pay,
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, GridDev g,
-    int nprobe, uint64_t seed, int ncells, const Tin* __restrict__ yin,
+    int nprobe, uint64_t seed, int ncells, const Tin* __restrict__ yin, uint64_t idx_base,
     double* __restrict__ Mw, double* __restrict__ Mr, double* __restrict__ Myy) {
     constexpr int NW = ipow_c<D>(7);
     constexpr int NR = ipow_c<D>(4);
@@ -613,7 +613,10 @@ __global__ __launch_bounds__(64) void cell_moments(
             const double yv = y_by_idx ? (double)yin[orig] : (double)get_slot(p, D);
             rvb[lane * nr] = yv;
             if (nprobe > 0) {
-                for (int j = 0; j < nprobe; ++j) rvb[lane * nr + 1 + j] = rademacher(seed, j, orig);
+                // probe entries follow the point's index in the whole data
+                // set (idx_base: the first point of this chunk)
+                for (int j = 0; j < nprobe; ++j)
+                    rvb[lane * nr + 1 + j] = rademacher(seed, j, idx_base + orig);
             }
         } else {
             for (int q = 0; q < kPw; ++q) pw[lane][q] = 0.0;
@@ -1255,19 +1258,20 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
             FKGP_HIP(hipMemcpyAsync(out.keep_pay, pin, sizeof(P) * (size_t)n,
                                     hipMemcpyDeviceToDevice, s));
         const size_t lds_mom = sizeof(double) * 64 * (kPw + nr);
+        const uint64_t idx_base = cc ? (uint64_t)cc->idx_base : 0ull;   // chunk's first point
         if (d == 1)
-            cell_moments<1, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
-                                                                 (int)ncells, y, Mw, Mr, Myy);
+            cell_moments<1, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(
+                pin, cstart, cend, g, nprobe, seed, (int)ncells, y, idx_base, Mw, Mr, Myy);
         else if (d == 2 && nprobe == 0)
             cell_moments2<Tin><<<(unsigned)ncells, 64, 0, s>>>(pin, cstart, cend, g, Mw, Mr, Myy);
         else if (d == 2)
-            cell_moments<2, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
-                                                                 (int)ncells, y, Mw, Mr, Myy);
+            cell_moments<2, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(
+                pin, cstart, cend, g, nprobe, seed, (int)ncells, y, idx_base, Mw, Mr, Myy);
         else if (nprobe == 0)
             cell_moments3<Tin><<<(unsigned)ncells, 64, 0, s>>>(pin, cstart, cend, g, Mw, Mr, Myy);
         else
-            cell_moments<3, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(pin, cstart, cend, g, nprobe, seed,
-                                                                 (int)ncells, y, Mw, Mr, Myy);
+            cell_moments<3, Tin><<<(unsigned)ncells, 64, lds_mom, s>>>(
+                pin, cstart, cend, g, nprobe, seed, (int)ncells, y, idx_base, Mw, Mr, Myy);
         FKGP_HIP(hipGetLastError());
     } else {
         FKGP_HIP(hipMemsetAsync(Mw, 0, sizeof(double) * ncells * NB, s));

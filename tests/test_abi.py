@@ -132,3 +132,25 @@ def test_new_entry_points_validate_on_the_host():
     grad = (ctypes.c_double * 5)()
     assert L.fkgp_mll_and_grad(None, ctypes.byref(hyp), ctypes.byref(opts), ctypes.byref(mll),
                                grad, None, None) == P.EINVAL
+
+
+def test_streamed_precompute_validates_on_the_host():
+    """fkgp_precompute_host rejects kept points and out-of-range probe
+    counts before touching a device (probe sketches themselves are allowed)."""
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    L = P.load_library()
+    g = P._Grid()
+    g.d = 1
+    g.m[0] = 50
+    g.spacing[0] = 0.02
+    out = ctypes.c_void_p()
+    keep = P._PreOpts(P.F32, 0, 0, 1, 0)
+    assert L.fkgp_precompute_host(ctypes.byref(g), None, None, 0, P.F32, ctypes.byref(keep), 0,
+                                  None, ctypes.byref(out)) == P.EINVAL
+    assert b"keeps no points" in L.fkgp_last_error()
+    many = P._PreOpts(P.F32, 32, 0, 0, 0)
+    assert L.fkgp_precompute_host(ctypes.byref(g), None, None, 0, P.F32, ctypes.byref(many), 0,
+                                  None, ctypes.byref(out)) == P.EINVAL
+    assert b"n_probes" in L.fkgp_last_error()
+    assert out.value is None

@@ -76,3 +76,34 @@ def test_streamed_out_of_grid_and_empty():
     h = P.precompute_host(grid, [e0], e0, chunk=100)
     wtw, wty, yty = P.export_stats(h)
     assert float(wtw.abs().max()) == 0.0 and yty == 0.0
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_streamed_probe_sketches(d):
+    """Probe sketches from the streamed precompute: each point's Rademacher
+    entries follow its index in the whole data set, so chunking changes
+    nothing but the order of the per-cell sums (the chunk size 7,777 leaves
+    cells split across chunks)."""
+    _need_gpu()
+    n = 40000
+    grid, X, y = case(d, n, 120 + d, np.float64)
+    seed, npr = 77, 5
+    xs = [torch.from_numpy(np.ascontiguousarray(X[k])).cuda() for k in range(d)]
+    h1 = P.precompute(grid, xs, torch.from_numpy(y).cuda(), stats_dtype=torch.float64,
+                      n_probes=npr, probe_seed=seed)
+    h2 = P.precompute_host(grid, [X[k] for k in range(d)], y, stats_dtype=torch.float64,
+                           chunk=7777, n_probes=npr, probe_seed=seed)
+    s1 = P.export_sketches(h1).cpu().numpy()
+    s2 = P.export_sketches(h2).cpu().numpy()
+    assert s2.shape == (npr, h1.m_total)
+    assert rel(s2, s1) <= 1e-13
+    sk_o = oracle.probe_sketches(grid, X, seed, npr)
+    assert rel(s2, sk_o) <= 1e-13
+    a, b = P.export_stats(h1), P.export_stats(h2)
+    assert rel(b[1].cpu(), a[1].cpu()) <= 1e-13 and abs(b[2] - a[2]) <= 1e-13 * abs(a[2])
+    # the MLL from either handle: same statistics, same probes
+    hyp = {"lengthscale": [0.1] * d, "outputscale": 1.0, "noise": 0.3}
+    v1, g1, _ = P.mll_and_grad(h1, hyp, 10, 1e-10, 5000)
+    v2, g2, _ = P.mll_and_grad(h2, hyp, 10, 1e-10, 5000)
+    assert abs(v2 - v1) <= 1e-8 * abs(v1)
+    assert np.max(np.abs(np.array(g2) - np.array(g1))) <= 1e-7 * np.max(np.abs(g1))
