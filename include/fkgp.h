@@ -112,7 +112,8 @@ typedef struct {
     int keep_points;         /* 1: the handle also keeps the points in cell
                                 order (n * 4 values of the input dtype) and
                                 the cell bounds, for fkgp_ski_solve (in 3-D
-                                not together with probe sketches) */
+                                with probe sketches, y is put back into the
+                                kept points from the input after the sort) */
     int interp;              /* fkgp_interp: the interpolation scheme of W,
                                 used by every later call on the handle */
 } fkgp_precompute_opts;

@@ -1253,11 +1253,6 @@ fkgp_status fkgp_precompute(const fkgp_grid* grid, const void* const* x, const v
             set_error("keep_points must be 0 or 1");
             return FKGP_EINVAL;
         }
-        if (o.keep_points && g.d > 2 && o.n_probes > 0) {
-            set_error("in 3-D keep_points and probe sketches exclude each other (the point "
-                      "index takes the slot of y)");
-            return FKGP_EINVAL;
-        }
         if (o.stats_dtype != FKGP_F32 && o.stats_dtype != FKGP_F64) {
             set_error("stats dtype must be FKGP_F32 or FKGP_F64");
             return FKGP_EINVAL;

@@ -1122,6 +1122,20 @@ __global__ void add_moments(double* __restrict__ acc, const double* __restrict__
         acc[i] = first ? v[i] : acc[i] + v[i];
 }
 
+// Kept points of a 3-D sort that carried the point index in y's slot (probe
+// sketches requested): y is put back into the slot from the input, so the
+// kept payload is (x, y, z, y) as without probes.
+template <class Tin>
+__global__ void kept_payload_with_y(const typename PayloadOf<Tin>::type* __restrict__ pay,
+                                    const Tin* __restrict__ y, int64_t n,
+                                    typename PayloadOf<Tin>::type* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    auto p = pay[i];
+    p.w = y[slot_to_idx(p.w)];
+    out[i] = p;
+}
+
 template <class Tin>
 fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void* yv,
                              int64_t n, fkgp_dtype stats, int nprobe, uint64_t seed,
@@ -1254,9 +1268,16 @@ fkgp_status precompute_typed(const GridDev& g, const void* const* xv, const void
         // kin/pin now hold the sorted keys/payload
         cell_bounds<<<(unsigned)((n + 1023) / 1024), 256, 0, s>>>(kin, n, cstart, cend);
         FKGP_HIP(hipGetLastError());
-        if (out.keep_pay)
-            FKGP_HIP(hipMemcpyAsync(out.keep_pay, pin, sizeof(P) * (size_t)n,
-                                    hipMemcpyDeviceToDevice, s));
+        if (out.keep_pay) {
+            if (d == 3 && nprobe > 0) {
+                kept_payload_with_y<Tin><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+                    pin, y, n, static_cast<P*>(out.keep_pay));
+                FKGP_HIP(hipGetLastError());
+            } else {
+                FKGP_HIP(hipMemcpyAsync(out.keep_pay, pin, sizeof(P) * (size_t)n,
+                                        hipMemcpyDeviceToDevice, s));
+            }
+        }
         const size_t lds_mom = sizeof(double) * 64 * (kPw + nr);
         const uint64_t idx_base = cc ? (uint64_t)cc->idx_base : 0ull;   // chunk's first point
         if (d == 1)

@@ -71,11 +71,29 @@ def test_ski_solve_errors_and_empty():
     h = P.precompute(grid, xs, yt)
     with pytest.raises(P.FkgpError):
         P.ski_solve(h, HYP[1])
-    g3 = oracle.make_grid([8, 8, 8], lo=0.0, hi=1.0)
-    x3 = [torch.rand(100, device="cuda") * 0.9 + 0.05 for _ in range(3)]
-    with pytest.raises(P.FkgpError):   # 3-D: kept points exclude probe sketches
-        P.precompute(g3, x3, torch.rand(100, device="cuda"), keep_points=True, n_probes=2)
     e = torch.empty(0, device="cuda", dtype=torch.float32)
     h0 = P.precompute(grid, [e], e, keep_points=True)
     mu, info = P.ski_solve(h0, HYP[1])
     assert info["converged"] and float(mu.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_kept_points_with_probe_sketches_3d(dtype):
+    """In 3-D the sort carries the point index in y's slot when probe sketches
+    are requested; the kept points get y back from the input, so one handle
+    serves the plain SKI solve and the MLL: its SKI mean, statistics and
+    sketches equal those of handles made with either option alone."""
+    _need_gpu()
+    d, m = 3, [14, 12, 10]
+    grid, X, y, xs, yt = case(d, 20000, m, 61, dtype)
+    hb = P.precompute(grid, xs, yt, stats_dtype=torch.float64, keep_points=True, n_probes=4,
+                      probe_seed=9)
+    hk = P.precompute(grid, xs, yt, stats_dtype=torch.float64, keep_points=True)
+    hp = P.precompute(grid, xs, yt, stats_dtype=torch.float64, n_probes=4, probe_seed=9)
+    mu_b, ib = P.ski_solve(hb, HYP[d], tol=1e-11, maxiter=20000)
+    mu_k, ik = P.ski_solve(hk, HYP[d], tol=1e-11, maxiter=20000)
+    assert ib["converged"] and ik["converged"]
+    assert torch.equal(mu_b, mu_k)   # same kept points, same arithmetic
+    a, b = P.export_stats(hb), P.export_stats(hp)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2] == b[2]
+    assert torch.equal(P.export_sketches(hb), P.export_sketches(hp))
