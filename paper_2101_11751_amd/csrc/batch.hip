@@ -83,9 +83,11 @@ __device__ inline void line_base(const PassGeom& pg, int r, int64_t li, int64_t&
 }
 
 // Lines read in place by the register line FFT (contiguous lines, and
-// strided lines shorter than 32 nodes): line pairs of the flattened (active
-// right-hand side, line) list, one pair per wave (64/L pairs when L < 64).
-// dst = scale * conv(src) (+ add_coef * addv).
+// strided lines shorter than 32 nodes), one line pair per wave (64/L pairs
+// when L < 64).  A vector of several lines pairs its own lines (an odd one
+// leaves the last pair half empty), so its result does not depend on the
+// other right-hand sides of the item; one-line vectors (1-D) are paired with
+// each other.  dst = scale * conv(src) (+ add_coef * addv).
 template <int LG>
 __device__ void pass_reg_direct(const double* src, double* dst, const int* act, int na,
                                 const PassGeom& pg, const cplx<double>* tws, const double* lams,
@@ -96,8 +98,9 @@ __device__ void pass_reg_direct(const double* src, double* dst, const int* act, 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int e_lane = L >= 64 ? lane : (lane & (L - 1));
     const int g_lane = L >= 64 ? 0 : lane / L;
-    const int64_t nlines = pg.per_vec * na;
-    const int64_t npairs = (nlines + 1) / 2;
+    const bool cross = pg.per_vec == 1;
+    const int64_t ppv = (pg.per_vec + 1) / 2;   // pairs per vector (several lines)
+    const int64_t npairs = cross ? (na + 1) / 2 : ppv * na;
     const int nw = blockDim.x >> 6;
     for (int64_t pb = (int64_t)wave * G; pb < npairs; pb += (int64_t)nw * G) {
         const int64_t pair = pb + g_lane;
@@ -105,12 +108,17 @@ __device__ void pass_reg_direct(const double* src, double* dst, const int* act, 
         bool ok[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int64_t l = 2 * pair + h;
-            ok[h] = pair < npairs && l < nlines;
-            if (ok[h]) {
-                const int64_t ri = l / pg.per_vec;
-                line_base(pg, act[ri], l - ri * pg.per_vec, base[h], abase[h]);
+            int64_t ri, li;
+            if (cross) {
+                ri = 2 * pair + h;
+                li = 0;
+                ok[h] = pair < npairs && ri < na;
+            } else {
+                ri = pair / ppv;
+                li = 2 * (pair - ri * ppv) + h;
+                ok[h] = pair < npairs && li < pg.per_vec;
             }
+            if (ok[h]) line_base(pg, act[ri], li, base[h], abase[h]);
         }
         cplx<double> z[R];
 #pragma unroll
@@ -199,21 +207,33 @@ __device__ void pass_reg_strided(const double* src, double* dst, const int* act,
 }
 
 // Long lines by the four-step FFT, one line pair at a time for the whole
-// workgroup (Y: L complex scratch of this item).
+// workgroup (Y: L complex scratch of this item); pairs formed as in
+// pass_reg_direct.
 template <int LG1, int LG2>
 __device__ void pass_long(const double* src, double* dst, const int* act, int na,
                           const PassGeom& pg, const cplx<double>* tw1, const cplx<double>* tw2,
                           const cplx<double>* twh, const double* lamp, double scale,
                           const double* addv, double add_coef, cplx<double>* Y) {
-    const int64_t nlines = pg.per_vec * na;
-    for (int64_t la = 0; la < nlines; la += 2) {
+    const bool cross = pg.per_vec == 1;
+    const int64_t ppv = (pg.per_vec + 1) / 2;
+    const int64_t npairs = cross ? (na + 1) / 2 : ppv * na;
+    for (int64_t pair = 0; pair < npairs; ++pair) {
         int64_t base[2] = {0, 0}, abase[2] = {0, 0};
-        const bool hb = la + 1 < nlines;
+        int64_t ri[2], li[2];
+        if (cross) {
+            ri[0] = 2 * pair;
+            ri[1] = 2 * pair + 1;
+            li[0] = li[1] = 0;
+        } else {
+            ri[0] = ri[1] = pair / ppv;
+            li[0] = 2 * (pair - ri[0] * ppv);
+            li[1] = li[0] + 1;
+        }
+        const bool hb = cross ? ri[1] < na : li[1] < pg.per_vec;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int64_t l = (h == 0 || hb) ? la + h : la;
-            const int64_t ri = l / pg.per_vec;
-            line_base(pg, act[ri], l - ri * pg.per_vec, base[h], abase[h]);
+            const int hh = hb ? h : 0;
+            line_base(pg, act[ri[hh]], li[hh], base[h], abase[h]);
         }
         wg_conv_long<double, LG1, LG2>(src + base[0], hb ? src + base[1] : nullptr, pg.S,
                                        pg.m_line, dst + base[0], hb ? dst + base[1] : nullptr,

@@ -3233,28 +3233,43 @@ fkgp_status build_batch_items(const std::vector<BatchProb>& probs, const std::ve
                               const std::vector<int>* iters, Scratch& sc,
                               BatchItem** items_dev, int& nitems) {
     const size_t np = probs.size();
-    std::vector<double> w(np);   // cost of one iteration of one right-hand side
+    // per-iteration cost of one right-hand side, and the iterations (known
+    // from the previous evaluation, else equal)
+    std::vector<double> w(np), its(np), ones(np, 1.0);
     for (size_t p = 0; p < np; ++p) {
         const double M = (double)probs[p].M;
-        const double it = (iters && p < iters->size() && (*iters)[p] > 0) ? (*iters)[p] : 1.0;
-        w[p] = it * M * std::log2(M + 2.0);
+        its[p] = (iters && p < iters->size() && (*iters)[p] > 0) ? (*iters)[p] : 1.0;
+        w[p] = M * std::log2(M + 2.0);
     }
-    auto item_cost = [&](size_t p, int nr) { return w[p] * (1.0 + nr); };
-    std::vector<int> g(np, NR);   // group size per problem
-    for (int pass = 0; pass < 2; ++pass) {
-        double total = 0.0, longest1 = 0.0;
-        for (size_t p = 0; p < np; ++p) {
-            const int nit = (nrhs[p] + g[p] - 1) / g[p];
-            total += nit * item_cost(p, g[p]);
-            longest1 = std::max(longest1, item_cost(p, 1));
+    auto item_cost = [&](size_t p, int nr) { return its[p] * w[p] * (1.0 + nr); };
+    auto grouping = [&](const std::vector<double>& k, std::vector<int>& g) {
+        auto cost = [&](size_t p, int nr) { return k[p] * w[p] * (1.0 + nr); };
+        for (int pass = 0; pass < 2; ++pass) {
+            double total = 0.0, longest1 = 0.0;
+            for (size_t p = 0; p < np; ++p) {
+                const int nit = (nrhs[p] + g[p] - 1) / g[p];
+                total += nit * cost(p, g[p]);
+                longest1 = std::max(longest1, cost(p, 1));
+            }
+            const double target = std::max(total / std::max(1, slots), longest1);
+            for (size_t p = 0; p < np; ++p) {
+                int nr = NR;
+                while (nr > 1 && cost(p, std::min(nr, nrhs[p])) > target) nr /= 2;
+                g[p] = std::max(1, nr);
+            }
         }
-        const double target = std::max(total / std::max(1, slots), longest1);
-        for (size_t p = 0; p < np; ++p) {
-            int nr = NR;
-            while (nr > 1 && item_cost(p, std::min(nr, nrhs[p])) > target) nr /= 2;
-            g[p] = std::max(1, nr);
-        }
-    }
+    };
+    // Group sizes per problem.  A 1-D problem's right-hand sides share
+    // complex FFT lines inside an item, so its results depend on the
+    // grouping: it takes the groups of equal iterations, which depend on
+    // the shapes alone.  Vectors of several lines pair their own lines, so
+    // larger problems follow the measured iterations without changing any
+    // result: every call gives bitwise the same values.
+    std::vector<int> g(np, NR), g_shape(np, NR);
+    grouping(ones, g_shape);
+    grouping(its, g);
+    for (size_t p = 0; p < np; ++p)
+        if (probs[p].d == 1) g[p] = g_shape[p];
     struct Pending {
         BatchItem it;
         double cost;

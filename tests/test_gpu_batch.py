@@ -76,6 +76,28 @@ def test_batch_deterministic_and_errors():
         P.batch_mll_and_grad([h4], [hyp4])
 
 
+def test_batch_bitwise_repeatable_across_regrouping():
+    """The first evaluation of a batch groups right-hand sides by problem
+    size alone; later ones also weigh the iterations each problem took, so a
+    slow 2-D problem is split into smaller groups.  Every evaluation must
+    still give bitwise the same values: a 2-D problem pairs only its own
+    grid lines in the complex FFTs (41 lines per vector: one half-empty
+    pair), a 1-D problem keeps the size-based groups."""
+    _need_gpu()
+    probs = [problem(21, 1, [4000], 30000, 7), problem(22, 2, [41, 41], 20000, 7),
+             problem(23, 2, [25, 33], 5000, 5)]
+    hs = [p[0] for p in probs]
+    hyps = [p[1] for p in probs]
+    hyps[0].update(lengthscale=[0.2], noise=0.5)
+    hyps[1].update(lengthscale=[0.02, 0.02], noise=0.01)
+    runs = [P.batch_mll_and_grad(hs, hyps, 20, 1e-8, 3000) for _ in range(3)]
+    its = [i["iterations_probes_max"] for i in runs[0][2]]
+    assert its[1] > 5 * its[0], its   # the regrouping case is exercised
+    for m, g, _ in runs[1:]:
+        assert m == runs[0][0]
+        assert g == runs[0][1]
+
+
 def test_batch_long_lines():
     """1-D problems with 1500 .. 8192 nodes (circulants of 4096 .. 16384
     points, four-step line FFT inside the persistent kernel) beside short
@@ -108,10 +130,12 @@ def test_batch_long_lines():
 def test_batch_tiles_agree_and_autotune():
     """Every (right-hand sides per workgroup, workgroup size) tile gives the
     same result up to rounding (the workgroup size changes the reduction
-    order and the grouping changes which grid lines share a complex FFT, and
-    Lanczos coefficients taken from CG pass rounding on, so the comparison
-    uses the batch-vs-single tolerance); the autotuner reports the tile it
-    chose."""
+    order and, for 1-D problems, the grouping changes which right-hand sides
+    share a complex FFT, and Lanczos coefficients taken from CG pass rounding
+    on, so the comparison uses the batch-vs-single tolerance); at one
+    workgroup size a 2-D problem gives bitwise the same values for every
+    group size, since its grid lines are paired within one right-hand side;
+    the autotuner reports the tile it chose."""
     _need_gpu()
     probs = [problem(13, 2, [45, 37], 20000, 6), problem(14, 1, [700], 15000, 9),
              problem(15, 2, [20, 70], 9000, 4)]
@@ -129,6 +153,9 @@ def test_batch_tiles_agree_and_autotune():
                 ref[block] = (m, g, inf)
                 if block == 256:
                     continue
+            else:
+                for k in (0, 2):   # the 2-D problems
+                    assert m[k] == ref[block][0][k] and g[k] == ref[block][1][k], (nr, block, k)
             r0 = ref[256]
             for k in range(len(hs)):
                 scale = (abs(r0[2][k]["logdet"]) + abs(r0[2][k]["quad"])
