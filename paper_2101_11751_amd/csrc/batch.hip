@@ -120,13 +120,27 @@ __device__ void pass_reg_direct(const double* src, double* dst, const int* act, 
             }
             if (ok[h]) line_base(pg, act[ri], li, base[h], abase[h]);
         }
-        cplx<double> z[R];
+        // all loads first, the added vector's too (a node past the line's
+        // end reads its last node, an absent line reads line 0 of vector 0;
+        // both are masked)
+        double xa[R], xb[R], aa[R], ab[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const int e = q * 64 + e_lane;
-            const bool in = e < pg.m_line;
-            z[q].re = (in && ok[0]) ? src[base[0] + e * pg.S] : 0.0;
-            z[q].im = (in && ok[1]) ? src[base[1] + e * pg.S] : 0.0;
+            const int64_t off = (int64_t)(e < pg.m_line ? e : pg.m_line - 1) * pg.S;
+            xa[q] = src[base[0] + off];
+            xb[q] = src[base[1] + off];
+            if (addv) {
+                aa[q] = addv[abase[0] + off];
+                ab[q] = addv[abase[1] + off];
+            }
+        }
+        cplx<double> z[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const bool in = q * 64 + e_lane < pg.m_line;
+            z[q].re = (in && ok[0]) ? xa[q] : 0.0;
+            z[q].im = (in && ok[1]) ? xb[q] : 0.0;
         }
         conv_line_regs<double, LG>(z, e_lane, tws, lams);
 #pragma unroll
@@ -135,12 +149,12 @@ __device__ void pass_reg_direct(const double* src, double* dst, const int* act, 
             if (e >= pg.m_line) continue;
             if (ok[0]) {
                 double v = scale * z[q].re;
-                if (addv) v += add_coef * addv[abase[0] + e * pg.S];
+                if (addv) v += add_coef * aa[q];
                 dst[base[0] + e * pg.S] = v;
             }
             if (ok[1]) {
                 double v = scale * z[q].im;
-                if (addv) v += add_coef * addv[abase[1] + e * pg.S];
+                if (addv) v += add_coef * ab[q];
                 dst[base[1] + e * pg.S] = v;
             }
         }
@@ -168,9 +182,23 @@ __device__ void pass_reg_strided(const double* src, double* dst, const int* act,
         const int i0 = (bi % nblk) * kStrBlock;
         const int nv = min(kStrBlock, S - i0);
         const double* s0 = src + (int64_t)r * pg.M + i0;
-        for (int idx = threadIdx.x; idx < kStrBlock * m; idx += nt) {
-            const int e = idx / kStrBlock, l = idx - e * kStrBlock;
-            T[l * ms + e] = l < nv ? s0[(int64_t)e * S + l] : 0.0;
+        // loads in batches of 8 per thread, issued before their LDS stores
+        // (a column past the block reads the block's last column, masked)
+        for (int idx0 = threadIdx.x; idx0 < kStrBlock * m; idx0 += 8 * nt) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = idx0 + u * nt;
+                const int e = idx / kStrBlock, l = idx - e * kStrBlock;
+                const int ec = idx < kStrBlock * m ? e : m - 1;
+                v[u] = s0[(int64_t)ec * S + (l < nv ? l : nv - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = idx0 + u * nt;
+                const int e = idx / kStrBlock, l = idx - e * kStrBlock;
+                if (idx < kStrBlock * m) T[l * ms + e] = l < nv ? v[u] : 0.0;
+            }
         }
         __syncthreads();
         for (int pr = wave; pr < kStrBlock / 2; pr += nw) {
@@ -194,12 +222,26 @@ __device__ void pass_reg_strided(const double* src, double* dst, const int* act,
         __syncthreads();
         double* d0 = dst + (int64_t)r * pg.M + i0;
         const double* a0 = addv ? addv + (int64_t)r * pg.ldr + pg.halo + i0 : nullptr;
-        for (int idx = threadIdx.x; idx < kStrBlock * m; idx += nt) {
-            const int e = idx / kStrBlock, l = idx - e * kStrBlock;
-            if (l < nv) {
-                double v = scale * T[l * ms + e];
-                if (a0) v += add_coef * a0[(int64_t)e * S + l];
-                d0[(int64_t)e * S + l] = v;
+        for (int idx0 = threadIdx.x; idx0 < kStrBlock * m; idx0 += 8 * nt) {
+            double av[8];
+            if (a0) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int idx = idx0 + u * nt;
+                    const int e = idx / kStrBlock, l = idx - e * kStrBlock;
+                    const int ec = idx < kStrBlock * m ? e : m - 1;
+                    av[u] = a0[(int64_t)ec * S + (l < nv ? l : nv - 1)];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = idx0 + u * nt;
+                const int e = idx / kStrBlock, l = idx - e * kStrBlock;
+                if (idx < kStrBlock * m && l < nv) {
+                    double v = scale * T[l * ms + e];
+                    if (a0) v += add_coef * av[u];
+                    d0[(int64_t)e * S + l] = v;
+                }
             }
         }
         __syncthreads();
@@ -326,17 +368,40 @@ __device__ void spmv_rows(const TA* __restrict__ A, const double* rp, double* ur
                 for (int q = 0; q < RW; ++q) av[b][q] = (double)ap[q];
             }
             const int64_t off = (D == 1 ? 0 : (int64_t)(a - 3) * m1) - 3;
+            if constexpr (NR <= 4) {
+                // the x windows of every slot are loaded with the matrix row
+                // (each slot owns a padded r_hat, inactive ones included), so
+                // a stencil row costs one round trip
+                double xv[NR][RW + 6];
 #pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                if (r >= nr || done[r]) continue;
-                const double* xb = rp + r * ldr + halo + j0 + off;
-                double xv[RW + 6];
+                for (int r = 0; r < NR; ++r) {
+                    const double* xb = rp + r * ldr + halo + j0 + off;
 #pragma unroll
-                for (int c = 0; c < RW + 6; ++c) xv[c] = xb[c];
+                    for (int c = 0; c < RW + 6; ++c) xv[r][c] = xb[c];
+                }
 #pragma unroll
-                for (int b = 0; b < 7; ++b)
+                for (int r = 0; r < NR; ++r) {
+                    if (r >= nr || done[r]) continue;
 #pragma unroll
-                    for (int q = 0; q < RW; ++q) acc[r][q] = fma(av[b][q], xv[q + b], acc[r][q]);
+                    for (int b = 0; b < 7; ++b)
+#pragma unroll
+                        for (int q = 0; q < RW; ++q)
+                            acc[r][q] = fma(av[b][q], xv[r][q + b], acc[r][q]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    if (r >= nr || done[r]) continue;
+                    const double* xb = rp + r * ldr + halo + j0 + off;
+                    double xv[RW + 6];
+#pragma unroll
+                    for (int c = 0; c < RW + 6; ++c) xv[c] = xb[c];
+#pragma unroll
+                    for (int b = 0; b < 7; ++b)
+#pragma unroll
+                        for (int q = 0; q < RW; ++q)
+                            acc[r][q] = fma(av[b][q], xv[q + b], acc[r][q]);
+                }
             }
         }
 #pragma unroll
@@ -355,12 +420,113 @@ __device__ void spmv_rows(const TA* __restrict__ A, const double* rp, double* ur
     }
 }
 
+// Rows per tile of the staged product below (its LDS: batch_stage_doubles).
+template <int BB>
+constexpr int kStageRows = 2 * BB;
+
+// (C) with FP32-stored W^T W, the x windows staged through LDS: per tile of
+// 2 BB rows, the active slots' r_hat over the tile plus the stencil margin
+// h = 3 m1 + 3 (2-D) or 3 (1-D) go to X[r][.] with all loads issued
+// together, while each thread loads the 49 (7) entries of its two rows;
+// after one barrier the products read x from LDS.  A tile costs one memory
+// round trip instead of one per stencil row.  The products and dots are
+// summed in the same order as spmv_rows, so the results are bitwise the
+// same.  The window of padded index halo + t0 - h + i (halo = h) is
+// clamped to the padded vector; clamped slots serve no valid row.
+template <int NR, int D, int BB>
+__device__ void spmv_rows_staged(const float* __restrict__ A, const double* rp, double* ur,
+                                 const double* bh, const int* done, int nr, int64_t M,
+                                 int64_t ldr, int m1, double* X, double (&v)[2 * NR]) {
+    constexpr int RW = 2;
+    constexpr int TR = kStageRows<BB>;
+    constexpr int NB = D == 1 ? 7 : 49;
+    constexpr int NA = D == 1 ? 1 : 7;
+    constexpr int SU = 4;   // staged loads per thread and slot per batch
+    const int h = (D == 1 ? 0 : 3 * m1) + 3;
+    const int WL = TR + 2 * h;
+    const int tid = threadIdx.x;
+#pragma unroll 1
+    for (int64_t t0 = 0; t0 < M; t0 += TR) {
+        // window loads first (every active slot), then this thread's rows of A
+#pragma unroll 1
+        for (int i0 = tid; i0 < WL; i0 += SU * BB) {
+            double w[NR][SU];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (r >= nr || done[r]) continue;
+                const double* xr = rp + r * ldr;
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const int64_t pi = t0 + i0 + u * BB;   // = halo + t0 - h + i
+                    w[r][u] = xr[pi < ldr ? pi : ldr - 1];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (r >= nr || done[r]) continue;
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const int i = i0 + u * BB;
+                    if (i < WL) X[r * WL + i] = w[r][u];
+                }
+            }
+        }
+        const int64_t j0 = t0 + RW * tid;
+        const bool row_ok = j0 < M;
+        const float* At = A + ((row_ok ? j0 : 0) / kRowTile) * NB * kRowTile +
+                          ((row_ok ? j0 : 0) % kRowTile);
+        float2 av[NB];
+#pragma unroll
+        for (int o = 0; o < NB; ++o) av[o] = *reinterpret_cast<const float2*>(At + o * kRowTile);
+        __syncthreads();
+        if (row_ok) {
+            double acc[NR][RW];
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+#pragma unroll
+                for (int q = 0; q < RW; ++q) acc[r][q] = 0.0;
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                const int wb = RW * tid + h + (D == 1 ? 0 : (a - 3) * m1) - 3;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    if (r >= nr || done[r]) continue;
+                    double xv[RW + 6];
+#pragma unroll
+                    for (int c = 0; c < RW + 6; ++c) xv[c] = X[r * WL + wb + c];
+#pragma unroll
+                    for (int b = 0; b < 7; ++b) {
+                        const float2 ab = av[a * 7 + b];
+                        acc[r][0] = fma((double)ab.x, xv[b], acc[r][0]);
+                        acc[r][1] = fma((double)ab.y, xv[1 + b], acc[r][1]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (r >= nr || done[r]) continue;
+#pragma unroll
+                for (int q = 0; q < RW; ++q) {
+                    if (j0 + q < M) {
+                        const double xc = X[r * WL + RW * tid + h + q];
+                        ur[r * M + j0 + q] = acc[r][q];
+                        v[2 * r] = fma(xc, acc[r][q], v[2 * r]);
+                        v[2 * r + 1] = fma(xc, bh[r * M + j0 + q], v[2 * r + 1]);
+                    }
+                }
+            }
+        }
+        __syncthreads();   // X is rewritten by the next tile
+    }
+}
+
 // BB threads per work item (256 or 512); the register budget allows two
 // waves per SIMD (two 256-thread items or one 512-thread item per CU).
 template <int NR, int BB>
 __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __restrict__ probs,
                                                          const BatchItem* __restrict__ items,
-                                                         double tol, int maxiter) {
+                                                         double tol, int maxiter,
+                                                         int64_t lds_doubles) {
     constexpr int kBB = BB;
     extern __shared__ double lds_dyn[];
     __shared__ double red[2 * NR * kMaxWaves];
@@ -451,6 +617,10 @@ __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __rest
     }
     __syncthreads();
 
+    // the staged banded product (FP32-stored matrix) when its windows fit in
+    // the LDS past the spectra (they share it with the strided-pass transpose)
+    const bool stage = P.a_f32 && batch_stage_doubles(P.d, P.m[1], NR, kBB) <=
+                                      lds_doubles - (int64_t)(T - lds_dyn);
     PassGeom pg1{}, pg0{};
     if (P.d == 1) {
         pg0 = PassGeom{P.m[0], 1, 1, M, ldr, halo};
@@ -486,28 +656,37 @@ __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __rest
                 const double* vrr = vr + r * M;
                 const double* kbr = kb + r * M;
                 const double* bhr = bh + r * M;
+                // every load of a chunk is issued before the first use (the
+                // tail reads a valid element and masks it): one round trip
 #pragma unroll 1
                 for (int64_t i0 = tid; i0 < M; i0 += 4 * kBB) {
-                    double s[4], z[4], k4[4], b4[4];
+                    double s0[4], u0[4], z0[4], v0[4], k4[4], b4[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int64_t i = i0 + u * kBB;
-                        const bool in = i < M;
-                        s[u] = in ? fma(b, spr[i], urr[i]) : 0.0;
-                        z[u] = in ? fma(b, zpr[i], vrr[i]) : 0.0;
-                        k4[u] = in ? kbr[i] : 0.0;
-                        b4[u] = in ? bhr[i] : 0.0;
+                        const int64_t ic = i < M ? i : M - 1;
+                        s0[u] = spr[ic];
+                        u0[u] = urr[ic];
+                        z0[u] = zpr[ic];
+                        v0[u] = vrr[ic];
+                        k4[u] = kbr[ic];
+                        b4[u] = bhr[ic];
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int64_t i = i0 + u * kBB;
-                        if (i < M) {
-                            spr[i] = s[u];
-                            zpr[i] = z[u];
+                        const bool in = i < M;
+                        const double s = in ? fma(b, s0[u], u0[u]) : 0.0;
+                        const double z = in ? fma(b, z0[u], v0[u]) : 0.0;
+                        const double kk = in ? k4[u] : 0.0;
+                        const double bb4 = in ? b4[u] : 0.0;
+                        if (in) {
+                            spr[i] = s;
+                            zpr[i] = z;
                         }
-                        const double a = fma(c, k4[u], z[u]);
-                        v[2 * r] = fma(s[u], a, v[2 * r]);
-                        v[2 * r + 1] = fma(a, b4[u], v[2 * r + 1]);
+                        const double a = fma(c, kk, z);
+                        v[2 * r] = fma(s, a, v[2 * r]);
+                        v[2 * r + 1] = fma(a, bb4, v[2 * r + 1]);
                     }
                 }
             }
@@ -541,20 +720,23 @@ __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __rest
             double* rpr = rp + r * ldr + halo;
 #pragma unroll 1
             for (int64_t i0 = tid; i0 < M; i0 += 4 * kBB) {
-                double xs[4], xr[4];
+                double s0[4], x0[4], k4[4], z0[4], r0v[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int64_t i = i0 + u * kBB;
-                    const bool in = i < M;
-                    xs[u] = in ? fma(a, spr[i], uxr[i]) : 0.0;
-                    xr[u] = in ? fma(-a, fma(c, kbr[i], zpr[i]), rpr[i]) : 0.0;
+                    const int64_t ic = i < M ? i : M - 1;
+                    s0[u] = spr[ic];
+                    x0[u] = uxr[ic];
+                    k4[u] = kbr[ic];
+                    z0[u] = zpr[ic];
+                    r0v[u] = rpr[ic];
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int64_t i = i0 + u * kBB;
                     if (i < M) {
-                        uxr[i] = xs[u];
-                        rpr[i] = xr[u];
+                        uxr[i] = fma(a, s0[u], x0[u]);
+                        rpr[i] = fma(-a, fma(c, k4[u], z0[u]), r0v[u]);
                     }
                 }
             }
@@ -566,7 +748,14 @@ __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __rest
             double v[2 * NR];
 #pragma unroll
             for (int k = 0; k < 2 * NR; ++k) v[k] = 0.0;
-            if (P.d == 1) {
+            if (stage) {
+                if (P.d == 1)
+                    spmv_rows_staged<NR, 1, BB>(static_cast<const float*>(P.A), rp, ur, bh,
+                                                done, nr, M, ldr, 1, T, v);
+                else
+                    spmv_rows_staged<NR, 2, BB>(static_cast<const float*>(P.A), rp, ur, bh,
+                                                done, nr, M, ldr, P.m[1], T, v);
+            } else if (P.d == 1) {
                 if (P.a_f32)
                     spmv_rows<NR, float, 1>(static_cast<const float*>(P.A), rp, ur, bh, done,
                                              nr, M, ldr, halo, 1, v);
@@ -671,7 +860,8 @@ fkgp_status launch_nr(const BatchProb* probs, const BatchItem* items, int nitems
     if (lds > 64 * 1024)
         FKGP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_cg_kernel<NR, BB>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    batch_cg_kernel<NR, BB><<<nitems, BB, lds, s>>>(probs, items, tol, maxiter);
+    batch_cg_kernel<NR, BB><<<nitems, BB, lds, s>>>(probs, items, tol, maxiter,
+                                                    (int64_t)(lds / sizeof(double)));
     FKGP_HIP(hipGetLastError());
     return FKGP_OK;
 }
@@ -702,19 +892,19 @@ fkgp_status launch_batch_cg(const BatchProb* probs_dev, const BatchItem* items_d
                             size_t lds, double tol, int maxiter, int nr, int block,
                             hipStream_t s) {
     if (nitems == 0) return FKGP_OK;
-    const int key = nr * 1000 + block;
+    const int key = nr * 10000 + block;
     switch (key) {
-        case 2256:
+        case 20256:
             return launch_nr<2, 256>(probs_dev, items_dev, nitems, lds, tol, maxiter, s);
-        case 4256:
+        case 40256:
             return launch_nr<4, 256>(probs_dev, items_dev, nitems, lds, tol, maxiter, s);
-        case 8256:
+        case 80256:
             return launch_nr<8, 256>(probs_dev, items_dev, nitems, lds, tol, maxiter, s);
-        case 2512:
+        case 20512:
             return launch_nr<2, 512>(probs_dev, items_dev, nitems, lds, tol, maxiter, s);
-        case 4512:
+        case 40512:
             return launch_nr<4, 512>(probs_dev, items_dev, nitems, lds, tol, maxiter, s);
-        case 8512:
+        case 80512:
             return launch_nr<8, 512>(probs_dev, items_dev, nitems, lds, tol, maxiter, s);
         default:
             set_error("batched solver: right-hand sides per item must be 2, 4 or 8 and the "

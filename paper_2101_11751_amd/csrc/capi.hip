@@ -3345,7 +3345,8 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
     std::vector<int> nrhs_v(np), long_L(np, 0);
     std::vector<double*> Vs(np), wxs(np), alph(np), bet(np);
     std::vector<PState*> pss(np);
-    size_t lds = 0;
+    size_t lds = 0;      // spectra and strided-pass transpose, largest problem
+    int stage_m1 = 0;    // largest m1 of a 2-D problem (staged product margin)
     for (int p = 0; p < np; ++p) {
         const fkgp_handle* h = hs[p];
         fkgp_status rs = make_ctx(h, &hyps[p], FKGP_F64, ctx[p], sc);
@@ -3397,6 +3398,7 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
                 long_L[p] = std::max(long_L[p], 1 << P.log2L[k]);
         }
         lds = std::max(lds, batch_lds_bytes(P.d, P.m, P.log2L));
+        stage_m1 = std::max(stage_m1, P.d == 1 ? 0 : P.m[1]);
         P.a_f32 = h->dt == FKGP_F32 ? 1 : 0;
         P.A = h->A;
         P.so = c.so;
@@ -3432,6 +3434,15 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
     }
     const std::vector<int>* hint = iters_hint.empty() ? nullptr : &iters_hint;
     auto slots_for = [&](int block) { return std::max(1, ncu) * (block == 256 ? 2 : 1); };
+    // dynamic LDS per tile: room for the staged banded product's windows on
+    // top of the spectra, within 64 KB (two 256-thread items per CU);
+    // problems whose windows do not fit use the unstaged product
+    auto lds_for = [&](int nr, int block) {
+        const size_t cap = 64 * 1024;
+        const size_t want = lds + sizeof(double) * (size_t)batch_stage_doubles(2, stage_m1, nr,
+                                                                               block);
+        return std::max(lds, std::min(want, cap));
+    };
     // tile: forced, cached or tuned
     BatchTile tile{o.batch_rhs, o.batch_block};
     if (tile.nr == 0 || tile.block == 0) {
@@ -3463,13 +3474,13 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
                     build_batch_items(probs, nrhs_v, long_L, cand.nr, slots_for(cand.block),
                                       hint, tsc, &it_dev, nit);
                 if (rs == FKGP_OK)   // warm-up launch (code object load), then the trial
-                    rs = launch_batch_cg(probs_dev, it_dev, nit, lds, o.tol, 1, cand.nr,
-                                         cand.block, st);
+                    rs = launch_batch_cg(probs_dev, it_dev, nit, lds_for(cand.nr, cand.block),
+                                         o.tol, 1, cand.nr, cand.block, st);
                 if (rs == FKGP_OK) {
                     FKGP_HIP(hipEventRecord(e0, st));
-                    rs = launch_batch_cg(probs_dev, it_dev, nit, lds, o.tol,
-                                         std::min(o.maxiter, kTuneIters), cand.nr, cand.block,
-                                         st);
+                    rs = launch_batch_cg(probs_dev, it_dev, nit, lds_for(cand.nr, cand.block),
+                                         o.tol, std::min(o.maxiter, kTuneIters), cand.nr,
+                                         cand.block, st);
                     FKGP_HIP(hipEventRecord(e1, st));
                 }
                 if (rs != FKGP_OK) {
@@ -3498,7 +3509,8 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
     fkgp_status rs = build_batch_items(probs, nrhs_v, long_L, NR, slots_for(tile.block), hint,
                                        sc, &items_dev, nitems);
     if (rs != FKGP_OK) return rs;
-    rs = launch_batch_cg(probs_dev, items_dev, nitems, lds, o.tol, o.maxiter, NR, tile.block, st);
+    rs = launch_batch_cg(probs_dev, items_dev, nitems, lds_for(NR, tile.block), o.tol,
+                         o.maxiter, NR, tile.block, st);
     if (rs != FKGP_OK) return rs;
     FKGP_HIP(hipStreamSynchronize(st));
     fkgp_status res = FKGP_OK;

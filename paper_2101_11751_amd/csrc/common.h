@@ -437,6 +437,14 @@ __host__ __device__ inline int64_t batch_rhat_stride(int64_t M, int64_t halo) {
     return M + 2 * halo + 8;
 }
 size_t batch_work_doubles(int64_t M, int64_t halo, int nr);
+// LDS (doubles) of the batched kernel's staged banded product for nr
+// right-hand sides and `block` threads: a tile of 2 block rows plus the
+// stencil margin 3 m1 + 3 (2-D) or 3 (1-D) on both sides, per right-hand
+// side.  It shares the LDS past the spectra with the strided-pass transpose.
+__host__ __device__ inline int64_t batch_stage_doubles(int d, int m1, int nr, int block) {
+    const int64_t h = (d == 1 ? 0 : 3 * (int64_t)m1) + 3;
+    return (int64_t)nr * (2 * block + 2 * h);
+}
 // Dynamic LDS of the batched kernel for one problem (spectra, transpose).
 size_t batch_lds_bytes(int d, const int* m, const int* log2L);
 fkgp_status launch_batch_cg(const BatchProb* probs_dev, const BatchItem* items_dev, int nitems,
