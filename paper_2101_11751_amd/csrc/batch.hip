@@ -285,6 +285,154 @@ __device__ void pass_long(const double* src, double* dst, const int* act, int na
     }
 }
 
+// Dense Toeplitz line passes (2-D problems with both m_k <= kBatchTzMax):
+// out[j] = sum_k c[|j - k|] u[k] along each line, 64 lines on the lanes of a
+// wave and kBatchTzNJ consecutive outputs in its registers, the lines staged
+// through LDS.  The column comes reflected and zero-padded:
+// ext[q] = c[|q - (NJ - 1) - (m - 1)|] for |.| < m, else 0, so that the NJ
+// values an output block needs at step k form one contiguous wave-uniform
+// slice; a block of NJ steps reads the 2 NJ - 1 values it spans once.  For
+// lines of ~100 nodes this takes about half the instructions of a 256-point
+// FFT convolution, with no cross-lane traffic, and is exact to the plain
+// summation bound.
+constexpr int kTzNJ = kBatchTzNJ;
+
+// acc[t] += sum_{k in [kb, kb + NJ)} ext[j0 - k + m - 1 + t + NJ - 1] u[k]
+// (TAIL: steps past the line's end read a valid node and are masked).
+template <bool TAIL>
+__device__ __forceinline__ void tz_block(double (&acc)[kTzNJ], const double* ext,
+                                         const double* urow, int ustride, int j0, int kb,
+                                         int m) {
+    constexpr int NJ = kTzNJ;
+    const int base = j0 - kb + m - 1;   // index into ext without the left pad
+    double E[2 * NJ - 1];
+#pragma unroll
+    for (int q = 0; q < 2 * NJ - 1; ++q) E[q] = ext[base + q];   // pad NJ - 1 cancels -NJ + 1
+    double u[NJ];
+#pragma unroll
+    for (int s = 0; s < NJ; ++s) {
+        const int k = kb + s;
+        const double v = urow[(int64_t)(TAIL ? (k < m ? k : m - 1) : k) * ustride];
+        u[s] = (!TAIL || k < m) ? v : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < NJ; ++s)
+#pragma unroll
+        for (int t = 0; t < NJ; ++t) acc[t] = fma(E[NJ - 1 - s + t], u[s], acc[t]);
+}
+
+// One output block: acc[t] = out[j0 + t] of the lane's line.
+__device__ __forceinline__ void tz_line_block(double (&acc)[kTzNJ], const double* ext,
+                                              const double* urow, int ustride, int j0, int m) {
+    constexpr int NJ = kTzNJ;
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) acc[t] = 0.0;
+    int kb = 0;
+#pragma unroll 1
+    for (; kb + NJ <= m; kb += NJ) tz_block<false>(acc, ext, urow, ustride, j0, kb, m);
+    if (kb < m) tz_block<true>(acc, ext, urow, ustride, j0, kb, m);
+}
+
+// Pass along dimension 1 (contiguous lines: row i0 of the m0 x m1 vector):
+// dst[i0][j] = sum_k c1[|j - k|] src[i0][k].  Blocks of 64 rows are staged
+// as S[row][k] with an odd row stride (conflict-free lane reads).
+__device__ void tz_rows(const double* src, double* dst, int m0, int m1, const double* ext1,
+                        double* S) {
+    constexpr int NJ = kTzNJ;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6, nt = blockDim.x;
+    const int ls = m1 | 1;
+    const int njb = (m1 + NJ - 1) / NJ;
+    for (int rb = 0; rb < m0; rb += 64) {
+        const int nrow = min(64, m0 - rb);
+        const double* s0 = src + (int64_t)rb * m1;
+        const int cnt = nrow * m1;
+        for (int i0 = threadIdx.x; i0 < cnt; i0 += 8 * nt) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u * nt;
+                v[u] = s0[i < cnt ? i : cnt - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u * nt;
+                if (i < cnt) {
+                    const int row = i / m1;
+                    S[row * ls + (i - row * m1)] = v[u];
+                }
+            }
+        }
+        __syncthreads();
+        // lanes past the block's last row compute on another row and store nothing
+        const double* urow = S + (lane < nrow ? lane : 0) * ls;
+        for (int jb = wave; jb < njb; jb += nw) {
+            const int j0 = jb * NJ;
+            double acc[NJ];
+            tz_line_block(acc, ext1, urow, 1, j0, m1);
+            if (lane < nrow) {
+                double* d = dst + (int64_t)(rb + lane) * m1;
+#pragma unroll
+                for (int t = 0; t < NJ; ++t)
+                    if (j0 + t < m1) d[j0 + t] = acc[t];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Pass along dimension 0 (strided lines: column i1): dst[j][i1] = scale *
+// sum_k c0[|j - k|] src[k][i1] + add_coef * addv[j m1 + i1] (addv: padded
+// r_hat, halo applied by the caller).  Blocks of 64 columns are staged as
+// S[k][col]; src == dst allowed (a block's reads precede its writes).
+__device__ void tz_cols(const double* src, double* dst, int m0, int m1, const double* ext0,
+                        double scale, const double* addv, double add_coef, double* S) {
+    constexpr int NJ = kTzNJ;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6, nt = blockDim.x;
+    const int njb = (m0 + NJ - 1) / NJ;
+    for (int cb = 0; cb < m1; cb += 64) {
+        const int ncol = min(64, m1 - cb);
+        const int cnt = m0 * 64;
+        for (int i0 = threadIdx.x; i0 < cnt; i0 += 8 * nt) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u * nt;
+                const int k = (i < cnt ? i : cnt - 1) >> 6, c = i & 63;
+                v[u] = src[(int64_t)k * m1 + cb + (c < ncol ? c : ncol - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u * nt;
+                if (i < cnt) S[i] = v[u];
+            }
+        }
+        __syncthreads();
+        const int col = cb + (lane < ncol ? lane : ncol - 1);
+        for (int jb = wave; jb < njb; jb += nw) {
+            const int j0 = jb * NJ;
+            double a[NJ];
+#pragma unroll
+            for (int t = 0; t < NJ; ++t) {
+                const int j = j0 + t < m0 ? j0 + t : m0 - 1;
+                a[t] = addv[(int64_t)j * m1 + col];
+            }
+            double acc[NJ];
+            tz_line_block(acc, ext0, S + lane, 64, j0, m0);
+            if (lane < ncol) {
+#pragma unroll
+                for (int t = 0; t < NJ; ++t)
+                    if (j0 + t < m0)
+                        dst[(int64_t)(j0 + t) * m1 + col] = fma(add_coef, a[t], scale * acc[t]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Spectrum data of one dimension as the kernel sees it.
 struct DimSpec {
     int lg;                       // log2 of the circulant length
@@ -543,7 +691,22 @@ __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __rest
     // spectra into LDS (long dimensions: only the sub-length twiddles)
     DimSpec dsp[2] = {};
     double* T = nullptr;
-    {
+    const bool tz = P.col[0] != nullptr;   // dense Toeplitz line passes
+    double* ext[2] = {nullptr, nullptr};
+    if (tz) {
+        // reflected, zero-padded columns (see tz_block), then the staging block
+        double* q = lds_dyn;
+        for (int k = 0; k < 2; ++k) {
+            const int m = P.m[k], n = 2 * m + 2 * kTzNJ;
+            for (int i = tid; i < n; i += kBB) {
+                const int o = i - (kTzNJ - 1) - (m - 1);
+                q[i] = (o > -m && o < m) ? P.col[k][o < 0 ? -o : o] : 0.0;
+            }
+            ext[k] = q;
+            q += n;
+        }
+        T = q;
+    } else {
         unsigned char* p = reinterpret_cast<unsigned char*>(lds_dyn);
         for (int k = 0; k < P.d; ++k) {
             const int lg = P.log2L[k], L = 1 << lg;
@@ -811,12 +974,23 @@ __global__ __launch_bounds__(BB, 2) void batch_cg_kernel(const BatchProb* __rest
         // never paired with a probe's: the passes run over [y] and the
         // probes separately.
         if (na > 0) {
-            const bool split = pre && act[0] == 0 && na > 1;
+            const bool split = !tz && pre && act[0] == 0 && na > 1;
             const int ng = split ? 2 : 1;
             for (int gi = 0; gi < ng; ++gi) {
                 const int* ga = split && gi == 1 ? act + 1 : act;
                 const int gn = split ? (gi == 0 ? 1 : na - 1) : na;
-                if (P.d == 1) {
+                if (tz) {
+                    for (int q = 0; q < gn; ++q) {
+                        const int r = ga[q];
+                        tz_rows(ur + r * M, vr + r * M, P.m[0], P.m[1], ext[1], T);
+                    }
+                    __syncthreads();
+                    for (int q = 0; q < gn; ++q) {
+                        const int r = ga[q];
+                        tz_cols(vr + r * M, vr + r * M, P.m[0], P.m[1], ext[0], P.so,
+                                rp + r * ldr + halo, P.s2, T);
+                    }
+                } else if (P.d == 1) {
                     line_pass(dsp[0], false, ur, vr, ga, gn, pg0, P.so, rp, P.s2, T, it.yscr);
                 } else {
                     line_pass(dsp[1], false, ur, vr, ga, gn, pg1, 1.0, nullptr, 0.0, T,
@@ -873,6 +1047,7 @@ size_t batch_work_doubles(int64_t M, int64_t halo, int nr) {
 }
 
 size_t batch_lds_bytes(int d, const int* m, const int* log2L) {
+    if (batch_tz(d, m)) return sizeof(double) * (size_t)batch_tz_doubles(m);
     size_t l = 0;
     for (int k = 0; k < d; ++k) {
         if (log2L[k] > kBatchRegMaxLog2) {

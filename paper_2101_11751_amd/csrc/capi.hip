@@ -3397,6 +3397,17 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
             if (k < h->g.d && P.log2L[k] > kBatchRegMaxLog2)
                 long_L[p] = std::max(long_L[p], 1 << P.log2L[k]);
         }
+        P.col[0] = P.col[1] = nullptr;
+        if (batch_tz(P.d, P.m)) {
+            for (int k = 0; k < 2; ++k) {
+                double* col = nullptr;
+                FKGP_HIP(sc.get(&col, (size_t)P.m[k]));
+                rs = build_toeplitz_col(h->g, k, hyps[p].lengthscale[k], false, hyps[p].kernel,
+                                        FKGP_F64, col, st);
+                if (rs != FKGP_OK) return rs;
+                P.col[k] = col;
+            }
+        }
         lds = std::max(lds, batch_lds_bytes(P.d, P.m, P.log2L));
         stage_m1 = std::max(stage_m1, P.d == 1 ? 0 : P.m[1]);
         P.a_f32 = h->dt == FKGP_F32 ? 1 : 0;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include <string>
 
 #include "../../include/fkgp.h"
@@ -419,6 +421,8 @@ struct BatchProb {
                                // residual in the span of W; null: slot 0 from x_0 = 0
     const void* tw[2];         // FP64 twiddles per dimension
     const double* lam[2];      // FP64 spectra per dimension
+    const double* col[2];      // 2-D, both m_k <= kBatchTzMax: FP64 kernel columns
+                               // c[j], j < m_k (dense Toeplitz line passes); else null
     double* alphas;            // [nrhs][kMaxLanczos]
     double* betas;             // [nrhs][kMaxLanczos]
     PState* ps;                // [nrhs]
@@ -437,6 +441,22 @@ __host__ __device__ inline int64_t batch_rhat_stride(int64_t M, int64_t halo) {
     return M + 2 * halo + 8;
 }
 size_t batch_work_doubles(int64_t M, int64_t halo, int nr);
+// 2-D problems with both dimensions at most kBatchTzMax nodes apply K_G in
+// the batched kernel as two dense Toeplitz line passes (kBatchTzNJ
+// consecutive outputs per lane, lines on the lanes); longer lines and 1-D
+// problems use the line FFT.
+constexpr int kBatchTzMax = 128;
+constexpr int kBatchTzNJ = 8;
+inline bool batch_tz(int d, const int* m) {
+    return d == 2 && m[0] <= kBatchTzMax && m[1] <= kBatchTzMax;
+}
+// LDS (doubles) of those passes: both reflected columns (2 m + 2 NJ each)
+// and the staging block, 64 lines of odd stride (pass along dimension 1) or
+// m_0 rows of 64 columns (pass along dimension 0).
+inline int64_t batch_tz_doubles(const int* m) {
+    const int64_t ext = 2 * (int64_t)m[0] + 2 * kBatchTzNJ + 2 * (int64_t)m[1] + 2 * kBatchTzNJ;
+    return ext + 64 * std::max<int64_t>(m[1] | 1, m[0]);
+}
 // LDS (doubles) of the batched kernel's staged banded product for nr
 // right-hand sides and `block` threads: a tile of 2 block rows plus the
 // stencil margin 3 m1 + 3 (2-D) or 3 (1-D) on both sides, per right-hand
