@@ -2289,11 +2289,9 @@ __global__ void probe_wtx(const PState* __restrict__ ps, const double* __restric
 // by the implicit symmetric QL iteration with Wilkinson-type shifts, tracking
 // only the first row of the eigenvector matrix (Gauss quadrature weights).
 // One thread per probe, FP64.
-__global__ void lanczos_logdet(const PState* __restrict__ ps, const double* __restrict__ alphas,
-                               const double* __restrict__ betas, int N, int steps,
-                               double* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+__device__ double lanczos_logdet_one(const PState* __restrict__ ps,
+                                     const double* __restrict__ alphas,
+                                     const double* __restrict__ betas, int j, int steps) {
     int k = min(steps, min(ps[j].iters, kMaxLanczos));
     double dg[kMaxLanczos], e[kMaxLanczos], q[kMaxLanczos];
     const double* a = alphas + j * kMaxLanczos;
@@ -2353,7 +2351,28 @@ __global__ void lanczos_logdet(const PState* __restrict__ ps, const double* __re
     }
     double acc = 0.0;
     for (int i = 0; i < k; ++i) acc += q[i] * q[i] * log(dg[i]);
-    out[j] = ok ? acc : NAN;
+    return ok ? acc : NAN;
+}
+
+__global__ void lanczos_logdet(const PState* __restrict__ ps, const double* __restrict__ alphas,
+                               const double* __restrict__ betas, int N, int steps,
+                               double* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < N) out[j] = lanczos_logdet_one(ps, alphas, betas, j, steps);
+}
+
+// The same for many problems in one launch (problem blockIdx.y).
+struct LogdetJob {
+    const PState* ps;
+    const double* alphas;
+    const double* betas;
+    double* out;
+    int N;
+};
+__global__ void lanczos_logdet_multi(const LogdetJob* __restrict__ jobs, int steps) {
+    const LogdetJob jb = jobs[blockIdx.y];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < jb.N) jb.out[j] = lanczos_logdet_one(jb.ps, jb.alphas, jb.betas, j, steps);
 }
 
 // dots[r] = A[r] . B[r] for k pairs of FP64 vectors of length M.
@@ -2554,77 +2573,90 @@ fkgp_status probe_cg(const OpCtx& c, const double* bh, int N, double n, double t
 
 // MLL and gradient from solved systems: V = [W^T z~, W^T z_0 .. W^T z_{N-1}],
 // wx = [W^T z~, W^T x_0 .. W^T x_{N-1}] (x_j = A^{-1} z_j), the probes' CG
-// coefficients and states.  V and wx are [N+1][M] device buffers.
-fkgp_status mll_post(const OpCtx& c, const fkgp_hypers* hyp, const fkgp_mll_opts& o,
-                     const double* V, const double* wx, const double* alphas,
-                     const double* betas, const PState* ps, double* mll, double* grad,
-                     Scratch& sc, hipStream_t st, double& logdet_out, double& q_out,
-                     const double* tr_exact = nullptr, double* dq_out = nullptr) {
+// coefficients and states.  V and wx are [N+1][M] device buffers.  The
+// device part (mll_post_enqueue) leaves every number the host needs in
+// `res` (mll_post_doubles of them): [0] y.mu, [1] mu.(A mu), then per
+// theta (log l_k, log s) N + 1 dots, then N dots for the noise, then the N
+// Lanczos log-determinant terms (written by the caller when `logdet` is
+// false); mll_post_finish turns a host copy of it into the MLL and its
+// gradient.  Nothing in between waits for the device.
+size_t mll_post_doubles(int d, int N) { return 2 + (size_t)(d + 1) * (N + 1) + 2 * (size_t)N; }
+
+fkgp_status mll_post_enqueue(const OpCtx& c, const fkgp_hypers* hyp, const fkgp_mll_opts& o,
+                             const double* V, const double* wx, const double* alphas,
+                             const double* betas, const PState* ps, double* res, bool logdet,
+                             Scratch& sc, hipStream_t st) {
     const fkgp_handle* h = c.h;
     const int d = h->g.d;
     const int N = h->nprobe;
     const int64_t M = h->M;
-    const double n = (double)h->n;
-    double *DV, *mu, *Amu, *pad64, *dotp, *dots, *ld;
+    double *DV, *mu, *Amu, *pad64, *dotp;
     FKGP_HIP(sc.get(&DV, M * (N + 1)));
     FKGP_HIP(sc.get(&mu, M));
     FKGP_HIP(sc.get(&Amu, M));
     FKGP_HIP(sc.get(&pad64, M + 2 * c.halo));
     FKGP_HIP(sc.get(&dotp, (size_t)vec_blocks(M) * (N + 1) * 2));
-    FKGP_HIP(sc.get(&dots, 4 * (N + 1)));
-    FKGP_HIP(sc.get(&ld, N));
+    double* th_dots = res + 2;
+    double* s_dots = res + 2 + (size_t)(d + 1) * (N + 1);
+    double* ld = s_dots + N;
     fkgp_status rs = kg_apply(h->g, c.sp64, FKGP_F64, V, mu, 1, c.so, nullptr, 0.0, nullptr, st);
     if (rs != FKGP_OK) return rs;
-    lanczos_logdet<<<(N + 63) / 64, 64, 0, st>>>(ps, alphas, betas, N, o.lanczos_steps, ld);
-    FKGP_HIP(hipGetLastError());
+    if (logdet) {
+        lanczos_logdet<<<(N + 63) / 64, 64, 0, st>>>(ps, alphas, betas, N, o.lanczos_steps, ld);
+        FKGP_HIP(hipGetLastError());
+    }
     // y^T A^{-1} y and ||z~||^2 need W^T y . mu and mu . (W^T W mu)
     FKGP_HIP(hipMemsetAsync(pad64, 0, sizeof(double) * (M + 2 * c.halo), st));
     FKGP_HIP(hipMemcpyAsync(pad64 + c.halo, mu, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
     rs = apply_B64(c, pad64, Amu, nullptr, st);
     if (rs != FKGP_OK) return rs;
-    rs = dots_dev(h->wty, mu, M, 1, dotp, dots, st);
+    rs = dots_dev(h->wty, mu, M, 1, dotp, res, st);
     if (rs != FKGP_OK) return rs;
-    rs = dots_dev(mu, Amu, M, 1, dotp, dots + 1, st);
+    rs = dots_dev(mu, Amu, M, 1, dotp, res + 1, st);
     if (rs != FKGP_OK) return rs;
-    std::vector<double> hv(2), hld(N);
-    FKGP_HIP(hipMemcpyAsync(hv.data(), dots, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
-    FKGP_HIP(hipMemcpyAsync(hld.data(), ld, sizeof(double) * N, hipMemcpyDeviceToHost, st));
     // theta = log l_k (k < d), log s (k = d): DV = dK [w_y, b_hat_j]
-    std::vector<double> quad(d + 1), tr(d + 1);
-    std::vector<double> hd(N + 1);
     for (int th = 0; th <= d; ++th) {
-        Scratch sth(st);
         Spectra dsp;
-        rs = make_spectra(h, hyp, FKGP_F64, th < d ? th : -1, dsp, sth);
+        rs = make_spectra(h, hyp, FKGP_F64, th < d ? th : -1, dsp, sc);
         if (rs != FKGP_OK) return rs;
         rs = kg_apply(h->g, dsp, FKGP_F64, V, DV, N + 1, c.so, nullptr, 0.0, nullptr, st);
         if (rs != FKGP_OK) return rs;
-        rs = dots_dev(wx, DV, M, N + 1, dotp, dots + 2, st);
+        rs = dots_dev(wx, DV, M, N + 1, dotp, th_dots + (size_t)th * (N + 1), st);
         if (rs != FKGP_OK) return rs;
-        FKGP_HIP(hipMemcpyAsync(hd.data(), dots + 2, sizeof(double) * (N + 1),
-                                hipMemcpyDeviceToHost, st));
-        FKGP_HIP(hipStreamSynchronize(st));
+    }
+    // sigma: x_j^T z_j = (n - b_hat_j . K_G W^T x_j) / s2
+    rs = kg_apply(h->g, c.sp64, FKGP_F64, wx + M, DV + M, N, c.so, nullptr, 0.0, nullptr, st);
+    if (rs != FKGP_OK) return rs;
+    return dots_dev(V + M, DV + M, M, N, dotp, s_dots, st);
+}
+
+fkgp_status mll_post_finish(const OpCtx& c, const double* hres, double* mll, double* grad,
+                            double& logdet_out, double& q_out, const double* tr_exact = nullptr,
+                            double* dq_out = nullptr) {
+    const fkgp_handle* h = c.h;
+    const int d = h->g.d;
+    const int N = h->nprobe;
+    const double n = (double)h->n;
+    const double* th_dots = hres + 2;
+    const double* s_dots = hres + 2 + (size_t)(d + 1) * (N + 1);
+    const double* hld = s_dots + N;
+    std::vector<double> quad(d + 1), tr(d + 1);
+    for (int th = 0; th <= d; ++th) {
+        const double* hd = th_dots + (size_t)th * (N + 1);
         quad[th] = hd[0];
         double acc = 0.0;
         for (int j = 0; j < N; ++j) acc += hd[1 + j];
         tr[th] = acc / N;
     }
-    // sigma: x_j^T z_j = (n - b_hat_j . K_G W^T x_j) / s2
-    rs = kg_apply(h->g, c.sp64, FKGP_F64, wx + M, DV + M, N, c.so, nullptr, 0.0, nullptr, st);
-    if (rs != FKGP_OK) return rs;
-    rs = dots_dev(V + M, DV + M, M, N, dotp, dots + 2, st);
-    if (rs != FKGP_OK) return rs;
-    FKGP_HIP(hipMemcpyAsync(hd.data(), dots + 2, sizeof(double) * N, hipMemcpyDeviceToHost, st));
-    FKGP_HIP(hipStreamSynchronize(st));
     const double s2 = c.s2;
     const double yty = h->yty;
-    const double q = (yty - hv[0]) / s2;
-    const double zz = (yty - 2.0 * hv[0] + hv[1]) / (s2 * s2);
+    const double q = (yty - hres[0]) / s2;
+    const double zz = (yty - 2.0 * hres[0] + hres[1]) / (s2 * s2);
     double logdet = 0.0;
     for (int j = 0; j < N; ++j) logdet += n * hld[j];
     logdet /= N;
     double trs = 0.0;
-    for (int j = 0; j < N; ++j) trs += (n - hd[j]) / s2;
+    for (int j = 0; j < N; ++j) trs += (n - s_dots[j]) / s2;
     trs = 2.0 * s2 * trs / N;
     if (tr_exact) {   // exact traces: tr(S dK) per theta, then tr(A^{-1})
         for (int th = 0; th <= d; ++th) tr[th] = tr_exact[th];
@@ -2645,6 +2677,22 @@ fkgp_status mll_post(const OpCtx& c, const fkgp_hypers* hyp, const fkgp_mll_opts
         return FKGP_EDEVICE;
     }
     return FKGP_OK;
+}
+
+fkgp_status mll_post(const OpCtx& c, const fkgp_hypers* hyp, const fkgp_mll_opts& o,
+                     const double* V, const double* wx, const double* alphas,
+                     const double* betas, const PState* ps, double* mll, double* grad,
+                     Scratch& sc, hipStream_t st, double& logdet_out, double& q_out,
+                     const double* tr_exact = nullptr, double* dq_out = nullptr) {
+    const size_t nres = mll_post_doubles(c.h->g.d, c.h->nprobe);
+    double* res = nullptr;
+    FKGP_HIP(sc.get(&res, nres));
+    fkgp_status rs = mll_post_enqueue(c, hyp, o, V, wx, alphas, betas, ps, res, true, sc, st);
+    if (rs != FKGP_OK) return rs;
+    std::vector<double> hres(nres);
+    FKGP_HIP(hipMemcpyAsync(hres.data(), res, sizeof(double) * nres, hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipStreamSynchronize(st));
+    return mll_post_finish(c, hres.data(), mll, grad, logdet_out, q_out, tr_exact, dq_out);
 }
 
 // E[j] = unit vector e_{q0 + j} (E zeroed by the caller), j < nr.
@@ -3345,6 +3393,7 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
     std::vector<int> nrhs_v(np), long_L(np, 0);
     std::vector<double*> Vs(np), wxs(np), alph(np), bet(np);
     std::vector<PState*> pss(np);
+    std::vector<std::vector<double>> hbs(np);   // ||b||^2 of each problem's right-hand sides
     size_t lds = 0;      // spectra and strided-pass transpose, largest problem
     int stage_m1 = 0;    // largest m1 of a 2-D problem (staged product margin)
     for (int p = 0; p < np; ++p) {
@@ -3379,10 +3428,10 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
         rs = kg_apply(h->g, c.sp64, FKGP_F64, h->wty, r0y, 1, -c.so / c.s2, nullptr, 0.0,
                       nullptr, st);
         if (rs != FKGP_OK) return rs;
-        std::vector<double> hb(nrhs, (double)h->n);
+        std::vector<double>& hb = hbs[p];   // kept until the stream is synchronised
+        hb.assign(nrhs, (double)h->n);
         hb[0] = h->yty;
         FKGP_HIP(hipMemcpyAsync(bn, hb.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
-        FKGP_HIP(hipStreamSynchronize(st));   // hb leaves scope
         BatchProb& P = probs[p];
         P.d = h->g.d;
         P.m[0] = h->g.m[0];
@@ -3523,21 +3572,63 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
     rs = launch_batch_cg(probs_dev, items_dev, nitems, lds_for(NR, tile.block), o.tol,
                          o.maxiter, NR, tile.block, st);
     if (rs != FKGP_OK) return rs;
+    // every problem's MLL and gradient work is queued behind the launch and
+    // read back with one copy; the log-determinants of all probes run in
+    // one launch
+    std::vector<size_t> roff(np + 1, 0), psoff(np, 0);
+    size_t nps = 0;
+    int maxN = 0;
+    for (int p = 0; p < np; ++p) {
+        roff[p + 1] = roff[p] + mll_post_doubles(hs[p]->g.d, hs[p]->nprobe);
+        psoff[p] = nps;
+        nps += (size_t)hs[p]->nprobe + 1;
+        maxN = std::max(maxN, hs[p]->nprobe);
+    }
+    double* res_dev = nullptr;
+    PState* ps_all = nullptr;
+    LogdetJob* jobs_dev = nullptr;
+    FKGP_HIP(sc.get(&res_dev, roff[np]));
+    FKGP_HIP(sc.get(&ps_all, nps));
+    FKGP_HIP(sc.get(&jobs_dev, (size_t)np));
+    std::vector<LogdetJob> jobs(np);
+    for (int p = 0; p < np; ++p) {
+        const fkgp_handle* h = hs[p];
+        const int N = h->nprobe;
+        const int64_t M = h->M;
+        FKGP_HIP(hipMemcpyAsync(ps_all + psoff[p], pss[p], sizeof(PState) * (N + 1),
+                                hipMemcpyDeviceToDevice, st));
+        // V = [W^T z~ (= wx_0), b_hat_j]
+        FKGP_HIP(hipMemcpyAsync(Vs[p], wxs[p], sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+        FKGP_HIP(hipMemcpyAsync(Vs[p] + M, h->sketches, sizeof(double) * M * N,
+                                hipMemcpyDeviceToDevice, st));
+        Scratch sp_(st);
+        rs = mll_post_enqueue(ctx[p], &hyps[p], o, Vs[p], wxs[p], alph[p] + kMaxLanczos,
+                              bet[p] + kMaxLanczos, pss[p] + 1, res_dev + roff[p], false, sp_,
+                              st);
+        if (rs != FKGP_OK) return rs;
+        jobs[p] = LogdetJob{pss[p] + 1, alph[p] + kMaxLanczos, bet[p] + kMaxLanczos,
+                            res_dev + roff[p + 1] - N, N};
+    }
+    FKGP_HIP(hipMemcpyAsync(jobs_dev, jobs.data(), sizeof(LogdetJob) * np,
+                            hipMemcpyHostToDevice, st));
+    if (maxN > 0) {
+        lanczos_logdet_multi<<<dim3((maxN + 63) / 64, np), 64, 0, st>>>(jobs_dev,
+                                                                         o.lanczos_steps);
+        FKGP_HIP(hipGetLastError());
+    }
+    std::vector<double> hres(roff[np]);
+    std::vector<PState> hps(nps);
+    FKGP_HIP(hipMemcpyAsync(hres.data(), res_dev, sizeof(double) * roff[np],
+                            hipMemcpyDeviceToHost, st));
+    FKGP_HIP(hipMemcpyAsync(hps.data(), ps_all, sizeof(PState) * nps, hipMemcpyDeviceToHost,
+                            st));
     FKGP_HIP(hipStreamSynchronize(st));
     fkgp_status res = FKGP_OK;
     std::vector<int> iters_now(np, 0);
     for (int p = 0; p < np; ++p) {
         const fkgp_handle* h = hs[p];
         const int N = h->nprobe;
-        const int64_t M = h->M;
-        std::vector<PState> hsv(N + 1);
-        FKGP_HIP(hipMemcpyAsync(hsv.data(), pss[p], sizeof(PState) * (N + 1),
-                                hipMemcpyDeviceToHost, st));
-        // V = [W^T z~ (= wx_0), b_hat_j]
-        FKGP_HIP(hipMemcpyAsync(Vs[p], wxs[p], sizeof(double) * M, hipMemcpyDeviceToDevice, st));
-        FKGP_HIP(hipMemcpyAsync(Vs[p] + M, h->sketches, sizeof(double) * M * N,
-                                hipMemcpyDeviceToDevice, st));
-        FKGP_HIP(hipStreamSynchronize(st));
+        const PState* hsv = hps.data() + psoff[p];
         int itmax = 0;
         bool conv = true;
         for (int j = 0; j <= N; ++j) {
@@ -3550,10 +3641,8 @@ fkgp_status batch_mll_impl(const fkgp_handle* const* hs, int np, const fkgp_hype
             iters_now[p] = std::max(iters_now[p], hsv[j].iters);
         }
         double logdet = 0.0, q = 0.0, dq[5];
-        Scratch sp_(st);
-        rs = mll_post(ctx[p], &hyps[p], o, Vs[p], wxs[p], alph[p] + kMaxLanczos,
-                      bet[p] + kMaxLanczos, pss[p] + 1, &mll[p], grad + 5 * p, sp_, st, logdet,
-                      q, nullptr, dq);
+        rs = mll_post_finish(ctx[p], hres.data() + roff[p], &mll[p], grad + 5 * p, logdet, q,
+                             nullptr, dq);
         if (rs != FKGP_OK) return rs;
         for (int k = h->g.d + 2; k < 5; ++k) grad[5 * p + k] = 0.0;
         if (infos) {
