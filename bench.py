@@ -62,6 +62,8 @@ def _parse():
     ap.add_argument("--mll-tol", type=float, default=1e-4)
     ap.add_argument("--mll-maxiter", type=int, default=20000)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-batch-loop", action="store_true",
+                    help="batch64 without the per-problem comparison loop (profiling runs)")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cov", action="store_true")
@@ -209,7 +211,7 @@ def mll_compare(P, workloads, torch, dev, reps, tol, maxiter):
             "iterations_y": b["iterations_y"], "iterations_probes_max": b["iterations_probes_max"]}
 
 
-def batch_compare(P, workloads, torch, dev, tol, maxiter):
+def batch_compare(P, workloads, torch, dev, tol, maxiter, loop_cmp=True):
     """The many-problem workload (64 uneven problems, 32 right-hand sides
     each): MLL + gradient of every problem in one persistent launch (tiles
     autotuned; the tuning trial runs in an untimed first call) vs one
@@ -234,6 +236,12 @@ def batch_compare(P, workloads, torch, dev, tol, maxiter):
     t_batch = time.perf_counter() - t0
     log(f"batch64: one launch {t_batch:.3f} s (tile {ib[0]['batch_rhs']} rhs x "
         f"{ib[0]['batch_block']} threads)")
+    if not loop_cmp:
+        iters = max(max(i["iterations_y"], i["iterations_probes_max"]) for i in ib)
+        for h in hs:
+            h.close()
+        return {"workload": "batch64 (one launch only)", "n_total": n_total,
+                "batched_s_per_eval": t_batch, "iterations_max": iters}
     t0 = time.perf_counter()
     loop = [P.mll_and_grad(h, hyp, steps, tol, maxiter) for h, hyp in zip(hs, hyps)]
     torch.cuda.synchronize()
@@ -581,7 +589,8 @@ def main():
         result["precompute_2d"] = precompute_extra(P, workloads, torch, dev)
     if not args.no_batch:
         torch.cuda.empty_cache()
-        bc = batch_compare(P, workloads, torch, dev, args.batch_tol, args.batch_maxiter)
+        bc = batch_compare(P, workloads, torch, dev, args.batch_tol, args.batch_maxiter,
+                           loop_cmp=not args.no_batch_loop)
         result["batch_mll_grad_s_per_eval"] = bc["batched_s_per_eval"]
         result["batch_mll_grad"] = bc
     if not args.no_sweep:
