@@ -98,6 +98,31 @@ def test_batch_bitwise_repeatable_across_regrouping():
         assert g == runs[0][1]
 
 
+def test_batch_toeplitz_path_limits():
+    """2-D problems at the limits of the dense Toeplitz line passes: 128 x 128
+    (largest on that path), 129 x 40 (line FFT: one dimension too long), and
+    65 x 7 (two 64-row blocks, lines shorter than one 8-output block); each
+    matches the single-problem path."""
+    _need_gpu()
+    specs = [(31, 2, [128, 128], 30000, 3), (32, 2, [129, 40], 20000, 3),
+             (33, 2, [65, 7], 6000, 3)]
+    probs = [problem(*s) for s in specs]
+    hs = [p[0] for p in probs]
+    hyps = [p[1] for p in probs]
+    # 10 Lanczos steps as in the other batch-vs-single comparisons (the
+    # coefficients come from CG and carry its rounding into the estimate)
+    mll_b, g_b, inf_b = P.batch_mll_and_grad(hs, hyps, lanczos_steps=10, tol=1e-10,
+                                             maxiter=20000)
+    for k, h in enumerate(hs):
+        mll_s, g_s, inf_s = P.mll_and_grad(h, hyps[k], 10, 1e-10, 20000)
+        assert inf_b[k]["status"] == 0 and inf_s["status"] == 0
+        print(f"{k}: logdet {inf_b[k]['logdet']:.12g} / {inf_s['logdet']:.12g}, quad "
+              f"{inf_b[k]['quad']:.12g} / {inf_s['quad']:.12g}")
+        scale = abs(inf_s["logdet"]) + abs(inf_s["quad"]) + h.n * math.log(2 * math.pi)
+        assert abs(mll_b[k] - mll_s) <= 1e-7 * scale, (k, mll_b[k], mll_s)
+        np.testing.assert_allclose(g_b[k], g_s, rtol=0, atol=1e-5 * np.max(np.abs(g_s)))
+
+
 def test_batch_long_lines():
     """1-D problems with 1500 .. 8192 nodes (circulants of 4096 .. 16384
     points, four-step line FFT inside the persistent kernel) beside short
