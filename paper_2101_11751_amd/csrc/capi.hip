@@ -194,6 +194,11 @@ int red_blocks(int64_t M) {
     return (int)b;
 }
 
+// Sum of v over the workgroup (kRedBlock threads, fixed tree order).  The
+// result is read from sh[0] by every thread with no barrier after it, so
+// only thread 0 may use it when another block_sum on the same `sh` follows
+// (the next call's first store can overwrite sh[0] before a slower thread
+// has read it); every caller here consumes it in thread 0.
 __device__ inline double block_sum(double v, double* sh) {
     sh[threadIdx.x] = v;
     __syncthreads();
