@@ -24,12 +24,16 @@
 //       the previous iteration, fused here), and the dots s_p.ap, ap.b_hat
 //       with ap = z_p + c_p kappa_b (never stored);
 //   (B) u_x += alpha s_p, r_hat -= alpha ap;
-//   (C) u_r = W^T W r_hat with several consecutive rows per thread (the
-//       x values of a stencil row are shared by neighbouring rows) and the
-//       dots r_hat.u_r, r_hat.b_hat fused;
-//   (D) v_r = s K_G u_r + s2 r_hat: line convolutions per grid dimension,
-//       short lines by the register line FFT (strided lines staged through
-//       an LDS transpose), long lines by the four-step FFT.
+//   (C) u_r = W^T W r_hat with two consecutive rows per thread (the x
+//       values of a stencil row are shared by neighbouring rows) and the
+//       dots r_hat.u_r, r_hat.b_hat fused; with an FP32-stored matrix the
+//       x windows of a tile of rows are staged through LDS;
+//   (D) v_r = s K_G u_r + s2 r_hat: line products per grid dimension, dense
+//       Toeplitz passes for 2-D grids with both dimensions up to 128 nodes,
+//       else short lines by the register line FFT (strided lines staged
+//       through an LDS transpose) and long lines by the four-step FFT.
+// Each pass issues a chunk's loads together, so an iteration of an item is
+// a short chain of memory round trips.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
